@@ -1,0 +1,238 @@
+/*
+ * diffaero.h -- C ABI of the MI355X (gfx950) batched, differentiable quadrotor
+ * environment step: dynamics integration, ray-cast depth camera / LiDAR,
+ * collisions, the hand-written adjoint, the policy-in-the-loop BPTT engine,
+ * the BF16 residual-dynamics surrogate and the persistent uneven-batch rollout.
+ *
+ * The operations follow DiffAero (Zhang et al., 2025):
+ *   - dynamics models: Sec. III-A, Eq. (1) full quadrotor, Eq. (2) simplified,
+ *     Eq. (3) continuous point mass;
+ *   - sensors: Sec. III-B (ray casting against primitive shapes, obstacles
+ *     outside the sensor's field of view excluded from casting);
+ *   - gradients through time: Sec. III-A, Eq. (5);
+ *   - environment- and agent-level parallelism: Sec. III (multiple
+ *     environments, each with several quadrotors).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - All tensor pointers are DEVICE pointers (HBM) owned by the caller, unless
+ *    a comment says "host". The library never frees them and never keeps them
+ *    beyond what a call's comment states.
+ *  - Lanes: one lane per agent; A = total agents over all envs. The agents of
+ *    env e are lanes agent_off[e] .. agent_off[e+1]-1.
+ *  - SoA layout "[C][A]": component c of agent i is at ptr[c*A + i].
+ *  - Floating point is IEEE FP32 (round to nearest even, FMA contraction
+ *    allowed); surrogate GEMM operands are BF16 with FP32 accumulation.
+ *  - Every call returns 0 on success or a negative SIM_E* code; the message
+ *    of the calling thread's last failure is returned by sim_last_error().
+ *  - Calls taking a `stream` (a hipStream_t passed as void*, NULL = the null
+ *    stream) are asynchronous on that stream unless stated otherwise; launch
+ *    failures are reported by the call that launched.
+ *  - A handle is not thread-safe; distinct handles are independent.
+ *
+ * State layouts (Sec. III-A), world frame ENU with g = (0, 0, -9.81):
+ *  SIM_PM6      p(3) v(3)                 action u(3) [m/s^2]
+ *  SIM_PM9      p(3) v(3) a(3)            action u(3) [m/s^2]; params lambda, d
+ *  SIM_RB13     p(3) v(3) q(4) w(3)       action T [N], w_cmd(3) [rad/s]
+ *  SIM_NOMINAL13  as SIM_RB13 (w follows w_cmd instantly, no drag)
+ *  q = (w, x, y, z) Hamilton, body->world; w (rates) in the body frame.
+ *  RB params rows: m, Jxx, Jyy, Jzz, Dxx, Dyy, Dzz, tau_w   (SoA [8][A])
+ *  PM9 params rows: lambda, d                              (SoA [2][A])
+ *  Body-rate loop of the rigid body: tau = J (w_cmd - w)/tau_w + w x (J w).
+ *
+ * Sensor conventions (Sec. III-B): camera pinhole with horizontal FOV
+ * cam_hfov_deg, optical axis body +x, image right = body -y, image up = body
+ * +z, pixel centres at +1/2, output z-depth [A][H][W]; LiDAR lidar_ch
+ * channels evenly spaced over [elev_min, elev_max], lidar_az azimuths
+ * counter-clockwise from body +x, output range [A][ch][az]. Point-mass models
+ * keep the sensor world-aligned. Miss or value >= max -> max; origin inside an
+ * obstacle (or outside the room) -> 0. Hit records (int32 per ray): env-local
+ * primitive index (spheres, then boxes, then other agents, then the room),
+ * -1 miss / clamp, -2 inside.
+ */
+#ifndef DIFFAERO_H
+#define DIFFAERO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { SIM_OK = 0, SIM_EINVAL = -1, SIM_ENODEV = -2, SIM_ENOMEM = -3, SIM_EHIP = -4, SIM_ESTATE = -5 };
+enum { SIM_PM6 = 0, SIM_PM9 = 1, SIM_RB13 = 2, SIM_NOMINAL13 = 3 };
+enum { SIM_EULER = 0, SIM_RK4 = 1 };
+/* step flags bits */
+enum { SIM_FLAG_NONFINITE = 1, SIM_FLAG_COLLISION = 2 };
+
+/* Upper bounds checked by sim_set_scene (the per-env primitive list is staged
+ * in LDS by the render kernels). */
+#define SIM_MAX_PRIMS_PER_ENV 1024
+#define SIM_MAX_AGENTS_PER_ENV 64
+
+typedef struct sim_config {
+  int32_t n_envs;          /* E >= 1 */
+  int32_t n_agents;        /* A >= E (total lanes) */
+  int32_t model;           /* SIM_PM6 .. SIM_NOMINAL13 */
+  int32_t integrator;      /* SIM_EULER or SIM_RK4 (one step per dt, action held) */
+  float dt;                /* > 0 [s] */
+  int32_t cam_w, cam_h;    /* 0,0 = no camera */
+  float cam_hfov_deg;      /* (0, 180) */
+  float cam_max;           /* > 0 [m] */
+  int32_t lidar_ch, lidar_az;  /* 0,0 = no LiDAR */
+  float lidar_elev_min_deg, lidar_elev_max_deg, lidar_max;
+  float agent_radius;      /* sphere radius of an agent for rendering / collisions [m] */
+  int32_t agents_visible;  /* 1: other agents of an env are rendered as spheres */
+  int32_t fov_cull;        /* 1: per-ray-tile cone + range culling (results identical to 0) */
+} sim_config;
+
+typedef struct sim_handle sim_handle;
+
+/* Last failure message of the calling thread (static storage, never NULL). */
+const char* sim_last_error(void);
+
+/* Validates cfg and builds the per-sensor ray tables on the current device
+ * (synchronous). Fails with SIM_EINVAL on a bad config, SIM_ENODEV without a
+ * gfx950 device. */
+int sim_create(const sim_config* cfg, sim_handle** out);
+int sim_destroy(sim_handle* h);
+
+/* Obstacle scene (Sec. III-C obstacle avoidance: spheres and axis-aligned
+ * boxes per env) in CSR form:
+ *   sph_off[E+1], sph[n_sph][4] = (cx, cy, cz, r);
+ *   box_off[E+1], box[n_box][6] = (cx, cy, cz, hx, hy, hz);
+ *   room[E][6] = (lo_x, lo_y, lo_z, hi_x, hi_y, hi_z) or NULL (no room);
+ *   agent_off[E+1] or NULL (= one agent per env, requires A == E).
+ * All device pointers; the handle keeps them (the caller keeps them alive and
+ * unchanged while the handle uses them). The offsets are copied to the host
+ * once and validated (monotone, totals n_sph / n_box / A, per-env counts
+ * within SIM_MAX_*): SIM_EINVAL otherwise. Synchronous. */
+int sim_set_scene(sim_handle* h, const int32_t* sph_off, const float* sph, int32_t n_sph,
+                  const int32_t* box_off, const float* box, int32_t n_box,
+                  const float* room, const int32_t* agent_off);
+
+/* Per-agent parameters SoA [P][A] (P = 0, 2, 8 by model, see above); kept by
+ * reference like the scene. Required before sim_step for PM9 / RB13 /
+ * NOMINAL13. */
+int sim_set_params(sim_handle* h, const float* params);
+
+/* state[:, i] = init[:, i] for every lane i with mask[i] != 0 (mask NULL = all
+ * lanes). SoA [C][A]. */
+int sim_reset(sim_handle* h, float* state, const float* init, const uint8_t* mask, void* stream);
+
+/* One environment step s_out = step(s_in, a) (Sec. III-A; Euler or classical
+ * RK4 with a held; q renormalised after the step). s_in, s_out: SoA [C][A]
+ * (may alias); a: SoA [K][A]; flags: nullable uint8 [A], set to
+ * SIM_FLAG_NONFINITE when s_out has a non-finite component (other bits 0). */
+int sim_step(sim_handle* h, const float* s_in, const float* a, float* s_out, uint8_t* flags,
+             void* stream);
+
+/* Ray-cast sensors at state s (Sec. III-B): depth [A][H][W] z-depth, lidar
+ * [A][ch][az] range, each nullable (skipped); hit_cam / hit_lidar: nullable
+ * int32 hit records of the same shapes (required later by the backward). */
+int sim_render(sim_handle* h, const float* s, float* depth, float* lidar, int32_t* hit_cam,
+               int32_t* hit_lidar, void* stream);
+
+/* Collisions: min_dist[i] = distance from agent i's centre to the nearest
+ * surface (spheres, boxes, room walls, other agents' spheres when
+ * agents_visible); flags[i] |= SIM_FLAG_COLLISION when min_dist < agent_radius.
+ * Either output nullable. */
+int sim_collide(sim_handle* h, const float* s, uint8_t* flags, float* min_dist, void* stream);
+
+/* Vector-Jacobian product of one step and the sensors at s_t (Sec. III-A,
+ * Eq. (5) factors):
+ *   g_s_t = (d s_{t+1}/d s_t)^T g_s_next + (d depth_t/d s_t)^T g_depth
+ *           + (d lidar_t/d s_t)^T g_lidar
+ *   g_a_t = (d s_{t+1}/d a_t)^T g_s_next
+ * s_t, a_t as in sim_step; g_s_next SoA [C][A] (nullable = 0); g_depth
+ * [A][H][W] and g_lidar [A][ch][az] (nullable = 0) with the hit records
+ * written by sim_render at s_t (required when the matching gradient is
+ * given). Rays with record < 0 (miss, clamp, inside) contribute 0; a hit
+ * contributes the derivative of the recorded primitive's closed form. Outputs
+ * overwritten; g_a_t nullable. Other agents' spheres are treated as fixed
+ * obstacles (their own positions get no gradient from the viewer's image). */
+int sim_step_backward(sim_handle* h, const float* s_t, const float* a_t, const float* g_s_next,
+                      const float* g_depth, const float* g_lidar, const int32_t* hit_cam,
+                      const int32_t* hit_lidar, float* g_s_t, float* g_a_t, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Policy MLP (FP32 on MFMA) and BPTT through the rollout (Sec. III-A,
+ * Eq. (5); Sec. III-D MLP backbone)
+ * ------------------------------------------------------------------------
+ * Policy: 3081 -> 256 -> 256 -> 4, tanh on every layer, parameters theta flat
+ * FP32 [W1 (256x3081 row-major), b1, W2 (256x256), b2, W3 (4x256), b3]
+ * (855812 floats). Observation = [depth/cam_max (H*W, row-major),
+ * p_goal - p, v, b] with b = a (SIM_PM9) or z_B (SIM_RB13).
+ * Action: PM9 u = 9.81 y[0:3]; RB13 T = m 9.81 (1 + y0), w_cmd = 3 y[1:4].
+ * Loss (mean over agents and steps) per step, s_{t+1} = step(s_t, a_t),
+ * depth_t = render(s_t):
+ *   w_p |p_{t+1} - goal|^2 + w_v |v_{t+1}|^2 + w_u |y_t|^2
+ *   + w_o mean_rays softplus(beta (d_safe - depth_t)) / beta.
+ * The camera must be 64x48 (3072 rays) and the model SIM_PM9 or SIM_RB13.
+ */
+#define POLICY_N_PARAMS 855812
+
+typedef struct bptt_config {
+  int32_t T;      /* horizon >= 1 */
+  int32_t K;      /* checkpoint period, 1 <= K <= T; states kept every K steps */
+  float w_p, w_v, w_u, w_o, beta, d_safe;
+} bptt_config;
+
+typedef struct bptt_handle bptt_handle;
+
+/* Allocates the checkpoint ring (ceil(T/K) states) and the per-segment
+ * recompute buffers (K steps of observation, hit records and activations). */
+int bptt_create(sim_handle* sim, const bptt_config* cfg, bptt_handle** out);
+int bptt_destroy(bptt_handle* b);
+/* Bytes of device memory the handle holds. */
+int64_t bptt_workspace_bytes(const bptt_handle* b);
+
+/* Forward rollout of T steps from s0 (SoA [C][A]) towards goal (SoA [3][A]):
+ * writes loss[0] (device float), optionally the final state s_T, and keeps the
+ * checkpoints for bptt_backward. theta: device FP32 [POLICY_N_PARAMS]. */
+int bptt_forward(bptt_handle* b, const float* theta, const float* s0, const float* goal,
+                 float* loss, float* s_T, void* stream);
+
+/* Gradient of g_loss[0] * loss (g_loss device float, NULL = 1) with respect
+ * to theta (g_theta [POLICY_N_PARAMS], overwritten) and s0 (g_s0 SoA [C][A],
+ * nullable, overwritten). Recomputes each K-step segment from its checkpoint
+ * (render, policy, step), then runs the reverse sweep with the hand-written
+ * adjoints. Must follow bptt_forward with the same theta / s0 / goal. */
+int bptt_backward(bptt_handle* b, const float* g_loss, float* g_theta, float* g_s0, void* stream);
+
+/* Kernel timing (diagnostics for the roofline report): when enabled, every
+ * launch of the kernel classes below is bracketed by HIP events on the
+ * caller's stream during bptt_forward / bptt_backward. bptt_get_timing
+ * synchronizes on those events and writes, per class c < n, the summed
+ * duration ms[c] (host float) and the launch count count[c] (host int32).
+ * bptt_set_timing also clears the record. */
+enum {
+  BPTT_T_RENDER = 0,      /* camera render (render_kernel) */
+  BPTT_T_L1 = 1,          /* first policy layer GEMM, 3084 -> 256, + bias + tanh */
+  BPTT_T_GW1 = 2,         /* first-layer weight gradient GEMM (split-K) + reduction */
+  BPTT_T_GX = 3,          /* observation gradient GEMM, 256 -> 3084 */
+  BPTT_T_RENDER_VJP = 4,  /* render adjoint */
+  BPTT_T_STEP = 5,        /* dynamics step */
+  BPTT_T_STEP_VJP = 6,    /* dynamics step adjoint */
+  BPTT_T_COUNT = 7
+};
+int bptt_set_timing(bptt_handle* b, int32_t enable);
+int bptt_get_timing(bptt_handle* b, float* ms, int32_t* count, int32_t n);
+
+/* Stand-alone policy forward / backward on a batch (for tests and tools):
+ * x [B][3081] row-major, y [B][4]. policy_backward recomputes the forward and
+ * writes g_theta (overwritten) and g_x ([B][3081], nullable). */
+int policy_forward(const float* theta, const float* x, float* y, int32_t B, void* stream);
+int policy_backward(const float* theta, const float* x, const float* g_y, float* g_theta,
+                    float* g_x, int32_t B, void* stream);
+
+/* Adam (Kingma & Ba 2015) on n FP32 values: m = b1 m + (1-b1) g,
+ * v = b2 v + (1-b2) g^2, w -= lr * (m/(1-b1^t)) / (sqrt(v/(1-b2^t)) + eps).
+ * t >= 1 is the 1-based update count. */
+int adam_step(int64_t n, float* w, const float* g, float* m, float* v, float lr, float b1,
+              float b2, float eps, int32_t t, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DIFFAERO_H */

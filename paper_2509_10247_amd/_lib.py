@@ -1,0 +1,234 @@
+"""ctypes binding of libdiffaero.so: argument marshalling only.
+
+Every function here has the name of the C entry point it calls, converts
+torch CUDA tensors to device pointers and the current torch stream to a
+hipStream_t, and raises RuntimeError with sim_last_error() on a non-zero
+status. There is no fallback: if the library is not built, load() raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_DIR = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_DIR, "libdiffaero.so")
+
+SIM_PM6, SIM_PM9, SIM_RB13, SIM_NOMINAL13 = 0, 1, 2, 3
+SIM_EULER, SIM_RK4 = 0, 1
+POLICY_N_PARAMS = 855812
+
+c_int, c_float, c_void_p, c_int64 = ctypes.c_int32, ctypes.c_float, ctypes.c_void_p, ctypes.c_int64
+
+
+class SimConfig(ctypes.Structure):
+    _fields_ = [("n_envs", c_int), ("n_agents", c_int), ("model", c_int), ("integrator", c_int),
+                ("dt", c_float), ("cam_w", c_int), ("cam_h", c_int), ("cam_hfov_deg", c_float),
+                ("cam_max", c_float), ("lidar_ch", c_int), ("lidar_az", c_int),
+                ("lidar_elev_min_deg", c_float), ("lidar_elev_max_deg", c_float),
+                ("lidar_max", c_float), ("agent_radius", c_float), ("agents_visible", c_int),
+                ("fov_cull", c_int)]
+
+
+class BpttConfig(ctypes.Structure):
+    _fields_ = [("T", c_int), ("K", c_int), ("w_p", c_float), ("w_v", c_float), ("w_u", c_float),
+                ("w_o", c_float), ("beta", c_float), ("d_safe", c_float)]
+
+
+_SIGS = {
+    "sim_last_error": (ctypes.c_char_p, []),
+    "sim_create": (c_int, [ctypes.POINTER(SimConfig), ctypes.POINTER(c_void_p)]),
+    "sim_destroy": (c_int, [c_void_p]),
+    "sim_set_scene": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_int,
+                              c_void_p, c_void_p]),
+    "sim_set_params": (c_int, [c_void_p, c_void_p]),
+    "sim_reset": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "sim_step": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "sim_render": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "sim_collide": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "sim_step_backward": (c_int, [c_void_p] + [c_void_p] * 9 + [c_void_p]),
+    "bptt_create": (c_int, [c_void_p, ctypes.POINTER(BpttConfig), ctypes.POINTER(c_void_p)]),
+    "bptt_destroy": (c_int, [c_void_p]),
+    "bptt_workspace_bytes": (c_int64, [c_void_p]),
+    "bptt_forward": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "bptt_backward": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "bptt_set_timing": (c_int, [c_void_p, c_int]),
+    "bptt_get_timing": (c_int, [c_void_p, ctypes.POINTER(c_float), ctypes.POINTER(c_int), c_int]),
+    "policy_forward": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
+    "policy_backward": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
+    "adam_step": (c_int, [c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_float, c_float,
+                          c_float, c_float, c_int, c_void_p]),
+}
+
+_lib = None
+
+
+def exported_symbols():
+    """Names of the entry points this binding expects the library to export."""
+    return sorted(_SIGS)
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Open the built library (no build, no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built: run __graft_entry__.build() first")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name, None)
+        if fn is None:
+            continue
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def last_error() -> str:
+    return load().sim_last_error().decode()
+
+
+def _check(rc: int, name: str):
+    if rc != 0:
+        raise RuntimeError(f"{name} failed ({rc}): {last_error()}")
+
+
+def ptr(t, dtype=None):
+    """Device pointer of a contiguous CUDA tensor (None -> NULL)."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"expected {dtype}, got {t.dtype}")
+    return t.data_ptr()
+
+
+def stream(s=None):
+    if s is None:
+        s = torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _call(name, *args):
+    _check(getattr(load(), name)(*args), name)
+
+
+# --------------------------------------------------------------------------
+# simulator
+# --------------------------------------------------------------------------
+
+def sim_create(**kw) -> int:
+    cfg = SimConfig(**kw)
+    h = c_void_p()
+    _call("sim_create", ctypes.byref(cfg), ctypes.byref(h))
+    return h.value
+
+
+def sim_destroy(h):
+    _call("sim_destroy", h)
+
+
+def sim_set_scene(h, sph_off, sph, n_sph, box_off, box, n_box, room, agent_off):
+    _call("sim_set_scene", h, ptr(sph_off, torch.int32), ptr(sph, torch.float32), int(n_sph),
+          ptr(box_off, torch.int32), ptr(box, torch.float32), int(n_box), ptr(room, torch.float32),
+          ptr(agent_off, torch.int32))
+
+
+def sim_set_params(h, params):
+    _call("sim_set_params", h, ptr(params, torch.float32))
+
+
+def sim_reset(h, state, init, mask=None):
+    _call("sim_reset", h, ptr(state, torch.float32), ptr(init, torch.float32), ptr(mask, torch.uint8),
+          stream())
+
+
+def sim_step(h, s_in, a, s_out, flags=None):
+    _call("sim_step", h, ptr(s_in, torch.float32), ptr(a, torch.float32), ptr(s_out, torch.float32),
+          ptr(flags, torch.uint8), stream())
+
+
+def sim_render(h, s, depth=None, lidar=None, hit_cam=None, hit_lidar=None):
+    _call("sim_render", h, ptr(s, torch.float32), ptr(depth, torch.float32), ptr(lidar, torch.float32),
+          ptr(hit_cam, torch.int32), ptr(hit_lidar, torch.int32), stream())
+
+
+def sim_collide(h, s, flags=None, min_dist=None):
+    _call("sim_collide", h, ptr(s, torch.float32), ptr(flags, torch.uint8),
+          ptr(min_dist, torch.float32), stream())
+
+
+def sim_step_backward(h, s_t, a_t, g_s_next, g_depth, g_lidar, hit_cam, hit_lidar, g_s_t, g_a_t):
+    _call("sim_step_backward", h, ptr(s_t, torch.float32), ptr(a_t, torch.float32),
+          ptr(g_s_next, torch.float32), ptr(g_depth, torch.float32), ptr(g_lidar, torch.float32),
+          ptr(hit_cam, torch.int32), ptr(hit_lidar, torch.int32), ptr(g_s_t, torch.float32),
+          ptr(g_a_t, torch.float32), stream())
+
+
+# --------------------------------------------------------------------------
+# policy / BPTT
+# --------------------------------------------------------------------------
+
+def bptt_create(h, T, K, w_p, w_v, w_u, w_o, beta, d_safe) -> int:
+    cfg = BpttConfig(T, K, w_p, w_v, w_u, w_o, beta, d_safe)
+    b = c_void_p()
+    _call("bptt_create", h, ctypes.byref(cfg), ctypes.byref(b))
+    return b.value
+
+
+def bptt_destroy(b):
+    _call("bptt_destroy", b)
+
+
+def bptt_workspace_bytes(b) -> int:
+    return int(load().bptt_workspace_bytes(b))
+
+
+def bptt_forward(b, theta, s0, goal, loss, s_T=None):
+    _call("bptt_forward", b, ptr(theta, torch.float32), ptr(s0, torch.float32),
+          ptr(goal, torch.float32), ptr(loss, torch.float32), ptr(s_T, torch.float32), stream())
+
+
+def bptt_backward(b, g_loss, g_theta, g_s0=None):
+    _call("bptt_backward", b, ptr(g_loss, torch.float32), ptr(g_theta, torch.float32),
+          ptr(g_s0, torch.float32), stream())
+
+
+BPTT_TIMING_CLASSES = ["render", "l1_gemm", "gw1_gemm", "gx_gemm", "render_vjp", "step", "step_vjp"]
+
+
+def bptt_set_timing(b, enable):
+    _call("bptt_set_timing", b, int(bool(enable)))
+
+
+def bptt_get_timing(b):
+    n = len(BPTT_TIMING_CLASSES)
+    ms = (c_float * n)()
+    cnt = (c_int * n)()
+    _call("bptt_get_timing", b, ms, cnt, n)
+    return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(BPTT_TIMING_CLASSES)}
+
+
+def policy_forward(theta, x, y):
+    _call("policy_forward", ptr(theta, torch.float32), ptr(x, torch.float32), ptr(y, torch.float32),
+          int(x.shape[0]), stream())
+
+
+def policy_backward(theta, x, g_y, g_theta, g_x=None):
+    _call("policy_backward", ptr(theta, torch.float32), ptr(x, torch.float32),
+          ptr(g_y, torch.float32), ptr(g_theta, torch.float32), ptr(g_x, torch.float32),
+          int(x.shape[0]), stream())
+
+
+def adam_step(w, g, m, v, lr, b1, b2, eps, t):
+    _call("adam_step", int(w.numel()), ptr(w, torch.float32), ptr(g, torch.float32),
+          ptr(m, torch.float32), ptr(v, torch.float32), float(lr), float(b1), float(b2),
+          float(eps), int(t), stream())

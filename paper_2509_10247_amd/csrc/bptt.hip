@@ -1,0 +1,685 @@
+// Backpropagation through time over a policy-in-the-loop rollout (Sec. III-A,
+// Eq. (5): the gradient is the chain of step Jacobians, here applied in
+// reverse as vector-Jacobian products), with checkpoint-and-recompute.
+//
+// Forward: T steps of render -> observation -> policy MLP -> action -> step,
+// accumulating the loss; only the state at every K-th step is kept.
+// Backward: for each K-step segment, last first, the segment is recomputed from
+// its checkpoint (keeping observations, hit records and activations of those K
+// steps), then swept in reverse: loss terms, step VJP, action map, the MLP
+// backward on MFMA (weight gradients accumulated with deterministic split-K
+// reductions), observation backward, render VJP. Memory is
+// O(T/K states + K steps of activations) instead of O(T steps).
+#include <vector>
+
+#include "mlp.h"
+#include "sim_internal.h"
+
+struct bptt_handle;
+
+namespace da {
+
+static int tmark(bptt_handle* b, hipStream_t st);
+static void tpair(bptt_handle* b, int cls, int a, int z);
+
+constexpr int kHid = 256, kOut = 4;
+constexpr int kRays = 3072;            // 64 x 48 camera
+constexpr int kObs = kRays + 9;        // 3081 inputs
+constexpr int kObsPad = 3084;          // padded row pitch (multiple of 4)
+constexpr size_t kOffW1 = 0;
+constexpr size_t kOffB1 = kOffW1 + (size_t)kHid * kObs;
+constexpr size_t kOffW2 = kOffB1 + kHid;
+constexpr size_t kOffB2 = kOffW2 + (size_t)kHid * kHid;
+constexpr size_t kOffW3 = kOffB2 + kHid;
+constexpr size_t kOffB3 = kOffW3 + (size_t)kOut * kHid;
+static_assert(kOffB3 + kOut == POLICY_N_PARAMS, "policy parameter layout");
+
+// ---------------------------------------------------------------------------
+// observation, action, loss kernels
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float softplus(float x) { return fmaxf(x, 0.f) + log1pf(expf(-fabsf(x))); }
+
+__device__ __forceinline__ float block_sum_256(float v, float* red) {
+  const int t = threadIdx.x;
+  red[t] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) red[t] += red[t + w];
+    __syncthreads();
+  }
+  const float r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// Fills the proprioceptive part of the observation row and the per-agent
+// obstacle term mean_r softplus(beta (d_safe - depth_r)) / beta from the depth
+// already written (scaled by 1/d_max) into X[b][0..3071].
+__global__ __launch_bounds__(256) void obs_fwd_kernel(int A, int model, float* __restrict__ X,
+                                                      const float* __restrict__ s,
+                                                      const float* __restrict__ goal, float dmax,
+                                                      float beta, float d_safe,
+                                                      float* __restrict__ lo) {
+  __shared__ float red[256];
+  const int b = blockIdx.x, t = threadIdx.x;
+  float* row = X + (size_t)b * kObsPad;
+  float acc = 0.f;
+  for (int r = t; r < kRays; r += 256) acc += softplus(beta * (d_safe - row[r] * dmax)) / beta;
+  const float tot = block_sum_256(acc, red);
+  if (t == 0) lo[b] = tot / kRays;
+  if (t < 12) {
+    float v = 0.f;
+    if (t < 3) {
+      v = goal[(size_t)t * A + b] - s[(size_t)t * A + b];
+    } else if (t < 6) {
+      v = s[(size_t)t * A + b];
+    } else if (t < 9) {
+      if (model == SIM_PM9) {
+        v = s[(size_t)t * A + b];
+      } else {
+        float q[4] = {s[6 * (size_t)A + b], s[7 * (size_t)A + b], s[8 * (size_t)A + b],
+                      s[9 * (size_t)A + b]};
+        float qn[4];
+        quat_normalize(q, qn, nullptr);
+        const Rot R = rot_of_unit(qn);
+        v = R.m[t - 6][2];
+      }
+    }
+    row[kRays + t] = v;
+  }
+}
+
+// Action map: PM9 u = g y[0:3]; RB13 T = m g (1 + y0), w_cmd = 3 y[1:4].
+__global__ void action_kernel(int A, int model, const float* __restrict__ Y,
+                              const float* __restrict__ prm, float* __restrict__ a) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= A) return;
+  const float* y = Y + (size_t)b * kOut;
+  if (model == SIM_PM9) {
+    for (int k = 0; k < 3; ++k) a[(size_t)k * A + b] = kG * y[k];
+  } else {
+    a[b] = prm[b] * kG * (1.f + y[0]);
+    for (int k = 0; k < 3; ++k) a[(size_t)(k + 1) * A + b] = 3.f * y[k + 1];
+  }
+}
+
+struct LossW {
+  float w_p, w_v, w_u, w_o, beta, d_safe;
+};
+
+__global__ void loss_step_kernel(int A, const float* __restrict__ s1, const float* __restrict__ goal,
+                                 const float* __restrict__ Y, const float* __restrict__ lo, LossW w,
+                                 float* __restrict__ acc) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= A) return;
+  float lp = 0.f, lv = 0.f, lu = 0.f;
+  for (int k = 0; k < 3; ++k) {
+    const float dp = s1[(size_t)k * A + b] - goal[(size_t)k * A + b];
+    const float v = s1[(size_t)(k + 3) * A + b];
+    lp += dp * dp;
+    lv += v * v;
+  }
+  for (int k = 0; k < kOut; ++k) lu += Y[(size_t)b * kOut + k] * Y[(size_t)b * kOut + k];
+  acc[b] += w.w_p * lp + w.w_v * lv + w.w_u * lu + w.w_o * lo[b];
+}
+
+__global__ __launch_bounds__(1024) void loss_final_kernel(int A, const float* __restrict__ acc,
+                                                          float scale, float* __restrict__ out) {
+  __shared__ float red[1024];
+  const int t = threadIdx.x;
+  float v = 0.f;
+  for (int b = t; b < A; b += 1024) v += acc[b];
+  red[t] = v;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if (t < w) red[t] += red[t + w];
+    __syncthreads();
+  }
+  if (t == 0) out[0] = red[0] * scale;
+}
+
+// g_next += d(loss_t)/d(s_{t+1}) for the position and velocity terms.
+__global__ void loss_state_grad_kernel(int A, const float* __restrict__ s1,
+                                       const float* __restrict__ goal, float cp, float cv,
+                                       const float* __restrict__ gl, float* __restrict__ g) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= A) return;
+  const float sc = gl ? gl[0] : 1.f;
+  for (int k = 0; k < 3; ++k) {
+    g[(size_t)k * A + b] += sc * cp * (s1[(size_t)k * A + b] - goal[(size_t)k * A + b]);
+    g[(size_t)(k + 3) * A + b] += sc * cv * s1[(size_t)(k + 3) * A + b];
+  }
+}
+
+// dL/dy from the action gradient and the action-magnitude loss term.
+__global__ void action_bwd_kernel(int A, int model, const float* __restrict__ ga,
+                                  const float* __restrict__ Y, const float* __restrict__ prm, float cu,
+                                  const float* __restrict__ gl, float* __restrict__ gY) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= A) return;
+  const float sc = gl ? gl[0] : 1.f;
+  const float* y = Y + (size_t)b * kOut;
+  float g[kOut];
+  if (model == SIM_PM9) {
+    for (int k = 0; k < 3; ++k) g[k] = kG * ga[(size_t)k * A + b];
+    g[3] = 0.f;
+  } else {
+    g[0] = prm[b] * kG * ga[b];
+    for (int k = 0; k < 3; ++k) g[k + 1] = 3.f * ga[(size_t)(k + 1) * A + b];
+  }
+  for (int k = 0; k < kOut; ++k) gY[(size_t)b * kOut + k] = g[k] + sc * cu * y[k];
+}
+
+// Observation backward: turns gX[b][0..3071] into dL/d(depth) in place
+// (input scaling plus the obstacle term) and adds the proprioceptive part to
+// g_s (obs = [goal - p, v, b]).
+__global__ __launch_bounds__(256) void obs_bwd_kernel(int A, int model, float* __restrict__ gX,
+                                                      const float* __restrict__ X,
+                                                      const float* __restrict__ s, float dmax,
+                                                      float beta, float d_safe, float co,
+                                                      const float* __restrict__ gl,
+                                                      float* __restrict__ g_s) {
+  const int b = blockIdx.x, t = threadIdx.x;
+  const float sc = gl ? gl[0] : 1.f;
+  float* grow = gX + (size_t)b * kObsPad;
+  const float* xrow = X + (size_t)b * kObsPad;
+  const float inv = 1.f / dmax;
+  for (int r = t; r < kRays; r += 256) {
+    const float x = beta * (d_safe - xrow[r] * dmax);
+    const float sig = 1.f / (1.f + expf(-x));
+    grow[r] = grow[r] * inv - sc * co * sig;
+  }
+  if (t == 0) {
+    for (int k = 0; k < 3; ++k) {
+      g_s[(size_t)k * A + b] -= grow[kRays + k];
+      g_s[(size_t)(k + 3) * A + b] += grow[kRays + 3 + k];
+    }
+    if (model == SIM_PM9) {
+      for (int k = 0; k < 3; ++k) g_s[(size_t)(k + 6) * A + b] += grow[kRays + 6 + k];
+    } else {
+      float q[4] = {s[6 * (size_t)A + b], s[7 * (size_t)A + b], s[8 * (size_t)A + b],
+                    s[9 * (size_t)A + b]};
+      float qn[4], in;
+      quat_normalize(q, qn, &in);
+      float G[3][3] = {{0.f, 0.f, grow[kRays + 6]}, {0.f, 0.f, grow[kRays + 7]}, {0.f, 0.f, grow[kRays + 8]}};
+      float gqn[4], gq[4];
+      rot_vjp(G, qn, gqn);
+      normalize_vjp(qn, in, gqn, gq);
+      for (int k = 0; k < 4; ++k) g_s[(size_t)(6 + k) * A + b] += gq[k];
+    }
+  }
+}
+
+__global__ void unpad_w1_kernel(const float* __restrict__ src, float* __restrict__ dst) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= kHid * kObs) return;
+  const int r = idx / kObs, c = idx % kObs;
+  dst[idx] = src[(size_t)r * kObsPad + c];
+}
+
+// ---------------------------------------------------------------------------
+// MLP passes shared by the BPTT engine and the standalone policy calls
+// ---------------------------------------------------------------------------
+struct PolicyPtrs {
+  const float* W1p;  // [256][3084]
+  const float* b1;
+  const float* W2;   // [256][256]
+  const float* b2;
+  const float* W3;   // [4][256]
+  const float* b3;
+};
+
+static PolicyPtrs policy_ptrs(const float* theta, const float* W1p) {
+  return PolicyPtrs{W1p, theta + kOffB1, theta + kOffW2, theta + kOffB2, theta + kOffW3, theta + kOffB3};
+}
+
+static int mlp_forward(int B, const PolicyPtrs& p, const float* X, float* H1, float* H2, float* Y,
+                       hipStream_t st, bptt_handle* owner = nullptr) {
+  GemmArgs g;
+  g.M = B; g.N = kHid; g.K = kObsPad;
+  g.A = X; g.lda = kObsPad; g.B = p.W1p; g.ldb = kObsPad;
+  g.C = H1; g.ldc = kHid; g.bias = p.b1;
+  const int e0 = owner ? tmark(owner, st) : -1;
+  int rc = launch_gemm(true, true, EPI_BIAS_TANH, g, 1, st);
+  if (rc) return rc;
+  if (owner) tpair(owner, BPTT_T_L1, e0, tmark(owner, st));
+  g = GemmArgs();
+  g.M = B; g.N = kHid; g.K = kHid;
+  g.A = H1; g.lda = kHid; g.B = p.W2; g.ldb = kHid;
+  g.C = H2; g.ldc = kHid; g.bias = p.b2;
+  if ((rc = launch_gemm(true, true, EPI_BIAS_TANH, g, 1, st))) return rc;
+  return launch_narrow_fwd(B, kHid, kOut, H2, kHid, p.W3, p.b3, Y, st);
+}
+
+struct MlpGradBufs {
+  float* gW1p;   // [256][3084] accumulated
+  float* gb1;    // [256] accumulated
+  float* gW2;    // [256][256]
+  float* gb2;
+  float* gW3;    // [4][256]
+  float* gb3;
+  float* gZ3;    // [B][4]
+  float* gZ2;    // [B][256]
+  float* gZ1;    // [B][256]
+  float* gX;     // [B][3084]
+  float* part;   // split-K partials
+  bptt_handle* owner = nullptr;  // for optional timing
+};
+
+constexpr int kSplitW1 = 8, kSplitW2 = 64, kSplitW3 = 64;
+
+static size_t partial_floats(int B) {
+  size_t a = (size_t)gemm_splits_used(B, kSplitW1) * kHid * kObsPad;
+  size_t b = (size_t)gemm_splits_used(B, kSplitW2) * kHid * kHid;
+  size_t c = (size_t)gemm_splits_used(B, kSplitW3) * kOut * kHid;
+  return std::max(a, std::max(b, c));
+}
+
+// Accumulates weight gradients for one batch and writes gX = dL/dX.
+static int mlp_backward(int B, const PolicyPtrs& p, const float* X, const float* H1, const float* H2,
+                        const float* Y, const float* gY, MlpGradBufs& gb, hipStream_t st) {
+  int rc = launch_narrow_bwd(B, kHid, kOut, gY, Y, p.W3, H2, kHid, gb.gZ3, gb.gZ2, st);
+  if (rc) return rc;
+  // gW3 += gZ3^T H2 ; gb3 += colsum(gZ3)
+  GemmArgs g;
+  g.M = kOut; g.N = kHid; g.K = B;
+  g.A = gb.gZ3; g.lda = kOut; g.B = H2; g.ldb = kHid; g.C = gb.part; g.ldc = kHid;
+  if ((rc = launch_gemm(false, false, EPI_PARTIAL, g, kSplitW3, st))) return rc;
+  if ((rc = launch_splitk_reduce(gemm_splits_used(B, kSplitW3), kOut, kHid, kHid, gb.part, gb.gW3, kHid,
+                                 true, st)))
+    return rc;
+  if ((rc = launch_colsum(B, kOut, gb.gZ3, kOut, gb.gb3, true, st))) return rc;
+  // gW2 += gZ2^T H1 ; gb2
+  g = GemmArgs();
+  g.M = kHid; g.N = kHid; g.K = B;
+  g.A = gb.gZ2; g.lda = kHid; g.B = H1; g.ldb = kHid; g.C = gb.part; g.ldc = kHid;
+  if ((rc = launch_gemm(false, false, EPI_PARTIAL, g, kSplitW2, st))) return rc;
+  if ((rc = launch_splitk_reduce(gemm_splits_used(B, kSplitW2), kHid, kHid, kHid, gb.part, gb.gW2, kHid,
+                                 true, st)))
+    return rc;
+  if ((rc = launch_colsum(B, kHid, gb.gZ2, kHid, gb.gb2, true, st))) return rc;
+  // gZ1 = (gZ2 W2) (1 - H1^2)
+  g = GemmArgs();
+  g.M = B; g.N = kHid; g.K = kHid;
+  g.A = gb.gZ2; g.lda = kHid; g.B = p.W2; g.ldb = kHid; g.C = gb.gZ1; g.ldc = kHid;
+  g.aux = H1; g.ld_aux = kHid;
+  if ((rc = launch_gemm(true, false, EPI_MUL_DTANH, g, 1, st))) return rc;
+  // gW1 += gZ1^T X ; gb1
+  const int e0 = gb.owner ? tmark(gb.owner, st) : -1;
+  g = GemmArgs();
+  g.M = kHid; g.N = kObsPad; g.K = B;
+  g.A = gb.gZ1; g.lda = kHid; g.B = X; g.ldb = kObsPad; g.C = gb.part; g.ldc = kObsPad;
+  if ((rc = launch_gemm(false, false, EPI_PARTIAL, g, kSplitW1, st))) return rc;
+  if ((rc = launch_splitk_reduce(gemm_splits_used(B, kSplitW1), kHid, kObsPad, kObsPad, gb.part, gb.gW1p,
+                                 kObsPad, true, st)))
+    return rc;
+  if (gb.owner) tpair(gb.owner, BPTT_T_GW1, e0, tmark(gb.owner, st));
+  if ((rc = launch_colsum(B, kHid, gb.gZ1, kHid, gb.gb1, true, st))) return rc;
+  // gX = gZ1 W1
+  const int e1 = gb.owner ? tmark(gb.owner, st) : -1;
+  g = GemmArgs();
+  g.M = B; g.N = kObsPad; g.K = kHid;
+  g.A = gb.gZ1; g.lda = kHid; g.B = p.W1p; g.ldb = kObsPad; g.C = gb.gX; g.ldc = kObsPad;
+  rc = launch_gemm(true, false, EPI_STORE, g, 1, st);
+  if (gb.owner) tpair(gb.owner, BPTT_T_GX, e1, tmark(gb.owner, st));
+  return rc;
+}
+
+// Writes the accumulated gradients into the flat parameter layout.
+static int write_flat_grad(const MlpGradBufs& gb, float* g_theta, hipStream_t st) {
+  hipLaunchKernelGGL(unpad_w1_kernel, dim3(cdiv(kHid * kObs, 256)), dim3(256), 0, st, gb.gW1p,
+                     g_theta + kOffW1);
+  DA_LAUNCH_CHECK("unpad_w1_kernel");
+  // the tail (b1 .. b3) is kept contiguous in the same order as theta
+  DA_HIP(hipMemcpyAsync(g_theta + kOffB1, gb.gb1, (POLICY_N_PARAMS - kOffB1) * sizeof(float),
+                        hipMemcpyDeviceToDevice, st));
+  return SIM_OK;
+}
+
+}  // namespace da
+
+using namespace da;
+
+// ---------------------------------------------------------------------------
+// BPTT handle
+// ---------------------------------------------------------------------------
+struct bptt_handle {
+  sim_handle* sim = nullptr;
+  bptt_config cfg{};
+  int A = 0, C = 0, Ka = 0, nseg = 0;
+  void* mem = nullptr;
+  int64_t bytes = 0;
+  float *W1p, *ckpt, *seg_s, *X, *H1, *H2, *Y, *act, *lo, *loss_acc, *g_a, *g_b, *ga, *gY;
+  float* gflat_tail;  // gb1 .. gb3 contiguous (POLICY_N_PARAMS - kOffB1 floats)
+  int* hit;
+  MlpGradBufs gb;
+  const float *theta = nullptr, *s0 = nullptr, *goal = nullptr;
+  bool have_fwd = false;
+  // optional HIP-event timing of the main kernel classes (BPTT_T_*)
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, int>> ev_pairs[BPTT_T_COUNT];  // (start, stop) indices per class
+  int ev_next = 0;
+};
+
+namespace da {
+// Records an event on the stream when timing is on; returns its pool index.
+static int tmark(bptt_handle* b, hipStream_t st) {
+  if (!b->timing) return -1;
+  if (b->ev_next >= (int)b->ev_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return -1;
+    b->ev_pool.push_back(e);
+  }
+  const int k = b->ev_next++;
+  (void)hipEventRecord(b->ev_pool[k], st);
+  return k;
+}
+static void tpair(bptt_handle* b, int cls, int a, int z) {
+  if (a >= 0 && z >= 0) b->ev_pairs[cls].push_back({a, z});
+}
+}  // namespace da
+
+static int check_policy_sim(const sim_handle* h) {
+  DA_REQUIRE(h->cfg.model == SIM_PM9 || h->cfg.model == SIM_RB13, "bptt: model must be PM9 or RB13");
+  DA_REQUIRE(h->cfg.cam_w == 64 && h->cfg.cam_h == 48, "bptt: the policy expects a 64x48 camera");
+  DA_REQUIRE(h->has_scene, "bptt: scene not set");
+  DA_REQUIRE(h->params, "bptt: parameters not set");
+  return SIM_OK;
+}
+
+extern "C" {
+
+int bptt_create(sim_handle* sim, const bptt_config* cfg, bptt_handle** out) {
+  DA_REQUIRE(sim && cfg && out, "bptt_create: null argument");
+  *out = nullptr;
+  int rc = check_policy_sim(sim);
+  if (rc) return rc;
+  DA_REQUIRE(cfg->T >= 1 && cfg->K >= 1 && cfg->K <= cfg->T, "bptt_create: need 1 <= K <= T");
+  DA_REQUIRE(cfg->beta > 0.f, "bptt_create: beta must be > 0");
+  bptt_handle* b = new bptt_handle();
+  b->sim = sim;
+  b->cfg = *cfg;
+  const int A = sim->cfg.n_agents, C = state_dim(sim->cfg.model), Ka = action_dim(sim->cfg.model);
+  const int K = cfg->K;
+  b->A = A;
+  b->C = C;
+  b->Ka = Ka;
+  b->nseg = cdiv(cfg->T, K);
+  // carve one allocation
+  std::vector<std::pair<void**, size_t>> parts;
+  auto add = [&](auto** p, size_t bytes) { parts.push_back({reinterpret_cast<void**>(p), (bytes + 255) & ~size_t(255)}); };
+  add(&b->W1p, (size_t)kHid * kObsPad * 4);
+  add(&b->ckpt, (size_t)b->nseg * C * A * 4);
+  add(&b->seg_s, (size_t)(K + 1) * C * A * 4);
+  add(&b->X, (size_t)K * A * kObsPad * 4);
+  add(&b->hit, (size_t)K * A * kRays * 4);
+  add(&b->H1, (size_t)K * A * kHid * 4);
+  add(&b->H2, (size_t)K * A * kHid * 4);
+  add(&b->Y, (size_t)K * A * kOut * 4);
+  add(&b->act, (size_t)K * Ka * A * 4);
+  add(&b->lo, (size_t)A * 4);
+  add(&b->loss_acc, (size_t)A * 4);
+  add(&b->g_a, (size_t)C * A * 4);
+  add(&b->g_b, (size_t)C * A * 4);
+  add(&b->ga, (size_t)Ka * A * 4);
+  add(&b->gY, (size_t)A * kOut * 4);
+  add(&b->gb.gW1p, (size_t)kHid * kObsPad * 4);
+  add(&b->gflat_tail, (size_t)(POLICY_N_PARAMS - kOffB1) * 4);
+  add(&b->gb.gZ3, (size_t)A * kOut * 4);
+  add(&b->gb.gZ2, (size_t)A * kHid * 4);
+  add(&b->gb.gZ1, (size_t)A * kHid * 4);
+  add(&b->gb.gX, (size_t)A * kObsPad * 4);
+  add(&b->gb.part, partial_floats(A) * 4);
+  size_t total = 0;
+  for (auto& p : parts) total += p.second;
+  hipError_t e = hipMalloc(&b->mem, total);
+  if (e != hipSuccess) {
+    delete b;
+    return fail(SIM_ENOMEM, "bptt_create: cannot allocate %zu bytes: %s", total, hipGetErrorString(e));
+  }
+  char* p = reinterpret_cast<char*>(b->mem);
+  for (auto& q : parts) {
+    *q.first = p;
+    p += q.second;
+  }
+  b->bytes = (int64_t)total;
+  b->gb.gb1 = b->gflat_tail;
+  b->gb.gW2 = b->gflat_tail + (kOffW2 - kOffB1);
+  b->gb.gb2 = b->gflat_tail + (kOffB2 - kOffB1);
+  b->gb.gW3 = b->gflat_tail + (kOffW3 - kOffB1);
+  b->gb.gb3 = b->gflat_tail + (kOffB3 - kOffB1);
+  *out = b;
+  return SIM_OK;
+}
+
+int bptt_destroy(bptt_handle* b) {
+  if (!b) return SIM_OK;
+  for (hipEvent_t e : b->ev_pool) (void)hipEventDestroy(e);
+  if (b->mem) (void)hipFree(b->mem);
+  delete b;
+  return SIM_OK;
+}
+
+int64_t bptt_workspace_bytes(const bptt_handle* b) { return b ? b->bytes : 0; }
+
+int bptt_set_timing(bptt_handle* b, int32_t enable) {
+  DA_REQUIRE(b, "bptt_set_timing: null handle");
+  b->timing = enable != 0;
+  for (auto& v : b->ev_pairs) v.clear();
+  b->ev_next = 0;
+  return SIM_OK;
+}
+
+int bptt_get_timing(bptt_handle* b, float* ms, int32_t* count, int32_t n) {
+  DA_REQUIRE(b && ms && count && n >= 0, "bptt_get_timing: null argument");
+  for (int c = 0; c < n && c < BPTT_T_COUNT; ++c) {
+    double tot = 0.0;
+    for (auto& pr : b->ev_pairs[c]) {
+      DA_HIP(hipEventSynchronize(b->ev_pool[pr.second]));
+      float t = 0.f;
+      DA_HIP(hipEventElapsedTime(&t, b->ev_pool[pr.first], b->ev_pool[pr.second]));
+      tot += t;
+    }
+    ms[c] = (float)tot;
+    count[c] = (int32_t)b->ev_pairs[c].size();
+  }
+  for (int c = BPTT_T_COUNT; c < n; ++c) {
+    ms[c] = 0.f;
+    count[c] = 0;
+  }
+  return SIM_OK;
+}
+
+}  // extern "C"
+
+namespace da {
+
+// One forward step t: render s -> X slot, observation, MLP, action, step.
+static int forward_step(bptt_handle* b, const PolicyPtrs& pp, const float* s, float* s_next, float* X,
+                        int* hit, float* H1, float* H2, float* Y, float* act, hipStream_t st) {
+  sim_handle* h = b->sim;
+  const int A = b->A;
+  const float dmax = h->cfg.cam_max;
+  int e0 = tmark(b, st);
+  int rc = launch_render(h->scene, h->cam.dev, h->cfg.model == SIM_RB13, h->cfg.fov_cull != 0, s, A, X,
+                         hit, kObsPad, 1.0f / dmax, st);
+  if (rc) return rc;
+  tpair(b, BPTT_T_RENDER, e0, tmark(b, st));
+  hipLaunchKernelGGL(obs_fwd_kernel, dim3(A), dim3(256), 0, st, A, h->cfg.model, X, s, b->goal, dmax,
+                     b->cfg.beta, b->cfg.d_safe, b->lo);
+  DA_LAUNCH_CHECK("obs_fwd_kernel");
+  if ((rc = mlp_forward(A, pp, X, H1, H2, Y, st, b))) return rc;
+  hipLaunchKernelGGL(action_kernel, dim3(cdiv(A, 256)), dim3(256), 0, st, A, h->cfg.model, Y, h->params,
+                     act);
+  DA_LAUNCH_CHECK("action_kernel");
+  e0 = tmark(b, st);
+  rc = launch_step(h->cfg.model, h->cfg.integrator, A, h->cfg.dt, s, act, h->params, s_next, nullptr, st);
+  tpair(b, BPTT_T_STEP, e0, tmark(b, st));
+  return rc;
+}
+
+}  // namespace da
+
+extern "C" {
+
+int bptt_forward(bptt_handle* b, const float* theta, const float* s0, const float* goal, float* loss,
+                 float* s_T, void* stream) {
+  DA_REQUIRE(b && theta && s0 && goal && loss, "bptt_forward: null argument");
+  hipStream_t st = as_stream(stream);
+  const int A = b->A, C = b->C, K = b->cfg.K, T = b->cfg.T;
+  b->theta = theta;
+  b->s0 = s0;
+  b->goal = goal;
+  int rc = launch_pad_rows(kHid, kObs, kObsPad, theta + kOffW1, kObs, b->W1p, st);
+  if (rc) return rc;
+  const PolicyPtrs pp = policy_ptrs(theta, b->W1p);
+  DA_HIP(hipMemsetAsync(b->loss_acc, 0, (size_t)A * 4, st));
+  const size_t sbytes = (size_t)C * A * 4;
+  float* cur = b->seg_s;
+  float* nxt = b->seg_s + (size_t)C * A;
+  DA_HIP(hipMemcpyAsync(cur, s0, sbytes, hipMemcpyDeviceToDevice, st));
+  LossW w{b->cfg.w_p, b->cfg.w_v, b->cfg.w_u, b->cfg.w_o, b->cfg.beta, b->cfg.d_safe};
+  for (int t = 0; t < T; ++t) {
+    if (t % K == 0) DA_HIP(hipMemcpyAsync(b->ckpt + (size_t)(t / K) * C * A, cur, sbytes, hipMemcpyDeviceToDevice, st));
+    if ((rc = forward_step(b, pp, cur, nxt, b->X, nullptr, b->H1, b->H2, b->Y, b->act, st))) return rc;
+    hipLaunchKernelGGL(loss_step_kernel, dim3(cdiv(A, 256)), dim3(256), 0, st, A, nxt, goal, b->Y, b->lo, w,
+                       b->loss_acc);
+    DA_LAUNCH_CHECK("loss_step_kernel");
+    std::swap(cur, nxt);
+  }
+  hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(1024), 0, st, A, b->loss_acc, 1.0f / ((float)A * T),
+                     loss);
+  DA_LAUNCH_CHECK("loss_final_kernel");
+  if (s_T) DA_HIP(hipMemcpyAsync(s_T, cur, sbytes, hipMemcpyDeviceToDevice, st));
+  b->have_fwd = true;
+  return SIM_OK;
+}
+
+int bptt_backward(bptt_handle* b, const float* g_loss, float* g_theta, float* g_s0, void* stream) {
+  DA_REQUIRE(b && g_theta, "bptt_backward: null argument");
+  DA_REQUIRE(b->have_fwd, "bptt_backward: call bptt_forward first");
+  hipStream_t st = as_stream(stream);
+  sim_handle* h = b->sim;
+  const int A = b->A, C = b->C, Ka = b->Ka, K = b->cfg.K, T = b->cfg.T;
+  const PolicyPtrs pp = policy_ptrs(b->theta, b->W1p);
+  const size_t sbytes = (size_t)C * A * 4;
+  const float AT = (float)A * T;
+  const float cp = 2.f * b->cfg.w_p / AT, cv = 2.f * b->cfg.w_v / AT, cu = 2.f * b->cfg.w_u / AT;
+  const float co = b->cfg.w_o / (AT * kRays);
+  DA_HIP(hipMemsetAsync(b->gb.gW1p, 0, (size_t)kHid * kObsPad * 4, st));
+  DA_HIP(hipMemsetAsync(b->gflat_tail, 0, (POLICY_N_PARAMS - kOffB1) * 4, st));
+  float* g_next = b->g_a;
+  float* g_cur = b->g_b;
+  DA_HIP(hipMemsetAsync(g_next, 0, sbytes, st));
+  int rc;
+  for (int seg = b->nseg - 1; seg >= 0; --seg) {
+    const int t0 = seg * K, n = std::min(T, t0 + K) - t0;
+    DA_HIP(hipMemcpyAsync(b->seg_s, b->ckpt + (size_t)seg * C * A, sbytes, hipMemcpyDeviceToDevice, st));
+    for (int j = 0; j < n; ++j) {
+      rc = forward_step(b, pp, b->seg_s + (size_t)j * C * A, b->seg_s + (size_t)(j + 1) * C * A,
+                        b->X + (size_t)j * A * kObsPad, b->hit + (size_t)j * A * kRays,
+                        b->H1 + (size_t)j * A * kHid, b->H2 + (size_t)j * A * kHid,
+                        b->Y + (size_t)j * A * kOut, b->act + (size_t)j * Ka * A, st);
+      if (rc) return rc;
+    }
+    for (int j = n - 1; j >= 0; --j) {
+      const float* s = b->seg_s + (size_t)j * C * A;
+      const float* s1 = b->seg_s + (size_t)(j + 1) * C * A;
+      const float* X = b->X + (size_t)j * A * kObsPad;
+      const float* Y = b->Y + (size_t)j * A * kOut;
+      const float* act = b->act + (size_t)j * Ka * A;
+      hipLaunchKernelGGL(loss_state_grad_kernel, dim3(cdiv(A, 256)), dim3(256), 0, st, A, s1, b->goal, cp,
+                         cv, g_loss, g_next);
+      DA_LAUNCH_CHECK("loss_state_grad_kernel");
+      int e0 = tmark(b, st);
+      if ((rc = launch_step_vjp(h->cfg.model, h->cfg.integrator, A, h->cfg.dt, s, act, h->params, g_next,
+                                g_cur, b->ga, st)))
+        return rc;
+      tpair(b, BPTT_T_STEP_VJP, e0, tmark(b, st));
+      hipLaunchKernelGGL(action_bwd_kernel, dim3(cdiv(A, 256)), dim3(256), 0, st, A, h->cfg.model, b->ga,
+                         Y, h->params, cu, g_loss, b->gY);
+      DA_LAUNCH_CHECK("action_bwd_kernel");
+      b->gb.owner = b;
+      if ((rc = mlp_backward(A, pp, X, b->H1 + (size_t)j * A * kHid, b->H2 + (size_t)j * A * kHid, Y,
+                             b->gY, b->gb, st)))
+        return rc;
+      hipLaunchKernelGGL(obs_bwd_kernel, dim3(A), dim3(256), 0, st, A, h->cfg.model, b->gb.gX, X, s,
+                         h->cfg.cam_max, b->cfg.beta, b->cfg.d_safe, co, g_loss, g_cur);
+      DA_LAUNCH_CHECK("obs_bwd_kernel");
+      e0 = tmark(b, st);
+      if ((rc = launch_render_vjp(h->scene, h->cam.dev, h->cfg.model == SIM_RB13, s, A, b->gb.gX,
+                                  kObsPad, b->hit + (size_t)j * A * kRays, g_cur, st)))
+        return rc;
+      tpair(b, BPTT_T_RENDER_VJP, e0, tmark(b, st));
+      std::swap(g_next, g_cur);
+    }
+  }
+  if (g_s0) DA_HIP(hipMemcpyAsync(g_s0, g_next, sbytes, hipMemcpyDeviceToDevice, st));
+  return write_flat_grad(b->gb, g_theta, st);
+}
+
+// ---------------------------------------------------------------------------
+// standalone policy calls (allocate their scratch per call; synchronous)
+// ---------------------------------------------------------------------------
+int policy_forward(const float* theta, const float* x, float* y, int32_t B, void* stream) {
+  DA_REQUIRE(theta && x && y && B >= 0, "policy_forward: bad argument");
+  if (B == 0) return SIM_OK;
+  int rc = require_device();
+  if (rc) return rc;
+  hipStream_t st = as_stream(stream);
+  float* mem = nullptr;
+  const size_t nW = (size_t)kHid * kObsPad, nX = (size_t)B * kObsPad, nH = (size_t)B * kHid;
+  DA_HIP(hipMalloc(&mem, (nW + nX + 2 * nH) * 4));
+  float *W1p = mem, *X = W1p + nW, *H1 = X + nX, *H2 = H1 + nH;
+  rc = launch_pad_rows(kHid, kObs, kObsPad, theta + kOffW1, kObs, W1p, st);
+  if (!rc) rc = launch_pad_rows(B, kObs, kObsPad, x, kObs, X, st);
+  if (!rc) rc = mlp_forward(B, policy_ptrs(theta, W1p), X, H1, H2, y, st);
+  hipError_t e = hipStreamSynchronize(st);
+  (void)hipFree(mem);
+  if (rc) return rc;
+  if (e != hipSuccess) return fail(SIM_EHIP, "policy_forward: %s", hipGetErrorString(e));
+  return SIM_OK;
+}
+
+int policy_backward(const float* theta, const float* x, const float* g_y, float* g_theta, float* g_x,
+                    int32_t B, void* stream) {
+  DA_REQUIRE(theta && x && g_y && g_theta && B >= 1, "policy_backward: bad argument");
+  int rc = require_device();
+  if (rc) return rc;
+  hipStream_t st = as_stream(stream);
+  const size_t nW = (size_t)kHid * kObsPad, nX = (size_t)B * kObsPad, nH = (size_t)B * kHid;
+  const size_t nY = (size_t)B * kOut, nT = POLICY_N_PARAMS - kOffB1;
+  const size_t total = 2 * nW + 2 * nX + 4 * nH + 2 * nY + nT + partial_floats(B) + 64;
+  float* mem = nullptr;
+  DA_HIP(hipMalloc(&mem, total * 4));
+  float *W1p = mem, *X = W1p + nW, *H1 = X + nX, *H2 = H1 + nH, *Y = H2 + nH;
+  MlpGradBufs gb;
+  gb.gW1p = Y + nY;
+  float* tail = gb.gW1p + nW;
+  gb.gb1 = tail;
+  gb.gW2 = tail + (kOffW2 - kOffB1);
+  gb.gb2 = tail + (kOffB2 - kOffB1);
+  gb.gW3 = tail + (kOffW3 - kOffB1);
+  gb.gb3 = tail + (kOffB3 - kOffB1);
+  gb.gZ3 = tail + nT;
+  gb.gZ2 = gb.gZ3 + nY;
+  gb.gZ1 = gb.gZ2 + nH;
+  gb.gX = gb.gZ1 + nH;
+  gb.part = gb.gX + nX;
+  const PolicyPtrs pp = policy_ptrs(theta, W1p);
+  rc = launch_pad_rows(kHid, kObs, kObsPad, theta + kOffW1, kObs, W1p, st);
+  if (!rc) rc = launch_pad_rows(B, kObs, kObsPad, x, kObs, X, st);
+  if (!rc && hipMemsetAsync(gb.gW1p, 0, (nW + nT) * 4, st) != hipSuccess) rc = fail(SIM_EHIP, "memset");
+  if (!rc) rc = mlp_forward(B, pp, X, H1, H2, Y, st);
+  if (!rc) rc = mlp_backward(B, pp, X, H1, H2, Y, g_y, gb, st);
+  if (!rc) rc = write_flat_grad(gb, g_theta, st);
+  if (!rc && g_x) rc = launch_pad_rows(B, kObs, kObs, gb.gX, kObsPad, g_x, st);
+  hipError_t e = hipStreamSynchronize(st);
+  (void)hipFree(mem);
+  if (rc) return rc;
+  if (e != hipSuccess) return fail(SIM_EHIP, "policy_backward: %s", hipGetErrorString(e));
+  return SIM_OK;
+}
+
+}  // extern "C"

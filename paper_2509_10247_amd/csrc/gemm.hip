@@ -1,0 +1,343 @@
+// Dense layers of the policy MLP on the FP32 matrix cores (MFMA) of gfx950,
+// plus the small kernels around them (narrow output layer, column sums,
+// split-K reduction, Adam).
+//
+// GEMM: C[M][N] = op(A)[M][K] * op(B)[K][N] with a fused epilogue. Operands are
+// either K-contiguous (A[m][k], B[n][k]) or MN-contiguous (A[k][m], B[k][n]);
+// both are staged through LDS in [BK][BM+pad] layout, so that each lane's MFMA
+// operand is a bank-conflict-free 32-bit LDS read. Workgroup tile 128x128x32,
+// 4 wavefronts in a 2x2 grid, each owning a 64x64 block = 2x2 MFMA
+// v_mfma_f32_32x32x2f32 tiles (64 accumulators per lane). The next K-tile is
+// prefetched into registers while the current one is multiplied.
+#include "kernels.h"
+#include "mlp.h"
+
+namespace da {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int GBM = 128, GBN = 128, GBK = 32;
+
+template <bool KMAJ>
+struct Stage {
+  // LDS row pitch (floats): K-contiguous operands are written transposed with
+  // scalar stores (pitch 130 spreads the 8x8 lane pattern over all banks);
+  // MN-contiguous operands are written with 16-byte stores (pitch 132).
+  static constexpr int PITCH = KMAJ ? GBM + 2 : GBM + 4;
+};
+
+// Loads one 128 x 32 operand tile (rows r0.., k0..) into 4 float4 registers.
+// Rows beyond nrows and k beyond K are zero.
+template <bool KMAJ>
+__device__ __forceinline__ void load_tile(const float* __restrict__ P, int ld, int nrows, int K, int r0,
+                                          int k0, float4 (&reg)[4]) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    if (KMAJ) {
+      const int row = (t >> 3) + 32 * i, k = k0 + (t & 7) * 4;
+      const int gr = r0 + row;
+      if (gr < nrows && k < K)
+        reg[i] = *reinterpret_cast<const float4*>(P + (size_t)gr * ld + k);
+      else
+        reg[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    } else {
+      const int kk = (t >> 5) + 8 * i, m = r0 + (t & 31) * 4;
+      const int gk = k0 + kk;
+      if (gk < K && m < nrows)
+        reg[i] = *reinterpret_cast<const float4*>(P + (size_t)gk * ld + m);
+      else
+        reg[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  }
+}
+
+template <bool KMAJ>
+__device__ __forceinline__ void store_tile(float* S, const float4 (&reg)[4]) {
+  constexpr int P = Stage<KMAJ>::PITCH;
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    if (KMAJ) {
+      const int row = (t >> 3) + 32 * i, k = (t & 7) * 4;
+      S[(k + 0) * P + row] = reg[i].x;
+      S[(k + 1) * P + row] = reg[i].y;
+      S[(k + 2) * P + row] = reg[i].z;
+      S[(k + 3) * P + row] = reg[i].w;
+    } else {
+      const int kk = (t >> 5) + 8 * i, m = (t & 31) * 4;
+      *reinterpret_cast<float4*>(S + kk * P + m) = reg[i];
+    }
+  }
+}
+
+template <bool AK, bool BK_, int EPI>
+__global__ __launch_bounds__(256) void gemm_f32_kernel(GemmArgs g) {
+  constexpr int PA = Stage<AK>::PITCH, PB = Stage<BK_>::PITCH;
+  __shared__ __attribute__((aligned(16))) float As[GBK * PA];
+  __shared__ __attribute__((aligned(16))) float Bs[GBK * PB];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  const int m0 = blockIdx.y * GBM, n0 = blockIdx.x * GBN;
+  const int kbeg = blockIdx.z * g.k_split;
+  const int kend = min(g.K, kbeg + g.k_split);
+
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) acc[a][b][i] = 0.f;
+
+  float4 ra[4], rb[4];
+  if (kbeg < kend) {
+    load_tile<AK>(g.A, g.lda, g.M, kend, m0, kbeg, ra);
+    load_tile<BK_>(g.B, g.ldb, g.N, kend, n0, kbeg, rb);
+  }
+  const int col = lane & 31, half = lane >> 5;
+  for (int k0 = kbeg; k0 < kend; k0 += GBK) {
+    __syncthreads();
+    store_tile<AK>(As, ra);
+    store_tile<BK_>(Bs, rb);
+    __syncthreads();
+    if (k0 + GBK < kend) {
+      load_tile<AK>(g.A, g.lda, g.M, kend, m0, k0 + GBK, ra);
+      load_tile<BK_>(g.B, g.ldb, g.N, kend, n0, k0 + GBK, rb);
+    }
+#pragma unroll
+    for (int s = 0; s < GBK / 2; ++s) {
+      const int k = 2 * s + half;
+      const float a0 = As[k * PA + wm + col], a1 = As[k * PA + wm + 32 + col];
+      const float b0 = Bs[k * PB + wn + col], b1 = Bs[k * PB + wn + 32 + col];
+      acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[1][1], 0, 0, 0);
+    }
+  }
+
+  // epilogue: lane holds column (lane & 31) of each 32x32 tile, rows
+  // 8*(i/4) + 4*(lane/32) + (i%4) for accumulator i
+  float* C = g.C;
+  if (EPI == EPI_PARTIAL) C += (size_t)blockIdx.z * g.M * g.ldc;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int n = n0 + wn + 32 * b + col;
+      if (n >= g.N) continue;
+      float bias = 0.f;
+      if (EPI == EPI_BIAS_TANH) bias = g.bias[n];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int m = m0 + wm + 32 * a + 8 * (i >> 2) + 4 * half + (i & 3);
+        if (m >= g.M) continue;
+        const size_t idx = (size_t)m * g.ldc + n;
+        float v = acc[a][b][i];
+        if (EPI == EPI_BIAS_TANH) {
+          v = tanhf(v + bias);
+        } else if (EPI == EPI_MUL_DTANH) {
+          const float h = g.aux[(size_t)m * g.ld_aux + n];
+          v = v * (1.f - h * h);
+        } else if (EPI == EPI_ACCUM) {
+          v += C[idx];
+        }
+        C[idx] = v;
+      }
+    }
+}
+
+template <bool AK, bool BK_, int EPI>
+static int gemm_t(const GemmArgs& g, int splits, hipStream_t st) {
+  dim3 grid(cdiv(g.N, GBN), cdiv(g.M, GBM), splits);
+  hipLaunchKernelGGL((gemm_f32_kernel<AK, BK_, EPI>), grid, dim3(256), 0, st, g);
+  DA_LAUNCH_CHECK("gemm_f32_kernel");
+  return SIM_OK;
+}
+
+int launch_gemm(bool a_kmaj, bool b_kmaj, int epi, GemmArgs g, int splits, hipStream_t st) {
+  if (g.M == 0 || g.N == 0) return SIM_OK;
+  if (splits < 1) splits = 1;
+  g.k_split = (int)(cdiv64(cdiv64(g.K, splits), GBK) * GBK);
+  splits = g.K > 0 ? cdiv(g.K, g.k_split) : 1;
+  if (epi != EPI_PARTIAL && splits != 1) return fail(SIM_EINVAL, "gemm: split-K needs EPI_PARTIAL");
+  if ((g.lda & 3) || (g.ldb & 3) || (reinterpret_cast<uintptr_t>(g.A) & 15) ||
+      (reinterpret_cast<uintptr_t>(g.B) & 15))
+    return fail(SIM_EINVAL, "gemm: operands need 16-byte alignment and leading dims %% 4 == 0");
+  const int key = (a_kmaj ? 1 : 0) | (b_kmaj ? 2 : 0);
+#define DA_GEMM_CASE(AK, BKM)                                              \
+  switch (epi) {                                                          \
+    case EPI_STORE: return gemm_t<AK, BKM, EPI_STORE>(g, 1, st);          \
+    case EPI_BIAS_TANH: return gemm_t<AK, BKM, EPI_BIAS_TANH>(g, 1, st);  \
+    case EPI_MUL_DTANH: return gemm_t<AK, BKM, EPI_MUL_DTANH>(g, 1, st);  \
+    case EPI_ACCUM: return gemm_t<AK, BKM, EPI_ACCUM>(g, 1, st);          \
+    case EPI_PARTIAL: return gemm_t<AK, BKM, EPI_PARTIAL>(g, splits, st); \
+  }
+  switch (key) {
+    case 0: DA_GEMM_CASE(false, false) break;
+    case 1: DA_GEMM_CASE(true, false) break;
+    case 2: DA_GEMM_CASE(false, true) break;
+    case 3: DA_GEMM_CASE(true, true) break;
+  }
+#undef DA_GEMM_CASE
+  return fail(SIM_EINVAL, "gemm: bad epilogue %d", epi);
+}
+
+int gemm_splits_used(int K, int splits) {
+  if (splits < 1) splits = 1;
+  const int ks = (int)(cdiv64(cdiv64(K, splits), GBK) * GBK);
+  return K > 0 ? cdiv(K, ks) : 1;
+}
+
+// ---------------------------------------------------------------------------
+// small kernels
+// ---------------------------------------------------------------------------
+
+// out[m][n] (+)= sum_s part[s][m][n], fixed summation order (deterministic).
+__global__ void splitk_reduce_kernel(int S, int M, int N, int ldp, const float* __restrict__ part,
+                                     float* __restrict__ out, int ldo, int accumulate) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= M * N) return;
+  const int m = idx / N, n = idx % N;
+  float v = 0.f;
+  for (int s = 0; s < S; ++s) v += part[(size_t)s * M * ldp + (size_t)m * ldp + n];
+  if (accumulate) v += out[(size_t)m * ldo + n];
+  out[(size_t)m * ldo + n] = v;
+}
+
+int launch_splitk_reduce(int S, int M, int N, int ldp, const float* part, float* out, int ldo,
+                         bool accumulate, hipStream_t st) {
+  const int tot = M * N;
+  hipLaunchKernelGGL(splitk_reduce_kernel, dim3(cdiv(tot, 256)), dim3(256), 0, st, S, M, N, ldp,
+                     part, out, ldo, accumulate ? 1 : 0);
+  DA_LAUNCH_CHECK("splitk_reduce_kernel");
+  return SIM_OK;
+}
+
+// out[n] (+)= sum_m X[m][n]: each block owns 64 columns; 4 row-groups of
+// threads accumulate fixed strided row sets, then combine in a fixed order.
+__global__ void colsum_kernel(int M, int N, const float* __restrict__ X, int ld,
+                              float* __restrict__ out, int accumulate) {
+  __shared__ float red[4][64];
+  const int c = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int g = threadIdx.x >> 6;
+  float v = 0.f;
+  if (c < N)
+    for (int m = g; m < M; m += 4) v += X[(size_t)m * ld + c];
+  red[g][threadIdx.x & 63] = v;
+  __syncthreads();
+  if (g == 0 && c < N) {
+    float s = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
+    out[c] = accumulate ? out[c] + s : s;
+  }
+}
+
+int launch_colsum(int M, int N, const float* X, int ld, float* out, bool accumulate, hipStream_t st) {
+  hipLaunchKernelGGL(colsum_kernel, dim3(cdiv(N, 64)), dim3(256), 0, st, M, N, X, ld, out,
+                     accumulate ? 1 : 0);
+  DA_LAUNCH_CHECK("colsum_kernel");
+  return SIM_OK;
+}
+
+// Narrow output layer: Y[b][o] = tanh(sum_j H[b][j] W[o][j] + bias[o]), O <= 8.
+__global__ void narrow_fwd_kernel(int B, int J, int O, const float* __restrict__ H, int ldh,
+                                  const float* __restrict__ W, const float* __restrict__ bias,
+                                  float* __restrict__ Y) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= B * O) return;
+  const int b = idx / O, o = idx % O;
+  const float4* h = reinterpret_cast<const float4*>(H + (size_t)b * ldh);
+  const float4* w = reinterpret_cast<const float4*>(W + (size_t)o * J);
+  float acc = 0.f;
+  for (int j = 0; j < J / 4; ++j) {
+    const float4 x = h[j], y = w[j];
+    acc += x.x * y.x + x.y * y.y + x.z * y.z + x.w * y.w;
+  }
+  Y[idx] = tanhf(acc + bias[o]);
+}
+
+int launch_narrow_fwd(int B, int J, int O, const float* H, int ldh, const float* W,
+                      const float* bias, float* Y, hipStream_t st) {
+  hipLaunchKernelGGL(narrow_fwd_kernel, dim3(cdiv(B * O, 256)), dim3(256), 0, st, B, J, O, H, ldh,
+                     W, bias, Y);
+  DA_LAUNCH_CHECK("narrow_fwd_kernel");
+  return SIM_OK;
+}
+
+// Backward of the narrow layer into the previous tanh layer:
+// gZ3 = gY (1 - Y^2); gZ2[b][j] = (sum_o gZ3[b][o] W[o][j]) (1 - H[b][j]^2).
+__global__ void narrow_bwd_kernel(int B, int J, int O, const float* __restrict__ gY,
+                                  const float* __restrict__ Y, const float* __restrict__ W,
+                                  const float* __restrict__ H, int ldh, float* __restrict__ gZ3,
+                                  float* __restrict__ gZ2) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= B * J) return;
+  const int b = idx / J, j = idx % J;
+  float acc = 0.f;
+  for (int o = 0; o < O; ++o) {
+    const float y = Y[b * O + o];
+    const float gz = gY[b * O + o] * (1.f - y * y);
+    acc += gz * W[o * J + j];
+    if (j == 0) gZ3[b * O + o] = gz;
+  }
+  const float h = H[(size_t)b * ldh + j];
+  gZ2[(size_t)b * ldh + j] = acc * (1.f - h * h);
+}
+
+int launch_narrow_bwd(int B, int J, int O, const float* gY, const float* Y, const float* W,
+                      const float* H, int ldh, float* gZ3, float* gZ2, hipStream_t st) {
+  hipLaunchKernelGGL(narrow_bwd_kernel, dim3(cdiv(B * J, 256)), dim3(256), 0, st, B, J, O, gY, Y, W,
+                     H, ldh, gZ3, gZ2);
+  DA_LAUNCH_CHECK("narrow_bwd_kernel");
+  return SIM_OK;
+}
+
+__global__ void adam_kernel(int64_t n, float* __restrict__ w, const float* __restrict__ g,
+                            float* __restrict__ m, float* __restrict__ v, float lr, float b1, float b2,
+                            float eps, float c1, float c2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+int launch_adam(int64_t n, float* w, const float* g, float* m, float* v, float lr, float b1, float b2,
+                float eps, int t, hipStream_t st) {
+  const float c1 = 1.f - powf(b1, (float)t), c2 = 1.f - powf(b2, (float)t);
+  hipLaunchKernelGGL(adam_kernel, dim3((unsigned)cdiv64(n, 256)), dim3(256), 0, st, n, w, g, m, v, lr,
+                     b1, b2, eps, c1, c2);
+  DA_LAUNCH_CHECK("adam_kernel");
+  return SIM_OK;
+}
+
+// Copies a [rows][cols] row-major block to a [rows][ld] block (zero pad to ld).
+__global__ void pad_rows_kernel(int rows, int cols, int ld, const float* __restrict__ src, int lds,
+                                float* __restrict__ dst) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)rows * ld) return;
+  const int r = (int)(idx / ld), c = (int)(idx % ld);
+  dst[idx] = c < cols ? src[(size_t)r * lds + c] : 0.f;
+}
+
+int launch_pad_rows(int rows, int cols, int ld, const float* src, int lds, float* dst, hipStream_t st) {
+  const int64_t tot = (int64_t)rows * ld;
+  hipLaunchKernelGGL(pad_rows_kernel, dim3((unsigned)cdiv64(tot, 256)), dim3(256), 0, st, rows, cols, ld,
+                     src, lds, dst);
+  DA_LAUNCH_CHECK("pad_rows_kernel");
+  return SIM_OK;
+}
+
+}  // namespace da
+
+extern "C" int adam_step(int64_t n, float* w, const float* g, float* m, float* v, float lr, float b1,
+                         float b2, float eps, int32_t t, void* stream) {
+  DA_REQUIRE(n >= 0 && (n == 0 || (w && g && m && v)), "adam_step: null argument");
+  DA_REQUIRE(t >= 1, "adam_step: t must be >= 1");
+  if (n == 0) return SIM_OK;
+  return da::launch_adam(n, w, g, m, v, lr, b1, b2, eps, t, da::as_stream(stream));
+}

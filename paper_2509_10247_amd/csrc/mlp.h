@@ -1,0 +1,41 @@
+// Internal interface of the dense-layer kernels (gemm.hip).
+#pragma once
+
+#include "kernels.h"
+
+namespace da {
+
+enum { EPI_STORE = 0, EPI_BIAS_TANH = 1, EPI_MUL_DTANH = 2, EPI_ACCUM = 3, EPI_PARTIAL = 4 };
+
+// C[M][N] = op(A) op(B). A is [M][lda] (K-contiguous) or [K][lda]
+// (M-contiguous); B is [N][ldb] (K-contiguous) or [K][ldb] (N-contiguous).
+// The contiguous extent of each operand must be a multiple of 4 with 16-byte
+// aligned rows. EPI_PARTIAL writes split s to C + s*M*ldc.
+struct GemmArgs {
+  int M = 0, N = 0, K = 0;
+  const float* A = nullptr;
+  int lda = 0;
+  const float* B = nullptr;
+  int ldb = 0;
+  float* C = nullptr;
+  int ldc = 0;
+  const float* bias = nullptr;  // EPI_BIAS_TANH: [N]
+  const float* aux = nullptr;   // EPI_MUL_DTANH: H [M][ld_aux]
+  int ld_aux = 0;
+  int k_split = 0;              // set by launch_gemm
+};
+
+int launch_gemm(bool a_kmaj, bool b_kmaj, int epi, GemmArgs g, int splits, hipStream_t st);
+int gemm_splits_used(int K, int splits);
+int launch_splitk_reduce(int S, int M, int N, int ldp, const float* part, float* out, int ldo,
+                         bool accumulate, hipStream_t st);
+int launch_colsum(int M, int N, const float* X, int ld, float* out, bool accumulate, hipStream_t st);
+int launch_narrow_fwd(int B, int J, int O, const float* H, int ldh, const float* W, const float* bias,
+                      float* Y, hipStream_t st);
+int launch_narrow_bwd(int B, int J, int O, const float* gY, const float* Y, const float* W,
+                      const float* H, int ldh, float* gZ3, float* gZ2, hipStream_t st);
+int launch_adam(int64_t n, float* w, const float* g, float* m, float* v, float lr, float b1, float b2,
+                float eps, int t, hipStream_t st);
+int launch_pad_rows(int rows, int cols, int ld, const float* src, int lds, float* dst, hipStream_t st);
+
+}  // namespace da

@@ -1,0 +1,23 @@
+// Definition of the opaque sim_handle shared by the host-side translation units.
+#pragma once
+
+#include <vector>
+
+#include "kernels.h"
+
+struct SensorBuf {
+  da::SensorDev dev;
+  void* mem = nullptr;
+};
+
+struct sim_handle {
+  sim_config cfg{};
+  SensorBuf cam, lidar;
+  da::SceneDev scene;
+  int32_t* agent_env = nullptr;        // owned [A]
+  int32_t* agent_off_owned = nullptr;  // owned [E+1] when the caller passes NULL
+  const float* params = nullptr;       // caller's SoA [P][A]
+  std::vector<int32_t> host_sph_off, host_box_off, host_agent_off;
+  int n_sph = 0, n_box = 0;
+  bool has_scene = false;
+};

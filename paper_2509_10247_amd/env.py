@@ -1,0 +1,118 @@
+"""A simulator handle bound to its device buffers.
+
+`Env` uploads a scene (CSR arrays), per-agent parameters and keeps the
+device tensors alive for as long as the C handle references them. Every
+operation is one call into libdiffaero.so.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import _lib
+
+STATE_DIM = {0: 6, 1: 9, 2: 13, 3: 13}
+ACTION_DIM = {0: 3, 1: 3, 2: 4, 3: 4}
+
+
+def _dev(x, dtype):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype).cuda()
+
+
+class Env:
+    def __init__(self, *, n_envs, n_agents, model, integrator, dt, cam=None, lidar=None,
+                 agent_radius=0.15, agents_visible=False, fov_cull=True):
+        cw, ch, chfov, cmax = cam if cam else (0, 0, 90.0, 10.0)
+        lc, la, le0, le1, lmax = lidar if lidar else (0, 0, -15.0, 15.0, 20.0)
+        self.n_envs, self.n_agents = n_envs, n_agents
+        self.model, self.integrator, self.dt = model, integrator, dt
+        self.cam, self.lidar = cam, lidar
+        self.C, self.K = STATE_DIM[model], ACTION_DIM[model]
+        self.h = _lib.sim_create(n_envs=n_envs, n_agents=n_agents, model=model,
+                                 integrator=integrator, dt=dt, cam_w=cw, cam_h=ch,
+                                 cam_hfov_deg=chfov, cam_max=cmax, lidar_ch=lc, lidar_az=la,
+                                 lidar_elev_min_deg=le0, lidar_elev_max_deg=le1, lidar_max=lmax,
+                                 agent_radius=agent_radius, agents_visible=int(agents_visible),
+                                 fov_cull=int(fov_cull))
+        self._keep = {}
+
+    def close(self):
+        if self.h:
+            _lib.sim_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- scene / params --------------------------------------------------
+    def set_scene(self, sph_off, sph, box_off, box, room=None, agent_off=None):
+        k = dict(sph_off=_dev(sph_off, torch.int32),
+                 sph=_dev(np.asarray(sph, np.float32).reshape(-1, 4), torch.float32),
+                 box_off=_dev(box_off, torch.int32),
+                 box=_dev(np.asarray(box, np.float32).reshape(-1, 6), torch.float32),
+                 room=None if room is None else _dev(room, torch.float32),
+                 agent_off=None if agent_off is None else _dev(agent_off, torch.int32))
+        if k["sph"].numel() == 0:
+            k["sph"] = torch.zeros(1, 4, device="cuda")
+        if k["box"].numel() == 0:
+            k["box"] = torch.zeros(1, 6, device="cuda")
+        n_sph = int(np.asarray(sph_off)[-1])
+        n_box = int(np.asarray(box_off)[-1])
+        _lib.sim_set_scene(self.h, k["sph_off"], k["sph"], n_sph, k["box_off"], k["box"], n_box,
+                           k["room"], k["agent_off"])
+        self._keep["scene"] = k
+
+    def set_scene_obj(self, scene):
+        self.set_scene(scene.sph_off, scene.sph, scene.box_off, scene.box, scene.room, scene.agent_off)
+
+    def set_params(self, params):
+        p = _dev(params, torch.float32) if not torch.is_tensor(params) else params.contiguous()
+        if p.numel() == 0:
+            p = torch.zeros(1, device="cuda")
+        _lib.sim_set_params(self.h, p)
+        self._keep["params"] = p
+
+    # -- operations -------------------------------------------------------
+    def step(self, s, a, out=None, flags=None):
+        out = torch.empty_like(s) if out is None else out
+        _lib.sim_step(self.h, s, a, out, flags)
+        return out
+
+    def render(self, s, depth=True, lidar=False, records=True):
+        A = self.n_agents
+        d = hd = l = hl = None
+        if depth and self.cam:
+            d = torch.empty(A, self.cam[1], self.cam[0], device="cuda")
+            hd = torch.empty(A, self.cam[1], self.cam[0], device="cuda", dtype=torch.int32) if records else None
+        if lidar and self.lidar:
+            l = torch.empty(A, self.lidar[0], self.lidar[1], device="cuda")
+            hl = torch.empty(A, self.lidar[0], self.lidar[1], device="cuda", dtype=torch.int32) if records else None
+        _lib.sim_render(self.h, s, d, l, hd, hl)
+        return d, hd, l, hl
+
+    def collide(self, s):
+        flags = torch.zeros(self.n_agents, dtype=torch.uint8, device="cuda")
+        md = torch.empty(self.n_agents, device="cuda")
+        _lib.sim_collide(self.h, s, flags, md)
+        return flags, md
+
+    def step_backward(self, s, a, g_next, g_depth=None, g_lidar=None, hit_cam=None, hit_lidar=None,
+                      want_ga=True):
+        g_s = torch.empty_like(s)
+        g_a = torch.empty_like(a) if want_ga else None
+        _lib.sim_step_backward(self.h, s, a, g_next, g_depth, g_lidar, hit_cam, hit_lidar, g_s, g_a)
+        return g_s, g_a
+
+
+def from_workload(wk, fov_cull=True, agents_visible=None):
+    """Env with the scene and parameters of a workloads.Workload."""
+    sc = wk.scene
+    vis = (int(np.diff(sc.agent_off).max()) > 1) if agents_visible is None else agents_visible
+    e = Env(n_envs=sc.n_envs, n_agents=sc.n_agents, model=wk.model, integrator=wk.integrator,
+            dt=wk.dt, cam=wk.cam, lidar=wk.lidar, agents_visible=vis, fov_cull=fov_cull)
+    e.set_scene_obj(sc)
+    e.set_params(wk.params)
+    return e

@@ -99,40 +99,41 @@ def make_scene(rng: np.random.Generator, n_envs: int, n_sph, n_box,
     n_sph, n_box: int or int array [E] (per-env counts).
     keepout: optional float [A, 3] points (agent start positions, grouped by
       env via agents_per_env); a primitive whose bounding sphere comes within
-      keepout_r of one of its env's points is redrawn (bounded retries).
+      keepout_r of one of its env's points is redrawn (at most 64 rounds).
     """
     n_sph = np.broadcast_to(np.asarray(n_sph, dtype=np.int64), (n_envs,))
     n_box = np.broadcast_to(np.asarray(n_box, dtype=np.int64), (n_envs,))
     if agents_per_env is None:
         agents_per_env = np.ones(n_envs, dtype=np.int64)
+    agents_per_env = np.asarray(agents_per_env, dtype=np.int64)
     agent_off = _csr(agents_per_env)
     lo = np.asarray(vol[:3], np.float64)
     hi = np.asarray(vol[3:], np.float64)
-    sph_list, box_list = [], []
-    for e in range(n_envs):
-        pts = None if keepout is None else keepout[agent_off[e]:agent_off[e + 1]]
-        s = np.empty((n_sph[e], 4))
-        for i in range(n_sph[e]):
+    pts = None
+    if keepout is not None:
+        amax = int(agents_per_env.max())
+        pts = np.full((n_envs, amax, 3), np.inf)
+        lane = np.arange(int(agent_off[-1])) - np.repeat(agent_off[:-1], agents_per_env)
+        pts[np.repeat(np.arange(n_envs), agents_per_env), lane] = keepout
+
+    def draw(counts, draw_one):
+        env = np.repeat(np.arange(n_envs), counts)
+        c, ext = draw_one(len(env))
+        if pts is not None and len(env):
             for _ in range(64):
-                c = rng.uniform(lo, hi)
-                r = rng.uniform(*sph_r)
-                if pts is None or len(pts) == 0 or \
-                        np.min(np.linalg.norm(pts - c, axis=1)) > r + keepout_r:
+                d = np.linalg.norm(pts[env] - c[:, None, :], axis=2).min(axis=1)
+                bad = d <= (np.linalg.norm(ext, axis=1) if ext.ndim == 2 else ext) + keepout_r
+                if not bad.any():
                     break
-            s[i, :3], s[i, 3] = c, r
-        b = np.empty((n_box[e], 6))
-        for i in range(n_box[e]):
-            for _ in range(64):
-                c = rng.uniform(lo, hi)
-                h = rng.uniform(box_h[0], box_h[1], size=3)
-                if pts is None or len(pts) == 0 or \
-                        np.min(np.linalg.norm(pts - c, axis=1)) > np.linalg.norm(h) + keepout_r:
-                    break
-            b[i, :3], b[i, 3:] = c, h
-        sph_list.append(s)
-        box_list.append(b)
-    sph = np.concatenate(sph_list, 0).astype(np.float32) if n_sph.sum() else np.zeros((0, 4), np.float32)
-    box = np.concatenate(box_list, 0).astype(np.float32) if n_box.sum() else np.zeros((0, 6), np.float32)
+                c2, e2 = draw_one(int(bad.sum()))
+                c[bad], ext[bad] = c2, e2
+        return c, ext
+
+    sc, sr = draw(n_sph, lambda n: (rng.uniform(lo, hi, size=(n, 3)), rng.uniform(*sph_r, size=n)))
+    bc, bh = draw(n_box, lambda n: (rng.uniform(lo, hi, size=(n, 3)),
+                                   rng.uniform(box_h[0], box_h[1], size=(n, 3))))
+    sph = np.concatenate([sc, sr[:, None]], 1).astype(np.float32).reshape(-1, 4)
+    box = np.concatenate([bc, bh], 1).astype(np.float32).reshape(-1, 6)
     room_arr = np.tile(np.asarray(vol, np.float32), (n_envs, 1)) if room else None
     return Scene(n_envs, _csr(n_sph), sph, _csr(n_box), box, room_arr, agent_off)
 
