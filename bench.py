@@ -34,12 +34,14 @@ def parse():
     p.add_argument("--envs", type=int, default=16384)
     p.add_argument("--horizon", type=int, default=32)
     p.add_argument("--ckpt", type=int, default=8)
+    p.add_argument("--recompute-all", action="store_true",
+                   help="keep only the K-step state checkpoints (recompute policy and step too)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-kernel-timing", action="store_true")
     return p.parse_args()
 
 
-def cpu_baseline(model, seed=0, n_envs=4, T=32):
+def cpu_baseline(model, seed=0, n_envs=64, T=32):
     """The FP64 oracle (forward rollout + autograd backward) on a bounded
     sample of the same workload, on the host's cores."""
     import numpy as np
@@ -74,7 +76,7 @@ def main():
     wk = wl.bptt(seed=0, n_envs=A, T=T, model=model)
     theta = wl.flatten_mlp(wl.mlp_init(np.random.default_rng(1), wl.POLICY_DIMS))
     e = env.from_workload(wk)
-    eng = bptt.BpttEngine(e, T, K)
+    eng = bptt.BpttEngine(e, T, K, store_activations=not args.recompute_all)
     th = torch.tensor(theta, device="cuda")
     s0 = torch.tensor(wk.state0, device="cuda")
     goal = torch.tensor(wk.goal, device="cuda")
@@ -135,6 +137,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"bptt_{args.model}_rk4_{A}env_T{T}_K{K}_cam64x48_room24sph16box",
                    "envs": A, "horizon": T, "checkpoint_every": K, "env_steps_per_step": A * T,
+                   "stored_activations": not args.recompute_all,
+                   "workspace_bytes": eng.workspace_bytes(),
                    "policy": "mlp 3081-256-256-4 tanh (fp32 mfma)"},
         "roofline": roofline,
         "kernel_breakdown": breakdown,

@@ -174,8 +174,15 @@ int sim_step_backward(sim_handle* h, const float* s_t, const float* a_t, const f
 
 typedef struct bptt_config {
   int32_t T;      /* horizon >= 1 */
-  int32_t K;      /* checkpoint period, 1 <= K <= T; states kept every K steps */
+  int32_t K;      /* checkpoint period, 1 <= K <= T */
   float w_p, w_v, w_u, w_o, beta, d_safe;
+  /* 0: keep the state every K steps; the backward recomputes each K-step
+   *    segment completely (render, policy, step): memory O(T/K + K) steps.
+   * 1: also keep every step's state, policy activations and action (about
+   *    530 floats per agent and step); the backward recomputes only the
+   *    rendered observations and hit records (about 6150 floats per agent and
+   *    step) per segment. Same gradient, bit for bit. */
+  int32_t store_activations;
 } bptt_config;
 
 typedef struct bptt_handle bptt_handle;

@@ -33,7 +33,8 @@ class SimConfig(ctypes.Structure):
 
 class BpttConfig(ctypes.Structure):
     _fields_ = [("T", c_int), ("K", c_int), ("w_p", c_float), ("w_v", c_float), ("w_u", c_float),
-                ("w_o", c_float), ("beta", c_float), ("d_safe", c_float)]
+                ("w_o", c_float), ("beta", c_float), ("d_safe", c_float),
+                ("store_activations", c_int)]
 
 
 _SIGS = {
@@ -177,8 +178,8 @@ def sim_step_backward(h, s_t, a_t, g_s_next, g_depth, g_lidar, hit_cam, hit_lida
 # policy / BPTT
 # --------------------------------------------------------------------------
 
-def bptt_create(h, T, K, w_p, w_v, w_u, w_o, beta, d_safe) -> int:
-    cfg = BpttConfig(T, K, w_p, w_v, w_u, w_o, beta, d_safe)
+def bptt_create(h, T, K, w_p, w_v, w_u, w_o, beta, d_safe, store_activations=1) -> int:
+    cfg = BpttConfig(T, K, w_p, w_v, w_u, w_o, beta, d_safe, int(store_activations))
     b = c_void_p()
     _call("bptt_create", h, ctypes.byref(cfg), ctypes.byref(b))
     return b.value

@@ -37,56 +37,31 @@ static_assert(kOffB3 + kOut == POLICY_N_PARAMS, "policy parameter layout");
 // ---------------------------------------------------------------------------
 // observation, action, loss kernels
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float softplus(float x) { return fmaxf(x, 0.f) + log1pf(expf(-fabsf(x))); }
+// logistic function on the hardware exp2 unit and reciprocal (a few ulp; the
+// loss derivative it feeds is compared at 1e-3 relative)
+__device__ __forceinline__ float sigmoid(float x) { return __frcp_rn(1.f + __expf(-x)); }
 
-__device__ __forceinline__ float block_sum_256(float v, float* red) {
-  const int t = threadIdx.x;
-  red[t] = v;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (t < w) red[t] += red[t + w];
-    __syncthreads();
+// Fills the proprioceptive part of the observation row, X[b][3072..3083] =
+// [goal - p, v, b, 0, 0, 0] (the depth part is written by the renderer).
+__global__ void obs_fwd_kernel(int A, int model, float* __restrict__ X, const float* __restrict__ s,
+                               const float* __restrict__ goal) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= A) return;
+  float* row = X + (size_t)b * kObsPad + kRays;
+  for (int k = 0; k < 3; ++k) {
+    row[k] = goal[(size_t)k * A + b] - s[(size_t)k * A + b];
+    row[3 + k] = s[(size_t)(3 + k) * A + b];
   }
-  const float r = red[0];
-  __syncthreads();
-  return r;
-}
-
-// Fills the proprioceptive part of the observation row and the per-agent
-// obstacle term mean_r softplus(beta (d_safe - depth_r)) / beta from the depth
-// already written (scaled by 1/d_max) into X[b][0..3071].
-__global__ __launch_bounds__(256) void obs_fwd_kernel(int A, int model, float* __restrict__ X,
-                                                      const float* __restrict__ s,
-                                                      const float* __restrict__ goal, float dmax,
-                                                      float beta, float d_safe,
-                                                      float* __restrict__ lo) {
-  __shared__ float red[256];
-  const int b = blockIdx.x, t = threadIdx.x;
-  float* row = X + (size_t)b * kObsPad;
-  float acc = 0.f;
-  for (int r = t; r < kRays; r += 256) acc += softplus(beta * (d_safe - row[r] * dmax)) / beta;
-  const float tot = block_sum_256(acc, red);
-  if (t == 0) lo[b] = tot / kRays;
-  if (t < 12) {
-    float v = 0.f;
-    if (t < 3) {
-      v = goal[(size_t)t * A + b] - s[(size_t)t * A + b];
-    } else if (t < 6) {
-      v = s[(size_t)t * A + b];
-    } else if (t < 9) {
-      if (model == SIM_PM9) {
-        v = s[(size_t)t * A + b];
-      } else {
-        float q[4] = {s[6 * (size_t)A + b], s[7 * (size_t)A + b], s[8 * (size_t)A + b],
-                      s[9 * (size_t)A + b]};
-        float qn[4];
-        quat_normalize(q, qn, nullptr);
-        const Rot R = rot_of_unit(qn);
-        v = R.m[t - 6][2];
-      }
-    }
-    row[kRays + t] = v;
+  if (model == SIM_PM9) {
+    for (int k = 0; k < 3; ++k) row[6 + k] = s[(size_t)(6 + k) * A + b];
+  } else {
+    float q[4] = {s[6 * (size_t)A + b], s[7 * (size_t)A + b], s[8 * (size_t)A + b], s[9 * (size_t)A + b]};
+    float qn[4];
+    quat_normalize(q, qn, nullptr);
+    const Rot R = rot_of_unit(qn);
+    for (int k = 0; k < 3; ++k) row[6 + k] = R.m[k][2];
   }
+  row[9] = row[10] = row[11] = 0.f;
 }
 
 // Action map: PM9 u = g y[0:3]; RB13 T = m g (1 + y0), w_cmd = 3 y[1:4].
@@ -185,8 +160,7 @@ __global__ __launch_bounds__(256) void obs_bwd_kernel(int A, int model, float* _
   const float* xrow = X + (size_t)b * kObsPad;
   const float inv = 1.f / dmax;
   for (int r = t; r < kRays; r += 256) {
-    const float x = beta * (d_safe - xrow[r] * dmax);
-    const float sig = 1.f / (1.f + expf(-x));
+    const float sig = sigmoid(beta * (d_safe - xrow[r] * dmax));
     grow[r] = grow[r] * inv - sc * co * sig;
   }
   if (t == 0) {
@@ -272,7 +246,7 @@ static size_t partial_floats(int B) {
   size_t a = (size_t)gemm_splits_used(B, kSplitW1) * kHid * kObsPad;
   size_t b = (size_t)gemm_splits_used(B, kSplitW2) * kHid * kHid;
   size_t c = (size_t)gemm_splits_used(B, kSplitW3) * kOut * kHid;
-  return std::max(a, std::max(b, c));
+  return std::max(std::max(a, std::max(b, c)), (size_t)colsum_workspace_floats(kHid));
 }
 
 // Accumulates weight gradients for one batch and writes gX = dL/dX.
@@ -288,7 +262,7 @@ static int mlp_backward(int B, const PolicyPtrs& p, const float* X, const float*
   if ((rc = launch_splitk_reduce(gemm_splits_used(B, kSplitW3), kOut, kHid, kHid, gb.part, gb.gW3, kHid,
                                  true, st)))
     return rc;
-  if ((rc = launch_colsum(B, kOut, gb.gZ3, kOut, gb.gb3, true, st))) return rc;
+  if ((rc = launch_colsum(B, kOut, gb.gZ3, kOut, gb.gb3, true, gb.part, st))) return rc;
   // gW2 += gZ2^T H1 ; gb2
   g = GemmArgs();
   g.M = kHid; g.N = kHid; g.K = B;
@@ -297,7 +271,7 @@ static int mlp_backward(int B, const PolicyPtrs& p, const float* X, const float*
   if ((rc = launch_splitk_reduce(gemm_splits_used(B, kSplitW2), kHid, kHid, kHid, gb.part, gb.gW2, kHid,
                                  true, st)))
     return rc;
-  if ((rc = launch_colsum(B, kHid, gb.gZ2, kHid, gb.gb2, true, st))) return rc;
+  if ((rc = launch_colsum(B, kHid, gb.gZ2, kHid, gb.gb2, true, gb.part, st))) return rc;
   // gZ1 = (gZ2 W2) (1 - H1^2)
   g = GemmArgs();
   g.M = B; g.N = kHid; g.K = kHid;
@@ -314,7 +288,7 @@ static int mlp_backward(int B, const PolicyPtrs& p, const float* X, const float*
                                  kObsPad, true, st)))
     return rc;
   if (gb.owner) tpair(gb.owner, BPTT_T_GW1, e0, tmark(gb.owner, st));
-  if ((rc = launch_colsum(B, kHid, gb.gZ1, kHid, gb.gb1, true, st))) return rc;
+  if ((rc = launch_colsum(B, kHid, gb.gZ1, kHid, gb.gb1, true, gb.part, st))) return rc;
   // gX = gZ1 W1
   const int e1 = gb.owner ? tmark(gb.owner, st) : -1;
   g = GemmArgs();
@@ -355,6 +329,7 @@ struct bptt_handle {
   MlpGradBufs gb;
   const float *theta = nullptr, *s0 = nullptr, *goal = nullptr;
   bool have_fwd = false;
+  bool store = false;
   // optional HIP-event timing of the main kernel classes (BPTT_T_*)
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
@@ -406,18 +381,22 @@ int bptt_create(sim_handle* sim, const bptt_config* cfg, bptt_handle** out) {
   b->C = C;
   b->Ka = Ka;
   b->nseg = cdiv(cfg->T, K);
+  b->store = cfg->store_activations != 0;
+  // slots: with stored activations every step has its own state / activation
+  // slot; otherwise only the K steps of the segment being recomputed
+  const int SL = b->store ? cfg->T : K;
   // carve one allocation
   std::vector<std::pair<void**, size_t>> parts;
   auto add = [&](auto** p, size_t bytes) { parts.push_back({reinterpret_cast<void**>(p), (bytes + 255) & ~size_t(255)}); };
   add(&b->W1p, (size_t)kHid * kObsPad * 4);
   add(&b->ckpt, (size_t)b->nseg * C * A * 4);
-  add(&b->seg_s, (size_t)(K + 1) * C * A * 4);
+  add(&b->seg_s, (size_t)(SL + 1) * C * A * 4);
   add(&b->X, (size_t)K * A * kObsPad * 4);
   add(&b->hit, (size_t)K * A * kRays * 4);
-  add(&b->H1, (size_t)K * A * kHid * 4);
-  add(&b->H2, (size_t)K * A * kHid * 4);
-  add(&b->Y, (size_t)K * A * kOut * 4);
-  add(&b->act, (size_t)K * Ka * A * 4);
+  add(&b->H1, (size_t)SL * A * kHid * 4);
+  add(&b->H2, (size_t)SL * A * kHid * 4);
+  add(&b->Y, (size_t)SL * A * kOut * 4);
+  add(&b->act, (size_t)SL * Ka * A * 4);
   add(&b->lo, (size_t)A * 4);
   add(&b->loss_acc, (size_t)A * 4);
   add(&b->g_a, (size_t)C * A * 4);
@@ -502,12 +481,12 @@ static int forward_step(bptt_handle* b, const PolicyPtrs& pp, const float* s, fl
   const int A = b->A;
   const float dmax = h->cfg.cam_max;
   int e0 = tmark(b, st);
+  // depth / d_max straight into the observation rows, obstacle term fused
   int rc = launch_render(h->scene, h->cam.dev, h->cfg.model == SIM_RB13, h->cfg.fov_cull != 0, s, A, X,
-                         hit, kObsPad, 1.0f / dmax, st);
+                         hit, kObsPad, 1.0f / dmax, st, b->lo, b->cfg.beta, b->cfg.d_safe);
   if (rc) return rc;
   tpair(b, BPTT_T_RENDER, e0, tmark(b, st));
-  hipLaunchKernelGGL(obs_fwd_kernel, dim3(A), dim3(256), 0, st, A, h->cfg.model, X, s, b->goal, dmax,
-                     b->cfg.beta, b->cfg.d_safe, b->lo);
+  hipLaunchKernelGGL(obs_fwd_kernel, dim3(cdiv(A, 256)), dim3(256), 0, st, A, h->cfg.model, X, s, b->goal);
   DA_LAUNCH_CHECK("obs_fwd_kernel");
   if ((rc = mlp_forward(A, pp, X, H1, H2, Y, st, b))) return rc;
   hipLaunchKernelGGL(action_kernel, dim3(cdiv(A, 256)), dim3(256), 0, st, A, h->cfg.model, Y, h->params,
@@ -527,7 +506,7 @@ int bptt_forward(bptt_handle* b, const float* theta, const float* s0, const floa
                  float* s_T, void* stream) {
   DA_REQUIRE(b && theta && s0 && goal && loss, "bptt_forward: null argument");
   hipStream_t st = as_stream(stream);
-  const int A = b->A, C = b->C, K = b->cfg.K, T = b->cfg.T;
+  const int A = b->A, C = b->C, Ka = b->Ka, K = b->cfg.K, T = b->cfg.T;
   b->theta = theta;
   b->s0 = s0;
   b->goal = goal;
@@ -536,22 +515,29 @@ int bptt_forward(bptt_handle* b, const float* theta, const float* s0, const floa
   const PolicyPtrs pp = policy_ptrs(theta, b->W1p);
   DA_HIP(hipMemsetAsync(b->loss_acc, 0, (size_t)A * 4, st));
   const size_t sbytes = (size_t)C * A * 4;
-  float* cur = b->seg_s;
-  float* nxt = b->seg_s + (size_t)C * A;
-  DA_HIP(hipMemcpyAsync(cur, s0, sbytes, hipMemcpyDeviceToDevice, st));
+  DA_HIP(hipMemcpyAsync(b->seg_s, s0, sbytes, hipMemcpyDeviceToDevice, st));
   LossW w{b->cfg.w_p, b->cfg.w_v, b->cfg.w_u, b->cfg.w_o, b->cfg.beta, b->cfg.d_safe};
   for (int t = 0; t < T; ++t) {
-    if (t % K == 0) DA_HIP(hipMemcpyAsync(b->ckpt + (size_t)(t / K) * C * A, cur, sbytes, hipMemcpyDeviceToDevice, st));
-    if ((rc = forward_step(b, pp, cur, nxt, b->X, nullptr, b->H1, b->H2, b->Y, b->act, st))) return rc;
-    hipLaunchKernelGGL(loss_step_kernel, dim3(cdiv(A, 256)), dim3(256), 0, st, A, nxt, goal, b->Y, b->lo, w,
-                       b->loss_acc);
+    // stored mode: state t in slot t; otherwise two ping-pong slots
+    const int si = b->store ? t : (t & 1), so = b->store ? t + 1 : ((t + 1) & 1);
+    const int a = b->store ? t : 0;
+    float* cur = b->seg_s + (size_t)si * C * A;
+    float* nxt = b->seg_s + (size_t)so * C * A;
+    if (!b->store && t % K == 0)
+      DA_HIP(hipMemcpyAsync(b->ckpt + (size_t)(t / K) * C * A, cur, sbytes, hipMemcpyDeviceToDevice, st));
+    if ((rc = forward_step(b, pp, cur, nxt, b->X, nullptr, b->H1 + (size_t)a * A * kHid,
+                           b->H2 + (size_t)a * A * kHid, b->Y + (size_t)a * A * kOut,
+                           b->act + (size_t)a * Ka * A, st)))
+      return rc;
+    hipLaunchKernelGGL(loss_step_kernel, dim3(cdiv(A, 256)), dim3(256), 0, st, A, nxt, goal,
+                       b->Y + (size_t)a * A * kOut, b->lo, w, b->loss_acc);
     DA_LAUNCH_CHECK("loss_step_kernel");
-    std::swap(cur, nxt);
   }
   hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(1024), 0, st, A, b->loss_acc, 1.0f / ((float)A * T),
                      loss);
   DA_LAUNCH_CHECK("loss_final_kernel");
-  if (s_T) DA_HIP(hipMemcpyAsync(s_T, cur, sbytes, hipMemcpyDeviceToDevice, st));
+  const int last = b->store ? T : (T & 1);
+  if (s_T) DA_HIP(hipMemcpyAsync(s_T, b->seg_s + (size_t)last * C * A, sbytes, hipMemcpyDeviceToDevice, st));
   b->have_fwd = true;
   return SIM_OK;
 }
@@ -567,6 +553,7 @@ int bptt_backward(bptt_handle* b, const float* g_loss, float* g_theta, float* g_
   const float AT = (float)A * T;
   const float cp = 2.f * b->cfg.w_p / AT, cv = 2.f * b->cfg.w_v / AT, cu = 2.f * b->cfg.w_u / AT;
   const float co = b->cfg.w_o / (AT * kRays);
+  const float dmax = h->cfg.cam_max;
   DA_HIP(hipMemsetAsync(b->gb.gW1p, 0, (size_t)kHid * kObsPad * 4, st));
   DA_HIP(hipMemsetAsync(b->gflat_tail, 0, (POLICY_N_PARAMS - kOffB1) * 4, st));
   float* g_next = b->g_a;
@@ -575,20 +562,40 @@ int bptt_backward(bptt_handle* b, const float* g_loss, float* g_theta, float* g_
   int rc;
   for (int seg = b->nseg - 1; seg >= 0; --seg) {
     const int t0 = seg * K, n = std::min(T, t0 + K) - t0;
-    DA_HIP(hipMemcpyAsync(b->seg_s, b->ckpt + (size_t)seg * C * A, sbytes, hipMemcpyDeviceToDevice, st));
-    for (int j = 0; j < n; ++j) {
-      rc = forward_step(b, pp, b->seg_s + (size_t)j * C * A, b->seg_s + (size_t)(j + 1) * C * A,
-                        b->X + (size_t)j * A * kObsPad, b->hit + (size_t)j * A * kRays,
-                        b->H1 + (size_t)j * A * kHid, b->H2 + (size_t)j * A * kHid,
-                        b->Y + (size_t)j * A * kOut, b->act + (size_t)j * Ka * A, st);
-      if (rc) return rc;
+    // recompute the segment: observations and hit records always; states,
+    // activations and actions only when they were not stored
+    if (b->store) {
+      for (int j = 0; j < n; ++j) {
+        const float* s = b->seg_s + (size_t)(t0 + j) * C * A;
+        float* X = b->X + (size_t)j * A * kObsPad;
+        const int e0 = tmark(b, st);
+        rc = launch_render(h->scene, h->cam.dev, h->cfg.model == SIM_RB13, h->cfg.fov_cull != 0, s, A, X,
+                           b->hit + (size_t)j * A * kRays, kObsPad, 1.0f / dmax, st);
+        if (rc) return rc;
+        tpair(b, BPTT_T_RENDER, e0, tmark(b, st));
+        hipLaunchKernelGGL(obs_fwd_kernel, dim3(cdiv(A, 256)), dim3(256), 0, st, A, h->cfg.model, X, s,
+                           b->goal);
+        DA_LAUNCH_CHECK("obs_fwd_kernel");
+      }
+    } else {
+      DA_HIP(hipMemcpyAsync(b->seg_s, b->ckpt + (size_t)seg * C * A, sbytes, hipMemcpyDeviceToDevice, st));
+      for (int j = 0; j < n; ++j) {
+        rc = forward_step(b, pp, b->seg_s + (size_t)j * C * A, b->seg_s + (size_t)(j + 1) * C * A,
+                          b->X + (size_t)j * A * kObsPad, b->hit + (size_t)j * A * kRays,
+                          b->H1 + (size_t)j * A * kHid, b->H2 + (size_t)j * A * kHid,
+                          b->Y + (size_t)j * A * kOut, b->act + (size_t)j * Ka * A, st);
+        if (rc) return rc;
+      }
     }
     for (int j = n - 1; j >= 0; --j) {
-      const float* s = b->seg_s + (size_t)j * C * A;
-      const float* s1 = b->seg_s + (size_t)(j + 1) * C * A;
+      const int si = b->store ? t0 + j : j;  // state / activation slot of step t0 + j
+      const float* s = b->seg_s + (size_t)si * C * A;
+      const float* s1 = b->seg_s + (size_t)(si + 1) * C * A;
       const float* X = b->X + (size_t)j * A * kObsPad;
-      const float* Y = b->Y + (size_t)j * A * kOut;
-      const float* act = b->act + (size_t)j * Ka * A;
+      const float* H1 = b->H1 + (size_t)si * A * kHid;
+      const float* H2 = b->H2 + (size_t)si * A * kHid;
+      const float* Y = b->Y + (size_t)si * A * kOut;
+      const float* act = b->act + (size_t)si * Ka * A;
       hipLaunchKernelGGL(loss_state_grad_kernel, dim3(cdiv(A, 256)), dim3(256), 0, st, A, s1, b->goal, cp,
                          cv, g_loss, g_next);
       DA_LAUNCH_CHECK("loss_state_grad_kernel");
@@ -601,11 +608,9 @@ int bptt_backward(bptt_handle* b, const float* g_loss, float* g_theta, float* g_
                          Y, h->params, cu, g_loss, b->gY);
       DA_LAUNCH_CHECK("action_bwd_kernel");
       b->gb.owner = b;
-      if ((rc = mlp_backward(A, pp, X, b->H1 + (size_t)j * A * kHid, b->H2 + (size_t)j * A * kHid, Y,
-                             b->gY, b->gb, st)))
-        return rc;
+      if ((rc = mlp_backward(A, pp, X, H1, H2, Y, b->gY, b->gb, st))) return rc;
       hipLaunchKernelGGL(obs_bwd_kernel, dim3(A), dim3(256), 0, st, A, h->cfg.model, b->gb.gX, X, s,
-                         h->cfg.cam_max, b->cfg.beta, b->cfg.d_safe, co, g_loss, g_cur);
+                         dmax, b->cfg.beta, b->cfg.d_safe, co, g_loss, g_cur);
       DA_LAUNCH_CHECK("obs_bwd_kernel");
       e0 = tmark(b, st);
       if ((rc = launch_render_vjp(h->scene, h->cam.dev, h->cfg.model == SIM_RB13, s, A, b->gb.gX,

@@ -215,28 +215,49 @@ int launch_splitk_reduce(int S, int M, int N, int ldp, const float* part, float*
   return SIM_OK;
 }
 
-// out[n] (+)= sum_m X[m][n]: each block owns 64 columns; 4 row-groups of
-// threads accumulate fixed strided row sets, then combine in a fixed order.
-__global__ void colsum_kernel(int M, int N, const float* __restrict__ X, int ld,
-                              float* __restrict__ out, int accumulate) {
+// out[n] (+)= sum_m X[m][n], in two deterministic stages: block (cx, sp)
+// sums rows [sp*rows_per, (sp+1)*rows_per) of 64 columns into part[sp][n]
+// (4 row-groups of 64 threads, fixed strides, fixed combine order); then each
+// column adds its kColsumSplits partials in order.
+constexpr int kColsumSplits = 32;
+
+__global__ void colsum_partial_kernel(int M, int N, const float* __restrict__ X, int ld, int rows_per,
+                                      float* __restrict__ part) {
   __shared__ float red[4][64];
   const int c = blockIdx.x * 64 + (threadIdx.x & 63);
   const int g = threadIdx.x >> 6;
+  const int r0 = blockIdx.y * rows_per, r1 = min(M, r0 + rows_per);
   float v = 0.f;
   if (c < N)
-    for (int m = g; m < M; m += 4) v += X[(size_t)m * ld + c];
+    for (int m = r0 + g; m < r1; m += 4) v += X[(size_t)m * ld + c];
   red[g][threadIdx.x & 63] = v;
   __syncthreads();
-  if (g == 0 && c < N) {
-    float s = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
-    out[c] = accumulate ? out[c] + s : s;
-  }
+  if (g == 0 && c < N)
+    part[(size_t)blockIdx.y * N + c] =
+        ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
 }
 
-int launch_colsum(int M, int N, const float* X, int ld, float* out, bool accumulate, hipStream_t st) {
-  hipLaunchKernelGGL(colsum_kernel, dim3(cdiv(N, 64)), dim3(256), 0, st, M, N, X, ld, out,
+__global__ void colsum_final_kernel(int S, int N, const float* __restrict__ part, float* __restrict__ out,
+                                    int accumulate) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= N) return;
+  float v = 0.f;
+  for (int s = 0; s < S; ++s) v += part[(size_t)s * N + c];
+  out[c] = accumulate ? out[c] + v : v;
+}
+
+int colsum_workspace_floats(int N) { return kColsumSplits * N; }
+
+int launch_colsum(int M, int N, const float* X, int ld, float* out, bool accumulate, float* work,
+                  hipStream_t st) {
+  const int rows_per = cdiv(M, kColsumSplits);
+  const int S = cdiv(M, rows_per);
+  hipLaunchKernelGGL(colsum_partial_kernel, dim3(cdiv(N, 64), S), dim3(256), 0, st, M, N, X, ld, rows_per,
+                     work);
+  DA_LAUNCH_CHECK("colsum_partial_kernel");
+  hipLaunchKernelGGL(colsum_final_kernel, dim3(cdiv(N, 256)), dim3(256), 0, st, S, N, work, out,
                      accumulate ? 1 : 0);
-  DA_LAUNCH_CHECK("colsum_kernel");
+  DA_LAUNCH_CHECK("colsum_final_kernel");
   return SIM_OK;
 }
 

@@ -43,9 +43,11 @@ int launch_step_vjp(int model, int integ, int A, float dt, const float* s, const
                     const float* prm, const float* g_next, float* g_s, float* g_a, hipStream_t st);
 
 // Render one sensor for agents [0, A): out[i*out_ld + r] = value * out_scale
-// (out_ld >= n_rays), rec[i*n_rays + r] (nullable).
+// (out_ld >= n_rays), rec[i*n_rays + r] (nullable). If term is given, also
+// term[i] = mean_r softplus(beta (d_safe - value_r)) / beta (fused epilogue).
 int launch_render(const SceneDev& sc, const SensorDev& sen, bool rotate, bool cull, const float* s,
-                  int A, float* out, int* rec, int out_ld, float out_scale, hipStream_t st);
+                  int A, float* out, int* rec, int out_ld, float out_scale, hipStream_t st,
+                  float* term = nullptr, float beta = 1.f, float d_safe = 0.f);
 // Adds the sensor's contribution (d out/d s)^T g to g_s (p and q components);
 // g[i*g_ld + r] is the gradient of the (unscaled) sensor value.
 int launch_render_vjp(const SceneDev& sc, const SensorDev& sen, bool rotate, const float* s, int A,

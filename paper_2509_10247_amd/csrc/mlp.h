@@ -29,7 +29,10 @@ int launch_gemm(bool a_kmaj, bool b_kmaj, int epi, GemmArgs g, int splits, hipSt
 int gemm_splits_used(int K, int splits);
 int launch_splitk_reduce(int S, int M, int N, int ldp, const float* part, float* out, int ldo,
                          bool accumulate, hipStream_t st);
-int launch_colsum(int M, int N, const float* X, int ld, float* out, bool accumulate, hipStream_t st);
+// Column sums out[n] (+)= sum_m X[m][n]; work holds colsum_workspace_floats(N).
+int colsum_workspace_floats(int N);
+int launch_colsum(int M, int N, const float* X, int ld, float* out, bool accumulate, float* work,
+                  hipStream_t st);
 int launch_narrow_fwd(int B, int J, int O, const float* H, int ldh, const float* W, const float* bias,
                       float* Y, hipStream_t st);
 int launch_narrow_bwd(int B, int J, int O, const float* gY, const float* Y, const float* W,

@@ -46,6 +46,11 @@ static size_t render_lds_bytes(int P) {
 
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// softplus(x) = max(x, 0) + log(1 + exp(-|x|)) on the hardware exp2 / log2 units.
+__device__ __forceinline__ float softplus_fast(float x) {
+  return fmaxf(x, 0.f) + __logf(1.f + __expf(-fabsf(x)));
+}
+
 // Sphere test with origin-relative centre w = c - o, r2 = r^2, C = |w|^2 - r^2 > 0
 // (origin outside). Nearest root written as C / (tc + sqrt(disc)) with the
 // discriminant taken from the perpendicular distance, which avoids the
@@ -108,7 +113,8 @@ __global__ __launch_bounds__(256) void render_kernel(SceneDev sc, SensorDev sen,
                                                      const float* __restrict__ s, int A,
                                                      float* __restrict__ out,
                                                      int* __restrict__ rec, int out_ld,
-                                                     float out_scale) {
+                                                     float out_scale, float* __restrict__ term,
+                                                     float beta, float d_safe) {
   extern __shared__ float4 smem_f4[];
   const int P = sc.max_prims > 0 ? sc.max_prims : 1;
   RenderLds L = carve(smem_f4, P);
@@ -184,6 +190,7 @@ __global__ __launch_bounds__(256) void render_kernel(SceneDev sc, SensorDev sen,
   int* rrow = rec ? rec + (size_t)i * nr : nullptr;
   short* list = L.lists + wave * P;
   const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  float tacc = 0.f;  // optional per-agent sum of softplus(beta (d_safe - value)) / beta
 
   for (int tile = wave; tile < sen.n_tiles; tile += 4) {
     const int r = sen.tile_rays[tile * kTileRays + lane];
@@ -191,6 +198,7 @@ __global__ __launch_bounds__(256) void render_kernel(SceneDev sc, SensorDev sen,
       if (r >= 0) {
         orow[r] = 0.f;
         if (rrow) rrow[r] = -2;
+        if (term) tacc += softplus_fast(beta * d_safe) / beta;
       }
       continue;
     }
@@ -219,7 +227,7 @@ __global__ __launch_bounds__(256) void render_kernel(SceneDev sc, SensorDev sen,
     if (r < 0) continue;
     const float4 db = sen.dirs[r];
     const f3 d = ROT ? rot_apply(R, mk3(db.x, db.y, db.z)) : mk3(db.x, db.y, db.z);
-    const f3 inv = mk3(1.0f / d.x, 1.0f / d.y, 1.0f / d.z);
+    const f3 inv = mk3(__builtin_amdgcn_rcpf(d.x), __builtin_amdgcn_rcpf(d.y), __builtin_amdgcn_rcpf(d.z));
     float best = kInf;
     int id = -1;
     for (int j = 0; j < ks; ++j) {
@@ -268,22 +276,40 @@ __global__ __launch_bounds__(256) void render_kernel(SceneDev sc, SensorDev sen,
     }
     orow[r] = val * out_scale;
     if (rrow) rrow[r] = rc;
+    if (term) tacc += softplus_fast(beta * (d_safe - val)) / beta;
+  }
+  if (term) {
+    // fixed-order reduction: butterfly within each wave, then waves 0..3
+    for (int off = 32; off > 0; off >>= 1) tacc += __shfl_xor(tacc, off);
+    __syncthreads();
+    float* wsum = reinterpret_cast<float*>(L.pa);
+    if (lane == 0) wsum[wave] = tacc;
+    __syncthreads();
+    if (tid == 0) term[i] = (((wsum[0] + wsum[1]) + wsum[2]) + wsum[3]) / (float)nr;
   }
 }
 
 // ---------------------------------------------------------------------------
 // adjoint
 // ---------------------------------------------------------------------------
-// dt/do = -n/(n.d) is ill-conditioned near silhouettes: in FP32 the
-// discriminant r^2 - |perp|^2 of a grazing ray loses relative precision as
-// 1/(n.d)^2, so the per-ray hit geometry of the adjoint is evaluated in FP64
-// (directions from an FP64 table, rotation from the quaternion in FP64) and
-// accumulated in FP64 before the per-agent reduction.
+// Sphere hits: dt/do = -n/(n.d) is ill-conditioned near silhouettes (in FP32
+// the discriminant r^2 - |perp|^2 of a grazing ray loses relative precision as
+// 1/(n.d)^2), so the sphere geometry is evaluated in FP64 from an FP64
+// direction table and an FP64 rotation. Plane hits (box entry face, room exit
+// face) have dt/do_f = -1/d_f, well conditioned for every hit inside the
+// sensor range, and stay in FP32. Per-thread sums and the per-agent reduction
+// are FP64.
 struct d3 {
   double x, y, z;
 };
 __device__ __forceinline__ d3 dk3(double x, double y, double z) { return d3{x, y, z}; }
 __device__ __forceinline__ double ddot(d3 a, d3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+// 1/x: hardware reciprocal estimate refined by one Newton step (full FP64).
+__device__ __forceinline__ double rcp64(double x) {
+  const double r = __builtin_amdgcn_rcp(x);
+  const double e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
 
 template <bool ROT>
 __global__ __launch_bounds__(256) void render_vjp_kernel(SceneDev sc, SensorDev sen,
@@ -295,9 +321,10 @@ __global__ __launch_bounds__(256) void render_vjp_kernel(SceneDev sc, SensorDev 
   const int i = blockIdx.x;
   const int tid = threadIdx.x;
   const int env = sc.agent_env[i];
-  const d3 o = dk3(s[i], s[(size_t)A + i], s[2 * (size_t)A + i]);
+  const f3 o = mk3(s[i], s[(size_t)A + i], s[2 * (size_t)A + i]);
   double qn[4] = {1.0, 0.0, 0.0, 0.0}, inv_n = 1.0;
   double R[3][3] = {{1.0, 0.0, 0.0}, {0.0, 1.0, 0.0}, {0.0, 0.0, 1.0}};
+  Rot R32;
   if (ROT) {
     const double q[4] = {s[6 * (size_t)A + i], s[7 * (size_t)A + i], s[8 * (size_t)A + i],
                          s[9 * (size_t)A + i]};
@@ -313,6 +340,8 @@ __global__ __launch_bounds__(256) void render_vjp_kernel(SceneDev sc, SensorDev 
     R[2][0] = 2.0 * (x * z - w * y);
     R[2][1] = 2.0 * (y * z + w * x);
     R[2][2] = 1.0 - 2.0 * (x * x + y * y);
+    for (int a = 0; a < 3; ++a)
+      for (int c = 0; c < 3; ++c) R32.m[a][c] = (float)R[a][c];
   }
   const int s0 = sc.sph_off[env], ns = sc.sph_off[env + 1] - s0;
   const int b0 = sc.box_off[env], nb = sc.box_off[env + 1] - b0;
@@ -331,14 +360,9 @@ __global__ __launch_bounds__(256) void render_vjp_kernel(SceneDev sc, SensorDev 
     // records outside this env's primitive range (or a room id without a
     // room) cannot come from sim_render on the same scene: ignored
     if (k < 0 || gv == 0.f || k > np || (k == np && !sc.room)) continue;
-    const double* b64 = sen.dirs64 + (size_t)r * 4;
-    const d3 dbv = dk3(b64[0], b64[1], b64[2]);
-    const d3 d = ROT ? dk3(R[0][0] * dbv.x + R[0][1] * dbv.y + R[0][2] * dbv.z,
-                           R[1][0] * dbv.x + R[1][1] * dbv.y + R[1][2] * dbv.z,
-                           R[2][0] * dbv.x + R[2][1] * dbv.y + R[2][2] * dbv.z)
-                     : dbv;
-    const double gt = (double)gv * b64[3];
-    d3 dto, dtd;  // dt/do and dt/dd
+    const float4 db = sen.dirs[r];
+    const float gt = gv * db.w;
+    f3 dto, dtd;  // dt/do and dt/dd (FP32 results)
     if (k < ns || (k >= ns + nb && k < np)) {
       d3 c;
       double rad;
@@ -351,56 +375,65 @@ __global__ __launch_bounds__(256) void render_vjp_kernel(SceneDev sc, SensorDev 
         c = dk3(s[j], s[(size_t)A + j], s[2 * (size_t)A + j]);
         rad = sc.agent_radius;
       }
-      const d3 w = dk3(c.x - o.x, c.y - o.y, c.z - o.z);
+      const double* b64 = sen.dirs64 + (size_t)r * 4;
+      const d3 dbv = dk3(b64[0], b64[1], b64[2]);
+      const d3 d = ROT ? dk3(R[0][0] * dbv.x + R[0][1] * dbv.y + R[0][2] * dbv.z,
+                             R[1][0] * dbv.x + R[1][1] * dbv.y + R[1][2] * dbv.z,
+                             R[2][0] * dbv.x + R[2][1] * dbv.y + R[2][2] * dbv.z)
+                       : dbv;
+      // t = tc - sqrt(disc) and, at the hit point, n.d = -sqrt(disc)/r, so
+      // dt/do = -n/(n.d) = (t d - w)/sqrt(disc) and dt/dd = t dt/do
+      const d3 w = dk3(c.x - (double)o.x, c.y - (double)o.y, c.z - (double)o.z);
       const double C = ddot(w, w) - rad * rad;
       const double tc = ddot(d, w);
       const d3 p = dk3(w.x - tc * d.x, w.y - tc * d.y, w.z - tc * d.z);
-      const double disc = fmax(rad * rad - ddot(p, p), 0.0);
-      const double t = C / (tc + sqrt(disc));
-      const d3 n = dk3((t * d.x - w.x) / rad, (t * d.y - w.y) / rad, (t * d.z - w.z) / rad);
-      const double nd = ddot(n, d);
-      if (!(fabs(nd) > 0.0)) continue;
-      dto = dk3(-n.x / nd, -n.y / nd, -n.z / nd);
-      dtd = dk3(-t * n.x / nd, -t * n.y / nd, -t * n.z / nd);
+      const double disc = rad * rad - ddot(p, p);
+      if (!(disc > 0.0)) continue;
+      const double sq = sqrt(disc);
+      const double t = C * rcp64(tc + sq);
+      const double is = rcp64(sq);
+      const double ox = (t * d.x - w.x) * is, oy = (t * d.y - w.y) * is, oz = (t * d.z - w.z) * is;
+      dto = mk3((float)ox, (float)oy, (float)oz);
+      dtd = mk3((float)(t * ox), (float)(t * oy), (float)(t * oz));
     } else {
       // box entry face or room exit face: t = (plane_f - o_f) / d_f
-      const double dv[3] = {d.x, d.y, d.z};
-      const double ov[3] = {o.x, o.y, o.z};
-      int f = 0;
-      double plane;
+      const f3 d = ROT ? rot_apply(R32, mk3(db.x, db.y, db.z)) : mk3(db.x, db.y, db.z);
+      const float dv[3] = {d.x, d.y, d.z};
+      const float ov[3] = {o.x, o.y, o.z};
+      const float iv[3] = {__builtin_amdgcn_rcpf(d.x), __builtin_amdgcn_rcpf(d.y),
+                           __builtin_amdgcn_rcpf(d.z)};
+      float pl[3];
       if (k < ns + nb) {
         const float* b = sc.box + (size_t)(b0 + k - ns) * 6;
-        double te[3];
-        for (int a = 0; a < 3; ++a) {
-          const double lo = (double)b[a] - (double)b[3 + a], hi = (double)b[a] + (double)b[3 + a];
-          te[a] = fmin((lo - ov[a]) / dv[a], (hi - ov[a]) / dv[a]);
-        }
-        if (te[1] > te[f]) f = 1;
-        if (te[2] > te[f]) f = 2;
-        plane = dv[f] > 0.0 ? (double)b[f] - (double)b[3 + f] : (double)b[f] + (double)b[3 + f];
+        for (int a = 0; a < 3; ++a) pl[a] = dv[a] > 0.f ? b[a] - b[3 + a] : b[a] + b[3 + a];
       } else {
         const float* rm = sc.room + (size_t)env * 6;
-        double te[3];
-        for (int a = 0; a < 3; ++a) te[a] = ((dv[a] > 0.0 ? rm[3 + a] : rm[a]) - ov[a]) / dv[a];
+        for (int a = 0; a < 3; ++a) pl[a] = dv[a] > 0.f ? rm[3 + a] : rm[a];
+      }
+      float te[3];
+      for (int a = 0; a < 3; ++a) te[a] = (pl[a] - ov[a]) * iv[a];
+      int f = 0;
+      if (k < ns + nb) {  // entry: the latest slab entry
+        if (te[1] > te[f]) f = 1;
+        if (te[2] > te[f]) f = 2;
+      } else {            // exit: the earliest face
         if (te[1] < te[f]) f = 1;
         if (te[2] < te[f]) f = 2;
-        plane = dv[f] > 0.0 ? rm[3 + f] : rm[f];
       }
-      if (dv[f] == 0.0) continue;
-      const double t = (plane - ov[f]) / dv[f];
-      double e[3] = {0.0, 0.0, 0.0};
-      e[f] = -1.0 / dv[f];
-      dto = dk3(e[0], e[1], e[2]);
-      dtd = dk3(t * e[0], t * e[1], t * e[2]);
+      if (dv[f] == 0.f) continue;
+      float e[3] = {0.f, 0.f, 0.f};
+      e[f] = -iv[f];
+      dto = mk3(e[0], e[1], e[2]);
+      dtd = scl(dto, te[f]);
     }
-    go[0] += gt * dto.x;
-    go[1] += gt * dto.y;
-    go[2] += gt * dto.z;
+    go[0] += (double)(gt * dto.x);
+    go[1] += (double)(gt * dto.y);
+    go[2] += (double)(gt * dto.z);
     if (ROT) {
-      const double gd[3] = {gt * dtd.x, gt * dtd.y, gt * dtd.z};
-      const double bb[3] = {dbv.x, dbv.y, dbv.z};
+      const float gd[3] = {gt * dtd.x, gt * dtd.y, gt * dtd.z};
+      const float bb[3] = {db.x, db.y, db.z};
       for (int a = 0; a < 3; ++a)
-        for (int c = 0; c < 3; ++c) gR[a * 3 + c] += gd[a] * bb[c];
+        for (int c = 0; c < 3; ++c) gR[a * 3 + c] += (double)(gd[a] * bb[c]);
     }
   }
   for (int c = 0; c < 3; ++c) red[c][tid] = go[c];
@@ -479,20 +512,21 @@ __global__ __launch_bounds__(256) void collide_kernel(SceneDev sc, const float* 
 // launchers
 // ---------------------------------------------------------------------------
 int launch_render(const SceneDev& sc, const SensorDev& sen, bool rotate, bool cull, const float* s,
-                  int A, float* out, int* rec, int out_ld, float out_scale, hipStream_t st) {
+                  int A, float* out, int* rec, int out_ld, float out_scale, hipStream_t st,
+                  float* term, float beta, float d_safe) {
   if (A == 0) return SIM_OK;
   const int P = sc.max_prims > 0 ? sc.max_prims : 1;
   const size_t lds = render_lds_bytes(P);
   if (rotate) {
     if (cull)
-      hipLaunchKernelGGL((render_kernel<true, true>), dim3(A), dim3(256), lds, st, sc, sen, s, A, out, rec, out_ld, out_scale);
+      hipLaunchKernelGGL((render_kernel<true, true>), dim3(A), dim3(256), lds, st, sc, sen, s, A, out, rec, out_ld, out_scale, term, beta, d_safe);
     else
-      hipLaunchKernelGGL((render_kernel<true, false>), dim3(A), dim3(256), lds, st, sc, sen, s, A, out, rec, out_ld, out_scale);
+      hipLaunchKernelGGL((render_kernel<true, false>), dim3(A), dim3(256), lds, st, sc, sen, s, A, out, rec, out_ld, out_scale, term, beta, d_safe);
   } else {
     if (cull)
-      hipLaunchKernelGGL((render_kernel<false, true>), dim3(A), dim3(256), lds, st, sc, sen, s, A, out, rec, out_ld, out_scale);
+      hipLaunchKernelGGL((render_kernel<false, true>), dim3(A), dim3(256), lds, st, sc, sen, s, A, out, rec, out_ld, out_scale, term, beta, d_safe);
     else
-      hipLaunchKernelGGL((render_kernel<false, false>), dim3(A), dim3(256), lds, st, sc, sen, s, A, out, rec, out_ld, out_scale);
+      hipLaunchKernelGGL((render_kernel<false, false>), dim3(A), dim3(256), lds, st, sc, sen, s, A, out, rec, out_ld, out_scale, term, beta, d_safe);
   }
   DA_LAUNCH_CHECK("render_kernel");
   return SIM_OK;

@@ -46,21 +46,21 @@ def test_policy_forward_backward_matches_fp64():
     assert ok, f"g_x rel {rel:.2e}"
 
 
-def _engine(wk, T, K):
+def _engine(wk, T, K, store=True):
     from paper_2509_10247_amd import bptt, env
     e = env.from_workload(wk)
-    return e, bptt.BpttEngine(e, T, K)
+    return e, bptt.BpttEngine(e, T, K, store_activations=store)
 
 
-@pytest.mark.parametrize("model", [wl.RB13, wl.PM9])
-def test_bptt_gradient_matches_oracle(model):
+@pytest.mark.parametrize("model,store", [(wl.RB13, True), (wl.PM9, True), (wl.RB13, False)])
+def test_bptt_gradient_matches_oracle(model, store):
     """8 envs, horizon 32, checkpoints every 8 steps: loss, policy gradient
     (per parameter block) and initial-state gradient vs the FP64 oracle's
     autograd gradient (itself pinned to central FD with h = 1e-3)."""
     wk = wl.bptt(seed=11, n_envs=8, T=32, model=model)
     print_case("bptt_grad", model=model, A=8, T=32, K=8)
     theta = _theta(12)
-    e, eng = _engine(wk, 32, 8)
+    e, eng = _engine(wk, 32, 8, store)
     th, s0, goal = cuda(theta), cuda(wk.state0), cuda(wk.goal)
     loss = eng.forward(th, s0, goal)
     g_th, g_s0 = eng.backward()
@@ -82,8 +82,8 @@ def test_bptt_checkpoint_period_is_bitwise_invariant():
     theta = _theta(14)
     th, s0, goal = cuda(theta), cuda(wk.state0), cuda(wk.goal)
     outs = []
-    for K in (1, 5, 12):
-        e, eng = _engine(wk, 12, K)
+    for K, store in ((1, True), (5, True), (12, True), (5, False), (1, False)):
+        e, eng = _engine(wk, 12, K, store)
         loss = eng.forward(th, s0, goal)
         g_th, g_s0 = eng.backward()
         outs.append((loss.clone(), g_th.clone(), g_s0.clone()))
@@ -121,7 +121,8 @@ def test_bptt_full_size_sampled_agents():
     e, eng = _engine(wk, T, 8)
     eng.forward(th, s0, goal)
     g8, gs8 = eng.backward()
-    eng32 = __import__("paper_2509_10247_amd.bptt", fromlist=["x"]).BpttEngine(e, T, 32)
+    eng32 = __import__("paper_2509_10247_amd.bptt", fromlist=["x"]).BpttEngine(e, T, 32,
+                                                                                store_activations=False)
     eng32.forward(th, s0, goal)
     g32, gs32 = eng32.backward()
     assert torch.equal(g8, g32) and torch.equal(gs8, gs32)
