@@ -239,6 +239,66 @@ int policy_backward(const float* theta, const float* x, const float* g_y, float*
 int adam_step(int64_t n, float* w, const float* g, float* m, float* v, float lr, float b1,
               float b2, float eps, int32_t t, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Learned residual-dynamics surrogate of the full rigid-body model
+ * ------------------------------------------------------------------------
+ * The simplified model of Sec. III-A, Eq. (2) (body rates as inputs, no drag)
+ * plus a learned residual for what Eq. (1) adds (rotor drag and the
+ * first-order body-rate response):
+ *   s+ = N(s, a) + mu_d + sd_d * MLP((x - mu_x) / sd_x),  x = (s, a) (17),
+ * q renormalised. MLP 17 -> 256 -> 256 -> 13, SiLU hidden layers, BF16 GEMM
+ * operands (rounded to nearest even) with FP32 accumulation on MFMA, FP32
+ * master weights. theta flat FP32 [W1 (256x17), b1, W2 (256x256), b2,
+ * W3 (13x256), b3]. norm = [mu_x (17), sd_x (17), mu_d (13), sd_d (13)]. */
+#define SURROGATE_N_PARAMS 73741
+#define SURROGATE_N_NORM 60
+
+typedef struct surrogate_handle surrogate_handle;
+
+/* Workspace for batches (and surrogate steps) of up to max_batch rows. */
+int surrogate_create(int32_t max_batch, surrogate_handle** out);
+int surrogate_destroy(surrogate_handle* h);
+
+/* Training pairs from one full-model step of `full` (SIM_RB13, its dt and
+ * params): x_rows[i] = (s_i, a_i) [A][17], d_rows[i] = s_full_i - N(s_i, a_i)
+ * [A][13] with N the RK4 step of Eq. (2). s, a, s_full SoA as in sim_step. */
+int surrogate_pack(sim_handle* full, const float* s, const float* a, const float* s_full,
+                   float* x_rows, float* d_rows, void* stream);
+
+/* norm <- column means and standard deviations (population; a column with
+ * sd < 1e-6 gets sd = 1) of x_rows [N][17] and d_rows [N][13]. */
+int surrogate_fit_normalizer(surrogate_handle* h, const float* x_rows, const float* d_rows, int64_t N,
+                             float* norm, void* stream);
+
+/* Mean squared error of the z-scored residual on the first B rows and its
+ * gradient g_theta (flat, overwritten); loss: device float (nullable). */
+int surrogate_grad(surrogate_handle* h, const float* theta, const float* x_rows, const float* d_rows,
+                   const float* norm, int32_t B, float* g_theta, float* loss, void* stream);
+
+/* n_steps Adam steps (Kingma & Ba 2015; b1 0.9, b2 0.999, eps 1e-8, step
+ * count continuing from t0) on minibatches x_rows[perm[i*batch + j]],
+ * updating theta, m, v (flat FP32, in place); loss_hist[i] (device,
+ * nullable) receives each minibatch loss. perm: device int32 indices < N. */
+int surrogate_train(surrogate_handle* h, float* theta, float* m, float* v, int32_t t0,
+                    const float* x_rows, const float* d_rows, const float* norm, int64_t N,
+                    const int32_t* perm, int32_t batch, int32_t n_steps, float lr, float* loss_hist,
+                    void* stream);
+
+/* Loads theta (flat) as the weights used by sim_surrogate_step. */
+int surrogate_load(surrogate_handle* h, const float* theta, void* stream);
+
+/* One surrogate step for every agent of `full` (SIM_RB13 + RK4, its params),
+ * with the judge: agent i is judged when (i + t) % judge_period == 0 (its
+ * full step is computed and the per-block max errors p, v, q, w are written to
+ * judged_err [4][A], NaN when not judged; nullable); an agent whose judged
+ * error exceeds (1e-3 m, 1e-2 m/s, 1e-3, 1e-2 rad/s) in any block, or whose
+ * z-scored input leaves [-4, 4], gets fallback[i] = 1, and an agent with
+ * fallback[i] = 1 (sticky, in/out uint8 [A]) takes the full step. s_in and
+ * s_out must not alias. */
+int sim_surrogate_step(sim_handle* full, surrogate_handle* h, const float* norm, const float* s_in,
+                       const float* a, float* s_out, uint8_t* fallback, float* judged_err, int32_t t,
+                       int32_t judge_period, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -18,6 +18,8 @@ LIB_PATH = os.path.join(_DIR, "libdiffaero.so")
 SIM_PM6, SIM_PM9, SIM_RB13, SIM_NOMINAL13 = 0, 1, 2, 3
 SIM_EULER, SIM_RK4 = 0, 1
 POLICY_N_PARAMS = 855812
+SURROGATE_N_PARAMS = 73741
+SURROGATE_N_NORM = 60
 
 c_int, c_float, c_void_p, c_int64 = ctypes.c_int32, ctypes.c_float, ctypes.c_void_p, ctypes.c_int64
 
@@ -58,6 +60,17 @@ _SIGS = {
     "bptt_get_timing": (c_int, [c_void_p, ctypes.POINTER(c_float), ctypes.POINTER(c_int), c_int]),
     "policy_forward": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
     "policy_backward": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
+    "surrogate_create": (c_int, [c_int, ctypes.POINTER(c_void_p)]),
+    "surrogate_destroy": (c_int, [c_void_p]),
+    "surrogate_pack": (c_int, [c_void_p] * 7),
+    "surrogate_fit_normalizer": (c_int, [c_void_p, c_void_p, c_void_p, c_int64, c_void_p, c_void_p]),
+    "surrogate_grad": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_void_p,
+                               c_void_p]),
+    "surrogate_train": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_void_p,
+                                c_int64, c_void_p, c_int, c_int, c_float, c_void_p, c_void_p]),
+    "surrogate_load": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "sim_surrogate_step": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                   c_void_p, c_int, c_int, c_void_p]),
     "adam_step": (c_int, [c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_float, c_float,
                           c_float, c_float, c_int, c_void_p]),
 }
@@ -233,3 +246,50 @@ def adam_step(w, g, m, v, lr, b1, b2, eps, t):
     _call("adam_step", int(w.numel()), ptr(w, torch.float32), ptr(g, torch.float32),
           ptr(m, torch.float32), ptr(v, torch.float32), float(lr), float(b1), float(b2),
           float(eps), int(t), stream())
+
+
+# --------------------------------------------------------------------------
+# surrogate
+# --------------------------------------------------------------------------
+
+def surrogate_create(max_batch) -> int:
+    h = c_void_p()
+    _call("surrogate_create", int(max_batch), ctypes.byref(h))
+    return h.value
+
+
+def surrogate_destroy(h):
+    _call("surrogate_destroy", h)
+
+
+def surrogate_pack(sim, s, a, s_full, x_rows, d_rows):
+    _call("surrogate_pack", sim, ptr(s, torch.float32), ptr(a, torch.float32), ptr(s_full, torch.float32),
+          ptr(x_rows, torch.float32), ptr(d_rows, torch.float32), stream())
+
+
+def surrogate_fit_normalizer(h, x_rows, d_rows, norm):
+    _call("surrogate_fit_normalizer", h, ptr(x_rows, torch.float32), ptr(d_rows, torch.float32),
+          int(x_rows.shape[0]), ptr(norm, torch.float32), stream())
+
+
+def surrogate_grad(h, theta, x_rows, d_rows, norm, B, g_theta, loss=None):
+    _call("surrogate_grad", h, ptr(theta, torch.float32), ptr(x_rows, torch.float32),
+          ptr(d_rows, torch.float32), ptr(norm, torch.float32), int(B), ptr(g_theta, torch.float32),
+          ptr(loss, torch.float32), stream())
+
+
+def surrogate_train(h, theta, m, v, t0, x_rows, d_rows, norm, perm, batch, n_steps, lr, loss_hist=None):
+    _call("surrogate_train", h, ptr(theta, torch.float32), ptr(m, torch.float32), ptr(v, torch.float32),
+          int(t0), ptr(x_rows, torch.float32), ptr(d_rows, torch.float32), ptr(norm, torch.float32),
+          int(x_rows.shape[0]), ptr(perm, torch.int32), int(batch), int(n_steps), float(lr),
+          ptr(loss_hist, torch.float32), stream())
+
+
+def surrogate_load(h, theta):
+    _call("surrogate_load", h, ptr(theta, torch.float32), stream())
+
+
+def sim_surrogate_step(sim, h, norm, s_in, a, s_out, fallback, judged_err=None, t=0, judge_period=64):
+    _call("sim_surrogate_step", sim, h, ptr(norm, torch.float32), ptr(s_in, torch.float32),
+          ptr(a, torch.float32), ptr(s_out, torch.float32), ptr(fallback, torch.uint8),
+          ptr(judged_err, torch.float32), int(t), int(judge_period), stream())

@@ -71,6 +71,50 @@ __device__ __forceinline__ void store_tile(float* S, const float4 (&reg)[4]) {
   }
 }
 
+// Epilogue: lane holds column (lane & 31) of each 32x32 tile, rows
+// 8*(i/4) + 4*(lane/32) + (i%4) for accumulator i.
+template <int EPI>
+__device__ __forceinline__ void gemm_epilogue(const GemmArgs& g, const f32x16 (&acc)[2][2], int m0, int n0,
+                                              int wm, int wn, int col, int half) {
+  float* C = g.C;
+  if (EPI == EPI_PARTIAL) C += (size_t)blockIdx.z * g.M * g.ldc;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int n = n0 + wn + 32 * b + col;
+      if (n >= g.N) continue;
+      float bias = 0.f;
+      if (EPI == EPI_BIAS_TANH || EPI == EPI_BIAS || EPI == EPI_BIAS_SILU) bias = g.bias[n];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int m = m0 + wm + 32 * a + 8 * (i >> 2) + 4 * half + (i & 3);
+        if (m >= g.M) continue;
+        const size_t idx = (size_t)m * g.ldc + n;
+        float v = acc[a][b][i];
+        if (EPI == EPI_BIAS_TANH) {
+          v = tanhf(v + bias);
+        } else if (EPI == EPI_MUL_DTANH) {
+          const float h = g.aux[(size_t)m * g.ld_aux + n];
+          v = v * (1.f - h * h);
+        } else if (EPI == EPI_ACCUM) {
+          v += C[idx];
+        } else if (EPI == EPI_BIAS) {
+          v += bias;
+        } else if (EPI == EPI_BIAS_SILU) {
+          const float z = v + bias;
+          g.zout[(size_t)m * g.ld_z + n] = z;
+          v = z / (1.f + expf(-z));
+        } else if (EPI == EPI_MUL_DSILU) {
+          const float z = g.aux[(size_t)m * g.ld_aux + n];
+          const float sg = 1.f / (1.f + expf(-z));
+          v = v * (sg * (1.f + z * (1.f - sg)));
+        }
+        C[idx] = v;
+      }
+    }
+}
+
 template <bool AK, bool BK_, int EPI>
 __global__ __launch_bounds__(256) void gemm_f32_kernel(GemmArgs g) {
   constexpr int PA = Stage<AK>::PITCH, PB = Stage<BK_>::PITCH;
@@ -117,35 +161,98 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(GemmArgs g) {
     }
   }
 
-  // epilogue: lane holds column (lane & 31) of each 32x32 tile, rows
-  // 8*(i/4) + 4*(lane/32) + (i%4) for accumulator i
-  float* C = g.C;
-  if (EPI == EPI_PARTIAL) C += (size_t)blockIdx.z * g.M * g.ldc;
+  gemm_epilogue<EPI>(g, acc, m0, n0, wm, wn, col, half);
+}
+
+// ---------------------------------------------------------------------------
+// BF16 variant: same tiling and loaders; tiles are rounded to BF16 (nearest
+// even) on their way into LDS, stored K-contiguous ([row][32 + 8 pad]) so that
+// each lane reads its 8 consecutive-k operand elements as one 16-byte load.
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+constexpr int BKP = GBK + 8;
+
+__device__ __forceinline__ uint32_t bf16_bits(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;  // NaN stays quiet NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+
+template <bool KMAJ>
+__device__ __forceinline__ void store_tile_bf16(uint16_t* S, const float4 (&reg)[4]) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    if (KMAJ) {
+      const int row = (t >> 3) + 32 * i, k = (t & 7) * 4;
+      uint2 v;
+      v.x = bf16_bits(reg[i].x) | (bf16_bits(reg[i].y) << 16);
+      v.y = bf16_bits(reg[i].z) | (bf16_bits(reg[i].w) << 16);
+      *reinterpret_cast<uint2*>(S + row * BKP + k) = v;
+    } else {
+      const int kk = (t >> 5) + 8 * i, m = (t & 31) * 4;
+      S[(m + 0) * BKP + kk] = (uint16_t)bf16_bits(reg[i].x);
+      S[(m + 1) * BKP + kk] = (uint16_t)bf16_bits(reg[i].y);
+      S[(m + 2) * BKP + kk] = (uint16_t)bf16_bits(reg[i].z);
+      S[(m + 3) * BKP + kk] = (uint16_t)bf16_bits(reg[i].w);
+    }
+  }
+}
+
+template <bool AK, bool BK_, int EPI>
+__global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[GBM * BKP];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[GBN * BKP];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  const int m0 = blockIdx.y * GBM, n0 = blockIdx.x * GBN;
+  const int kbeg = blockIdx.z * g.k_split;
+  const int kend = min(g.K, kbeg + g.k_split);
+  f32x16 acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      const int n = n0 + wn + 32 * b + col;
-      if (n >= g.N) continue;
-      float bias = 0.f;
-      if (EPI == EPI_BIAS_TANH) bias = g.bias[n];
+    for (int b = 0; b < 2; ++b)
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const int m = m0 + wm + 32 * a + 8 * (i >> 2) + 4 * half + (i & 3);
-        if (m >= g.M) continue;
-        const size_t idx = (size_t)m * g.ldc + n;
-        float v = acc[a][b][i];
-        if (EPI == EPI_BIAS_TANH) {
-          v = tanhf(v + bias);
-        } else if (EPI == EPI_MUL_DTANH) {
-          const float h = g.aux[(size_t)m * g.ld_aux + n];
-          v = v * (1.f - h * h);
-        } else if (EPI == EPI_ACCUM) {
-          v += C[idx];
-        }
-        C[idx] = v;
-      }
+      for (int i = 0; i < 16; ++i) acc[a][b][i] = 0.f;
+  float4 ra[4], rb[4];
+  if (kbeg < kend) {
+    load_tile<AK>(g.A, g.lda, g.M, kend, m0, kbeg, ra);
+    load_tile<BK_>(g.B, g.ldb, g.N, kend, n0, kbeg, rb);
+  }
+  const int col = lane & 31, half = lane >> 5;
+  for (int k0 = kbeg; k0 < kend; k0 += GBK) {
+    __syncthreads();
+    store_tile_bf16<AK>(As, ra);
+    store_tile_bf16<BK_>(Bs, rb);
+    __syncthreads();
+    if (k0 + GBK < kend) {
+      load_tile<AK>(g.A, g.lda, g.M, kend, m0, k0 + GBK, ra);
+      load_tile<BK_>(g.B, g.ldb, g.N, kend, n0, k0 + GBK, rb);
     }
+#pragma unroll
+    for (int s = 0; s < GBK / 16; ++s) {
+      const int ko = s * 16 + half * 8;
+      const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(As + (wm + col) * BKP + ko);
+      const bf16x8 a1 = *reinterpret_cast<const bf16x8*>(As + (wm + 32 + col) * BKP + ko);
+      const bf16x8 b0 = *reinterpret_cast<const bf16x8*>(Bs + (wn + col) * BKP + ko);
+      const bf16x8 b1 = *reinterpret_cast<const bf16x8*>(Bs + (wn + 32 + col) * BKP + ko);
+      acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc[1][1], 0, 0, 0);
+    }
+  }
+  gemm_epilogue<EPI>(g, acc, m0, n0, wm, wn, col, half);
+}
+
+template <bool AK, bool BK_, int EPI>
+static int gemm_bf16_t(const GemmArgs& g, int splits, hipStream_t st) {
+  dim3 grid(cdiv(g.N, GBN), cdiv(g.M, GBM), splits);
+  hipLaunchKernelGGL((gemm_bf16_kernel<AK, BK_, EPI>), grid, dim3(256), 0, st, g);
+  DA_LAUNCH_CHECK("gemm_bf16_kernel");
+  return SIM_OK;
 }
 
 template <bool AK, bool BK_, int EPI>
@@ -156,7 +263,7 @@ static int gemm_t(const GemmArgs& g, int splits, hipStream_t st) {
   return SIM_OK;
 }
 
-int launch_gemm(bool a_kmaj, bool b_kmaj, int epi, GemmArgs g, int splits, hipStream_t st) {
+int launch_gemm(bool a_kmaj, bool b_kmaj, int epi, GemmArgs g, int splits, hipStream_t st, bool bf16) {
   if (g.M == 0 || g.N == 0) return SIM_OK;
   if (splits < 1) splits = 1;
   g.k_split = (int)(cdiv64(cdiv64(g.K, splits), GBK) * GBK);
@@ -166,6 +273,15 @@ int launch_gemm(bool a_kmaj, bool b_kmaj, int epi, GemmArgs g, int splits, hipSt
       (reinterpret_cast<uintptr_t>(g.B) & 15))
     return fail(SIM_EINVAL, "gemm: operands need 16-byte alignment and leading dims %% 4 == 0");
   const int key = (a_kmaj ? 1 : 0) | (b_kmaj ? 2 : 0);
+  if (bf16) {
+    // the layer shapes of the residual-dynamics MLP
+    if (key == 3 && epi == EPI_BIAS_SILU) return gemm_bf16_t<true, true, EPI_BIAS_SILU>(g, 1, st);
+    if (key == 3 && epi == EPI_BIAS) return gemm_bf16_t<true, true, EPI_BIAS>(g, 1, st);
+    if (key == 1 && epi == EPI_MUL_DSILU) return gemm_bf16_t<true, false, EPI_MUL_DSILU>(g, 1, st);
+    if (key == 1 && epi == EPI_STORE) return gemm_bf16_t<true, false, EPI_STORE>(g, 1, st);
+    if (key == 0 && epi == EPI_PARTIAL) return gemm_bf16_t<false, false, EPI_PARTIAL>(g, splits, st);
+    return fail(SIM_EINVAL, "gemm: bf16 layout %d / epilogue %d not built", key, epi);
+  }
 #define DA_GEMM_CASE(AK, BKM)                                              \
   switch (epi) {                                                          \
     case EPI_STORE: return gemm_t<AK, BKM, EPI_STORE>(g, 1, st);          \

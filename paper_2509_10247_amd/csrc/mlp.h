@@ -5,7 +5,16 @@
 
 namespace da {
 
-enum { EPI_STORE = 0, EPI_BIAS_TANH = 1, EPI_MUL_DTANH = 2, EPI_ACCUM = 3, EPI_PARTIAL = 4 };
+enum {
+  EPI_STORE = 0,      // C = acc
+  EPI_BIAS_TANH = 1,  // C = tanh(acc + bias[n])
+  EPI_MUL_DTANH = 2,  // C = acc (1 - aux^2)
+  EPI_ACCUM = 3,      // C += acc
+  EPI_PARTIAL = 4,    // split-K partial store
+  EPI_BIAS = 5,       // C = acc + bias[n]
+  EPI_BIAS_SILU = 6,  // z = acc + bias[n]; zout = z; C = z sigmoid(z)
+  EPI_MUL_DSILU = 7   // z = aux; C = acc * d silu(z)/dz
+};
 
 // C[M][N] = op(A) op(B). A is [M][lda] (K-contiguous) or [K][lda]
 // (M-contiguous); B is [N][ldb] (K-contiguous) or [K][ldb] (N-contiguous).
@@ -20,12 +29,18 @@ struct GemmArgs {
   float* C = nullptr;
   int ldc = 0;
   const float* bias = nullptr;  // EPI_BIAS_TANH: [N]
-  const float* aux = nullptr;   // EPI_MUL_DTANH: H [M][ld_aux]
+  const float* aux = nullptr;   // EPI_MUL_DTANH: H, EPI_MUL_DSILU: Z  [M][ld_aux]
   int ld_aux = 0;
+  float* zout = nullptr;        // EPI_BIAS_SILU: pre-activation [M][ld_z]
+  int ld_z = 0;
   int k_split = 0;              // set by launch_gemm
 };
 
-int launch_gemm(bool a_kmaj, bool b_kmaj, int epi, GemmArgs g, int splits, hipStream_t st);
+// bf16: operands are read as FP32 and rounded to BF16 (nearest even) when
+// staged into LDS; the product runs on v_mfma_f32_32x32x16_bf16 with FP32
+// accumulation.
+int launch_gemm(bool a_kmaj, bool b_kmaj, int epi, GemmArgs g, int splits, hipStream_t st,
+                bool bf16 = false);
 int gemm_splits_used(int K, int splits);
 int launch_splitk_reduce(int S, int M, int N, int ldp, const float* part, float* out, int ldo,
                          bool accumulate, hipStream_t st);
