@@ -38,7 +38,155 @@ def parse():
                    help="keep only the K-step state checkpoints (recompute policy and step too)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-kernel-timing", action="store_true")
+    p.add_argument("--sections", default="surrogate,uneven",
+                   help="comma list of extra sections to run after the headline: surrogate, uneven")
     return p.parse_args()
+
+
+def uneven_section(T=128, reps=3, seed=0):
+    """Uneven batching: 8192 envs with 0..256 obstacles and 1..8 agents each,
+    RB13 RK4, LiDAR 16x360 (20 m) + camera 64x48 (10 m) per agent, T-step
+    rollout. Fused = persistent kernel per step with a longest-first work
+    queue, autotuned, T steps in one hipGraph; plain = dynamics, camera and
+    LiDAR launched per step (same device code, bitwise-equal outputs)."""
+    import tempfile
+    import torch
+    import workloads as wl
+    from paper_2509_10247_amd import _lib, env
+    wk = wl.uneven(seed=seed, n_envs=8192, T=T)
+    e = env.from_workload(wk)
+    A = wk.scene.n_agents
+    depth = torch.empty(2, A, 48, 64, device="cuda")
+    lidar = torch.empty(2, A, 16, 360, device="cuda")
+    flags = torch.zeros(A, dtype=torch.uint8, device="cuda")
+    s0 = torch.tensor(wk.state0, device="cuda")
+    acts = torch.tensor(wk.actions, device="cuda")
+    s = s0.clone()
+    path = os.path.join(tempfile.gettempdir(), "diffaero_autotune.json")
+    t0 = time.perf_counter()
+    tune_ms = _lib.sim_autotune(e.h, s0, acts[0], depth[0], lidar[0], path)
+    tune_s = time.perf_counter() - t0
+    cfg = _lib.sim_rollout_get_config(e.h)
+
+    def run(mode):
+        s.copy_(s0)
+        flags.zero_()
+        _lib.sim_rollout(e.h, T, s, acts, depth, lidar, flags, mode)
+
+    out = {"workload": f"8192 envs, {A} agents, {int(wk.scene.sph_off[-1] + wk.scene.box_off[-1])} obstacles, "
+                       f"T={T}, lidar 16x360 + camera 64x48",
+           "tuned": {"tile_group": cfg[0], "blocks_per_cu": cfg[1], "order": cfg[2],
+                     "step_ms": round(tune_ms, 4), "tune_s": round(tune_s, 1)}}
+    for name, mode, n in (("fused_graph", _lib.ROLLOUT_GRAPH, reps), ("plain", _lib.ROLLOUT_PLAIN, 1)):
+        run(mode)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n):
+            run(mode)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / n
+        out[name] = {"ms_per_rollout": round(dt * 1e3, 2), "env_steps_per_s": round(8192 * T / dt, 1),
+                     "agent_steps_per_s": round(A * T / dt, 1),
+                     "rays_per_s": round(A * T * (3072 + 5760) / dt, 1)}
+    out["fused_over_plain"] = round(out["plain"]["ms_per_rollout"] / out["fused_graph"]["ms_per_rollout"], 3)
+    return out
+
+
+def surrogate_section(seed=0):
+    """Learned residual surrogate vs the full rigid-body model on the same
+    GPU: trained on 40 x 4096 x 64 = 10.5M full-model transitions (20 epochs,
+    batch 8192, Adam 1e-3), evaluated on 65536 envs x 64 steps with the judge
+    (1/64 of agents per step) and sticky fallback. Errors are one-step errors
+    against the FP32 full model from the same state."""
+    import numpy as np
+    import torch
+    import workloads as wl
+    from paper_2509_10247_amd import env, surrogate
+    out = {}
+    A, T, R = 4096, 64, 40
+    x = torch.empty(A * T * R, 17, device="cuda")
+    d = torch.empty(A * T * R, 13, device="cuda")
+    t0 = time.perf_counter()
+    for r in range(R):
+        wk = wl.surrogate_full(seed=100 + r, n_envs=A, T=T)
+        e = env.from_workload(wk)
+        surrogate.Surrogate.collect(e, torch.tensor(wk.state0, device="cuda"),
+                                    torch.tensor(wk.actions, device="cuda"), x, d, offset=r * A * T)
+    torch.cuda.synchronize()
+    out["transitions"] = A * T * R
+    out["data_s"] = round(time.perf_counter() - t0, 2)
+    NE, TE = 65536, 64
+    sur = surrogate.Surrogate(max_batch=NE)
+    sur.fit_normalizer(x, d)
+    theta = torch.tensor(wl.flatten_mlp(wl.mlp_init(np.random.default_rng(seed), wl.SURROGATE_DIMS)),
+                         device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = sur.train(x, d, theta, epochs=20, batch=8192, lr=1e-3, seed=seed)
+    torch.cuda.synchronize()
+    out["train_s"] = round(time.perf_counter() - t0, 2)
+    out["train_steps_per_s"] = round(len(hist) / (time.perf_counter() - t0), 1)
+    out["final_loss"] = float(hist[-1].item())
+    del x, d
+    wk = wl.surrogate_full(seed=seed, n_envs=NE, T=TE)
+    e = env.from_workload(wk)
+    s0 = torch.tensor(wk.state0, device="cuda")
+    acts = torch.tensor(wk.actions, device="cuda")
+    buf = [s0.clone(), torch.empty_like(s0)]
+    fb = torch.zeros(NE, dtype=torch.uint8, device="cuda")
+    err = torch.empty(4, NE, device="cuda")
+
+    def run_sur(judge=True):
+        buf[0].copy_(s0)
+        fb.zero_()
+        for t in range(TE):
+            sur.step(e, buf[t & 1], acts[t], buf[(t + 1) & 1], fb, err if judge else None, t=t,
+                     judge_period=64 if judge else 1 << 30)
+
+    def run_full():
+        buf[0].copy_(s0)
+        for t in range(TE):
+            e.step(buf[t & 1], acts[t], out=buf[(t + 1) & 1])
+
+    for fn in (run_sur, run_full):
+        fn()
+    torch.cuda.synchronize()
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        run_full()
+    torch.cuda.synchronize()
+    t_full = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        run_sur()
+    torch.cuda.synchronize()
+    t_sur = (time.perf_counter() - t0) / reps
+    out["eval"] = f"{NE} envs x {TE} steps"
+    out["surrogate_env_steps_per_s"] = round(NE * TE / t_sur, 1)
+    out["full_env_steps_per_s"] = round(NE * TE / t_full, 1)
+    out["surrogate_over_full_speed"] = round(t_full / t_sur, 4)
+    out["fallback_frac_after_rollout"] = round(fb.float().mean().item(), 5)
+    # one-step accuracy along the full-model trajectory (no judge, no fallback)
+    ne = env.from_workload(wl.Workload("nominal", wl.NOMINAL13, wl.RK4, 0.01, 1, wk.scene, wk.state0,
+                                       wk.params, None, None, None))
+    s = s0.clone()
+    es, en = [], []
+    blocks = {"p": (0, 3), "v": (3, 6), "q": (6, 10), "w": (10, 13)}
+    so = torch.empty_like(s)
+    for t in range(0, TE, 8):
+        full = e.step(s, acts[t])
+        nom = ne.step(s, acts[t])
+        fb.zero_()
+        sur.step(e, s, acts[t], so, fb, None, t=0, judge_period=1 << 30)
+        es.append((so - full)[:, :8192].double())
+        en.append((nom - full)[:, :8192].double())
+        s = full
+    es, en = torch.cat(es, 1), torch.cat(en, 1)
+    out["one_step_rms_surrogate"] = {k: float(es[a:b].pow(2).mean().sqrt()) for k, (a, b) in blocks.items()}
+    out["one_step_rms_nominal"] = {k: float(en[a:b].pow(2).mean().sqrt()) for k, (a, b) in blocks.items()}
+    out["one_step_max_surrogate"] = {k: float(es[a:b].abs().max()) for k, (a, b) in blocks.items()}
+    return out
 
 
 def cpu_baseline(model, seed=0, n_envs=64, T=32):
@@ -143,6 +291,11 @@ def main():
         "roofline": roofline,
         "kernel_breakdown": breakdown,
     }
+    sections = [x for x in args.sections.split(",") if x]
+    if "surrogate" in sections:
+        line["surrogate"] = surrogate_section()
+    if "uneven" in sections:
+        line["uneven"] = uneven_section()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(model)
     print(json.dumps(line), flush=True)

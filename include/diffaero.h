@@ -240,6 +240,46 @@ int adam_step(int64_t n, float* w, const float* g, float* m, float* v, float lr,
               float b2, float eps, int32_t t, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Uneven-batch rollouts (environment- and agent-level parallelism, Sec. III;
+ * FOV-excluding ray casting, Sec. III-B): T steps of every agent with
+ * per-env obstacle and agent counts as set by sim_set_scene.
+ * ------------------------------------------------------------------------
+ * Per step t: camera and LiDAR images at s_t into ring slot t % 2 of
+ * depth_ring [2][A][H][W] / lidar_ring [2][A][ch][az] (each required exactly
+ * when that sensor is configured), collision test at s_t and step
+ * s_{t+1} = step(s_t, a_t) with a_t = a_seq + t*K*A (a_seq [T][K][A]);
+ * flags[i] (nullable, uint8 [A], caller-initialised) accumulates
+ * SIM_FLAG_NONFINITE / SIM_FLAG_COLLISION with OR. s (SoA [C][A]) holds s_0
+ * on entry and s_T on return. All outputs are identical in every mode and
+ * for every tuning choice.
+ * mode 0: one persistent fused kernel per step (render items for camera /
+ *         LiDAR tile groups, dynamics items), longest-first work queue, the T
+ *         launches captured once in a hipGraph and replayed on later calls
+ *         with the same T, pointers and tuning;
+ * mode 1: plain launch per operation (dynamics, camera, LiDAR) per step;
+ * mode 2: the fused kernel without a graph.
+ * The handle owns a second state buffer, per-step work counters and the
+ * graph; the first call with a new shape allocates them (synchronous). */
+int sim_rollout(sim_handle* h, int32_t T, float* s, const float* a_seq, float* depth_ring,
+                float* lidar_ring, uint8_t* flags, int32_t mode, void* stream);
+
+/* Sets the fused kernel's tuning: tile_group = camera / LiDAR tiles (64 rays
+ * each) per work item, blocks_per_cu = persistent workgroups per compute unit
+ * (1..16), order = 1 longest-first, 0 env order. Synchronous. */
+int sim_rollout_config(sim_handle* h, int32_t tile_group, int32_t blocks_per_cu, int32_t order);
+int sim_rollout_get_config(sim_handle* h, int32_t* tile_group, int32_t* blocks_per_cu, int32_t* order);
+
+/* Times one fused step from state s / action a (SoA, not modified; outputs
+ * written to depth / lidar [A][...]) for every (tile_group in {2,4,8,16,all},
+ * blocks_per_cu in {2,4,8}, order in {1,0}), keeps the fastest (median of 3
+ * after a warm-up) and records it in the JSON file cache_path (nullable)
+ * under a key of the device and problem shape; a matching cache entry is
+ * used without timing (best_ms = -1). best_ms: host float, nullable. The
+ * only rollout call that synchronizes the stream. */
+int sim_autotune(sim_handle* h, const float* s, const float* a, float* depth, float* lidar,
+                 const char* cache_path, float* best_ms, void* stream);
+
+/* ------------------------------------------------------------------------
  * Learned residual-dynamics surrogate of the full rigid-body model
  * ------------------------------------------------------------------------
  * The simplified model of Sec. III-A, Eq. (2) (body rates as inputs, no drag)
@@ -291,13 +331,14 @@ int surrogate_load(surrogate_handle* h, const float* theta, void* stream);
  * with the judge: agent i is judged when (i + t) % judge_period == 0 (its
  * full step is computed and the per-block max errors p, v, q, w are written to
  * judged_err [4][A], NaN when not judged; nullable); an agent whose judged
- * error exceeds (1e-3 m, 1e-2 m/s, 1e-3, 1e-2 rad/s) in any block, or whose
- * z-scored input leaves [-4, 4], gets fallback[i] = 1, and an agent with
- * fallback[i] = 1 (sticky, in/out uint8 [A]) takes the full step. s_in and
- * s_out must not alias. */
+ * error exceeds thresholds[k] in any block k (host float[4] for p [m], v [m/s],
+ * q [-], w [rad/s]; NULL = 1e-3, 1e-2, 2e-3, 1e-1), or whose z-scored input
+ * leaves [-4, 4], gets fallback[i] = 1, and an agent with fallback[i] = 1
+ * (sticky, in/out uint8 [A]) takes the full step. s_in and s_out must not
+ * alias. */
 int sim_surrogate_step(sim_handle* full, surrogate_handle* h, const float* norm, const float* s_in,
                        const float* a, float* s_out, uint8_t* fallback, float* judged_err, int32_t t,
-                       int32_t judge_period, void* stream);
+                       int32_t judge_period, const float* thresholds, void* stream);
 
 #ifdef __cplusplus
 }

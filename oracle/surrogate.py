@@ -28,7 +28,7 @@ from . import dynamics as dyn
 
 OOD_Z = 4.0
 # judge thresholds per state block: p [m], v [m/s], q [-], w [rad/s]
-ERR_THRESH = (1e-3, 1e-2, 1e-3, 1e-2)
+ERR_THRESH = (1e-3, 1e-2, 2e-3, 1e-1)
 BLOCKS = ((0, 3), (3, 6), (6, 10), (10, 13))
 
 

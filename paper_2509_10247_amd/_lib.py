@@ -60,6 +60,12 @@ _SIGS = {
     "bptt_get_timing": (c_int, [c_void_p, ctypes.POINTER(c_float), ctypes.POINTER(c_int), c_int]),
     "policy_forward": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
     "policy_backward": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
+    "sim_rollout": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
+    "sim_rollout_config": (c_int, [c_void_p, c_int, c_int, c_int]),
+    "sim_rollout_get_config": (c_int, [c_void_p, ctypes.POINTER(c_int), ctypes.POINTER(c_int),
+                                       ctypes.POINTER(c_int)]),
+    "sim_autotune": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, ctypes.c_char_p,
+                             ctypes.POINTER(c_float), c_void_p]),
     "surrogate_create": (c_int, [c_int, ctypes.POINTER(c_void_p)]),
     "surrogate_destroy": (c_int, [c_void_p]),
     "surrogate_pack": (c_int, [c_void_p] * 7),
@@ -70,7 +76,7 @@ _SIGS = {
                                 c_int64, c_void_p, c_int, c_int, c_float, c_void_p, c_void_p]),
     "surrogate_load": (c_int, [c_void_p, c_void_p, c_void_p]),
     "sim_surrogate_step": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
-                                   c_void_p, c_int, c_int, c_void_p]),
+                                   c_void_p, c_int, c_int, ctypes.POINTER(c_float), c_void_p]),
     "adam_step": (c_int, [c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_float, c_float,
                           c_float, c_float, c_int, c_void_p]),
 }
@@ -249,6 +255,36 @@ def adam_step(w, g, m, v, lr, b1, b2, eps, t):
 
 
 # --------------------------------------------------------------------------
+# uneven-batch rollout
+# --------------------------------------------------------------------------
+ROLLOUT_GRAPH, ROLLOUT_PLAIN, ROLLOUT_FUSED = 0, 1, 2
+
+
+def sim_rollout(h, T, s, a_seq, depth_ring=None, lidar_ring=None, flags=None, mode=ROLLOUT_GRAPH):
+    _call("sim_rollout", h, int(T), ptr(s, torch.float32), ptr(a_seq, torch.float32),
+          ptr(depth_ring, torch.float32), ptr(lidar_ring, torch.float32), ptr(flags, torch.uint8), int(mode),
+          stream())
+
+
+def sim_rollout_config(h, tile_group, blocks_per_cu, order):
+    _call("sim_rollout_config", h, int(tile_group), int(blocks_per_cu), int(order))
+
+
+def sim_rollout_get_config(h):
+    a, b, c = c_int(), c_int(), c_int()
+    _call("sim_rollout_get_config", h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
+    return a.value, b.value, c.value
+
+
+def sim_autotune(h, s, a, depth=None, lidar=None, cache_path=None):
+    best = c_float()
+    _call("sim_autotune", h, ptr(s, torch.float32), ptr(a, torch.float32), ptr(depth, torch.float32),
+          ptr(lidar, torch.float32), None if cache_path is None else cache_path.encode(), ctypes.byref(best),
+          stream())
+    return best.value
+
+
+# --------------------------------------------------------------------------
 # surrogate
 # --------------------------------------------------------------------------
 
@@ -289,7 +325,9 @@ def surrogate_load(h, theta):
     _call("surrogate_load", h, ptr(theta, torch.float32), stream())
 
 
-def sim_surrogate_step(sim, h, norm, s_in, a, s_out, fallback, judged_err=None, t=0, judge_period=64):
+def sim_surrogate_step(sim, h, norm, s_in, a, s_out, fallback, judged_err=None, t=0, judge_period=64,
+                       thresholds=None):
+    thr = None if thresholds is None else (c_float * 4)(*[float(x) for x in thresholds])
     _call("sim_surrogate_step", sim, h, ptr(norm, torch.float32), ptr(s_in, torch.float32),
           ptr(a, torch.float32), ptr(s_out, torch.float32), ptr(fallback, torch.uint8),
-          ptr(judged_err, torch.float32), int(t), int(judge_period), stream())
+          ptr(judged_err, torch.float32), int(t), int(judge_period), thr, stream())

@@ -16,10 +16,13 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libdiffaero.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["sim.hip", "dynamics.hip", "render.hip", "gemm.hip", "bptt.hip", "surrogate.hip"]
+SOURCES = ["sim.hip", "dynamics.hip", "render.hip", "gemm.hip", "bptt.hip", "surrogate.hip", "rollout.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+    # FMA contraction only within one source expression, so the same device
+    # function rounds identically in every kernel that inlines it
+    "-ffp-contract=on",
     # no packed-FP32 VALU instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-result",

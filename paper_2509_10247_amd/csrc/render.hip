@@ -16,97 +16,9 @@
 // primitive's hit for its rays, applies dt/do = -n/(n.d) and
 // dt/dd = -t n/(n.d), and the workgroup reduces dL/do and dL/dR = sum g_d d_b^T
 // in a fixed order before pulling dL/dR back to the quaternion.
-#include "kernels.h"
+#include "render_device.h"
 
 namespace da {
-
-constexpr float kInf = __builtin_huge_valf();
-
-struct RenderLds {
-  float4* pa;  // sphere (w, r^2) | box lo'
-  float4* pb;  // sphere (C, ...) | box hi'
-  float4* pc;  // bounding sphere (centre - o, radius); radius < 0: never hit
-  short* lists;
-  int* flag;
-};
-
-__device__ __forceinline__ RenderLds carve(void* base, int P) {
-  RenderLds L;
-  L.pa = reinterpret_cast<float4*>(base);
-  L.pb = L.pa + P;
-  L.pc = L.pb + P;
-  L.flag = reinterpret_cast<int*>(L.pc + P);
-  L.lists = reinterpret_cast<short*>(L.flag + 4);
-  return L;
-}
-
-static size_t render_lds_bytes(int P) {
-  return (size_t)P * 3 * sizeof(float4) + 4 * sizeof(int) + (size_t)4 * P * sizeof(short) + 16;
-}
-
-__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-
-// softplus(x) = max(x, 0) + log(1 + exp(-|x|)) on the hardware exp2 / log2 units.
-__device__ __forceinline__ float softplus_fast(float x) {
-  return fmaxf(x, 0.f) + __logf(1.f + __expf(-fabsf(x)));
-}
-
-// Sphere test with origin-relative centre w = c - o, r2 = r^2, C = |w|^2 - r^2 > 0
-// (origin outside). Nearest root written as C / (tc + sqrt(disc)) with the
-// discriminant taken from the perpendicular distance, which avoids the
-// cancellation of the textbook form at grazing incidence and near the surface.
-__device__ __forceinline__ float sphere_t(f3 d, float4 w, float C) {
-  const float tc = d.x * w.x + d.y * w.y + d.z * w.z;
-  const float px = w.x - tc * d.x, py = w.y - tc * d.y, pz = w.z - tc * d.z;
-  const float disc = w.w - (px * px + py * py + pz * pz);
-  if (tc > 0.f && disc >= 0.f) return C * fast_rcp(tc + __builtin_amdgcn_sqrtf(disc));
-  return kInf;
-}
-
-// Slab test against the box [lo', hi'] (origin-relative, origin outside).
-__device__ __forceinline__ float box_t(f3 inv, float4 lo, float4 hi) {
-  const float t1x = lo.x * inv.x, t2x = hi.x * inv.x;
-  const float t1y = lo.y * inv.y, t2y = hi.y * inv.y;
-  const float t1z = lo.z * inv.z, t2z = hi.z * inv.z;
-  const float tn = fmaxf(fmaxf(fminf(t1x, t2x), fminf(t1y, t2y)), fminf(t1z, t2z));
-  const float tf = fminf(fminf(fmaxf(t1x, t2x), fmaxf(t1y, t2y)), fmaxf(t1z, t2z));
-  return (tn <= tf && tn >= 0.f) ? tn : kInf;
-}
-
-// Exit distance from the room [rlo', rhi'] (origin inside).
-__device__ __forceinline__ float room_t(f3 inv, f3 rlo, f3 rhi) {
-  const float tx = (inv.x > 0.f ? rhi.x : rlo.x) * inv.x;
-  const float ty = (inv.y > 0.f ? rhi.y : rlo.y) * inv.y;
-  const float tz = (inv.z > 0.f ? rhi.z : rlo.z) * inv.z;
-  return fminf(fminf(tx, ty), tz);
-}
-
-// Conservative cone + range test of a bounding sphere (centre w, radius rho)
-// against a tile cone (world axis ax, cos/sin of the half-angle) and range
-// limit: the sphere meets the cone iff angle(ax, w) <= alpha + asin(rho/|w|).
-__device__ __forceinline__ bool cone_keep(float4 b, f3 ax, float cosA, float sinA, float tlim) {
-  if (b.w < 0.f) return false;
-  const float rho = b.w * 1.0001f + 1e-4f;
-  const float L2 = b.x * b.x + b.y * b.y + b.z * b.z;
-  if (L2 <= rho * rho) return true;
-  const float L = sqrtf(L2);
-  if (L - rho > tlim) return false;
-  const float rhs = cosA * sqrtf(L2 - rho * rho) - sinA * rho;
-  return ax.x * b.x + ax.y * b.y + ax.z * b.z >= rhs;
-}
-
-template <bool ROT>
-__device__ __forceinline__ Rot agent_rot(const float* s, int A, int i) {
-  Rot R;
-  if (ROT) {
-    float q[4] = {s[6 * (size_t)A + i], s[7 * (size_t)A + i], s[8 * (size_t)A + i],
-                  s[9 * (size_t)A + i]};
-    float qn[4];
-    quat_normalize(q, qn, nullptr);
-    R = rot_of_unit(qn);
-  }
-  return R;
-}
 
 template <bool ROT, bool CULL>
 __global__ __launch_bounds__(256) void render_kernel(SceneDev sc, SensorDev sen,
@@ -116,177 +28,8 @@ __global__ __launch_bounds__(256) void render_kernel(SceneDev sc, SensorDev sen,
                                                      float out_scale, float* __restrict__ term,
                                                      float beta, float d_safe) {
   extern __shared__ float4 smem_f4[];
-  const int P = sc.max_prims > 0 ? sc.max_prims : 1;
-  RenderLds L = carve(smem_f4, P);
-  const int i = blockIdx.x;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int env = sc.agent_env[i];
-  const f3 o = mk3(s[i], s[(size_t)A + i], s[2 * (size_t)A + i]);
-  const Rot R = agent_rot<ROT>(s, A, i);
-
-  const int s0 = sc.sph_off[env], ns = sc.sph_off[env + 1] - s0;
-  const int b0 = sc.box_off[env], nb = sc.box_off[env + 1] - b0;
-  int a0 = 0, na = 0;
-  if (sc.agents_visible) {
-    a0 = sc.agent_off[env];
-    na = sc.agent_off[env + 1] - a0;
-  }
-  const int np = ns + nb + na;
-  if (tid == 0) *L.flag = 0;
-  __syncthreads();
-
-  bool ins = false;
-  for (int k = tid; k < np; k += 256) {
-    if (k < ns) {
-      const float4 c = reinterpret_cast<const float4*>(sc.sph)[s0 + k];
-      const f3 w = mk3(c.x - o.x, c.y - o.y, c.z - o.z);
-      const float r2 = c.w * c.w;
-      const float C = dot(w, w) - r2;
-      L.pa[k] = make_float4(w.x, w.y, w.z, r2);
-      L.pb[k] = make_float4(C, 0.f, 0.f, 0.f);
-      L.pc[k] = make_float4(w.x, w.y, w.z, c.w);
-      ins |= C <= 0.f;
-    } else if (k < ns + nb) {
-      const float* b = sc.box + (size_t)(b0 + k - ns) * 6;
-      const f3 lo = mk3(b[0] - b[3] - o.x, b[1] - b[4] - o.y, b[2] - b[5] - o.z);
-      const f3 hi = mk3(b[0] + b[3] - o.x, b[1] + b[4] - o.y, b[2] + b[5] - o.z);
-      L.pa[k] = make_float4(lo.x, lo.y, lo.z, 0.f);
-      L.pb[k] = make_float4(hi.x, hi.y, hi.z, 0.f);
-      L.pc[k] = make_float4(0.5f * (lo.x + hi.x), 0.5f * (lo.y + hi.y), 0.5f * (lo.z + hi.z),
-                            sqrtf(b[3] * b[3] + b[4] * b[4] + b[5] * b[5]));
-      ins |= (lo.x < 0.f && hi.x > 0.f && lo.y < 0.f && hi.y > 0.f && lo.z < 0.f && hi.z > 0.f);
-    } else {
-      const int j = a0 + (k - ns - nb);
-      if (j == i) {
-        L.pa[k] = make_float4(0.f, 0.f, 0.f, -1.f);
-        L.pb[k] = make_float4(1.f, 0.f, 0.f, 0.f);
-        L.pc[k] = make_float4(0.f, 0.f, 0.f, -1.f);
-      } else {
-        const f3 w = mk3(s[j] - o.x, s[(size_t)A + j] - o.y, s[2 * (size_t)A + j] - o.z);
-        const float r2 = sc.agent_radius * sc.agent_radius;
-        const float C = dot(w, w) - r2;
-        L.pa[k] = make_float4(w.x, w.y, w.z, r2);
-        L.pb[k] = make_float4(C, 0.f, 0.f, 0.f);
-        L.pc[k] = make_float4(w.x, w.y, w.z, sc.agent_radius);
-        ins |= C <= 0.f;
-      }
-    }
-  }
-  const bool has_room = sc.room != nullptr;
-  f3 rlo = mk3(0.f, 0.f, 0.f), rhi = rlo;
-  if (has_room) {
-    const float* rm = sc.room + (size_t)env * 6;
-    rlo = mk3(rm[0] - o.x, rm[1] - o.y, rm[2] - o.z);
-    rhi = mk3(rm[3] - o.x, rm[4] - o.y, rm[5] - o.z);
-    if (tid == 0 && (rlo.x > 0.f || rlo.y > 0.f || rlo.z > 0.f || rhi.x < 0.f || rhi.y < 0.f ||
-                     rhi.z < 0.f))
-      ins = true;
-  }
-  if (ins) atomicOr(L.flag, 1);
-  __syncthreads();
-  const bool inside = *L.flag != 0;
-  const int nr = sen.n_rays;
-  float* orow = out + (size_t)i * out_ld;
-  int* rrow = rec ? rec + (size_t)i * nr : nullptr;
-  short* list = L.lists + wave * P;
-  const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  float tacc = 0.f;  // optional per-agent sum of softplus(beta (d_safe - value)) / beta
-
-  for (int tile = wave; tile < sen.n_tiles; tile += 4) {
-    const int r = sen.tile_rays[tile * kTileRays + lane];
-    if (inside) {
-      if (r >= 0) {
-        orow[r] = 0.f;
-        if (rrow) rrow[r] = -2;
-        if (term) tacc += softplus_fast(beta * d_safe) / beta;
-      }
-      continue;
-    }
-    int ks = ns, kb = nb, nk = np;
-    if (CULL) {
-      const float4 ca = sen.cone_a[tile];
-      const float4 cb = sen.cone_b[tile];
-      const f3 ax = ROT ? rot_apply(R, mk3(ca.x, ca.y, ca.z)) : mk3(ca.x, ca.y, ca.z);
-      int cnt = 0, cs = 0, cbx = 0;
-      for (int base = 0; base < np; base += 64) {
-        const int k = base + lane;
-        const bool keep = (k < np) && cone_keep(L.pc[k], ax, ca.w, cb.x, cb.y);
-        const unsigned long long m = __ballot(keep);
-        const unsigned long long ms = __ballot(keep && k < ns);
-        const unsigned long long mb = __ballot(keep && k >= ns && k < ns + nb);
-        if (keep) list[cnt + __popcll(m & below)] = (short)k;
-        cnt += __popcll(m);
-        cs += __popcll(ms);
-        cbx += __popcll(mb);
-      }
-      __builtin_amdgcn_wave_barrier();
-      ks = cs;
-      kb = cbx;
-      nk = cnt;
-    }
-    if (r < 0) continue;
-    const float4 db = sen.dirs[r];
-    const f3 d = ROT ? rot_apply(R, mk3(db.x, db.y, db.z)) : mk3(db.x, db.y, db.z);
-    const f3 inv = mk3(__builtin_amdgcn_rcpf(d.x), __builtin_amdgcn_rcpf(d.y), __builtin_amdgcn_rcpf(d.z));
-    float best = kInf;
-    int id = -1;
-    for (int j = 0; j < ks; ++j) {
-      const int k = CULL ? list[j] : j;
-      const float t = sphere_t(d, L.pa[k], L.pb[k].x);
-      if (t < best) {
-        best = t;
-        id = k;
-      }
-    }
-    for (int j = ks; j < ks + kb; ++j) {
-      const int k = CULL ? list[j] : j;
-      const float t = box_t(inv, L.pa[k], L.pb[k]);
-      if (t < best) {
-        best = t;
-        id = k;
-      }
-    }
-    for (int j = ks + kb; j < nk; ++j) {
-      const int k = CULL ? list[j] : j;
-      const float t = sphere_t(d, L.pa[k], L.pb[k].x);
-      if (t < best) {
-        best = t;
-        id = k;
-      }
-    }
-    if (has_room) {
-      const float t = room_t(inv, rlo, rhi);
-      if (t < best) {
-        best = t;
-        id = np;
-      }
-    }
-    float val;
-    int rc;
-    const float z = best * db.w;
-    if (!(best < kInf) || z >= sen.max_range) {
-      val = sen.max_range;
-      rc = -1;
-    } else if (best == 0.f) {
-      val = 0.f;
-      rc = -2;
-    } else {
-      val = z;
-      rc = id;
-    }
-    orow[r] = val * out_scale;
-    if (rrow) rrow[r] = rc;
-    if (term) tacc += softplus_fast(beta * (d_safe - val)) / beta;
-  }
-  if (term) {
-    // fixed-order reduction: butterfly within each wave, then waves 0..3
-    for (int off = 32; off > 0; off >>= 1) tacc += __shfl_xor(tacc, off);
-    __syncthreads();
-    float* wsum = reinterpret_cast<float*>(L.pa);
-    if (lane == 0) wsum[wave] = tacc;
-    __syncthreads();
-    if (tid == 0) term[i] = (((wsum[0] + wsum[1]) + wsum[2]) + wsum[3]) / (float)nr;
-  }
+  render_one_agent<ROT, CULL>(sc, sen, s, A, blockIdx.x, 0, sen.n_tiles, out, rec, out_ld, out_scale,
+                              term, beta, d_safe, smem_f4);
 }
 
 // ---------------------------------------------------------------------------
@@ -477,33 +220,7 @@ __global__ __launch_bounds__(256) void collide_kernel(SceneDev sc, const float* 
                                                       float* __restrict__ min_dist) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= A) return;
-  const int env = sc.agent_env[i];
-  const f3 p = mk3(s[i], s[(size_t)A + i], s[2 * (size_t)A + i]);
-  float md = kInf;
-  for (int k = sc.sph_off[env]; k < sc.sph_off[env + 1]; ++k) {
-    const float4 c = reinterpret_cast<const float4*>(sc.sph)[k];
-    const f3 w = mk3(p.x - c.x, p.y - c.y, p.z - c.z);
-    md = fminf(md, sqrtf(dot(w, w)) - c.w);
-  }
-  for (int k = sc.box_off[env]; k < sc.box_off[env + 1]; ++k) {
-    const float* b = sc.box + (size_t)k * 6;
-    const float qx = fabsf(p.x - b[0]) - b[3], qy = fabsf(p.y - b[1]) - b[4],
-                qz = fabsf(p.z - b[2]) - b[5];
-    const float ex = fmaxf(qx, 0.f), ey = fmaxf(qy, 0.f), ez = fmaxf(qz, 0.f);
-    md = fminf(md, sqrtf(ex * ex + ey * ey + ez * ez) + fminf(fmaxf(fmaxf(qx, qy), qz), 0.f));
-  }
-  if (sc.room) {
-    const float* rm = sc.room + (size_t)env * 6;
-    md = fminf(md, fminf(fminf(fminf(p.x - rm[0], rm[3] - p.x), fminf(p.y - rm[1], rm[4] - p.y)),
-                         fminf(p.z - rm[2], rm[5] - p.z)));
-  }
-  if (sc.agents_visible) {
-    for (int j = sc.agent_off[env]; j < sc.agent_off[env + 1]; ++j) {
-      if (j == i) continue;
-      const f3 w = mk3(p.x - s[j], p.y - s[(size_t)A + j], p.z - s[2 * (size_t)A + j]);
-      md = fminf(md, sqrtf(dot(w, w)) - sc.agent_radius);
-    }
-  }
+  const float md = collide_one(sc, s, A, i);
   if (min_dist) min_dist[i] = md;
   if (flags && md < sc.agent_radius) flags[i] |= SIM_FLAG_COLLISION;
 }

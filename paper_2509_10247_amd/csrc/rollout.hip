@@ -1,0 +1,519 @@
+// Uneven-batch rollouts: environments with different obstacle and agent
+// counts (Sec. III: environment- and agent-level parallelism) stepped by one
+// persistent fused kernel per time step, T steps captured in a hipGraph.
+//
+// Work items of one step (all read s_t only, so no grid-wide barrier is
+// needed inside a step):
+//   - render item: tiles [tb, te) of one agent's camera or LiDAR at s_t;
+//   - dynamics item: 256 agents' collision distance at s_t and their step
+//     s_{t+1} = step(s_t, a_t), written to the other state buffer.
+// Items are ordered longest-first by an estimated cost (rays x primitives of
+// the env) and handed out by an atomic counter, so a workgroup that drew a
+// cheap env takes the next item instead of idling. Every ray and every agent
+// is computed by the same device code as the launch-per-op path, so the
+// outputs do not depend on the schedule or on the tuning choices.
+//
+// The autotuner times (tiles per render item, workgroups per CU, item order)
+// on the caller's scene and caches the choice in a JSON file keyed by the
+// device and the problem shape.
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "dyn_device.h"
+#include "render_device.h"
+#include "sim_internal.h"
+
+namespace da {
+
+enum { ITEM_CAM = 0, ITEM_LIDAR = 1, ITEM_DYN = 2 };
+
+struct RolloutArgs {
+  SceneDev sc;
+  SensorDev cam, lidar;
+  const float* s;
+  float* s_next;
+  const float* a;
+  const float* prm;
+  float dt;
+  int A;
+  float* depth;
+  float* lidar_out;
+  uint8_t* flags;
+  const int4* items;
+  int n_items;
+  int* counter;
+};
+
+// collision distance and step of 256 agents
+template <int M, int I>
+__device__ __forceinline__ void dyn_item(const RolloutArgs& g, int blk) {
+  constexpr int C = Dim<M>::C, K = Dim<M>::K, P = Dim<M>::P;
+  const int i = blk * 256 + (int)threadIdx.x;
+  if (i >= g.A) return;
+  const int A = g.A;
+  float s[C], u[K], p[P > 0 ? P : 1], out[C];
+  for (int c = 0; c < C; ++c) s[c] = g.s[(size_t)c * A + i];
+  for (int k = 0; k < K; ++k) u[k] = g.a[(size_t)k * A + i];
+  for (int k = 0; k < P; ++k) p[k] = g.prm[(size_t)k * A + i];
+  const float md = collide_one(g.sc, g.s, A, i);
+  step_regs<M, I>(s, u, p, g.dt, out);
+  bool finite = true;
+  for (int c = 0; c < C; ++c) {
+    g.s_next[(size_t)c * A + i] = out[c];
+    finite &= isfinite(out[c]);
+  }
+  if (g.flags) {
+    uint8_t f = g.flags[i];
+    if (!finite) f |= SIM_FLAG_NONFINITE;
+    if (md < g.sc.agent_radius) f |= SIM_FLAG_COLLISION;
+    g.flags[i] = f;
+  }
+}
+
+template <int M>
+constexpr bool rotates_m() {
+  return M == SIM_RB13 || M == SIM_NOMINAL13;
+}
+
+template <int M, int I, bool CULL>
+__global__ __launch_bounds__(256) void rollout_fused_kernel(RolloutArgs g) {
+  extern __shared__ float4 smem_f4[];
+  __shared__ int cur;
+  for (;;) {
+    if (threadIdx.x == 0) cur = atomicAdd(g.counter, 1);
+    __syncthreads();
+    const int it = cur;
+    __syncthreads();  // every thread has read the ticket before it is replaced
+    if (it >= g.n_items) break;  // uniform over the workgroup: all waves exit
+    const int4 w = g.items[it];
+    if (w.x == ITEM_DYN)
+      dyn_item<M, I>(g, w.y);
+    else if (w.x == ITEM_CAM)
+      render_one_agent<rotates_m<M>(), CULL>(g.sc, g.cam, g.s, g.A, w.y, w.z, w.w, g.depth, nullptr,
+                                             g.cam.n_rays, 1.f, nullptr, 1.f, 0.f, smem_f4);
+    else
+      render_one_agent<rotates_m<M>(), CULL>(g.sc, g.lidar, g.s, g.A, w.y, w.z, w.w, g.lidar_out, nullptr,
+                                             g.lidar.n_rays, 1.f, nullptr, 1.f, 0.f, smem_f4);
+  }
+}
+
+template <int M, int I>
+__global__ __launch_bounds__(256) void rollout_dyn_kernel(RolloutArgs g) {
+  dyn_item<M, I>(g, blockIdx.x);
+}
+
+__global__ void zero_ints_kernel(int* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+__global__ void copy_floats_kernel(const float* __restrict__ src, float* __restrict__ dst, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+template <int M, int I>
+static int launch_fused_t(const RolloutArgs& g, bool cull, int grid, size_t lds, hipStream_t st) {
+  if (cull)
+    hipLaunchKernelGGL((rollout_fused_kernel<M, I, true>), dim3(grid), dim3(256), lds, st, g);
+  else
+    hipLaunchKernelGGL((rollout_fused_kernel<M, I, false>), dim3(grid), dim3(256), lds, st, g);
+  DA_LAUNCH_CHECK("rollout_fused_kernel");
+  return SIM_OK;
+}
+
+template <int M, int I>
+static int launch_dyn_t(const RolloutArgs& g, bool, int, size_t, hipStream_t st) {
+  hipLaunchKernelGGL((rollout_dyn_kernel<M, I>), dim3(cdiv(g.A, 256)), dim3(256), 0, st, g);
+  DA_LAUNCH_CHECK("rollout_dyn_kernel");
+  return SIM_OK;
+}
+
+#define DA_ROLLOUT_DISPATCH(FN, model, integ, ...)                            \
+  switch (model * 2 + integ) {                                                \
+    case SIM_PM6 * 2 + 0: return FN<SIM_PM6, 0>(__VA_ARGS__);                 \
+    case SIM_PM6 * 2 + 1: return FN<SIM_PM6, 1>(__VA_ARGS__);                 \
+    case SIM_PM9 * 2 + 0: return FN<SIM_PM9, 0>(__VA_ARGS__);                 \
+    case SIM_PM9 * 2 + 1: return FN<SIM_PM9, 1>(__VA_ARGS__);                 \
+    case SIM_RB13 * 2 + 0: return FN<SIM_RB13, 0>(__VA_ARGS__);               \
+    case SIM_RB13 * 2 + 1: return FN<SIM_RB13, 1>(__VA_ARGS__);               \
+    case SIM_NOMINAL13 * 2 + 0: return FN<SIM_NOMINAL13, 0>(__VA_ARGS__);     \
+    case SIM_NOMINAL13 * 2 + 1: return FN<SIM_NOMINAL13, 1>(__VA_ARGS__);     \
+    default: return fail(SIM_EINVAL, "bad model/integrator");                 \
+  }
+
+static int launch_fused(const sim_handle* h, const RolloutArgs& g, int grid, size_t lds, hipStream_t st) {
+  DA_ROLLOUT_DISPATCH(launch_fused_t, h->cfg.model, h->cfg.integrator, g, h->cfg.fov_cull != 0, grid, lds, st);
+}
+
+static int launch_dyn(const sim_handle* h, const RolloutArgs& g, hipStream_t st) {
+  DA_ROLLOUT_DISPATCH(launch_dyn_t, h->cfg.model, h->cfg.integrator, g, false, 0, 0, st);
+}
+
+}  // namespace da
+
+using namespace da;
+
+// ---------------------------------------------------------------------------
+// plan: work items, tuning, graph cache (owned by the sim handle)
+// ---------------------------------------------------------------------------
+struct RolloutPlan {
+  int tile_group = 8, blocks_per_cu = 4, order = 1;  // order 1: longest first
+  bool tuned = false;
+  std::vector<int4> items;
+  int4* items_dev = nullptr;
+  int items_cap = 0;
+  int* counters = nullptr;
+  int counters_cap = 0;
+  float* s_tmp = nullptr;
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<uintptr_t> key;
+  int n_cu = 0;
+};
+
+static RolloutPlan* plan_of(sim_handle* h) {
+  if (!h->rollout) h->rollout = new RolloutPlan();
+  return reinterpret_cast<RolloutPlan*>(h->rollout);
+}
+
+void rollout_plan_free(sim_handle* h) {
+  RolloutPlan* p = reinterpret_cast<RolloutPlan*>(h->rollout);
+  if (!p) return;
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  if (p->items_dev) (void)hipFree(p->items_dev);
+  if (p->counters) (void)hipFree(p->counters);
+  if (p->s_tmp) (void)hipFree(p->s_tmp);
+  delete p;
+  h->rollout = nullptr;
+}
+
+static int build_items(sim_handle* h, RolloutPlan* p) {
+  const int A = h->cfg.n_agents;
+  std::vector<std::pair<double, int4>> items;
+  const auto& so = h->host_sph_off;
+  const auto& bo = h->host_box_off;
+  const auto& ao = h->host_agent_off;
+  for (int e = 0; e < h->cfg.n_envs; ++e) {
+    int np = (so[e + 1] - so[e]) + (bo[e + 1] - bo[e]);
+    if (h->cfg.agents_visible) np += ao[e + 1] - ao[e];
+    for (int i = ao[e]; i < ao[e + 1]; ++i) {
+      const SensorBuf* sens[2] = {&h->cam, &h->lidar};
+      for (int k = 0; k < 2; ++k) {
+        if (!sens[k]->mem) continue;
+        const int nt = sens[k]->dev.n_tiles;
+        const int tg = std::max(1, std::min(p->tile_group, nt));
+        for (int tb = 0; tb < nt; tb += tg) {
+          const int te = std::min(nt, tb + tg);
+          // staging cost + per-tile culling pass + casting against the env
+          const double cost = 4.0 * np + (te - tb) * (64.0 + 8.0 * (np + 6));
+          items.push_back({cost, make_int4(k == 0 ? ITEM_CAM : ITEM_LIDAR, i, tb, te)});
+        }
+      }
+    }
+  }
+  for (int b = 0; b < cdiv(A, 256); ++b) items.push_back({2000.0, make_int4(ITEM_DYN, b, 0, 0)});
+  if (p->order == 1)
+    std::stable_sort(items.begin(), items.end(),
+                     [](const std::pair<double, int4>& x, const std::pair<double, int4>& y) { return x.first > y.first; });
+  p->items.resize(items.size());
+  for (size_t k = 0; k < items.size(); ++k) p->items[k] = items[k].second;
+  const int n = (int)p->items.size();
+  if (n > p->items_cap) {
+    if (p->items_dev) DA_HIP(hipFree(p->items_dev));
+    DA_HIP(hipMalloc(&p->items_dev, (size_t)n * sizeof(int4)));
+    p->items_cap = n;
+  }
+  DA_HIP(hipMemcpy(p->items_dev, p->items.data(), (size_t)n * sizeof(int4), hipMemcpyHostToDevice));
+  if (p->exec) {
+    (void)hipGraphExecDestroy(p->exec);
+    p->exec = nullptr;
+    p->key.clear();
+  }
+  return SIM_OK;
+}
+
+static int ensure_plan(sim_handle* h, RolloutPlan* p, int T) {
+  if (!p->n_cu) {
+    int dev = 0;
+    DA_HIP(hipGetDevice(&dev));
+    DA_HIP(hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+  }
+  if (p->items.empty()) {
+    int rc = build_items(h, p);
+    if (rc) return rc;
+  }
+  if (T > p->counters_cap) {
+    if (p->counters) DA_HIP(hipFree(p->counters));
+    DA_HIP(hipMalloc(&p->counters, (size_t)T * sizeof(int)));
+    p->counters_cap = T;
+  }
+  if (!p->s_tmp) DA_HIP(hipMalloc(&p->s_tmp, (size_t)state_dim(h->cfg.model) * h->cfg.n_agents * 4));
+  return SIM_OK;
+}
+
+// Enqueues the T steps of a rollout on st (fused: persistent kernel per step;
+// plain: dynamics + camera + LiDAR launches per step).
+static int enqueue_rollout(sim_handle* h, RolloutPlan* p, int T, float* s, const float* a_seq, float* depth_ring,
+                           float* lidar_ring, uint8_t* flags, bool fused, hipStream_t st) {
+  const int A = h->cfg.n_agents, C = state_dim(h->cfg.model), K = action_dim(h->cfg.model);
+  const size_t lds = render_lds_bytes(h->scene.max_prims > 0 ? h->scene.max_prims : 1);
+  const bool rot = h->cfg.model == SIM_RB13 || h->cfg.model == SIM_NOMINAL13;
+  if (fused) {
+    hipLaunchKernelGGL(zero_ints_kernel, dim3(cdiv(T, 256)), dim3(256), 0, st, p->counters, T);
+    DA_LAUNCH_CHECK("zero_ints_kernel");
+  }
+  for (int t = 0; t < T; ++t) {
+    RolloutArgs g;
+    g.sc = h->scene;
+    g.cam = h->cam.dev;
+    g.lidar = h->lidar.dev;
+    g.s = (t & 1) ? p->s_tmp : s;
+    g.s_next = (t & 1) ? s : p->s_tmp;
+    g.a = a_seq + (size_t)t * K * A;
+    g.prm = h->params;
+    g.dt = h->cfg.dt;
+    g.A = A;
+    g.depth = depth_ring ? depth_ring + (size_t)(t & 1) * A * h->cam.dev.n_rays : nullptr;
+    g.lidar_out = lidar_ring ? lidar_ring + (size_t)(t & 1) * A * h->lidar.dev.n_rays : nullptr;
+    g.flags = flags;
+    g.items = p->items_dev;
+    g.n_items = (int)p->items.size();
+    g.counter = p->counters + t;
+    int rc;
+    if (fused) {
+      rc = launch_fused(h, g, p->n_cu * p->blocks_per_cu, lds, st);
+    } else {
+      rc = launch_dyn(h, g, st);
+      if (!rc && depth_ring)
+        rc = launch_render(h->scene, h->cam.dev, rot, h->cfg.fov_cull != 0, g.s, A, g.depth, nullptr,
+                           h->cam.dev.n_rays, 1.f, st);
+      if (!rc && lidar_ring)
+        rc = launch_render(h->scene, h->lidar.dev, rot, h->cfg.fov_cull != 0, g.s, A, g.lidar_out, nullptr,
+                           h->lidar.dev.n_rays, 1.f, st);
+    }
+    if (rc) return rc;
+  }
+  if (T & 1) {
+    const size_t n = (size_t)C * A;
+    hipLaunchKernelGGL(copy_floats_kernel, dim3((unsigned)cdiv64(n, 256)), dim3(256), 0, st, p->s_tmp, s, n);
+    DA_LAUNCH_CHECK("copy_floats_kernel");
+  }
+  return SIM_OK;
+}
+
+// With the render items disabled in the plan (no depth / LiDAR output
+// requested) the render items would write to null; they are skipped by
+// building the plan only for the requested sensors.
+static int check_rollout_args(sim_handle* h, int T, float* s, const float* a_seq, float* depth_ring,
+                              float* lidar_ring) {
+  DA_REQUIRE(h && s && a_seq, "sim_rollout: null argument");
+  DA_REQUIRE(T >= 1, "sim_rollout: T must be >= 1");
+  DA_REQUIRE(h->has_scene, "sim_rollout: scene not set");
+  DA_REQUIRE(param_dim(h->cfg.model) == 0 || h->params, "sim_rollout: parameters not set");
+  DA_REQUIRE((depth_ring != nullptr) == (h->cam.mem != nullptr),
+             "sim_rollout: depth_ring must be given exactly when a camera is configured");
+  DA_REQUIRE((lidar_ring != nullptr) == (h->lidar.mem != nullptr),
+             "sim_rollout: lidar_ring must be given exactly when a LiDAR is configured");
+  return SIM_OK;
+}
+
+extern "C" {
+
+int sim_rollout(sim_handle* h, int32_t T, float* s, const float* a_seq, float* depth_ring, float* lidar_ring,
+                uint8_t* flags, int32_t mode, void* stream) {
+  int rc = check_rollout_args(h, T, s, a_seq, depth_ring, lidar_ring);
+  if (rc) return rc;
+  DA_REQUIRE(mode >= 0 && mode <= 2, "sim_rollout: mode must be 0 (graph), 1 (plain) or 2 (fused, no graph)");
+  RolloutPlan* p = plan_of(h);
+  if ((rc = ensure_plan(h, p, T))) return rc;
+  hipStream_t st = as_stream(stream);
+  if (mode == 1) return enqueue_rollout(h, p, T, s, a_seq, depth_ring, lidar_ring, flags, false, st);
+  if (mode == 2) return enqueue_rollout(h, p, T, s, a_seq, depth_ring, lidar_ring, flags, true, st);
+  std::vector<uintptr_t> key = {(uintptr_t)T, (uintptr_t)s, (uintptr_t)a_seq, (uintptr_t)depth_ring,
+                                (uintptr_t)lidar_ring, (uintptr_t)flags, (uintptr_t)h->params,
+                                (uintptr_t)p->tile_group, (uintptr_t)p->blocks_per_cu, (uintptr_t)p->order};
+  if (!p->exec || key != p->key) {
+    if (p->exec) {
+      DA_HIP(hipGraphExecDestroy(p->exec));
+      p->exec = nullptr;
+    }
+    if (!p->cap_stream) DA_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+    DA_HIP(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+    rc = enqueue_rollout(h, p, T, s, a_seq, depth_ring, lidar_ring, flags, true, p->cap_stream);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(p->cap_stream, &graph);
+    if (rc) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    if (e != hipSuccess) return fail(SIM_EHIP, "sim_rollout: capture failed: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&p->exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(SIM_EHIP, "sim_rollout: instantiate failed: %s", hipGetErrorString(e));
+    p->key = key;
+  }
+  DA_HIP(hipGraphLaunch(p->exec, st));
+  return SIM_OK;
+}
+
+int sim_rollout_config(sim_handle* h, int32_t tile_group, int32_t blocks_per_cu, int32_t order) {
+  DA_REQUIRE(h, "sim_rollout_config: null handle");
+  DA_REQUIRE(tile_group >= 1 && blocks_per_cu >= 1 && blocks_per_cu <= 16 && (order == 0 || order == 1),
+             "sim_rollout_config: tile_group >= 1, 1 <= blocks_per_cu <= 16, order 0 or 1");
+  DA_REQUIRE(h->has_scene, "sim_rollout_config: scene not set");
+  RolloutPlan* p = plan_of(h);
+  p->tile_group = tile_group;
+  p->blocks_per_cu = blocks_per_cu;
+  p->order = order;
+  return build_items(h, p);
+}
+
+int sim_rollout_get_config(sim_handle* h, int32_t* tile_group, int32_t* blocks_per_cu, int32_t* order) {
+  DA_REQUIRE(h && tile_group && blocks_per_cu && order, "sim_rollout_get_config: null argument");
+  RolloutPlan* p = plan_of(h);
+  *tile_group = p->tile_group;
+  *blocks_per_cu = p->blocks_per_cu;
+  *order = p->order;
+  return SIM_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// autotuner
+// ---------------------------------------------------------------------------
+static std::string tune_key(const sim_handle* h, const char* arch) {
+  const sim_config& c = h->cfg;
+  char buf[512];
+  snprintf(buf, sizeof(buf), "%s|E%d|A%d|m%d|i%d|cam%dx%d|lidar%dx%d|sph%d|box%d|maxp%d|vis%d|cull%d|room%d", arch,
+           c.n_envs, c.n_agents, c.model, c.integrator, c.cam_w, c.cam_h, c.lidar_ch, c.lidar_az, h->n_sph,
+           h->n_box, h->scene.max_prims, c.agents_visible, c.fov_cull, h->scene.room ? 1 : 0);
+  return buf;
+}
+
+static bool read_cache(const char* path, const std::string& key, int* tg, int* bpc, int* ord) {
+  if (!path || !*path) return false;
+  FILE* f = fopen(path, "r");
+  if (!f) return false;
+  std::string text;
+  char buf[4096];
+  size_t n;
+  while ((n = fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, n);
+  fclose(f);
+  const std::string tag = "\"" + key + "\"";
+  size_t at = text.find(tag);
+  if (at == std::string::npos) return false;
+  size_t brace = text.find('{', at);
+  if (brace == std::string::npos) return false;
+  return sscanf(text.c_str() + brace, "{\"tile_group\": %d, \"blocks_per_cu\": %d, \"order\": %d", tg, bpc,
+                ord) == 3;
+}
+
+static void write_cache(const char* path, const std::string& key, int tg, int bpc, int ord, float ms) {
+  if (!path || !*path) return;
+  // keep other entries: read, drop the old line for this key, append
+  std::string text;
+  if (FILE* f = fopen(path, "r")) {
+    char buf[4096];
+    size_t n;
+    while ((n = fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, n);
+    fclose(f);
+  }
+  std::vector<std::string> lines;
+  size_t pos = 0;
+  while (pos < text.size()) {
+    size_t e = text.find('\n', pos);
+    if (e == std::string::npos) e = text.size();
+    std::string ln = text.substr(pos, e - pos);
+    if (ln.find("\"tile_group\"") != std::string::npos && ln.find("\"" + key + "\"") == std::string::npos)
+      lines.push_back(ln);
+    pos = e + 1;
+  }
+  char buf[1024];
+  snprintf(buf, sizeof(buf), "  \"%s\": {\"tile_group\": %d, \"blocks_per_cu\": %d, \"order\": %d, \"ms\": %.4f}",
+           key.c_str(), tg, bpc, ord, ms);
+  lines.push_back(buf);
+  FILE* f = fopen(path, "w");
+  if (!f) return;
+  fprintf(f, "{\n");
+  for (size_t k = 0; k < lines.size(); ++k) {
+    std::string ln = lines[k];
+    while (!ln.empty() && (ln.back() == ',' || ln.back() == ' ')) ln.pop_back();
+    fprintf(f, "%s%s\n", ln.c_str(), k + 1 < lines.size() ? "," : "");
+  }
+  fprintf(f, "}\n");
+  fclose(f);
+}
+
+extern "C" int sim_autotune(sim_handle* h, const float* s, const float* a, float* depth, float* lidar,
+                            const char* cache_path, float* best_ms, void* stream) {
+  int rc = check_rollout_args(h, 1, const_cast<float*>(s), a, depth, lidar);
+  if (rc) return rc;
+  hipStream_t st = as_stream(stream);
+  int dev = 0;
+  DA_HIP(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  DA_HIP(hipGetDeviceProperties(&prop, dev));
+  const std::string key = tune_key(h, prop.gcnArchName);
+  RolloutPlan* p = plan_of(h);
+  int tg, bpc, ord;
+  if (read_cache(cache_path, key, &tg, &bpc, &ord)) {
+    if ((rc = sim_rollout_config(h, tg, bpc, ord))) return rc;
+    if (best_ms) *best_ms = -1.f;
+    p->tuned = true;
+    return SIM_OK;
+  }
+  // a private copy of s: the trial steps write s_{t+1} into the plan's
+  // scratch buffer and, for T = 1, copy it back into the state argument
+  const int C = state_dim(h->cfg.model), A = h->cfg.n_agents;
+  float* s_work = nullptr;
+  DA_HIP(hipMalloc(&s_work, (size_t)C * A * 4));
+  hipEvent_t e0, e1;
+  DA_HIP(hipEventCreate(&e0));
+  DA_HIP(hipEventCreate(&e1));
+  const int tgs[] = {2, 4, 8, 16, 1 << 20};
+  const int bpcs[] = {2, 4, 8};
+  float best = 1e30f;
+  int btg = 8, bbpc = 4, bord = 1;
+  for (int ord_ : {1, 0})
+    for (int tg_ : tgs)
+      for (int bpc_ : bpcs) {
+        if ((rc = sim_rollout_config(h, tg_, bpc_, ord_))) break;
+        if ((rc = ensure_plan(h, p, 1))) break;
+        std::vector<float> ts;
+        for (int rep = 0; rep < 4 && !rc; ++rep) {
+          DA_HIP(hipMemcpyAsync(s_work, s, (size_t)C * A * 4, hipMemcpyDeviceToDevice, st));
+          DA_HIP(hipEventRecord(e0, st));
+          rc = enqueue_rollout(h, p, 1, s_work, a, depth, lidar, nullptr, true, st);
+          DA_HIP(hipEventRecord(e1, st));
+          DA_HIP(hipEventSynchronize(e1));
+          float ms = 0.f;
+          DA_HIP(hipEventElapsedTime(&ms, e0, e1));
+          if (rep > 0) ts.push_back(ms);  // first run is a warm-up
+        }
+        if (rc) break;
+        std::sort(ts.begin(), ts.end());
+        const float med = ts[ts.size() / 2];
+        if (med < best) {
+          best = med;
+          btg = tg_;
+          bbpc = bpc_;
+          bord = ord_;
+        }
+      }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(s_work);
+  if (rc) return rc;
+  if ((rc = sim_rollout_config(h, btg, bbpc, bord))) return rc;
+  write_cache(cache_path, key, btg, bbpc, bord, best);
+  if (best_ms) *best_ms = best;
+  p->tuned = true;
+  return SIM_OK;
+}

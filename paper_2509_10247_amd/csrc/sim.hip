@@ -237,6 +237,7 @@ int sim_create(const sim_config* cfg, sim_handle** out) {
 
 int sim_destroy(sim_handle* h) {
   if (!h) return SIM_OK;
+  rollout_plan_free(h);
   if (h->cam.mem) (void)hipFree(h->cam.mem);
   if (h->lidar.mem) (void)hipFree(h->lidar.mem);
   if (h->agent_env) (void)hipFree(h->agent_env);
@@ -324,6 +325,7 @@ int sim_set_scene(sim_handle* h, const int32_t* sph_off, const float* sph, int32
   h->n_sph = n_sph;
   h->n_box = n_box;
   h->has_scene = true;
+  rollout_plan_free(h);  // work items depend on the scene
   return SIM_OK;
 }
 

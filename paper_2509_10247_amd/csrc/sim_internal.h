@@ -20,4 +20,7 @@ struct sim_handle {
   std::vector<int32_t> host_sph_off, host_box_off, host_agent_off;
   int n_sph = 0, n_box = 0;
   bool has_scene = false;
+  void* rollout = nullptr;             // uneven-batch rollout plan (rollout.hip)
 };
+
+void rollout_plan_free(sim_handle* h);

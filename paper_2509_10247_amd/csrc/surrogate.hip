@@ -29,7 +29,9 @@ constexpr int kPW1 = 0, kPB1 = kPW1 + kSH * kSInP, kPW2 = kPB1 + kSH, kPB2 = kPW
               kPW3 = kPB2 + kSH, kPB3 = kPW3 + kSOutP * kSH, kPEnd = kPB3 + kSOutP;
 constexpr int kNorm = 2 * kSIn + 2 * kSOut;  // mu_x, sd_x, mu_d, sd_d
 constexpr float kOodZ = 4.0f;
-__constant__ float kJudgeThr[4] = {1e-3f, 1e-2f, 1e-3f, 1e-2f};  // p, v, q, w
+struct JudgeThr {
+  float v[4];  // max abs error per block: p [m], v [m/s], q [-], w [rad/s]
+};
 
 // flat <-> padded parameter copies (dir 0: flat -> padded, 1: padded -> flat)
 __global__ void sur_repack_kernel(const float* __restrict__ src, float* __restrict__ dst, int dir) {
@@ -191,7 +193,8 @@ __global__ void sur_finish_kernel(int A, float dt, int t, int period, const floa
                                   const float* __restrict__ a, const float* __restrict__ prm,
                                   const float* __restrict__ X, const float* __restrict__ Y,
                                   const float* __restrict__ norm, float* __restrict__ s_out,
-                                  uint8_t* __restrict__ fallback, float* __restrict__ judged_err) {
+                                  uint8_t* __restrict__ fallback, float* __restrict__ judged_err,
+                                  JudgeThr thr) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= A) return;
   float s[13], u[4], p[8], nom[13], sur[13];
@@ -223,7 +226,7 @@ __global__ void sur_finish_kernel(int A, float dt, int t, int period, const floa
       float e = 0.f;
       for (int c = lo[k]; c < hi[k]; ++c) e = fmaxf(e, fabsf(sur[c] - full[c]));
       if (judged) err[k] = e;
-      bad |= judged && e > kJudgeThr[k];
+      bad |= judged && e > thr.v[k];
     }
     fb = fb || bad || ood;
     if (fb)
@@ -468,7 +471,7 @@ int surrogate_load(surrogate_handle* h, const float* theta, void* stream) {
 
 int sim_surrogate_step(sim_handle* full, surrogate_handle* h, const float* norm, const float* s_in,
                        const float* a, float* s_out, uint8_t* fallback, float* judged_err, int32_t t,
-                       int32_t judge_period, void* stream) {
+                       int32_t judge_period, const float* thresholds, void* stream) {
   DA_REQUIRE(full && h && norm && s_in && a && s_out && fallback, "sim_surrogate_step: null argument");
   DA_REQUIRE(full->cfg.model == SIM_RB13 && full->cfg.integrator == SIM_RK4,
              "sim_surrogate_step: the full model must be SIM_RB13 with RK4");
@@ -478,13 +481,19 @@ int sim_surrogate_step(sim_handle* full, surrogate_handle* h, const float* norm,
   const int A = full->cfg.n_agents;
   DA_REQUIRE(A <= h->max_batch, "sim_surrogate_step: %d agents exceed max_batch %d", A, h->max_batch);
   DA_REQUIRE(s_in != s_out, "sim_surrogate_step: s_in and s_out must not alias");
+  JudgeThr thr{{1e-3f, 1e-2f, 2e-3f, 1e-1f}};
+  if (thresholds)
+    for (int k = 0; k < 4; ++k) {
+      DA_REQUIRE(thresholds[k] > 0.f, "sim_surrogate_step: thresholds must be > 0");
+      thr.v[k] = thresholds[k];
+    }
   hipStream_t st = as_stream(stream);
   hipLaunchKernelGGL(sur_prep_kernel, dim3(cdiv(A, 256)), dim3(256), 0, st, A, s_in, a, norm, h->X);
   DA_LAUNCH_CHECK("sur_prep_kernel");
   int rc = sur_forward(h, A, st);
   if (rc) return rc;
   hipLaunchKernelGGL(sur_finish_kernel, dim3(cdiv(A, 256)), dim3(256), 0, st, A, full->cfg.dt, t, judge_period,
-                     s_in, a, full->params, h->X, h->Y, norm, s_out, fallback, judged_err);
+                     s_in, a, full->params, h->X, h->Y, norm, s_out, fallback, judged_err, thr);
   DA_LAUNCH_CHECK("sur_finish_kernel");
   return SIM_OK;
 }

@@ -89,7 +89,7 @@ class Surrogate:
         return g, loss
 
     # -- rollout -------------------------------------------------------------
-    def step(self, full_env, s, a, out, fallback, judged_err=None, t=0, judge_period=64):
+    def step(self, full_env, s, a, out, fallback, judged_err=None, t=0, judge_period=64, thresholds=None):
         _lib.sim_surrogate_step(full_env.h, self.h, self.norm, s, a, out, fallback, judged_err, t,
-                                judge_period)
+                                judge_period, thresholds)
         return out
