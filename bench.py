@@ -22,7 +22,18 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_MFMA = 157.3e12
+PEAK_BF16_MFMA = 2.5e15
+PEAK_FP32_VALU = 157.3e12          # packed FP32 FMA, 256 CUs x 2.4 GHz
+PEAK_FP32_VALU_NONPACKED = 78.6e12  # one FP32 FMA per lane and clock
 PEAK_HBM = 8.0e12
+
+# FLOPs per unit of render work (FMA = 2; add, mul, min, max, sqrt, rcp,
+# exp2, log2 = 1; compares and selects = 0), counted from the kernel's
+# expressions: direction rotation 15 + reciprocals 3 + room exit 5 + depth
+# scale 2 per cast ray, plus 11 for the fused softplus obstacle term; 17 per
+# ray-sphere test, 16 per ray-box slab test; 21 per tile-cone test of a
+# primitive and 15 per tile for the rotated cone axis.
+RENDER_FLOP = {"ray": 25, "ray_term": 11, "sphere": 17, "box": 16, "cone": 21, "tile": 15}
 
 
 def parse():
@@ -36,6 +47,10 @@ def parse():
     p.add_argument("--ckpt", type=int, default=8)
     p.add_argument("--recompute-all", action="store_true",
                    help="keep only the K-step state checkpoints (recompute policy and step too)")
+    p.add_argument("--policy-gemm", choices=["fp32", "bf16x3"], default="bf16x3",
+                   help="policy layers on FP32 MFMA, or FP32 recovered from three BF16 MFMA products")
+    p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                   help="also run a plain device copy of MIB MiB (for HBM counter scaling)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-kernel-timing", action="store_true")
     p.add_argument("--sections", default="surrogate,uneven",
@@ -189,6 +204,72 @@ def surrogate_section(seed=0):
     return out
 
 
+def render_work_flops(e, s, term):
+    """Algorithmic FLOPs of one camera render at state s: the ray and test
+    counts come from sim_render_work (the same kernel with counters)."""
+    import torch
+    from paper_2509_10247_amd import _lib
+    A = e.n_agents
+    out = torch.empty(A, e.cam[1] * e.cam[0], device="cuda")
+    work = torch.zeros(A, 4, 6, dtype=torch.int32, device="cuda")
+    _lib.sim_render_work(e.h, 0, s, out, work)
+    w = work.long().sum((0, 1)).tolist()
+    c = dict(zip(_lib.WORK_FIELDS, w))
+    f = RENDER_FLOP
+    flops = (c["rays"] * (f["ray"] + (f["ray_term"] if term else 0)) + c["sphere_tests"] * f["sphere"]
+             + c["box_tests"] * f["box"] + c["agent_tests"] * f["sphere"] + c["cone_tests"] * f["cone"]
+             + c["tiles"] * f["tile"])
+    return flops, c
+
+
+def dominant_roofline(tm, e, s0, A, gemm_mode):
+    """Roofline of the kernel class with the largest total time in one
+    iteration: algorithmic work per launch / average launch duration (HIP
+    events on the kernels' stream)."""
+    from paper_2509_10247_amd import _lib
+    dom = max(tm, key=lambda k: tm[k][0])
+    avg_s = tm[dom][0] / max(tm[dom][1], 1) / 1e3
+    base = {"kernel": dom, "launches": tm[dom][1], "avg_launch_ms": round(avg_s * 1e3, 4),
+            "traffic": None}
+    gemm_flops = {"l1_gemm": 2.0 * A * 3084 * 256, "gw1_gemm": 2.0 * 256 * 3084 * A,
+                  "gx_gemm": 2.0 * A * 256 * 3084}
+    if dom in gemm_flops:
+        ach = gemm_flops[dom] / avg_s
+        x3 = gemm_mode == _lib.POLICY_GEMM_BF16X3
+        peak = PEAK_BF16_MFMA if x3 else PEAK_FP32_MFMA
+        base.update({"bound": "mfma", "achieved": round(ach / 1e12, 2), "peak": peak / 1e12,
+                     "unit": "TFLOP/s", "frac": round(ach / peak, 4),
+                     "flops_per_launch": gemm_flops[dom]})
+        if x3:
+            base["note"] = "FP32 product from three BF16 MFMA products: executed MFMA work is 3x"
+        return base
+    if dom == "render":
+        flops, cnt = render_work_flops(e, s0, term=True)
+        ach = flops / avg_s
+        written = cnt["rays"] * 8.0   # depth value + hit record per cast ray
+        base.update({"bound": "alu", "achieved": round(ach / 1e12, 2), "peak": PEAK_FP32_VALU / 1e12,
+                     "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_VALU, 4),
+                     "frac_of_nonpacked_fp32": round(ach / PEAK_FP32_VALU_NONPACKED, 4),
+                     "flops_per_launch": flops, "work_per_launch": cnt,
+                     "hbm_written_bytes": written,
+                     "hbm_frac_of_writes": round(written / avg_s / PEAK_HBM, 4)})
+        return base
+    base.update({"bound": "unknown", "achieved": None, "peak": None, "unit": None, "frac": None})
+    return base
+
+
+def copy_calibration(mib):
+    """A plain device copy of known size (for scaling HBM byte counters)."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(f"[copy-calibration] 3 copies of {mib} MiB", file=sys.stderr, flush=True)
+
+
 def cpu_baseline(model, seed=0, n_envs=64, T=32):
     """The FP64 oracle (forward rollout + autograd backward) on a bounded
     sample of the same workload, on the host's cores."""
@@ -224,7 +305,8 @@ def main():
     wk = wl.bptt(seed=0, n_envs=A, T=T, model=model)
     theta = wl.flatten_mlp(wl.mlp_init(np.random.default_rng(1), wl.POLICY_DIMS))
     e = env.from_workload(wk)
-    eng = bptt.BpttEngine(e, T, K, store_activations=not args.recompute_all)
+    gemm_mode = _lib.POLICY_GEMM_BF16X3 if args.policy_gemm == "bf16x3" else _lib.POLICY_GEMM_FP32
+    eng = bptt.BpttEngine(e, T, K, store_activations=not args.recompute_all, policy_gemm=gemm_mode)
     th = torch.tensor(theta, device="cuda")
     s0 = torch.tensor(wk.state0, device="cuda")
     goal = torch.tensor(wk.goal, device="cuda")
@@ -246,6 +328,8 @@ def main():
     value = A * T * args.steps / elapsed
 
     roofline, breakdown = None, None
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
     if not args.no_kernel_timing:
         # one more iteration with HIP events around each kernel class, on the
         # stream the kernels run on
@@ -256,19 +340,7 @@ def main():
         _lib.bptt_set_timing(eng.h, 0)
         breakdown = {k: {"ms_total": round(v[0], 3), "launches": v[1],
                          "ms_avg": round(v[0] / max(v[1], 1), 4)} for k, v in tm.items()}
-        gemm_flops = {"l1_gemm": 2.0 * A * 3084 * 256, "gw1_gemm": 2.0 * 256 * 3084 * A,
-                      "gx_gemm": 2.0 * A * 256 * 3084}
-        dom = max(tm, key=lambda k: tm[k][0])
-        if dom in gemm_flops:
-            avg_s = tm[dom][0] / tm[dom][1] / 1e3
-            ach = gemm_flops[dom] / avg_s
-            roofline = {"bound": "mfma", "kernel": dom, "achieved": round(ach / 1e12, 2),
-                        "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s",
-                        "frac": round(ach / PEAK_FP32_MFMA, 4), "traffic": None,
-                        "flops_per_launch": gemm_flops[dom], "avg_launch_ms": round(avg_s * 1e3, 4)}
-        else:
-            roofline = {"bound": "unknown", "kernel": dom, "achieved": None, "peak": None,
-                        "unit": None, "frac": None, "traffic": None}
+        roofline = dominant_roofline(tm, e, s0, A, gemm_mode)
 
     line = {
         "metric": "env-steps/sec fwd+bwd with 64x48 depth",
@@ -287,7 +359,7 @@ def main():
                    "envs": A, "horizon": T, "checkpoint_every": K, "env_steps_per_step": A * T,
                    "stored_activations": not args.recompute_all,
                    "workspace_bytes": eng.workspace_bytes(),
-                   "policy": "mlp 3081-256-256-4 tanh (fp32 mfma)"},
+                   "policy": f"mlp 3081-256-256-4 tanh ({args.policy_gemm} mfma)"},
         "roofline": roofline,
         "kernel_breakdown": breakdown,
     }

@@ -133,6 +133,15 @@ int sim_step(sim_handle* h, const float* s_in, const float* a, float* s_out, uin
 int sim_render(sim_handle* h, const float* s, float* depth, float* lidar, int32_t* hit_cam,
                int32_t* hit_lidar, void* stream);
 
+/* Work count of one sensor's render at s (diagnostics for the roofline; the
+ * exclusion of obstacles outside the field of view is Sec. III-B): renders
+ * sensor 0 (camera) or 1 (LiDAR) into out ([A][n_rays], as sim_render) and
+ * writes work [A][4][6] int32 (per agent and wavefront): rays cast, ray-sphere
+ * tests, ray-box tests, ray-agent tests, tiles, tile-cone tests. Rays of an
+ * agent that is inside a primitive are not cast. Same image as sim_render. */
+int sim_render_work(sim_handle* h, int32_t sensor, const float* s, float* out, int32_t* work,
+                    void* stream);
+
 /* Collisions: min_dist[i] = distance from agent i's centre to the nearest
  * surface (spheres, boxes, room walls, other agents' spheres when
  * agents_visible); flags[i] |= SIM_FLAG_COLLISION when min_dist < agent_radius.
@@ -171,6 +180,11 @@ int sim_step_backward(sim_handle* h, const float* s_t, const float* a_t, const f
  * The camera must be 64x48 (3072 rays) and the model SIM_PM9 or SIM_RB13.
  */
 #define POLICY_N_PARAMS 855812
+/* Arithmetic of the policy's dense layers: FP32 operands on the FP32 matrix
+ * cores, or the FP32 product recovered from three BF16 products of a hi / lo
+ * split of each operand (Ootomo & Yokota 2022; relative error ~1e-5, FP32
+ * accumulation) on the BF16 matrix cores, which run 16x faster on gfx950. */
+enum { POLICY_GEMM_FP32 = 0, POLICY_GEMM_BF16X3 = 1 };
 
 typedef struct bptt_config {
   int32_t T;      /* horizon >= 1 */
@@ -183,6 +197,7 @@ typedef struct bptt_config {
    *    rendered observations and hit records (about 6150 floats per agent and
    *    step) per segment. Same gradient, bit for bit. */
   int32_t store_activations;
+  int32_t policy_gemm;   /* POLICY_GEMM_FP32 or POLICY_GEMM_BF16X3 */
 } bptt_config;
 
 typedef struct bptt_handle bptt_handle;
@@ -228,10 +243,12 @@ int bptt_get_timing(bptt_handle* b, float* ms, int32_t* count, int32_t n);
 
 /* Stand-alone policy forward / backward on a batch (for tests and tools):
  * x [B][3081] row-major, y [B][4]. policy_backward recomputes the forward and
- * writes g_theta (overwritten) and g_x ([B][3081], nullable). */
-int policy_forward(const float* theta, const float* x, float* y, int32_t B, void* stream);
+ * writes g_theta (overwritten) and g_x ([B][3081], nullable). gemm_mode:
+ * POLICY_GEMM_*. Allocate their scratch per call (synchronous). */
+int policy_forward(const float* theta, const float* x, float* y, int32_t B, int32_t gemm_mode,
+                   void* stream);
 int policy_backward(const float* theta, const float* x, const float* g_y, float* g_theta,
-                    float* g_x, int32_t B, void* stream);
+                    float* g_x, int32_t B, int32_t gemm_mode, void* stream);
 
 /* Adam (Kingma & Ba 2015) on n FP32 values: m = b1 m + (1-b1) g,
  * v = b2 v + (1-b2) g^2, w -= lr * (m/(1-b1^t)) / (sqrt(v/(1-b2^t)) + eps).

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_DIR, "libdiffaero.so")
 SIM_PM6, SIM_PM9, SIM_RB13, SIM_NOMINAL13 = 0, 1, 2, 3
 SIM_EULER, SIM_RK4 = 0, 1
 POLICY_N_PARAMS = 855812
+POLICY_GEMM_FP32, POLICY_GEMM_BF16X3 = 0, 1
 SURROGATE_N_PARAMS = 73741
 SURROGATE_N_NORM = 60
 
@@ -36,7 +37,7 @@ class SimConfig(ctypes.Structure):
 class BpttConfig(ctypes.Structure):
     _fields_ = [("T", c_int), ("K", c_int), ("w_p", c_float), ("w_v", c_float), ("w_u", c_float),
                 ("w_o", c_float), ("beta", c_float), ("d_safe", c_float),
-                ("store_activations", c_int)]
+                ("store_activations", c_int), ("policy_gemm", c_int)]
 
 
 _SIGS = {
@@ -49,6 +50,7 @@ _SIGS = {
     "sim_reset": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "sim_step": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "sim_render": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "sim_render_work": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p]),
     "sim_collide": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "sim_step_backward": (c_int, [c_void_p] + [c_void_p] * 9 + [c_void_p]),
     "bptt_create": (c_int, [c_void_p, ctypes.POINTER(BpttConfig), ctypes.POINTER(c_void_p)]),
@@ -58,8 +60,8 @@ _SIGS = {
     "bptt_backward": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "bptt_set_timing": (c_int, [c_void_p, c_int]),
     "bptt_get_timing": (c_int, [c_void_p, ctypes.POINTER(c_float), ctypes.POINTER(c_int), c_int]),
-    "policy_forward": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
-    "policy_backward": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
+    "policy_forward": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p]),
+    "policy_backward": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p]),
     "sim_rollout": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
     "sim_rollout_config": (c_int, [c_void_p, c_int, c_int, c_int]),
     "sim_rollout_get_config": (c_int, [c_void_p, ctypes.POINTER(c_int), ctypes.POINTER(c_int),
@@ -181,6 +183,15 @@ def sim_render(h, s, depth=None, lidar=None, hit_cam=None, hit_lidar=None):
           ptr(hit_cam, torch.int32), ptr(hit_lidar, torch.int32), stream())
 
 
+WORK_FIELDS = ("rays", "sphere_tests", "box_tests", "agent_tests", "tiles", "cone_tests")
+
+
+def sim_render_work(h, sensor, s, out, work):
+    """work: int32 [A][4][6] (see WORK_FIELDS)."""
+    _call("sim_render_work", h, int(sensor), ptr(s, torch.float32), ptr(out, torch.float32),
+          ptr(work, torch.int32), stream())
+
+
 def sim_collide(h, s, flags=None, min_dist=None):
     _call("sim_collide", h, ptr(s, torch.float32), ptr(flags, torch.uint8),
           ptr(min_dist, torch.float32), stream())
@@ -197,8 +208,9 @@ def sim_step_backward(h, s_t, a_t, g_s_next, g_depth, g_lidar, hit_cam, hit_lida
 # policy / BPTT
 # --------------------------------------------------------------------------
 
-def bptt_create(h, T, K, w_p, w_v, w_u, w_o, beta, d_safe, store_activations=1) -> int:
-    cfg = BpttConfig(T, K, w_p, w_v, w_u, w_o, beta, d_safe, int(store_activations))
+def bptt_create(h, T, K, w_p, w_v, w_u, w_o, beta, d_safe, store_activations=1,
+                policy_gemm=POLICY_GEMM_FP32) -> int:
+    cfg = BpttConfig(T, K, w_p, w_v, w_u, w_o, beta, d_safe, int(store_activations), int(policy_gemm))
     b = c_void_p()
     _call("bptt_create", h, ctypes.byref(cfg), ctypes.byref(b))
     return b.value
@@ -237,15 +249,15 @@ def bptt_get_timing(b):
     return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(BPTT_TIMING_CLASSES)}
 
 
-def policy_forward(theta, x, y):
+def policy_forward(theta, x, y, gemm_mode=POLICY_GEMM_FP32):
     _call("policy_forward", ptr(theta, torch.float32), ptr(x, torch.float32), ptr(y, torch.float32),
-          int(x.shape[0]), stream())
+          int(x.shape[0]), int(gemm_mode), stream())
 
 
-def policy_backward(theta, x, g_y, g_theta, g_x=None):
+def policy_backward(theta, x, g_y, g_theta, g_x=None, gemm_mode=POLICY_GEMM_FP32):
     _call("policy_backward", ptr(theta, torch.float32), ptr(x, torch.float32),
           ptr(g_y, torch.float32), ptr(g_theta, torch.float32), ptr(g_x, torch.float32),
-          int(x.shape[0]), stream())
+          int(x.shape[0]), int(gemm_mode), stream())
 
 
 def adam_step(w, g, m, v, lr, b1, b2, eps, t):

@@ -16,12 +16,13 @@ DEFAULT_WEIGHTS = dict(w_p=0.01, w_v=0.1, w_u=0.01, w_o=1.0, beta=10.0, d_safe=1
 class BpttEngine:
     """Owns a bptt_handle bound to an Env (which must outlive it)."""
 
-    def __init__(self, env, T: int, K: int, store_activations: bool = True, **weights):
+    def __init__(self, env, T: int, K: int, store_activations: bool = True,
+                 policy_gemm: int = _lib.POLICY_GEMM_FP32, **weights):
         w = dict(DEFAULT_WEIGHTS)
         w.update(weights)
         self.env, self.T, self.K = env, T, K
         self.h = _lib.bptt_create(env.h, T, K, w["w_p"], w["w_v"], w["w_u"], w["w_o"], w["beta"],
-                                  w["d_safe"], store_activations)
+                                  w["d_safe"], store_activations, policy_gemm)
 
     def workspace_bytes(self) -> int:
         return _lib.bptt_workspace_bytes(self.h)

@@ -37,10 +37,6 @@ static_assert(kOffB3 + kOut == POLICY_N_PARAMS, "policy parameter layout");
 // ---------------------------------------------------------------------------
 // observation, action, loss kernels
 // ---------------------------------------------------------------------------
-// logistic function on the hardware exp2 unit and reciprocal (a few ulp; the
-// loss derivative it feeds is compared at 1e-3 relative)
-__device__ __forceinline__ float sigmoid(float x) { return __frcp_rn(1.f + __expf(-x)); }
-
 // Fills the proprioceptive part of the observation row, X[b][3072..3083] =
 // [goal - p, v, b, 0, 0, 0] (the depth part is written by the renderer).
 __global__ void obs_fwd_kernel(int A, int model, float* __restrict__ X, const float* __restrict__ s,
@@ -145,42 +141,44 @@ __global__ void action_bwd_kernel(int A, int model, const float* __restrict__ ga
   for (int k = 0; k < kOut; ++k) gY[(size_t)b * kOut + k] = g[k] + sc * cu * y[k];
 }
 
-// Observation backward: turns gX[b][0..3071] into dL/d(depth) in place
-// (input scaling plus the obstacle term) and adds the proprioceptive part to
-// g_s (obs = [goal - p, v, b]).
-__global__ __launch_bounds__(256) void obs_bwd_kernel(int A, int model, float* __restrict__ gX,
-                                                      const float* __restrict__ X,
-                                                      const float* __restrict__ s, float dmax,
-                                                      float beta, float d_safe, float co,
-                                                      const float* __restrict__ gl,
-                                                      float* __restrict__ g_s) {
-  const int b = blockIdx.x, t = threadIdx.x;
-  const float sc = gl ? gl[0] : 1.f;
+// Observation backward, depth part: turns gX[b][0..3071] into dL/d(depth) in
+// place (input scaling 1/d_max plus the obstacle-loss derivative).
+__global__ __launch_bounds__(256) void obs_depth_bwd_kernel(float* __restrict__ gX, const float* __restrict__ X,
+                                                            float dmax, float beta, float d_safe, float co,
+                                                            const float* __restrict__ gl) {
+  const int b = blockIdx.x;
+  const float sc = gl ? gl[0] * co : co;
+  const float inv = 1.f / dmax;
   float* grow = gX + (size_t)b * kObsPad;
   const float* xrow = X + (size_t)b * kObsPad;
-  const float inv = 1.f / dmax;
-  for (int r = t; r < kRays; r += 256) {
-    const float sig = sigmoid(beta * (d_safe - xrow[r] * dmax));
-    grow[r] = grow[r] * inv - sc * co * sig;
+  for (int r = threadIdx.x; r < kRays; r += 256) {
+    const float sig = __frcp_rn(1.f + __expf(-beta * (d_safe - xrow[r] * dmax)));
+    grow[r] = grow[r] * inv - sc * sig;
   }
-  if (t == 0) {
-    for (int k = 0; k < 3; ++k) {
-      g_s[(size_t)k * A + b] -= grow[kRays + k];
-      g_s[(size_t)(k + 3) * A + b] += grow[kRays + 3 + k];
-    }
-    if (model == SIM_PM9) {
-      for (int k = 0; k < 3; ++k) g_s[(size_t)(k + 6) * A + b] += grow[kRays + 6 + k];
-    } else {
-      float q[4] = {s[6 * (size_t)A + b], s[7 * (size_t)A + b], s[8 * (size_t)A + b],
-                    s[9 * (size_t)A + b]};
-      float qn[4], in;
-      quat_normalize(q, qn, &in);
-      float G[3][3] = {{0.f, 0.f, grow[kRays + 6]}, {0.f, 0.f, grow[kRays + 7]}, {0.f, 0.f, grow[kRays + 8]}};
-      float gqn[4], gq[4];
-      rot_vjp(G, qn, gqn);
-      normalize_vjp(qn, in, gqn, gq);
-      for (int k = 0; k < 4; ++k) g_s[(size_t)(6 + k) * A + b] += gq[k];
-    }
+}
+
+// Observation backward, proprioceptive part: adds d(obs)/d(s)^T gX[b][3072..3080]
+// to g_s (obs = [goal - p, v, b]); the depth part is done in the gX GEMM.
+__global__ void obs_bwd_kernel(int A, int model, const float* __restrict__ gX, const float* __restrict__ s,
+                               float* __restrict__ g_s) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= A) return;
+  const float* grow = gX + (size_t)b * kObsPad + kRays;
+  for (int k = 0; k < 3; ++k) {
+    g_s[(size_t)k * A + b] -= grow[k];
+    g_s[(size_t)(k + 3) * A + b] += grow[3 + k];
+  }
+  if (model == SIM_PM9) {
+    for (int k = 0; k < 3; ++k) g_s[(size_t)(k + 6) * A + b] += grow[6 + k];
+  } else {
+    float q[4] = {s[6 * (size_t)A + b], s[7 * (size_t)A + b], s[8 * (size_t)A + b], s[9 * (size_t)A + b]};
+    float qn[4], in;
+    quat_normalize(q, qn, &in);
+    float G[3][3] = {{0.f, 0.f, grow[6]}, {0.f, 0.f, grow[7]}, {0.f, 0.f, grow[8]}};
+    float gqn[4], gq[4];
+    rot_vjp(G, qn, gqn);
+    normalize_vjp(qn, in, gqn, gq);
+    for (int k = 0; k < 4; ++k) g_s[(size_t)(6 + k) * A + b] += gq[k];
   }
 }
 
@@ -208,20 +206,20 @@ static PolicyPtrs policy_ptrs(const float* theta, const float* W1p) {
 }
 
 static int mlp_forward(int B, const PolicyPtrs& p, const float* X, float* H1, float* H2, float* Y,
-                       hipStream_t st, bptt_handle* owner = nullptr) {
+                       hipStream_t st, int prec, bptt_handle* owner = nullptr) {
   GemmArgs g;
   g.M = B; g.N = kHid; g.K = kObsPad;
   g.A = X; g.lda = kObsPad; g.B = p.W1p; g.ldb = kObsPad;
   g.C = H1; g.ldc = kHid; g.bias = p.b1;
   const int e0 = owner ? tmark(owner, st) : -1;
-  int rc = launch_gemm(true, true, EPI_BIAS_TANH, g, 1, st);
+  int rc = launch_gemm(true, true, EPI_BIAS_TANH, g, 1, st, prec);
   if (rc) return rc;
   if (owner) tpair(owner, BPTT_T_L1, e0, tmark(owner, st));
   g = GemmArgs();
   g.M = B; g.N = kHid; g.K = kHid;
   g.A = H1; g.lda = kHid; g.B = p.W2; g.ldb = kHid;
   g.C = H2; g.ldc = kHid; g.bias = p.b2;
-  if ((rc = launch_gemm(true, true, EPI_BIAS_TANH, g, 1, st))) return rc;
+  if ((rc = launch_gemm(true, true, EPI_BIAS_TANH, g, 1, st, prec))) return rc;
   return launch_narrow_fwd(B, kHid, kOut, H2, kHid, p.W3, p.b3, Y, st);
 }
 
@@ -250,15 +248,23 @@ static size_t partial_floats(int B) {
 }
 
 // Accumulates weight gradients for one batch and writes gX = dL/dX.
+// obs (nullable): turns the gX GEMM's epilogue into the observation backward
+// for the depth columns (input scaling and the obstacle-loss derivative).
+struct ObsGrad {
+  float scale, c, beta, d_safe, dmax;
+  const float* gl;
+};
+
 static int mlp_backward(int B, const PolicyPtrs& p, const float* X, const float* H1, const float* H2,
-                        const float* Y, const float* gY, MlpGradBufs& gb, hipStream_t st) {
+                        const float* Y, const float* gY, MlpGradBufs& gb, hipStream_t st, int prec,
+                        const ObsGrad* obs = nullptr) {
   int rc = launch_narrow_bwd(B, kHid, kOut, gY, Y, p.W3, H2, kHid, gb.gZ3, gb.gZ2, st);
   if (rc) return rc;
   // gW3 += gZ3^T H2 ; gb3 += colsum(gZ3)
   GemmArgs g;
   g.M = kOut; g.N = kHid; g.K = B;
   g.A = gb.gZ3; g.lda = kOut; g.B = H2; g.ldb = kHid; g.C = gb.part; g.ldc = kHid;
-  if ((rc = launch_gemm(false, false, EPI_PARTIAL, g, kSplitW3, st))) return rc;
+  if ((rc = launch_gemm(false, false, EPI_PARTIAL, g, kSplitW3, st, prec))) return rc;
   if ((rc = launch_splitk_reduce(gemm_splits_used(B, kSplitW3), kOut, kHid, kHid, gb.part, gb.gW3, kHid,
                                  true, st)))
     return rc;
@@ -267,7 +273,7 @@ static int mlp_backward(int B, const PolicyPtrs& p, const float* X, const float*
   g = GemmArgs();
   g.M = kHid; g.N = kHid; g.K = B;
   g.A = gb.gZ2; g.lda = kHid; g.B = H1; g.ldb = kHid; g.C = gb.part; g.ldc = kHid;
-  if ((rc = launch_gemm(false, false, EPI_PARTIAL, g, kSplitW2, st))) return rc;
+  if ((rc = launch_gemm(false, false, EPI_PARTIAL, g, kSplitW2, st, prec))) return rc;
   if ((rc = launch_splitk_reduce(gemm_splits_used(B, kSplitW2), kHid, kHid, kHid, gb.part, gb.gW2, kHid,
                                  true, st)))
     return rc;
@@ -277,13 +283,13 @@ static int mlp_backward(int B, const PolicyPtrs& p, const float* X, const float*
   g.M = B; g.N = kHid; g.K = kHid;
   g.A = gb.gZ2; g.lda = kHid; g.B = p.W2; g.ldb = kHid; g.C = gb.gZ1; g.ldc = kHid;
   g.aux = H1; g.ld_aux = kHid;
-  if ((rc = launch_gemm(true, false, EPI_MUL_DTANH, g, 1, st))) return rc;
+  if ((rc = launch_gemm(true, false, EPI_MUL_DTANH, g, 1, st, prec))) return rc;
   // gW1 += gZ1^T X ; gb1
   const int e0 = gb.owner ? tmark(gb.owner, st) : -1;
   g = GemmArgs();
   g.M = kHid; g.N = kObsPad; g.K = B;
   g.A = gb.gZ1; g.lda = kHid; g.B = X; g.ldb = kObsPad; g.C = gb.part; g.ldc = kObsPad;
-  if ((rc = launch_gemm(false, false, EPI_PARTIAL, g, kSplitW1, st))) return rc;
+  if ((rc = launch_gemm(false, false, EPI_PARTIAL, g, kSplitW1, st, prec))) return rc;
   if ((rc = launch_splitk_reduce(gemm_splits_used(B, kSplitW1), kHid, kObsPad, kObsPad, gb.part, gb.gW1p,
                                  kObsPad, true, st)))
     return rc;
@@ -294,7 +300,12 @@ static int mlp_backward(int B, const PolicyPtrs& p, const float* X, const float*
   g = GemmArgs();
   g.M = B; g.N = kObsPad; g.K = kHid;
   g.A = gb.gZ1; g.lda = kHid; g.B = p.W1p; g.ldb = kObsPad; g.C = gb.gX; g.ldc = kObsPad;
-  rc = launch_gemm(true, false, EPI_STORE, g, 1, st);
+  if (obs) {
+    g.aux = X; g.ld_aux = kObsPad; g.obs_split = kRays;
+    g.obs_scale = obs->scale; g.obs_c = obs->c; g.obs_beta = obs->beta; g.obs_d = obs->d_safe;
+    g.obs_dmax = obs->dmax; g.obs_gl = obs->gl;
+  }
+  rc = launch_gemm(true, false, obs ? EPI_OBS_GRAD : EPI_STORE, g, 1, st, prec);
   if (gb.owner) tpair(gb.owner, BPTT_T_GX, e1, tmark(gb.owner, st));
   return rc;
 }
@@ -330,6 +341,9 @@ struct bptt_handle {
   const float *theta = nullptr, *s0 = nullptr, *goal = nullptr;
   bool have_fwd = false;
   bool store = false;
+  int prec = GEMM_FP32;
+  hipStream_t side = nullptr;               // recompute stream (stored mode)
+  hipEvent_t ev_start = nullptr, ev_rec[2] = {nullptr, nullptr}, ev_free[2] = {nullptr, nullptr};
   // optional HIP-event timing of the main kernel classes (BPTT_T_*)
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
@@ -382,6 +396,9 @@ int bptt_create(sim_handle* sim, const bptt_config* cfg, bptt_handle** out) {
   b->Ka = Ka;
   b->nseg = cdiv(cfg->T, K);
   b->store = cfg->store_activations != 0;
+  DA_REQUIRE(cfg->policy_gemm == POLICY_GEMM_FP32 || cfg->policy_gemm == POLICY_GEMM_BF16X3,
+             "bptt_create: policy_gemm must be POLICY_GEMM_FP32 or POLICY_GEMM_BF16X3");
+  b->prec = cfg->policy_gemm == POLICY_GEMM_BF16X3 ? GEMM_BF16X3 : GEMM_FP32;
   // slots: with stored activations every step has its own state / activation
   // slot; otherwise only the K steps of the segment being recomputed
   const int SL = b->store ? cfg->T : K;
@@ -391,8 +408,11 @@ int bptt_create(sim_handle* sim, const bptt_config* cfg, bptt_handle** out) {
   add(&b->W1p, (size_t)kHid * kObsPad * 4);
   add(&b->ckpt, (size_t)b->nseg * C * A * 4);
   add(&b->seg_s, (size_t)(SL + 1) * C * A * 4);
-  add(&b->X, (size_t)K * A * kObsPad * 4);
-  add(&b->hit, (size_t)K * A * kRays * 4);
+  // stored mode double-buffers the per-segment observations / hit records so
+  // the next segment's renders can be recomputed while this one is swept
+  const int sets = b->store ? 2 : 1;
+  add(&b->X, (size_t)sets * K * A * kObsPad * 4);
+  add(&b->hit, (size_t)sets * K * A * kRays * 4);
   add(&b->H1, (size_t)SL * A * kHid * 4);
   add(&b->H2, (size_t)SL * A * kHid * 4);
   add(&b->Y, (size_t)SL * A * kOut * 4);
@@ -435,6 +455,9 @@ int bptt_create(sim_handle* sim, const bptt_config* cfg, bptt_handle** out) {
 int bptt_destroy(bptt_handle* b) {
   if (!b) return SIM_OK;
   for (hipEvent_t e : b->ev_pool) (void)hipEventDestroy(e);
+  for (hipEvent_t e : {b->ev_start, b->ev_rec[0], b->ev_rec[1], b->ev_free[0], b->ev_free[1]})
+    if (e) (void)hipEventDestroy(e);
+  if (b->side) (void)hipStreamDestroy(b->side);
   if (b->mem) (void)hipFree(b->mem);
   delete b;
   return SIM_OK;
@@ -488,7 +511,7 @@ static int forward_step(bptt_handle* b, const PolicyPtrs& pp, const float* s, fl
   tpair(b, BPTT_T_RENDER, e0, tmark(b, st));
   hipLaunchKernelGGL(obs_fwd_kernel, dim3(cdiv(A, 256)), dim3(256), 0, st, A, h->cfg.model, X, s, b->goal);
   DA_LAUNCH_CHECK("obs_fwd_kernel");
-  if ((rc = mlp_forward(A, pp, X, H1, H2, Y, st, b))) return rc;
+  if ((rc = mlp_forward(A, pp, X, H1, H2, Y, st, b->prec, b))) return rc;
   hipLaunchKernelGGL(action_kernel, dim3(cdiv(A, 256)), dim3(256), 0, st, A, h->cfg.model, Y, h->params,
                      act);
   DA_LAUNCH_CHECK("action_kernel");
@@ -560,24 +583,59 @@ int bptt_backward(bptt_handle* b, const float* g_loss, float* g_theta, float* g_
   float* g_cur = b->g_b;
   DA_HIP(hipMemsetAsync(g_next, 0, sbytes, st));
   int rc;
+  const size_t xset = (size_t)K * A * kObsPad, hset = (size_t)K * A * kRays;
+  // stored mode: renders of a segment only (states are kept); they run on the
+  // side stream one segment ahead of the sweep
+  auto recompute_renders = [&](int seg, hipStream_t q) -> int {
+    const int t0 = seg * K, n = std::min(T, t0 + K) - t0;
+    float* Xs = b->X + (size_t)(seg & 1) * xset;
+    int* Hs = b->hit + (size_t)(seg & 1) * hset;
+    for (int j = 0; j < n; ++j) {
+      const float* s = b->seg_s + (size_t)(t0 + j) * C * A;
+      float* X = Xs + (size_t)j * A * kObsPad;
+      const int e0 = tmark(b, q);
+      int r = launch_render(h->scene, h->cam.dev, h->cfg.model == SIM_RB13, h->cfg.fov_cull != 0, s, A, X,
+                            Hs + (size_t)j * A * kRays, kObsPad, 1.0f / dmax, q);
+      if (r) return r;
+      tpair(b, BPTT_T_RENDER, e0, tmark(b, q));
+      hipLaunchKernelGGL(obs_fwd_kernel, dim3(cdiv(A, 256)), dim3(256), 0, q, A, h->cfg.model, X, s, b->goal);
+      DA_LAUNCH_CHECK("obs_fwd_kernel");
+    }
+    return SIM_OK;
+  };
+  // with kernel timing on, the recompute stays on the caller's stream so that
+  // every timed kernel runs alone
+  const bool overlap = b->store && !b->timing;
+  if (b->store && !overlap) {
+    if ((rc = recompute_renders(b->nseg - 1, st))) return rc;
+  } else if (overlap) {
+    if (!b->side) {
+      DA_HIP(hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking));
+      for (hipEvent_t* e : {&b->ev_start, &b->ev_rec[0], &b->ev_rec[1], &b->ev_free[0], &b->ev_free[1]})
+        DA_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
+    }
+    // everything enqueued so far on the caller's stream (forward pass, zeroing)
+    // precedes the side stream's first recompute
+    DA_HIP(hipEventRecord(b->ev_start, st));
+    DA_HIP(hipStreamWaitEvent(b->side, b->ev_start, 0));
+    if ((rc = recompute_renders(b->nseg - 1, b->side))) return rc;
+    DA_HIP(hipEventRecord(b->ev_rec[(b->nseg - 1) & 1], b->side));
+  }
   for (int seg = b->nseg - 1; seg >= 0; --seg) {
     const int t0 = seg * K, n = std::min(T, t0 + K) - t0;
-    // recompute the segment: observations and hit records always; states,
-    // activations and actions only when they were not stored
-    if (b->store) {
-      for (int j = 0; j < n; ++j) {
-        const float* s = b->seg_s + (size_t)(t0 + j) * C * A;
-        float* X = b->X + (size_t)j * A * kObsPad;
-        const int e0 = tmark(b, st);
-        rc = launch_render(h->scene, h->cam.dev, h->cfg.model == SIM_RB13, h->cfg.fov_cull != 0, s, A, X,
-                           b->hit + (size_t)j * A * kRays, kObsPad, 1.0f / dmax, st);
-        if (rc) return rc;
-        tpair(b, BPTT_T_RENDER, e0, tmark(b, st));
-        hipLaunchKernelGGL(obs_fwd_kernel, dim3(cdiv(A, 256)), dim3(256), 0, st, A, h->cfg.model, X, s,
-                           b->goal);
-        DA_LAUNCH_CHECK("obs_fwd_kernel");
+    const int set = b->store ? (seg & 1) : 0;
+    if (b->store && !overlap) {
+      if (seg > 0 && (rc = recompute_renders(seg - 1, st))) return rc;
+    } else if (overlap) {
+      if (seg > 0) {
+        // set (seg-1)&1 was last read by the sweep of seg+1
+        if (seg + 1 <= b->nseg - 1) DA_HIP(hipStreamWaitEvent(b->side, b->ev_free[(seg - 1) & 1], 0));
+        if ((rc = recompute_renders(seg - 1, b->side))) return rc;
+        DA_HIP(hipEventRecord(b->ev_rec[(seg - 1) & 1], b->side));
       }
+      DA_HIP(hipStreamWaitEvent(st, b->ev_rec[set], 0));
     } else {
+      // recompute the whole segment from its checkpoint
       DA_HIP(hipMemcpyAsync(b->seg_s, b->ckpt + (size_t)seg * C * A, sbytes, hipMemcpyDeviceToDevice, st));
       for (int j = 0; j < n; ++j) {
         rc = forward_step(b, pp, b->seg_s + (size_t)j * C * A, b->seg_s + (size_t)(j + 1) * C * A,
@@ -591,7 +649,8 @@ int bptt_backward(bptt_handle* b, const float* g_loss, float* g_theta, float* g_
       const int si = b->store ? t0 + j : j;  // state / activation slot of step t0 + j
       const float* s = b->seg_s + (size_t)si * C * A;
       const float* s1 = b->seg_s + (size_t)(si + 1) * C * A;
-      const float* X = b->X + (size_t)j * A * kObsPad;
+      const float* X = b->X + (size_t)set * xset + (size_t)j * A * kObsPad;
+      const int* hit = b->hit + (size_t)set * hset + (size_t)j * A * kRays;
       const float* H1 = b->H1 + (size_t)si * A * kHid;
       const float* H2 = b->H2 + (size_t)si * A * kHid;
       const float* Y = b->Y + (size_t)si * A * kOut;
@@ -608,17 +667,21 @@ int bptt_backward(bptt_handle* b, const float* g_loss, float* g_theta, float* g_
                          Y, h->params, cu, g_loss, b->gY);
       DA_LAUNCH_CHECK("action_bwd_kernel");
       b->gb.owner = b;
-      if ((rc = mlp_backward(A, pp, X, H1, H2, Y, b->gY, b->gb, st))) return rc;
-      hipLaunchKernelGGL(obs_bwd_kernel, dim3(A), dim3(256), 0, st, A, h->cfg.model, b->gb.gX, X, s,
-                         dmax, b->cfg.beta, b->cfg.d_safe, co, g_loss, g_cur);
+      if ((rc = mlp_backward(A, pp, X, H1, H2, Y, b->gY, b->gb, st, b->prec))) return rc;
+      hipLaunchKernelGGL(obs_depth_bwd_kernel, dim3(A), dim3(256), 0, st, b->gb.gX, X, dmax, b->cfg.beta,
+                         b->cfg.d_safe, co, g_loss);
+      DA_LAUNCH_CHECK("obs_depth_bwd_kernel");
+      hipLaunchKernelGGL(obs_bwd_kernel, dim3(cdiv(A, 256)), dim3(256), 0, st, A, h->cfg.model, b->gb.gX, s,
+                         g_cur);
       DA_LAUNCH_CHECK("obs_bwd_kernel");
       e0 = tmark(b, st);
       if ((rc = launch_render_vjp(h->scene, h->cam.dev, h->cfg.model == SIM_RB13, s, A, b->gb.gX,
-                                  kObsPad, b->hit + (size_t)j * A * kRays, g_cur, st)))
+                                  kObsPad, hit, g_cur, st)))
         return rc;
       tpair(b, BPTT_T_RENDER_VJP, e0, tmark(b, st));
       std::swap(g_next, g_cur);
     }
+    if (overlap) DA_HIP(hipEventRecord(b->ev_free[set], st));
   }
   if (g_s0) DA_HIP(hipMemcpyAsync(g_s0, g_next, sbytes, hipMemcpyDeviceToDevice, st));
   return write_flat_grad(b->gb, g_theta, st);
@@ -627,8 +690,13 @@ int bptt_backward(bptt_handle* b, const float* g_loss, float* g_theta, float* g_
 // ---------------------------------------------------------------------------
 // standalone policy calls (allocate their scratch per call; synchronous)
 // ---------------------------------------------------------------------------
-int policy_forward(const float* theta, const float* x, float* y, int32_t B, void* stream) {
+static int policy_prec(int32_t mode) {
+  return mode == POLICY_GEMM_BF16X3 ? GEMM_BF16X3 : GEMM_FP32;
+}
+
+int policy_forward(const float* theta, const float* x, float* y, int32_t B, int32_t gemm_mode, void* stream) {
   DA_REQUIRE(theta && x && y && B >= 0, "policy_forward: bad argument");
+  DA_REQUIRE(gemm_mode == POLICY_GEMM_FP32 || gemm_mode == POLICY_GEMM_BF16X3, "policy_forward: bad gemm_mode");
   if (B == 0) return SIM_OK;
   int rc = require_device();
   if (rc) return rc;
@@ -639,7 +707,7 @@ int policy_forward(const float* theta, const float* x, float* y, int32_t B, void
   float *W1p = mem, *X = W1p + nW, *H1 = X + nX, *H2 = H1 + nH;
   rc = launch_pad_rows(kHid, kObs, kObsPad, theta + kOffW1, kObs, W1p, st);
   if (!rc) rc = launch_pad_rows(B, kObs, kObsPad, x, kObs, X, st);
-  if (!rc) rc = mlp_forward(B, policy_ptrs(theta, W1p), X, H1, H2, y, st);
+  if (!rc) rc = mlp_forward(B, policy_ptrs(theta, W1p), X, H1, H2, y, st, policy_prec(gemm_mode));
   hipError_t e = hipStreamSynchronize(st);
   (void)hipFree(mem);
   if (rc) return rc;
@@ -648,8 +716,9 @@ int policy_forward(const float* theta, const float* x, float* y, int32_t B, void
 }
 
 int policy_backward(const float* theta, const float* x, const float* g_y, float* g_theta, float* g_x,
-                    int32_t B, void* stream) {
+                    int32_t B, int32_t gemm_mode, void* stream) {
   DA_REQUIRE(theta && x && g_y && g_theta && B >= 1, "policy_backward: bad argument");
+  DA_REQUIRE(gemm_mode == POLICY_GEMM_FP32 || gemm_mode == POLICY_GEMM_BF16X3, "policy_backward: bad gemm_mode");
   int rc = require_device();
   if (rc) return rc;
   hipStream_t st = as_stream(stream);
@@ -676,8 +745,8 @@ int policy_backward(const float* theta, const float* x, const float* g_y, float*
   rc = launch_pad_rows(kHid, kObs, kObsPad, theta + kOffW1, kObs, W1p, st);
   if (!rc) rc = launch_pad_rows(B, kObs, kObsPad, x, kObs, X, st);
   if (!rc && hipMemsetAsync(gb.gW1p, 0, (nW + nT) * 4, st) != hipSuccess) rc = fail(SIM_EHIP, "memset");
-  if (!rc) rc = mlp_forward(B, pp, X, H1, H2, Y, st);
-  if (!rc) rc = mlp_backward(B, pp, X, H1, H2, Y, g_y, gb, st);
+  if (!rc) rc = mlp_forward(B, pp, X, H1, H2, Y, st, policy_prec(gemm_mode));
+  if (!rc) rc = mlp_backward(B, pp, X, H1, H2, Y, g_y, gb, st, policy_prec(gemm_mode));
   if (!rc) rc = write_flat_grad(gb, g_theta, st);
   if (!rc && g_x) rc = launch_pad_rows(B, kObs, kObs, gb.gX, kObsPad, g_x, st);
   hipError_t e = hipStreamSynchronize(st);

@@ -78,6 +78,8 @@ __device__ __forceinline__ void gemm_epilogue(const GemmArgs& g, const f32x16 (&
                                               int wm, int wn, int col, int half) {
   float* C = g.C;
   if (EPI == EPI_PARTIAL) C += (size_t)blockIdx.z * g.M * g.ldc;
+  float obs_c = g.obs_c;
+  if (EPI == EPI_OBS_GRAD && g.obs_gl) obs_c *= g.obs_gl[0];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -109,6 +111,12 @@ __device__ __forceinline__ void gemm_epilogue(const GemmArgs& g, const f32x16 (&
           const float z = g.aux[(size_t)m * g.ld_aux + n];
           const float sg = 1.f / (1.f + expf(-z));
           v = v * (sg * (1.f + z * (1.f - sg)));
+        } else if (EPI == EPI_OBS_GRAD) {
+          if (n < g.obs_split) {
+            const float x = g.aux[(size_t)m * g.ld_aux + n];
+            const float sg = __frcp_rn(1.f + __expf(-g.obs_beta * (g.obs_d - x * g.obs_dmax)));
+            v = v * g.obs_scale - obs_c * sg;
+          }
         }
         C[idx] = v;
       }
@@ -255,6 +263,106 @@ static int gemm_bf16_t(const GemmArgs& g, int splits, hipStream_t st) {
   return SIM_OK;
 }
 
+// ---------------------------------------------------------------------------
+// FP32 products from BF16 matrix cores: each operand x is split as
+// x = hi + lo with hi = bf16(x), lo = bf16(x - hi) (x keeps about 16
+// significant bits), and A B ~ Ah Bh + Ah Bl + Al Bh accumulated in FP32 (the
+// Al Bl term, ~2^-16 relative, is dropped). This is the split-precision scheme
+// of Ootomo & Yokota (2022); its relative error (~1e-5) sits far inside the
+// gradient tolerance while the BF16 matrix rate is 16x the FP32 one on gfx950.
+// ---------------------------------------------------------------------------
+template <bool KMAJ>
+__device__ __forceinline__ void store_tile_split(uint16_t* H, uint16_t* L, const float4 (&reg)[4]) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const float x[4] = {reg[i].x, reg[i].y, reg[i].z, reg[i].w};
+    uint32_t hb[4], lb[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      hb[j] = bf16_bits(x[j]);
+      lb[j] = bf16_bits(x[j] - __uint_as_float(hb[j] << 16));
+    }
+    if (KMAJ) {
+      const int row = (t >> 3) + 32 * i, k = (t & 7) * 4;
+      *reinterpret_cast<uint2*>(H + row * BKP + k) = make_uint2(hb[0] | (hb[1] << 16), hb[2] | (hb[3] << 16));
+      *reinterpret_cast<uint2*>(L + row * BKP + k) = make_uint2(lb[0] | (lb[1] << 16), lb[2] | (lb[3] << 16));
+    } else {
+      const int kk = (t >> 5) + 8 * i, m = (t & 31) * 4;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        H[(m + j) * BKP + kk] = (uint16_t)hb[j];
+        L[(m + j) * BKP + kk] = (uint16_t)lb[j];
+      }
+    }
+  }
+}
+
+template <bool AK, bool BK_, int EPI>
+__global__ __launch_bounds__(256) void gemm_x3_kernel(GemmArgs g) {
+  __shared__ __attribute__((aligned(16))) uint16_t Ah[GBM * BKP];
+  __shared__ __attribute__((aligned(16))) uint16_t Al[GBM * BKP];
+  __shared__ __attribute__((aligned(16))) uint16_t Bh[GBN * BKP];
+  __shared__ __attribute__((aligned(16))) uint16_t Bl[GBN * BKP];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  const int m0 = blockIdx.y * GBM, n0 = blockIdx.x * GBN;
+  const int kbeg = blockIdx.z * g.k_split;
+  const int kend = min(g.K, kbeg + g.k_split);
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) acc[a][b][i] = 0.f;
+  float4 ra[4], rb[4];
+  if (kbeg < kend) {
+    load_tile<AK>(g.A, g.lda, g.M, kend, m0, kbeg, ra);
+    load_tile<BK_>(g.B, g.ldb, g.N, kend, n0, kbeg, rb);
+  }
+  const int col = lane & 31, half = lane >> 5;
+  for (int k0 = kbeg; k0 < kend; k0 += GBK) {
+    __syncthreads();
+    store_tile_split<AK>(Ah, Al, ra);
+    store_tile_split<BK_>(Bh, Bl, rb);
+    __syncthreads();
+    if (k0 + GBK < kend) {
+      load_tile<AK>(g.A, g.lda, g.M, kend, m0, k0 + GBK, ra);
+      load_tile<BK_>(g.B, g.ldb, g.N, kend, n0, k0 + GBK, rb);
+    }
+#pragma unroll
+    for (int s = 0; s < GBK / 16; ++s) {
+      const int ko = s * 16 + half * 8;
+      bf16x8 ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+      for (int x = 0; x < 2; ++x) {
+        ah[x] = *reinterpret_cast<const bf16x8*>(Ah + (wm + 32 * x + col) * BKP + ko);
+        al[x] = *reinterpret_cast<const bf16x8*>(Al + (wm + 32 * x + col) * BKP + ko);
+        bh[x] = *reinterpret_cast<const bf16x8*>(Bh + (wn + 32 * x + col) * BKP + ko);
+        bl[x] = *reinterpret_cast<const bf16x8*>(Bl + (wn + 32 * x + col) * BKP + ko);
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
+        }
+    }
+  }
+  gemm_epilogue<EPI>(g, acc, m0, n0, wm, wn, col, half);
+}
+
+template <bool AK, bool BK_, int EPI>
+static int gemm_x3_t(const GemmArgs& g, int splits, hipStream_t st) {
+  dim3 grid(cdiv(g.N, GBN), cdiv(g.M, GBM), splits);
+  hipLaunchKernelGGL((gemm_x3_kernel<AK, BK_, EPI>), grid, dim3(256), 0, st, g);
+  DA_LAUNCH_CHECK("gemm_x3_kernel");
+  return SIM_OK;
+}
+
 template <bool AK, bool BK_, int EPI>
 static int gemm_t(const GemmArgs& g, int splits, hipStream_t st) {
   dim3 grid(cdiv(g.N, GBN), cdiv(g.M, GBM), splits);
@@ -263,7 +371,7 @@ static int gemm_t(const GemmArgs& g, int splits, hipStream_t st) {
   return SIM_OK;
 }
 
-int launch_gemm(bool a_kmaj, bool b_kmaj, int epi, GemmArgs g, int splits, hipStream_t st, bool bf16) {
+int launch_gemm(bool a_kmaj, bool b_kmaj, int epi, GemmArgs g, int splits, hipStream_t st, int prec) {
   if (g.M == 0 || g.N == 0) return SIM_OK;
   if (splits < 1) splits = 1;
   g.k_split = (int)(cdiv64(cdiv64(g.K, splits), GBK) * GBK);
@@ -273,7 +381,15 @@ int launch_gemm(bool a_kmaj, bool b_kmaj, int epi, GemmArgs g, int splits, hipSt
       (reinterpret_cast<uintptr_t>(g.B) & 15))
     return fail(SIM_EINVAL, "gemm: operands need 16-byte alignment and leading dims %% 4 == 0");
   const int key = (a_kmaj ? 1 : 0) | (b_kmaj ? 2 : 0);
-  if (bf16) {
+  if (prec == GEMM_BF16X3) {
+    // the layer shapes of the policy MLP
+    if (key == 3 && epi == EPI_BIAS_TANH) return gemm_x3_t<true, true, EPI_BIAS_TANH>(g, 1, st);
+    if (key == 1 && epi == EPI_MUL_DTANH) return gemm_x3_t<true, false, EPI_MUL_DTANH>(g, 1, st);
+    if (key == 1 && epi == EPI_STORE) return gemm_x3_t<true, false, EPI_STORE>(g, 1, st);
+    if (key == 0 && epi == EPI_PARTIAL) return gemm_x3_t<false, false, EPI_PARTIAL>(g, splits, st);
+    return fail(SIM_EINVAL, "gemm: bf16x3 layout %d / epilogue %d not built", key, epi);
+  }
+  if (prec == GEMM_BF16) {
     // the layer shapes of the residual-dynamics MLP
     if (key == 3 && epi == EPI_BIAS_SILU) return gemm_bf16_t<true, true, EPI_BIAS_SILU>(g, 1, st);
     if (key == 3 && epi == EPI_BIAS) return gemm_bf16_t<true, true, EPI_BIAS>(g, 1, st);
@@ -289,6 +405,7 @@ int launch_gemm(bool a_kmaj, bool b_kmaj, int epi, GemmArgs g, int splits, hipSt
     case EPI_MUL_DTANH: return gemm_t<AK, BKM, EPI_MUL_DTANH>(g, 1, st);  \
     case EPI_ACCUM: return gemm_t<AK, BKM, EPI_ACCUM>(g, 1, st);          \
     case EPI_PARTIAL: return gemm_t<AK, BKM, EPI_PARTIAL>(g, splits, st); \
+    case EPI_OBS_GRAD: return gemm_t<AK, BKM, EPI_OBS_GRAD>(g, 1, st);    \
   }
   switch (key) {
     case 0: DA_GEMM_CASE(false, false) break;
@@ -335,7 +452,7 @@ int launch_splitk_reduce(int S, int M, int N, int ldp, const float* part, float*
 // sums rows [sp*rows_per, (sp+1)*rows_per) of 64 columns into part[sp][n]
 // (4 row-groups of 64 threads, fixed strides, fixed combine order); then each
 // column adds its kColsumSplits partials in order.
-constexpr int kColsumSplits = 32;
+constexpr int kColsumSplits = 256;
 
 __global__ void colsum_partial_kernel(int M, int N, const float* __restrict__ X, int ld, int rows_per,
                                       float* __restrict__ part) {
@@ -353,13 +470,22 @@ __global__ void colsum_partial_kernel(int M, int N, const float* __restrict__ X,
         ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
 }
 
+// 64 columns per block; 4 groups of 64 threads sum interleaved quarters of
+// the S partials, combined in a fixed order.
 __global__ void colsum_final_kernel(int S, int N, const float* __restrict__ part, float* __restrict__ out,
                                     int accumulate) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= N) return;
+  __shared__ float red[4][64];
+  const int c = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int g = threadIdx.x >> 6;
   float v = 0.f;
-  for (int s = 0; s < S; ++s) v += part[(size_t)s * N + c];
-  out[c] = accumulate ? out[c] + v : v;
+  if (c < N)
+    for (int s = g; s < S; s += 4) v += part[(size_t)s * N + c];
+  red[g][threadIdx.x & 63] = v;
+  __syncthreads();
+  if (g == 0 && c < N) {
+    const float tot = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
+    out[c] = accumulate ? out[c] + tot : tot;
+  }
 }
 
 int colsum_workspace_floats(int N) { return kColsumSplits * N; }
@@ -371,7 +497,7 @@ int launch_colsum(int M, int N, const float* X, int ld, float* out, bool accumul
   hipLaunchKernelGGL(colsum_partial_kernel, dim3(cdiv(N, 64), S), dim3(256), 0, st, M, N, X, ld, rows_per,
                      work);
   DA_LAUNCH_CHECK("colsum_partial_kernel");
-  hipLaunchKernelGGL(colsum_final_kernel, dim3(cdiv(N, 256)), dim3(256), 0, st, S, N, work, out,
+  hipLaunchKernelGGL(colsum_final_kernel, dim3(cdiv(N, 64)), dim3(256), 0, st, S, N, work, out,
                      accumulate ? 1 : 0);
   DA_LAUNCH_CHECK("colsum_final_kernel");
   return SIM_OK;

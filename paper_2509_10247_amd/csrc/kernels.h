@@ -48,6 +48,8 @@ int launch_step_vjp(int model, int integ, int A, float dt, const float* s, const
 int launch_render(const SceneDev& sc, const SensorDev& sen, bool rotate, bool cull, const float* s,
                   int A, float* out, int* rec, int out_ld, float out_scale, hipStream_t st,
                   float* term = nullptr, float beta = 1.f, float d_safe = 0.f);
+int launch_render_work(const SceneDev& sc, const SensorDev& sen, bool rotate, bool cull,
+                       const float* s, int A, float* out, int* work, hipStream_t st);
 // Adds the sensor's contribution (d out/d s)^T g to g_s (p and q components);
 // g[i*g_ld + r] is the gradient of the (unscaled) sensor value.
 int launch_render_vjp(const SceneDev& sc, const SensorDev& sen, bool rotate, const float* s, int A,

@@ -13,7 +13,9 @@ enum {
   EPI_PARTIAL = 4,    // split-K partial store
   EPI_BIAS = 5,       // C = acc + bias[n]
   EPI_BIAS_SILU = 6,  // z = acc + bias[n]; zout = z; C = z sigmoid(z)
-  EPI_MUL_DSILU = 7   // z = aux; C = acc * d silu(z)/dz
+  EPI_MUL_DSILU = 7,  // z = aux; C = acc * d silu(z)/dz
+  EPI_OBS_GRAD = 8    // n < obs_split: C = acc * obs_scale - obs_c * sigmoid(obs_beta (obs_d - aux * obs_dmax))
+                      // (gradient of the policy input and obstacle loss w.r.t. depth); else C = acc
 };
 
 // C[M][N] = op(A) op(B). A is [M][lda] (K-contiguous) or [K][lda]
@@ -33,14 +35,21 @@ struct GemmArgs {
   int ld_aux = 0;
   float* zout = nullptr;        // EPI_BIAS_SILU: pre-activation [M][ld_z]
   int ld_z = 0;
+  int obs_split = 0;            // EPI_OBS_GRAD parameters
+  float obs_scale = 1.f, obs_c = 0.f, obs_beta = 1.f, obs_d = 0.f, obs_dmax = 1.f;
+  const float* obs_gl = nullptr;  // EPI_OBS_GRAD: device scale of obs_c (nullable = 1)
   int k_split = 0;              // set by launch_gemm
 };
 
-// bf16: operands are read as FP32 and rounded to BF16 (nearest even) when
-// staged into LDS; the product runs on v_mfma_f32_32x32x16_bf16 with FP32
-// accumulation.
+// Precision of launch_gemm:
+//  GEMM_FP32:   v_mfma_f32_32x32x2f32 on FP32 operands;
+//  GEMM_BF16:   operands read as FP32 and rounded to BF16 (nearest even) when
+//               staged into LDS, v_mfma_f32_32x32x16_bf16, FP32 accumulation;
+//  GEMM_BF16X3: FP32 product from three BF16 products of the hi / lo split of
+//               each operand (relative error ~1e-5), FP32 accumulation.
+enum { GEMM_FP32 = 0, GEMM_BF16 = 1, GEMM_BF16X3 = 2 };
 int launch_gemm(bool a_kmaj, bool b_kmaj, int epi, GemmArgs g, int splits, hipStream_t st,
-                bool bf16 = false);
+                int prec = GEMM_FP32);
 int gemm_splits_used(int K, int splits);
 int launch_splitk_reduce(int S, int M, int N, int ldp, const float* part, float* out, int ldo,
                          bool accumulate, hipStream_t st);

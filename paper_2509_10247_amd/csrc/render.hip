@@ -32,16 +32,27 @@ __global__ __launch_bounds__(256) void render_kernel(SceneDev sc, SensorDev sen,
                               term, beta, d_safe, smem_f4);
 }
 
+// Same rendering, plus the per-wavefront work counters (diagnostics only).
+template <bool ROT, bool CULL>
+__global__ __launch_bounds__(256) void render_work_kernel(SceneDev sc, SensorDev sen,
+                                                          const float* __restrict__ s, int A,
+                                                          float* __restrict__ out, int out_ld,
+                                                          int* __restrict__ work) {
+  extern __shared__ float4 smem_f4[];
+  render_one_agent<ROT, CULL, true>(sc, sen, s, A, blockIdx.x, 0, sen.n_tiles, out, nullptr, out_ld,
+                                    1.0f, nullptr, 1.0f, 0.0f, smem_f4, work);
+}
+
 // ---------------------------------------------------------------------------
 // adjoint
 // ---------------------------------------------------------------------------
 // Sphere hits: dt/do = -n/(n.d) is ill-conditioned near silhouettes (in FP32
 // the discriminant r^2 - |perp|^2 of a grazing ray loses relative precision as
-// 1/(n.d)^2), so the sphere geometry is evaluated in FP64 from an FP64
-// direction table and an FP64 rotation. Plane hits (box entry face, room exit
-// face) have dt/do_f = -1/d_f, well conditioned for every hit inside the
-// sensor range, and stay in FP32. Per-thread sums and the per-agent reduction
-// are FP64.
+// 1/(n.d)^2), so sphere hits within ~17 deg of grazing (|n.d| < 0.3) are
+// evaluated in FP64 from an FP64 direction table and an FP64 rotation; the
+// others, and plane hits (box entry face, room exit face: dt/do_f = -1/d_f,
+// well conditioned for every hit inside the sensor range), in FP32.
+// Per-thread sums and the per-agent reduction are FP64.
 struct d3 {
   double x, y, z;
 };
@@ -60,7 +71,7 @@ __global__ __launch_bounds__(256) void render_vjp_kernel(SceneDev sc, SensorDev 
                                                          const float* __restrict__ g, int g_ld,
                                                          const int* __restrict__ rec,
                                                          float* __restrict__ g_s) {
-  __shared__ double red[12][256];
+  __shared__ double red[12][4];
   const int i = blockIdx.x;
   const int tid = threadIdx.x;
   const int env = sc.agent_env[i];
@@ -95,9 +106,15 @@ __global__ __launch_bounds__(256) void render_vjp_kernel(SceneDev sc, SensorDev 
   }
   const int np = ns + nb + na;
   const int nr = sen.n_rays;
-  double go[3] = {0.0, 0.0, 0.0};
-  double gR[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int r = tid; r < nr; r += 256) {
+  // per-thread sums (at most a dozen rays each) in FP32; the cross-thread
+  // reduction is FP64
+  float go[3] = {0.f, 0.f, 0.f};
+  float gR[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  // rays in the forward pass's tile order: a wavefront covers a compact
+  // angular patch, so its lanes mostly hit the same primitive
+  for (int tile = tid >> 6; tile < sen.n_tiles; tile += 4) {
+    const int r = sen.tile_rays[tile * kTileRays + (tid & 63)];
+    if (r < 0) continue;
     const int k = rec[(size_t)i * nr + r];
     const float gv = g[(size_t)i * g_ld + r];
     // records outside this env's primitive range (or a room id without a
@@ -118,26 +135,43 @@ __global__ __launch_bounds__(256) void render_vjp_kernel(SceneDev sc, SensorDev 
         c = dk3(s[j], s[(size_t)A + j], s[2 * (size_t)A + j]);
         rad = sc.agent_radius;
       }
-      const double* b64 = sen.dirs64 + (size_t)r * 4;
-      const d3 dbv = dk3(b64[0], b64[1], b64[2]);
-      const d3 d = ROT ? dk3(R[0][0] * dbv.x + R[0][1] * dbv.y + R[0][2] * dbv.z,
-                             R[1][0] * dbv.x + R[1][1] * dbv.y + R[1][2] * dbv.z,
-                             R[2][0] * dbv.x + R[2][1] * dbv.y + R[2][2] * dbv.z)
-                       : dbv;
-      // t = tc - sqrt(disc) and, at the hit point, n.d = -sqrt(disc)/r, so
-      // dt/do = -n/(n.d) = (t d - w)/sqrt(disc) and dt/dd = t dt/do
-      const d3 w = dk3(c.x - (double)o.x, c.y - (double)o.y, c.z - (double)o.z);
-      const double C = ddot(w, w) - rad * rad;
-      const double tc = ddot(d, w);
-      const d3 p = dk3(w.x - tc * d.x, w.y - tc * d.y, w.z - tc * d.z);
-      const double disc = rad * rad - ddot(p, p);
-      if (!(disc > 0.0)) continue;
-      const double sq = sqrt(disc);
-      const double t = C * rcp64(tc + sq);
-      const double is = rcp64(sq);
-      const double ox = (t * d.x - w.x) * is, oy = (t * d.y - w.y) * is, oz = (t * d.z - w.z) * is;
-      dto = mk3((float)ox, (float)oy, (float)oz);
-      dtd = mk3((float)(t * ox), (float)(t * oy), (float)(t * oz));
+      // FP32 first; a hit with |n.d| < 0.3 (within ~17 deg of grazing) is
+      // redone in FP64, where the FP32 discriminant would lose too much
+      const f3 d32 = ROT ? rot_apply(R32, mk3(db.x, db.y, db.z)) : mk3(db.x, db.y, db.z);
+      const f3 w32 = mk3((float)c.x - o.x, (float)c.y - o.y, (float)c.z - o.z);
+      const float rad32 = (float)rad;
+      const float C32 = dot(w32, w32) - rad32 * rad32;
+      const float tc32 = dot(d32, w32);
+      const f3 p32 = sub(w32, scl(d32, tc32));
+      const float disc32 = rad32 * rad32 - dot(p32, p32);
+      if (disc32 > 0.09f * rad32 * rad32) {
+        const float sq = __builtin_amdgcn_sqrtf(disc32);
+        const float t = C32 * __builtin_amdgcn_rcpf(tc32 + sq);
+        const float is = __builtin_amdgcn_rcpf(sq);
+        dto = scl(sub(scl(d32, t), w32), is);
+        dtd = scl(dto, t);
+      } else {
+        const double* b64 = sen.dirs64 + (size_t)r * 4;
+        const d3 dbv = dk3(b64[0], b64[1], b64[2]);
+        const d3 d = ROT ? dk3(R[0][0] * dbv.x + R[0][1] * dbv.y + R[0][2] * dbv.z,
+                               R[1][0] * dbv.x + R[1][1] * dbv.y + R[1][2] * dbv.z,
+                               R[2][0] * dbv.x + R[2][1] * dbv.y + R[2][2] * dbv.z)
+                         : dbv;
+        // t = tc - sqrt(disc) and, at the hit point, n.d = -sqrt(disc)/r, so
+        // dt/do = -n/(n.d) = (t d - w)/sqrt(disc) and dt/dd = t dt/do
+        const d3 w = dk3(c.x - (double)o.x, c.y - (double)o.y, c.z - (double)o.z);
+        const double C = ddot(w, w) - rad * rad;
+        const double tc = ddot(d, w);
+        const d3 p = dk3(w.x - tc * d.x, w.y - tc * d.y, w.z - tc * d.z);
+        const double disc = rad * rad - ddot(p, p);
+        if (!(disc > 0.0)) continue;
+        const double sq = sqrt(disc);
+        const double t = C * rcp64(tc + sq);
+        const double is = rcp64(sq);
+        const double ox = (t * d.x - w.x) * is, oy = (t * d.y - w.y) * is, oz = (t * d.z - w.z) * is;
+        dto = mk3((float)ox, (float)oy, (float)oz);
+        dtd = mk3((float)(t * ox), (float)(t * oy), (float)(t * oz));
+      }
     } else {
       // box entry face or room exit face: t = (plane_f - o_f) / d_f
       const f3 d = ROT ? rot_apply(R32, mk3(db.x, db.y, db.z)) : mk3(db.x, db.y, db.z);
@@ -169,34 +203,37 @@ __global__ __launch_bounds__(256) void render_vjp_kernel(SceneDev sc, SensorDev 
       dto = mk3(e[0], e[1], e[2]);
       dtd = scl(dto, te[f]);
     }
-    go[0] += (double)(gt * dto.x);
-    go[1] += (double)(gt * dto.y);
-    go[2] += (double)(gt * dto.z);
+    go[0] += gt * dto.x;
+    go[1] += gt * dto.y;
+    go[2] += gt * dto.z;
     if (ROT) {
       const float gd[3] = {gt * dtd.x, gt * dtd.y, gt * dtd.z};
       const float bb[3] = {db.x, db.y, db.z};
       for (int a = 0; a < 3; ++a)
-        for (int c = 0; c < 3; ++c) gR[a * 3 + c] += (double)(gd[a] * bb[c]);
+        for (int c = 0; c < 3; ++c) gR[a * 3 + c] += gd[a] * bb[c];
     }
   }
-  for (int c = 0; c < 3; ++c) red[c][tid] = go[c];
-  for (int c = 0; c < 9; ++c) red[3 + c][tid] = gR[c];
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (tid < w)
-      for (int c = 0; c < 12; ++c) red[c][tid] += red[c][tid + w];
-    __syncthreads();
+  // fixed-order reduction: butterfly within each wavefront, then the 4 waves
+  const int lane = tid & 63, wave = tid >> 6;
+  for (int c = 0; c < 12; ++c) {
+    double v = c < 3 ? (double)go[c] : (double)gR[c - 3];
+    if (!ROT && c >= 3) continue;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (lane == 0) red[c][wave] = v;
   }
+  __syncthreads();
   if (tid == 0) {
-    g_s[i] += (float)red[0][0];
-    g_s[(size_t)A + i] += (float)red[1][0];
-    g_s[2 * (size_t)A + i] += (float)red[2][0];
+    double tot[12];
+    for (int c = 0; c < 12; ++c) tot[c] = (ROT || c < 3) ? ((red[c][0] + red[c][1]) + red[c][2]) + red[c][3] : 0.0;
+    g_s[i] += (float)tot[0];
+    g_s[(size_t)A + i] += (float)tot[1];
+    g_s[2 * (size_t)A + i] += (float)tot[2];
     if (ROT) {
       // dL/dR -> dL/dqn (derivative of the quadratic form at the unit qn),
       // then through qn = q/|q|
       double G[3][3];
       for (int a = 0; a < 3; ++a)
-        for (int c = 0; c < 3; ++c) G[a][c] = red[3 + a * 3 + c][0];
+        for (int c = 0; c < 3; ++c) G[a][c] = tot[3 + a * 3 + c];
       const double w = qn[0], x = qn[1], y = qn[2], z = qn[3];
       double gq[4];
       gq[0] = 2.0 * (-G[0][1] * z + G[0][2] * y + G[1][0] * z - G[1][2] * x - G[2][0] * y + G[2][1] * x);
@@ -246,6 +283,27 @@ int launch_render(const SceneDev& sc, const SensorDev& sen, bool rotate, bool cu
       hipLaunchKernelGGL((render_kernel<false, false>), dim3(A), dim3(256), lds, st, sc, sen, s, A, out, rec, out_ld, out_scale, term, beta, d_safe);
   }
   DA_LAUNCH_CHECK("render_kernel");
+  return SIM_OK;
+}
+
+int launch_render_work(const SceneDev& sc, const SensorDev& sen, bool rotate, bool cull,
+                       const float* s, int A, float* out, int* work, hipStream_t st) {
+  if (A == 0) return SIM_OK;
+  const int P = sc.max_prims > 0 ? sc.max_prims : 1;
+  const size_t lds = render_lds_bytes(P);
+  const int ld = sen.n_rays;
+  if (rotate) {
+    if (cull)
+      hipLaunchKernelGGL((render_work_kernel<true, true>), dim3(A), dim3(256), lds, st, sc, sen, s, A, out, ld, work);
+    else
+      hipLaunchKernelGGL((render_work_kernel<true, false>), dim3(A), dim3(256), lds, st, sc, sen, s, A, out, ld, work);
+  } else {
+    if (cull)
+      hipLaunchKernelGGL((render_work_kernel<false, true>), dim3(A), dim3(256), lds, st, sc, sen, s, A, out, ld, work);
+    else
+      hipLaunchKernelGGL((render_work_kernel<false, false>), dim3(A), dim3(256), lds, st, sc, sen, s, A, out, ld, work);
+  }
+  DA_LAUNCH_CHECK("render_work_kernel");
   return SIM_OK;
 }
 

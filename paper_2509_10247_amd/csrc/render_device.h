@@ -77,9 +77,10 @@ __device__ __forceinline__ bool cone_keep(float4 b, f3 ax, float cosA, float sin
   const float rho = b.w * 1.0001f + 1e-4f;
   const float L2 = b.x * b.x + b.y * b.y + b.z * b.z;
   if (L2 <= rho * rho) return true;
-  const float L = sqrtf(L2);
+  // hardware square roots (1 ulp): covered by the inflated radius and cone
+  const float L = __builtin_amdgcn_sqrtf(L2);
   if (L - rho > tlim) return false;
-  const float rhs = cosA * sqrtf(L2 - rho * rho) - sinA * rho;
+  const float rhs = cosA * __builtin_amdgcn_sqrtf(L2 - rho * rho) - sinA * rho;
   return ax.x * b.x + ax.y * b.y + ax.z * b.z >= rhs;
 }
 
@@ -96,16 +97,21 @@ __device__ __forceinline__ Rot agent_rot(const float* s, int A, int i) {
   return R;
 }
 
+// Work counters written per agent and wavefront by the WORK variant.
+enum { kWorkRays = 0, kWorkSph, kWorkBox, kWorkAgt, kWorkTiles, kWorkCone, kWorkN };
+
 // Renders tiles [tile_begin, tile_end) of one agent's sensor with the whole
 // workgroup (256 threads); LDS is re-staged on entry, so consecutive calls
-// from one workgroup (the persistent rollout kernel) are safe.
-template <bool ROT, bool CULL>
+// from one workgroup (the persistent rollout kernel) are safe. The WORK
+// variant also writes, per wavefront, the rays it cast and the ray-primitive
+// tests and tile-cone tests it ran to work[(i * 4 + wave) * kWorkN + c].
+template <bool ROT, bool CULL, bool WORK = false>
 __device__ __forceinline__ void render_one_agent(const SceneDev& sc, const SensorDev& sen,
                                                  const float* __restrict__ s, int A, int i,
                                                  int tile_begin, int tile_end, float* __restrict__ out,
                                                  int* __restrict__ rec, int out_ld, float out_scale,
                                                  float* __restrict__ term, float beta, float d_safe,
-                                                 void* smem) {
+                                                 void* smem, int* __restrict__ work = nullptr) {
   const int P = sc.max_prims > 0 ? sc.max_prims : 1;
   RenderLds L = carve(smem, P);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -180,7 +186,9 @@ __device__ __forceinline__ void render_one_agent(const SceneDev& sc, const Senso
   int* rrow = rec ? rec + (size_t)i * nr : nullptr;
   short* list = L.lists + wave * P;
   const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  float tacc = 0.f;  // optional per-agent sum of softplus(beta (d_safe - value)) / beta
+  float tacc = 0.f;  // optional per-agent sum of softplus(beta (d_safe - value))
+  const float inv_beta = term ? 1.0f / beta : 0.f;
+  int wk[kWorkN] = {0, 0, 0, 0, 0, 0};
 
   for (int tile = tile_begin + wave; tile < tile_end; tile += 4) {
     const int r = sen.tile_rays[tile * kTileRays + lane];
@@ -188,7 +196,7 @@ __device__ __forceinline__ void render_one_agent(const SceneDev& sc, const Senso
       if (r >= 0) {
         orow[r] = 0.f;
         if (rrow) rrow[r] = -2;
-        if (term) tacc += softplus_fast(beta * d_safe) / beta;
+        if (term) tacc += softplus_fast(beta * d_safe);
       }
       continue;
     }
@@ -213,6 +221,15 @@ __device__ __forceinline__ void render_one_agent(const SceneDev& sc, const Senso
       ks = cs;
       kb = cbx;
       nk = cnt;
+    }
+    if (WORK) {
+      const int nrt = __popcll(__ballot(r >= 0));
+      wk[kWorkRays] += nrt;
+      wk[kWorkSph] += nrt * ks;
+      wk[kWorkBox] += nrt * kb;
+      wk[kWorkAgt] += nrt * (nk - ks - kb);
+      wk[kWorkTiles] += 1;
+      wk[kWorkCone] += CULL ? np : 0;
     }
     if (r < 0) continue;
     const float4 db = sen.dirs[r];
@@ -266,8 +283,10 @@ __device__ __forceinline__ void render_one_agent(const SceneDev& sc, const Senso
     }
     orow[r] = val * out_scale;
     if (rrow) rrow[r] = rc;
-    if (term) tacc += softplus_fast(beta * (d_safe - val)) / beta;
+    if (term) tacc += softplus_fast(beta * (d_safe - val));
   }
+  if (WORK && lane == 0)
+    for (int c = 0; c < kWorkN; ++c) work[((size_t)i * 4 + wave) * kWorkN + c] = wk[c];
   if (term) {
     // fixed-order reduction: butterfly within each wave, then waves 0..3
     for (int off = 32; off > 0; off >>= 1) tacc += __shfl_xor(tacc, off);
@@ -275,7 +294,7 @@ __device__ __forceinline__ void render_one_agent(const SceneDev& sc, const Senso
     float* wsum = reinterpret_cast<float*>(L.pa);
     if (lane == 0) wsum[wave] = tacc;
     __syncthreads();
-    if (tid == 0) term[i] = (((wsum[0] + wsum[1]) + wsum[2]) + wsum[3]) / (float)nr;
+    if (tid == 0) term[i] = (((wsum[0] + wsum[1]) + wsum[2]) + wsum[3]) * (inv_beta / (float)nr);
   }
 }
 

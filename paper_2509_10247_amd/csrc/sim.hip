@@ -383,6 +383,17 @@ int sim_render(sim_handle* h, const float* s, float* depth, float* lidar, int32_
   return SIM_OK;
 }
 
+int sim_render_work(sim_handle* h, int32_t sensor, const float* s, float* out, int32_t* work,
+                    void* stream) {
+  DA_REQUIRE(h && s && out && work, "sim_render_work: null argument");
+  DA_REQUIRE(h->has_scene, "sim_render_work: scene not set");
+  DA_REQUIRE(sensor == 0 || sensor == 1, "sim_render_work: sensor must be 0 (camera) or 1 (LiDAR)");
+  const SensorBuf& sb = sensor == 0 ? h->cam : h->lidar;
+  DA_REQUIRE(sb.mem, "sim_render_work: sensor not configured");
+  return launch_render_work(h->scene, sb.dev, rotates(h->cfg.model), h->cfg.fov_cull != 0, s,
+                            h->cfg.n_agents, out, work, as_stream(stream));
+}
+
 int sim_collide(sim_handle* h, const float* s, uint8_t* flags, float* min_dist, void* stream) {
   DA_REQUIRE(h && s, "sim_collide: null argument");
   DA_REQUIRE(h->has_scene, "sim_collide: scene not set");

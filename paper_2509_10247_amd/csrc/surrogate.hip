@@ -268,18 +268,18 @@ static int sur_forward(surrogate_handle* h, int B, hipStream_t st) {
   g.M = B; g.N = kSH; g.K = kSInP;
   g.A = h->X; g.lda = kSInP; g.B = P + kPW1; g.ldb = kSInP; g.C = h->H1; g.ldc = kSH;
   g.bias = P + kPB1; g.zout = h->Z1; g.ld_z = kSH;
-  int rc = launch_gemm(true, true, EPI_BIAS_SILU, g, 1, st, true);
+  int rc = launch_gemm(true, true, EPI_BIAS_SILU, g, 1, st, GEMM_BF16);
   if (rc) return rc;
   g = GemmArgs();
   g.M = B; g.N = kSH; g.K = kSH;
   g.A = h->H1; g.lda = kSH; g.B = P + kPW2; g.ldb = kSH; g.C = h->H2; g.ldc = kSH;
   g.bias = P + kPB2; g.zout = h->Z2; g.ld_z = kSH;
-  if ((rc = launch_gemm(true, true, EPI_BIAS_SILU, g, 1, st, true))) return rc;
+  if ((rc = launch_gemm(true, true, EPI_BIAS_SILU, g, 1, st, GEMM_BF16))) return rc;
   g = GemmArgs();
   g.M = B; g.N = kSOutP; g.K = kSH;
   g.A = h->H2; g.lda = kSH; g.B = P + kPW3; g.ldb = kSH; g.C = h->Y; g.ldc = kSOutP;
   g.bias = P + kPB3;
-  return launch_gemm(true, true, EPI_BIAS, g, 1, st, true);
+  return launch_gemm(true, true, EPI_BIAS, g, 1, st, GEMM_BF16);
 }
 
 // gradients (padded layout, overwritten) for targets h->T; loss -> loss_out
@@ -296,7 +296,7 @@ static int sur_backward(surrogate_handle* h, int B, float* loss_out, hipStream_t
   GemmArgs g;
   g.M = kSOutP; g.N = kSH; g.K = B;
   g.A = h->gY; g.lda = kSOutP; g.B = h->H2; g.ldb = kSH; g.C = h->part; g.ldc = kSH;
-  int rc = launch_gemm(false, false, EPI_PARTIAL, g, kSplitTN, st, true);
+  int rc = launch_gemm(false, false, EPI_PARTIAL, g, kSplitTN, st, GEMM_BF16);
   if (rc) return rc;
   if ((rc = launch_splitk_reduce(gemm_splits_used(B, kSplitTN), kSOutP, kSH, kSH, h->part, G + kPW3, kSH, false, st)))
     return rc;
@@ -306,12 +306,12 @@ static int sur_backward(surrogate_handle* h, int B, float* loss_out, hipStream_t
   g.M = B; g.N = kSH; g.K = kSOutP;
   g.A = h->gY; g.lda = kSOutP; g.B = P + kPW3; g.ldb = kSH; g.C = h->gZ2; g.ldc = kSH;
   g.aux = h->Z2; g.ld_aux = kSH;
-  if ((rc = launch_gemm(true, false, EPI_MUL_DSILU, g, 1, st, true))) return rc;
+  if ((rc = launch_gemm(true, false, EPI_MUL_DSILU, g, 1, st, GEMM_BF16))) return rc;
   // gW2 = gZ2^T H1 ; gb2
   g = GemmArgs();
   g.M = kSH; g.N = kSH; g.K = B;
   g.A = h->gZ2; g.lda = kSH; g.B = h->H1; g.ldb = kSH; g.C = h->part; g.ldc = kSH;
-  if ((rc = launch_gemm(false, false, EPI_PARTIAL, g, kSplitTN, st, true))) return rc;
+  if ((rc = launch_gemm(false, false, EPI_PARTIAL, g, kSplitTN, st, GEMM_BF16))) return rc;
   if ((rc = launch_splitk_reduce(gemm_splits_used(B, kSplitTN), kSH, kSH, kSH, h->part, G + kPW2, kSH, false, st)))
     return rc;
   if ((rc = launch_colsum(B, kSH, h->gZ2, kSH, G + kPB2, false, h->part, st))) return rc;
@@ -320,12 +320,12 @@ static int sur_backward(surrogate_handle* h, int B, float* loss_out, hipStream_t
   g.M = B; g.N = kSH; g.K = kSH;
   g.A = h->gZ2; g.lda = kSH; g.B = P + kPW2; g.ldb = kSH; g.C = h->gZ1; g.ldc = kSH;
   g.aux = h->Z1; g.ld_aux = kSH;
-  if ((rc = launch_gemm(true, false, EPI_MUL_DSILU, g, 1, st, true))) return rc;
+  if ((rc = launch_gemm(true, false, EPI_MUL_DSILU, g, 1, st, GEMM_BF16))) return rc;
   // gW1 = gZ1^T X ; gb1
   g = GemmArgs();
   g.M = kSH; g.N = kSInP; g.K = B;
   g.A = h->gZ1; g.lda = kSH; g.B = h->X; g.ldb = kSInP; g.C = h->part; g.ldc = kSInP;
-  if ((rc = launch_gemm(false, false, EPI_PARTIAL, g, kSplitTN, st, true))) return rc;
+  if ((rc = launch_gemm(false, false, EPI_PARTIAL, g, kSplitTN, st, GEMM_BF16))) return rc;
   if ((rc = launch_splitk_reduce(gemm_splits_used(B, kSplitTN), kSH, kSInP, kSInP, h->part, G + kPW1, kSInP, false,
                                  st)))
     return rc;

@@ -1,6 +1,7 @@
-"""GPU parity of the policy MLP (FP32 MFMA) and of BPTT through the rollout
-(Sec. III-A, Eq. 5) against the FP64 oracle, through the C ABI; bitwise
-invariance of the gradient to the checkpoint period."""
+"""GPU parity of the policy MLP (FP32 MFMA, and FP32 recovered from three
+BF16 MFMA products) and of BPTT through the rollout (Sec. III-A, Eq. 5)
+against the FP64 oracle, through the C ABI; bitwise invariance of the
+gradient to the checkpoint period."""
 import numpy as np
 import pytest
 import torch
@@ -21,46 +22,57 @@ def _theta(seed):
     return wl.flatten_mlp(wl.mlp_init(rng, wl.POLICY_DIMS))
 
 
-def test_policy_forward_backward_matches_fp64():
+FP32, X3 = 0, 1  # POLICY_GEMM_FP32, POLICY_GEMM_BF16X3
+
+
+@pytest.mark.parametrize("mode", [FP32, X3])
+def test_policy_forward_backward_matches_fp64(mode):
     from paper_2509_10247_amd import _lib
     B = 300  # two full 128-row tiles and a ragged tail
-    print_case("policy_mlp", B=B)
+    print_case("policy_mlp", B=B, gemm=mode)
     rng = np.random.default_rng(0)
     theta = _theta(1)
     x = rng.uniform(0, 1, (B, 3081)).astype(np.float32)
     x[:, 3072:] = rng.normal(size=(B, 9))
     gy = rng.normal(size=(B, 4)).astype(np.float32)
     th, xt, y = cuda(theta), cuda(x), torch.empty(B, 4, device="cuda")
-    _lib.policy_forward(th, xt, y)
+    _lib.policy_forward(th, xt, y, mode)
     gth, gx = torch.empty_like(th), torch.empty_like(xt)
-    _lib.policy_backward(th, xt, cuda(gy), gth, gx)
+    _lib.policy_backward(th, xt, cuda(gy), gth, gx, mode)
     thd = torch.tensor(theta.astype(np.float64), requires_grad=True)
     xd = torch.tensor(x.astype(np.float64), requires_grad=True)
     yd = opol.mlp_tanh(opol.unflatten(thd, wl.POLICY_DIMS), xd)
     (yd * torch.tensor(gy.astype(np.float64))).sum().backward()
     assert (f64(y) - yd.detach()).abs().max() < 2e-5
+    # The three-product split drops lo*lo, about 2^-16 of each product (FP32
+    # keeps 2^-24), so entries that nearly cancel over the batch miss a
+    # per-entry 1e-3 test more often; the per-block norm bar is unchanged.
+    min_comp = 0.999 if mode == FP32 else 0.995
     for name, a, b in BLOCKS:
         ok, rel, comp = grad_close(f64(gth)[a:b], thd.grad[a:b])
-        assert ok and comp > 0.999, f"{name}: rel {rel:.2e} comp {comp:.4f}"
+        print(f"  {name}: rel err {rel:.2e}, component pass {comp:.4f}")
+        assert ok and comp > min_comp, f"{name}: rel {rel:.2e} comp {comp:.4f}"
     ok, rel, _ = grad_close(f64(gx), xd.grad)
     assert ok, f"g_x rel {rel:.2e}"
 
 
-def _engine(wk, T, K, store=True):
+def _engine(wk, T, K, store=True, mode=FP32):
     from paper_2509_10247_amd import bptt, env
     e = env.from_workload(wk)
-    return e, bptt.BpttEngine(e, T, K, store_activations=store)
+    return e, bptt.BpttEngine(e, T, K, store_activations=store, policy_gemm=mode)
 
 
-@pytest.mark.parametrize("model,store", [(wl.RB13, True), (wl.PM9, True), (wl.RB13, False)])
-def test_bptt_gradient_matches_oracle(model, store):
+@pytest.mark.parametrize("model,store,mode", [(wl.RB13, True, FP32), (wl.PM9, True, FP32),
+                                              (wl.RB13, False, FP32), (wl.RB13, True, X3),
+                                              (wl.PM9, False, X3)])
+def test_bptt_gradient_matches_oracle(model, store, mode):
     """8 envs, horizon 32, checkpoints every 8 steps: loss, policy gradient
     (per parameter block) and initial-state gradient vs the FP64 oracle's
     autograd gradient (itself pinned to central FD with h = 1e-3)."""
     wk = wl.bptt(seed=11, n_envs=8, T=32, model=model)
-    print_case("bptt_grad", model=model, A=8, T=32, K=8)
+    print_case("bptt_grad", model=model, A=8, T=32, K=8, store=store, gemm=mode)
     theta = _theta(12)
-    e, eng = _engine(wk, 32, 8, store)
+    e, eng = _engine(wk, 32, 8, store, mode)
     th, s0, goal = cuda(theta), cuda(wk.state0), cuda(wk.goal)
     loss = eng.forward(th, s0, goal)
     g_th, g_s0 = eng.backward()
@@ -76,14 +88,15 @@ def test_bptt_gradient_matches_oracle(model, store):
     assert ok, f"g_s0: rel {rel:.2e}"
 
 
-def test_bptt_checkpoint_period_is_bitwise_invariant():
+@pytest.mark.parametrize("mode", [FP32, X3])
+def test_bptt_checkpoint_period_is_bitwise_invariant(mode):
     wk = wl.bptt(seed=13, n_envs=96, T=12, model=wl.RB13)
-    print_case("bptt_ckpt", A=96, T=12)
+    print_case("bptt_ckpt", A=96, T=12, gemm=mode)
     theta = _theta(14)
     th, s0, goal = cuda(theta), cuda(wk.state0), cuda(wk.goal)
     outs = []
     for K, store in ((1, True), (5, True), (12, True), (5, False), (1, False)):
-        e, eng = _engine(wk, 12, K, store)
+        e, eng = _engine(wk, 12, K, store, mode)
         loss = eng.forward(th, s0, goal)
         g_th, g_s0 = eng.backward()
         outs.append((loss.clone(), g_th.clone(), g_s0.clone()))
@@ -107,7 +120,8 @@ def test_autograd_function_and_loss_scaling():
     assert torch.allclose(s0.grad, 2.0 * gs_direct, rtol=1e-6, atol=1e-12)
 
 
-def test_bptt_full_size_sampled_agents():
+@pytest.mark.parametrize("mode", [FP32, X3])
+def test_bptt_full_size_sampled_agents(mode):
     """16384 envs, T = 32, K = 8 (the benchmark launch): the initial-state
     gradient of sampled agents equals the oracle's for those agents alone
     (agents interact only through the shared policy, so agent i's s0-gradient
@@ -115,14 +129,15 @@ def test_bptt_full_size_sampled_agents():
     K = 8 / K = 32 give bitwise-equal gradients."""
     A, T = 16384, 32
     wk = wl.bptt(seed=0, n_envs=A, T=T, model=wl.RB13)
-    print_case("bptt_full", A=A, T=T, K=8)
+    print_case("bptt_full", A=A, T=T, K=8, gemm=mode)
+    from paper_2509_10247_amd import bptt
     theta = _theta(1)
     th, s0, goal = cuda(theta), cuda(wk.state0), cuda(wk.goal)
-    e, eng = _engine(wk, T, 8)
+    e, eng = _engine(wk, T, 8, True, mode)
     eng.forward(th, s0, goal)
     g8, gs8 = eng.backward()
-    eng32 = __import__("paper_2509_10247_amd.bptt", fromlist=["x"]).BpttEngine(e, T, 32,
-                                                                                store_activations=False)
+    del eng
+    eng32 = bptt.BpttEngine(e, T, 32, store_activations=False, policy_gemm=mode)
     eng32.forward(th, s0, goal)
     g32, gs32 = eng32.backward()
     assert torch.equal(g8, g32) and torch.equal(gs8, gs32)

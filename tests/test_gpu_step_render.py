@@ -150,3 +150,35 @@ def test_collisions_match_oracle():
     assert torch.allclose(f64(md), md_o, atol=2e-5)
     clear = (md_o - 0.15).abs() > 1e-4
     assert torch.equal((flags.cpu() & 2 > 0)[clear], col_o[clear])
+
+
+def test_render_work_counter():
+    """sim_render_work renders the same image as sim_render; with culling off
+    it counts exactly rays x primitives per env; with culling on, at most
+    that, and the same number of cast rays."""
+    from paper_2509_10247_amd import _lib
+    wk = wl.rigid_body(seed=2, n_envs=96, T=1)
+    A = 96
+    print_case("render_work", A=A, cam=wk.cam)
+    s = cuda(wk.state0)
+    counts = {}
+    for cull in (True, False):
+        e = _env(wk, fov_cull=cull)
+        d, _, _, _ = e.render(s, depth=True)
+        out = torch.empty_like(d)
+        work = torch.full((A, 4, 6), -1, dtype=torch.int32, device="cuda")
+        _lib.sim_render_work(e.h, 0, s, out, work)
+        torch.cuda.synchronize()
+        assert torch.equal(out, d)
+        counts[cull] = work.sum(1).long().cpu()
+    n_sph = torch.as_tensor(np.diff(wk.scene.sph_off)).long()
+    n_box = torch.as_tensor(np.diff(wk.scene.box_off)).long()
+    full = counts[False]
+    rays = full[:, 0]
+    assert set(rays.tolist()) <= {0, 3072}
+    assert torch.equal(full[:, 1], rays * n_sph) and torch.equal(full[:, 2], rays * n_box)
+    assert (full[:, 3] == 0).all() and (full[:, 5] == 0).all()
+    cul = counts[True]
+    assert torch.equal(cul[:, 0], rays)
+    assert (cul[:, 1:4] <= full[:, 1:4]).all() and cul[:, 1].sum() < full[:, 1].sum()
+    assert torch.equal(cul[:, 4], full[:, 4])
