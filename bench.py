@@ -47,15 +47,90 @@ def parse():
     p.add_argument("--ckpt", type=int, default=8)
     p.add_argument("--recompute-all", action="store_true",
                    help="keep only the K-step state checkpoints (recompute policy and step too)")
-    p.add_argument("--policy-gemm", choices=["fp32", "bf16x3"], default="bf16x3",
+    p.add_argument("--policy-gemm", choices=["fp32", "bf16x3"], default="fp32",
                    help="policy layers on FP32 MFMA, or FP32 recovered from three BF16 MFMA products")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                    help="also run a plain device copy of MIB MiB (for HBM counter scaling)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-kernel-timing", action="store_true")
-    p.add_argument("--sections", default="surrogate,uneven",
-                   help="comma list of extra sections to run after the headline: surrogate, uneven")
+    p.add_argument("--sections", default="step,render,surrogate,uneven",
+                   help="comma list of extra sections after the headline: step, render, surrogate, uneven")
     return p.parse_args()
+
+
+def step_section(seed=0, reps=20):
+    """The dynamics step alone at sizes whose working set exceeds the 256 MB
+    last-level cache: RB13 RK4 at 2^22 envs and PM6 Euler at 2^23 envs.
+    Achieved HBM bandwidth = algorithmic bytes per launch / average launch
+    time (HIP events on the launch stream)."""
+    import numpy as np
+    import torch
+    import workloads as wl
+    from paper_2509_10247_amd import env
+    out = {}
+    for name, model, integ, n, nbytes in (("rb13_rk4", wl.RB13, wl.RK4, 1 << 22, (13 + 4 + 8 + 13) * 4),
+                                          ("pm6_euler", wl.PM6, wl.EULER, 1 << 23, (6 + 3 + 6) * 4)):
+        rng = np.random.default_rng(seed)
+        p0 = wl.start_positions(rng, n, wl.ROOM_C2)
+        e = env.Env(n_envs=n, n_agents=n, model=model, integrator=integ, dt=0.01)
+        e.set_params(wl.params(rng, model, n))
+        s = torch.tensor(wl.initial_state(rng, model, p0), device="cuda")
+        a = torch.tensor(wl.actions(rng, model, n, 1)[0], device="cuda")
+        nxt = torch.empty_like(s)
+        for _ in range(3):
+            e.step(s, a, out=nxt)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(reps):
+            e.step(s, a, out=nxt)
+            s, nxt = nxt, s
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / reps
+        assert torch.isfinite(s).all()
+        gbs = n * nbytes / (ms * 1e-3) / 1e9
+        out[name] = {"envs": n, "bytes_per_env_step": nbytes, "avg_launch_ms": round(ms, 4),
+                     "env_steps_per_s": round(n / (ms * 1e-3), 1),
+                     "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM / 1e9,
+                                  "unit": "GB/s", "frac": round(gbs * 1e9 / PEAK_HBM, 4)}}
+        del e, s, nxt, a
+        torch.cuda.empty_cache()
+    return out
+
+
+def render_section(seed=0, reps=10):
+    """Camera render alone on the 4096-env rigid-body scene (64x48, 10 m,
+    24 spheres + 16 boxes + room per env): rays/s and VALU FLOP/s from the
+    counted work (sim_render_work) / average launch time."""
+    import torch
+    import workloads as wl
+    from paper_2509_10247_amd import env
+    wk = wl.rigid_body(seed=seed, n_envs=4096, T=1)
+    e = env.from_workload(wk)
+    s = torch.tensor(wk.state0, device="cuda")
+    A = wk.scene.n_agents
+    d = torch.empty(A, 48, 64, device="cuda")
+    h = torch.empty(A, 48, 64, dtype=torch.int32, device="cuda")
+    from paper_2509_10247_amd import _lib
+    for _ in range(3):
+        _lib.sim_render(e.h, s, d, None, h, None)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        _lib.sim_render(e.h, s, d, None, h, None)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    flops, cnt = render_work_flops(e, s, term=False)
+    ach = flops / (ms * 1e-3)
+    return {"envs": A, "rays_per_launch": A * 3072, "avg_launch_ms": round(ms, 4),
+            "rays_per_s": round(A * 3072 / (ms * 1e-3), 1), "work_per_launch": cnt,
+            "roofline": {"bound": "alu", "achieved": round(ach / 1e12, 2), "peak": PEAK_FP32_VALU / 1e12,
+                         "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_VALU, 4),
+                         "frac_of_nonpacked_fp32": round(ach / PEAK_FP32_VALU_NONPACKED, 4),
+                         "flops_per_launch": flops}}
 
 
 def uneven_section(T=128, reps=3, seed=0):
@@ -364,6 +439,10 @@ def main():
         "kernel_breakdown": breakdown,
     }
     sections = [x for x in args.sections.split(",") if x]
+    if "step" in sections:
+        line["step"] = step_section()
+    if "render" in sections:
+        line["render"] = render_section()
     if "surrogate" in sections:
         line["surrogate"] = surrogate_section()
     if "uneven" in sections:

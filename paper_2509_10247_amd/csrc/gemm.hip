@@ -271,31 +271,64 @@ static int gemm_bf16_t(const GemmArgs& g, int splits, hipStream_t st) {
 // of Ootomo & Yokota (2022); its relative error (~1e-5) sits far inside the
 // gradient tolerance while the BF16 matrix rate is 16x the FP32 one on gfx950.
 // ---------------------------------------------------------------------------
+// Split-precision staging: thread t owns 16 consecutive k of tile row
+// m = t % 128 (k offset 16 * (t / 128)). K-major operands come in as four
+// float4 per thread; M-major operands as 16 scalar loads that are coalesced
+// across the wavefront's consecutive rows. Each value x is split into
+// hi = bf16(x) and lo = bf16(x - hi) and the thread's run is written to the
+// hi and lo planes as two 16-byte stores each; the row pitch (BKP bf16 =
+// five 16-byte units) keeps these stores and the MFMA fragment reads free of
+// bank conflicts.
 template <bool KMAJ>
-__device__ __forceinline__ void store_tile_split(uint16_t* H, uint16_t* L, const float4 (&reg)[4]) {
+__device__ __forceinline__ void load_run(const float* __restrict__ P, int ld, int rows, int kend, int r0,
+                                         int k0, float (&v)[16]) {
   const int t = threadIdx.x;
+  const int m = r0 + (t & 127), k = k0 + (t >> 7) * 16;
+  if (KMAJ) {
+    const float* row = P + (size_t)m * ld;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const float x[4] = {reg[i].x, reg[i].y, reg[i].z, reg[i].w};
-    uint32_t hb[4], lb[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      hb[j] = bf16_bits(x[j]);
-      lb[j] = bf16_bits(x[j] - __uint_as_float(hb[j] << 16));
-    }
-    if (KMAJ) {
-      const int row = (t >> 3) + 32 * i, k = (t & 7) * 4;
-      *reinterpret_cast<uint2*>(H + row * BKP + k) = make_uint2(hb[0] | (hb[1] << 16), hb[2] | (hb[3] << 16));
-      *reinterpret_cast<uint2*>(L + row * BKP + k) = make_uint2(lb[0] | (lb[1] << 16), lb[2] | (lb[3] << 16));
-    } else {
-      const int kk = (t >> 5) + 8 * i, m = (t & 31) * 4;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        H[(m + j) * BKP + kk] = (uint16_t)hb[j];
-        L[(m + j) * BKP + kk] = (uint16_t)lb[j];
+    for (int q = 0; q < 4; ++q) {
+      const int kk = k + 4 * q;
+      float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (m < rows) {
+        if (kk + 3 < kend) {
+          x = *reinterpret_cast<const float4*>(row + kk);
+        } else {
+          if (kk < kend) x.x = row[kk];
+          if (kk + 1 < kend) x.y = row[kk + 1];
+          if (kk + 2 < kend) x.z = row[kk + 2];
+        }
       }
+      v[4 * q] = x.x;
+      v[4 * q + 1] = x.y;
+      v[4 * q + 2] = x.z;
+      v[4 * q + 3] = x.w;
     }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+      v[j] = (m < rows && k + j < kend) ? P[(size_t)(k + j) * ld + m] : 0.f;
   }
+}
+
+__device__ __forceinline__ void store_run_split(uint16_t* H, uint16_t* L, const float (&v)[16]) {
+  const int t = threadIdx.x;
+  uint32_t hp[8], lp[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const uint32_t h0 = bf16_bits(v[2 * j]), h1 = bf16_bits(v[2 * j + 1]);
+    const uint32_t l0 = bf16_bits(v[2 * j] - __uint_as_float(h0 << 16));
+    const uint32_t l1 = bf16_bits(v[2 * j + 1] - __uint_as_float(h1 << 16));
+    hp[j] = h0 | (h1 << 16);
+    lp[j] = l0 | (l1 << 16);
+  }
+  const int off = (t & 127) * BKP + (t >> 7) * 16;
+  uint4* h4 = reinterpret_cast<uint4*>(H + off);
+  uint4* l4 = reinterpret_cast<uint4*>(L + off);
+  h4[0] = make_uint4(hp[0], hp[1], hp[2], hp[3]);
+  h4[1] = make_uint4(hp[4], hp[5], hp[6], hp[7]);
+  l4[0] = make_uint4(lp[0], lp[1], lp[2], lp[3]);
+  l4[1] = make_uint4(lp[4], lp[5], lp[6], lp[7]);
 }
 
 template <bool AK, bool BK_, int EPI>
@@ -316,20 +349,20 @@ __global__ __launch_bounds__(256) void gemm_x3_kernel(GemmArgs g) {
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int i = 0; i < 16; ++i) acc[a][b][i] = 0.f;
-  float4 ra[4], rb[4];
+  float va[16], vb[16];
   if (kbeg < kend) {
-    load_tile<AK>(g.A, g.lda, g.M, kend, m0, kbeg, ra);
-    load_tile<BK_>(g.B, g.ldb, g.N, kend, n0, kbeg, rb);
+    load_run<AK>(g.A, g.lda, g.M, kend, m0, kbeg, va);
+    load_run<BK_>(g.B, g.ldb, g.N, kend, n0, kbeg, vb);
   }
   const int col = lane & 31, half = lane >> 5;
   for (int k0 = kbeg; k0 < kend; k0 += GBK) {
     __syncthreads();
-    store_tile_split<AK>(Ah, Al, ra);
-    store_tile_split<BK_>(Bh, Bl, rb);
+    store_run_split(Ah, Al, va);
+    store_run_split(Bh, Bl, vb);
     __syncthreads();
     if (k0 + GBK < kend) {
-      load_tile<AK>(g.A, g.lda, g.M, kend, m0, k0 + GBK, ra);
-      load_tile<BK_>(g.B, g.ldb, g.N, kend, n0, k0 + GBK, rb);
+      load_run<AK>(g.A, g.lda, g.M, kend, m0, k0 + GBK, va);
+      load_run<BK_>(g.B, g.ldb, g.N, kend, n0, k0 + GBK, vb);
     }
 #pragma unroll
     for (int s = 0; s < GBK / 16; ++s) {
@@ -342,14 +375,19 @@ __global__ __launch_bounds__(256) void gemm_x3_kernel(GemmArgs g) {
         bh[x] = *reinterpret_cast<const bf16x8*>(Bh + (wn + 32 * x + col) * BKP + ko);
         bl[x] = *reinterpret_cast<const bf16x8*>(Bl + (wn + 32 * x + col) * BKP + ko);
       }
+      // small terms first, then hi * hi (lo * lo, about 2^-16 of the product, dropped)
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
           acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
           acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
-          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
         }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
     }
   }
   gemm_epilogue<EPI>(g, acc, m0, n0, wm, wn, col, half);

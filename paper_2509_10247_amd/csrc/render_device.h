@@ -13,7 +13,8 @@ constexpr float kInf = __builtin_huge_valf();
 struct RenderLds {
   float4* pa;  // sphere (w, r^2) | box lo'
   float4* pb;  // sphere (C, ...) | box hi'
-  float4* pc;  // bounding sphere (centre - o, radius); radius < 0: never hit
+  float4* pc;  // bounding sphere: (centre - o, sqrt(L^2 - rho^2))
+  float2* pd;  // (rho, L - rho); rho < 0: never hit
   short* lists;
   int* flag;
 };
@@ -23,13 +24,15 @@ __device__ __forceinline__ RenderLds carve(void* base, int P) {
   L.pa = reinterpret_cast<float4*>(base);
   L.pb = L.pa + P;
   L.pc = L.pb + P;
-  L.flag = reinterpret_cast<int*>(L.pc + P);
+  L.pd = reinterpret_cast<float2*>(L.pc + P);
+  L.flag = reinterpret_cast<int*>(L.pd + P);
   L.lists = reinterpret_cast<short*>(L.flag + 4);
   return L;
 }
 
 inline size_t render_lds_bytes(int P) {
-  return (size_t)P * 3 * sizeof(float4) + 4 * sizeof(int) + (size_t)4 * P * sizeof(short) + 16;
+  return (size_t)P * (3 * sizeof(float4) + sizeof(float2)) + 4 * sizeof(int) +
+         (size_t)4 * P * sizeof(short) + 16;
 }
 
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
@@ -69,19 +72,44 @@ __device__ __forceinline__ float room_t(f3 inv, f3 rlo, f3 rhi) {
   return fminf(fminf(tx, ty), tz);
 }
 
-// Conservative cone + range test of a bounding sphere (centre w, radius rho)
-// against a tile cone (world axis ax, cos/sin of the half-angle) and range
-// limit: the sphere meets the cone iff angle(ax, w) <= alpha + asin(rho/|w|).
-__device__ __forceinline__ bool cone_keep(float4 b, f3 ax, float cosA, float sinA, float tlim) {
-  if (b.w < 0.f) return false;
-  const float rho = b.w * 1.0001f + 1e-4f;
-  const float L2 = b.x * b.x + b.y * b.y + b.z * b.z;
-  if (L2 <= rho * rho) return true;
-  // hardware square roots (1 ulp): covered by the inflated radius and cone
+// Conservative cone + range test of a bounding sphere against a tile cone
+// (world axis ax, cos / sin of the half-angle alpha) and range limit. The
+// sphere (centre w, radius rho, L = |w|) meets the cone iff
+// angle(ax, w) <= alpha + asin(rho / L), i.e.
+// ax.w >= cos(alpha) sqrt(L^2 - rho^2) - sin(alpha) rho. The per-primitive
+// part is precomputed by cone_prep (once per agent); the radius is inflated to
+// cover the hardware square roots (1 ulp) and the rounding of the test.
+struct ConePrim {
+  float4 c;  // (w, sqrt(L^2 - rho^2)), -inf when the origin is inside
+  float2 d;  // (rho, L - rho), -inf when inside; rho < 0: never kept
+};
+
+__device__ __forceinline__ ConePrim cone_prep(f3 w, float radius) {
+  ConePrim p;
+  if (radius < 0.f) {
+    p.c = make_float4(0.f, 0.f, 0.f, 0.f);
+    p.d = make_float2(-1.f, 0.f);
+    return p;
+  }
+  const float rho = radius * 1.0001f + 1e-4f;
+  const float L2 = w.x * w.x + w.y * w.y + w.z * w.z;
+  if (L2 <= rho * rho) {
+    p.c = make_float4(w.x, w.y, w.z, -kInf);
+    p.d = make_float2(rho, -kInf);
+    return p;
+  }
   const float L = __builtin_amdgcn_sqrtf(L2);
-  if (L - rho > tlim) return false;
-  const float rhs = cosA * __builtin_amdgcn_sqrtf(L2 - rho * rho) - sinA * rho;
-  return ax.x * b.x + ax.y * b.y + ax.z * b.z >= rhs;
+  p.c = make_float4(w.x, w.y, w.z, __builtin_amdgcn_sqrtf(L2 - rho * rho));
+  p.d = make_float2(rho, L - rho);
+  return p;
+}
+
+// Written so that the -inf (inside) entries keep the primitive.
+__device__ __forceinline__ bool cone_keep(float4 c, float2 d, f3 ax, float cosA, float sinA,
+                                          float tlim) {
+  if (d.x < 0.f || d.y > tlim) return false;
+  const float rhs = cosA * c.w - sinA * d.x;
+  return !(ax.x * c.x + ax.y * c.y + ax.z * c.z < rhs);
 }
 
 template <bool ROT>
@@ -140,7 +168,9 @@ __device__ __forceinline__ void render_one_agent(const SceneDev& sc, const Senso
       const float C = dot(w, w) - r2;
       L.pa[k] = make_float4(w.x, w.y, w.z, r2);
       L.pb[k] = make_float4(C, 0.f, 0.f, 0.f);
-      L.pc[k] = make_float4(w.x, w.y, w.z, c.w);
+      const ConePrim cp = cone_prep(w, c.w);
+      L.pc[k] = cp.c;
+      L.pd[k] = cp.d;
       ins |= C <= 0.f;
     } else if (k < ns + nb) {
       const float* b = sc.box + (size_t)(b0 + k - ns) * 6;
@@ -148,22 +178,28 @@ __device__ __forceinline__ void render_one_agent(const SceneDev& sc, const Senso
       const f3 hi = mk3(b[0] + b[3] - o.x, b[1] + b[4] - o.y, b[2] + b[5] - o.z);
       L.pa[k] = make_float4(lo.x, lo.y, lo.z, 0.f);
       L.pb[k] = make_float4(hi.x, hi.y, hi.z, 0.f);
-      L.pc[k] = make_float4(0.5f * (lo.x + hi.x), 0.5f * (lo.y + hi.y), 0.5f * (lo.z + hi.z),
-                            sqrtf(b[3] * b[3] + b[4] * b[4] + b[5] * b[5]));
+      const ConePrim cp = cone_prep(mk3(0.5f * (lo.x + hi.x), 0.5f * (lo.y + hi.y), 0.5f * (lo.z + hi.z)),
+                                    sqrtf(b[3] * b[3] + b[4] * b[4] + b[5] * b[5]));
+      L.pc[k] = cp.c;
+      L.pd[k] = cp.d;
       ins |= (lo.x < 0.f && hi.x > 0.f && lo.y < 0.f && hi.y > 0.f && lo.z < 0.f && hi.z > 0.f);
     } else {
       const int j = a0 + (k - ns - nb);
       if (j == i) {
         L.pa[k] = make_float4(0.f, 0.f, 0.f, -1.f);
         L.pb[k] = make_float4(1.f, 0.f, 0.f, 0.f);
-        L.pc[k] = make_float4(0.f, 0.f, 0.f, -1.f);
+        const ConePrim cp = cone_prep(mk3(0.f, 0.f, 0.f), -1.f);
+        L.pc[k] = cp.c;
+        L.pd[k] = cp.d;
       } else {
         const f3 w = mk3(s[j] - o.x, s[(size_t)A + j] - o.y, s[2 * (size_t)A + j] - o.z);
         const float r2 = sc.agent_radius * sc.agent_radius;
         const float C = dot(w, w) - r2;
         L.pa[k] = make_float4(w.x, w.y, w.z, r2);
         L.pb[k] = make_float4(C, 0.f, 0.f, 0.f);
-        L.pc[k] = make_float4(w.x, w.y, w.z, sc.agent_radius);
+        const ConePrim cp = cone_prep(w, sc.agent_radius);
+        L.pc[k] = cp.c;
+        L.pd[k] = cp.d;
         ins |= C <= 0.f;
       }
     }
@@ -208,14 +244,16 @@ __device__ __forceinline__ void render_one_agent(const SceneDev& sc, const Senso
       int cnt = 0, cs = 0, cbx = 0;
       for (int base = 0; base < np; base += 64) {
         const int k = base + lane;
-        const bool keep = (k < np) && cone_keep(L.pc[k], ax, ca.w, cb.x, cb.y);
+        const bool keep = (k < np) && cone_keep(L.pc[k], L.pd[k], ax, ca.w, cb.x, cb.y);
         const unsigned long long m = __ballot(keep);
-        const unsigned long long ms = __ballot(keep && k < ns);
-        const unsigned long long mb = __ballot(keep && k >= ns && k < ns + nb);
+        // lanes of this chunk holding spheres / spheres or boxes (uniform)
+        const int rs = ns - base, rsb = ns + nb - base;
+        const unsigned long long ls = rs >= 64 ? ~0ull : (rs <= 0 ? 0ull : (1ull << rs) - 1ull);
+        const unsigned long long lsb = rsb >= 64 ? ~0ull : (rsb <= 0 ? 0ull : (1ull << rsb) - 1ull);
         if (keep) list[cnt + __popcll(m & below)] = (short)k;
         cnt += __popcll(m);
-        cs += __popcll(ms);
-        cbx += __popcll(mb);
+        cs += __popcll(m & ls);
+        cbx += __popcll(m & lsb & ~ls);
       }
       __builtin_amdgcn_wave_barrier();
       ks = cs;

@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "kernels.h"
+#include "render_device.h"
 #include "sim_internal.h"
 
 namespace da {
@@ -295,6 +296,14 @@ int sim_set_scene(sim_handle* h, const int32_t* sph_off, const float* sph, int32
     DA_REQUIRE(p <= SIM_MAX_PRIMS_PER_ENV + SIM_MAX_AGENTS_PER_ENV,
                "sim_set_scene: env %d has %d primitives", e, p);
     maxp = std::max(maxp, p);
+  }
+  {
+    int dev = 0, lds_max = 0;
+    DA_HIP(hipGetDevice(&dev));
+    DA_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    DA_REQUIRE(render_lds_bytes(maxp > 0 ? maxp : 1) <= (size_t)lds_max,
+               "sim_set_scene: %d primitives in one env need %zu B of LDS per workgroup (device: %d)",
+               maxp, render_lds_bytes(maxp), lds_max);
   }
   std::vector<int32_t> env_of(A);
   for (int e = 0; e < E; ++e)
