@@ -271,57 +271,49 @@ static int gemm_bf16_t(const GemmArgs& g, int splits, hipStream_t st) {
 // of Ootomo & Yokota (2022); its relative error (~1e-5) sits far inside the
 // gradient tolerance while the BF16 matrix rate is 16x the FP32 one on gfx950.
 // ---------------------------------------------------------------------------
-// Split-precision staging: thread t owns 16 consecutive k of tile row
-// m = t % 128 (k offset 16 * (t / 128)). K-major operands come in as four
-// float4 per thread; M-major operands as 16 scalar loads that are coalesced
-// across the wavefront's consecutive rows. Each value x is split into
-// hi = bf16(x) and lo = bf16(x - hi) and the thread's run is written to the
-// hi and lo planes as two 16-byte stores each; the row pitch (BKP bf16 =
-// five 16-byte units) keeps these stores and the MFMA fragment reads free of
-// bank conflicts.
-template <bool KMAJ>
-__device__ __forceinline__ void load_run(const float* __restrict__ P, int ld, int rows, int kend, int r0,
-                                         int k0, float (&v)[16]) {
+// Split-precision staging. Each value x is split into hi = bf16(x) and
+// lo = bf16(x - hi), written to an hi and a lo LDS plane in the MFMA fragment
+// layout [row][k] (pitch BKP). K-major operands use the coalesced load_tile
+// pattern (eight lanes per 128-byte row segment) and 8-byte stores.
+// M-major operands are loaded as 16-value k-runs of one row per thread
+// (scalar loads, coalesced across the wavefront's consecutive rows) and
+// written with 16-byte stores; the pitch (five 16-byte units) keeps these
+// stores and the fragment reads free of bank conflicts.
+__device__ __forceinline__ void split2(float a, float b, uint32_t& h, uint32_t& l) {
+  const uint32_t h0 = bf16_bits(a), h1 = bf16_bits(b);
+  const uint32_t l0 = bf16_bits(a - __uint_as_float(h0 << 16));
+  const uint32_t l1 = bf16_bits(b - __uint_as_float(h1 << 16));
+  h = h0 | (h1 << 16);
+  l = l0 | (l1 << 16);
+}
+
+__device__ __forceinline__ void store_tile_split_k(uint16_t* H, uint16_t* L, const float4 (&reg)[4]) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int off = ((t >> 3) + 32 * i) * BKP + (t & 7) * 4;
+    uint2 h, l;
+    split2(reg[i].x, reg[i].y, h.x, l.x);
+    split2(reg[i].z, reg[i].w, h.y, l.y);
+    *reinterpret_cast<uint2*>(H + off) = h;
+    *reinterpret_cast<uint2*>(L + off) = l;
+  }
+}
+
+__device__ __forceinline__ void load_run_m(const float* __restrict__ P, int ld, int rows, int kend, int r0,
+                                           int k0, float (&v)[16]) {
   const int t = threadIdx.x;
   const int m = r0 + (t & 127), k = k0 + (t >> 7) * 16;
-  if (KMAJ) {
-    const float* row = P + (size_t)m * ld;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int kk = k + 4 * q;
-      float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (m < rows) {
-        if (kk + 3 < kend) {
-          x = *reinterpret_cast<const float4*>(row + kk);
-        } else {
-          if (kk < kend) x.x = row[kk];
-          if (kk + 1 < kend) x.y = row[kk + 1];
-          if (kk + 2 < kend) x.z = row[kk + 2];
-        }
-      }
-      v[4 * q] = x.x;
-      v[4 * q + 1] = x.y;
-      v[4 * q + 2] = x.z;
-      v[4 * q + 3] = x.w;
-    }
-  } else {
-#pragma unroll
-    for (int j = 0; j < 16; ++j)
-      v[j] = (m < rows && k + j < kend) ? P[(size_t)(k + j) * ld + m] : 0.f;
-  }
+  for (int j = 0; j < 16; ++j)
+    v[j] = (m < rows && k + j < kend) ? P[(size_t)(k + j) * ld + m] : 0.f;
 }
 
 __device__ __forceinline__ void store_run_split(uint16_t* H, uint16_t* L, const float (&v)[16]) {
   const int t = threadIdx.x;
   uint32_t hp[8], lp[8];
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    const uint32_t h0 = bf16_bits(v[2 * j]), h1 = bf16_bits(v[2 * j + 1]);
-    const uint32_t l0 = bf16_bits(v[2 * j] - __uint_as_float(h0 << 16));
-    const uint32_t l1 = bf16_bits(v[2 * j + 1] - __uint_as_float(h1 << 16));
-    hp[j] = h0 | (h1 << 16);
-    lp[j] = l0 | (l1 << 16);
-  }
+  for (int j = 0; j < 8; ++j) split2(v[2 * j], v[2 * j + 1], hp[j], lp[j]);
   const int off = (t & 127) * BKP + (t >> 7) * 16;
   uint4* h4 = reinterpret_cast<uint4*>(H + off);
   uint4* l4 = reinterpret_cast<uint4*>(L + off);
@@ -330,6 +322,26 @@ __device__ __forceinline__ void store_run_split(uint16_t* H, uint16_t* L, const 
   l4[0] = make_uint4(lp[0], lp[1], lp[2], lp[3]);
   l4[1] = make_uint4(lp[4], lp[5], lp[6], lp[7]);
 }
+
+// Register staging of one operand tile in either layout.
+template <bool KMAJ>
+struct SplitStage;
+template <>
+struct SplitStage<true> {
+  float4 r[4];
+  __device__ void load(const float* P, int ld, int rows, int kend, int r0, int k0) {
+    load_tile<true>(P, ld, rows, kend, r0, k0, r);
+  }
+  __device__ void store(uint16_t* H, uint16_t* L) const { store_tile_split_k(H, L, r); }
+};
+template <>
+struct SplitStage<false> {
+  float v[16];
+  __device__ void load(const float* P, int ld, int rows, int kend, int r0, int k0) {
+    load_run_m(P, ld, rows, kend, r0, k0, v);
+  }
+  __device__ void store(uint16_t* H, uint16_t* L) const { store_run_split(H, L, v); }
+};
 
 template <bool AK, bool BK_, int EPI>
 __global__ __launch_bounds__(256) void gemm_x3_kernel(GemmArgs g) {
@@ -349,20 +361,21 @@ __global__ __launch_bounds__(256) void gemm_x3_kernel(GemmArgs g) {
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int i = 0; i < 16; ++i) acc[a][b][i] = 0.f;
-  float va[16], vb[16];
+  SplitStage<AK> sa;
+  SplitStage<BK_> sb;
   if (kbeg < kend) {
-    load_run<AK>(g.A, g.lda, g.M, kend, m0, kbeg, va);
-    load_run<BK_>(g.B, g.ldb, g.N, kend, n0, kbeg, vb);
+    sa.load(g.A, g.lda, g.M, kend, m0, kbeg);
+    sb.load(g.B, g.ldb, g.N, kend, n0, kbeg);
   }
   const int col = lane & 31, half = lane >> 5;
   for (int k0 = kbeg; k0 < kend; k0 += GBK) {
     __syncthreads();
-    store_run_split(Ah, Al, va);
-    store_run_split(Bh, Bl, vb);
+    sa.store(Ah, Al);
+    sb.store(Bh, Bl);
     __syncthreads();
     if (k0 + GBK < kend) {
-      load_run<AK>(g.A, g.lda, g.M, kend, m0, k0 + GBK, va);
-      load_run<BK_>(g.B, g.ldb, g.N, kend, n0, k0 + GBK, vb);
+      sa.load(g.A, g.lda, g.M, kend, m0, k0 + GBK);
+      sb.load(g.B, g.ldb, g.N, kend, n0, k0 + GBK);
     }
 #pragma unroll
     for (int s = 0; s < GBK / 16; ++s) {

@@ -65,37 +65,59 @@ __device__ __forceinline__ double rcp64(double x) {
   return fma(r, e, r);
 }
 
+// Unit quaternion qn = q/|q| of agent i (FP64), 1/|q| and the rotation R(qn).
+__device__ __forceinline__ void agent_frame64(const float* __restrict__ s, int A, int i, double (&qn)[4],
+                                              double& inv_n) {
+  const double q[4] = {s[6 * (size_t)A + i], s[7 * (size_t)A + i], s[8 * (size_t)A + i],
+                       s[9 * (size_t)A + i]};
+  inv_n = 1.0 / sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+  #pragma unroll
+  for (int k = 0; k < 4; ++k) qn[k] = q[k] * inv_n;
+}
+
+__device__ __forceinline__ void rot64(const double (&qn)[4], double (&R)[3][3]) {
+  const double w = qn[0], x = qn[1], y = qn[2], z = qn[3];
+  R[0][0] = 1.0 - 2.0 * (y * y + z * z);
+  R[0][1] = 2.0 * (x * y - w * z);
+  R[0][2] = 2.0 * (x * z + w * y);
+  R[1][0] = 2.0 * (x * y + w * z);
+  R[1][1] = 1.0 - 2.0 * (x * x + z * z);
+  R[1][2] = 2.0 * (y * z - w * x);
+  R[2][0] = 2.0 * (x * z - w * y);
+  R[2][1] = 2.0 * (y * z + w * x);
+  R[2][2] = 1.0 - 2.0 * (x * x + y * y);
+}
+
 template <bool ROT>
-__global__ __launch_bounds__(256) void render_vjp_kernel(SceneDev sc, SensorDev sen,
+__global__ __launch_bounds__(256, 5) void render_vjp_kernel(SceneDev sc, SensorDev sen,
                                                          const float* __restrict__ s, int A,
                                                          const float* __restrict__ g, int g_ld,
                                                          const int* __restrict__ rec,
                                                          float* __restrict__ g_s) {
   __shared__ double red[12][4];
+  __shared__ double Rsh[3][3];  // FP64 rotation, read by the grazing-hit path only
   const int i = blockIdx.x;
   const int tid = threadIdx.x;
   const int env = sc.agent_env[i];
   const f3 o = mk3(s[i], s[(size_t)A + i], s[2 * (size_t)A + i]);
-  double qn[4] = {1.0, 0.0, 0.0, 0.0}, inv_n = 1.0;
-  double R[3][3] = {{1.0, 0.0, 0.0}, {0.0, 1.0, 0.0}, {0.0, 0.0, 1.0}};
   Rot R32;
   if (ROT) {
-    const double q[4] = {s[6 * (size_t)A + i], s[7 * (size_t)A + i], s[8 * (size_t)A + i],
-                         s[9 * (size_t)A + i]};
-    inv_n = 1.0 / sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
-    for (int k = 0; k < 4; ++k) qn[k] = q[k] * inv_n;
-    const double w = qn[0], x = qn[1], y = qn[2], z = qn[3];
-    R[0][0] = 1.0 - 2.0 * (y * y + z * z);
-    R[0][1] = 2.0 * (x * y - w * z);
-    R[0][2] = 2.0 * (x * z + w * y);
-    R[1][0] = 2.0 * (x * y + w * z);
-    R[1][1] = 1.0 - 2.0 * (x * x + z * z);
-    R[1][2] = 2.0 * (y * z - w * x);
-    R[2][0] = 2.0 * (x * z - w * y);
-    R[2][1] = 2.0 * (y * z + w * x);
-    R[2][2] = 1.0 - 2.0 * (x * x + y * y);
+    double qn[4], inv_n, R[3][3];
+    agent_frame64(s, A, i, qn, inv_n);
+    rot64(qn, R);
+    #pragma unroll
     for (int a = 0; a < 3; ++a)
       for (int c = 0; c < 3; ++c) R32.m[a][c] = (float)R[a][c];
+    if (tid == 0)
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) Rsh[a][c] = R[a][c];
+  } else if (tid == 0) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) Rsh[a][c] = a == c ? 1.0 : 0.0;
   }
   const int s0 = sc.sph_off[env], ns = sc.sph_off[env + 1] - s0;
   const int b0 = sc.box_off[env], nb = sc.box_off[env + 1] - b0;
@@ -106,35 +128,67 @@ __global__ __launch_bounds__(256) void render_vjp_kernel(SceneDev sc, SensorDev 
   }
   const int np = ns + nb + na;
   const int nr = sen.n_rays;
-  // per-thread sums (at most a dozen rays each) in FP32; the cross-thread
+  // the env's primitives, staged once: sphere / agent (centre, radius);
+  // box (lo, -) and (hi, -); the room as entry np
+  extern __shared__ float4 vjp_lds[];
+  float4* P0 = vjp_lds;
+  float4* P1 = vjp_lds + (np + 1);
+  for (int k = tid; k <= np; k += 256) {
+    if (k < ns) {
+      P0[k] = reinterpret_cast<const float4*>(sc.sph)[s0 + k];
+    } else if (k < ns + nb) {
+      const float* b = sc.box + (size_t)(b0 + k - ns) * 6;
+      P0[k] = make_float4(b[0] - b[3], b[1] - b[4], b[2] - b[5], 0.f);
+      P1[k] = make_float4(b[0] + b[3], b[1] + b[4], b[2] + b[5], 0.f);
+    } else if (k < np) {
+      const int j = a0 + (k - ns - nb);
+      P0[k] = make_float4(s[j], s[(size_t)A + j], s[2 * (size_t)A + j], sc.agent_radius);
+    } else if (sc.room) {
+      const float* rm = sc.room + (size_t)env * 6;
+      P0[k] = make_float4(rm[0], rm[1], rm[2], 0.f);
+      P1[k] = make_float4(rm[3], rm[4], rm[5], 0.f);
+    }
+  }
+  __syncthreads();
+  // per-thread sums (at most a few dozen rays each) in FP32; the cross-thread
   // reduction is FP64
   float go[3] = {0.f, 0.f, 0.f};
   float gR[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   // rays in the forward pass's tile order: a wavefront covers a compact
-  // angular patch, so its lanes mostly hit the same primitive
-  for (int tile = tid >> 6; tile < sen.n_tiles; tile += 4) {
-    const int r = sen.tile_rays[tile * kTileRays + (tid & 63)];
-    if (r < 0) continue;
-    const int k = rec[(size_t)i * nr + r];
-    const float gv = g[(size_t)i * g_ld + r];
+  // angular patch, so its lanes mostly hit the same primitive. The next
+  // tile's ray index, record, incoming gradient and direction are loaded
+  // while the current tile is processed.
+  const int lane = tid & 63, wave = tid >> 6;
+  const int nt = sen.n_tiles;
+  const int* recrow = rec + (size_t)i * nr;
+  const float* grow = g + (size_t)i * g_ld;
+  int r_c = wave < nt ? sen.tile_rays[wave * kTileRays + lane] : -1;
+  int k_c = r_c >= 0 ? recrow[r_c] : -1;
+  float g_c = r_c >= 0 ? grow[r_c] : 0.f;
+  float4 db_c = r_c >= 0 ? sen.dirs[r_c] : make_float4(0.f, 0.f, 0.f, 0.f);
+  int r_n = wave + 4 < nt ? sen.tile_rays[(wave + 4) * kTileRays + lane] : -1;
+  for (int tile = wave; tile < nt; tile += 4) {
+    const int r_nn = tile + 8 < nt ? sen.tile_rays[(tile + 8) * kTileRays + lane] : -1;
+    const int k_n = r_n >= 0 ? recrow[r_n] : -1;
+    const float g_n = r_n >= 0 ? grow[r_n] : 0.f;
+    const float4 db_n = r_n >= 0 ? sen.dirs[r_n] : make_float4(0.f, 0.f, 0.f, 0.f);
+    const int r = r_c, k = k_c;
+    const float gv = g_c;
+    const float4 db = db_c;
+    r_c = r_n;
+    k_c = k_n;
+    g_c = g_n;
+    db_c = db_n;
+    r_n = r_nn;
     // records outside this env's primitive range (or a room id without a
     // room) cannot come from sim_render on the same scene: ignored
-    if (k < 0 || gv == 0.f || k > np || (k == np && !sc.room)) continue;
-    const float4 db = sen.dirs[r];
+    if (r < 0 || k < 0 || gv == 0.f || k > np || (k == np && !sc.room)) continue;
     const float gt = gv * db.w;
     f3 dto, dtd;  // dt/do and dt/dd (FP32 results)
     if (k < ns || (k >= ns + nb && k < np)) {
-      d3 c;
-      double rad;
-      if (k < ns) {
-        const float4 cc = reinterpret_cast<const float4*>(sc.sph)[s0 + k];
-        c = dk3(cc.x, cc.y, cc.z);
-        rad = cc.w;
-      } else {
-        const int j = a0 + (k - ns - nb);
-        c = dk3(s[j], s[(size_t)A + j], s[2 * (size_t)A + j]);
-        rad = sc.agent_radius;
-      }
+      const float4 cc = P0[k];
+      const d3 c = dk3(cc.x, cc.y, cc.z);
+      const double rad = cc.w;
       // FP32 first; a hit with |n.d| < 0.3 (within ~17 deg of grazing) is
       // redone in FP64, where the FP32 discriminant would lose too much
       const f3 d32 = ROT ? rot_apply(R32, mk3(db.x, db.y, db.z)) : mk3(db.x, db.y, db.z);
@@ -153,9 +207,9 @@ __global__ __launch_bounds__(256) void render_vjp_kernel(SceneDev sc, SensorDev 
       } else {
         const double* b64 = sen.dirs64 + (size_t)r * 4;
         const d3 dbv = dk3(b64[0], b64[1], b64[2]);
-        const d3 d = ROT ? dk3(R[0][0] * dbv.x + R[0][1] * dbv.y + R[0][2] * dbv.z,
-                               R[1][0] * dbv.x + R[1][1] * dbv.y + R[1][2] * dbv.z,
-                               R[2][0] * dbv.x + R[2][1] * dbv.y + R[2][2] * dbv.z)
+        const d3 d = ROT ? dk3(Rsh[0][0] * dbv.x + Rsh[0][1] * dbv.y + Rsh[0][2] * dbv.z,
+                               Rsh[1][0] * dbv.x + Rsh[1][1] * dbv.y + Rsh[1][2] * dbv.z,
+                               Rsh[2][0] * dbv.x + Rsh[2][1] * dbv.y + Rsh[2][2] * dbv.z)
                          : dbv;
         // t = tc - sqrt(disc) and, at the hit point, n.d = -sqrt(disc)/r, so
         // dt/do = -n/(n.d) = (t d - w)/sqrt(disc) and dt/dd = t dt/do
@@ -175,33 +229,28 @@ __global__ __launch_bounds__(256) void render_vjp_kernel(SceneDev sc, SensorDev 
     } else {
       // box entry face or room exit face: t = (plane_f - o_f) / d_f
       const f3 d = ROT ? rot_apply(R32, mk3(db.x, db.y, db.z)) : mk3(db.x, db.y, db.z);
-      const float dv[3] = {d.x, d.y, d.z};
-      const float ov[3] = {o.x, o.y, o.z};
-      const float iv[3] = {__builtin_amdgcn_rcpf(d.x), __builtin_amdgcn_rcpf(d.y),
-                           __builtin_amdgcn_rcpf(d.z)};
-      float pl[3];
-      if (k < ns + nb) {
-        const float* b = sc.box + (size_t)(b0 + k - ns) * 6;
-        for (int a = 0; a < 3; ++a) pl[a] = dv[a] > 0.f ? b[a] - b[3 + a] : b[a] + b[3 + a];
-      } else {
-        const float* rm = sc.room + (size_t)env * 6;
-        for (int a = 0; a < 3; ++a) pl[a] = dv[a] > 0.f ? rm[3 + a] : rm[a];
-      }
-      float te[3];
-      for (int a = 0; a < 3; ++a) te[a] = (pl[a] - ov[a]) * iv[a];
+      const f3 iv = mk3(__builtin_amdgcn_rcpf(d.x), __builtin_amdgcn_rcpf(d.y), __builtin_amdgcn_rcpf(d.z));
+      const float4 lo = P0[k], hi = P1[k];
+      const bool entry = k < ns + nb;  // box: entry face (near slab); room: exit face
+      const float px = (d.x > 0.f) == entry ? lo.x : hi.x;
+      const float py = (d.y > 0.f) == entry ? lo.y : hi.y;
+      const float pz = (d.z > 0.f) == entry ? lo.z : hi.z;
+      const float tx = (px - o.x) * iv.x, ty = (py - o.y) * iv.y, tz = (pz - o.z) * iv.z;
+      // entry: the latest slab entry; exit: the earliest face (first index on ties)
       int f = 0;
-      if (k < ns + nb) {  // entry: the latest slab entry
-        if (te[1] > te[f]) f = 1;
-        if (te[2] > te[f]) f = 2;
-      } else {            // exit: the earliest face
-        if (te[1] < te[f]) f = 1;
-        if (te[2] < te[f]) f = 2;
+      float tf = tx;
+      if (entry ? ty > tf : ty < tf) {
+        f = 1;
+        tf = ty;
       }
-      if (dv[f] == 0.f) continue;
-      float e[3] = {0.f, 0.f, 0.f};
-      e[f] = -iv[f];
-      dto = mk3(e[0], e[1], e[2]);
-      dtd = scl(dto, te[f]);
+      if (entry ? tz > tf : tz < tf) {
+        f = 2;
+        tf = tz;
+      }
+      const float df = f == 0 ? d.x : (f == 1 ? d.y : d.z);
+      if (df == 0.f) continue;
+      dto = mk3(f == 0 ? -iv.x : 0.f, f == 1 ? -iv.y : 0.f, f == 2 ? -iv.z : 0.f);
+      dtd = scl(dto, tf);
     }
     go[0] += gt * dto.x;
     go[1] += gt * dto.y;
@@ -209,12 +258,13 @@ __global__ __launch_bounds__(256) void render_vjp_kernel(SceneDev sc, SensorDev 
     if (ROT) {
       const float gd[3] = {gt * dtd.x, gt * dtd.y, gt * dtd.z};
       const float bb[3] = {db.x, db.y, db.z};
+      #pragma unroll
       for (int a = 0; a < 3; ++a)
         for (int c = 0; c < 3; ++c) gR[a * 3 + c] += gd[a] * bb[c];
     }
   }
   // fixed-order reduction: butterfly within each wavefront, then the 4 waves
-  const int lane = tid & 63, wave = tid >> 6;
+  #pragma unroll
   for (int c = 0; c < 12; ++c) {
     double v = c < 3 ? (double)go[c] : (double)gR[c - 3];
     if (!ROT && c >= 3) continue;
@@ -224,6 +274,7 @@ __global__ __launch_bounds__(256) void render_vjp_kernel(SceneDev sc, SensorDev 
   __syncthreads();
   if (tid == 0) {
     double tot[12];
+    #pragma unroll
     for (int c = 0; c < 12; ++c) tot[c] = (ROT || c < 3) ? ((red[c][0] + red[c][1]) + red[c][2]) + red[c][3] : 0.0;
     g_s[i] += (float)tot[0];
     g_s[(size_t)A + i] += (float)tot[1];
@@ -232,8 +283,11 @@ __global__ __launch_bounds__(256) void render_vjp_kernel(SceneDev sc, SensorDev 
       // dL/dR -> dL/dqn (derivative of the quadratic form at the unit qn),
       // then through qn = q/|q|
       double G[3][3];
+      #pragma unroll
       for (int a = 0; a < 3; ++a)
         for (int c = 0; c < 3; ++c) G[a][c] = tot[3 + a * 3 + c];
+      double qn[4], inv_n;
+      agent_frame64(s, A, i, qn, inv_n);
       const double w = qn[0], x = qn[1], y = qn[2], z = qn[3];
       double gq[4];
       gq[0] = 2.0 * (-G[0][1] * z + G[0][2] * y + G[1][0] * z - G[1][2] * x - G[2][0] * y + G[2][1] * x);
@@ -244,6 +298,7 @@ __global__ __launch_bounds__(256) void render_vjp_kernel(SceneDev sc, SensorDev 
       gq[3] = 2.0 * (-2.0 * G[0][0] * z - G[0][1] * w + G[0][2] * x + G[1][0] * w - 2.0 * G[1][1] * z +
                      G[1][2] * y + G[2][0] * x + G[2][1] * y);
       const double dd = qn[0] * gq[0] + qn[1] * gq[1] + qn[2] * gq[2] + qn[3] * gq[3];
+      #pragma unroll
       for (int k = 0; k < 4; ++k) g_s[(6 + k) * (size_t)A + i] += (float)((gq[k] - qn[k] * dd) * inv_n);
     }
   }
@@ -310,10 +365,11 @@ int launch_render_work(const SceneDev& sc, const SensorDev& sen, bool rotate, bo
 int launch_render_vjp(const SceneDev& sc, const SensorDev& sen, bool rotate, const float* s, int A,
                       const float* g, int g_ld, const int* rec, float* g_s, hipStream_t st) {
   if (A == 0) return SIM_OK;
+  const size_t lds = (size_t)2 * (sc.max_prims + 1) * sizeof(float4);
   if (rotate)
-    hipLaunchKernelGGL((render_vjp_kernel<true>), dim3(A), dim3(256), 0, st, sc, sen, s, A, g, g_ld, rec, g_s);
+    hipLaunchKernelGGL((render_vjp_kernel<true>), dim3(A), dim3(256), lds, st, sc, sen, s, A, g, g_ld, rec, g_s);
   else
-    hipLaunchKernelGGL((render_vjp_kernel<false>), dim3(A), dim3(256), 0, st, sc, sen, s, A, g, g_ld, rec, g_s);
+    hipLaunchKernelGGL((render_vjp_kernel<false>), dim3(A), dim3(256), lds, st, sc, sen, s, A, g, g_ld, rec, g_s);
   DA_LAUNCH_CHECK("render_vjp_kernel");
   return SIM_OK;
 }
