@@ -297,7 +297,41 @@ def render_work_flops(e, s, term):
     return flops, c
 
 
-def dominant_roofline(tm, e, s0, A, gemm_mode):
+# Sources of the camera render kernel; a traffic figure measured with
+# rocprofv3 is only reported while these are unchanged. (The BPTT launch mix,
+# forward renders without and recompute renders with hit records, is fixed.)
+RENDER_SOURCES = ("paper_2509_10247_amd/csrc/render_device.h", "paper_2509_10247_amd/csrc/render.hip",
+                  "paper_2509_10247_amd/csrc/common.h", "paper_2509_10247_amd/csrc/kernels.h")
+TRAFFIC_PROFILE = "profiles/render_kernel_bptt_rb13_16384env_counters.md"
+
+
+def source_hash(files):
+    import hashlib
+    h = hashlib.sha256()
+    for f in files:
+        h.update(f.encode())
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(files, profile):
+    """HBM bytes per launch from a committed rocprofv3 counter summary (a
+    fenced json block), or None if it is missing or the sources changed."""
+    path = os.path.join(ROOT, profile)
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    if "```json" not in text:
+        return None
+    block = text.split("```json", 1)[1].split("```", 1)[0]
+    rec = json.loads(block)
+    if rec.get("source_sha256") != source_hash(files):
+        return None
+    return rec
+
+
+def dominant_roofline(tm, e, s0, A, gemm_mode, store):
     """Roofline of the kernel class with the largest total time in one
     iteration: algorithmic work per launch / average launch duration (HIP
     events on the kernels' stream)."""
@@ -319,15 +353,28 @@ def dominant_roofline(tm, e, s0, A, gemm_mode):
             base["note"] = "FP32 product from three BF16 MFMA products: executed MFMA work is 3x"
         return base
     if dom == "render":
-        flops, cnt = render_work_flops(e, s0, term=True)
+        # half of the launches are the forward pass (observation row written,
+        # obstacle term fused), half the backward's recompute (observation
+        # row and hit record; the term only without stored activations)
+        f_term, cnt = render_work_flops(e, s0, term=True)
+        f_plain, _ = render_work_flops(e, s0, term=False)
+        flops = 0.5 * f_term + 0.5 * (f_plain if store else f_term)
         ach = flops / avg_s
-        written = cnt["rays"] * 8.0   # depth value + hit record per cast ray
+        n_env = e.n_envs
+        # algorithmic bytes: 4 B per ray written forward, 8 B in the recompute;
+        # read once: each env's 24 spheres, 16 boxes and room, and the state
+        written = cnt["rays"] * 6.0
+        read = n_env * (24 * 16 + 16 * 24 + 24) + A * 13 * 4
         base.update({"bound": "alu", "achieved": round(ach / 1e12, 2), "peak": PEAK_FP32_VALU / 1e12,
                      "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_VALU, 4),
                      "frac_of_nonpacked_fp32": round(ach / PEAK_FP32_VALU_NONPACKED, 4),
                      "flops_per_launch": flops, "work_per_launch": cnt,
-                     "hbm_written_bytes": written,
-                     "hbm_frac_of_writes": round(written / avg_s / PEAK_HBM, 4)})
+                     "algorithmic_bytes_per_launch": written + read,
+                     "hbm_frac": round((written + read) / avg_s / PEAK_HBM, 4)})
+        tr = measured_traffic(RENDER_SOURCES, TRAFFIC_PROFILE)
+        if tr is not None:
+            base["traffic"] = tr["fetch_bytes_per_launch"] + tr["write_bytes_per_launch"]
+            base["traffic_source"] = TRAFFIC_PROFILE
         return base
     base.update({"bound": "unknown", "achieved": None, "peak": None, "unit": None, "frac": None})
     return base
@@ -345,7 +392,7 @@ def copy_calibration(mib):
     print(f"[copy-calibration] 3 copies of {mib} MiB", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(model, seed=0, n_envs=64, T=32):
+def cpu_baseline(model, seed=0, n_envs=256, T=32):
     """The FP64 oracle (forward rollout + autograd backward) on a bounded
     sample of the same workload, on the host's cores."""
     import numpy as np
@@ -415,7 +462,7 @@ def main():
         _lib.bptt_set_timing(eng.h, 0)
         breakdown = {k: {"ms_total": round(v[0], 3), "launches": v[1],
                          "ms_avg": round(v[0] / max(v[1], 1), 4)} for k, v in tm.items()}
-        roofline = dominant_roofline(tm, e, s0, A, gemm_mode)
+        roofline = dominant_roofline(tm, e, s0, A, gemm_mode, not args.recompute_all)
 
     line = {
         "metric": "env-steps/sec fwd+bwd with 64x48 depth",

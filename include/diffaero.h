@@ -233,10 +233,16 @@ enum {
   BPTT_T_L1 = 1,          /* first policy layer GEMM, 3084 -> 256, + bias + tanh */
   BPTT_T_GW1 = 2,         /* first-layer weight gradient GEMM (split-K) + reduction */
   BPTT_T_GX = 3,          /* observation gradient GEMM, 256 -> 3084 */
-  BPTT_T_RENDER_VJP = 4,  /* render adjoint */
+  BPTT_T_RENDER_VJP = 4,  /* render adjoint, with the depth-observation gradient folded in */
   BPTT_T_STEP = 5,        /* dynamics step */
   BPTT_T_STEP_VJP = 6,    /* dynamics step adjoint */
-  BPTT_T_COUNT = 7
+  BPTT_T_L23 = 7,         /* second policy layer GEMM and the 256 -> 4 output layer */
+  BPTT_T_SMALL_FWD = 8,   /* observation tail and action map */
+  BPTT_T_SMALL_BWD = 9,   /* loss state gradient, action map, output layer and observation tail backward */
+  BPTT_T_GW23 = 10,       /* second and third layer weight / bias gradients (split-K + reductions) */
+  BPTT_T_GZ1 = 11,        /* first hidden layer gradient GEMM, 256 -> 256, times tanh' */
+  BPTT_T_COLSUM1 = 12,    /* first-layer bias gradient (column sum) */
+  BPTT_T_COUNT = 13
 };
 int bptt_set_timing(bptt_handle* b, int32_t enable);
 int bptt_get_timing(bptt_handle* b, float* ms, int32_t* count, int32_t n);

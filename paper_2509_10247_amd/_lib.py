@@ -234,7 +234,8 @@ def bptt_backward(b, g_loss, g_theta, g_s0=None):
           ptr(g_s0, torch.float32), stream())
 
 
-BPTT_TIMING_CLASSES = ["render", "l1_gemm", "gw1_gemm", "gx_gemm", "render_vjp", "step", "step_vjp"]
+BPTT_TIMING_CLASSES = ["render", "l1_gemm", "gw1_gemm", "gx_gemm", "render_vjp", "step", "step_vjp",
+                       "l23_fwd", "small_fwd", "small_bwd", "gw23", "gz1_gemm", "colsum_b1"]
 
 
 def bptt_set_timing(b, enable):

@@ -3,13 +3,16 @@
 // reverse as vector-Jacobian products), with checkpoint-and-recompute.
 //
 // Forward: T steps of render -> observation -> policy MLP -> action -> step,
-// accumulating the loss; only the state at every K-th step is kept.
-// Backward: for each K-step segment, last first, the segment is recomputed from
-// its checkpoint (keeping observations, hit records and activations of those K
-// steps), then swept in reverse: loss terms, step VJP, action map, the MLP
+// accumulating the loss. Without stored activations only the state at every
+// K-th step is kept and the backward recomputes each K-step segment from its
+// checkpoint (memory O(T/K states + K steps of activations)). With stored
+// activations every step's state, policy activations and action are kept
+// (about 530 floats per agent and step) and the backward recomputes only each
+// segment's rendered observations and hit records (about 6150 floats per
+// agent and step), on a second stream one segment ahead of the sweep.
+// Backward sweep, last step first: loss terms, step VJP, action map, the MLP
 // backward on MFMA (weight gradients accumulated with deterministic split-K
-// reductions), observation backward, render VJP. Memory is
-// O(T/K states + K steps of activations) instead of O(T steps).
+// reductions), observation backward, render VJP.
 #include <vector>
 
 #include "mlp.h"
@@ -141,24 +144,9 @@ __global__ void action_bwd_kernel(int A, int model, const float* __restrict__ ga
   for (int k = 0; k < kOut; ++k) gY[(size_t)b * kOut + k] = g[k] + sc * cu * y[k];
 }
 
-// Observation backward, depth part: turns gX[b][0..3071] into dL/d(depth) in
-// place (input scaling 1/d_max plus the obstacle-loss derivative).
-__global__ __launch_bounds__(256) void obs_depth_bwd_kernel(float* __restrict__ gX, const float* __restrict__ X,
-                                                            float dmax, float beta, float d_safe, float co,
-                                                            const float* __restrict__ gl) {
-  const int b = blockIdx.x;
-  const float sc = gl ? gl[0] * co : co;
-  const float inv = 1.f / dmax;
-  float* grow = gX + (size_t)b * kObsPad;
-  const float* xrow = X + (size_t)b * kObsPad;
-  for (int r = threadIdx.x; r < kRays; r += 256) {
-    const float sig = __frcp_rn(1.f + __expf(-beta * (d_safe - xrow[r] * dmax)));
-    grow[r] = grow[r] * inv - sc * sig;
-  }
-}
-
 // Observation backward, proprioceptive part: adds d(obs)/d(s)^T gX[b][3072..3080]
-// to g_s (obs = [goal - p, v, b]); the depth part is done in the gX GEMM.
+// to g_s (obs = [goal - p, v, b]); the depth part is folded into the render
+// adjoint (DepthObsGrad).
 __global__ void obs_bwd_kernel(int A, int model, const float* __restrict__ gX, const float* __restrict__ s,
                                float* __restrict__ g_s) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
@@ -215,12 +203,15 @@ static int mlp_forward(int B, const PolicyPtrs& p, const float* X, float* H1, fl
   int rc = launch_gemm(true, true, EPI_BIAS_TANH, g, 1, st, prec);
   if (rc) return rc;
   if (owner) tpair(owner, BPTT_T_L1, e0, tmark(owner, st));
+  const int e1 = owner ? tmark(owner, st) : -1;
   g = GemmArgs();
   g.M = B; g.N = kHid; g.K = kHid;
   g.A = H1; g.lda = kHid; g.B = p.W2; g.ldb = kHid;
   g.C = H2; g.ldc = kHid; g.bias = p.b2;
   if ((rc = launch_gemm(true, true, EPI_BIAS_TANH, g, 1, st, prec))) return rc;
-  return launch_narrow_fwd(B, kHid, kOut, H2, kHid, p.W3, p.b3, Y, st);
+  rc = launch_narrow_fwd(B, kHid, kOut, H2, kHid, p.W3, p.b3, Y, st);
+  if (owner) tpair(owner, BPTT_T_L23, e1, tmark(owner, st));
+  return rc;
 }
 
 struct MlpGradBufs {
@@ -230,12 +221,6 @@ struct MlpGradBufs {
   float* gb2;
   float* gW3;    // [4][256]
   float* gb3;
-  float* gZ3;    // [B][4]
-  float* gZ2;    // [B][256]
-  float* gZ1;    // [B][256]
-  float* gX;     // [B][3084]
-  float* part;   // split-K partials
-  bptt_handle* owner = nullptr;  // for optional timing
 };
 
 constexpr int kSplitW1 = 8, kSplitW2 = 64, kSplitW3 = 64;
@@ -247,67 +232,82 @@ static size_t partial_floats(int B) {
   return std::max(std::max(a, std::max(b, c)), (size_t)colsum_workspace_floats(kHid));
 }
 
-// Accumulates weight gradients for one batch and writes gX = dL/dX.
-// obs (nullable): turns the gX GEMM's epilogue into the observation backward
-// for the depth columns (input scaling and the obstacle-loss derivative).
-struct ObsGrad {
-  float scale, c, beta, d_safe, dmax;
-  const float* gl;
+// The layer gradients of one batch (the weight-gradient part reads them
+// while the data part of the next step may already run: two sets).
+struct LayerGrads {
+  float* gZ3;  // [B][4]
+  float* gZ2;  // [B][256]
+  float* gZ1;  // [B][256]
 };
 
-static int mlp_backward(int B, const PolicyPtrs& p, const float* X, const float* H1, const float* H2,
-                        const float* Y, const float* gY, MlpGradBufs& gb, hipStream_t st, int prec,
-                        const ObsGrad* obs = nullptr) {
-  int rc = launch_narrow_bwd(B, kHid, kOut, gY, Y, p.W3, H2, kHid, gb.gZ3, gb.gZ2, st);
+// Backward data path: layer gradients gZ3, gZ2, gZ1 and gX = dL/dX.
+static int mlp_backward_data(int B, const PolicyPtrs& p, const float* H1, const float* H2,
+                             const float* Y, const float* gY, const LayerGrads& z, float* gX,
+                             hipStream_t st, int prec, bptt_handle* owner, hipEvent_t z_ready = nullptr) {
+  int et = owner ? tmark(owner, st) : -1;
+  int rc = launch_narrow_bwd(B, kHid, kOut, gY, Y, p.W3, H2, kHid, z.gZ3, z.gZ2, st);
   if (rc) return rc;
+  if (owner) tpair(owner, BPTT_T_SMALL_BWD, et, tmark(owner, st));
+  // gZ1 = (gZ2 W2) (1 - H1^2)
+  et = owner ? tmark(owner, st) : -1;
+  GemmArgs g;
+  g.M = B; g.N = kHid; g.K = kHid;
+  g.A = z.gZ2; g.lda = kHid; g.B = p.W2; g.ldb = kHid; g.C = z.gZ1; g.ldc = kHid;
+  g.aux = H1; g.ld_aux = kHid;
+  if ((rc = launch_gemm(true, false, EPI_MUL_DTANH, g, 1, st, prec))) return rc;
+  if (owner) tpair(owner, BPTT_T_GZ1, et, tmark(owner, st));
+  if (z_ready) DA_HIP(hipEventRecord(z_ready, st));
+  // gX = gZ1 W1
+  et = owner ? tmark(owner, st) : -1;
+  g = GemmArgs();
+  g.M = B; g.N = kObsPad; g.K = kHid;
+  g.A = z.gZ1; g.lda = kHid; g.B = p.W1p; g.ldb = kObsPad; g.C = gX; g.ldc = kObsPad;
+  rc = launch_gemm(true, false, EPI_STORE, g, 1, st, prec);
+  if (owner) tpair(owner, BPTT_T_GX, et, tmark(owner, st));
+  return rc;
+}
+
+// Backward weight path: accumulates gW3, gb3, gW2, gb2, gW1, gb1 from the
+// layer gradients of one batch (deterministic split-K and column sums in
+// the work buffer `part`).
+static int mlp_backward_weights(int B, const float* X, const float* H1, const float* H2,
+                                const LayerGrads& z, MlpGradBufs& gb, float* part, hipStream_t st,
+                                int prec, bptt_handle* owner) {
   // gW3 += gZ3^T H2 ; gb3 += colsum(gZ3)
+  int et = owner ? tmark(owner, st) : -1;
   GemmArgs g;
   g.M = kOut; g.N = kHid; g.K = B;
-  g.A = gb.gZ3; g.lda = kOut; g.B = H2; g.ldb = kHid; g.C = gb.part; g.ldc = kHid;
-  if ((rc = launch_gemm(false, false, EPI_PARTIAL, g, kSplitW3, st, prec))) return rc;
-  if ((rc = launch_splitk_reduce(gemm_splits_used(B, kSplitW3), kOut, kHid, kHid, gb.part, gb.gW3, kHid,
+  g.A = z.gZ3; g.lda = kOut; g.B = H2; g.ldb = kHid; g.C = part; g.ldc = kHid;
+  int rc = launch_gemm(false, false, EPI_PARTIAL, g, kSplitW3, st, prec);
+  if (rc) return rc;
+  if ((rc = launch_splitk_reduce(gemm_splits_used(B, kSplitW3), kOut, kHid, kHid, part, gb.gW3, kHid,
                                  true, st)))
     return rc;
-  if ((rc = launch_colsum(B, kOut, gb.gZ3, kOut, gb.gb3, true, gb.part, st))) return rc;
+  if ((rc = launch_colsum(B, kOut, z.gZ3, kOut, gb.gb3, true, part, st))) return rc;
   // gW2 += gZ2^T H1 ; gb2
   g = GemmArgs();
   g.M = kHid; g.N = kHid; g.K = B;
-  g.A = gb.gZ2; g.lda = kHid; g.B = H1; g.ldb = kHid; g.C = gb.part; g.ldc = kHid;
+  g.A = z.gZ2; g.lda = kHid; g.B = H1; g.ldb = kHid; g.C = part; g.ldc = kHid;
   if ((rc = launch_gemm(false, false, EPI_PARTIAL, g, kSplitW2, st, prec))) return rc;
-  if ((rc = launch_splitk_reduce(gemm_splits_used(B, kSplitW2), kHid, kHid, kHid, gb.part, gb.gW2, kHid,
+  if ((rc = launch_splitk_reduce(gemm_splits_used(B, kSplitW2), kHid, kHid, kHid, part, gb.gW2, kHid,
                                  true, st)))
     return rc;
-  if ((rc = launch_colsum(B, kHid, gb.gZ2, kHid, gb.gb2, true, gb.part, st))) return rc;
-  // gZ1 = (gZ2 W2) (1 - H1^2)
-  g = GemmArgs();
-  g.M = B; g.N = kHid; g.K = kHid;
-  g.A = gb.gZ2; g.lda = kHid; g.B = p.W2; g.ldb = kHid; g.C = gb.gZ1; g.ldc = kHid;
-  g.aux = H1; g.ld_aux = kHid;
-  if ((rc = launch_gemm(true, false, EPI_MUL_DTANH, g, 1, st, prec))) return rc;
+  if ((rc = launch_colsum(B, kHid, z.gZ2, kHid, gb.gb2, true, part, st))) return rc;
+  if (owner) tpair(owner, BPTT_T_GW23, et, tmark(owner, st));
   // gW1 += gZ1^T X ; gb1
-  const int e0 = gb.owner ? tmark(gb.owner, st) : -1;
+  et = owner ? tmark(owner, st) : -1;
   g = GemmArgs();
   g.M = kHid; g.N = kObsPad; g.K = B;
-  g.A = gb.gZ1; g.lda = kHid; g.B = X; g.ldb = kObsPad; g.C = gb.part; g.ldc = kObsPad;
+  g.A = z.gZ1; g.lda = kHid; g.B = X; g.ldb = kObsPad; g.C = part; g.ldc = kObsPad;
   if ((rc = launch_gemm(false, false, EPI_PARTIAL, g, kSplitW1, st, prec))) return rc;
-  if ((rc = launch_splitk_reduce(gemm_splits_used(B, kSplitW1), kHid, kObsPad, kObsPad, gb.part, gb.gW1p,
+  if ((rc = launch_splitk_reduce(gemm_splits_used(B, kSplitW1), kHid, kObsPad, kObsPad, part, gb.gW1p,
                                  kObsPad, true, st)))
     return rc;
-  if (gb.owner) tpair(gb.owner, BPTT_T_GW1, e0, tmark(gb.owner, st));
-  if ((rc = launch_colsum(B, kHid, gb.gZ1, kHid, gb.gb1, true, gb.part, st))) return rc;
-  // gX = gZ1 W1
-  const int e1 = gb.owner ? tmark(gb.owner, st) : -1;
-  g = GemmArgs();
-  g.M = B; g.N = kObsPad; g.K = kHid;
-  g.A = gb.gZ1; g.lda = kHid; g.B = p.W1p; g.ldb = kObsPad; g.C = gb.gX; g.ldc = kObsPad;
-  if (obs) {
-    g.aux = X; g.ld_aux = kObsPad; g.obs_split = kRays;
-    g.obs_scale = obs->scale; g.obs_c = obs->c; g.obs_beta = obs->beta; g.obs_d = obs->d_safe;
-    g.obs_dmax = obs->dmax; g.obs_gl = obs->gl;
-  }
-  rc = launch_gemm(true, false, obs ? EPI_OBS_GRAD : EPI_STORE, g, 1, st, prec);
-  if (gb.owner) tpair(gb.owner, BPTT_T_GX, e1, tmark(gb.owner, st));
-  return rc;
+  if (owner) tpair(owner, BPTT_T_GW1, et, tmark(owner, st));
+  et = owner ? tmark(owner, st) : -1;
+  if ((rc = launch_colsum(B, kHid, z.gZ1, kHid, gb.gb1, true, part, st))) return rc;
+  if (owner) tpair(owner, BPTT_T_COLSUM1, et, tmark(owner, st));
+  return SIM_OK;
 }
 
 // Writes the accumulated gradients into the flat parameter layout.
@@ -338,6 +338,11 @@ struct bptt_handle {
   float* gflat_tail;  // gb1 .. gb3 contiguous (POLICY_N_PARAMS - kOffB1 floats)
   int* hit;
   MlpGradBufs gb;
+  LayerGrads z[2];       // layer gradients, by step parity
+  float *gX, *part, *part_w;
+  hipStream_t wgrad = nullptr;              // weight-gradient stream (stored mode)
+  hipEvent_t ev_z[2] = {nullptr, nullptr}, ev_w[2] = {nullptr, nullptr}, ev_seg = nullptr,
+             ev_wdone = nullptr;
   const float *theta = nullptr, *s0 = nullptr, *goal = nullptr;
   bool have_fwd = false;
   bool store = false;
@@ -425,11 +430,14 @@ int bptt_create(sim_handle* sim, const bptt_config* cfg, bptt_handle** out) {
   add(&b->gY, (size_t)A * kOut * 4);
   add(&b->gb.gW1p, (size_t)kHid * kObsPad * 4);
   add(&b->gflat_tail, (size_t)(POLICY_N_PARAMS - kOffB1) * 4);
-  add(&b->gb.gZ3, (size_t)A * kOut * 4);
-  add(&b->gb.gZ2, (size_t)A * kHid * 4);
-  add(&b->gb.gZ1, (size_t)A * kHid * 4);
-  add(&b->gb.gX, (size_t)A * kObsPad * 4);
-  add(&b->gb.part, partial_floats(A) * 4);
+  for (int q = 0; q < 2; ++q) {
+    add(&b->z[q].gZ3, (size_t)A * kOut * 4);
+    add(&b->z[q].gZ2, (size_t)A * kHid * 4);
+    add(&b->z[q].gZ1, (size_t)A * kHid * 4);
+  }
+  add(&b->gX, (size_t)A * kObsPad * 4);
+  add(&b->part, partial_floats(A) * 4);
+  add(&b->part_w, partial_floats(A) * 4);
   size_t total = 0;
   for (auto& p : parts) total += p.second;
   hipError_t e = hipMalloc(&b->mem, total);
@@ -455,9 +463,11 @@ int bptt_create(sim_handle* sim, const bptt_config* cfg, bptt_handle** out) {
 int bptt_destroy(bptt_handle* b) {
   if (!b) return SIM_OK;
   for (hipEvent_t e : b->ev_pool) (void)hipEventDestroy(e);
-  for (hipEvent_t e : {b->ev_start, b->ev_rec[0], b->ev_rec[1], b->ev_free[0], b->ev_free[1]})
+  for (hipEvent_t e : {b->ev_start, b->ev_rec[0], b->ev_rec[1], b->ev_free[0], b->ev_free[1], b->ev_z[0],
+                       b->ev_z[1], b->ev_w[0], b->ev_w[1], b->ev_seg, b->ev_wdone})
     if (e) (void)hipEventDestroy(e);
   if (b->side) (void)hipStreamDestroy(b->side);
+  if (b->wgrad) (void)hipStreamDestroy(b->wgrad);
   if (b->mem) (void)hipFree(b->mem);
   delete b;
   return SIM_OK;
@@ -509,12 +519,16 @@ static int forward_step(bptt_handle* b, const PolicyPtrs& pp, const float* s, fl
                          hit, kObsPad, 1.0f / dmax, st, b->lo, b->cfg.beta, b->cfg.d_safe);
   if (rc) return rc;
   tpair(b, BPTT_T_RENDER, e0, tmark(b, st));
+  e0 = tmark(b, st);
   hipLaunchKernelGGL(obs_fwd_kernel, dim3(cdiv(A, 256)), dim3(256), 0, st, A, h->cfg.model, X, s, b->goal);
   DA_LAUNCH_CHECK("obs_fwd_kernel");
+  tpair(b, BPTT_T_SMALL_FWD, e0, tmark(b, st));
   if ((rc = mlp_forward(A, pp, X, H1, H2, Y, st, b->prec, b))) return rc;
+  e0 = tmark(b, st);
   hipLaunchKernelGGL(action_kernel, dim3(cdiv(A, 256)), dim3(256), 0, st, A, h->cfg.model, Y, h->params,
                      act);
   DA_LAUNCH_CHECK("action_kernel");
+  tpair(b, BPTT_T_SMALL_FWD, e0, tmark(b, st));
   e0 = tmark(b, st);
   rc = launch_step(h->cfg.model, h->cfg.integrator, A, h->cfg.dt, s, act, h->params, s_next, nullptr, st);
   tpair(b, BPTT_T_STEP, e0, tmark(b, st));
@@ -611,16 +625,20 @@ int bptt_backward(bptt_handle* b, const float* g_loss, float* g_theta, float* g_
   } else if (overlap) {
     if (!b->side) {
       DA_HIP(hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking));
-      for (hipEvent_t* e : {&b->ev_start, &b->ev_rec[0], &b->ev_rec[1], &b->ev_free[0], &b->ev_free[1]})
+      DA_HIP(hipStreamCreateWithFlags(&b->wgrad, hipStreamNonBlocking));
+      for (hipEvent_t* e : {&b->ev_start, &b->ev_rec[0], &b->ev_rec[1], &b->ev_free[0], &b->ev_free[1],
+                            &b->ev_z[0], &b->ev_z[1], &b->ev_w[0], &b->ev_w[1], &b->ev_seg, &b->ev_wdone})
         DA_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
     }
     // everything enqueued so far on the caller's stream (forward pass, zeroing)
-    // precedes the side stream's first recompute
+    // precedes the side streams' first work
     DA_HIP(hipEventRecord(b->ev_start, st));
     DA_HIP(hipStreamWaitEvent(b->side, b->ev_start, 0));
+    DA_HIP(hipStreamWaitEvent(b->wgrad, b->ev_start, 0));
     if ((rc = recompute_renders(b->nseg - 1, b->side))) return rc;
     DA_HIP(hipEventRecord(b->ev_rec[(b->nseg - 1) & 1], b->side));
   }
+  int wsteps = 0;  // weight-gradient steps enqueued on the wgrad stream
   for (int seg = b->nseg - 1; seg >= 0; --seg) {
     const int t0 = seg * K, n = std::min(T, t0 + K) - t0;
     const int set = b->store ? (seg & 1) : 0;
@@ -655,33 +673,64 @@ int bptt_backward(bptt_handle* b, const float* g_loss, float* g_theta, float* g_
       const float* H2 = b->H2 + (size_t)si * A * kHid;
       const float* Y = b->Y + (size_t)si * A * kOut;
       const float* act = b->act + (size_t)si * Ka * A;
+      int e0 = tmark(b, st);
       hipLaunchKernelGGL(loss_state_grad_kernel, dim3(cdiv(A, 256)), dim3(256), 0, st, A, s1, b->goal, cp,
                          cv, g_loss, g_next);
       DA_LAUNCH_CHECK("loss_state_grad_kernel");
-      int e0 = tmark(b, st);
+      tpair(b, BPTT_T_SMALL_BWD, e0, tmark(b, st));
+      e0 = tmark(b, st);
       if ((rc = launch_step_vjp(h->cfg.model, h->cfg.integrator, A, h->cfg.dt, s, act, h->params, g_next,
                                 g_cur, b->ga, st)))
         return rc;
       tpair(b, BPTT_T_STEP_VJP, e0, tmark(b, st));
+      e0 = tmark(b, st);
       hipLaunchKernelGGL(action_bwd_kernel, dim3(cdiv(A, 256)), dim3(256), 0, st, A, h->cfg.model, b->ga,
                          Y, h->params, cu, g_loss, b->gY);
       DA_LAUNCH_CHECK("action_bwd_kernel");
-      b->gb.owner = b;
-      if ((rc = mlp_backward(A, pp, X, H1, H2, Y, b->gY, b->gb, st, b->prec))) return rc;
-      hipLaunchKernelGGL(obs_depth_bwd_kernel, dim3(A), dim3(256), 0, st, b->gb.gX, X, dmax, b->cfg.beta,
-                         b->cfg.d_safe, co, g_loss);
-      DA_LAUNCH_CHECK("obs_depth_bwd_kernel");
-      hipLaunchKernelGGL(obs_bwd_kernel, dim3(cdiv(A, 256)), dim3(256), 0, st, A, h->cfg.model, b->gb.gX, s,
+      tpair(b, BPTT_T_SMALL_BWD, e0, tmark(b, st));
+      // layer gradients of this step go to set `par`; with stored activations
+      // the weight gradients run on their own stream, overlapping the data
+      // path (gX GEMM, render adjoint) of this and the next step
+      const int par = (t0 + j) & 1;
+      const LayerGrads& z = b->z[par];
+      if (overlap && wsteps >= 2) DA_HIP(hipStreamWaitEvent(st, b->ev_w[par], 0));
+      if ((rc = mlp_backward_data(A, pp, H1, H2, Y, b->gY, z, b->gX, st, b->prec, b,
+                                  overlap ? b->ev_z[par] : nullptr)))
+        return rc;
+      if (overlap) {
+        DA_HIP(hipStreamWaitEvent(b->wgrad, b->ev_z[par], 0));
+        if ((rc = mlp_backward_weights(A, X, H1, H2, z, b->gb, b->part_w, b->wgrad, b->prec, nullptr)))
+          return rc;
+        DA_HIP(hipEventRecord(b->ev_w[par], b->wgrad));
+        ++wsteps;
+      } else if ((rc = mlp_backward_weights(A, X, H1, H2, z, b->gb, b->part, st, b->prec, b))) {
+        return rc;
+      }
+      e0 = tmark(b, st);
+      hipLaunchKernelGGL(obs_bwd_kernel, dim3(cdiv(A, 256)), dim3(256), 0, st, A, h->cfg.model, b->gX, s,
                          g_cur);
       DA_LAUNCH_CHECK("obs_bwd_kernel");
+      tpair(b, BPTT_T_SMALL_BWD, e0, tmark(b, st));
       e0 = tmark(b, st);
-      if ((rc = launch_render_vjp(h->scene, h->cam.dev, h->cfg.model == SIM_RB13, s, A, b->gb.gX,
-                                  kObsPad, hit, g_cur, st)))
+      // depth-observation backward fused into the render adjoint
+      const DepthObsGrad ob{X, dmax, b->cfg.beta, b->cfg.d_safe, co, g_loss};
+      if ((rc = launch_render_vjp(h->scene, h->cam.dev, h->cfg.model == SIM_RB13, s, A, b->gX,
+                                  kObsPad, hit, g_cur, st, &ob)))
         return rc;
       tpair(b, BPTT_T_RENDER_VJP, e0, tmark(b, st));
       std::swap(g_next, g_cur);
     }
-    if (overlap) DA_HIP(hipEventRecord(b->ev_free[set], st));
+    if (overlap) {
+      // the set is free once both the sweep and the weight gradients of this
+      // segment are done with it
+      DA_HIP(hipEventRecord(b->ev_seg, st));
+      DA_HIP(hipStreamWaitEvent(b->wgrad, b->ev_seg, 0));
+      DA_HIP(hipEventRecord(b->ev_free[set], b->wgrad));
+    }
+  }
+  if (overlap) {
+    DA_HIP(hipEventRecord(b->ev_wdone, b->wgrad));
+    DA_HIP(hipStreamWaitEvent(st, b->ev_wdone, 0));
   }
   if (g_s0) DA_HIP(hipMemcpyAsync(g_s0, g_next, sbytes, hipMemcpyDeviceToDevice, st));
   return write_flat_grad(b->gb, g_theta, st);
@@ -736,19 +785,21 @@ int policy_backward(const float* theta, const float* x, const float* g_y, float*
   gb.gb2 = tail + (kOffB2 - kOffB1);
   gb.gW3 = tail + (kOffW3 - kOffB1);
   gb.gb3 = tail + (kOffB3 - kOffB1);
-  gb.gZ3 = tail + nT;
-  gb.gZ2 = gb.gZ3 + nY;
-  gb.gZ1 = gb.gZ2 + nH;
-  gb.gX = gb.gZ1 + nH;
-  gb.part = gb.gX + nX;
+  LayerGrads z;
+  z.gZ3 = tail + nT;
+  z.gZ2 = z.gZ3 + nY;
+  z.gZ1 = z.gZ2 + nH;
+  float* gX = z.gZ1 + nH;
+  float* part = gX + nX;
   const PolicyPtrs pp = policy_ptrs(theta, W1p);
   rc = launch_pad_rows(kHid, kObs, kObsPad, theta + kOffW1, kObs, W1p, st);
   if (!rc) rc = launch_pad_rows(B, kObs, kObsPad, x, kObs, X, st);
   if (!rc && hipMemsetAsync(gb.gW1p, 0, (nW + nT) * 4, st) != hipSuccess) rc = fail(SIM_EHIP, "memset");
   if (!rc) rc = mlp_forward(B, pp, X, H1, H2, Y, st, policy_prec(gemm_mode));
-  if (!rc) rc = mlp_backward(B, pp, X, H1, H2, Y, g_y, gb, st, policy_prec(gemm_mode));
+  if (!rc) rc = mlp_backward_data(B, pp, H1, H2, Y, g_y, z, gX, st, policy_prec(gemm_mode), nullptr);
+  if (!rc) rc = mlp_backward_weights(B, X, H1, H2, z, gb, part, st, policy_prec(gemm_mode), nullptr);
   if (!rc) rc = write_flat_grad(gb, g_theta, st);
-  if (!rc && g_x) rc = launch_pad_rows(B, kObs, kObs, gb.gX, kObsPad, g_x, st);
+  if (!rc && g_x) rc = launch_pad_rows(B, kObs, kObs, gX, kObsPad, g_x, st);
   hipError_t e = hipStreamSynchronize(st);
   (void)hipFree(mem);
   if (rc) return rc;

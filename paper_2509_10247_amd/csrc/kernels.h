@@ -52,8 +52,17 @@ int launch_render_work(const SceneDev& sc, const SensorDev& sen, bool rotate, bo
                        const float* s, int A, float* out, int* work, hipStream_t st);
 // Adds the sensor's contribution (d out/d s)^T g to g_s (p and q components);
 // g[i*g_ld + r] is the gradient of the (unscaled) sensor value.
+// Depth-observation backward fused into the render adjoint: the incoming
+// per-ray gradient is g = g_obs / d_max - c sigmoid(beta (d_safe - x d_max))
+// with x the observation row value (depth / d_max) and c = co (* gl[0]).
+struct DepthObsGrad {
+  const float* x;   // observation rows (same pitch as g)
+  float dmax, beta, d_safe, co;
+  const float* gl;  // nullable scale of the loss gradient
+};
 int launch_render_vjp(const SceneDev& sc, const SensorDev& sen, bool rotate, const float* s, int A,
-                      const float* g, int g_ld, const int* rec, float* g_s, hipStream_t st);
+                      const float* g, int g_ld, const int* rec, float* g_s, hipStream_t st,
+                      const DepthObsGrad* obs = nullptr);
 int launch_collide(const SceneDev& sc, const float* s, int A, uint8_t* flags, float* min_dist,
                    hipStream_t st);
 

@@ -88,12 +88,12 @@ __device__ __forceinline__ void rot64(const double (&qn)[4], double (&R)[3][3]) 
   R[2][2] = 1.0 - 2.0 * (x * x + y * y);
 }
 
-template <bool ROT>
+template <bool ROT, bool OBS>
 __global__ __launch_bounds__(256, 5) void render_vjp_kernel(SceneDev sc, SensorDev sen,
                                                          const float* __restrict__ s, int A,
                                                          const float* __restrict__ g, int g_ld,
                                                          const int* __restrict__ rec,
-                                                         float* __restrict__ g_s) {
+                                                         float* __restrict__ g_s, DepthObsGrad ob) {
   __shared__ double red[12][4];
   __shared__ double Rsh[3][3];  // FP64 rotation, read by the grazing-hit path only
   const int i = blockIdx.x;
@@ -162,22 +162,34 @@ __global__ __launch_bounds__(256, 5) void render_vjp_kernel(SceneDev sc, SensorD
   const int nt = sen.n_tiles;
   const int* recrow = rec + (size_t)i * nr;
   const float* grow = g + (size_t)i * g_ld;
+  const float* xrow = OBS ? ob.x + (size_t)i * g_ld : nullptr;
+  const float inv_dmax = OBS ? 1.f / ob.dmax : 1.f;
+  const float osc = OBS ? (ob.gl ? ob.gl[0] * ob.co : ob.co) : 0.f;
   int r_c = wave < nt ? sen.tile_rays[wave * kTileRays + lane] : -1;
   int k_c = r_c >= 0 ? recrow[r_c] : -1;
   float g_c = r_c >= 0 ? grow[r_c] : 0.f;
+  float x_c = (OBS && r_c >= 0) ? xrow[r_c] : 0.f;
   float4 db_c = r_c >= 0 ? sen.dirs[r_c] : make_float4(0.f, 0.f, 0.f, 0.f);
   int r_n = wave + 4 < nt ? sen.tile_rays[(wave + 4) * kTileRays + lane] : -1;
   for (int tile = wave; tile < nt; tile += 4) {
     const int r_nn = tile + 8 < nt ? sen.tile_rays[(tile + 8) * kTileRays + lane] : -1;
     const int k_n = r_n >= 0 ? recrow[r_n] : -1;
     const float g_n = r_n >= 0 ? grow[r_n] : 0.f;
+    const float x_n = (OBS && r_n >= 0) ? xrow[r_n] : 0.f;
     const float4 db_n = r_n >= 0 ? sen.dirs[r_n] : make_float4(0.f, 0.f, 0.f, 0.f);
     const int r = r_c, k = k_c;
-    const float gv = g_c;
+    float gv = g_c;
+    if (OBS) {
+      // d(loss)/d(depth): the observation's 1/d_max scaling and the
+      // obstacle term softplus(beta (d_safe - depth)) / beta
+      const float sig = __frcp_rn(1.f + __expf(-ob.beta * (ob.d_safe - x_c * ob.dmax)));
+      gv = gv * inv_dmax - osc * sig;
+    }
     const float4 db = db_c;
     r_c = r_n;
     k_c = k_n;
     g_c = g_n;
+    x_c = x_n;
     db_c = db_n;
     r_n = r_nn;
     // records outside this env's primitive range (or a room id without a
@@ -363,13 +375,23 @@ int launch_render_work(const SceneDev& sc, const SensorDev& sen, bool rotate, bo
 }
 
 int launch_render_vjp(const SceneDev& sc, const SensorDev& sen, bool rotate, const float* s, int A,
-                      const float* g, int g_ld, const int* rec, float* g_s, hipStream_t st) {
+                      const float* g, int g_ld, const int* rec, float* g_s, hipStream_t st,
+                      const DepthObsGrad* obs) {
   if (A == 0) return SIM_OK;
   const size_t lds = (size_t)2 * (sc.max_prims + 1) * sizeof(float4);
-  if (rotate)
-    hipLaunchKernelGGL((render_vjp_kernel<true>), dim3(A), dim3(256), lds, st, sc, sen, s, A, g, g_ld, rec, g_s);
-  else
-    hipLaunchKernelGGL((render_vjp_kernel<false>), dim3(A), dim3(256), lds, st, sc, sen, s, A, g, g_ld, rec, g_s);
+  const DepthObsGrad ob = obs ? *obs : DepthObsGrad{nullptr, 1.f, 0.f, 0.f, 0.f, nullptr};
+  if (obs && !obs->x) return fail(SIM_EINVAL, "render_vjp: observation rows missing");
+  if (rotate) {
+    if (obs)
+      hipLaunchKernelGGL((render_vjp_kernel<true, true>), dim3(A), dim3(256), lds, st, sc, sen, s, A, g, g_ld, rec, g_s, ob);
+    else
+      hipLaunchKernelGGL((render_vjp_kernel<true, false>), dim3(A), dim3(256), lds, st, sc, sen, s, A, g, g_ld, rec, g_s, ob);
+  } else {
+    if (obs)
+      hipLaunchKernelGGL((render_vjp_kernel<false, true>), dim3(A), dim3(256), lds, st, sc, sen, s, A, g, g_ld, rec, g_s, ob);
+    else
+      hipLaunchKernelGGL((render_vjp_kernel<false, false>), dim3(A), dim3(256), lds, st, sc, sen, s, A, g, g_ld, rec, g_s, ob);
+  }
   DA_LAUNCH_CHECK("render_vjp_kernel");
   return SIM_OK;
 }
