@@ -47,7 +47,7 @@ def parse():
     p.add_argument("--ckpt", type=int, default=8)
     p.add_argument("--recompute-all", action="store_true",
                    help="keep only the K-step state checkpoints (recompute policy and step too)")
-    p.add_argument("--policy-gemm", choices=["fp32", "bf16x3"], default="fp32",
+    p.add_argument("--policy-gemm", choices=["fp32", "bf16x3"], default="bf16x3",
                    help="policy layers on FP32 MFMA, or FP32 recovered from three BF16 MFMA products")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                    help="also run a plain device copy of MIB MiB (for HBM counter scaling)")

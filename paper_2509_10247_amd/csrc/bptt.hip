@@ -193,14 +193,27 @@ static PolicyPtrs policy_ptrs(const float* theta, const float* W1p) {
   return PolicyPtrs{W1p, theta + kOffB1, theta + kOffW2, theta + kOffB2, theta + kOffW3, theta + kOffB3};
 }
 
+// First layer split three ways over K: with 128 x 128 tiles the 16384 x 256
+// output is one workgroup per CU, too few to hide the operand loads; the
+// partial sums are combined with the bias and tanh in one pass.
+constexpr int kSplitL1 = 3;
+
 static int mlp_forward(int B, const PolicyPtrs& p, const float* X, float* H1, float* H2, float* Y,
-                       hipStream_t st, int prec, bptt_handle* owner = nullptr) {
+                       hipStream_t st, int prec, float* part, bptt_handle* owner = nullptr) {
   GemmArgs g;
   g.M = B; g.N = kHid; g.K = kObsPad;
   g.A = X; g.lda = kObsPad; g.B = p.W1p; g.ldb = kObsPad;
   g.C = H1; g.ldc = kHid; g.bias = p.b1;
   const int e0 = owner ? tmark(owner, st) : -1;
-  int rc = launch_gemm(true, true, EPI_BIAS_TANH, g, 1, st, prec);
+  int rc;
+  if (part) {
+    g.C = part;
+    if ((rc = launch_gemm(true, true, EPI_PARTIAL, g, kSplitL1, st, prec))) return rc;
+    rc = launch_splitk_bias_tanh(gemm_splits_used(kObsPad, kSplitL1), B, kHid, kHid, part, p.b1, H1, kHid,
+                                 st);
+  } else {
+    rc = launch_gemm(true, true, EPI_BIAS_TANH, g, 1, st, prec);
+  }
   if (rc) return rc;
   if (owner) tpair(owner, BPTT_T_L1, e0, tmark(owner, st));
   const int e1 = owner ? tmark(owner, st) : -1;
@@ -226,7 +239,8 @@ struct MlpGradBufs {
 constexpr int kSplitW1 = 8, kSplitW2 = 64, kSplitW3 = 64;
 
 static size_t partial_floats(int B) {
-  size_t a = (size_t)gemm_splits_used(B, kSplitW1) * kHid * kObsPad;
+  const size_t l1 = (size_t)gemm_splits_used(kObsPad, kSplitL1) * B * kHid;
+  size_t a = std::max(l1, (size_t)gemm_splits_used(B, kSplitW1) * kHid * kObsPad);
   size_t b = (size_t)gemm_splits_used(B, kSplitW2) * kHid * kHid;
   size_t c = (size_t)gemm_splits_used(B, kSplitW3) * kOut * kHid;
   return std::max(std::max(a, std::max(b, c)), (size_t)colsum_workspace_floats(kHid));
@@ -523,7 +537,7 @@ static int forward_step(bptt_handle* b, const PolicyPtrs& pp, const float* s, fl
   hipLaunchKernelGGL(obs_fwd_kernel, dim3(cdiv(A, 256)), dim3(256), 0, st, A, h->cfg.model, X, s, b->goal);
   DA_LAUNCH_CHECK("obs_fwd_kernel");
   tpair(b, BPTT_T_SMALL_FWD, e0, tmark(b, st));
-  if ((rc = mlp_forward(A, pp, X, H1, H2, Y, st, b->prec, b))) return rc;
+  if ((rc = mlp_forward(A, pp, X, H1, H2, Y, st, b->prec, b->part, b))) return rc;
   e0 = tmark(b, st);
   hipLaunchKernelGGL(action_kernel, dim3(cdiv(A, 256)), dim3(256), 0, st, A, h->cfg.model, Y, h->params,
                      act);
@@ -752,11 +766,12 @@ int policy_forward(const float* theta, const float* x, float* y, int32_t B, int3
   hipStream_t st = as_stream(stream);
   float* mem = nullptr;
   const size_t nW = (size_t)kHid * kObsPad, nX = (size_t)B * kObsPad, nH = (size_t)B * kHid;
-  DA_HIP(hipMalloc(&mem, (nW + nX + 2 * nH) * 4));
+  DA_HIP(hipMalloc(&mem, (nW + nX + 2 * nH + partial_floats(B) + 64) * 4));
   float *W1p = mem, *X = W1p + nW, *H1 = X + nX, *H2 = H1 + nH;
+  float* part = H2 + nH;
   rc = launch_pad_rows(kHid, kObs, kObsPad, theta + kOffW1, kObs, W1p, st);
   if (!rc) rc = launch_pad_rows(B, kObs, kObsPad, x, kObs, X, st);
-  if (!rc) rc = mlp_forward(B, policy_ptrs(theta, W1p), X, H1, H2, y, st, policy_prec(gemm_mode));
+  if (!rc) rc = mlp_forward(B, policy_ptrs(theta, W1p), X, H1, H2, y, st, policy_prec(gemm_mode), part);
   hipError_t e = hipStreamSynchronize(st);
   (void)hipFree(mem);
   if (rc) return rc;
@@ -795,7 +810,7 @@ int policy_backward(const float* theta, const float* x, const float* g_y, float*
   rc = launch_pad_rows(kHid, kObs, kObsPad, theta + kOffW1, kObs, W1p, st);
   if (!rc) rc = launch_pad_rows(B, kObs, kObsPad, x, kObs, X, st);
   if (!rc && hipMemsetAsync(gb.gW1p, 0, (nW + nT) * 4, st) != hipSuccess) rc = fail(SIM_EHIP, "memset");
-  if (!rc) rc = mlp_forward(B, pp, X, H1, H2, Y, st, policy_prec(gemm_mode));
+  if (!rc) rc = mlp_forward(B, pp, X, H1, H2, Y, st, policy_prec(gemm_mode), part);
   if (!rc) rc = mlp_backward_data(B, pp, H1, H2, Y, g_y, z, gX, st, policy_prec(gemm_mode), nullptr);
   if (!rc) rc = mlp_backward_weights(B, X, H1, H2, z, gb, part, st, policy_prec(gemm_mode), nullptr);
   if (!rc) rc = write_flat_grad(gb, g_theta, st);

@@ -438,6 +438,7 @@ int launch_gemm(bool a_kmaj, bool b_kmaj, int epi, GemmArgs g, int splits, hipSt
     if (key == 1 && epi == EPI_MUL_DTANH) return gemm_x3_t<true, false, EPI_MUL_DTANH>(g, 1, st);
     if (key == 1 && epi == EPI_STORE) return gemm_x3_t<true, false, EPI_STORE>(g, 1, st);
     if (key == 0 && epi == EPI_PARTIAL) return gemm_x3_t<false, false, EPI_PARTIAL>(g, splits, st);
+    if (key == 3 && epi == EPI_PARTIAL) return gemm_x3_t<true, true, EPI_PARTIAL>(g, splits, st);
     return fail(SIM_EINVAL, "gemm: bf16x3 layout %d / epilogue %d not built", key, epi);
   }
   if (prec == GEMM_BF16) {
@@ -488,6 +489,38 @@ __global__ void splitk_reduce_kernel(int S, int M, int N, int ldp, const float* 
   for (int s = 0; s < S; ++s) v += part[(size_t)s * M * ldp + (size_t)m * ldp + n];
   if (accumulate) v += out[(size_t)m * ldo + n];
   out[(size_t)m * ldo + n] = v;
+}
+
+// out[m][n] = tanh(sum_s part[s][m][n] + bias[n]), four columns per thread
+// (N % 4 == 0, ldp % 4 == 0, ldo % 4 == 0).
+__global__ void splitk_bias_tanh_kernel(int S, int M, int N, int ldp, const float* __restrict__ part,
+                                        const float* __restrict__ bias, float* __restrict__ out, int ldo) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nq = N >> 2;
+  if (idx >= M * nq) return;
+  const int m = idx / nq, n = (idx % nq) * 4;
+  float4 v = *reinterpret_cast<const float4*>(part + (size_t)m * ldp + n);
+  for (int s = 1; s < S; ++s) {
+    const float4 w = *reinterpret_cast<const float4*>(part + (size_t)s * M * ldp + (size_t)m * ldp + n);
+    v.x += w.x;
+    v.y += w.y;
+    v.z += w.z;
+    v.w += w.w;
+  }
+  const float4 b = *reinterpret_cast<const float4*>(bias + n);
+  *reinterpret_cast<float4*>(out + (size_t)m * ldo + n) =
+      make_float4(tanhf(v.x + b.x), tanhf(v.y + b.y), tanhf(v.z + b.z), tanhf(v.w + b.w));
+}
+
+int launch_splitk_bias_tanh(int S, int M, int N, int ldp, const float* part, const float* bias, float* out,
+                            int ldo, hipStream_t st) {
+  if ((N & 3) || (ldp & 3) || (ldo & 3) || (reinterpret_cast<uintptr_t>(bias) & 15))
+    return fail(SIM_EINVAL, "splitk_bias_tanh: needs N, ldp, ldo %% 4 == 0 and an aligned bias");
+  const int tot = M * (N >> 2);
+  hipLaunchKernelGGL(splitk_bias_tanh_kernel, dim3(cdiv(tot, 256)), dim3(256), 0, st, S, M, N, ldp, part,
+                     bias, out, ldo);
+  DA_LAUNCH_CHECK("splitk_bias_tanh_kernel");
+  return SIM_OK;
 }
 
 int launch_splitk_reduce(int S, int M, int N, int ldp, const float* part, float* out, int ldo,

@@ -51,6 +51,8 @@ enum { GEMM_FP32 = 0, GEMM_BF16 = 1, GEMM_BF16X3 = 2 };
 int launch_gemm(bool a_kmaj, bool b_kmaj, int epi, GemmArgs g, int splits, hipStream_t st,
                 int prec = GEMM_FP32);
 int gemm_splits_used(int K, int splits);
+int launch_splitk_bias_tanh(int S, int M, int N, int ldp, const float* part, const float* bias, float* out,
+                            int ldo, hipStream_t st);
 int launch_splitk_reduce(int S, int M, int N, int ldp, const float* part, float* out, int ldo,
                          bool accumulate, hipStream_t st);
 // Column sums out[n] (+)= sum_m X[m][n]; work holds colsum_workspace_floats(N).
