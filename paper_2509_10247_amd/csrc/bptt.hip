@@ -187,7 +187,11 @@ struct PolicyPtrs {
   const float* b2;
   const float* W3;   // [4][256]
   const float* b3;
+  // optional split-BF16 copies of W1 (GEMM_BF16X3): W1 [256][kW1sLd] and its
+  // transpose [3084][256], split once per iteration instead of per workgroup
+  const uint16_t *W1s_hi = nullptr, *W1s_lo = nullptr, *W1t_hi = nullptr, *W1t_lo = nullptr;
 };
+constexpr int kW1sLd = (kObsPad + kSplitPad - 1) / kSplitPad * kSplitPad;  // 3104
 
 static PolicyPtrs policy_ptrs(const float* theta, const float* W1p) {
   return PolicyPtrs{W1p, theta + kOffB1, theta + kOffW2, theta + kOffB2, theta + kOffW3, theta + kOffB3};
@@ -206,6 +210,11 @@ static int mlp_forward(int B, const PolicyPtrs& p, const float* X, float* H1, fl
   g.C = H1; g.ldc = kHid; g.bias = p.b1;
   const int e0 = owner ? tmark(owner, st) : -1;
   int rc;
+  if (p.W1s_hi) {
+    g.B_hi = p.W1s_hi;
+    g.B_lo = p.W1s_lo;
+    g.ldb_s = kW1sLd;
+  }
   if (part) {
     g.C = part;
     if ((rc = launch_gemm(true, true, EPI_PARTIAL, g, kSplitL1, st, prec))) return rc;
@@ -257,7 +266,8 @@ struct LayerGrads {
 // Backward data path: layer gradients gZ3, gZ2, gZ1 and gX = dL/dX.
 static int mlp_backward_data(int B, const PolicyPtrs& p, const float* H1, const float* H2,
                              const float* Y, const float* gY, const LayerGrads& z, float* gX,
-                             hipStream_t st, int prec, bptt_handle* owner, hipEvent_t z_ready = nullptr) {
+                             hipStream_t st, int prec, bptt_handle* owner, hipEvent_t z_ready = nullptr,
+                             uint16_t* z1_hi = nullptr, uint16_t* z1_lo = nullptr) {
   int et = owner ? tmark(owner, st) : -1;
   int rc = launch_narrow_bwd(B, kHid, kOut, gY, Y, p.W3, H2, kHid, z.gZ3, z.gZ2, st);
   if (rc) return rc;
@@ -276,6 +286,12 @@ static int mlp_backward_data(int B, const PolicyPtrs& p, const float* H1, const 
   g = GemmArgs();
   g.M = B; g.N = kObsPad; g.K = kHid;
   g.A = z.gZ1; g.lda = kHid; g.B = p.W1p; g.ldb = kObsPad; g.C = gX; g.ldc = kObsPad;
+  if (p.W1t_hi && z1_hi) {
+    // both operands pre-split: gZ1 here, W1^T once per iteration
+    if ((rc = launch_split_rows(B, kHid, z.gZ1, kHid, z1_hi, z1_lo, kHid, st))) return rc;
+    g.A_hi = z1_hi; g.A_lo = z1_lo; g.lda_s = kHid;
+    g.B_hi = p.W1t_hi; g.B_lo = p.W1t_lo; g.ldb_s = kHid;
+  }
   rc = launch_gemm(true, false, EPI_STORE, g, 1, st, prec);
   if (owner) tpair(owner, BPTT_T_GX, et, tmark(owner, st));
   return rc;
@@ -354,6 +370,8 @@ struct bptt_handle {
   MlpGradBufs gb;
   LayerGrads z[2];       // layer gradients, by step parity
   float *gX, *part, *part_w;
+  uint16_t *W1s_hi = nullptr, *W1s_lo = nullptr, *W1t_hi = nullptr, *W1t_lo = nullptr;
+  uint16_t *z1_hi = nullptr, *z1_lo = nullptr;
   hipStream_t wgrad = nullptr;              // weight-gradient stream (stored mode)
   hipEvent_t ev_z[2] = {nullptr, nullptr}, ev_w[2] = {nullptr, nullptr}, ev_seg = nullptr,
              ev_wdone = nullptr;
@@ -387,6 +405,15 @@ static void tpair(bptt_handle* b, int cls, int a, int z) {
   if (a >= 0 && z >= 0) b->ev_pairs[cls].push_back({a, z});
 }
 }  // namespace da
+
+static PolicyPtrs bptt_policy_ptrs(const bptt_handle* b) {
+  PolicyPtrs p = policy_ptrs(b->theta, b->W1p);
+  p.W1s_hi = b->W1s_hi;
+  p.W1s_lo = b->W1s_lo;
+  p.W1t_hi = b->W1t_hi;
+  p.W1t_lo = b->W1t_lo;
+  return p;
+}
 
 static int check_policy_sim(const sim_handle* h) {
   DA_REQUIRE(h->cfg.model == SIM_PM9 || h->cfg.model == SIM_RB13, "bptt: model must be PM9 or RB13");
@@ -450,6 +477,14 @@ int bptt_create(sim_handle* sim, const bptt_config* cfg, bptt_handle** out) {
     add(&b->z[q].gZ1, (size_t)A * kHid * 4);
   }
   add(&b->gX, (size_t)A * kObsPad * 4);
+  if (b->prec == GEMM_BF16X3) {
+    add(&b->W1s_hi, (size_t)kHid * kW1sLd * 2);
+    add(&b->W1s_lo, (size_t)kHid * kW1sLd * 2);
+    add(&b->W1t_hi, (size_t)kObsPad * kHid * 2);
+    add(&b->W1t_lo, (size_t)kObsPad * kHid * 2);
+    add(&b->z1_hi, (size_t)A * kHid * 2);
+    add(&b->z1_lo, (size_t)A * kHid * 2);
+  }
   add(&b->part, partial_floats(A) * 4);
   add(&b->part_w, partial_floats(A) * 4);
   size_t total = 0;
@@ -563,7 +598,12 @@ int bptt_forward(bptt_handle* b, const float* theta, const float* s0, const floa
   b->goal = goal;
   int rc = launch_pad_rows(kHid, kObs, kObsPad, theta + kOffW1, kObs, b->W1p, st);
   if (rc) return rc;
-  const PolicyPtrs pp = policy_ptrs(theta, b->W1p);
+  if (b->W1s_hi) {
+    if ((rc = launch_split_rows(kHid, kObsPad, b->W1p, kObsPad, b->W1s_hi, b->W1s_lo, kW1sLd, st))) return rc;
+    if ((rc = launch_split_transpose(kHid, kObsPad, b->W1p, kObsPad, b->W1t_hi, b->W1t_lo, kHid, st)))
+      return rc;
+  }
+  const PolicyPtrs pp = bptt_policy_ptrs(b);
   DA_HIP(hipMemsetAsync(b->loss_acc, 0, (size_t)A * 4, st));
   const size_t sbytes = (size_t)C * A * 4;
   DA_HIP(hipMemcpyAsync(b->seg_s, s0, sbytes, hipMemcpyDeviceToDevice, st));
@@ -599,7 +639,7 @@ int bptt_backward(bptt_handle* b, const float* g_loss, float* g_theta, float* g_
   hipStream_t st = as_stream(stream);
   sim_handle* h = b->sim;
   const int A = b->A, C = b->C, Ka = b->Ka, K = b->cfg.K, T = b->cfg.T;
-  const PolicyPtrs pp = policy_ptrs(b->theta, b->W1p);
+  const PolicyPtrs pp = bptt_policy_ptrs(b);
   const size_t sbytes = (size_t)C * A * 4;
   const float AT = (float)A * T;
   const float cp = 2.f * b->cfg.w_p / AT, cv = 2.f * b->cfg.w_v / AT, cu = 2.f * b->cfg.w_u / AT;
@@ -709,7 +749,7 @@ int bptt_backward(bptt_handle* b, const float* g_loss, float* g_theta, float* g_
       const LayerGrads& z = b->z[par];
       if (overlap && wsteps >= 2) DA_HIP(hipStreamWaitEvent(st, b->ev_w[par], 0));
       if ((rc = mlp_backward_data(A, pp, H1, H2, Y, b->gY, z, b->gX, st, b->prec, b,
-                                  overlap ? b->ev_z[par] : nullptr)))
+                                  overlap ? b->ev_z[par] : nullptr, b->z1_hi, b->z1_lo)))
         return rc;
       if (overlap) {
         DA_HIP(hipStreamWaitEvent(b->wgrad, b->ev_z[par], 0));

@@ -323,27 +323,123 @@ __device__ __forceinline__ void store_run_split(uint16_t* H, uint16_t* L, const 
   l4[1] = make_uint4(lp[4], lp[5], lp[6], lp[7]);
 }
 
-// Register staging of one operand tile in either layout.
-template <bool KMAJ>
+// One operand of the split GEMM: FP32 (K-major or M-major) or pre-split
+// BF16 hi / lo planes (K-major, K padded to a multiple of 32).
+struct SplitOp {
+  const float* f;
+  int ld;
+  const uint16_t *h, *l;
+  int lds;
+  int rows;
+};
+
+// Register staging of one operand tile. Modes: 0 = FP32 K-major, 1 = FP32
+// M-major, 2 = pre-split (32-byte runs of one row per thread, copied as is).
+enum { OP_F32_K = 0, OP_F32_M = 1, OP_SPLIT = 2 };
+template <int MODE>
 struct SplitStage;
 template <>
-struct SplitStage<true> {
+struct SplitStage<OP_F32_K> {
   float4 r[4];
-  __device__ void load(const float* P, int ld, int rows, int kend, int r0, int k0) {
-    load_tile<true>(P, ld, rows, kend, r0, k0, r);
-  }
+  __device__ void load(const SplitOp& o, int kend, int r0, int k0) { load_tile<true>(o.f, o.ld, o.rows, kend, r0, k0, r); }
   __device__ void store(uint16_t* H, uint16_t* L) const { store_tile_split_k(H, L, r); }
 };
 template <>
-struct SplitStage<false> {
+struct SplitStage<OP_F32_M> {
   float v[16];
-  __device__ void load(const float* P, int ld, int rows, int kend, int r0, int k0) {
-    load_run_m(P, ld, rows, kend, r0, k0, v);
-  }
+  __device__ void load(const SplitOp& o, int kend, int r0, int k0) { load_run_m(o.f, o.ld, o.rows, kend, r0, k0, v); }
   __device__ void store(uint16_t* H, uint16_t* L) const { store_run_split(H, L, v); }
 };
+template <>
+struct SplitStage<OP_SPLIT> {
+  uint4 h[2], l[2];
+  // split boundaries are multiples of 32 and the planes are zero padded, so a
+  // 32-wide chunk never needs a K bound
+  __device__ void load(const SplitOp& o, int, int r0, int k0) {
+    const int t = threadIdx.x, row = r0 + (t >> 1), k = k0 + (t & 1) * 16;
+    if (row < o.rows) {
+      const uint4* hp = reinterpret_cast<const uint4*>(o.h + (size_t)row * o.lds + k);
+      const uint4* lp = reinterpret_cast<const uint4*>(o.l + (size_t)row * o.lds + k);
+      h[0] = hp[0];
+      h[1] = hp[1];
+      l[0] = lp[0];
+      l[1] = lp[1];
+    } else {
+      h[0] = h[1] = l[0] = l[1] = make_uint4(0u, 0u, 0u, 0u);
+    }
+  }
+  __device__ void store(uint16_t* H, uint16_t* L) const {
+    const int t = threadIdx.x;
+    const int off = (t >> 1) * BKP + (t & 1) * 16;
+    uint4* h4 = reinterpret_cast<uint4*>(H + off);
+    uint4* l4 = reinterpret_cast<uint4*>(L + off);
+    h4[0] = h[0];
+    h4[1] = h[1];
+    l4[0] = l[0];
+    l4[1] = l[1];
+  }
+};
 
-template <bool AK, bool BK_, int EPI>
+__global__ void split_rows_kernel(int R, int K, const float* __restrict__ src, int ld,
+                                  uint16_t* __restrict__ hi, uint16_t* __restrict__ lo, int ldo) {
+  const int q = ldo >> 3;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= R * q) return;
+  const int r = idx / q, k = (idx % q) * 8;
+  uint32_t hp[4], lp[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const float a = k + 2 * j < K ? src[(size_t)r * ld + k + 2 * j] : 0.f;
+    const float b = k + 2 * j + 1 < K ? src[(size_t)r * ld + k + 2 * j + 1] : 0.f;
+    split2(a, b, hp[j], lp[j]);
+  }
+  *reinterpret_cast<uint4*>(hi + (size_t)r * ldo + k) = make_uint4(hp[0], hp[1], hp[2], hp[3]);
+  *reinterpret_cast<uint4*>(lo + (size_t)r * ldo + k) = make_uint4(lp[0], lp[1], lp[2], lp[3]);
+}
+
+int launch_split_rows(int R, int K, const float* src, int ld, uint16_t* hi, uint16_t* lo, int ldo,
+                      hipStream_t st) {
+  if ((ldo & 7) || ldo < K) return fail(SIM_EINVAL, "split_rows: ldo must be >= K and a multiple of 8");
+  const int tot = R * (ldo >> 3);
+  if (tot == 0) return SIM_OK;
+  hipLaunchKernelGGL(split_rows_kernel, dim3(cdiv(tot, 256)), dim3(256), 0, st, R, K, src, ld, hi, lo, ldo);
+  DA_LAUNCH_CHECK("split_rows_kernel");
+  return SIM_OK;
+}
+
+// 32 x 32 tiles through LDS: reads rows of src, writes rows of the transpose.
+__global__ void split_transpose_kernel(int R, int K, const float* __restrict__ src, int ld,
+                                       uint16_t* __restrict__ hi, uint16_t* __restrict__ lo, int ldo) {
+  __shared__ float tile[32][33];
+  const int r0 = blockIdx.y * 32, k0 = blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8 threads
+  for (int y = ty; y < 32; y += 8) {
+    const int r = r0 + y, k = k0 + tx;
+    tile[y][tx] = (r < R && k < K) ? src[(size_t)r * ld + k] : 0.f;
+  }
+  __syncthreads();
+  for (int y = ty; y < 32; y += 8) {
+    const int k = k0 + y, r = r0 + tx;
+    if (k < K && r < ldo) {
+      const float x = tile[tx][y];
+      const uint32_t h = bf16_bits(x);
+      hi[(size_t)k * ldo + r] = (uint16_t)h;
+      lo[(size_t)k * ldo + r] = (uint16_t)bf16_bits(x - __uint_as_float(h << 16));
+    }
+  }
+}
+
+int launch_split_transpose(int R, int K, const float* src, int ld, uint16_t* hi, uint16_t* lo, int ldo,
+                           hipStream_t st) {
+  if ((ldo & 7) || ldo < R) return fail(SIM_EINVAL, "split_transpose: ldo must be >= R and a multiple of 8");
+  if (R == 0 || K == 0) return SIM_OK;
+  dim3 grid(cdiv(K, 32), cdiv(ldo, 32));
+  hipLaunchKernelGGL(split_transpose_kernel, grid, dim3(256), 0, st, R, K, src, ld, hi, lo, ldo);
+  DA_LAUNCH_CHECK("split_transpose_kernel");
+  return SIM_OK;
+}
+
+template <int AM, int BM_, int EPI>
 __global__ __launch_bounds__(256) void gemm_x3_kernel(GemmArgs g) {
   __shared__ __attribute__((aligned(16))) uint16_t Ah[GBM * BKP];
   __shared__ __attribute__((aligned(16))) uint16_t Al[GBM * BKP];
@@ -361,11 +457,13 @@ __global__ __launch_bounds__(256) void gemm_x3_kernel(GemmArgs g) {
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int i = 0; i < 16; ++i) acc[a][b][i] = 0.f;
-  SplitStage<AK> sa;
-  SplitStage<BK_> sb;
+  const SplitOp oa{g.A, g.lda, g.A_hi, g.A_lo, g.lda_s, g.M};
+  const SplitOp ob{g.B, g.ldb, g.B_hi, g.B_lo, g.ldb_s, g.N};
+  SplitStage<AM> sa;
+  SplitStage<BM_> sb;
   if (kbeg < kend) {
-    sa.load(g.A, g.lda, g.M, kend, m0, kbeg);
-    sb.load(g.B, g.ldb, g.N, kend, n0, kbeg);
+    sa.load(oa, kend, m0, kbeg);
+    sb.load(ob, kend, n0, kbeg);
   }
   const int col = lane & 31, half = lane >> 5;
   for (int k0 = kbeg; k0 < kend; k0 += GBK) {
@@ -374,8 +472,8 @@ __global__ __launch_bounds__(256) void gemm_x3_kernel(GemmArgs g) {
     sb.store(Bh, Bl);
     __syncthreads();
     if (k0 + GBK < kend) {
-      sa.load(g.A, g.lda, g.M, kend, m0, k0 + GBK);
-      sb.load(g.B, g.ldb, g.N, kend, n0, k0 + GBK);
+      sa.load(oa, kend, m0, k0 + GBK);
+      sb.load(ob, kend, n0, k0 + GBK);
     }
 #pragma unroll
     for (int s = 0; s < GBK / 16; ++s) {
@@ -406,10 +504,10 @@ __global__ __launch_bounds__(256) void gemm_x3_kernel(GemmArgs g) {
   gemm_epilogue<EPI>(g, acc, m0, n0, wm, wn, col, half);
 }
 
-template <bool AK, bool BK_, int EPI>
+template <int AM, int BM_, int EPI>
 static int gemm_x3_t(const GemmArgs& g, int splits, hipStream_t st) {
   dim3 grid(cdiv(g.N, GBN), cdiv(g.M, GBM), splits);
-  hipLaunchKernelGGL((gemm_x3_kernel<AK, BK_, EPI>), grid, dim3(256), 0, st, g);
+  hipLaunchKernelGGL((gemm_x3_kernel<AM, BM_, EPI>), grid, dim3(256), 0, st, g);
   DA_LAUNCH_CHECK("gemm_x3_kernel");
   return SIM_OK;
 }
@@ -433,13 +531,28 @@ int launch_gemm(bool a_kmaj, bool b_kmaj, int epi, GemmArgs g, int splits, hipSt
     return fail(SIM_EINVAL, "gemm: operands need 16-byte alignment and leading dims %% 4 == 0");
   const int key = (a_kmaj ? 1 : 0) | (b_kmaj ? 2 : 0);
   if (prec == GEMM_BF16X3) {
+    const bool as = g.A_hi != nullptr, bs = g.B_hi != nullptr;
+    if ((as && (!g.A_lo || (g.lda_s % kSplitPad) || (reinterpret_cast<uintptr_t>(g.A_hi) & 15) ||
+                (reinterpret_cast<uintptr_t>(g.A_lo) & 15))) ||
+        (bs && (!g.B_lo || (g.ldb_s % kSplitPad) || (reinterpret_cast<uintptr_t>(g.B_hi) & 15) ||
+                (reinterpret_cast<uintptr_t>(g.B_lo) & 15))))
+      return fail(SIM_EINVAL, "gemm: pre-split operands need hi and lo, ld %% 32 == 0, 16-byte alignment");
     // the layer shapes of the policy MLP
-    if (key == 3 && epi == EPI_BIAS_TANH) return gemm_x3_t<true, true, EPI_BIAS_TANH>(g, 1, st);
-    if (key == 1 && epi == EPI_MUL_DTANH) return gemm_x3_t<true, false, EPI_MUL_DTANH>(g, 1, st);
-    if (key == 1 && epi == EPI_STORE) return gemm_x3_t<true, false, EPI_STORE>(g, 1, st);
-    if (key == 0 && epi == EPI_PARTIAL) return gemm_x3_t<false, false, EPI_PARTIAL>(g, splits, st);
-    if (key == 3 && epi == EPI_PARTIAL) return gemm_x3_t<true, true, EPI_PARTIAL>(g, splits, st);
-    return fail(SIM_EINVAL, "gemm: bf16x3 layout %d / epilogue %d not built", key, epi);
+    constexpr int K_ = OP_F32_K, M_ = OP_F32_M, S_ = OP_SPLIT;
+    if (!as && !bs) {
+      if (key == 3 && epi == EPI_BIAS_TANH) return gemm_x3_t<K_, K_, EPI_BIAS_TANH>(g, 1, st);
+      if (key == 1 && epi == EPI_MUL_DTANH) return gemm_x3_t<K_, M_, EPI_MUL_DTANH>(g, 1, st);
+      if (key == 1 && epi == EPI_STORE) return gemm_x3_t<K_, M_, EPI_STORE>(g, 1, st);
+      if (key == 0 && epi == EPI_PARTIAL) return gemm_x3_t<M_, M_, EPI_PARTIAL>(g, splits, st);
+      if (key == 3 && epi == EPI_PARTIAL) return gemm_x3_t<K_, K_, EPI_PARTIAL>(g, splits, st);
+    } else if (!as && bs) {  // a pre-split operand is K-major whatever b_kmaj says
+      if (a_kmaj && epi == EPI_PARTIAL) return gemm_x3_t<K_, S_, EPI_PARTIAL>(g, splits, st);
+      if (a_kmaj && epi == EPI_BIAS_TANH) return gemm_x3_t<K_, S_, EPI_BIAS_TANH>(g, 1, st);
+    } else if (as && bs) {
+      if (epi == EPI_STORE) return gemm_x3_t<S_, S_, EPI_STORE>(g, 1, st);
+    }
+    return fail(SIM_EINVAL, "gemm: bf16x3 layout %d (split A %d, B %d) / epilogue %d not built", key, (int)as,
+                (int)bs, epi);
   }
   if (prec == GEMM_BF16) {
     // the layer shapes of the residual-dynamics MLP

@@ -39,7 +39,24 @@ struct GemmArgs {
   float obs_scale = 1.f, obs_c = 0.f, obs_beta = 1.f, obs_d = 0.f, obs_dmax = 1.f;
   const float* obs_gl = nullptr;  // EPI_OBS_GRAD: device scale of obs_c (nullable = 1)
   int k_split = 0;              // set by launch_gemm
+  // GEMM_BF16X3 only, optional: operands already split into BF16 hi / lo
+  // planes, K-major ([M or N][ld_s] with the K dimension contiguous and zero
+  // padded to a multiple of 32). When set, they replace A / B.
+  const uint16_t *A_hi = nullptr, *A_lo = nullptr;
+  int lda_s = 0;
+  const uint16_t *B_hi = nullptr, *B_lo = nullptr;
+  int ldb_s = 0;
 };
+
+// Split of FP32 rows into BF16 hi = bf16(x) and lo = bf16(x - hi) planes:
+// dst[r][k] for k < ldo (ldo % 8 == 0), zero beyond K.
+int launch_split_rows(int R, int K, const float* src, int ld, uint16_t* hi, uint16_t* lo, int ldo,
+                      hipStream_t st);
+// Same, transposed: dst[k][r] = split(src[r][k]) for k < K, r < ldo
+// (ldo % 8 == 0), zero for r >= R.
+int launch_split_transpose(int R, int K, const float* src, int ld, uint16_t* hi, uint16_t* lo, int ldo,
+                           hipStream_t st);
+constexpr int kSplitPad = 32;  // K padding of pre-split operands
 
 // Precision of launch_gemm:
 //  GEMM_FP32:   v_mfma_f32_32x32x2f32 on FP32 operands;
