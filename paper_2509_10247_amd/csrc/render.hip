@@ -48,22 +48,16 @@ __global__ __launch_bounds__(256) void render_work_kernel(SceneDev sc, SensorDev
 // ---------------------------------------------------------------------------
 // Sphere hits: dt/do = -n/(n.d) is ill-conditioned near silhouettes (in FP32
 // the discriminant r^2 - |perp|^2 of a grazing ray loses relative precision as
-// 1/(n.d)^2), so sphere hits within ~17 deg of grazing (|n.d| < 0.3) are
-// evaluated in FP64 from an FP64 direction table and an FP64 rotation; the
-// others, and plane hits (box entry face, room exit face: dt/do_f = -1/d_f,
-// well conditioned for every hit inside the sensor range), in FP32.
-// Per-thread sums and the per-agent reduction are FP64.
+// 1/(n.d)^2), so for sphere hits within ~17 deg of grazing (|n.d| < 0.3) the
+// discriminant is formed in FP64 from an FP64 direction table and an FP64
+// rotation; the others, and plane hits (box entry face, room exit face:
+// dt/do_f = -1/d_f, well conditioned for every hit inside the sensor range),
+// are FP32. Per-thread sums are FP32, the per-agent reduction FP64.
 struct d3 {
   double x, y, z;
 };
 __device__ __forceinline__ d3 dk3(double x, double y, double z) { return d3{x, y, z}; }
 __device__ __forceinline__ double ddot(d3 a, d3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
-// 1/x: hardware reciprocal estimate refined by one Newton step (full FP64).
-__device__ __forceinline__ double rcp64(double x) {
-  const double r = __builtin_amdgcn_rcp(x);
-  const double e = fma(-x, r, 1.0);
-  return fma(r, e, r);
-}
 
 // Unit quaternion qn = q/|q| of agent i (FP64), 1/|q| and the rotation R(qn).
 __device__ __forceinline__ void agent_frame64(const float* __restrict__ s, int A, int i, double (&qn)[4],
@@ -224,19 +218,22 @@ __global__ __launch_bounds__(256, 5) void render_vjp_kernel(SceneDev sc, SensorD
                                Rsh[2][0] * dbv.x + Rsh[2][1] * dbv.y + Rsh[2][2] * dbv.z)
                          : dbv;
         // t = tc - sqrt(disc) and, at the hit point, n.d = -sqrt(disc)/r, so
-        // dt/do = -n/(n.d) = (t d - w)/sqrt(disc) and dt/dd = t dt/do
+        // dt/do = -n/(n.d) = (t d - w)/sqrt(disc) and dt/dd = t dt/do.
+        // Only the discriminant (a difference of nearly equal squares near
+        // grazing) and t d - w (|w| >> r) need FP64; the square root and
+        // reciprocals of the well-scaled results are FP32.
         const d3 w = dk3(c.x - (double)o.x, c.y - (double)o.y, c.z - (double)o.z);
         const double C = ddot(w, w) - rad * rad;
         const double tc = ddot(d, w);
         const d3 p = dk3(w.x - tc * d.x, w.y - tc * d.y, w.z - tc * d.z);
         const double disc = rad * rad - ddot(p, p);
         if (!(disc > 0.0)) continue;
-        const double sq = sqrt(disc);
-        const double t = C * rcp64(tc + sq);
-        const double is = rcp64(sq);
-        const double ox = (t * d.x - w.x) * is, oy = (t * d.y - w.y) * is, oz = (t * d.z - w.z) * is;
-        dto = mk3((float)ox, (float)oy, (float)oz);
-        dtd = mk3((float)(t * ox), (float)(t * oy), (float)(t * oz));
+        const float sq = __builtin_amdgcn_sqrtf((float)disc);
+        const float t = (float)C * __builtin_amdgcn_rcpf((float)tc + sq);
+        const float is = __builtin_amdgcn_rcpf(sq);
+        const double td = (double)t;
+        dto = mk3((float)(td * d.x - w.x) * is, (float)(td * d.y - w.y) * is, (float)(td * d.z - w.z) * is);
+        dtd = scl(dto, t);
       }
     } else {
       // box entry face or room exit face: t = (plane_f - o_f) / d_f
@@ -337,7 +334,7 @@ int launch_render(const SceneDev& sc, const SensorDev& sen, bool rotate, bool cu
                   float* term, float beta, float d_safe) {
   if (A == 0) return SIM_OK;
   const int P = sc.max_prims > 0 ? sc.max_prims : 1;
-  const size_t lds = render_lds_bytes(P);
+  const size_t lds = render_lds_bytes(P, sen.n_tiles);
   if (rotate) {
     if (cull)
       hipLaunchKernelGGL((render_kernel<true, true>), dim3(A), dim3(256), lds, st, sc, sen, s, A, out, rec, out_ld, out_scale, term, beta, d_safe);
@@ -357,7 +354,7 @@ int launch_render_work(const SceneDev& sc, const SensorDev& sen, bool rotate, bo
                        const float* s, int A, float* out, int* work, hipStream_t st) {
   if (A == 0) return SIM_OK;
   const int P = sc.max_prims > 0 ? sc.max_prims : 1;
-  const size_t lds = render_lds_bytes(P);
+  const size_t lds = render_lds_bytes(P, sen.n_tiles);
   const int ld = sen.n_rays;
   if (rotate) {
     if (cull)

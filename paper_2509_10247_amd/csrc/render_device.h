@@ -17,6 +17,7 @@ struct RenderLds {
   float2* pd;  // (rho, L - rho); rho < 0: never hit
   short* lists;
   int* flag;
+  float4* ax;  // per tile of the call: (world cone axis, cos of the half-angle)
 };
 
 __device__ __forceinline__ RenderLds carve(void* base, int P) {
@@ -27,12 +28,15 @@ __device__ __forceinline__ RenderLds carve(void* base, int P) {
   L.pd = reinterpret_cast<float2*>(L.pc + P);
   L.flag = reinterpret_cast<int*>(L.pd + P);
   L.lists = reinterpret_cast<short*>(L.flag + 4);
+  L.ax = reinterpret_cast<float4*>(reinterpret_cast<char*>(base) + 64 * (size_t)P + 32);
   return L;
 }
 
-inline size_t render_lds_bytes(int P) {
-  return (size_t)P * (3 * sizeof(float4) + sizeof(float2)) + 4 * sizeof(int) +
-         (size_t)4 * P * sizeof(short) + 16;
+// P primitives (48 + 8 B each, 4 per-wave index lists of 2 B each), the flag
+// word and the rotated cone axes of up to T tiles.
+inline size_t render_lds_bytes(int P, int T) {
+  static_assert(3 * sizeof(float4) + sizeof(float2) + 4 * sizeof(short) == 64, "render LDS layout");
+  return 64 * (size_t)P + 32 + 16 * (size_t)T;
 }
 
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
@@ -214,6 +218,12 @@ __device__ __forceinline__ void render_one_agent(const SceneDev& sc, const Senso
                      rhi.z < 0.f))
       ins = true;
   }
+  if (CULL)
+    for (int tt = tid; tt < tile_end - tile_begin; tt += 256) {
+      const float4 ca = sen.cone_a[tile_begin + tt];
+      const f3 ax = ROT ? rot_apply(R, mk3(ca.x, ca.y, ca.z)) : mk3(ca.x, ca.y, ca.z);
+      L.ax[tt] = make_float4(ax.x, ax.y, ax.z, ca.w);
+    }
   if (ins) atomicOr(L.flag, 1);
   __syncthreads();
   const bool inside = *L.flag != 0;
@@ -238,9 +248,9 @@ __device__ __forceinline__ void render_one_agent(const SceneDev& sc, const Senso
     }
     int ks = ns, kb = nb, nk = np;
     if (CULL) {
-      const float4 ca = sen.cone_a[tile];
+      const float4 ca = L.ax[tile - tile_begin];
       const float4 cb = sen.cone_b[tile];
-      const f3 ax = ROT ? rot_apply(R, mk3(ca.x, ca.y, ca.z)) : mk3(ca.x, ca.y, ca.z);
+      const f3 ax = mk3(ca.x, ca.y, ca.z);
       int cnt = 0, cs = 0, cbx = 0;
       for (int base = 0; base < np; base += 64) {
         const int k = base + lane;

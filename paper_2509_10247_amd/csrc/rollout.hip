@@ -262,7 +262,9 @@ static int ensure_plan(sim_handle* h, RolloutPlan* p, int T) {
 static int enqueue_rollout(sim_handle* h, RolloutPlan* p, int T, float* s, const float* a_seq, float* depth_ring,
                            float* lidar_ring, uint8_t* flags, bool fused, hipStream_t st) {
   const int A = h->cfg.n_agents, C = state_dim(h->cfg.model), K = action_dim(h->cfg.model);
-  const size_t lds = render_lds_bytes(h->scene.max_prims > 0 ? h->scene.max_prims : 1);
+  const size_t lds = render_lds_bytes(h->scene.max_prims > 0 ? h->scene.max_prims : 1,
+                                      std::max(h->cam.mem ? h->cam.dev.n_tiles : 0,
+                                               h->lidar.mem ? h->lidar.dev.n_tiles : 0));
   const bool rot = h->cfg.model == SIM_RB13 || h->cfg.model == SIM_NOMINAL13;
   if (fused) {
     hipLaunchKernelGGL(zero_ints_kernel, dim3(cdiv(T, 256)), dim3(256), 0, st, p->counters, T);

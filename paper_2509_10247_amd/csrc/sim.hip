@@ -301,9 +301,11 @@ int sim_set_scene(sim_handle* h, const int32_t* sph_off, const float* sph, int32
     int dev = 0, lds_max = 0;
     DA_HIP(hipGetDevice(&dev));
     DA_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    DA_REQUIRE(render_lds_bytes(maxp > 0 ? maxp : 1) <= (size_t)lds_max,
-               "sim_set_scene: %d primitives in one env need %zu B of LDS per workgroup (device: %d)",
-               maxp, render_lds_bytes(maxp), lds_max);
+    const int nt = std::max(h->cam.mem ? h->cam.dev.n_tiles : 0, h->lidar.mem ? h->lidar.dev.n_tiles : 0);
+    const size_t need = render_lds_bytes(maxp > 0 ? maxp : 1, nt);
+    DA_REQUIRE(need <= (size_t)lds_max,
+               "sim_set_scene: %d primitives in one env and %d sensor tiles need %zu B of LDS per "
+               "workgroup (device: %d)", maxp, nt, need, lds_max);
   }
   std::vector<int32_t> env_of(A);
   for (int e = 0; e < E; ++e)
