@@ -18,6 +18,7 @@ struct RenderLds {
   short* lists;
   int* flag;
   float4* ax;  // per tile of the call: (world cone axis, cos of the half-angle)
+  int P;       // primitive capacity (stride of the per-wave lists)
 };
 
 __device__ __forceinline__ RenderLds carve(void* base, int P) {
@@ -29,6 +30,7 @@ __device__ __forceinline__ RenderLds carve(void* base, int P) {
   L.flag = reinterpret_cast<int*>(L.pd + P);
   L.lists = reinterpret_cast<short*>(L.flag + 4);
   L.ax = reinterpret_cast<float4*>(reinterpret_cast<char*>(base) + 64 * (size_t)P + 32);
+  L.P = P;
   return L;
 }
 
@@ -132,21 +134,23 @@ __device__ __forceinline__ Rot agent_rot(const float* s, int A, int i) {
 // Work counters written per agent and wavefront by the WORK variant.
 enum { kWorkRays = 0, kWorkSph, kWorkBox, kWorkAgt, kWorkTiles, kWorkCone, kWorkN };
 
-// Renders tiles [tile_begin, tile_end) of one agent's sensor with the whole
-// workgroup (256 threads); LDS is re-staged on entry, so consecutive calls
-// from one workgroup (the persistent rollout kernel) are safe. The WORK
-// variant also writes, per wavefront, the rays it cast and the ray-primitive
-// tests and tile-cone tests it ran to work[(i * 4 + wave) * kWorkN + c].
-template <bool ROT, bool CULL, bool WORK = false>
-__device__ __forceinline__ void render_one_agent(const SceneDev& sc, const SensorDev& sen,
-                                                 const float* __restrict__ s, int A, int i,
-                                                 int tile_begin, int tile_end, float* __restrict__ out,
-                                                 int* __restrict__ rec, int out_ld, float out_scale,
-                                                 float* __restrict__ term, float beta, float d_safe,
-                                                 void* smem, int* __restrict__ work = nullptr) {
-  const int P = sc.max_prims > 0 ? sc.max_prims : 1;
-  RenderLds L = carve(smem, P);
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+// An agent's environment staged in LDS (origin-relative primitives, cone
+// terms) with the values every tile of every sensor of that agent needs.
+struct AgentStage {
+  int i, ns, nb, np;
+  f3 o;
+  Rot R;
+  bool has_room, inside;
+  f3 rlo, rhi;
+};
+
+// Stages agent i's environment with the whole workgroup (256 threads); LDS
+// is re-staged on entry, so consecutive calls from one workgroup (the
+// persistent rollout kernel) are safe.
+template <bool ROT>
+__device__ __forceinline__ AgentStage stage_agent(const SceneDev& sc, const float* __restrict__ s, int A, int i,
+                                                  RenderLds& L) {
+  const int tid = threadIdx.x;
   __syncthreads();  // previous use of the LDS by this workgroup is complete
   const int env = sc.agent_env[i];
   const f3 o = mk3(s[i], s[(size_t)A + i], s[2 * (size_t)A + i]);
@@ -162,7 +166,6 @@ __device__ __forceinline__ void render_one_agent(const SceneDev& sc, const Senso
   const int np = ns + nb + na;
   if (tid == 0) *L.flag = 0;
   __syncthreads();
-
   bool ins = false;
   for (int k = tid; k < np; k += 256) {
     if (k < ns) {
@@ -218,19 +221,49 @@ __device__ __forceinline__ void render_one_agent(const SceneDev& sc, const Senso
                      rhi.z < 0.f))
       ins = true;
   }
+  if (ins) atomicOr(L.flag, 1);
+  __syncthreads();
+  AgentStage st;
+  st.i = i;
+  st.ns = ns;
+  st.nb = nb;
+  st.np = np;
+  st.o = o;
+  st.R = R;
+  st.has_room = has_room;
+  st.inside = *L.flag != 0;
+  st.rlo = rlo;
+  st.rhi = rhi;
+  return st;
+}
+
+// Renders tiles [tile_begin, tile_end) of one sensor of a staged agent with
+// the whole workgroup. The WORK variant also writes, per wavefront, the rays
+// it cast and the ray-primitive tests and tile-cone tests it ran to
+// work[(i * 4 + wave) * kWorkN + c].
+template <bool ROT, bool CULL, bool WORK = false>
+__device__ __forceinline__ void render_tiles(const AgentStage& ag, const SensorDev& sen, RenderLds& L,
+                                             int tile_begin, int tile_end, float* __restrict__ out,
+                                             int* __restrict__ rec, int out_ld, float out_scale,
+                                             float* __restrict__ term, float beta, float d_safe,
+                                             int* __restrict__ work = nullptr) {
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int i = ag.i, ns = ag.ns, nb = ag.nb, np = ag.np;
+  const Rot& R = ag.R;
+  const bool has_room = ag.has_room, inside = ag.inside;
+  const f3 rlo = ag.rlo, rhi = ag.rhi;
+  __syncthreads();  // the previous sensor's tiles are done with the axes and lists
   if (CULL)
     for (int tt = tid; tt < tile_end - tile_begin; tt += 256) {
       const float4 ca = sen.cone_a[tile_begin + tt];
       const f3 ax = ROT ? rot_apply(R, mk3(ca.x, ca.y, ca.z)) : mk3(ca.x, ca.y, ca.z);
       L.ax[tt] = make_float4(ax.x, ax.y, ax.z, ca.w);
     }
-  if (ins) atomicOr(L.flag, 1);
   __syncthreads();
-  const bool inside = *L.flag != 0;
   const int nr = sen.n_rays;
   float* orow = out + (size_t)i * out_ld;
   int* rrow = rec ? rec + (size_t)i * nr : nullptr;
-  short* list = L.lists + wave * P;
+  short* list = L.lists + wave * L.P;
   const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   float tacc = 0.f;  // optional per-agent sum of softplus(beta (d_safe - value))
   const float inv_beta = term ? 1.0f / beta : 0.f;
@@ -339,11 +372,26 @@ __device__ __forceinline__ void render_one_agent(const SceneDev& sc, const Senso
     // fixed-order reduction: butterfly within each wave, then waves 0..3
     for (int off = 32; off > 0; off >>= 1) tacc += __shfl_xor(tacc, off);
     __syncthreads();
-    float* wsum = reinterpret_cast<float*>(L.pa);
+    float* wsum = reinterpret_cast<float*>(L.ax);  // re-staged by the next render_tiles
     if (lane == 0) wsum[wave] = tacc;
     __syncthreads();
     if (tid == 0) term[i] = (((wsum[0] + wsum[1]) + wsum[2]) + wsum[3]) * (inv_beta / (float)nr);
   }
+}
+
+
+// Stage + render of one sensor (the launch-per-op render kernels).
+template <bool ROT, bool CULL, bool WORK = false>
+__device__ __forceinline__ void render_one_agent(const SceneDev& sc, const SensorDev& sen,
+                                                 const float* __restrict__ s, int A, int i,
+                                                 int tile_begin, int tile_end, float* __restrict__ out,
+                                                 int* __restrict__ rec, int out_ld, float out_scale,
+                                                 float* __restrict__ term, float beta, float d_safe,
+                                                 void* smem, int* __restrict__ work = nullptr) {
+  RenderLds L = carve(smem, sc.max_prims > 0 ? sc.max_prims : 1);
+  const AgentStage ag = stage_agent<ROT>(sc, s, A, i, L);
+  render_tiles<ROT, CULL, WORK>(ag, sen, L, tile_begin, tile_end, out, rec, out_ld, out_scale, term, beta,
+                                d_safe, work);
 }
 
 __device__ __forceinline__ float collide_one(const SceneDev& sc, const float* __restrict__ s, int A,

@@ -4,7 +4,9 @@
 //
 // Work items of one step (all read s_t only, so no grid-wide barrier is
 // needed inside a step):
-//   - render item: tiles [tb, te) of one agent's camera or LiDAR at s_t;
+//   - agent item: tiles [tb, te) of one agent's sensors at s_t, in the
+//     combined tile index space (camera tiles, then LiDAR tiles); the
+//     agent's environment is staged in LDS once for both sensors;
 //   - dynamics item: 256 agents' collision distance at s_t and their step
 //     s_{t+1} = step(s_t, a_t), written to the other state buffer.
 // Items are ordered longest-first by an estimated cost (rays x primitives of
@@ -29,7 +31,7 @@
 
 namespace da {
 
-enum { ITEM_CAM = 0, ITEM_LIDAR = 1, ITEM_DYN = 2 };
+enum { ITEM_AGENT = 0, ITEM_DYN = 2 };
 
 struct RolloutArgs {
   SceneDev sc;
@@ -80,7 +82,7 @@ constexpr bool rotates_m() {
 }
 
 template <int M, int I, bool CULL>
-__global__ __launch_bounds__(256) void rollout_fused_kernel(RolloutArgs g) {
+__global__ __launch_bounds__(256, 6) void rollout_fused_kernel(RolloutArgs g) {
   extern __shared__ float4 smem_f4[];
   __shared__ int cur;
   for (;;) {
@@ -90,14 +92,22 @@ __global__ __launch_bounds__(256) void rollout_fused_kernel(RolloutArgs g) {
     __syncthreads();  // every thread has read the ticket before it is replaced
     if (it >= g.n_items) break;  // uniform over the workgroup: all waves exit
     const int4 w = g.items[it];
-    if (w.x == ITEM_DYN)
+    if (w.x == ITEM_DYN) {
       dyn_item<M, I>(g, w.y);
-    else if (w.x == ITEM_CAM)
-      render_one_agent<rotates_m<M>(), CULL>(g.sc, g.cam, g.s, g.A, w.y, w.z, w.w, g.depth, nullptr,
-                                             g.cam.n_rays, 1.f, nullptr, 1.f, 0.f, smem_f4);
-    else
-      render_one_agent<rotates_m<M>(), CULL>(g.sc, g.lidar, g.s, g.A, w.y, w.z, w.w, g.lidar_out, nullptr,
-                                             g.lidar.n_rays, 1.f, nullptr, 1.f, 0.f, smem_f4);
+    } else {
+      constexpr bool ROT = rotates_m<M>();
+      RenderLds L = carve(smem_f4, g.sc.max_prims > 0 ? g.sc.max_prims : 1);
+      const AgentStage ag = stage_agent<ROT>(g.sc, g.s, g.A, w.y, L);
+      const int nc = g.depth ? g.cam.n_tiles : 0;
+      // one copy of the tile loop for both sensors
+      for (int part = 0; part < 2; ++part) {
+        const int b = part ? max(w.z, nc) - nc : w.z, e = part ? w.w - nc : min(w.w, nc);
+        if (b >= e) continue;
+        const SensorDev& sen = part ? g.lidar : g.cam;
+        render_tiles<ROT, CULL>(ag, sen, L, b, e, part ? g.lidar_out : g.depth, nullptr, sen.n_rays, 1.f,
+                                nullptr, 1.f, 0.f);
+      }
+    }
   }
 }
 
@@ -202,20 +212,16 @@ static int build_items(sim_handle* h, RolloutPlan* p) {
   for (int e = 0; e < h->cfg.n_envs; ++e) {
     int np = (so[e + 1] - so[e]) + (bo[e + 1] - bo[e]);
     if (h->cfg.agents_visible) np += ao[e + 1] - ao[e];
-    for (int i = ao[e]; i < ao[e + 1]; ++i) {
-      const SensorBuf* sens[2] = {&h->cam, &h->lidar};
-      for (int k = 0; k < 2; ++k) {
-        if (!sens[k]->mem) continue;
-        const int nt = sens[k]->dev.n_tiles;
-        const int tg = std::max(1, std::min(p->tile_group, nt));
-        for (int tb = 0; tb < nt; tb += tg) {
-          const int te = std::min(nt, tb + tg);
-          // staging cost + per-tile culling pass + casting against the env
-          const double cost = 4.0 * np + (te - tb) * (64.0 + 8.0 * (np + 6));
-          items.push_back({cost, make_int4(k == 0 ? ITEM_CAM : ITEM_LIDAR, i, tb, te)});
-        }
+    // combined tile index space: camera tiles, then LiDAR tiles
+    const int nt = (h->cam.mem ? h->cam.dev.n_tiles : 0) + (h->lidar.mem ? h->lidar.dev.n_tiles : 0);
+    const int tg = std::max(1, std::min(p->tile_group, nt));
+    for (int i = ao[e]; i < ao[e + 1]; ++i)
+      for (int tb = 0; tb < nt; tb += tg) {
+        const int te = std::min(nt, tb + tg);
+        // staging cost + per-tile culling pass + casting against the env
+        const double cost = 4.0 * np + (te - tb) * (64.0 + 8.0 * (np + 6));
+        items.push_back({cost, make_int4(ITEM_AGENT, i, tb, te)});
       }
-    }
   }
   for (int b = 0; b < cdiv(A, 256); ++b) items.push_back({2000.0, make_int4(ITEM_DYN, b, 0, 0)});
   if (p->order == 1)
