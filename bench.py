@@ -331,7 +331,7 @@ def measured_traffic(files, profile):
     return rec
 
 
-def dominant_roofline(tm, e, s0, A, gemm_mode, store):
+def dominant_roofline(tm, e, s0, A, T, K, gemm_mode, store):
     """Roofline of the kernel class with the largest total time in one
     iteration: algorithmic work per launch / average launch duration (HIP
     events on the kernels' stream)."""
@@ -353,17 +353,24 @@ def dominant_roofline(tm, e, s0, A, gemm_mode, store):
             base["note"] = "FP32 product from three BF16 MFMA products: executed MFMA work is 3x"
         return base
     if dom == "render":
-        # half of the launches are the forward pass (observation row written,
-        # obstacle term fused), half the backward's recompute (observation
-        # row and hit record; the term only without stored activations)
+        # launches: T forward renders (observation row, obstacle term fused;
+        # with stored activations the last two segments also write hit
+        # records) and the backward's recompute of the other segments
+        # (observation row and hit record; the term only without stored
+        # activations, where every segment is recomputed)
         f_term, cnt = render_work_flops(e, s0, term=True)
         f_plain, _ = render_work_flops(e, s0, term=False)
-        flops = 0.5 * f_term + 0.5 * (f_plain if store else f_term)
+        nseg = -(-T // K)
+        kept = (T - max(0, nseg - 2) * K) if store else 0
+        n_rec = T - kept
+        assert T + n_rec == tm[dom][1], "render launch count"
+        flops = (T * f_term + n_rec * (f_plain if store else f_term)) / (T + n_rec)
         ach = flops / avg_s
         n_env = e.n_envs
-        # algorithmic bytes: 4 B per ray written forward, 8 B in the recompute;
-        # read once: each env's 24 spheres, 16 boxes and room, and the state
-        written = cnt["rays"] * 6.0
+        # algorithmic bytes: 4 B per ray for the observation value, 4 B more
+        # where the hit record is written; read once: each env's 24 spheres,
+        # 16 boxes and room, and the state
+        written = cnt["rays"] * (4.0 * T + 4.0 * kept + 8.0 * n_rec) / (T + n_rec)
         read = n_env * (24 * 16 + 16 * 24 + 24) + A * 13 * 4
         base.update({"bound": "alu", "achieved": round(ach / 1e12, 2), "peak": PEAK_FP32_VALU / 1e12,
                      "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_VALU, 4),
@@ -462,7 +469,7 @@ def main():
         _lib.bptt_set_timing(eng.h, 0)
         breakdown = {k: {"ms_total": round(v[0], 3), "launches": v[1],
                          "ms_avg": round(v[0] / max(v[1], 1), 4)} for k, v in tm.items()}
-        roofline = dominant_roofline(tm, e, s0, A, gemm_mode, not args.recompute_all)
+        roofline = dominant_roofline(tm, e, s0, A, T, K, gemm_mode, not args.recompute_all)
 
     line = {
         "metric": "env-steps/sec fwd+bwd with 64x48 depth",

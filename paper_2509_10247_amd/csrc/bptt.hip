@@ -406,6 +406,10 @@ static void tpair(bptt_handle* b, int cls, int a, int z) {
 }
 }  // namespace da
 
+// Segments whose observations and hit records the forward leaves in the two
+// sets (stored mode): the last two.
+static bool kept_segment(const bptt_handle* b, int seg) { return b->store && seg >= b->nseg - 2; }
+
 static PolicyPtrs bptt_policy_ptrs(const bptt_handle* b) {
   PolicyPtrs p = policy_ptrs(b->theta, b->W1p);
   p.W1s_hi = b->W1s_hi;
@@ -608,6 +612,7 @@ int bptt_forward(bptt_handle* b, const float* theta, const float* s0, const floa
   const size_t sbytes = (size_t)C * A * 4;
   DA_HIP(hipMemcpyAsync(b->seg_s, s0, sbytes, hipMemcpyDeviceToDevice, st));
   LossW w{b->cfg.w_p, b->cfg.w_v, b->cfg.w_u, b->cfg.w_o, b->cfg.beta, b->cfg.d_safe};
+  const size_t xset = (size_t)K * A * kObsPad, hset = (size_t)K * A * kRays;
   for (int t = 0; t < T; ++t) {
     // stored mode: state t in slot t; otherwise two ping-pong slots
     const int si = b->store ? t : (t & 1), so = b->store ? t + 1 : ((t + 1) & 1);
@@ -616,7 +621,16 @@ int bptt_forward(bptt_handle* b, const float* theta, const float* s0, const floa
     float* nxt = b->seg_s + (size_t)so * C * A;
     if (!b->store && t % K == 0)
       DA_HIP(hipMemcpyAsync(b->ckpt + (size_t)(t / K) * C * A, cur, sbytes, hipMemcpyDeviceToDevice, st));
-    if ((rc = forward_step(b, pp, cur, nxt, b->X, nullptr, b->H1 + (size_t)a * A * kHid,
+    // stored mode: the last two segments render straight into the two
+    // observation / hit-record sets, which the backward then does not recompute
+    float* X = b->X;
+    int* hit = nullptr;
+    const int seg = t / K;
+    if (kept_segment(b, seg)) {
+      X = b->X + (size_t)(seg & 1) * xset + (size_t)(t % K) * A * kObsPad;
+      hit = b->hit + (size_t)(seg & 1) * hset + (size_t)(t % K) * A * kRays;
+    }
+    if ((rc = forward_step(b, pp, cur, nxt, X, hit, b->H1 + (size_t)a * A * kHid,
                            b->H2 + (size_t)a * A * kHid, b->Y + (size_t)a * A * kOut,
                            b->act + (size_t)a * Ka * A, st)))
       return rc;
@@ -675,7 +689,7 @@ int bptt_backward(bptt_handle* b, const float* g_loss, float* g_theta, float* g_
   // every timed kernel runs alone
   const bool overlap = b->store && !b->timing;
   if (b->store && !overlap) {
-    if ((rc = recompute_renders(b->nseg - 1, st))) return rc;
+    if (!kept_segment(b, b->nseg - 1) && (rc = recompute_renders(b->nseg - 1, st))) return rc;
   } else if (overlap) {
     if (!b->side) {
       DA_HIP(hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking));
@@ -689,7 +703,7 @@ int bptt_backward(bptt_handle* b, const float* g_loss, float* g_theta, float* g_
     DA_HIP(hipEventRecord(b->ev_start, st));
     DA_HIP(hipStreamWaitEvent(b->side, b->ev_start, 0));
     DA_HIP(hipStreamWaitEvent(b->wgrad, b->ev_start, 0));
-    if ((rc = recompute_renders(b->nseg - 1, b->side))) return rc;
+    if (!kept_segment(b, b->nseg - 1) && (rc = recompute_renders(b->nseg - 1, b->side))) return rc;
     DA_HIP(hipEventRecord(b->ev_rec[(b->nseg - 1) & 1], b->side));
   }
   int wsteps = 0;  // weight-gradient steps enqueued on the wgrad stream
@@ -697,12 +711,14 @@ int bptt_backward(bptt_handle* b, const float* g_loss, float* g_theta, float* g_
     const int t0 = seg * K, n = std::min(T, t0 + K) - t0;
     const int set = b->store ? (seg & 1) : 0;
     if (b->store && !overlap) {
-      if (seg > 0 && (rc = recompute_renders(seg - 1, st))) return rc;
+      if (seg > 0 && !kept_segment(b, seg - 1) && (rc = recompute_renders(seg - 1, st))) return rc;
     } else if (overlap) {
       if (seg > 0) {
-        // set (seg-1)&1 was last read by the sweep of seg+1
-        if (seg + 1 <= b->nseg - 1) DA_HIP(hipStreamWaitEvent(b->side, b->ev_free[(seg - 1) & 1], 0));
-        if ((rc = recompute_renders(seg - 1, b->side))) return rc;
+        if (!kept_segment(b, seg - 1)) {
+          // set (seg-1)&1 was last read by the sweep of seg+1
+          if (seg + 1 <= b->nseg - 1) DA_HIP(hipStreamWaitEvent(b->side, b->ev_free[(seg - 1) & 1], 0));
+          if ((rc = recompute_renders(seg - 1, b->side))) return rc;
+        }
         DA_HIP(hipEventRecord(b->ev_rec[(seg - 1) & 1], b->side));
       }
       DA_HIP(hipStreamWaitEvent(st, b->ev_rec[set], 0));
