@@ -42,10 +42,12 @@ static_assert(kOffB3 + kOut == POLICY_N_PARAMS, "policy parameter layout");
 // ---------------------------------------------------------------------------
 // Fills the proprioceptive part of the observation row, X[b][3072..3083] =
 // [goal - p, v, b, 0, 0, 0] (the depth part is written by the renderer).
+// (Lanes i0 .. i0 + n - 1 of A; the small per-agent kernels below take the
+// same range so that the forward can run the batch as two halves.)
 __global__ void obs_fwd_kernel(int A, int model, float* __restrict__ X, const float* __restrict__ s,
-                               const float* __restrict__ goal) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= A) return;
+                               const float* __restrict__ goal, int i0, int n) {
+  const int b = i0 + (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (b >= i0 + n) return;
   float* row = X + (size_t)b * kObsPad + kRays;
   for (int k = 0; k < 3; ++k) {
     row[k] = goal[(size_t)k * A + b] - s[(size_t)k * A + b];
@@ -65,9 +67,9 @@ __global__ void obs_fwd_kernel(int A, int model, float* __restrict__ X, const fl
 
 // Action map: PM9 u = g y[0:3]; RB13 T = m g (1 + y0), w_cmd = 3 y[1:4].
 __global__ void action_kernel(int A, int model, const float* __restrict__ Y,
-                              const float* __restrict__ prm, float* __restrict__ a) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= A) return;
+                              const float* __restrict__ prm, float* __restrict__ a, int i0, int n) {
+  const int b = i0 + (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (b >= i0 + n) return;
   const float* y = Y + (size_t)b * kOut;
   if (model == SIM_PM9) {
     for (int k = 0; k < 3; ++k) a[(size_t)k * A + b] = kG * y[k];
@@ -83,9 +85,9 @@ struct LossW {
 
 __global__ void loss_step_kernel(int A, const float* __restrict__ s1, const float* __restrict__ goal,
                                  const float* __restrict__ Y, const float* __restrict__ lo, LossW w,
-                                 float* __restrict__ acc) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= A) return;
+                                 float* __restrict__ acc, int i0, int n) {
+  const int b = i0 + (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (b >= i0 + n) return;
   float lp = 0.f, lv = 0.f, lu = 0.f;
   for (int k = 0; k < 3; ++k) {
     const float dp = s1[(size_t)k * A + b] - goal[(size_t)k * A + b];
@@ -406,6 +408,18 @@ static void tpair(bptt_handle* b, int cls, int a, int z) {
 }
 }  // namespace da
 
+// The second and third streams (segment recompute / second half of the
+// forward; weight gradients) and their events, created on first use.
+static int ensure_streams(bptt_handle* b) {
+  if (b->side) return SIM_OK;
+  DA_HIP(hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking));
+  DA_HIP(hipStreamCreateWithFlags(&b->wgrad, hipStreamNonBlocking));
+  for (hipEvent_t* e : {&b->ev_start, &b->ev_rec[0], &b->ev_rec[1], &b->ev_free[0], &b->ev_free[1], &b->ev_z[0],
+                        &b->ev_z[1], &b->ev_w[0], &b->ev_w[1], &b->ev_seg, &b->ev_wdone})
+    DA_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
+  return SIM_OK;
+}
+
 // Segments whose observations and hit records the forward leaves in the two
 // sets (stored mode): the last two.
 static bool kept_segment(const bptt_handle* b, int seg) { return b->store && seg >= b->nseg - 2; }
@@ -561,29 +575,36 @@ int bptt_get_timing(bptt_handle* b, float* ms, int32_t* count, int32_t n) {
 namespace da {
 
 // One forward step t: render s -> X slot, observation, MLP, action, step.
+// Lanes [i0, i0 + n) only (the full batch, or one half of it); X, H1, H2, Y
+// are the full row arrays, `part` the split-K work buffer of this lane range.
 static int forward_step(bptt_handle* b, const PolicyPtrs& pp, const float* s, float* s_next, float* X,
-                        int* hit, float* H1, float* H2, float* Y, float* act, hipStream_t st) {
+                        int* hit, float* H1, float* H2, float* Y, float* act, hipStream_t st, int i0,
+                        int n, float* part) {
   sim_handle* h = b->sim;
   const int A = b->A;
   const float dmax = h->cfg.cam_max;
   int e0 = tmark(b, st);
   // depth / d_max straight into the observation rows, obstacle term fused
   int rc = launch_render(h->scene, h->cam.dev, h->cfg.model == SIM_RB13, h->cfg.fov_cull != 0, s, A, X,
-                         hit, kObsPad, 1.0f / dmax, st, b->lo, b->cfg.beta, b->cfg.d_safe);
+                         hit, kObsPad, 1.0f / dmax, st, b->lo, b->cfg.beta, b->cfg.d_safe, i0, n);
   if (rc) return rc;
   tpair(b, BPTT_T_RENDER, e0, tmark(b, st));
   e0 = tmark(b, st);
-  hipLaunchKernelGGL(obs_fwd_kernel, dim3(cdiv(A, 256)), dim3(256), 0, st, A, h->cfg.model, X, s, b->goal);
+  hipLaunchKernelGGL(obs_fwd_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, A, h->cfg.model, X, s, b->goal,
+                     i0, n);
   DA_LAUNCH_CHECK("obs_fwd_kernel");
   tpair(b, BPTT_T_SMALL_FWD, e0, tmark(b, st));
-  if ((rc = mlp_forward(A, pp, X, H1, H2, Y, st, b->prec, b->part, b))) return rc;
+  if ((rc = mlp_forward(n, pp, X + (size_t)i0 * kObsPad, H1 + (size_t)i0 * kHid, H2 + (size_t)i0 * kHid,
+                        Y + (size_t)i0 * kOut, st, b->prec, part, b)))
+    return rc;
   e0 = tmark(b, st);
-  hipLaunchKernelGGL(action_kernel, dim3(cdiv(A, 256)), dim3(256), 0, st, A, h->cfg.model, Y, h->params,
-                     act);
+  hipLaunchKernelGGL(action_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, A, h->cfg.model, Y, h->params,
+                     act, i0, n);
   DA_LAUNCH_CHECK("action_kernel");
   tpair(b, BPTT_T_SMALL_FWD, e0, tmark(b, st));
   e0 = tmark(b, st);
-  rc = launch_step(h->cfg.model, h->cfg.integrator, A, h->cfg.dt, s, act, h->params, s_next, nullptr, st);
+  rc = launch_step(h->cfg.model, h->cfg.integrator, A, h->cfg.dt, s, act, h->params, s_next, nullptr, st,
+                   i0, n);
   tpair(b, BPTT_T_STEP, e0, tmark(b, st));
   return rc;
 }
@@ -613,6 +634,20 @@ int bptt_forward(bptt_handle* b, const float* theta, const float* s0, const floa
   DA_HIP(hipMemcpyAsync(b->seg_s, s0, sbytes, hipMemcpyDeviceToDevice, st));
   LossW w{b->cfg.w_p, b->cfg.w_v, b->cfg.w_u, b->cfg.w_o, b->cfg.beta, b->cfg.d_safe};
   const size_t xset = (size_t)K * A * kObsPad, hset = (size_t)K * A * kRays;
+  // With stored activations (and agents that do not see each other) the batch
+  // runs as two halves on two streams, so that one half's render (VALU) and
+  // the other half's policy GEMMs (matrix cores) overlap. The halves share
+  // nothing but read-only data; every lane's arithmetic is unchanged.
+  int nh = 1, hi0[2] = {0, 0}, hn[2] = {A, 0};
+  if (b->store && !b->timing && !b->sim->cfg.agents_visible && A >= 512) {
+    if ((rc = ensure_streams(b))) return rc;
+    nh = 2;
+    hn[0] = ((A / 2 + 127) / 128) * 128;
+    hi0[1] = hn[0];
+    hn[1] = A - hn[0];
+    DA_HIP(hipEventRecord(b->ev_start, st));
+    DA_HIP(hipStreamWaitEvent(b->side, b->ev_start, 0));
+  }
   for (int t = 0; t < T; ++t) {
     // stored mode: state t in slot t; otherwise two ping-pong slots
     const int si = b->store ? t : (t & 1), so = b->store ? t + 1 : ((t + 1) & 1);
@@ -630,13 +665,20 @@ int bptt_forward(bptt_handle* b, const float* theta, const float* s0, const floa
       X = b->X + (size_t)(seg & 1) * xset + (size_t)(t % K) * A * kObsPad;
       hit = b->hit + (size_t)(seg & 1) * hset + (size_t)(t % K) * A * kRays;
     }
-    if ((rc = forward_step(b, pp, cur, nxt, X, hit, b->H1 + (size_t)a * A * kHid,
-                           b->H2 + (size_t)a * A * kHid, b->Y + (size_t)a * A * kOut,
-                           b->act + (size_t)a * Ka * A, st)))
-      return rc;
-    hipLaunchKernelGGL(loss_step_kernel, dim3(cdiv(A, 256)), dim3(256), 0, st, A, nxt, goal,
-                       b->Y + (size_t)a * A * kOut, b->lo, w, b->loss_acc);
-    DA_LAUNCH_CHECK("loss_step_kernel");
+    for (int hf = 0; hf < nh; ++hf) {
+      hipStream_t q = hf ? b->side : st;
+      if ((rc = forward_step(b, pp, cur, nxt, X, hit, b->H1 + (size_t)a * A * kHid,
+                             b->H2 + (size_t)a * A * kHid, b->Y + (size_t)a * A * kOut,
+                             b->act + (size_t)a * Ka * A, q, hi0[hf], hn[hf], hf ? b->part_w : b->part)))
+        return rc;
+      hipLaunchKernelGGL(loss_step_kernel, dim3(cdiv(hn[hf], 256)), dim3(256), 0, q, A, nxt, goal,
+                         b->Y + (size_t)a * A * kOut, b->lo, w, b->loss_acc, hi0[hf], hn[hf]);
+      DA_LAUNCH_CHECK("loss_step_kernel");
+    }
+  }
+  if (nh == 2) {
+    DA_HIP(hipEventRecord(b->ev_seg, b->side));
+    DA_HIP(hipStreamWaitEvent(st, b->ev_seg, 0));
   }
   hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(1024), 0, st, A, b->loss_acc, 1.0f / ((float)A * T),
                      loss);
@@ -680,7 +722,8 @@ int bptt_backward(bptt_handle* b, const float* g_loss, float* g_theta, float* g_
                             Hs + (size_t)j * A * kRays, kObsPad, 1.0f / dmax, q);
       if (r) return r;
       tpair(b, BPTT_T_RENDER, e0, tmark(b, q));
-      hipLaunchKernelGGL(obs_fwd_kernel, dim3(cdiv(A, 256)), dim3(256), 0, q, A, h->cfg.model, X, s, b->goal);
+      hipLaunchKernelGGL(obs_fwd_kernel, dim3(cdiv(A, 256)), dim3(256), 0, q, A, h->cfg.model, X, s, b->goal,
+                         0, A);
       DA_LAUNCH_CHECK("obs_fwd_kernel");
     }
     return SIM_OK;
@@ -691,13 +734,7 @@ int bptt_backward(bptt_handle* b, const float* g_loss, float* g_theta, float* g_
   if (b->store && !overlap) {
     if (!kept_segment(b, b->nseg - 1) && (rc = recompute_renders(b->nseg - 1, st))) return rc;
   } else if (overlap) {
-    if (!b->side) {
-      DA_HIP(hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking));
-      DA_HIP(hipStreamCreateWithFlags(&b->wgrad, hipStreamNonBlocking));
-      for (hipEvent_t* e : {&b->ev_start, &b->ev_rec[0], &b->ev_rec[1], &b->ev_free[0], &b->ev_free[1],
-                            &b->ev_z[0], &b->ev_z[1], &b->ev_w[0], &b->ev_w[1], &b->ev_seg, &b->ev_wdone})
-        DA_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
-    }
+    if ((rc = ensure_streams(b))) return rc;
     // everything enqueued so far on the caller's stream (forward pass, zeroing)
     // precedes the side streams' first work
     DA_HIP(hipEventRecord(b->ev_start, st));
@@ -729,7 +766,7 @@ int bptt_backward(bptt_handle* b, const float* g_loss, float* g_theta, float* g_
         rc = forward_step(b, pp, b->seg_s + (size_t)j * C * A, b->seg_s + (size_t)(j + 1) * C * A,
                           b->X + (size_t)j * A * kObsPad, b->hit + (size_t)j * A * kRays,
                           b->H1 + (size_t)j * A * kHid, b->H2 + (size_t)j * A * kHid,
-                          b->Y + (size_t)j * A * kOut, b->act + (size_t)j * Ka * A, st);
+                          b->Y + (size_t)j * A * kOut, b->act + (size_t)j * Ka * A, st, 0, A, b->part);
         if (rc) return rc;
       }
     }

@@ -18,13 +18,14 @@ namespace da {
 // kernels
 // ---------------------------------------------------------------------------
 template <int M, int I>
-__global__ __launch_bounds__(256) void step_kernel(int A, float dt, const float* s_in,
+__global__ __launch_bounds__(256) void step_kernel(int n, int A, float dt, const float* s_in,
                                                    const float* __restrict__ a,
                                                    const float* __restrict__ prm, float* s_out,
                                                    uint8_t* __restrict__ flags) {
+  // n lanes from the (pre-offset) pointers; A is the SoA component stride
   constexpr int C = Dim<M>::C, K = Dim<M>::K, P = Dim<M>::P;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= A) return;
+  if (i >= n) return;
   float s[C], u[K], p[P > 0 ? P : 1], out[C];
   for (int c = 0; c < C; ++c) s[c] = s_in[(size_t)c * A + i];
   for (int k = 0; k < K; ++k) u[k] = a[(size_t)k * A + i];
@@ -61,9 +62,10 @@ __global__ __launch_bounds__(256) void step_vjp_kernel(int A, float dt, const fl
 
 template <int M, int I>
 static int launch_step_t(int A, float dt, const float* s_in, const float* a, const float* prm,
-                         float* s_out, uint8_t* flags, hipStream_t st) {
-  hipLaunchKernelGGL((step_kernel<M, I>), dim3(cdiv(A, 256)), dim3(256), 0, st, A, dt, s_in, a,
-                     prm, s_out, flags);
+                         float* s_out, uint8_t* flags, hipStream_t st, int i0, int n) {
+  if (n <= 0) return SIM_OK;
+  hipLaunchKernelGGL((step_kernel<M, I>), dim3(cdiv(n, 256)), dim3(256), 0, st, n, A, dt, s_in + i0,
+                     a + i0, prm ? prm + i0 : nullptr, s_out + i0, flags ? flags + i0 : nullptr);
   DA_LAUNCH_CHECK("step_kernel");
   return SIM_OK;
 }
@@ -91,8 +93,9 @@ static int launch_step_vjp_t(int A, float dt, const float* s, const float* a, co
   }
 
 int launch_step(int model, int integ, int A, float dt, const float* s_in, const float* a,
-                const float* prm, float* s_out, uint8_t* flags, hipStream_t st) {
-  DA_DISPATCH_MODEL(model, integ, launch_step_t, A, dt, s_in, a, prm, s_out, flags, st);
+                const float* prm, float* s_out, uint8_t* flags, hipStream_t st, int i0, int n) {
+  if (n < 0) n = A - i0;
+  DA_DISPATCH_MODEL(model, integ, launch_step_t, A, dt, s_in, a, prm, s_out, flags, st, i0, n);
 }
 
 int launch_step_vjp(int model, int integ, int A, float dt, const float* s, const float* a,

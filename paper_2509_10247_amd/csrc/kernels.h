@@ -37,8 +37,9 @@ int state_dim(int model);
 int action_dim(int model);
 int param_dim(int model);
 
+// Lanes [i0, i0 + n) of the A-lane SoA arrays (n < 0: through A).
 int launch_step(int model, int integ, int A, float dt, const float* s_in, const float* a,
-                const float* prm, float* s_out, uint8_t* flags, hipStream_t st);
+                const float* prm, float* s_out, uint8_t* flags, hipStream_t st, int i0 = 0, int n = -1);
 int launch_step_vjp(int model, int integ, int A, float dt, const float* s, const float* a,
                     const float* prm, const float* g_next, float* g_s, float* g_a, hipStream_t st);
 
@@ -47,7 +48,8 @@ int launch_step_vjp(int model, int integ, int A, float dt, const float* s, const
 // term[i] = mean_r softplus(beta (d_safe - value_r)) / beta (fused epilogue).
 int launch_render(const SceneDev& sc, const SensorDev& sen, bool rotate, bool cull, const float* s,
                   int A, float* out, int* rec, int out_ld, float out_scale, hipStream_t st,
-                  float* term = nullptr, float beta = 1.f, float d_safe = 0.f);
+                  float* term = nullptr, float beta = 1.f, float d_safe = 0.f, int i0 = 0,
+                  int n = -1);
 int launch_render_work(const SceneDev& sc, const SensorDev& sen, bool rotate, bool cull,
                        const float* s, int A, float* out, int* work, hipStream_t st);
 // Adds the sensor's contribution (d out/d s)^T g to g_s (p and q components);

@@ -26,10 +26,10 @@ __global__ __launch_bounds__(256) void render_kernel(SceneDev sc, SensorDev sen,
                                                      float* __restrict__ out,
                                                      int* __restrict__ rec, int out_ld,
                                                      float out_scale, float* __restrict__ term,
-                                                     float beta, float d_safe) {
+                                                     float beta, float d_safe, int i0) {
   extern __shared__ float4 smem_f4[];
-  render_one_agent<ROT, CULL>(sc, sen, s, A, blockIdx.x, 0, sen.n_tiles, out, rec, out_ld, out_scale,
-                              term, beta, d_safe, smem_f4);
+  render_one_agent<ROT, CULL>(sc, sen, s, A, i0 + (int)blockIdx.x, 0, sen.n_tiles, out, rec, out_ld,
+                              out_scale, term, beta, d_safe, smem_f4);
 }
 
 // Same rendering, plus the per-wavefront work counters (diagnostics only).
@@ -331,20 +331,21 @@ __global__ __launch_bounds__(256) void collide_kernel(SceneDev sc, const float* 
 // ---------------------------------------------------------------------------
 int launch_render(const SceneDev& sc, const SensorDev& sen, bool rotate, bool cull, const float* s,
                   int A, float* out, int* rec, int out_ld, float out_scale, hipStream_t st,
-                  float* term, float beta, float d_safe) {
-  if (A == 0) return SIM_OK;
+                  float* term, float beta, float d_safe, int i0, int n) {
+  if (n < 0) n = A - i0;
+  if (n <= 0) return SIM_OK;
   const int P = sc.max_prims > 0 ? sc.max_prims : 1;
   const size_t lds = render_lds_bytes(P, sen.n_tiles);
   if (rotate) {
     if (cull)
-      hipLaunchKernelGGL((render_kernel<true, true>), dim3(A), dim3(256), lds, st, sc, sen, s, A, out, rec, out_ld, out_scale, term, beta, d_safe);
+      hipLaunchKernelGGL((render_kernel<true, true>), dim3(n), dim3(256), lds, st, sc, sen, s, A, out, rec, out_ld, out_scale, term, beta, d_safe, i0);
     else
-      hipLaunchKernelGGL((render_kernel<true, false>), dim3(A), dim3(256), lds, st, sc, sen, s, A, out, rec, out_ld, out_scale, term, beta, d_safe);
+      hipLaunchKernelGGL((render_kernel<true, false>), dim3(n), dim3(256), lds, st, sc, sen, s, A, out, rec, out_ld, out_scale, term, beta, d_safe, i0);
   } else {
     if (cull)
-      hipLaunchKernelGGL((render_kernel<false, true>), dim3(A), dim3(256), lds, st, sc, sen, s, A, out, rec, out_ld, out_scale, term, beta, d_safe);
+      hipLaunchKernelGGL((render_kernel<false, true>), dim3(n), dim3(256), lds, st, sc, sen, s, A, out, rec, out_ld, out_scale, term, beta, d_safe, i0);
     else
-      hipLaunchKernelGGL((render_kernel<false, false>), dim3(A), dim3(256), lds, st, sc, sen, s, A, out, rec, out_ld, out_scale, term, beta, d_safe);
+      hipLaunchKernelGGL((render_kernel<false, false>), dim3(n), dim3(256), lds, st, sc, sen, s, A, out, rec, out_ld, out_scale, term, beta, d_safe, i0);
   }
   DA_LAUNCH_CHECK("render_kernel");
   return SIM_OK;
