@@ -297,6 +297,14 @@ def render_work_flops(e, s, term):
     return flops, c
 
 
+# FLOPs of the render adjoint per ray (same counting rules), from the
+# kernel's expressions: the folded depth-observation gradient 10 (every ray);
+# a sphere / agent hit 58 (rotation 15, offsets 3, C 6, tc 5, perpendicular
+# 6, discriminant 6, sqrt 1, t 3, 1/sqrt 1, dt/do 9, dt/dd 3); a box / room
+# face hit 27 (rotation 15, reciprocals 3, face distances 6, dt/dd 3); plus
+# 28 per hit for the accumulation of dL/do and dL/dR.
+RENDER_VJP_FLOP = {"ray": 10, "sphere_hit": 58 + 28, "plane_hit": 27 + 28}
+
 # Sources of the camera render kernel; a traffic figure measured with
 # rocprofv3 is only reported while these are unchanged. (The BPTT launch mix,
 # forward renders without and recompute renders with hit records, is fixed.)
@@ -315,9 +323,10 @@ def source_hash(files):
     return h.hexdigest()
 
 
-def measured_traffic(files, profile):
-    """HBM bytes per launch from a committed rocprofv3 counter summary (a
-    fenced json block), or None if it is missing or the sources changed."""
+def measured_traffic(files, profile, kernel="render"):
+    """HBM bytes per launch of `kernel` from a committed rocprofv3 counter
+    summary (a fenced json block), or None if it is missing or the sources
+    changed since the counters were taken."""
     path = os.path.join(ROOT, profile)
     if not os.path.exists(path):
         return None
@@ -328,10 +337,29 @@ def measured_traffic(files, profile):
     rec = json.loads(block)
     if rec.get("source_sha256") != source_hash(files):
         return None
-    return rec
+    return rec.get("kernels", {}).get(kernel)
 
 
-def dominant_roofline(tm, e, s0, A, T, K, gemm_mode, store):
+def render_vjp_flops(e, scene, s):
+    """Algorithmic FLOPs of one render-adjoint launch on the camera at state s:
+    hit types from the hit records of a render at s."""
+    import numpy as np
+    import torch
+    d, hit, _, _ = e.render(s, depth=True)
+    hit = hit.reshape(e.n_agents, -1).long()
+    env = torch.as_tensor(np.repeat(np.arange(scene.n_envs), np.diff(scene.agent_off)), device="cuda")
+    ns = torch.as_tensor(np.diff(scene.sph_off), device="cuda")[env][:, None]
+    nb = torch.as_tensor(np.diff(scene.box_off), device="cuda")[env][:, None]
+    sph = ((hit >= 0) & (hit < ns)).sum().item()
+    box = ((hit >= ns) & (hit < ns + nb)).sum().item()
+    other = (hit >= ns + nb).sum().item()   # room (agents are not visible here)
+    rays = hit.numel()
+    f = RENDER_VJP_FLOP
+    flops = rays * f["ray"] + sph * f["sphere_hit"] + (box + other) * f["plane_hit"]
+    return flops, {"rays": rays, "sphere_hits": sph, "box_hits": box, "room_hits": other}
+
+
+def dominant_roofline(tm, e, scene, s0, A, T, K, gemm_mode, store):
     """Roofline of the kernel class with the largest total time in one
     iteration: algorithmic work per launch / average launch duration (HIP
     events on the kernels' stream)."""
@@ -378,7 +406,22 @@ def dominant_roofline(tm, e, s0, A, T, K, gemm_mode, store):
                      "flops_per_launch": flops, "work_per_launch": cnt,
                      "algorithmic_bytes_per_launch": written + read,
                      "hbm_frac": round((written + read) / avg_s / PEAK_HBM, 4)})
-        tr = measured_traffic(RENDER_SOURCES, TRAFFIC_PROFILE)
+        tr = measured_traffic(RENDER_SOURCES, TRAFFIC_PROFILE, "render")
+        if tr is not None:
+            base["traffic"] = tr["fetch_bytes_per_launch"] + tr["write_bytes_per_launch"]
+            base["traffic_source"] = TRAFFIC_PROFILE
+        return base
+    if dom == "render_vjp":
+        flops, cnt = render_vjp_flops(e, scene, s0)
+        ach = flops / avg_s
+        read = cnt["rays"] * 12.0   # hit record, observation gradient, observation value
+        base.update({"bound": "alu", "achieved": round(ach / 1e12, 2), "peak": PEAK_FP32_VALU / 1e12,
+                     "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_VALU, 4),
+                     "frac_of_nonpacked_fp32": round(ach / PEAK_FP32_VALU_NONPACKED, 4),
+                     "flops_per_launch": flops, "work_per_launch": cnt,
+                     "algorithmic_bytes_per_launch": read,
+                     "hbm_frac": round(read / avg_s / PEAK_HBM, 4)})
+        tr = measured_traffic(RENDER_SOURCES, TRAFFIC_PROFILE, "render_vjp")
         if tr is not None:
             base["traffic"] = tr["fetch_bytes_per_launch"] + tr["write_bytes_per_launch"]
             base["traffic_source"] = TRAFFIC_PROFILE
@@ -469,7 +512,7 @@ def main():
         _lib.bptt_set_timing(eng.h, 0)
         breakdown = {k: {"ms_total": round(v[0], 3), "launches": v[1],
                          "ms_avg": round(v[0] / max(v[1], 1), 4)} for k, v in tm.items()}
-        roofline = dominant_roofline(tm, e, s0, A, T, K, gemm_mode, not args.recompute_all)
+        roofline = dominant_roofline(tm, e, wk.scene, s0, A, T, K, gemm_mode, not args.recompute_all)
 
     line = {
         "metric": "env-steps/sec fwd+bwd with 64x48 depth",

@@ -43,9 +43,12 @@ inline size_t render_lds_bytes(int P, int T) {
 
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// softplus(x) = max(x, 0) + log(1 + exp(-|x|)) on the hardware exp2 / log2 units.
+// softplus(x) = max(x, 0) + log(1 + exp(-|x|)) on the hardware exp2 / log2
+// units; the log2 argument lies in [1, 2], where the raw instruction needs no
+// range reduction.
 __device__ __forceinline__ float softplus_fast(float x) {
-  return fmaxf(x, 0.f) + __logf(1.f + __expf(-fabsf(x)));
+  constexpr float kLog2e = 1.4426950408889634f, kLn2 = 0.6931471805599453f;
+  return fmaxf(x, 0.f) + kLn2 * __builtin_amdgcn_logf(1.f + __builtin_amdgcn_exp2f(-fabsf(x) * kLog2e));
 }
 
 // Sphere test with origin-relative centre w = c - o, r2 = r^2, C = |w|^2 - r^2 > 0
@@ -269,8 +272,17 @@ __device__ __forceinline__ void render_tiles(const AgentStage& ag, const SensorD
   const float inv_beta = term ? 1.0f / beta : 0.f;
   int wk[kWorkN] = {0, 0, 0, 0, 0, 0};
 
+  // the next tile's ray index and direction are loaded while this tile is
+  // processed (ray index two tiles ahead, direction one tile ahead)
+  int r_n = tile_begin + wave < tile_end ? sen.tile_rays[(tile_begin + wave) * kTileRays + lane] : -1;
+  float4 db_n = r_n >= 0 ? sen.dirs[r_n] : make_float4(0.f, 0.f, 0.f, 0.f);
+  int r_nn = tile_begin + wave + 4 < tile_end ? sen.tile_rays[(tile_begin + wave + 4) * kTileRays + lane] : -1;
   for (int tile = tile_begin + wave; tile < tile_end; tile += 4) {
-    const int r = sen.tile_rays[tile * kTileRays + lane];
+    const int r = r_n;
+    const float4 db = db_n;
+    r_n = r_nn;
+    db_n = r_n >= 0 ? sen.dirs[r_n] : make_float4(0.f, 0.f, 0.f, 0.f);
+    r_nn = tile + 8 < tile_end ? sen.tile_rays[(tile + 8) * kTileRays + lane] : -1;
     if (inside) {
       if (r >= 0) {
         orow[r] = 0.f;
@@ -313,7 +325,6 @@ __device__ __forceinline__ void render_tiles(const AgentStage& ag, const SensorD
       wk[kWorkCone] += CULL ? np : 0;
     }
     if (r < 0) continue;
-    const float4 db = sen.dirs[r];
     const f3 d = ROT ? rot_apply(R, mk3(db.x, db.y, db.z)) : mk3(db.x, db.y, db.z);
     const f3 inv = mk3(__builtin_amdgcn_rcpf(d.x), __builtin_amdgcn_rcpf(d.y), __builtin_amdgcn_rcpf(d.z));
     float best = kInf;
