@@ -176,7 +176,7 @@ __global__ __launch_bounds__(256, 5) void render_vjp_kernel(SceneDev sc, SensorD
     if (OBS) {
       // d(loss)/d(depth): the observation's 1/d_max scaling and the
       // obstacle term softplus(beta (d_safe - depth)) / beta
-      const float sig = __frcp_rn(1.f + __expf(-ob.beta * (ob.d_safe - x_c * ob.dmax)));
+      const float sig = __builtin_amdgcn_rcpf(1.f + __expf(-ob.beta * (ob.d_safe - x_c * ob.dmax)));
       gv = gv * inv_dmax - osc * sig;
     }
     const float4 db = db_c;
@@ -190,6 +190,7 @@ __global__ __launch_bounds__(256, 5) void render_vjp_kernel(SceneDev sc, SensorD
     // room) cannot come from sim_render on the same scene: ignored
     if (r < 0 || k < 0 || gv == 0.f || k > np || (k == np && !sc.room)) continue;
     const float gt = gv * db.w;
+    const f3 d32 = ROT ? rot_apply(R32, mk3(db.x, db.y, db.z)) : mk3(db.x, db.y, db.z);
     f3 dto, dtd;  // dt/do and dt/dd (FP32 results)
     if (k < ns || (k >= ns + nb && k < np)) {
       const float4 cc = P0[k];
@@ -197,7 +198,6 @@ __global__ __launch_bounds__(256, 5) void render_vjp_kernel(SceneDev sc, SensorD
       const double rad = cc.w;
       // FP32 first; a hit with |n.d| < 0.3 (within ~17 deg of grazing) is
       // redone in FP64, where the FP32 discriminant would lose too much
-      const f3 d32 = ROT ? rot_apply(R32, mk3(db.x, db.y, db.z)) : mk3(db.x, db.y, db.z);
       const f3 w32 = mk3((float)c.x - o.x, (float)c.y - o.y, (float)c.z - o.z);
       const float rad32 = (float)rad;
       const float C32 = dot(w32, w32) - rad32 * rad32;
@@ -237,7 +237,7 @@ __global__ __launch_bounds__(256, 5) void render_vjp_kernel(SceneDev sc, SensorD
       }
     } else {
       // box entry face or room exit face: t = (plane_f - o_f) / d_f
-      const f3 d = ROT ? rot_apply(R32, mk3(db.x, db.y, db.z)) : mk3(db.x, db.y, db.z);
+      const f3 d = d32;
       const f3 iv = mk3(__builtin_amdgcn_rcpf(d.x), __builtin_amdgcn_rcpf(d.y), __builtin_amdgcn_rcpf(d.z));
       const float4 lo = P0[k], hi = P1[k];
       const bool entry = k < ns + nb;  // box: entry face (near slab); room: exit face
