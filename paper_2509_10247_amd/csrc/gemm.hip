@@ -180,12 +180,6 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(GemmArgs g) {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 constexpr int BKP = GBK + 8;
 
-__device__ __forceinline__ uint32_t bf16_bits(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;  // NaN stays quiet NaN
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return u >> 16;
-}
 
 template <bool KMAJ>
 __device__ __forceinline__ void store_tile_bf16(uint16_t* S, const float4 (&reg)[4]) {

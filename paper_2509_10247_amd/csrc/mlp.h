@@ -58,6 +58,14 @@ int launch_split_transpose(int R, int K, const float* src, int ld, uint16_t* hi,
                            hipStream_t st);
 constexpr int kSplitPad = 32;  // K padding of pre-split operands
 
+// FP32 -> BF16 bit pattern, round to nearest even (NaN stays a quiet NaN).
+__device__ __forceinline__ uint32_t bf16_bits(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+
 // Precision of launch_gemm:
 //  GEMM_FP32:   v_mfma_f32_32x32x2f32 on FP32 operands;
 //  GEMM_BF16:   operands read as FP32 and rounded to BF16 (nearest even) when

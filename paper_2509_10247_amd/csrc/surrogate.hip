@@ -173,30 +173,91 @@ __global__ __launch_bounds__(1024) void sur_loss_kernel(int B, const float* __re
 }
 
 // ---------------------------------------------------------------------------
-// step: input prep and the fused finish (nominal step + residual + judge)
+// fused inference step: one workgroup per 64 agents keeps the layer inputs and
+// hidden activations in LDS (BF16, as the GEMM path rounds them) and reads the
+// BF16 weights as MFMA B fragments from L2; each agent then takes the nominal
+// step, the residual, the judge and the fallback. Same rounding points and
+// the same k order as the GEMM path, so the same results.
 // ---------------------------------------------------------------------------
-__global__ void sur_prep_kernel(int A, const float* __restrict__ s, const float* __restrict__ a,
-                                const float* __restrict__ norm, float* __restrict__ X) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= A) return;
-  for (int c = 0; c < kSInP; ++c) {
-    float v = 0.f;
-    if (c < 13)
-      v = (s[(size_t)c * A + i] - norm[c]) / norm[kSIn + c];
-    else if (c < kSIn)
-      v = (a[(size_t)(c - 13) * A + i] - norm[c]) / norm[kSIn + c];
-    X[(size_t)i * kSInP + c] = v;
+typedef __bf16 sbf16x8 __attribute__((ext_vector_type(8)));
+typedef float sf32x16 __attribute__((ext_vector_type(16)));
+// BF16 weights, k contiguous per output: W1 [256][32] (k >= 17 zero),
+// W2 [256][256], W3 [32][256] (rows >= 13 zero)
+constexpr int kW1bK = 32, kW3bN = 32;
+constexpr int kBW1 = 0, kBW2 = kBW1 + kSH * kW1bK, kBW3 = kBW2 + kSH * kSH, kBEnd = kBW3 + kW3bN * kSH;
+constexpr int kFB = 64;           // agents per workgroup
+constexpr int kZP = kW1bK + 8;    // LDS pitch (BF16) of the z rows
+constexpr int kHP = kSH + 8;      // LDS pitch (BF16) of the hidden rows: conflict-free fragment reads
+
+__global__ void sur_bf16_weights_kernel(const float* __restrict__ P, uint16_t* __restrict__ Wb) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= kBEnd) return;
+  float v = 0.f;
+  if (idx < kBW2) {
+    const int r = idx / kW1bK, c = idx % kW1bK;
+    if (c < kSInP) v = P[kPW1 + r * kSInP + c];
+  } else if (idx < kBW3) {
+    v = P[kPW2 + (idx - kBW2)];
+  } else {
+    const int r = (idx - kBW3) / kSH, c = (idx - kBW3) % kSH;
+    if (r < kSOutP) v = P[kPW3 + r * kSH + c];
+  }
+  Wb[idx] = (uint16_t)bf16_bits(v);
+}
+
+// one 64 x 64 slice (columns n0 ..) of a hidden layer: acc[row block][col block]
+template <int KC>
+__device__ __forceinline__ void sur_layer(const uint16_t* __restrict__ In, int in_pitch,
+                                          const uint16_t* __restrict__ W, int w_ld, int n0, int col, int half,
+                                          sf32x16 (&acc)[2][2]) {
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) acc[a][b][i] = 0.f;
+#pragma unroll 4
+  for (int kc = 0; kc < KC; ++kc) {
+    const int ko = kc * 16 + half * 8;
+    sbf16x8 af[2], bf[2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x) {
+      af[x] = *reinterpret_cast<const sbf16x8*>(In + (32 * x + col) * in_pitch + ko);
+      bf[x] = *reinterpret_cast<const sbf16x8*>(W + (size_t)(n0 + 32 * x + col) * w_ld + ko);
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[a], bf[b], acc[a][b], 0, 0, 0);
   }
 }
 
-__global__ void sur_finish_kernel(int A, float dt, int t, int period, const float* __restrict__ s_in,
-                                  const float* __restrict__ a, const float* __restrict__ prm,
-                                  const float* __restrict__ X, const float* __restrict__ Y,
-                                  const float* __restrict__ norm, float* __restrict__ s_out,
-                                  uint8_t* __restrict__ fallback, float* __restrict__ judged_err,
-                                  JudgeThr thr) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= A) return;
+// bias + SiLU, rounded to BF16 into Out (rows 8(i/4) + 4 half + i%4 of each
+// 32-row block, column col of each 32-column block)
+__device__ __forceinline__ void sur_silu_out(const sf32x16 (&acc)[2][2], const float* __restrict__ bias,
+                                             uint16_t* __restrict__ Out, int n0, int col, int half) {
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    const int n = n0 + 32 * b + col;
+    const float bn = bias[n];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int row = 32 * a + 8 * (i >> 2) + 4 * half + (i & 3);
+        const float z = acc[a][b][i] + bn;
+        Out[row * kHP + n] = (uint16_t)bf16_bits(z / (1.f + expf(-z)));
+      }
+  }
+}
+
+// surrogate + judge + fallback of one agent (the finish of the step)
+__device__ __forceinline__ void sur_finish_one(int A, int i, float dt, int t, int period,
+                                               const float* __restrict__ s_in, const float* __restrict__ a,
+                                               const float* __restrict__ prm, const float* y, const float* z,
+                                               const float* __restrict__ norm, float* __restrict__ s_out,
+                                               uint8_t* __restrict__ fallback, float* __restrict__ judged_err,
+                                               const JudgeThr& thr) {
   float s[13], u[4], p[8], nom[13], sur[13];
   for (int c = 0; c < 13; ++c) s[c] = s_in[(size_t)c * A + i];
   for (int k = 0; k < 4; ++k) u[k] = a[(size_t)k * A + i];
@@ -204,14 +265,14 @@ __global__ void sur_finish_kernel(int A, float dt, int t, int period, const floa
   step_regs<SIM_NOMINAL13, SIM_RK4>(s, u, p, dt, nom);
   const float* mu_d = norm + 2 * kSIn;
   const float* sd_d = norm + 2 * kSIn + kSOut;
-  for (int c = 0; c < 13; ++c) sur[c] = nom[c] + mu_d[c] + sd_d[c] * Y[(size_t)i * kSOutP + c];
+  for (int c = 0; c < 13; ++c) sur[c] = nom[c] + mu_d[c] + sd_d[c] * y[c];
   {
     float qn[4];
     quat_normalize(sur + 6, qn, nullptr);
     for (int k = 0; k < 4; ++k) sur[6 + k] = qn[k];
   }
   bool ood = false;
-  for (int c = 0; c < kSIn; ++c) ood |= fabsf(X[(size_t)i * kSInP + c]) > kOodZ;
+  for (int c = 0; c < kSIn; ++c) ood |= fabsf(z[c]) > kOodZ;
   const bool judged = ((i + t) % period) == 0;
   bool fb = fallback[i] != 0;
   float err[4] = {__builtin_nanf(""), __builtin_nanf(""), __builtin_nanf(""), __builtin_nanf("")};
@@ -238,6 +299,66 @@ __global__ void sur_finish_kernel(int A, float dt, int t, int period, const floa
     for (int k = 0; k < 4; ++k) judged_err[(size_t)k * A + i] = err[k];
 }
 
+__global__ __launch_bounds__(256) void sur_step_kernel(int A, float dt, int t, int period,
+                                                       const float* __restrict__ s_in,
+                                                       const float* __restrict__ a,
+                                                       const float* __restrict__ prm,
+                                                       const float* __restrict__ norm,
+                                                       const float* __restrict__ P,
+                                                       const uint16_t* __restrict__ Wb,
+                                                       float* __restrict__ s_out, uint8_t* __restrict__ fallback,
+                                                       float* __restrict__ judged_err, JudgeThr thr) {
+  __shared__ __attribute__((aligned(16))) uint16_t Zs[kFB * kZP];
+  __shared__ __attribute__((aligned(16))) uint16_t Hs[kFB * kHP];  // layer 1, then layer 2 output
+  __shared__ float Ys[kFB][kSOutP];
+  __shared__ float Zf[kFB][kSIn];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int col = lane & 31, half = lane >> 5;
+  const int r0 = blockIdx.x * kFB;
+  // z-scored inputs (rows past A are zero and never written back)
+  if (tid < kFB) {
+    const int i = r0 + tid;
+    for (int c = 0; c < kZP; ++c) {
+      float v = 0.f;
+      if (i < A && c < kSIn)
+        v = c < 13 ? (s_in[(size_t)c * A + i] - norm[c]) / norm[kSIn + c]
+                   : (a[(size_t)(c - 13) * A + i] - norm[c]) / norm[kSIn + c];
+      if (c < kSIn) Zf[tid][c] = v;
+      Zs[tid * kZP + c] = (uint16_t)bf16_bits(v);
+    }
+  }
+  __syncthreads();
+  const int n0 = wave * 64;
+  sf32x16 acc[2][2];
+  sur_layer<kW1bK / 16>(Zs, kZP, Wb + kBW1, kW1bK, n0, col, half, acc);
+  sur_silu_out(acc, P + kPB1, Hs, n0, col, half);
+  __syncthreads();
+  sur_layer<kSH / 16>(Hs, kHP, Wb + kBW2, kSH, n0, col, half, acc);
+  __syncthreads();  // every wave is done reading layer 1's output
+  sur_silu_out(acc, P + kPB2, Hs, n0, col, half);
+  __syncthreads();
+  if (wave < 2) {
+    // output layer: rows 32 wave .., 32 padded columns (13 used)
+    sf32x16 y;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) y[i] = 0.f;
+#pragma unroll 4
+    for (int kc = 0; kc < kSH / 16; ++kc) {
+      const int ko = kc * 16 + half * 8;
+      const sbf16x8 af = *reinterpret_cast<const sbf16x8*>(Hs + (32 * wave + col) * kHP + ko);
+      const sbf16x8 bf = *reinterpret_cast<const sbf16x8*>(Wb + kBW3 + (size_t)col * kSH + ko);
+      y = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af, bf, y, 0, 0, 0);
+    }
+    if (col < kSOutP)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) Ys[32 * wave + 8 * (i >> 2) + 4 * half + (i & 3)][col] = y[i] + P[kPB3 + col];
+  }
+  __syncthreads();
+  if (tid < kFB && r0 + tid < A)
+    sur_finish_one(A, r0 + tid, dt, t, period, s_in, a, prm, Ys[tid], Zf[tid], norm, s_out, fallback,
+                   judged_err, thr);
+}
+
 }  // namespace da
 
 using namespace da;
@@ -249,6 +370,7 @@ struct surrogate_handle {
   float *P, *G, *Pm, *Pv;  // padded params, grads, Adam moments
   float *X, *Z1, *H1, *Z2, *H2, *Y, *T, *gY, *gZ2, *gZ1, *row_err, *part;
   double* mom;
+  uint16_t* Wb = nullptr;  // BF16 weights of the fused inference step
   bool loaded = false;
 };
 
@@ -362,6 +484,7 @@ int surrogate_create(int32_t max_batch, surrogate_handle** out) {
   add(&h->gZ1, B * kSH * 4);
   add(&h->row_err, B * 4);
   add(&h->part, sur_part_floats(max_batch) * 4);
+  add(&h->Wb, (size_t)kBEnd * 2);
   add(&h->mom, (size_t)kSIn * 256 * 2 * sizeof(double));
   size_t total = 0;
   for (auto& p : parts) total += p.second;
@@ -463,8 +586,11 @@ int surrogate_train(surrogate_handle* h, float* theta, float* m, float* v, int32
 
 int surrogate_load(surrogate_handle* h, const float* theta, void* stream) {
   DA_REQUIRE(h && theta, "surrogate_load: null argument");
-  int rc = repack(theta, h->P, 0, as_stream(stream));
+  hipStream_t st = as_stream(stream);
+  int rc = repack(theta, h->P, 0, st);
   if (rc) return rc;
+  hipLaunchKernelGGL(sur_bf16_weights_kernel, dim3(cdiv(kBEnd, 256)), dim3(256), 0, st, h->P, h->Wb);
+  DA_LAUNCH_CHECK("sur_bf16_weights_kernel");
   h->loaded = true;
   return SIM_OK;
 }
@@ -488,13 +614,10 @@ int sim_surrogate_step(sim_handle* full, surrogate_handle* h, const float* norm,
       thr.v[k] = thresholds[k];
     }
   hipStream_t st = as_stream(stream);
-  hipLaunchKernelGGL(sur_prep_kernel, dim3(cdiv(A, 256)), dim3(256), 0, st, A, s_in, a, norm, h->X);
-  DA_LAUNCH_CHECK("sur_prep_kernel");
-  int rc = sur_forward(h, A, st);
-  if (rc) return rc;
-  hipLaunchKernelGGL(sur_finish_kernel, dim3(cdiv(A, 256)), dim3(256), 0, st, A, full->cfg.dt, t, judge_period,
-                     s_in, a, full->params, h->X, h->Y, norm, s_out, fallback, judged_err, thr);
-  DA_LAUNCH_CHECK("sur_finish_kernel");
+  if (A == 0) return SIM_OK;
+  hipLaunchKernelGGL(sur_step_kernel, dim3(cdiv(A, kFB)), dim3(256), 0, st, A, full->cfg.dt, t, judge_period,
+                     s_in, a, full->params, norm, h->P, h->Wb, s_out, fallback, judged_err, thr);
+  DA_LAUNCH_CHECK("sur_step_kernel");
   return SIM_OK;
 }
 
