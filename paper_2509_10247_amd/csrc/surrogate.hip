@@ -174,17 +174,22 @@ __global__ __launch_bounds__(1024) void sur_loss_kernel(int B, const float* __re
 
 // ---------------------------------------------------------------------------
 // fused inference step: one workgroup per 64 agents keeps the layer inputs and
-// hidden activations in LDS (BF16, as the GEMM path rounds them) and reads the
-// BF16 weights as MFMA B fragments from L2; each agent then takes the nominal
-// step, the residual, the judge and the fallback. Same rounding points and
-// the same k order as the GEMM path, so the same results.
+// hidden activations in LDS (BF16, rounded where the training forward rounds
+// them) and reads the BF16 weights as MFMA fragments from L2; each agent then
+// takes the nominal step, the residual, the judge and the fallback.
 // ---------------------------------------------------------------------------
 typedef __bf16 sbf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 sbf16x4 __attribute__((ext_vector_type(4)));
 typedef float sf32x16 __attribute__((ext_vector_type(16)));
-// BF16 weights, k contiguous per output: W1 [256][32] (k >= 17 zero),
-// W2 [256][256], W3 [32][256] (rows >= 13 zero)
+typedef float sf32x4 __attribute__((ext_vector_type(4)));
+// BF16 weights in MFMA fragment order: for output block nb (32 outputs) and
+// k chunk kc (16 inputs) the 64 lanes' A fragments are one contiguous 1 KB
+// run, lane (col, half) holding W[32 nb + col][16 kc + 8 half .. + 7], so a
+// wave's fragment load is fully coalesced. W1: 8 blocks x 2 chunks (inputs
+// >= 17 zero), W2: 8 x 16, W3: 1 x 16 (outputs >= 13 zero).
 constexpr int kW1bK = 32, kW3bN = 32;
 constexpr int kBW1 = 0, kBW2 = kBW1 + kSH * kW1bK, kBW3 = kBW2 + kSH * kSH, kBEnd = kBW3 + kW3bN * kSH;
+__host__ __device__ constexpr int frag_index(int nb, int kc, int KC, int lane) { return ((nb * KC + kc) * 64 + lane) * 8; }
 constexpr int kFB = 64;           // agents per workgroup
 constexpr int kZP = kW1bK + 8;    // LDS pitch (BF16) of the z rows
 constexpr int kHP = kSH + 8;      // LDS pitch (BF16) of the hidden rows: conflict-free fragment reads
@@ -192,23 +197,28 @@ constexpr int kHP = kSH + 8;      // LDS pitch (BF16) of the hidden rows: confli
 __global__ void sur_bf16_weights_kernel(const float* __restrict__ P, uint16_t* __restrict__ Wb) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= kBEnd) return;
-  float v = 0.f;
+  // region, then (nb, kc, lane, e) of the fragment order
+  int base, KC, src, ld, rows;
   if (idx < kBW2) {
-    const int r = idx / kW1bK, c = idx % kW1bK;
-    if (c < kSInP) v = P[kPW1 + r * kSInP + c];
+    base = kBW1; KC = kW1bK / 16; src = kPW1; ld = kSInP; rows = kSH;
   } else if (idx < kBW3) {
-    v = P[kPW2 + (idx - kBW2)];
+    base = kBW2; KC = kSH / 16; src = kPW2; ld = kSH; rows = kSH;
   } else {
-    const int r = (idx - kBW3) / kSH, c = (idx - kBW3) % kSH;
-    if (r < kSOutP) v = P[kPW3 + r * kSH + c];
+    base = kBW3; KC = kSH / 16; src = kPW3; ld = kSH; rows = kSOutP;
   }
+  const int f = idx - base, e = f & 7, lane = (f >> 3) & 63, kc = (f >> 9) % KC, nb = (f >> 9) / KC;
+  const int n = 32 * nb + (lane & 31), k = 16 * kc + 8 * (lane >> 5) + e;
+  const float v = (n < rows && k < ld) ? P[src + n * ld + k] : 0.f;
   Wb[idx] = (uint16_t)bf16_bits(v);
 }
 
-// one 64 x 64 slice (columns n0 ..) of a hidden layer: acc[row block][col block]
+// One 64-output x 64-agent slice of a hidden layer, computed transposed
+// (weights as the MFMA A operand, agents as B): acc[a][b][i] holds output
+// n0 + 32a + 8(i/4) + 4half + i%4 of agent 32b + col, so each lane owns four
+// consecutive outputs of one agent.
 template <int KC>
 __device__ __forceinline__ void sur_layer(const uint16_t* __restrict__ In, int in_pitch,
-                                          const uint16_t* __restrict__ W, int w_ld, int n0, int col, int half,
+                                          const uint16_t* __restrict__ W, int n0, int lane, int col, int half,
                                           sf32x16 (&acc)[2][2]) {
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -219,50 +229,72 @@ __device__ __forceinline__ void sur_layer(const uint16_t* __restrict__ In, int i
 #pragma unroll 4
   for (int kc = 0; kc < KC; ++kc) {
     const int ko = kc * 16 + half * 8;
-    sbf16x8 af[2], bf[2];
+    sbf16x8 wf[2], hf[2];
 #pragma unroll
     for (int x = 0; x < 2; ++x) {
-      af[x] = *reinterpret_cast<const sbf16x8*>(In + (32 * x + col) * in_pitch + ko);
-      bf[x] = *reinterpret_cast<const sbf16x8*>(W + (size_t)(n0 + 32 * x + col) * w_ld + ko);
+      wf[x] = *reinterpret_cast<const sbf16x8*>(W + frag_index(n0 / 32 + x, kc, KC, lane));
+      hf[x] = *reinterpret_cast<const sbf16x8*>(In + (32 * x + col) * in_pitch + ko);
     }
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[a], bf[b], acc[a][b], 0, 0, 0);
+      for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wf[a], hf[b], acc[a][b], 0, 0, 0);
   }
 }
 
-// bias + SiLU, rounded to BF16 into Out (rows 8(i/4) + 4 half + i%4 of each
-// 32-row block, column col of each 32-column block)
+// SiLU of one pre-activation: z sigmoid(z) with the hardware base-2
+// exponential and reciprocal (both within 1 ulp; the result is rounded to
+// BF16 next). Limits: z -> -inf gives -0, z -> +inf gives z.
+__device__ __forceinline__ float silu_fast(float z) {
+  constexpr float kLog2e = 1.44269504088896341f;
+  return z * __builtin_amdgcn_rcpf(1.f + __builtin_amdgcn_exp2f(-z * kLog2e));
+}
+
+// bias + SiLU, rounded to BF16 (nearest even) into Out[agent][output], four
+// outputs per 8-byte store
 __device__ __forceinline__ void sur_silu_out(const sf32x16 (&acc)[2][2], const float* __restrict__ bias,
                                              uint16_t* __restrict__ Out, int n0, int col, int half) {
 #pragma unroll
-  for (int b = 0; b < 2; ++b) {
-    const int n = n0 + 32 * b + col;
-    const float bn = bias[n];
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int g = 0; g < 4; ++g) {
+      const int n = n0 + 32 * a + 8 * g + 4 * half;
+      const float4 bn = *reinterpret_cast<const float4*>(bias + n);
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const int row = 32 * a + 8 * (i >> 2) + 4 * half + (i & 3);
-        const float z = acc[a][b][i] + bn;
-        Out[row * kHP + n] = (uint16_t)bf16_bits(z / (1.f + expf(-z)));
+      for (int b = 0; b < 2; ++b) {
+        const sf32x4 z = {acc[a][b][4 * g] + bn.x, acc[a][b][4 * g + 1] + bn.y, acc[a][b][4 * g + 2] + bn.z,
+                          acc[a][b][4 * g + 3] + bn.w};
+        const sf32x4 h = {silu_fast(z.x), silu_fast(z.y), silu_fast(z.z), silu_fast(z.w)};
+        *reinterpret_cast<sbf16x4*>(Out + (32 * b + col) * kHP + n) = __builtin_convertvector(h, sbf16x4);
       }
-  }
+    }
 }
 
-// surrogate + judge + fallback of one agent (the finish of the step)
+// The finish of the step for one agent: the surrogate state (nominal step +
+// residual, q renormalised), the full step where the agent is judged, out of
+// distribution or already on the fallback, then the judge and the sticky
+// fallback.
 __device__ __forceinline__ void sur_finish_one(int A, int i, float dt, int t, int period,
                                                const float* __restrict__ s_in, const float* __restrict__ a,
-                                               const float* __restrict__ prm, const float* y, const float* z,
+                                               const float* __restrict__ prm, const float* y, bool ood,
                                                const float* __restrict__ norm, float* __restrict__ s_out,
                                                uint8_t* __restrict__ fallback, float* __restrict__ judged_err,
                                                const JudgeThr& thr) {
-  float s[13], u[4], p[8], nom[13], sur[13];
+  float s[13], u[4], p[8], nom[13], sur[13], full[13];
   for (int c = 0; c < 13; ++c) s[c] = s_in[(size_t)c * A + i];
   for (int k = 0; k < 4; ++k) u[k] = a[(size_t)k * A + i];
   for (int k = 0; k < 8; ++k) p[k] = prm[(size_t)k * A + i];
-  step_regs<SIM_NOMINAL13, SIM_RK4>(s, u, p, dt, nom);
+  const bool judged = ((i + t) % period) == 0;
+  bool fb = fallback[i] != 0;
+  const bool need = judged || ood || fb;
+  // where any lane of the wave needs the full step, both steps are taken
+  // side by side (two independent dependency chains in one block of code)
+  if (__builtin_amdgcn_ballot_w64(need) != 0) {
+    step_regs<SIM_NOMINAL13, SIM_RK4>(s, u, p, dt, nom);
+    step_regs<SIM_RB13, SIM_RK4>(s, u, p, dt, full);
+  } else {
+    step_regs<SIM_NOMINAL13, SIM_RK4>(s, u, p, dt, nom);
+  }
   const float* mu_d = norm + 2 * kSIn;
   const float* sd_d = norm + 2 * kSIn + kSOut;
   for (int c = 0; c < 13; ++c) sur[c] = nom[c] + mu_d[c] + sd_d[c] * y[c];
@@ -271,16 +303,10 @@ __device__ __forceinline__ void sur_finish_one(int A, int i, float dt, int t, in
     quat_normalize(sur + 6, qn, nullptr);
     for (int k = 0; k < 4; ++k) sur[6 + k] = qn[k];
   }
-  bool ood = false;
-  for (int c = 0; c < kSIn; ++c) ood |= fabsf(z[c]) > kOodZ;
-  const bool judged = ((i + t) % period) == 0;
-  bool fb = fallback[i] != 0;
   float err[4] = {__builtin_nanf(""), __builtin_nanf(""), __builtin_nanf(""), __builtin_nanf("")};
   float out[13];
   for (int c = 0; c < 13; ++c) out[c] = sur[c];
-  if (judged || ood || fb) {
-    float full[13];
-    step_regs<SIM_RB13, SIM_RK4>(s, u, p, dt, full);
+  if (need) {
     const int lo[4] = {0, 3, 6, 10}, hi[4] = {3, 6, 10, 13};
     bool bad = false;
     for (int k = 0; k < 4; ++k) {
@@ -299,64 +325,83 @@ __device__ __forceinline__ void sur_finish_one(int A, int i, float dt, int t, in
     for (int k = 0; k < 4; ++k) judged_err[(size_t)k * A + i] = err[k];
 }
 
-__global__ __launch_bounds__(256) void sur_step_kernel(int A, float dt, int t, int period,
-                                                       const float* __restrict__ s_in,
-                                                       const float* __restrict__ a,
-                                                       const float* __restrict__ prm,
-                                                       const float* __restrict__ norm,
-                                                       const float* __restrict__ P,
-                                                       const uint16_t* __restrict__ Wb,
-                                                       float* __restrict__ s_out, uint8_t* __restrict__ fallback,
-                                                       float* __restrict__ judged_err, JudgeThr thr) {
+// LDS: 39 KB, so four workgroups of four waves share a CU
+__global__ __launch_bounds__(256, 4) void sur_step_kernel(int A, float dt, int t, int period,
+                                                          const float* __restrict__ s_in,
+                                                          const float* __restrict__ a,
+                                                          const float* __restrict__ prm,
+                                                          const float* __restrict__ norm,
+                                                          const float* __restrict__ P,
+                                                          const uint16_t* __restrict__ Wb,
+                                                          float* __restrict__ s_out, uint8_t* __restrict__ fallback,
+                                                          float* __restrict__ judged_err, JudgeThr thr) {
+  // z rows (BF16) until layer 1 has read them, then the output layer (FP32)
   __shared__ __attribute__((aligned(16))) uint16_t Zs[kFB * kZP];
   __shared__ __attribute__((aligned(16))) uint16_t Hs[kFB * kHP];  // layer 1, then layer 2 output
-  __shared__ float Ys[kFB][kSOutP];
-  __shared__ float Zf[kFB][kSIn];
+  __shared__ uint8_t Ob[4][kFB];  // out-of-distribution input, per column group
+  static_assert(kFB * kSOutP * 4 <= kFB * kZP * 2, "output layer fits the z rows");
+  float(*Ys)[kSOutP] = reinterpret_cast<float(*)[kSOutP]>(Zs);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int col = lane & 31, half = lane >> 5;
   const int r0 = blockIdx.x * kFB;
-  // z-scored inputs (rows past A are zero and never written back)
-  if (tid < kFB) {
-    const int i = r0 + tid;
-    for (int c = 0; c < kZP; ++c) {
+  // z-scored inputs, agent tid % 64, columns tid / 64 + 4j (rows past A are
+  // zero and never written back; columns 17 .. 39 are zero)
+  {
+    const int m = tid & 63, i = r0 + m;
+    bool ood = false;
+    for (int c = tid >> 6; c < kZP; c += 4) {
       float v = 0.f;
       if (i < A && c < kSIn)
         v = c < 13 ? (s_in[(size_t)c * A + i] - norm[c]) / norm[kSIn + c]
                    : (a[(size_t)(c - 13) * A + i] - norm[c]) / norm[kSIn + c];
-      if (c < kSIn) Zf[tid][c] = v;
-      Zs[tid * kZP + c] = (uint16_t)bf16_bits(v);
+      ood |= fabsf(v) > kOodZ;
+      Zs[m * kZP + c] = (uint16_t)bf16_bits(v);
     }
+    Ob[tid >> 6][m] = ood;
   }
   __syncthreads();
   const int n0 = wave * 64;
   sf32x16 acc[2][2];
-  sur_layer<kW1bK / 16>(Zs, kZP, Wb + kBW1, kW1bK, n0, col, half, acc);
+  sur_layer<kW1bK / 16>(Zs, kZP, Wb + kBW1, n0, lane, col, half, acc);
   sur_silu_out(acc, P + kPB1, Hs, n0, col, half);
   __syncthreads();
-  sur_layer<kSH / 16>(Hs, kHP, Wb + kBW2, kSH, n0, col, half, acc);
+  sur_layer<kSH / 16>(Hs, kHP, Wb + kBW2, n0, lane, col, half, acc);
   __syncthreads();  // every wave is done reading layer 1's output
   sur_silu_out(acc, P + kPB2, Hs, n0, col, half);
   __syncthreads();
   if (wave < 2) {
-    // output layer: rows 32 wave .., 32 padded columns (13 used)
-    sf32x16 y;
+    // output layer, transposed: outputs 8(i/4) + 4half + i%4 (13 of 32 used)
+    // of agents 32 wave + col; all weight fragments requested up front, even
+    // and odd k chunks accumulated separately
+    sf32x16 y, y1;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) y[i] = 0.f;
-#pragma unroll 4
-    for (int kc = 0; kc < kSH / 16; ++kc) {
+    for (int i = 0; i < 16; ++i) y[i] = y1[i] = 0.f;
+#pragma unroll
+    for (int kc = 0; kc < kSH / 16; kc += 2) {
       const int ko = kc * 16 + half * 8;
-      const sbf16x8 af = *reinterpret_cast<const sbf16x8*>(Hs + (32 * wave + col) * kHP + ko);
-      const sbf16x8 bf = *reinterpret_cast<const sbf16x8*>(Wb + kBW3 + (size_t)col * kSH + ko);
-      y = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af, bf, y, 0, 0, 0);
+      const sbf16x8 w0 = *reinterpret_cast<const sbf16x8*>(Wb + kBW3 + frag_index(0, kc, kSH / 16, lane));
+      const sbf16x8 w1 = *reinterpret_cast<const sbf16x8*>(Wb + kBW3 + frag_index(0, kc + 1, kSH / 16, lane));
+      const sbf16x8 h0 = *reinterpret_cast<const sbf16x8*>(Hs + (32 * wave + col) * kHP + ko);
+      const sbf16x8 h1 = *reinterpret_cast<const sbf16x8*>(Hs + (32 * wave + col) * kHP + ko + 16);
+      y = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w0, h0, y, 0, 0, 0);
+      y1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1, h1, y1, 0, 0, 0);
     }
-    if (col < kSOutP)
+    y += y1;
 #pragma unroll
-      for (int i = 0; i < 16; ++i) Ys[32 * wave + 8 * (i >> 2) + 4 * half + (i & 3)][col] = y[i] + P[kPB3 + col];
+    for (int g = 0; g < 2; ++g)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int n = 8 * g + 4 * half + j;
+        Ys[32 * wave + col][n] = y[4 * g + j] + P[kPB3 + n];
+      }
   }
   __syncthreads();
-  if (tid < kFB && r0 + tid < A)
-    sur_finish_one(A, r0 + tid, dt, t, period, s_in, a, prm, Ys[tid], Zf[tid], norm, s_out, fallback,
-                   judged_err, thr);
+  // finish, on one wave (which one rotates with the workgroup, so that the
+  // finishing waves of co-resident workgroups use different SIMDs)
+  if (wave == (blockIdx.x & 3) && r0 + lane < A)
+    sur_finish_one(A, r0 + lane, dt, t, period, s_in, a, prm, Ys[lane],
+                   (Ob[0][lane] | Ob[1][lane] | Ob[2][lane] | Ob[3][lane]) != 0, norm, s_out, fallback, judged_err,
+                   thr);
 }
 
 }  // namespace da
