@@ -189,8 +189,8 @@ __device__ __forceinline__ void store_tile_bf16(uint16_t* S, const float4 (&reg)
     if (KMAJ) {
       const int row = (t >> 3) + 32 * i, k = (t & 7) * 4;
       uint2 v;
-      v.x = bf16_bits(reg[i].x) | (bf16_bits(reg[i].y) << 16);
-      v.y = bf16_bits(reg[i].z) | (bf16_bits(reg[i].w) << 16);
+      v.x = bf16_pack2(reg[i].x, reg[i].y);
+      v.y = bf16_pack2(reg[i].z, reg[i].w);
       *reinterpret_cast<uint2*>(S + row * BKP + k) = v;
     } else {
       const int kk = (t >> 5) + 8 * i, m = (t & 31) * 4;
@@ -274,11 +274,8 @@ static int gemm_bf16_t(const GemmArgs& g, int splits, hipStream_t st) {
 // written with 16-byte stores; the pitch (five 16-byte units) keeps these
 // stores and the fragment reads free of bank conflicts.
 __device__ __forceinline__ void split2(float a, float b, uint32_t& h, uint32_t& l) {
-  const uint32_t h0 = bf16_bits(a), h1 = bf16_bits(b);
-  const uint32_t l0 = bf16_bits(a - __uint_as_float(h0 << 16));
-  const uint32_t l1 = bf16_bits(b - __uint_as_float(h1 << 16));
-  h = h0 | (h1 << 16);
-  l = l0 | (l1 << 16);
+  h = bf16_pack2(a, b);
+  l = bf16_pack2(a - __uint_as_float(h << 16), b - __uint_as_float(h & 0xffff0000u));
 }
 
 __device__ __forceinline__ void store_tile_split_k(uint16_t* H, uint16_t* L, const float4 (&reg)[4]) {
@@ -433,8 +430,9 @@ int launch_split_transpose(int R, int K, const float* src, int ld, uint16_t* hi,
   return SIM_OK;
 }
 
+// at most 168 registers per lane: three workgroups per CU (LDS 40 KB each)
 template <int AM, int BM_, int EPI>
-__global__ __launch_bounds__(256) void gemm_x3_kernel(GemmArgs g) {
+__global__ __launch_bounds__(256, 3) void gemm_x3_kernel(GemmArgs g) {
   __shared__ __attribute__((aligned(16))) uint16_t Ah[GBM * BKP];
   __shared__ __attribute__((aligned(16))) uint16_t Al[GBM * BKP];
   __shared__ __attribute__((aligned(16))) uint16_t Bh[GBN * BKP];
@@ -593,6 +591,9 @@ __global__ void splitk_reduce_kernel(int S, int M, int N, int ldp, const float* 
   if (idx >= M * N) return;
   const int m = idx / N, n = idx % N;
   float v = 0.f;
+  // unrolled so that the loads of eight partials are in flight together; the
+  // adds keep their order
+#pragma unroll 8
   for (int s = 0; s < S; ++s) v += part[(size_t)s * M * ldp + (size_t)m * ldp + n];
   if (accumulate) v += out[(size_t)m * ldo + n];
   out[(size_t)m * ldo + n] = v;
@@ -653,6 +654,7 @@ __global__ void colsum_partial_kernel(int M, int N, const float* __restrict__ X,
   const int r0 = blockIdx.y * rows_per, r1 = min(M, r0 + rows_per);
   float v = 0.f;
   if (c < N)
+#pragma unroll 8
     for (int m = r0 + g; m < r1; m += 4) v += X[(size_t)m * ld + c];
   red[g][threadIdx.x & 63] = v;
   __syncthreads();
@@ -670,6 +672,7 @@ __global__ void colsum_final_kernel(int S, int N, const float* __restrict__ part
   const int g = threadIdx.x >> 6;
   float v = 0.f;
   if (c < N)
+#pragma unroll 8
     for (int s = g; s < S; s += 4) v += part[(size_t)s * N + c];
   red[g][threadIdx.x & 63] = v;
   __syncthreads();

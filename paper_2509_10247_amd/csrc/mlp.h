@@ -58,12 +58,17 @@ int launch_split_transpose(int R, int K, const float* src, int ld, uint16_t* hi,
                            hipStream_t st);
 constexpr int kSplitPad = 32;  // K padding of pre-split operands
 
-// FP32 -> BF16 bit pattern, round to nearest even (NaN stays a quiet NaN).
+// FP32 -> BF16, round to nearest even, on the gfx950 conversion instruction
+// (v_cvt_pk_bf16_f32; for every non-NaN input it gives the bits of the
+// integer rounding (u + 0x7fff + lsb) >> 16, NaN stays NaN).
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ uint32_t bf16_bits(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return u >> 16;
+  return __builtin_bit_cast(uint16_t, static_cast<__bf16>(f));
+}
+// two values packed: bits of a in the low half, b in the high half
+__device__ __forceinline__ uint32_t bf16_pack2(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2_t){a, b}, bf16x2_t));
 }
 
 // Precision of launch_gemm:
