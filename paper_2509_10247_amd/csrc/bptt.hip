@@ -28,7 +28,8 @@ static void tpair(bptt_handle* b, int cls, int a, int z);
 constexpr int kHid = 256, kOut = 4;
 constexpr int kRays = 3072;            // 64 x 48 camera
 constexpr int kObs = kRays + 9;        // 3081 inputs
-constexpr int kObsPad = 3084;          // padded row pitch (multiple of 4)
+constexpr int kObsK = 3084;            // policy-input extent of the GEMMs (multiple of 4, >= kObs)
+constexpr int kObsPad = 3104;          // row pitch: 128-byte aligned rows for the GEMM operand / output
 constexpr size_t kOffW1 = 0;
 constexpr size_t kOffB1 = kOffW1 + (size_t)kHid * kObs;
 constexpr size_t kOffW2 = kOffB1 + kHid;
@@ -207,7 +208,7 @@ constexpr int kSplitL1 = 3;
 static int mlp_forward(int B, const PolicyPtrs& p, const float* X, float* H1, float* H2, float* Y,
                        hipStream_t st, int prec, float* part, bptt_handle* owner = nullptr) {
   GemmArgs g;
-  g.M = B; g.N = kHid; g.K = kObsPad;
+  g.M = B; g.N = kHid; g.K = kObsK;
   g.A = X; g.lda = kObsPad; g.B = p.W1p; g.ldb = kObsPad;
   g.C = H1; g.ldc = kHid; g.bias = p.b1;
   const int e0 = owner ? tmark(owner, st) : -1;
@@ -220,7 +221,7 @@ static int mlp_forward(int B, const PolicyPtrs& p, const float* X, float* H1, fl
   if (part) {
     g.C = part;
     if ((rc = launch_gemm(true, true, EPI_PARTIAL, g, kSplitL1, st, prec))) return rc;
-    rc = launch_splitk_bias_tanh(gemm_splits_used(kObsPad, kSplitL1), B, kHid, kHid, part, p.b1, H1, kHid,
+    rc = launch_splitk_bias_tanh(gemm_splits_used(kObsK, kSplitL1), B, kHid, kHid, part, p.b1, H1, kHid,
                                  st);
   } else {
     rc = launch_gemm(true, true, EPI_BIAS_TANH, g, 1, st, prec);
@@ -250,7 +251,7 @@ struct MlpGradBufs {
 constexpr int kSplitW1 = 8, kSplitW2 = 64, kSplitW3 = 64;
 
 static size_t partial_floats(int B) {
-  const size_t l1 = (size_t)gemm_splits_used(kObsPad, kSplitL1) * B * kHid;
+  const size_t l1 = (size_t)gemm_splits_used(kObsK, kSplitL1) * B * kHid;
   size_t a = std::max(l1, (size_t)gemm_splits_used(B, kSplitW1) * kHid * kObsPad);
   size_t b = (size_t)gemm_splits_used(B, kSplitW2) * kHid * kHid;
   size_t c = (size_t)gemm_splits_used(B, kSplitW3) * kOut * kHid;
@@ -286,7 +287,7 @@ static int mlp_backward_data(int B, const PolicyPtrs& p, const float* H1, const 
   // gX = gZ1 W1
   et = owner ? tmark(owner, st) : -1;
   g = GemmArgs();
-  g.M = B; g.N = kObsPad; g.K = kHid;
+  g.M = B; g.N = kObsK; g.K = kHid;
   g.A = z.gZ1; g.lda = kHid; g.B = p.W1p; g.ldb = kObsPad; g.C = gX; g.ldc = kObsPad;
   if (p.W1t_hi && z1_hi) {
     // both operands pre-split: gZ1 here, W1^T once per iteration
@@ -329,10 +330,10 @@ static int mlp_backward_weights(int B, const float* X, const float* H1, const fl
   // gW1 += gZ1^T X ; gb1
   et = owner ? tmark(owner, st) : -1;
   g = GemmArgs();
-  g.M = kHid; g.N = kObsPad; g.K = B;
+  g.M = kHid; g.N = kObsK; g.K = B;
   g.A = z.gZ1; g.lda = kHid; g.B = X; g.ldb = kObsPad; g.C = part; g.ldc = kObsPad;
   if ((rc = launch_gemm(false, false, EPI_PARTIAL, g, kSplitW1, st, prec))) return rc;
-  if ((rc = launch_splitk_reduce(gemm_splits_used(B, kSplitW1), kHid, kObsPad, kObsPad, part, gb.gW1p,
+  if ((rc = launch_splitk_reduce(gemm_splits_used(B, kSplitW1), kHid, kObsK, kObsPad, part, gb.gW1p,
                                  kObsPad, true, st)))
     return rc;
   if (owner) tpair(owner, BPTT_T_GW1, et, tmark(owner, st));

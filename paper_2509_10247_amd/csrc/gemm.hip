@@ -18,6 +18,40 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int GBM = 128, GBN = 128, GBK = 32;
 
+// Tile of a workgroup. Workgroups are dispatched round-robin over the eight
+// XCDs by linear index (x fastest, then y, then z), and each XCD has its own
+// L2. The linear index is remapped so that XCD k works through one
+// contiguous range of tiles, ordered split (z) slowest and, within a split,
+// with the grid dimension that has fewer tiles fastest: the tiles that read
+// the same operand rows run on one XCD, one after another, and share its L2.
+// The map is a bijection for any grid. It pays for the split-K launches
+// (the long-K layers, which stream a large operand); the others keep the
+// dispatch order.
+constexpr int kXcds = 8;
+struct Tile {
+  int m, n, z;  // M-tile, N-tile, K-split
+};
+template <bool XCD>
+__device__ __forceinline__ Tile gemm_tile() {
+  if (!XCD) return Tile{(int)blockIdx.y, (int)blockIdx.x, (int)blockIdx.z};
+  const int NX = gridDim.x, NY = gridDim.y;
+  const int total = NX * NY * gridDim.z;
+  const int L = blockIdx.x + NX * (blockIdx.y + NY * blockIdx.z);
+  const int k = L % kXcds, j = L / kXcds, q = total / kXcds, r = total % kXcds;
+  const int t = k * q + min(k, r) + j;
+  const int per_z = NX * NY, w = t % per_z;
+  Tile c;
+  c.z = t / per_z;
+  if (NX <= NY) {
+    c.n = w % NX;
+    c.m = w / NX;
+  } else {
+    c.m = w % NY;
+    c.n = w / NY;
+  }
+  return c;
+}
+
 template <bool KMAJ>
 struct Stage {
   // LDS row pitch (floats): K-contiguous operands are written transposed with
@@ -75,9 +109,9 @@ __device__ __forceinline__ void store_tile(float* S, const float4 (&reg)[4]) {
 // 8*(i/4) + 4*(lane/32) + (i%4) for accumulator i.
 template <int EPI>
 __device__ __forceinline__ void gemm_epilogue(const GemmArgs& g, const f32x16 (&acc)[2][2], int m0, int n0,
-                                              int wm, int wn, int col, int half) {
+                                              int wm, int wn, int col, int half, int split) {
   float* C = g.C;
-  if (EPI == EPI_PARTIAL) C += (size_t)blockIdx.z * g.M * g.ldc;
+  if (EPI == EPI_PARTIAL) C += (size_t)split * g.M * g.ldc;
   float obs_c = g.obs_c;
   if (EPI == EPI_OBS_GRAD && g.obs_gl) obs_c *= g.obs_gl[0];
 #pragma unroll
@@ -130,8 +164,9 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(GemmArgs g) {
   __shared__ __attribute__((aligned(16))) float Bs[GBK * PB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
-  const int m0 = blockIdx.y * GBM, n0 = blockIdx.x * GBN;
-  const int kbeg = blockIdx.z * g.k_split;
+  const Tile tile = gemm_tile<EPI == EPI_PARTIAL>();
+  const int m0 = tile.m * GBM, n0 = tile.n * GBN;
+  const int kbeg = tile.z * g.k_split;
   const int kend = min(g.K, kbeg + g.k_split);
 
   f32x16 acc[2][2];
@@ -169,7 +204,7 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(GemmArgs g) {
     }
   }
 
-  gemm_epilogue<EPI>(g, acc, m0, n0, wm, wn, col, half);
+  gemm_epilogue<EPI>(g, acc, m0, n0, wm, wn, col, half, tile.z);
 }
 
 // ---------------------------------------------------------------------------
@@ -208,8 +243,9 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g) {
   __shared__ __attribute__((aligned(16))) uint16_t Bs[GBN * BKP];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
-  const int m0 = blockIdx.y * GBM, n0 = blockIdx.x * GBN;
-  const int kbeg = blockIdx.z * g.k_split;
+  const Tile tile = gemm_tile<EPI == EPI_PARTIAL>();
+  const int m0 = tile.m * GBM, n0 = tile.n * GBN;
+  const int kbeg = tile.z * g.k_split;
   const int kend = min(g.K, kbeg + g.k_split);
   f32x16 acc[2][2];
 #pragma unroll
@@ -246,7 +282,7 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g) {
       acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc[1][1], 0, 0, 0);
     }
   }
-  gemm_epilogue<EPI>(g, acc, m0, n0, wm, wn, col, half);
+  gemm_epilogue<EPI>(g, acc, m0, n0, wm, wn, col, half, tile.z);
 }
 
 template <bool AK, bool BK_, int EPI>
@@ -439,8 +475,9 @@ __global__ __launch_bounds__(256, 3) void gemm_x3_kernel(GemmArgs g) {
   __shared__ __attribute__((aligned(16))) uint16_t Bl[GBN * BKP];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
-  const int m0 = blockIdx.y * GBM, n0 = blockIdx.x * GBN;
-  const int kbeg = blockIdx.z * g.k_split;
+  const Tile tile = gemm_tile<EPI == EPI_PARTIAL>();
+  const int m0 = tile.m * GBM, n0 = tile.n * GBN;
+  const int kbeg = tile.z * g.k_split;
   const int kend = min(g.K, kbeg + g.k_split);
   f32x16 acc[2][2];
 #pragma unroll
@@ -493,7 +530,7 @@ __global__ __launch_bounds__(256, 3) void gemm_x3_kernel(GemmArgs g) {
           acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
     }
   }
-  gemm_epilogue<EPI>(g, acc, m0, n0, wm, wn, col, half);
+  gemm_epilogue<EPI>(g, acc, m0, n0, wm, wn, col, half, tile.z);
 }
 
 template <int AM, int BM_, int EPI>
