@@ -118,9 +118,9 @@ __global__ __launch_bounds__(1024) void loss_final_kernel(int A, const float* __
 // g_next += d(loss_t)/d(s_{t+1}) for the position and velocity terms.
 __global__ void loss_state_grad_kernel(int A, const float* __restrict__ s1,
                                        const float* __restrict__ goal, float cp, float cv,
-                                       const float* __restrict__ gl, float* __restrict__ g) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= A) return;
+                                       const float* __restrict__ gl, float* __restrict__ g, int i0, int n) {
+  const int b = i0 + (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (b >= i0 + n) return;
   const float sc = gl ? gl[0] : 1.f;
   for (int k = 0; k < 3; ++k) {
     g[(size_t)k * A + b] += sc * cp * (s1[(size_t)k * A + b] - goal[(size_t)k * A + b]);
@@ -131,9 +131,9 @@ __global__ void loss_state_grad_kernel(int A, const float* __restrict__ s1,
 // dL/dy from the action gradient and the action-magnitude loss term.
 __global__ void action_bwd_kernel(int A, int model, const float* __restrict__ ga,
                                   const float* __restrict__ Y, const float* __restrict__ prm, float cu,
-                                  const float* __restrict__ gl, float* __restrict__ gY) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= A) return;
+                                  const float* __restrict__ gl, float* __restrict__ gY, int i0, int n) {
+  const int b = i0 + (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (b >= i0 + n) return;
   const float sc = gl ? gl[0] : 1.f;
   const float* y = Y + (size_t)b * kOut;
   float g[kOut];
@@ -151,9 +151,9 @@ __global__ void action_bwd_kernel(int A, int model, const float* __restrict__ ga
 // to g_s (obs = [goal - p, v, b]); the depth part is folded into the render
 // adjoint (DepthObsGrad).
 __global__ void obs_bwd_kernel(int A, int model, const float* __restrict__ gX, const float* __restrict__ s,
-                               float* __restrict__ g_s) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= A) return;
+                               float* __restrict__ g_s, int i0, int n) {
+  const int b = i0 + (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (b >= i0 + n) return;
   const float* grow = gX + (size_t)b * kObsPad + kRays;
   for (int k = 0; k < 3; ++k) {
     g_s[(size_t)k * A + b] -= grow[k];
@@ -384,6 +384,9 @@ struct bptt_handle {
   int prec = GEMM_FP32;
   hipStream_t side = nullptr;               // recompute stream (stored mode)
   hipEvent_t ev_start = nullptr, ev_rec[2] = {nullptr, nullptr}, ev_free[2] = {nullptr, nullptr};
+  // second half of the batch in the backward sweep (stored mode)
+  hipStream_t half2 = nullptr;
+  hipEvent_t ev_z2[2] = {nullptr, nullptr}, ev_seg2 = nullptr, ev_h2done = nullptr;
   // optional HIP-event timing of the main kernel classes (BPTT_T_*)
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
@@ -415,8 +418,10 @@ static int ensure_streams(bptt_handle* b) {
   if (b->side) return SIM_OK;
   DA_HIP(hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking));
   DA_HIP(hipStreamCreateWithFlags(&b->wgrad, hipStreamNonBlocking));
+  DA_HIP(hipStreamCreateWithFlags(&b->half2, hipStreamNonBlocking));
   for (hipEvent_t* e : {&b->ev_start, &b->ev_rec[0], &b->ev_rec[1], &b->ev_free[0], &b->ev_free[1], &b->ev_z[0],
-                        &b->ev_z[1], &b->ev_w[0], &b->ev_w[1], &b->ev_seg, &b->ev_wdone})
+                        &b->ev_z[1], &b->ev_w[0], &b->ev_w[1], &b->ev_seg, &b->ev_wdone, &b->ev_z2[0], &b->ev_z2[1],
+                        &b->ev_seg2, &b->ev_h2done})
     DA_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
   return SIM_OK;
 }
@@ -532,10 +537,12 @@ int bptt_destroy(bptt_handle* b) {
   if (!b) return SIM_OK;
   for (hipEvent_t e : b->ev_pool) (void)hipEventDestroy(e);
   for (hipEvent_t e : {b->ev_start, b->ev_rec[0], b->ev_rec[1], b->ev_free[0], b->ev_free[1], b->ev_z[0],
-                       b->ev_z[1], b->ev_w[0], b->ev_w[1], b->ev_seg, b->ev_wdone})
+                       b->ev_z[1], b->ev_w[0], b->ev_w[1], b->ev_seg, b->ev_wdone, b->ev_z2[0], b->ev_z2[1],
+                       b->ev_seg2, b->ev_h2done})
     if (e) (void)hipEventDestroy(e);
   if (b->side) (void)hipStreamDestroy(b->side);
   if (b->wgrad) (void)hipStreamDestroy(b->wgrad);
+  if (b->half2) (void)hipStreamDestroy(b->half2);
   if (b->mem) (void)hipFree(b->mem);
   delete b;
   return SIM_OK;
@@ -741,8 +748,21 @@ int bptt_backward(bptt_handle* b, const float* g_loss, float* g_theta, float* g_
     DA_HIP(hipEventRecord(b->ev_start, st));
     DA_HIP(hipStreamWaitEvent(b->side, b->ev_start, 0));
     DA_HIP(hipStreamWaitEvent(b->wgrad, b->ev_start, 0));
+    DA_HIP(hipStreamWaitEvent(b->half2, b->ev_start, 0));
     if (!kept_segment(b, b->nseg - 1) && (rc = recompute_renders(b->nseg - 1, b->side))) return rc;
     DA_HIP(hipEventRecord(b->ev_rec[(b->nseg - 1) & 1], b->side));
+  }
+  // With stored activations (and agents that do not see each other) the data
+  // path of the sweep runs as two halves of the batch on two streams, so that
+  // one half's policy GEMMs (matrix cores) can overlap the other half's render
+  // adjoint (VALU) and the kernels' tails overlap. Every lane's arithmetic is
+  // unchanged and the weight gradients stay full-batch.
+  int nh = 1, hi0[2] = {0, 0}, hn[2] = {A, 0};
+  if (overlap && !h->cfg.agents_visible && A >= 512) {
+    nh = 2;
+    hn[0] = ((A / 2 + 127) / 128) * 128;
+    hi0[1] = hn[0];
+    hn[1] = A - hn[0];
   }
   int wsteps = 0;  // weight-gradient steps enqueued on the wgrad stream
   for (int seg = b->nseg - 1; seg >= 0; --seg) {
@@ -760,6 +780,7 @@ int bptt_backward(bptt_handle* b, const float* g_loss, float* g_theta, float* g_
         DA_HIP(hipEventRecord(b->ev_rec[(seg - 1) & 1], b->side));
       }
       DA_HIP(hipStreamWaitEvent(st, b->ev_rec[set], 0));
+      if (nh == 2) DA_HIP(hipStreamWaitEvent(b->half2, b->ev_rec[set], 0));
     } else {
       // recompute the whole segment from its checkpoint
       DA_HIP(hipMemcpyAsync(b->seg_s, b->ckpt + (size_t)seg * C * A, sbytes, hipMemcpyDeviceToDevice, st));
@@ -781,32 +802,41 @@ int bptt_backward(bptt_handle* b, const float* g_loss, float* g_theta, float* g_
       const float* H2 = b->H2 + (size_t)si * A * kHid;
       const float* Y = b->Y + (size_t)si * A * kOut;
       const float* act = b->act + (size_t)si * Ka * A;
-      int e0 = tmark(b, st);
-      hipLaunchKernelGGL(loss_state_grad_kernel, dim3(cdiv(A, 256)), dim3(256), 0, st, A, s1, b->goal, cp,
-                         cv, g_loss, g_next);
-      DA_LAUNCH_CHECK("loss_state_grad_kernel");
-      tpair(b, BPTT_T_SMALL_BWD, e0, tmark(b, st));
-      e0 = tmark(b, st);
-      if ((rc = launch_step_vjp(h->cfg.model, h->cfg.integrator, A, h->cfg.dt, s, act, h->params, g_next,
-                                g_cur, b->ga, st)))
-        return rc;
-      tpair(b, BPTT_T_STEP_VJP, e0, tmark(b, st));
-      e0 = tmark(b, st);
-      hipLaunchKernelGGL(action_bwd_kernel, dim3(cdiv(A, 256)), dim3(256), 0, st, A, h->cfg.model, b->ga,
-                         Y, h->params, cu, g_loss, b->gY);
-      DA_LAUNCH_CHECK("action_bwd_kernel");
-      tpair(b, BPTT_T_SMALL_BWD, e0, tmark(b, st));
       // layer gradients of this step go to set `par`; with stored activations
       // the weight gradients run on their own stream, overlapping the data
       // path (gX GEMM, render adjoint) of this and the next step
       const int par = (t0 + j) & 1;
       const LayerGrads& z = b->z[par];
-      if (overlap && wsteps >= 2) DA_HIP(hipStreamWaitEvent(st, b->ev_w[par], 0));
-      if ((rc = mlp_backward_data(A, pp, H1, H2, Y, b->gY, z, b->gX, st, b->prec, b,
-                                  overlap ? b->ev_z[par] : nullptr, b->z1_hi, b->z1_lo)))
-        return rc;
+      for (int hf = 0; hf < nh; ++hf) {
+        hipStream_t q = hf ? b->half2 : st;
+        const int i0 = hi0[hf], m = hn[hf];
+        int e0 = tmark(b, q);
+        hipLaunchKernelGGL(loss_state_grad_kernel, dim3(cdiv(m, 256)), dim3(256), 0, q, A, s1, b->goal, cp, cv,
+                           g_loss, g_next, i0, m);
+        DA_LAUNCH_CHECK("loss_state_grad_kernel");
+        tpair(b, BPTT_T_SMALL_BWD, e0, tmark(b, q));
+        e0 = tmark(b, q);
+        if ((rc = launch_step_vjp(h->cfg.model, h->cfg.integrator, A, h->cfg.dt, s, act, h->params, g_next,
+                                  g_cur, b->ga, q, i0, m)))
+          return rc;
+        tpair(b, BPTT_T_STEP_VJP, e0, tmark(b, q));
+        e0 = tmark(b, q);
+        hipLaunchKernelGGL(action_bwd_kernel, dim3(cdiv(m, 256)), dim3(256), 0, q, A, h->cfg.model, b->ga, Y,
+                           h->params, cu, g_loss, b->gY, i0, m);
+        DA_LAUNCH_CHECK("action_bwd_kernel");
+        tpair(b, BPTT_T_SMALL_BWD, e0, tmark(b, q));
+        if (overlap && wsteps >= 2) DA_HIP(hipStreamWaitEvent(q, b->ev_w[par], 0));
+        const LayerGrads zh{z.gZ3 + (size_t)i0 * kOut, z.gZ2 + (size_t)i0 * kHid, z.gZ1 + (size_t)i0 * kHid};
+        hipEvent_t zr = overlap ? (hf ? b->ev_z2[par] : b->ev_z[par]) : nullptr;
+        if ((rc = mlp_backward_data(m, pp, H1 + (size_t)i0 * kHid, H2 + (size_t)i0 * kHid, Y + (size_t)i0 * kOut,
+                                    b->gY + (size_t)i0 * kOut, zh, b->gX + (size_t)i0 * kObsPad, q, b->prec, b, zr,
+                                    b->z1_hi ? b->z1_hi + (size_t)i0 * kHid : nullptr,
+                                    b->z1_lo ? b->z1_lo + (size_t)i0 * kHid : nullptr)))
+          return rc;
+      }
       if (overlap) {
         DA_HIP(hipStreamWaitEvent(b->wgrad, b->ev_z[par], 0));
+        if (nh == 2) DA_HIP(hipStreamWaitEvent(b->wgrad, b->ev_z2[par], 0));
         if ((rc = mlp_backward_weights(A, X, H1, H2, z, b->gb, b->part_w, b->wgrad, b->prec, nullptr)))
           return rc;
         DA_HIP(hipEventRecord(b->ev_w[par], b->wgrad));
@@ -814,18 +844,22 @@ int bptt_backward(bptt_handle* b, const float* g_loss, float* g_theta, float* g_
       } else if ((rc = mlp_backward_weights(A, X, H1, H2, z, b->gb, b->part, st, b->prec, b))) {
         return rc;
       }
-      e0 = tmark(b, st);
-      hipLaunchKernelGGL(obs_bwd_kernel, dim3(cdiv(A, 256)), dim3(256), 0, st, A, h->cfg.model, b->gX, s,
-                         g_cur);
-      DA_LAUNCH_CHECK("obs_bwd_kernel");
-      tpair(b, BPTT_T_SMALL_BWD, e0, tmark(b, st));
-      e0 = tmark(b, st);
-      // depth-observation backward fused into the render adjoint
-      const DepthObsGrad ob{X, dmax, b->cfg.beta, b->cfg.d_safe, co, g_loss};
-      if ((rc = launch_render_vjp(h->scene, h->cam.dev, h->cfg.model == SIM_RB13, s, A, b->gX,
-                                  kObsPad, hit, g_cur, st, &ob)))
-        return rc;
-      tpair(b, BPTT_T_RENDER_VJP, e0, tmark(b, st));
+      for (int hf = 0; hf < nh; ++hf) {
+        hipStream_t q = hf ? b->half2 : st;
+        const int i0 = hi0[hf], m = hn[hf];
+        int e0 = tmark(b, q);
+        hipLaunchKernelGGL(obs_bwd_kernel, dim3(cdiv(m, 256)), dim3(256), 0, q, A, h->cfg.model, b->gX, s, g_cur,
+                           i0, m);
+        DA_LAUNCH_CHECK("obs_bwd_kernel");
+        tpair(b, BPTT_T_SMALL_BWD, e0, tmark(b, q));
+        e0 = tmark(b, q);
+        // depth-observation backward fused into the render adjoint
+        const DepthObsGrad ob{X, dmax, b->cfg.beta, b->cfg.d_safe, co, g_loss};
+        if ((rc = launch_render_vjp(h->scene, h->cam.dev, h->cfg.model == SIM_RB13, s, A, b->gX, kObsPad, hit,
+                                    g_cur, q, &ob, i0, m)))
+          return rc;
+        tpair(b, BPTT_T_RENDER_VJP, e0, tmark(b, q));
+      }
       std::swap(g_next, g_cur);
     }
     if (overlap) {
@@ -833,12 +867,20 @@ int bptt_backward(bptt_handle* b, const float* g_loss, float* g_theta, float* g_
       // segment are done with it
       DA_HIP(hipEventRecord(b->ev_seg, st));
       DA_HIP(hipStreamWaitEvent(b->wgrad, b->ev_seg, 0));
+      if (nh == 2) {
+        DA_HIP(hipEventRecord(b->ev_seg2, b->half2));
+        DA_HIP(hipStreamWaitEvent(b->wgrad, b->ev_seg2, 0));
+      }
       DA_HIP(hipEventRecord(b->ev_free[set], b->wgrad));
     }
   }
   if (overlap) {
     DA_HIP(hipEventRecord(b->ev_wdone, b->wgrad));
     DA_HIP(hipStreamWaitEvent(st, b->ev_wdone, 0));
+    if (nh == 2) {
+      DA_HIP(hipEventRecord(b->ev_h2done, b->half2));
+      DA_HIP(hipStreamWaitEvent(st, b->ev_h2done, 0));
+    }
   }
   if (g_s0) DA_HIP(hipMemcpyAsync(g_s0, g_next, sbytes, hipMemcpyDeviceToDevice, st));
   return write_flat_grad(b->gb, g_theta, st);

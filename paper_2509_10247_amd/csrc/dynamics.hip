@@ -40,15 +40,16 @@ __global__ __launch_bounds__(256) void step_kernel(int n, int A, float dt, const
 }
 
 template <int M, int I>
-__global__ __launch_bounds__(256) void step_vjp_kernel(int A, float dt, const float* __restrict__ s_in,
+__global__ __launch_bounds__(256) void step_vjp_kernel(int n, int A, float dt, const float* __restrict__ s_in,
                                                        const float* __restrict__ a,
                                                        const float* __restrict__ prm,
                                                        const float* __restrict__ g_next,
                                                        float* __restrict__ g_s,
                                                        float* __restrict__ g_a) {
+  // n lanes from the (pre-offset) pointers; A is the SoA component stride
   constexpr int C = Dim<M>::C, K = Dim<M>::K, P = Dim<M>::P;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= A) return;
+  if (i >= n) return;
   float s[C], u[K], p[P > 0 ? P : 1], g[C], gs[C], gu[K];
   for (int c = 0; c < C; ++c) s[c] = s_in[(size_t)c * A + i];
   for (int k = 0; k < K; ++k) u[k] = a[(size_t)k * A + i];
@@ -72,9 +73,10 @@ static int launch_step_t(int A, float dt, const float* s_in, const float* a, con
 
 template <int M, int I>
 static int launch_step_vjp_t(int A, float dt, const float* s, const float* a, const float* prm,
-                             const float* g_next, float* g_s, float* g_a, hipStream_t st) {
-  hipLaunchKernelGGL((step_vjp_kernel<M, I>), dim3(cdiv(A, 256)), dim3(256), 0, st, A, dt, s, a,
-                     prm, g_next, g_s, g_a);
+                             const float* g_next, float* g_s, float* g_a, hipStream_t st, int i0, int n) {
+  if (n <= 0) return SIM_OK;
+  hipLaunchKernelGGL((step_vjp_kernel<M, I>), dim3(cdiv(n, 256)), dim3(256), 0, st, n, A, dt, s + i0, a + i0,
+                     prm ? prm + i0 : nullptr, g_next ? g_next + i0 : nullptr, g_s + i0, g_a ? g_a + i0 : nullptr);
   DA_LAUNCH_CHECK("step_vjp_kernel");
   return SIM_OK;
 }
@@ -99,8 +101,10 @@ int launch_step(int model, int integ, int A, float dt, const float* s_in, const 
 }
 
 int launch_step_vjp(int model, int integ, int A, float dt, const float* s, const float* a,
-                    const float* prm, const float* g_next, float* g_s, float* g_a, hipStream_t st) {
-  DA_DISPATCH_MODEL(model, integ, launch_step_vjp_t, A, dt, s, a, prm, g_next, g_s, g_a, st);
+                    const float* prm, const float* g_next, float* g_s, float* g_a, hipStream_t st, int i0,
+                    int n) {
+  if (n < 0) n = A - i0;
+  DA_DISPATCH_MODEL(model, integ, launch_step_vjp_t, A, dt, s, a, prm, g_next, g_s, g_a, st, i0, n);
 }
 
 int state_dim(int model) {

@@ -41,7 +41,8 @@ int param_dim(int model);
 int launch_step(int model, int integ, int A, float dt, const float* s_in, const float* a,
                 const float* prm, float* s_out, uint8_t* flags, hipStream_t st, int i0 = 0, int n = -1);
 int launch_step_vjp(int model, int integ, int A, float dt, const float* s, const float* a,
-                    const float* prm, const float* g_next, float* g_s, float* g_a, hipStream_t st);
+                    const float* prm, const float* g_next, float* g_s, float* g_a, hipStream_t st, int i0 = 0,
+                    int n = -1);
 
 // Render one sensor for agents [0, A): out[i*out_ld + r] = value * out_scale
 // (out_ld >= n_rays), rec[i*n_rays + r] (nullable). If term is given, also
@@ -64,7 +65,7 @@ struct DepthObsGrad {
 };
 int launch_render_vjp(const SceneDev& sc, const SensorDev& sen, bool rotate, const float* s, int A,
                       const float* g, int g_ld, const int* rec, float* g_s, hipStream_t st,
-                      const DepthObsGrad* obs = nullptr);
+                      const DepthObsGrad* obs = nullptr, int i0 = 0, int n = -1);
 int launch_collide(const SceneDev& sc, const float* s, int A, uint8_t* flags, float* min_dist,
                    hipStream_t st);
 

@@ -87,10 +87,10 @@ __global__ __launch_bounds__(256, 5) void render_vjp_kernel(SceneDev sc, SensorD
                                                          const float* __restrict__ s, int A,
                                                          const float* __restrict__ g, int g_ld,
                                                          const int* __restrict__ rec,
-                                                         float* __restrict__ g_s, DepthObsGrad ob) {
+                                                         float* __restrict__ g_s, DepthObsGrad ob, int i0) {
   __shared__ double red[12][4];
   __shared__ double Rsh[3][3];  // FP64 rotation, read by the grazing-hit path only
-  const int i = blockIdx.x;
+  const int i = i0 + (int)blockIdx.x;
   const int tid = threadIdx.x;
   const int env = sc.agent_env[i];
   const f3 o = mk3(s[i], s[(size_t)A + i], s[2 * (size_t)A + i]);
@@ -374,21 +374,23 @@ int launch_render_work(const SceneDev& sc, const SensorDev& sen, bool rotate, bo
 
 int launch_render_vjp(const SceneDev& sc, const SensorDev& sen, bool rotate, const float* s, int A,
                       const float* g, int g_ld, const int* rec, float* g_s, hipStream_t st,
-                      const DepthObsGrad* obs) {
-  if (A == 0) return SIM_OK;
+                      const DepthObsGrad* obs, int i0, int n) {
+  if (n < 0) n = A - i0;
+  if (n <= 0) return SIM_OK;
   const size_t lds = (size_t)2 * (sc.max_prims + 1) * sizeof(float4);
   const DepthObsGrad ob = obs ? *obs : DepthObsGrad{nullptr, 1.f, 0.f, 0.f, 0.f, nullptr};
   if (obs && !obs->x) return fail(SIM_EINVAL, "render_vjp: observation rows missing");
+  const dim3 grid(n), blk(256);
   if (rotate) {
     if (obs)
-      hipLaunchKernelGGL((render_vjp_kernel<true, true>), dim3(A), dim3(256), lds, st, sc, sen, s, A, g, g_ld, rec, g_s, ob);
+      hipLaunchKernelGGL((render_vjp_kernel<true, true>), grid, blk, lds, st, sc, sen, s, A, g, g_ld, rec, g_s, ob, i0);
     else
-      hipLaunchKernelGGL((render_vjp_kernel<true, false>), dim3(A), dim3(256), lds, st, sc, sen, s, A, g, g_ld, rec, g_s, ob);
+      hipLaunchKernelGGL((render_vjp_kernel<true, false>), grid, blk, lds, st, sc, sen, s, A, g, g_ld, rec, g_s, ob, i0);
   } else {
     if (obs)
-      hipLaunchKernelGGL((render_vjp_kernel<false, true>), dim3(A), dim3(256), lds, st, sc, sen, s, A, g, g_ld, rec, g_s, ob);
+      hipLaunchKernelGGL((render_vjp_kernel<false, true>), grid, blk, lds, st, sc, sen, s, A, g, g_ld, rec, g_s, ob, i0);
     else
-      hipLaunchKernelGGL((render_vjp_kernel<false, false>), dim3(A), dim3(256), lds, st, sc, sen, s, A, g, g_ld, rec, g_s, ob);
+      hipLaunchKernelGGL((render_vjp_kernel<false, false>), grid, blk, lds, st, sc, sen, s, A, g, g_ld, rec, g_s, ob, i0);
   }
   DA_LAUNCH_CHECK("render_vjp_kernel");
   return SIM_OK;

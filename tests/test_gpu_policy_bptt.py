@@ -106,6 +106,29 @@ def test_bptt_checkpoint_period_is_bitwise_invariant(mode):
         assert torch.equal(s, outs[0][2])
 
 
+@pytest.mark.parametrize("mode", [FP32, X3])
+def test_bptt_half_batch_sweep_is_bitwise_invariant(mode):
+    """1000 agents: with stored activations the forward and the backward sweep
+    run as two halves of the batch (512 + 488 lanes) on two streams; the
+    gradients equal those of the single-stream recompute run bit for bit."""
+    A, T = 1000, 6
+    wk = wl.bptt(seed=17, n_envs=A, T=T, model=wl.RB13)
+    print_case("bptt_halves", A=A, T=T, gemm=mode)
+    theta = _theta(18)
+    th, s0, goal = cuda(theta), cuda(wk.state0), cuda(wk.goal)
+    outs = []
+    for K, store in ((3, True), (2, True), (3, False)):
+        e, eng = _engine(wk, T, K, store, mode)
+        loss = eng.forward(th, s0, goal)
+        g_th, g_s0 = eng.backward()
+        outs.append((loss.clone(), g_th.clone(), g_s0.clone()))
+        del eng
+    for l, g, s in outs[1:]:
+        assert torch.equal(l, outs[0][0])
+        assert torch.equal(g, outs[0][1])
+        assert torch.equal(s, outs[0][2])
+
+
 def test_autograd_function_and_loss_scaling():
     from paper_2509_10247_amd import bptt
     wk = wl.bptt(seed=15, n_envs=32, T=4, model=wl.PM9)
