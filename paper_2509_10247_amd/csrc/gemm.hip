@@ -734,55 +734,81 @@ int launch_colsum(int M, int N, const float* X, int ld, float* out, bool accumul
   return SIM_OK;
 }
 
-// Narrow output layer: Y[b][o] = tanh(sum_j H[b][j] W[o][j] + bias[o]), O <= 8.
-__global__ void narrow_fwd_kernel(int B, int J, int O, const float* __restrict__ H, int ldh,
-                                  const float* __restrict__ W, const float* __restrict__ bias,
-                                  float* __restrict__ Y) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= B * O) return;
-  const int b = idx / O, o = idx % O;
-  const float4* h = reinterpret_cast<const float4*>(H + (size_t)b * ldh);
-  const float4* w = reinterpret_cast<const float4*>(W + (size_t)o * J);
-  float acc = 0.f;
-  for (int j = 0; j < J / 4; ++j) {
-    const float4 x = h[j], y = w[j];
-    acc += x.x * y.x + x.y * y.y + x.z * y.z + x.w * y.w;
+// Narrow output layer: Y[b][o] = tanh(sum_j H[b][j] W[o][j] + bias[o]), O <= 8,
+// J % 4 == 0. A wavefront takes a few rows in turn; for each, lane l
+// multiplies H[b][4l .. 4l + 3] (and every 256 columns further) with the same
+// columns of W, so one load instruction reads a whole 1 KB row, and the O
+// partial sums are reduced across the wavefront.
+constexpr int kNarrowRows = 4;  // rows per wavefront
+__global__ __launch_bounds__(256) void narrow_fwd_kernel(int B, int J, int O, const float* __restrict__ H,
+                                                         int ldh, const float* __restrict__ W,
+                                                         const float* __restrict__ bias, float* __restrict__ Y) {
+  const int lane = threadIdx.x & 63;
+  const int b0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * kNarrowRows;
+  for (int r = 0; r < kNarrowRows; ++r) {
+    const int b = b0 + r;
+    if (b >= B) break;
+    float acc[8];
+#pragma unroll
+    for (int o = 0; o < 8; ++o) acc[o] = 0.f;
+    for (int j = 4 * lane; j < J; j += 256) {
+      const float4 x = *reinterpret_cast<const float4*>(H + (size_t)b * ldh + j);
+#pragma unroll
+      for (int o = 0; o < 8; ++o)
+        if (o < O) {
+          const float4 y = *reinterpret_cast<const float4*>(W + (size_t)o * J + j);
+          acc[o] += x.x * y.x + x.y * y.y + x.z * y.z + x.w * y.w;
+        }
+    }
+    float mine = 0.f;
+#pragma unroll
+    for (int o = 0; o < 8; ++o)
+      if (o < O) {
+        float v = acc[o];
+#pragma unroll
+        for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+        if (lane == o) mine = v;
+      }
+    if (lane < O) Y[(size_t)b * O + lane] = tanhf(mine + bias[lane]);
   }
-  Y[idx] = tanhf(acc + bias[o]);
 }
 
 int launch_narrow_fwd(int B, int J, int O, const float* H, int ldh, const float* W,
                       const float* bias, float* Y, hipStream_t st) {
-  hipLaunchKernelGGL(narrow_fwd_kernel, dim3(cdiv(B * O, 256)), dim3(256), 0, st, B, J, O, H, ldh,
-                     W, bias, Y);
+  if (O > 8 || (J & 3) || (ldh & 3)) return fail(SIM_EINVAL, "narrow_fwd: O <= 8, J and ldh multiples of 4");
+  if (B == 0) return SIM_OK;
+  hipLaunchKernelGGL(narrow_fwd_kernel, dim3(cdiv(B, 4 * kNarrowRows)), dim3(256), 0, st, B, J, O, H, ldh, W,
+                     bias, Y);
   DA_LAUNCH_CHECK("narrow_fwd_kernel");
   return SIM_OK;
 }
 
 // Backward of the narrow layer into the previous tanh layer:
 // gZ3 = gY (1 - Y^2); gZ2[b][j] = (sum_o gZ3[b][o] W[o][j]) (1 - H[b][j]^2).
-__global__ void narrow_bwd_kernel(int B, int J, int O, const float* __restrict__ gY,
-                                  const float* __restrict__ Y, const float* __restrict__ W,
-                                  const float* __restrict__ H, int ldh, float* __restrict__ gZ3,
-                                  float* __restrict__ gZ2) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= B * J) return;
-  const int b = idx / J, j = idx % J;
+// 256 columns of one row per workgroup (nb workgroups per row).
+__global__ __launch_bounds__(256) void narrow_bwd_kernel(int J, int O, int nb, const float* __restrict__ gY,
+                                                         const float* __restrict__ Y, const float* __restrict__ W,
+                                                         const float* __restrict__ H, int ldh,
+                                                         float* __restrict__ gZ3, float* __restrict__ gZ2) {
+  const int b = blockIdx.x / nb, j = (blockIdx.x % nb) * 256 + threadIdx.x;
   float acc = 0.f;
   for (int o = 0; o < O; ++o) {
     const float y = Y[b * O + o];
     const float gz = gY[b * O + o] * (1.f - y * y);
-    acc += gz * W[o * J + j];
+    if (j < J) acc += gz * W[o * J + j];
     if (j == 0) gZ3[b * O + o] = gz;
   }
+  if (j >= J) return;
   const float h = H[(size_t)b * ldh + j];
   gZ2[(size_t)b * ldh + j] = acc * (1.f - h * h);
 }
 
 int launch_narrow_bwd(int B, int J, int O, const float* gY, const float* Y, const float* W,
                       const float* H, int ldh, float* gZ3, float* gZ2, hipStream_t st) {
-  hipLaunchKernelGGL(narrow_bwd_kernel, dim3(cdiv(B * J, 256)), dim3(256), 0, st, B, J, O, gY, Y, W,
-                     H, ldh, gZ3, gZ2);
+  if (B == 0 || J == 0) return SIM_OK;
+  const int nb = cdiv(J, 256);
+  hipLaunchKernelGGL(narrow_bwd_kernel, dim3((unsigned)((int64_t)B * nb)), dim3(256), 0, st, J, O, nb, gY, Y, W, H,
+                     ldh, gZ3, gZ2);
   DA_LAUNCH_CHECK("narrow_bwd_kernel");
   return SIM_OK;
 }
