@@ -53,8 +53,8 @@ def parse():
                    help="also run a plain device copy of MIB MiB (for HBM counter scaling)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-kernel-timing", action="store_true")
-    p.add_argument("--sections", default="step,render,surrogate,uneven",
-                   help="comma list of extra sections after the headline: step, render, surrogate, uneven")
+    p.add_argument("--sections", default="step,render,imu,surrogate,uneven",
+                   help="comma list of extra sections after the headline: step, render, imu, surrogate, uneven")
     return p.parse_args()
 
 
@@ -97,6 +97,41 @@ def step_section(seed=0, reps=20):
         del e, s, nxt, a
         torch.cuda.empty_cache()
     return out
+
+
+def imu_section(seed=0, reps=20):
+    """IMU reading with drift and noise (RB13) alone at 2^22 agents: 13 state,
+    4 action, 8 parameter and 6 bias floats read, 6 bias and 6 reading floats
+    written per agent; twelve normals from Philox4x64-10 per agent."""
+    import numpy as np
+    import torch
+    import workloads as wl
+    from paper_2509_10247_amd import env
+    n, nbytes = 1 << 22, (13 + 4 + 8 + 6 + 6 + 6) * 4
+    rng = np.random.default_rng(seed)
+    p0 = wl.start_positions(rng, n, wl.ROOM_C2)
+    e = env.Env(n_envs=n, n_agents=n, model=wl.RB13, integrator=wl.RK4, dt=0.01)
+    e.set_params(wl.params(rng, wl.RB13, n))
+    s = torch.tensor(wl.initial_state(rng, wl.RB13, p0), device="cuda")
+    a = torch.tensor(wl.actions(rng, wl.RB13, n, 1)[0], device="cuda")
+    bias = torch.zeros(6, n, device="cuda")
+    sig = dict(sigma_acc=0.05, sigma_gyro=0.01, sigma_bacc=0.02, sigma_bgyro=0.004)
+    for t in range(3):
+        e.imu(s, a, bias, t=t, seed=1, **sig)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for t in range(reps):
+        out = e.imu(s, a, bias, t=3 + t, seed=1, **sig)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    assert torch.isfinite(out).all()
+    gbs = n * nbytes / (ms * 1e-3) / 1e9
+    return {"agents": n, "bytes_per_reading": nbytes, "avg_launch_ms": round(ms, 4),
+            "readings_per_s": round(n / (ms * 1e-3), 1),
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                         "frac": round(gbs * 1e9 / PEAK_HBM, 4)}}
 
 
 def render_section(seed=0, reps=10):
@@ -540,6 +575,8 @@ def main():
         line["step"] = step_section()
     if "render" in sections:
         line["render"] = render_section()
+    if "imu" in sections:
+        line["imu"] = imu_section()
     if "surrogate" in sections:
         line["surrogate"] = surrogate_section()
     if "uneven" in sections:

@@ -148,6 +148,44 @@ int sim_render_work(sim_handle* h, int32_t sensor, const float* s, float* out, i
  * Either output nullable. */
 int sim_collide(sim_handle* h, const float* s, uint8_t* flags, float* min_dist, void* stream);
 
+/* IMU with configurable noise and drift (Sec. III-B; the paper gives no
+ * noise model, so this one is a reading): for the rigid-body models
+ * (SIM_RB13, SIM_NOMINAL13) the accelerometer reads the body-frame specific
+ * force f = R^T (dv/dt - g) of the model at (s, a) over the step, i.e.
+ * (T/m) e_z - diag(D) R^T v for SIM_RB13 and (T/m) e_z for SIM_NOMINAL13,
+ * and the gyroscope reads the body rate w (state components 10..12).
+ * Drift is a bias random walk, noise is white:
+ *   b+   = b + sigma_b sqrt(dt) xi_b          (per component, 3 + 3)
+ *   out  = (f, w) + b+ + (sigma_acc, sigma_gyro) xi_w
+ * with xi standard normals from Philox4x64-10 (Salmon et al. 2011) keyed by
+ * (seed, 0), counter (t, agent, block, 0), blocks 0..2, each 64-bit output
+ * turned into u = ((x >> 11) + 1) 2^-53 and consecutive pairs into two
+ * normals by Box-Muller (r = sqrt(-2 ln u1), angle 2 pi u2, cos then sin):
+ * normals 0..2 accelerometer bias, 3..5 gyro bias, 6..8 accelerometer
+ * noise, 9..11 gyro noise. Same (seed, t) gives the same draw. */
+typedef struct {
+  float sigma_acc;    /* accelerometer white noise [m/s^2] */
+  float sigma_gyro;   /* gyroscope white noise [rad/s] */
+  float sigma_bacc;   /* accelerometer bias random walk [m/s^2 / sqrt(s)] */
+  float sigma_bgyro;  /* gyroscope bias random walk [rad/s / sqrt(s)] */
+} imu_config;
+
+/* One IMU reading per agent at (s, a) (as sim_step's inputs): out [6][A]
+ * (f_x, f_y, f_z, w_x, w_y, w_z) SoA; bias [6][A] SoA in/out (the caller
+ * zeroes it at the start of a rollout; updated in place before the reading);
+ * t is the step index. Errors: SIM_EINVAL for point-mass models (their
+ * attitude rule is not built), null arguments, negative sigmas, missing
+ * parameters. */
+int sim_imu(sim_handle* h, const float* s, const float* a, float* bias, const imu_config* cfg, uint64_t seed,
+            int64_t t, float* out, void* stream);
+
+/* Vector-Jacobian product of the noise-free IMU reading (the bias and noise
+ * are additive and carry no gradient): g_s = (d out/d s)^T g_out,
+ * g_a = (d out/d a)^T g_out; g_out [6][A]; g_s [C][A] and g_a [K][A]
+ * (nullable) are accumulated into (+=). */
+int sim_imu_backward(sim_handle* h, const float* s, const float* a, const float* g_out, float* g_s, float* g_a,
+                     void* stream);
+
 /* Vector-Jacobian product of one step and the sensors at s_t (Sec. III-A,
  * Eq. (5) factors):
  *   g_s_t = (d s_{t+1}/d s_t)^T g_s_next + (d depth_t/d s_t)^T g_depth

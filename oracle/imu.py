@@ -1,0 +1,95 @@
+"""FP64 oracle of the IMU reading with noise and drift (test infrastructure;
+see the package header: only the tests, the smoke check and the CPU baseline
+may import it).
+
+Sec. III-B gives the IMU "configurable noise and drift parameters" and no
+model; the reading implemented here (and by the kernels) is:
+
+  * accelerometer: the body-frame specific force over the step,
+    f = R^T (dv/dt - g), with dv/dt the model's right-hand side at (s, a)
+    (rigid-body models only: they carry the attitude R);
+  * gyroscope: the body rate w (state components 10..12);
+  * drift: bias random walk b+ = b + sigma_b sqrt(dt) xi_b, per component;
+  * noise: out = (f, w) + b+ + sigma xi_w.
+
+The standard normals xi come from the counter-based generator Philox4x64-10
+(Salmon, Moraes, Dror and Shaw, SC 2011), written out below from its
+definition with Python integers: key (seed, 0), counter (t, agent, block, 0)
+for blocks 0..2. Each 64-bit output x gives u = ((x >> 11) + 1) 2^-53 in
+(0, 1]; consecutive outputs (u1, u2) give the Box-Muller pair
+(r cos(2 pi u2), r sin(2 pi u2)), r = sqrt(-2 ln u1). Normals 0..2 drive the
+accelerometer bias, 3..5 the gyro bias, 6..8 the accelerometer noise and
+9..11 the gyro noise.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import torch
+
+from . import dynamics as dyn
+
+MASK64 = (1 << 64) - 1
+# Philox4x64 round multipliers and Weyl key increments (Salmon et al. 2011)
+PHILOX_M = (0xD2E7470EE14C6C93, 0xCA5A826395121157)
+PHILOX_W = (0x9E3779B97F4A7C15, 0xBB67AE8584CAA73B)
+
+
+def philox4x64(counter, key, rounds: int = 10):
+    """Philox4x64-R block of one 256-bit counter (4 words) under a 128-bit key
+    (2 words), Python integers. Each round multiplies words 0 and 2 by the
+    round constants (128-bit products), swaps the halves into the next
+    counter and xors the high halves with the other words and the key; the
+    key is bumped by the Weyl constants before every round but the first."""
+    c = [int(x) & MASK64 for x in counter]
+    k = [int(x) & MASK64 for x in key]
+    for r in range(rounds):
+        if r > 0:
+            k = [(k[0] + PHILOX_W[0]) & MASK64, (k[1] + PHILOX_W[1]) & MASK64]
+        p0 = PHILOX_M[0] * c[0]
+        p1 = PHILOX_M[1] * c[2]
+        c = [(p1 >> 64) ^ c[1] ^ k[0], p1 & MASK64, (p0 >> 64) ^ c[3] ^ k[1], p0 & MASK64]
+    return c
+
+
+def unit53(x: int) -> float:
+    """(0, 1] from the top 53 bits of a 64-bit word."""
+    return ((x >> 11) + 1) * 2.0 ** -53
+
+
+def normals(seed: int, t: int, n_agents: int) -> np.ndarray:
+    """The twelve standard normals of every agent at step t, [A, 12] float64."""
+    out = np.empty((n_agents, 12))
+    for i in range(n_agents):
+        for blk in range(3):
+            w = philox4x64((t, i, blk, 0), (seed, 0))
+            for p in range(2):
+                r = math.sqrt(-2.0 * math.log(unit53(w[2 * p])))
+                a = 2.0 * math.pi * unit53(w[2 * p + 1])
+                out[i, 4 * blk + 2 * p] = r * math.cos(a)
+                out[i, 4 * blk + 2 * p + 1] = r * math.sin(a)
+    return out
+
+
+def reading(model: int, s: torch.Tensor, u: torch.Tensor, prm: torch.Tensor) -> torch.Tensor:
+    """Noise-free reading [A, 6] = (R^T (dv/dt - g), w) at s [A, 13],
+    u [A, 4], prm [A, P] (differentiable with autograd)."""
+    if model not in (dyn.RB13, dyn.NOMINAL13):
+        raise ValueError("the IMU needs a rigid-body model")
+    ds = dyn.RHS[model](s, u, prm)
+    acc = ds[:, 3:6] - dyn.gravity(s)
+    R = dyn.quat_to_rot(s[:, 6:10])
+    f = (R.transpose(1, 2) @ acc.unsqueeze(-1)).squeeze(-1)
+    return torch.cat([f, s[:, 10:13]], 1)
+
+
+def imu_step(model, s, u, prm, bias, sigmas, seed: int, t: int, dt: float):
+    """One reading with drift and noise. bias [A, 6]; sigmas = (acc, gyro,
+    bacc, bgyro). Returns (out [A, 6], new bias [A, 6])."""
+    s_acc, s_gyro, s_bacc, s_bgyro = sigmas
+    xi = torch.tensor(normals(seed, t, s.shape[0]), dtype=s.dtype)
+    sb = torch.tensor([s_bacc] * 3 + [s_bgyro] * 3, dtype=s.dtype) * math.sqrt(dt)
+    sw = torch.tensor([s_acc] * 3 + [s_gyro] * 3, dtype=s.dtype)
+    b = bias + sb * xi[:, :6]
+    return reading(model, s, u, prm) + b + sw * xi[:, 6:], b

@@ -34,6 +34,11 @@ class SimConfig(ctypes.Structure):
                 ("fov_cull", c_int)]
 
 
+class ImuConfig(ctypes.Structure):
+    _fields_ = [("sigma_acc", c_float), ("sigma_gyro", c_float), ("sigma_bacc", c_float),
+                ("sigma_bgyro", c_float)]
+
+
 class BpttConfig(ctypes.Structure):
     _fields_ = [("T", c_int), ("K", c_int), ("w_p", c_float), ("w_v", c_float), ("w_u", c_float),
                 ("w_o", c_float), ("beta", c_float), ("d_safe", c_float),
@@ -53,6 +58,9 @@ _SIGS = {
     "sim_render_work": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p]),
     "sim_collide": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "sim_step_backward": (c_int, [c_void_p] + [c_void_p] * 9 + [c_void_p]),
+    "sim_imu": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, ctypes.POINTER(ImuConfig), ctypes.c_uint64,
+                        c_int64, c_void_p, c_void_p]),
+    "sim_imu_backward": (c_int, [c_void_p] * 7),
     "bptt_create": (c_int, [c_void_p, ctypes.POINTER(BpttConfig), ctypes.POINTER(c_void_p)]),
     "bptt_destroy": (c_int, [c_void_p]),
     "bptt_workspace_bytes": (c_int64, [c_void_p]),
@@ -195,6 +203,18 @@ def sim_render_work(h, sensor, s, out, work):
 def sim_collide(h, s, flags=None, min_dist=None):
     _call("sim_collide", h, ptr(s, torch.float32), ptr(flags, torch.uint8),
           ptr(min_dist, torch.float32), stream())
+
+
+def sim_imu(h, s, a, bias, cfg, seed, t, out):
+    """cfg: ImuConfig; bias [6][A] updated in place; out [6][A]."""
+    _call("sim_imu", h, ptr(s, torch.float32), ptr(a, torch.float32), ptr(bias, torch.float32),
+          ctypes.byref(cfg), int(seed) & ((1 << 64) - 1), int(t), ptr(out, torch.float32), stream())
+
+
+def sim_imu_backward(h, s, a, g_out, g_s, g_a=None):
+    """Accumulates into g_s [C][A] and g_a [K][A] (nullable)."""
+    _call("sim_imu_backward", h, ptr(s, torch.float32), ptr(a, torch.float32), ptr(g_out, torch.float32),
+          ptr(g_s, torch.float32), ptr(g_a, torch.float32), stream())
 
 
 def sim_step_backward(h, s_t, a_t, g_s_next, g_depth, g_lidar, hit_cam, hit_lidar, g_s_t, g_a_t):

@@ -1,0 +1,191 @@
+// IMU reading with noise and drift (Sec. III-B) and its vector-Jacobian
+// product. The accelerometer reads the body-frame specific force of the
+// rigid-body model over the step, the gyroscope the body rate; a bias random
+// walk (drift) and white noise are added. Random numbers: Philox4x64-10
+// (Salmon, Moraes, Dror and Shaw, "Parallel random numbers: as easy as 1, 2,
+// 3", SC 2011), one counter per (step, agent, block), Box-Muller in FP32.
+#include "dyn_device.h"
+#include "sim_internal.h"
+
+namespace da {
+
+// Philox4x64 with 10 rounds: the multiply-xor round on counter c with the
+// key bumped by the Weyl constants between rounds.
+__device__ __forceinline__ void philox4x64_10(uint64_t (&c)[4], uint64_t k0, uint64_t k1) {
+  constexpr uint64_t kM0 = 0xD2E7470EE14C6C93ull, kM1 = 0xCA5A826395121157ull;
+  constexpr uint64_t kW0 = 0x9E3779B97F4A7C15ull, kW1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += kW0;
+      k1 += kW1;
+    }
+    const uint64_t hi0 = __umul64hi(kM0, c[0]), lo0 = kM0 * c[0];
+    const uint64_t hi1 = __umul64hi(kM1, c[2]), lo1 = kM1 * c[2];
+    const uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+  }
+}
+
+// ln u for u = ((x >> 11) + 1) 2^-53 in (0, 1], to FP32 accuracy: for
+// u <= 1/2 the logarithm of u itself; above, log1p(-v) with v = 1 - u formed
+// exactly in integers (u rounded to FP32 would lose v near 1).
+__device__ __forceinline__ float log_unit53(uint64_t x) {
+  const uint64_t k = (x >> 11) + 1;  // 1 .. 2^53
+  const float lo = logf((float)k * 0x1.0p-53f);
+  const float hi = log1pf(-(float)((1ull << 53) - k) * 0x1.0p-53f);
+  return k <= (1ull << 52) ? lo : hi;
+}
+
+// the twelve standard normals of agent i at step t (Box-Muller; the angle
+// as sincospi(2 u), without range reduction)
+__device__ __forceinline__ void imu_normals(uint64_t seed, int64_t t, int i, float (&n)[12]) {
+#pragma unroll
+  for (int blk = 0; blk < 3; ++blk) {
+    uint64_t c[4] = {(uint64_t)t, (uint64_t)i, (uint64_t)blk, 0ull};
+    philox4x64_10(c, seed, 0ull);
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      const float r = sqrtf(-2.0f * log_unit53(c[2 * p]));
+      float sa, ca;
+      sincospif(2.0f * ((float)((c[2 * p + 1] >> 11) + 1) * 0x1.0p-53f), &sa, &ca);
+      n[4 * blk + 2 * p] = r * ca;
+      n[4 * blk + 2 * p + 1] = r * sa;
+    }
+  }
+}
+
+// noise-free reading (f, w) of agent i
+template <int M>
+__device__ __forceinline__ void imu_true(const float* s, const float* u, const float* prm, float (&o)[6]) {
+  const float Tm = u[0] / prm[0];
+  o[0] = 0.f;
+  o[1] = 0.f;
+  o[2] = Tm;
+  if (M == SIM_RB13) {
+    float qn[4];
+    quat_normalize(s + 6, qn, nullptr);
+    const Rot R = rot_of_unit(qn);
+    const f3 vb = rot_apply_t(R, mk3(s[3], s[4], s[5]));
+    o[0] -= prm[4] * vb.x;
+    o[1] -= prm[5] * vb.y;
+    o[2] -= prm[6] * vb.z;
+  }
+  o[3] = s[10];
+  o[4] = s[11];
+  o[5] = s[12];
+}
+
+struct ImuSig {
+  float acc, gyro, bacc, bgyro;
+};
+
+template <int M>
+__global__ void imu_kernel(int A, float dt, const float* __restrict__ s_in, const float* __restrict__ a,
+                           const float* __restrict__ prm, float* __restrict__ bias, ImuSig sg, uint64_t seed,
+                           int64_t t, float* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A) return;
+  float s[13], u[4], p[8], o[6], n[12];
+  for (int c = 0; c < 13; ++c) s[c] = s_in[(size_t)c * A + i];
+  for (int k = 0; k < 4; ++k) u[k] = a[(size_t)k * A + i];
+  for (int k = 0; k < 8; ++k) p[k] = prm[(size_t)k * A + i];
+  imu_true<M>(s, u, p, o);
+  imu_normals(seed, t, i, n);
+  const float sq = sqrtf(dt);
+  for (int c = 0; c < 6; ++c) {
+    const float sb = (c < 3 ? sg.bacc : sg.bgyro) * sq, sw = c < 3 ? sg.acc : sg.gyro;
+    const float b = bias[(size_t)c * A + i] + sb * n[c];
+    bias[(size_t)c * A + i] = b;
+    out[(size_t)c * A + i] = o[c] + b + sw * n[6 + c];
+  }
+}
+
+// g_s += (d(f, w)/ds)^T g, g_a += (d(f, w)/da)^T g
+template <int M>
+__global__ void imu_vjp_kernel(int A, const float* __restrict__ s_in, const float* __restrict__ a,
+                               const float* __restrict__ prm, const float* __restrict__ g_out,
+                               float* __restrict__ g_s, float* __restrict__ g_a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A) return;
+  float g[6];
+  for (int c = 0; c < 6; ++c) g[c] = g_out[(size_t)c * A + i];
+  const float m = prm[i];
+  if (g_a) g_a[i] += g[2] / m;
+  if (M == SIM_RB13) {
+    const float q[4] = {s_in[6 * (size_t)A + i], s_in[7 * (size_t)A + i], s_in[8 * (size_t)A + i],
+                        s_in[9 * (size_t)A + i]};
+    const f3 v = mk3(s_in[3 * (size_t)A + i], s_in[4 * (size_t)A + i], s_in[5 * (size_t)A + i]);
+    float qn[4], inv;
+    quat_normalize(q, qn, &inv);
+    const Rot R = rot_of_unit(qn);
+    // f_drag = -D R^T v: d/dv = -R D g, d/dR[r][c] = -v_r D_c g_c
+    const float Dg[3] = {prm[4 * (size_t)A + i] * g[0], prm[5 * (size_t)A + i] * g[1], prm[6 * (size_t)A + i] * g[2]};
+    const f3 gv = rot_apply(R, mk3(Dg[0], Dg[1], Dg[2]));
+    g_s[3 * (size_t)A + i] -= gv.x;
+    g_s[4 * (size_t)A + i] -= gv.y;
+    g_s[5 * (size_t)A + i] -= gv.z;
+    const float vv[3] = {v.x, v.y, v.z};
+    float G[3][3];
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) G[r][c] = -vv[r] * Dg[c];
+    float gqn[4], gq[4];
+    rot_vjp(G, qn, gqn);
+    normalize_vjp(qn, inv, gqn, gq);
+    for (int k = 0; k < 4; ++k) g_s[(size_t)(6 + k) * A + i] += gq[k];
+  }
+  for (int k = 0; k < 3; ++k) g_s[(size_t)(10 + k) * A + i] += g[3 + k];
+}
+
+}  // namespace da
+
+using namespace da;
+
+extern "C" {
+
+int sim_imu(sim_handle* h, const float* s, const float* a, float* bias, const imu_config* cfg, uint64_t seed,
+            int64_t t, float* out, void* stream) {
+  DA_REQUIRE(h && s && a && bias && cfg && out, "sim_imu: null argument");
+  DA_REQUIRE(h->cfg.model == SIM_RB13 || h->cfg.model == SIM_NOMINAL13,
+             "sim_imu: the IMU needs a rigid-body model (SIM_RB13 or SIM_NOMINAL13)");
+  DA_REQUIRE(h->params, "sim_imu: parameters not set");
+  DA_REQUIRE(cfg->sigma_acc >= 0.f && cfg->sigma_gyro >= 0.f && cfg->sigma_bacc >= 0.f && cfg->sigma_bgyro >= 0.f,
+             "sim_imu: sigmas must be >= 0");
+  DA_REQUIRE(t >= 0, "sim_imu: t must be >= 0");
+  const int A = h->cfg.n_agents;
+  if (A == 0) return SIM_OK;
+  const ImuSig sg{cfg->sigma_acc, cfg->sigma_gyro, cfg->sigma_bacc, cfg->sigma_bgyro};
+  hipStream_t st = as_stream(stream);
+  if (h->cfg.model == SIM_RB13)
+    hipLaunchKernelGGL(imu_kernel<SIM_RB13>, dim3(cdiv(A, 256)), dim3(256), 0, st, A, h->cfg.dt, s, a, h->params,
+                       bias, sg, seed, t, out);
+  else
+    hipLaunchKernelGGL(imu_kernel<SIM_NOMINAL13>, dim3(cdiv(A, 256)), dim3(256), 0, st, A, h->cfg.dt, s, a,
+                       h->params, bias, sg, seed, t, out);
+  DA_LAUNCH_CHECK("imu_kernel");
+  return SIM_OK;
+}
+
+int sim_imu_backward(sim_handle* h, const float* s, const float* a, const float* g_out, float* g_s, float* g_a,
+                     void* stream) {
+  DA_REQUIRE(h && s && a && g_out && g_s, "sim_imu_backward: null argument");
+  DA_REQUIRE(h->cfg.model == SIM_RB13 || h->cfg.model == SIM_NOMINAL13,
+             "sim_imu_backward: the IMU needs a rigid-body model (SIM_RB13 or SIM_NOMINAL13)");
+  DA_REQUIRE(h->params, "sim_imu_backward: parameters not set");
+  const int A = h->cfg.n_agents;
+  if (A == 0) return SIM_OK;
+  hipStream_t st = as_stream(stream);
+  if (h->cfg.model == SIM_RB13)
+    hipLaunchKernelGGL(imu_vjp_kernel<SIM_RB13>, dim3(cdiv(A, 256)), dim3(256), 0, st, A, s, a, h->params, g_out,
+                       g_s, g_a);
+  else
+    hipLaunchKernelGGL(imu_vjp_kernel<SIM_NOMINAL13>, dim3(cdiv(A, 256)), dim3(256), 0, st, A, s, a, h->params,
+                       g_out, g_s, g_a);
+  DA_LAUNCH_CHECK("imu_vjp_kernel");
+  return SIM_OK;
+}
+
+}  // extern "C"

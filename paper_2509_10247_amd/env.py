@@ -99,6 +99,21 @@ class Env:
         _lib.sim_collide(self.h, s, flags, md)
         return flags, md
 
+    def imu(self, s, a, bias, t, seed=0, sigma_acc=0.0, sigma_gyro=0.0, sigma_bacc=0.0, sigma_bgyro=0.0):
+        """IMU reading [6, A] (specific force, body rate) with drift and noise;
+        bias [6, A] is updated in place."""
+        cfg = _lib.ImuConfig(sigma_acc, sigma_gyro, sigma_bacc, sigma_bgyro)
+        out = torch.empty(6, self.n_agents, device="cuda")
+        _lib.sim_imu(self.h, s, a, bias, cfg, seed, t, out)
+        return out
+
+    def imu_backward(self, s, a, g_out):
+        """(d reading/d s)^T g_out and (d reading/d a)^T g_out of the noise-free reading."""
+        g_s = torch.zeros_like(s)
+        g_a = torch.zeros_like(a)
+        _lib.sim_imu_backward(self.h, s, a, g_out, g_s, g_a)
+        return g_s, g_a
+
     def step_backward(self, s, a, g_next, g_depth=None, g_lidar=None, hit_cam=None, hit_lidar=None,
                       want_ga=True):
         g_s = torch.empty_like(s)

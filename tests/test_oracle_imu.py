@@ -1,0 +1,133 @@
+"""Pins of the IMU oracle: the generator against numpy's Philox4x64-10,
+the normals' statistics, closed-form readings, the drift and noise variances
+and the reading's gradient against finite differences."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import dynamics as dyn
+from oracle import imu
+
+D = torch.float64
+
+
+def _numpy_block(counter, key):
+    """numpy's Philox advances its 256-bit counter before each block, so the
+    block of counter c is the first one drawn after setting c - 1."""
+    c = sum(int(w) << (64 * j) for j, w in enumerate(counter)) - 1
+    c %= 1 << 256
+    words = np.array([(c >> (64 * j)) & imu.MASK64 for j in range(4)], dtype=np.uint64)
+    bg = np.random.Philox(key=np.array(key, dtype=np.uint64), counter=words)
+    return [int(x) for x in bg.random_raw(4)]
+
+
+@pytest.mark.parametrize("counter,key", [((1, 0, 0, 0), (5, 7)), ((17, 3, 2, 0), (12345, 0)),
+                                         ((0, 5, 2, 0), (2 ** 64 - 1, 0)), ((0, 0, 0, 0), (0, 0)),
+                                         ((2 ** 64 - 1, 2 ** 63, 1, 9), (31337, 271828))])
+def test_philox_matches_numpy(counter, key):
+    assert imu.philox4x64(counter, key) == _numpy_block(counter, key)
+
+
+def test_normals_are_standard():
+    z = np.concatenate([imu.normals(seed, t, 2000).ravel() for seed, t in ((1, 0), (1, 7), (99, 3))])
+    n = z.size
+    assert abs(z.mean()) < 5.0 / math.sqrt(n)
+    assert abs(z.var() - 1.0) < 5.0 * math.sqrt(2.0 / n)
+    # Box-Muller pair members are uncorrelated; fourth moment of a normal is 3
+    pairs = z.reshape(-1, 2)
+    assert abs(np.mean(pairs[:, 0] * pairs[:, 1])) < 5.0 / math.sqrt(len(pairs))
+    assert abs(np.mean(z ** 4) - 3.0) < 0.1
+
+
+def test_draws_depend_only_on_seed_and_step():
+    a = imu.normals(4, 10, 8)
+    assert np.array_equal(a, imu.normals(4, 10, 8))
+    assert not np.allclose(a, imu.normals(4, 11, 8))
+    assert not np.allclose(a, imu.normals(5, 10, 8))
+    # agent i's draw does not depend on how many agents there are
+    assert np.array_equal(a[:3], imu.normals(4, 10, 3))
+
+
+def _rb_case():
+    s = torch.zeros(3, 13, dtype=D)
+    s[:, 6] = 1.0
+    u = torch.zeros(3, 4, dtype=D)
+    prm = torch.tensor([[1.5, 0.01, 0.01, 0.02, 0.3, 0.5, 0.7, 0.03]] * 3, dtype=D)
+    return s, u, prm
+
+
+def test_reading_closed_forms():
+    s, u, prm = _rb_case()
+    # hover: the accelerometer reads g along body z, whatever the attitude
+    u[:, 0] = 1.5 * dyn.G
+    s[1, 6:10] = torch.tensor([math.cos(0.4), math.sin(0.4), 0.0, 0.0], dtype=D)
+    s[2, 6:10] = torch.tensor([0.5, 0.5, 0.5, 0.5], dtype=D)
+    s[:, 10:13] = torch.tensor([0.1, -0.2, 0.3], dtype=D)
+    for model in (dyn.NOMINAL13, dyn.RB13):
+        r = imu.reading(model, s, u, prm)
+        assert torch.allclose(r[:, :3], torch.tensor([0.0, 0.0, dyn.G], dtype=D).expand(3, 3), atol=1e-12)
+        assert torch.equal(r[:, 3:], s[:, 10:13])
+    # free fall reads zero
+    u[:, 0] = 0.0
+    assert torch.allclose(imu.reading(dyn.RB13, s, u, prm)[:, :3], torch.zeros(3, 3, dtype=D), atol=1e-12)
+    # rotor drag: yaw +90 deg (body x -> world y), world velocity (1, 0, 0) is
+    # body (0, -1, 0); f = (T/m) e_z - D (0, -1, 0) = (0, D_y, T/m)
+    s, u, prm = _rb_case()
+    c = math.cos(math.pi / 4)
+    s[:, 6:10] = torch.tensor([c, 0.0, 0.0, c], dtype=D)
+    s[:, 3] = 1.0
+    u[:, 0] = 3.0
+    r = imu.reading(dyn.RB13, s, u, prm)
+    assert torch.allclose(r[:, :3], torch.tensor([0.0, 0.5, 2.0], dtype=D).expand(3, 3), atol=1e-12)
+    # the simplified model has no drag
+    r = imu.reading(dyn.NOMINAL13, s, u, prm)
+    assert torch.allclose(r[:, :3], torch.tensor([0.0, 0.0, 2.0], dtype=D).expand(3, 3), atol=1e-12)
+
+
+def test_point_mass_has_no_imu():
+    with pytest.raises(ValueError):
+        imu.reading(dyn.PM9, torch.zeros(1, 9, dtype=D), torch.zeros(1, 3, dtype=D), torch.ones(1, 2, dtype=D))
+
+
+def test_drift_and_noise_variances():
+    A, n, dt = 2000, 16, 0.01
+    sig = (0.2, 0.05, 0.3, 0.1)
+    s, u, prm = _rb_case()
+    s, u, prm = s[:1].expand(A, 13).clone(), u[:1].expand(A, 4).clone(), prm[:1].expand(A, 8).clone()
+    bias = torch.zeros(A, 6, dtype=D)
+    true = imu.reading(dyn.RB13, s, u, prm)
+    for t in range(n):
+        out, bias = imu.imu_step(dyn.RB13, s, u, prm, bias, sig, seed=3, t=t, dt=dt)
+    var_b = bias.var(0)
+    exp_b = torch.tensor([sig[2] ** 2] * 3 + [sig[3] ** 2] * 3, dtype=D) * n * dt
+    assert torch.all((var_b / exp_b - 1.0).abs() < 0.12)
+    var_w = (out - true - bias).var(0)
+    exp_w = torch.tensor([sig[0] ** 2] * 3 + [sig[1] ** 2] * 3, dtype=D)
+    assert torch.all((var_w / exp_w - 1.0).abs() < 0.12)
+
+
+@pytest.mark.parametrize("model", [dyn.RB13, dyn.NOMINAL13])
+def test_reading_gradient_matches_finite_differences(model):
+    g = torch.Generator().manual_seed(0)
+    s = torch.randn(3, 13, generator=g, dtype=D)
+    s[:, 6:10] += torch.tensor([2.0, 0.0, 0.0, 0.0], dtype=D)
+    u = torch.randn(3, 4, generator=g, dtype=D) + torch.tensor([10.0, 0, 0, 0], dtype=D)
+    prm = torch.tensor([[1.5, 0.01, 0.01, 0.02, 0.3, 0.5, 0.7, 0.03]] * 3, dtype=D)
+    w = torch.randn(3, 6, generator=g, dtype=D)
+    s.requires_grad_(True)
+    u.requires_grad_(True)
+    (imu.reading(model, s, u, prm) * w).sum().backward()
+    h = 1e-6
+    for x, gx in ((s, s.grad), (u, u.grad)):
+        fd = torch.zeros_like(x)
+        with torch.no_grad():
+            for idx in np.ndindex(*x.shape):
+                xp, xm = x.detach().clone(), x.detach().clone()
+                xp[idx] += h
+                xm[idx] -= h
+                sp, up = (xp, u.detach()) if x is s else (s.detach(), xp)
+                sm, um = (xm, u.detach()) if x is s else (s.detach(), xm)
+                fd[idx] = ((imu.reading(model, sp, up, prm) - imu.reading(model, sm, um, prm)) * w).sum() / (2 * h)
+        assert torch.allclose(gx, fd, rtol=1e-6, atol=1e-8)
