@@ -60,7 +60,8 @@ def parse():
 
 def step_section(seed=0, reps=20):
     """The dynamics step alone at sizes whose working set exceeds the 256 MB
-    last-level cache: RB13 RK4 at 2^22 envs and PM6 Euler at 2^23 envs.
+    last-level cache: RB13 RK4 at 2^22 envs, PM6 Euler and the discrete point
+    mass of Eq. (4) at 2^23 envs.
     Achieved HBM bandwidth = algorithmic bytes per launch / average launch
     time (HIP events on the launch stream)."""
     import numpy as np
@@ -69,7 +70,8 @@ def step_section(seed=0, reps=20):
     from paper_2509_10247_amd import env
     out = {}
     for name, model, integ, n, nbytes in (("rb13_rk4", wl.RB13, wl.RK4, 1 << 22, (13 + 4 + 8 + 13) * 4),
-                                          ("pm6_euler", wl.PM6, wl.EULER, 1 << 23, (6 + 3 + 6) * 4)):
+                                          ("pm6_euler", wl.PM6, wl.EULER, 1 << 23, (6 + 3 + 6) * 4),
+                                          ("pmd_eq4", wl.PMD, wl.EULER, 1 << 23, (9 + 3 + 9) * 4)):
         rng = np.random.default_rng(seed)
         p0 = wl.start_positions(rng, n, wl.ROOM_C2)
         e = env.Env(n_envs=n, n_agents=n, model=model, integrator=integ, dt=0.01)

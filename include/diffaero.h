@@ -35,6 +35,12 @@
  *  SIM_PM9      p(3) v(3) a(3)            action u(3) [m/s^2]; params lambda, d
  *  SIM_RB13     p(3) v(3) q(4) w(3)       action T [N], w_cmd(3) [rad/s]
  *  SIM_NOMINAL13  as SIM_RB13 (w follows w_cmd instantly, no drag)
+ *  SIM_PMD      p(3) v(3) u_prev(3)       action u(3) [m/s^2]: the discrete
+ *               point mass of Eq. (4), the command applied with a one-step
+ *               lag (u_prev is the acceleration applied over the step):
+ *                 p+ = p + v dt + 1/2 (u_prev + g) dt^2
+ *                 v+ = v + 1/2 (u_prev + u) dt + g dt,   u_prev+ = u
+ *               (the integrator field is ignored: Eq. (4) is the step)
  *  q = (w, x, y, z) Hamilton, body->world; w (rates) in the body frame.
  *  RB params rows: m, Jxx, Jyy, Jzz, Dxx, Dyy, Dzz, tau_w   (SoA [8][A])
  *  PM9 params rows: lambda, d                              (SoA [2][A])
@@ -60,7 +66,7 @@ extern "C" {
 #endif
 
 enum { SIM_OK = 0, SIM_EINVAL = -1, SIM_ENODEV = -2, SIM_ENOMEM = -3, SIM_EHIP = -4, SIM_ESTATE = -5 };
-enum { SIM_PM6 = 0, SIM_PM9 = 1, SIM_RB13 = 2, SIM_NOMINAL13 = 3 };
+enum { SIM_PM6 = 0, SIM_PM9 = 1, SIM_RB13 = 2, SIM_NOMINAL13 = 3, SIM_PMD = 4 };
 enum { SIM_EULER = 0, SIM_RK4 = 1 };
 /* step flags bits */
 enum { SIM_FLAG_NONFINITE = 1, SIM_FLAG_COLLISION = 2 };

@@ -16,12 +16,15 @@ State layouts (per agent, SoA in memory, [A, C] tensors here):
   PM9  (p, v, a)       action u (3, m/s^2)      Eq. (3); params (lambda, d)
   RB13 (p, v, q, w)    action (T, w_cmd)        Eq. (1); params (m, J, D, tau_w)
   NOMINAL13 (p, v, q, w)  action (T, w_cmd)     Eq. (2); w follows w_cmd instantly
+  PMD  (p, v, u_prev)  action u (3, m/s^2)      Eq. (4), discrete: the command is
+                                                applied one step later (u_prev is
+                                                the acceleration over the step)
 """
 from __future__ import annotations
 
 import torch
 
-PM6, PM9, RB13, NOMINAL13 = 0, 1, 2, 3
+PM6, PM9, RB13, NOMINAL13, PMD = 0, 1, 2, 3, 4
 EULER, RK4 = 0, 1
 G = 9.81
 
@@ -126,12 +129,27 @@ def integrate(f, s, u, prm, dt, integrator):
     return s + (dt / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
 
 
+def step_pmd(s, u, dt):
+    """Eq. (4) as a causal step: u_t is the acceleration applied over step t
+    (state components 6..8) and u_{t+1} the one commanded now, which is
+    applied over the next step. Gravity is added to the commanded
+    acceleration, as in Eq. (3):
+        p_{t+1} = p_t + v_t dt + 1/2 (u_t + g) dt^2
+        v_{t+1} = v_t + 1/2 ((u_t + g) + (u_{t+1} + g)) dt."""
+    p, v, u_t = s[:, 0:3], s[:, 3:6], s[:, 6:9]
+    g = gravity(s)
+    a_t, a_n = u_t + g, u + g
+    return torch.cat([p + v * dt + 0.5 * a_t * dt * dt, v + 0.5 * (a_t + a_n) * dt, u], 1)
+
+
 def step(model, s, u, prm, dt, integrator):
     """s_{t+1} = step(s_t, a_t). Tensors [A, C], [A, K], [A, P] float64.
 
     For the quaternion models q is renormalised after the step; the nominal
     model starts the step with w := w_cmd so that its state reports the
-    commanded rate."""
+    commanded rate. The discrete point mass (Eq. 4) is its own integrator."""
+    if model == PMD:
+        return step_pmd(s, u, dt)
     if model == NOMINAL13:
         s = torch.cat([s[:, :10], u[:, 1:4]], 1)
     out = integrate(RHS[model], s, u, prm, dt, integrator)

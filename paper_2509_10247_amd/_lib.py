@@ -15,7 +15,7 @@ import torch
 _DIR = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_DIR, "libdiffaero.so")
 
-SIM_PM6, SIM_PM9, SIM_RB13, SIM_NOMINAL13 = 0, 1, 2, 3
+SIM_PM6, SIM_PM9, SIM_RB13, SIM_NOMINAL13, SIM_PMD = 0, 1, 2, 3, 4
 SIM_EULER, SIM_RK4 = 0, 1
 POLICY_N_PARAMS = 855812
 POLICY_GEMM_FP32, POLICY_GEMM_BF16X3 = 0, 1

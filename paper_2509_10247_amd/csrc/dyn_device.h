@@ -25,6 +25,10 @@ template <>
 struct Dim<SIM_NOMINAL13> {
   static constexpr int C = 13, K = 4, P = 8;
 };
+template <>
+struct Dim<SIM_PMD> {
+  static constexpr int C = 9, K = 3, P = 0;
+};
 
 // ---------------------------------------------------------------------------
 // right-hand sides f(s, u)
@@ -227,9 +231,27 @@ __device__ __forceinline__ constexpr bool has_quat() {
   return M == SIM_RB13 || M == SIM_NOMINAL13;
 }
 
+// Discrete point mass, Eq. (4): position by the constant-acceleration
+// formula over the step, velocity by the trapezoid of the applied
+// accelerations of this and the next step; the command takes effect one step
+// later (state components 6..8 hold the acceleration applied over the step).
+// Gravity is added to the commanded acceleration, as in Eq. (3).
+__device__ __forceinline__ void step_pmd(const float* s0, const float* u, float dt, float* out) {
+  for (int k = 0; k < 3; ++k) {
+    const float gk = k == 2 ? -kG : 0.f;
+    const float a_t = s0[6 + k] + gk, a_n = u[k] + gk;
+    out[k] = s0[k] + s0[3 + k] * dt + 0.5f * a_t * dt * dt;
+    out[3 + k] = s0[3 + k] + 0.5f * (a_t + a_n) * dt;
+    out[6 + k] = u[k];
+  }
+}
+
 template <int M, int I>
 __device__ __forceinline__ void step_regs(const float* s0, const float* u, const float* prm,
                                           float dt, float* out) {
+  if constexpr (M == SIM_PMD) {
+    step_pmd(s0, u, dt, out);
+  } else {
   constexpr int C = Dim<M>::C;
   float s[C];
   for (int c = 0; c < C; ++c) s[c] = s0[c];
@@ -269,12 +291,24 @@ __device__ __forceinline__ void step_regs(const float* s0, const float* u, const
     quat_normalize(out + 6, qn, nullptr);
     for (int k = 0; k < 4; ++k) out[6 + k] = qn[k];
   }
+  }
 }
 
 template <int M, int I>
 __device__ __forceinline__ void step_vjp_regs(const float* s0, const float* u, const float* prm,
                                               float dt, const float* gout, float* gs_out,
                                               float* gu) {
+  if constexpr (M == SIM_PMD) {
+    // the step is linear: p+ = p + v dt + dt^2/2 a, v+ = v + dt/2 (a + u) + g dt, a+ = u
+    for (int k = 0; k < 3; ++k) {
+      const float gp = gout[k], gv = gout[3 + k], ga = gout[6 + k];
+      gs_out[k] = gp;
+      gs_out[3 + k] = gp * dt + gv;
+      gs_out[6 + k] = gp * (0.5f * dt * dt) + gv * (0.5f * dt);
+      gu[k] = gv * (0.5f * dt) + ga;
+    }
+    return;
+  } else {
   constexpr int C = Dim<M>::C;
   constexpr int K = Dim<M>::K;
   float s[C];
@@ -366,6 +400,7 @@ __device__ __forceinline__ void step_vjp_regs(const float* s0, const float* u, c
     gs[10] = gs[11] = gs[12] = 0.f;
   }
   for (int c = 0; c < C; ++c) gs_out[c] = gs[c];
+  }
 }
 
 }  // namespace da

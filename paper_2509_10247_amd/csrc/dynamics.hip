@@ -91,6 +91,8 @@ static int launch_step_vjp_t(int A, float dt, const float* s, const float* a, co
     case SIM_RB13 * 2 + 1: return FN<SIM_RB13, 1>(__VA_ARGS__);               \
     case SIM_NOMINAL13 * 2 + 0: return FN<SIM_NOMINAL13, 0>(__VA_ARGS__);     \
     case SIM_NOMINAL13 * 2 + 1: return FN<SIM_NOMINAL13, 1>(__VA_ARGS__);     \
+    case SIM_PMD * 2 + 0: return FN<SIM_PMD, 0>(__VA_ARGS__);                 \
+    case SIM_PMD * 2 + 1: return FN<SIM_PMD, 0>(__VA_ARGS__);                 \
     default: return fail(SIM_EINVAL, "bad model/integrator %d/%d", model, integ); \
   }
 
@@ -110,14 +112,16 @@ int launch_step_vjp(int model, int integ, int A, float dt, const float* s, const
 int state_dim(int model) {
   switch (model) {
     case SIM_PM6: return 6;
-    case SIM_PM9: return 9;
+    case SIM_PM9:
+    case SIM_PMD: return 9;
     default: return 13;
   }
 }
-int action_dim(int model) { return (model == SIM_PM6 || model == SIM_PM9) ? 3 : 4; }
+int action_dim(int model) { return (model == SIM_PM6 || model == SIM_PM9 || model == SIM_PMD) ? 3 : 4; }
 int param_dim(int model) {
   switch (model) {
-    case SIM_PM6: return 0;
+    case SIM_PM6:
+    case SIM_PMD: return 0;
     case SIM_PM9: return 2;
     default: return 8;
   }

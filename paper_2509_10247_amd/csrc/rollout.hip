@@ -153,6 +153,8 @@ static int launch_dyn_t(const RolloutArgs& g, bool, int, size_t, hipStream_t st)
     case SIM_RB13 * 2 + 1: return FN<SIM_RB13, 1>(__VA_ARGS__);               \
     case SIM_NOMINAL13 * 2 + 0: return FN<SIM_NOMINAL13, 0>(__VA_ARGS__);     \
     case SIM_NOMINAL13 * 2 + 1: return FN<SIM_NOMINAL13, 1>(__VA_ARGS__);     \
+    case SIM_PMD * 2 + 0: return FN<SIM_PMD, 0>(__VA_ARGS__);                 \
+    case SIM_PMD * 2 + 1: return FN<SIM_PMD, 0>(__VA_ARGS__);                 \
     default: return fail(SIM_EINVAL, "bad model/integrator");                 \
   }
 

@@ -195,7 +195,7 @@ int sim_create(const sim_config* cfg, sim_handle** out) {
   *out = nullptr;
   const sim_config& c = *cfg;
   DA_REQUIRE(c.n_envs >= 1 && c.n_agents >= c.n_envs, "sim_create: need n_agents >= n_envs >= 1");
-  DA_REQUIRE(c.model >= SIM_PM6 && c.model <= SIM_NOMINAL13, "sim_create: bad model %d", c.model);
+  DA_REQUIRE(c.model >= SIM_PM6 && c.model <= SIM_PMD, "sim_create: bad model %d", c.model);
   DA_REQUIRE(c.integrator == SIM_EULER || c.integrator == SIM_RK4, "sim_create: bad integrator");
   DA_REQUIRE(c.dt > 0.f && std::isfinite(c.dt), "sim_create: dt must be > 0");
   DA_REQUIRE((c.cam_w == 0) == (c.cam_h == 0) && c.cam_w >= 0 && c.cam_h >= 0 &&

@@ -11,8 +11,8 @@ import torch
 
 from . import _lib
 
-STATE_DIM = {0: 6, 1: 9, 2: 13, 3: 13}
-ACTION_DIM = {0: 3, 1: 3, 2: 4, 3: 4}
+STATE_DIM = {0: 6, 1: 9, 2: 13, 3: 13, 4: 9}
+ACTION_DIM = {0: 3, 1: 3, 2: 4, 3: 4, 4: 3}
 
 
 def _dev(x, dtype):

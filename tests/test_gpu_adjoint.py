@@ -20,7 +20,7 @@ def _env(wk, **kw):
 
 @pytest.mark.parametrize("model,integ", [(wl.PM6, wl.EULER), (wl.PM9, wl.RK4), (wl.PM9, wl.EULER),
                                          (wl.RB13, wl.RK4), (wl.RB13, wl.EULER),
-                                         (wl.NOMINAL13, wl.RK4)])
+                                         (wl.NOMINAL13, wl.RK4), (wl.PMD, wl.EULER)])
 def test_step_vjp_parity(model, integ):
     A = 700
     print_case("step_vjp", model=model, integ=integ, A=A)

@@ -23,7 +23,7 @@ def _env(wk, **kw):
 
 @pytest.mark.parametrize("model,integ", [(wl.PM6, wl.EULER), (wl.PM6, wl.RK4), (wl.PM9, wl.EULER),
                                          (wl.PM9, wl.RK4), (wl.RB13, wl.EULER), (wl.RB13, wl.RK4),
-                                         (wl.NOMINAL13, wl.RK4)])
+                                         (wl.NOMINAL13, wl.RK4), (wl.PMD, wl.EULER), (wl.PMD, wl.RK4)])
 def test_one_step_parity_ragged(model, integ):
     A = 1000  # several 256-lane blocks and a ragged tail
     print_case("one_step", model=model, integ=integ, A=A)

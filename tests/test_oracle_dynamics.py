@@ -228,11 +228,11 @@ def test_rotation_matrix_properties():
     assert torch.allclose(dyn.quat_to_rot(qy)[0, :, 2], torch.tensor([math.sin(th), 0.0, math.cos(th)], dtype=D))
 
 
-@pytest.mark.parametrize("model", [dyn.RB13, dyn.NOMINAL13, dyn.PM9, dyn.PM6])
+@pytest.mark.parametrize("model", [dyn.RB13, dyn.NOMINAL13, dyn.PM9, dyn.PM6, dyn.PMD])
 def test_step_yaw_equivariance_and_translation_invariance(model):
     rng = np.random.default_rng(7)
     A = 16
-    C = {dyn.PM6: 6, dyn.PM9: 9, dyn.RB13: 13, dyn.NOMINAL13: 13}[model]
+    C = {dyn.PM6: 6, dyn.PM9: 9, dyn.RB13: 13, dyn.NOMINAL13: 13, dyn.PMD: 9}[model]
     s = torch.tensor(rng.normal(size=(A, C)))
     if C == 13:
         s[:, 6:10] = s[:, 6:10] / s[:, 6:10].norm(dim=1, keepdim=True)
@@ -259,7 +259,7 @@ def test_step_yaw_equivariance_and_translation_invariance(model):
     ur = u.clone()
     if C == 13:
         sr[:, 6:10] = dyn.quat_mul(yaw_quat(torch.full((A,), psi)), s[:, 6:10])
-    elif model == dyn.PM9:
+    elif model in (dyn.PM9, dyn.PMD):
         sr[:, 6:9] = s[:, 6:9] @ Rz.T
         ur = u @ Rz.T
     else:
@@ -297,13 +297,13 @@ def test_nominal_reports_commanded_rate_and_thrust_parabola():
 
 @pytest.mark.parametrize("model,integ", [(dyn.PM6, dyn.EULER), (dyn.PM9, dyn.RK4),
                                          (dyn.RB13, dyn.RK4), (dyn.RB13, dyn.EULER),
-                                         (dyn.NOMINAL13, dyn.RK4)])
+                                         (dyn.NOMINAL13, dyn.RK4), (dyn.PMD, dyn.EULER)])
 def test_step_jacobian_autograd_matches_central_fd(model, integ):
     """The step VJP used by the gradient oracle (autograd) agrees with central
     differences of the step map (Eq. 5's factors dS_{t+1}/dS_t, dS_{t+1}/da_t)."""
     rng = np.random.default_rng(8)
     A = 6
-    C = {dyn.PM6: 6, dyn.PM9: 9, dyn.RB13: 13, dyn.NOMINAL13: 13}[model]
+    C = {dyn.PM6: 6, dyn.PM9: 9, dyn.RB13: 13, dyn.NOMINAL13: 13, dyn.PMD: 9}[model]
     K = 4 if C == 13 else 3
     s = torch.tensor(rng.normal(size=(A, C)))
     if C == 13:
@@ -331,3 +331,55 @@ def test_step_jacobian_autograd_matches_central_fd(model, integ):
                 fm = (dyn.step(model, s, xm, prm, DT, integ) * w).sum()
             fd = (fp - fm) / (2 * h)
             assert abs(fd - (g * dirn).sum()) <= 1e-7 * max(1.0, abs(fd))
+
+
+# ----------------------------------------------------------------------------
+# discrete point mass, Eq. (4)
+# ----------------------------------------------------------------------------
+
+def test_pmd_constant_acceleration_is_exact_kinematics():
+    """With the same command every step (and already applied), Eq. (4) is the
+    exact constant-acceleration motion p0 + v0 t + (c + g) t^2 / 2."""
+    A, n = 5, 40
+    rng = np.random.default_rng(9)
+    c = torch.tensor(rng.uniform(-9.81, 9.81, (A, 3)))
+    s = torch.cat([torch.tensor(rng.normal(size=(A, 6))), c], 1)
+    p0, v0 = s[:, 0:3].clone(), s[:, 3:6].clone()
+    for _ in range(n):
+        s = dyn.step(dyn.PMD, s, c, torch.zeros(A, 0, dtype=D), DT, dyn.EULER)
+    t = n * DT
+    acc = c + torch.tensor([0.0, 0.0, -9.81], dtype=D)
+    assert torch.allclose(s[:, 0:3], p0 + v0 * t + 0.5 * acc * t * t, atol=1e-11)
+    assert torch.allclose(s[:, 3:6], v0 + acc * t, atol=1e-11)
+    assert torch.equal(s[:, 6:9], c)
+
+
+def test_pmd_command_acts_one_step_later():
+    """A new command leaves this step's position unchanged, enters this step's
+    velocity through the trapezoid, and is the applied acceleration of the
+    next step; hover u = (0, 0, g) at rest stays at rest."""
+    s = torch.zeros(2, 9, dtype=D)
+    s[:, 8] = 9.81
+    u = torch.tensor([[0.0, 0.0, 9.81], [2.0, -4.0, 9.81]], dtype=D)
+    s1 = dyn.step(dyn.PMD, s, u, torch.zeros(2, 0, dtype=D), DT, dyn.RK4)
+    assert torch.equal(s1[0], s[0])
+    assert torch.equal(s1[1, 0:3], torch.zeros(3, dtype=D))
+    assert torch.allclose(s1[1, 3:6], torch.tensor([1.0, -2.0, 0.0], dtype=D) * DT, atol=1e-15)
+    assert torch.equal(s1[1, 6:9], u[1])
+    s2 = dyn.step(dyn.PMD, s1, u, torch.zeros(2, 0, dtype=D), DT, dyn.RK4)
+    # second step: position moves with v1 dt + u dt^2 / 2 (horizontal part)
+    assert torch.allclose(s2[1, 0:2], s1[1, 3:5] * DT + 0.5 * u[1, 0:2] * DT * DT, atol=1e-15)
+
+
+def test_pmd_velocity_is_exact_for_linear_acceleration():
+    """The trapezoid of Eq. (4) integrates an acceleration that varies linearly
+    between the step's samples exactly: v_T - v_0 = sum of the trapezoids =
+    the integral of the piecewise-linear profile through the commands."""
+    A, n = 3, 30
+    k = torch.tensor([[0.5, -1.0, 2.0]], dtype=D)
+    u_of = lambda j: k * (j * DT) + torch.tensor([[0.0, 0.0, 9.81]], dtype=D)  # noqa: E731
+    s = torch.cat([torch.zeros(A, 6, dtype=D), u_of(0).expand(A, 3)], 1)
+    for j in range(n):
+        s = dyn.step(dyn.PMD, s, u_of(j + 1).expand(A, 3), torch.zeros(A, 0, dtype=D), DT, dyn.EULER)
+    t = n * DT
+    assert torch.allclose(s[:, 3:6], (0.5 * k * t * t).expand(A, 3), atol=1e-12)

@@ -29,11 +29,11 @@ from typing import Optional
 import numpy as np
 
 # Model / component-count constants (names follow include/diffaero.h).
-PM6, PM9, RB13, NOMINAL13 = 0, 1, 2, 3
+PM6, PM9, RB13, NOMINAL13, PMD = 0, 1, 2, 3, 4
 EULER, RK4 = 0, 1
-STATE_DIM = {PM6: 6, PM9: 9, RB13: 13, NOMINAL13: 13}
-ACTION_DIM = {PM6: 3, PM9: 3, RB13: 4, NOMINAL13: 4}
-PARAM_DIM = {PM6: 0, PM9: 2, RB13: 8, NOMINAL13: 8}
+STATE_DIM = {PM6: 6, PM9: 9, RB13: 13, NOMINAL13: 13, PMD: 9}
+ACTION_DIM = {PM6: 3, PM9: 3, RB13: 4, NOMINAL13: 4, PMD: 3}
+PARAM_DIM = {PM6: 0, PM9: 2, RB13: 8, NOMINAL13: 8, PMD: 0}
 
 G = 9.81
 ROOM_C2 = (-10.0, -10.0, 0.0, 10.0, 10.0, 8.0)
@@ -170,7 +170,7 @@ def initial_state(rng, model: int, p0: np.ndarray) -> np.ndarray:
     s = np.zeros((C, A), np.float64)
     s[0:3] = p0.T
     s[3:6] = rng.uniform(-1.0, 1.0, size=(3, A))
-    if model == PM9:
+    if model in (PM9, PMD):
         s[6:9] = rng.uniform(-1.0, 1.0, size=(3, A))
     elif model in (RB13, NOMINAL13):
         roll = rng.uniform(-0.2, 0.2, A)
@@ -189,7 +189,7 @@ def params(rng, model: int, n_agents: int, drag_range=None, tau_w=0.03,
     PM9 rows: lambda (control latency factor), d (drag coefficient).
     """
     A = n_agents
-    if model == PM6:
+    if model in (PM6, PMD):
         return np.zeros((0, A), np.float32)
     if model == PM9:
         return np.stack([rng.uniform(*lam_range, A), rng.uniform(*pm_drag_range, A)]).astype(np.float32)
@@ -209,7 +209,7 @@ def actions(rng, model: int, n_agents: int, T: int, mass: float = 1.0) -> np.nda
     PM: 3-D acceleration command, uniform in [-1, 1] * g per component.
     RB: collective thrust uniform in m*g*[0.7, 1.3], body rates U[-2, 2] rad/s.
     """
-    if model in (PM6, PM9):
+    if model in (PM6, PM9, PMD):
         return (G * rng.uniform(-1.0, 1.0, size=(T, 3, n_agents))).astype(np.float32)
     a = np.empty((T, 4, n_agents))
     a[:, 0] = mass * G * rng.uniform(0.7, 1.3, size=(T, n_agents))
