@@ -72,7 +72,8 @@ enum { SIM_EULER = 0, SIM_RK4 = 1 };
 enum { SIM_FLAG_NONFINITE = 1, SIM_FLAG_COLLISION = 2 };
 
 /* Upper bounds checked by sim_set_scene (the per-env primitive list is staged
- * in LDS by the render kernels). */
+ * in LDS by the render kernels): obstacles (spheres + boxes) of one env, and
+ * agents of one env. */
 #define SIM_MAX_PRIMS_PER_ENV 1024
 #define SIM_MAX_AGENTS_PER_ENV 64
 
@@ -294,7 +295,8 @@ int bptt_get_timing(bptt_handle* b, float* ms, int32_t* count, int32_t n);
 /* Stand-alone policy forward / backward on a batch (for tests and tools):
  * x [B][3081] row-major, y [B][4]. policy_backward recomputes the forward and
  * writes g_theta (overwritten) and g_x ([B][3081], nullable). gemm_mode:
- * POLICY_GEMM_*. Allocate their scratch per call (synchronous). */
+ * POLICY_GEMM_*. Allocate their scratch per call (synchronous). B = 0 is a
+ * no-op for policy_forward (x and y may then be NULL). */
 int policy_forward(const float* theta, const float* x, float* y, int32_t B, int32_t gemm_mode,
                    void* stream);
 int policy_backward(const float* theta, const float* x, const float* g_y, float* g_theta,

@@ -894,9 +894,10 @@ static int policy_prec(int32_t mode) {
 }
 
 int policy_forward(const float* theta, const float* x, float* y, int32_t B, int32_t gemm_mode, void* stream) {
-  DA_REQUIRE(theta && x && y && B >= 0, "policy_forward: bad argument");
+  DA_REQUIRE(B >= 0, "policy_forward: B must be >= 0");
   DA_REQUIRE(gemm_mode == POLICY_GEMM_FP32 || gemm_mode == POLICY_GEMM_BF16X3, "policy_forward: bad gemm_mode");
   if (B == 0) return SIM_OK;
+  DA_REQUIRE(theta && x && y, "policy_forward: null argument");
   int rc = require_device();
   if (rc) return rc;
   hipStream_t st = as_stream(stream);

@@ -292,9 +292,9 @@ int sim_set_scene(sim_handle* h, const int32_t* sph_off, const float* sph, int32
   int maxp = 0;
   for (int e = 0; e < E; ++e) {
     int p = (so[e + 1] - so[e]) + (bo[e + 1] - bo[e]);
+    DA_REQUIRE(p <= SIM_MAX_PRIMS_PER_ENV, "sim_set_scene: env %d has %d primitives (spheres + boxes; at most %d)",
+               e, p, SIM_MAX_PRIMS_PER_ENV);
     if (h->cfg.agents_visible) p += ao[e + 1] - ao[e];
-    DA_REQUIRE(p <= SIM_MAX_PRIMS_PER_ENV + SIM_MAX_AGENTS_PER_ENV,
-               "sim_set_scene: env %d has %d primitives", e, p);
     maxp = std::max(maxp, p);
   }
   {
