@@ -133,6 +133,48 @@ def hit_box(o, d, c, h):
     return t, -dn.abs(), face
 
 
+def hit_cylinder(o, d, c, r, h):
+    """Vertical cylinder (axis along world z; centre c, radius r, half-height
+    h). The ray is inside the infinite cylinder for t in [ts0, ts1], the
+    roots of |(o + t d - c)_xy| = r, and inside the slab |o_z + t d_z - c_z|
+    <= h for t in [tz0, tz1]; it hits at the start of the intersection of the
+    two intervals when that is >= 0 (the side if the cylinder interval starts
+    last, else a cap). Origin inside -> 0. Returns (t, cos of incidence)."""
+    oc = o - c
+    dx, dy, dz = d[..., 0], d[..., 1], d[..., 2]
+    a = dx * dx + dy * dy
+    b = dx * oc[..., 0] + dy * oc[..., 1]
+    C = oc[..., 0] ** 2 + oc[..., 1] ** 2 - r * r
+    disc = b * b - a * C
+    slanted = a > 0
+    real = slanted & (disc >= 0)
+    sq = torch.sqrt(_safe(disc, real, 0.0))
+    asafe = _safe(a, slanted)
+    ts0 = torch.where(real, (-b - sq) / asafe, torch.full_like(a, INF))
+    ts1 = torch.where(real, (-b + sq) / asafe, torch.full_like(a, -INF))
+    # a vertical ray is inside the infinite cylinder for all t or never
+    ts0 = torch.where(~slanted, torch.where(C <= 0, torch.full_like(a, -INF), torch.full_like(a, INF)), ts0)
+    ts1 = torch.where(~slanted, torch.where(C <= 0, torch.full_like(a, INF), torch.full_like(a, -INF)), ts1)
+    nz = dz != 0
+    dzs = _safe(dz, nz)
+    z1 = (-h - oc[..., 2]) / dzs
+    z2 = (h - oc[..., 2]) / dzs
+    in_slab = oc[..., 2].abs() <= h
+    tz0 = torch.where(nz, torch.minimum(z1, z2), torch.where(in_slab, torch.full_like(a, -INF), torch.full_like(a, INF)))
+    tz1 = torch.where(nz, torch.maximum(z1, z2), torch.where(in_slab, torch.full_like(a, INF), torch.full_like(a, -INF)))
+    tn = torch.maximum(ts0, tz0)
+    tf = torch.minimum(ts1, tz1)
+    inside = (C < 0) & (oc[..., 2].abs() < h)
+    hit = (~inside) & (tn <= tf) & (tn >= 0)
+    t = torch.where(hit, tn, torch.full_like(tn, INF))
+    t = torch.where(inside, torch.zeros_like(t), t)
+    side = ts0 >= tz0
+    px = oc[..., 0] + _safe(t, hit, 0.0) * dx
+    py = oc[..., 1] + _safe(t, hit, 0.0) * dy
+    cos_side = (px * dx + py * dy) / _safe(r, r > 0)
+    return t, torch.where(side, cos_side, -dz.abs())
+
+
 def hit_room(o, d, lo, hi):
     """Inner faces of the room box: exit distance min over axes of the
     distance to the face the ray heads for. Origin outside the room -> 0."""
@@ -159,7 +201,17 @@ class DenseScene:
         ns = np.diff(scene.sph_off)
         nb = np.diff(scene.box_off)
         na = np.diff(scene.agent_off)
-        self.E, self.ns, self.nb, self.na = E, ns, nb, na
+        has_cyl = getattr(scene, "cyl_off", None) is not None
+        nc = np.diff(scene.cyl_off) if has_cyl else np.zeros(E, np.int64)
+        self.E, self.ns, self.nb, self.na, self.nc = E, ns, nb, na, nc
+        Cn = int(nc.max(initial=0))
+        self.Cn = Cn
+        cyl = np.zeros((E, Cn, 5))
+        for e in range(E):
+            if has_cyl:
+                cyl[e, :nc[e]] = scene.cyl[scene.cyl_off[e]:scene.cyl_off[e + 1]]
+        self.cyl = torch.tensor(cyl)
+        self.cyl_ok = torch.tensor(np.arange(Cn)[None, :] < nc[:, None])
         S, B, Am = int(ns.max(initial=0)), int(nb.max(initial=0)), int(na.max(initial=0))
         self.S, self.B, self.Am = S, B, Am
         sph = np.zeros((E, S, 4))
@@ -216,6 +268,15 @@ def cast(ds: DenseScene, o, d, lanes, all_pos=None, frozen=None):
         ts.append(torch.where(ok, t, torch.full_like(t, INF)))
         coss.append(cs)
         faces.append(fc)
+    if ds.Cn:
+        c = ds.cyl[env, :, :3][:, None]
+        r = ds.cyl[env, :, 3][:, None]
+        h = ds.cyl[env, :, 4][:, None]
+        t, cs = hit_cylinder(O, D, c, r, h)
+        ok = ds.cyl_ok[env][:, None, :]
+        ts.append(torch.where(ok, t, torch.full_like(t, INF)))
+        coss.append(cs)
+        faces.append(torch.full(t.shape, -1, dtype=torch.long))
     if all_pos is not None and ds.Am:
         others = ds.env_lanes[env]                       # [a, Am]
         valid = (others >= 0) & (others != lanes[:, None])
@@ -241,18 +302,22 @@ def cast(ds: DenseScene, o, d, lanes, all_pos=None, frozen=None):
     cos_all = torch.cat(coss, -1)
     face_all = torch.cat(faces, -1)
     # padded index -> env-local id
+    # env-local ids: spheres, boxes, cylinders, other agents, room
     ns = torch.tensor(ds.ns, dtype=torch.long)[env][:, None]
     nb = torch.tensor(ds.nb, dtype=torch.long)[env][:, None]
+    nc = torch.tensor(ds.nc, dtype=torch.long)[env][:, None]
     na = torch.tensor(ds.na, dtype=torch.long)[env][:, None]
     cols = []
     if ds.S:
         cols.append(torch.arange(ds.S).expand(a, -1))
     if ds.B:
         cols.append(ns + torch.arange(ds.B)[None, :])
+    if ds.Cn:
+        cols.append(ns + nb + torch.arange(ds.Cn)[None, :])
     if all_pos is not None and ds.Am:
-        cols.append(ns + nb + torch.arange(ds.Am)[None, :])
+        cols.append(ns + nb + nc + torch.arange(ds.Am)[None, :])
     if ds.room is not None:
-        cols.append(ns + nb + (na if all_pos is not None else 0))
+        cols.append(ns + nb + nc + (na if all_pos is not None else 0))
     local_id = torch.cat(cols, -1)                          # [a, P]
     if frozen is None:
         t_min = t_all.min(-1, keepdim=True).values
@@ -342,8 +407,10 @@ def stable_rays(model, ds, s, d_body, zfac, max_range, lanes=None, agents_visibl
 
 def sdf_min(ds: DenseScene, s, agents_visible=True):
     """Distance from each agent's centre to the nearest obstacle surface:
-    spheres |p-c|-r, boxes (exterior/interior box SDF), room walls (distance
-    to the nearest inner face, negative outside), other agents' spheres.
+    spheres |p-c|-r, boxes (exterior/interior box SDF), vertical cylinders
+    (the same construction on the radial and axial excess), room walls
+    (distance to the nearest inner face, negative outside), other agents'
+    spheres.
     Returns (min_dist [A], collided [A] = min_dist < r_a)."""
     p = s[:, 0:3]
     env = ds.agent_env
@@ -360,6 +427,18 @@ def sdf_min(ds: DenseScene, s, agents_visible=True):
         qv = (p[:, None] - c).abs() - h
         dist = qv.clamp(min=0).norm(dim=-1) + qv.max(-1).values.clamp(max=0)
         cands.append(torch.where(ds.box_ok[env], dist, torch.full_like(dist, INF)))
+    if ds.Cn:
+        # capped vertical cylinder: radial and axial excess, exterior norm +
+        # interior max
+        c = ds.cyl[env, :, :3]
+        r = ds.cyl[env, :, 3]
+        h = ds.cyl[env, :, 4]
+        w = p[:, None] - c
+        qr = w[..., :2].norm(dim=-1) - r
+        qz = w[..., 2].abs() - h
+        q = torch.stack([qr, qz], -1)
+        dist = q.clamp(min=0).norm(dim=-1) + q.max(-1).values.clamp(max=0)
+        cands.append(torch.where(ds.cyl_ok[env], dist, torch.full_like(dist, INF)))
     if ds.room is not None:
         lo, hi = ds.room[env, :3], ds.room[env, 3:]
         cands.append(torch.minimum(p - lo, hi - p).min(-1, keepdim=True).values)

@@ -50,6 +50,12 @@ class Scene:
     box: np.ndarray              # float32 [n_box, 6]
     room: Optional[np.ndarray]   # float32 [E, 6] or None
     agent_off: np.ndarray        # int32 [E+1]
+    cyl_off: Optional[np.ndarray] = None  # int32 [E+1] (None: no cylinders)
+    cyl: Optional[np.ndarray] = None      # float32 [n_cyl, 5]: centre, radius, half-height (axis z)
+
+    @property
+    def has_cylinders(self) -> bool:
+        return self.cyl_off is not None and int(self.cyl_off[-1]) > 0
 
     @property
     def n_agents(self) -> int:
@@ -77,7 +83,10 @@ class Scene:
         ao = np.zeros(len(envs) + 1, dtype=np.int32)
         ao[1:] = np.cumsum(cnt)
         room = None if self.room is None else np.ascontiguousarray(self.room[envs])
-        return Scene(len(envs), so, s, bo, b, room, ao)
+        co = c = None
+        if self.cyl_off is not None:
+            co, c = take(self.cyl_off, self.cyl)
+        return Scene(len(envs), so, s, bo, b, room, ao, co, c)
 
     def agent_lanes(self, envs) -> np.ndarray:
         envs = np.asarray(envs)
@@ -93,10 +102,14 @@ def _csr(counts) -> np.ndarray:
 
 def make_scene(rng: np.random.Generator, n_envs: int, n_sph, n_box,
                vol, sph_r, box_h, room: bool, agents_per_env=None,
-               keepout: Optional[np.ndarray] = None, keepout_r: float = 0.3) -> Scene:
-    """Random spheres / boxes with centres uniform in `vol` (lo3, hi3).
+               keepout: Optional[np.ndarray] = None, keepout_r: float = 0.3,
+               n_cyl=0, cyl_r=(0.2, 0.8), cyl_h=(0.3, 1.5)) -> Scene:
+    """Random spheres / boxes (and optional vertical cylinders) with centres
+    uniform in `vol` (lo3, hi3).
 
-    n_sph, n_box: int or int array [E] (per-env counts).
+    n_sph, n_box, n_cyl: int or int array [E] (per-env counts); cylinders are
+    drawn after the other primitives and only when some are asked for, so
+    scenes without them use the same random stream as before.
     keepout: optional float [A, 3] points (agent start positions, grouped by
       env via agents_per_env); a primitive whose bounding sphere comes within
       keepout_r of one of its env's points is redrawn (at most 64 rounds).
@@ -135,7 +148,14 @@ def make_scene(rng: np.random.Generator, n_envs: int, n_sph, n_box,
     sph = np.concatenate([sc, sr[:, None]], 1).astype(np.float32).reshape(-1, 4)
     box = np.concatenate([bc, bh], 1).astype(np.float32).reshape(-1, 6)
     room_arr = np.tile(np.asarray(vol, np.float32), (n_envs, 1)) if room else None
-    return Scene(n_envs, _csr(n_sph), sph, _csr(n_box), box, room_arr, agent_off)
+    n_cyl = np.broadcast_to(np.asarray(n_cyl, dtype=np.int64), (n_envs,))
+    cyl_off = cyl = None
+    if n_cyl.sum() > 0:
+        cc, cx = draw(n_cyl, lambda n: (rng.uniform(lo, hi, size=(n, 3)),
+                                       np.stack([rng.uniform(*cyl_r, size=n), rng.uniform(*cyl_h, size=n)], 1)))
+        cyl = np.concatenate([cc, cx], 1).astype(np.float32).reshape(-1, 5)
+        cyl_off = _csr(n_cyl)
+    return Scene(n_envs, _csr(n_sph), sph, _csr(n_box), box, room_arr, agent_off, cyl_off, cyl)
 
 
 # ---------------------------------------------------------------------------
