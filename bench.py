@@ -31,9 +31,11 @@ PEAK_HBM = 8.0e12
 # exp2, log2 = 1; compares and selects = 0), counted from the kernel's
 # expressions: direction rotation 15 + reciprocals 3 + room exit 5 + depth
 # scale 2 per cast ray, plus 11 for the fused softplus obstacle term; 17 per
-# ray-sphere test, 16 per ray-box slab test; 21 per tile-cone test of a
-# primitive and 15 per tile for the rotated cone axis.
-RENDER_FLOP = {"ray": 25, "ray_term": 11, "sphere": 17, "box": 16, "cone": 21, "tile": 15}
+# ray-sphere test, 16 per ray-box slab test, 26 per ray-cylinder test
+# (radial quadratic 12, root and reciprocals 6, slab 4, interval overlap 4);
+# 21 per tile-cone test of a primitive and 15 per tile for the rotated cone
+# axis.
+RENDER_FLOP = {"ray": 25, "ray_term": 11, "sphere": 17, "box": 16, "cylinder": 26, "cone": 21, "tile": 15}
 
 
 def parse():
@@ -323,13 +325,14 @@ def render_work_flops(e, s, term):
     from paper_2509_10247_amd import _lib
     A = e.n_agents
     out = torch.empty(A, e.cam[1] * e.cam[0], device="cuda")
-    work = torch.zeros(A, 4, 6, dtype=torch.int32, device="cuda")
+    work = torch.zeros(A, 4, 7, dtype=torch.int32, device="cuda")
     _lib.sim_render_work(e.h, 0, s, out, work)
     w = work.long().sum((0, 1)).tolist()
     c = dict(zip(_lib.WORK_FIELDS, w))
     f = RENDER_FLOP
     flops = (c["rays"] * (f["ray"] + (f["ray_term"] if term else 0)) + c["sphere_tests"] * f["sphere"]
-             + c["box_tests"] * f["box"] + c["agent_tests"] * f["sphere"] + c["cone_tests"] * f["cone"]
+             + c["box_tests"] * f["box"] + c["cylinder_tests"] * f["cylinder"] + c["agent_tests"] * f["sphere"]
+             + c["cone_tests"] * f["cone"]
              + c["tiles"] * f["tile"])
     return flops, c
 

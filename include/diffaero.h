@@ -118,6 +118,19 @@ int sim_set_scene(sim_handle* h, const int32_t* sph_off, const float* sph, int32
                   const int32_t* box_off, const float* box, int32_t n_box,
                   const float* room, const int32_t* agent_off);
 
+/* Vertical cylinders (axis along world z; Sec. III-B names cylinders among
+ * the primitives the ray caster intersects) added to the scene set by the
+ * last sim_set_scene, which starts with none:
+ *   cyl_off[E+1], cyl[n_cyl][5] = (cx, cy, cz, r, h), h the half-height,
+ *   r > 0 and h > 0 (not checked: the values stay on the device).
+ * Device pointers kept by reference like the scene; cyl_off NULL (with
+ * n_cyl = 0) removes them. Hit-record ids within an env: spheres, boxes,
+ * cylinders, other agents, room. The offsets are copied to the host and
+ * validated like sim_set_scene's; spheres + boxes + cylinders per env must not
+ * exceed SIM_MAX_PRIMS_PER_ENV: SIM_EINVAL otherwise (the scene keeps its
+ * previous cylinders). Synchronous. */
+int sim_set_cylinders(sim_handle* h, const int32_t* cyl_off, const float* cyl, int32_t n_cyl);
+
 /* Per-agent parameters SoA [P][A] (P = 0, 2, 8 by model, see above); kept by
  * reference like the scene. Required before sim_step for PM9 / RB13 /
  * NOMINAL13. */
@@ -143,14 +156,15 @@ int sim_render(sim_handle* h, const float* s, float* depth, float* lidar, int32_
 /* Work count of one sensor's render at s (diagnostics for the roofline; the
  * exclusion of obstacles outside the field of view is Sec. III-B): renders
  * sensor 0 (camera) or 1 (LiDAR) into out ([A][n_rays], as sim_render) and
- * writes work [A][4][6] int32 (per agent and wavefront): rays cast, ray-sphere
- * tests, ray-box tests, ray-agent tests, tiles, tile-cone tests. Rays of an
+ * writes work [A][4][7] int32 (per agent and wavefront): rays cast, ray-sphere
+ * tests, ray-box tests, ray-agent tests, tiles, tile-cone tests, ray-cylinder
+ * tests. Rays of an
  * agent that is inside a primitive are not cast. Same image as sim_render. */
 int sim_render_work(sim_handle* h, int32_t sensor, const float* s, float* out, int32_t* work,
                     void* stream);
 
 /* Collisions: min_dist[i] = distance from agent i's centre to the nearest
- * surface (spheres, boxes, room walls, other agents' spheres when
+ * surface (spheres, boxes, cylinders, room walls, other agents' spheres when
  * agents_visible); flags[i] |= SIM_FLAG_COLLISION when min_dist < agent_radius.
  * Either output nullable. */
 int sim_collide(sim_handle* h, const float* s, uint8_t* flags, float* min_dist, void* stream);

@@ -51,6 +51,7 @@ _SIGS = {
     "sim_destroy": (c_int, [c_void_p]),
     "sim_set_scene": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_int,
                               c_void_p, c_void_p]),
+    "sim_set_cylinders": (c_int, [c_void_p, c_void_p, c_void_p, c_int]),
     "sim_set_params": (c_int, [c_void_p, c_void_p]),
     "sim_reset": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "sim_step": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
@@ -172,6 +173,10 @@ def sim_set_scene(h, sph_off, sph, n_sph, box_off, box, n_box, room, agent_off):
           ptr(agent_off, torch.int32))
 
 
+def sim_set_cylinders(h, cyl_off, cyl, n_cyl):
+    _call("sim_set_cylinders", h, ptr(cyl_off, torch.int32), ptr(cyl, torch.float32), int(n_cyl))
+
+
 def sim_set_params(h, params):
     _call("sim_set_params", h, ptr(params, torch.float32))
 
@@ -191,11 +196,11 @@ def sim_render(h, s, depth=None, lidar=None, hit_cam=None, hit_lidar=None):
           ptr(hit_cam, torch.int32), ptr(hit_lidar, torch.int32), stream())
 
 
-WORK_FIELDS = ("rays", "sphere_tests", "box_tests", "agent_tests", "tiles", "cone_tests")
+WORK_FIELDS = ("rays", "sphere_tests", "box_tests", "agent_tests", "tiles", "cone_tests", "cylinder_tests")
 
 
 def sim_render_work(h, sensor, s, out, work):
-    """work: int32 [A][4][6] (see WORK_FIELDS)."""
+    """work: int32 [A][4][7] (see WORK_FIELDS)."""
     _call("sim_render_work", h, int(sensor), ptr(s, torch.float32), ptr(out, torch.float32),
           ptr(work, torch.int32), stream())
 

@@ -25,12 +25,14 @@ struct SceneDev {
   const float* sph = nullptr;     // [n_sph][4]
   const int* box_off = nullptr;   // [E+1]
   const float* box = nullptr;     // [n_box][6]
+  const int* cyl_off = nullptr;   // [E+1] or null (no cylinders)
+  const float* cyl = nullptr;     // [n_cyl][5]
   const float* room = nullptr;    // [E][6] or null
   const int* agent_off = nullptr; // [E+1]
   const int* agent_env = nullptr; // [A]
   float agent_radius = 0.15f;
   int agents_visible = 0;
-  int max_prims = 0;              // max over envs of spheres + boxes + visible agents
+  int max_prims = 0;              // max over envs of spheres + boxes + cylinders + visible agents
 };
 
 int state_dim(int model);

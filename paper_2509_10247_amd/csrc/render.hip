@@ -2,15 +2,16 @@
 //
 // Forward: one workgroup (4 wavefronts) per agent. The agent's environment
 // primitives are staged once in LDS in origin-relative form (sphere: centre
-// minus origin, r^2 and |c-o|^2 - r^2; box: lo-o, hi-o), shared by all of that
+// minus origin, r^2 and |c-o|^2 - r^2; box: lo-o, hi-o; cylinder: centre
+// minus origin, r^2, radial excess and half-height), shared by all of that
 // agent's rays. Each wavefront then walks the sensor's ray tiles (64 rays, a
 // small angular patch); per tile it culls the primitive list against the
 // tile's bounding cone and range limit (the paper's exclusion of obstacles
 // outside the sensor field of view), compacting the survivors with a wave
 // ballot in index order, and each lane casts its ray against the survivors:
-// spheres, boxes, other agents' spheres, then the room. Culling is
-// conservative, so the nearest hit (lowest index on ties) is identical with
-// culling on or off.
+// spheres, boxes, vertical cylinders, other agents' spheres, then the room.
+// Culling is conservative, so the nearest hit (lowest index on ties) is
+// identical with culling on or off.
 //
 // Backward: one workgroup per agent; each thread recomputes the recorded
 // primitive's hit for its rays, applies dt/do = -n/(n.d) and
@@ -20,7 +21,7 @@
 
 namespace da {
 
-template <bool ROT, bool CULL>
+template <bool ROT, bool CULL, bool CYL>
 __global__ __launch_bounds__(256) void render_kernel(SceneDev sc, SensorDev sen,
                                                      const float* __restrict__ s, int A,
                                                      float* __restrict__ out,
@@ -28,7 +29,7 @@ __global__ __launch_bounds__(256) void render_kernel(SceneDev sc, SensorDev sen,
                                                      float out_scale, float* __restrict__ term,
                                                      float beta, float d_safe, int i0) {
   extern __shared__ float4 smem_f4[];
-  render_one_agent<ROT, CULL>(sc, sen, s, A, i0 + (int)blockIdx.x, 0, sen.n_tiles, out, rec, out_ld,
+  render_one_agent<ROT, CULL, CYL>(sc, sen, s, A, i0 + (int)blockIdx.x, 0, sen.n_tiles, out, rec, out_ld,
                               out_scale, term, beta, d_safe, smem_f4);
 }
 
@@ -39,7 +40,7 @@ __global__ __launch_bounds__(256) void render_work_kernel(SceneDev sc, SensorDev
                                                           float* __restrict__ out, int out_ld,
                                                           int* __restrict__ work) {
   extern __shared__ float4 smem_f4[];
-  render_one_agent<ROT, CULL, true>(sc, sen, s, A, blockIdx.x, 0, sen.n_tiles, out, nullptr, out_ld,
+  render_one_agent<ROT, CULL, true, true>(sc, sen, s, A, blockIdx.x, 0, sen.n_tiles, out, nullptr, out_ld,
                                     1.0f, nullptr, 1.0f, 0.0f, smem_f4, work);
 }
 
@@ -82,7 +83,17 @@ __device__ __forceinline__ void rot64(const double (&qn)[4], double (&R)[3][3]) 
   R[2][2] = 1.0 - 2.0 * (x * x + y * y);
 }
 
-template <bool ROT, bool OBS>
+// FP64 world direction of ray r (body direction rotated by the FP64 R)
+template <bool ROT>
+__device__ __forceinline__ d3 ray_dir64(const SensorDev& sen, int r, const double (&R)[3][3]) {
+  const double* b64 = sen.dirs64 + (size_t)r * 4;
+  const d3 b = dk3(b64[0], b64[1], b64[2]);
+  if (!ROT) return b;
+  return dk3(R[0][0] * b.x + R[0][1] * b.y + R[0][2] * b.z, R[1][0] * b.x + R[1][1] * b.y + R[1][2] * b.z,
+             R[2][0] * b.x + R[2][1] * b.y + R[2][2] * b.z);
+}
+
+template <bool ROT, bool OBS, bool CYL>
 __global__ __launch_bounds__(256, 5) void render_vjp_kernel(SceneDev sc, SensorDev sen,
                                                          const float* __restrict__ s, int A,
                                                          const float* __restrict__ g, int g_ld,
@@ -115,15 +126,21 @@ __global__ __launch_bounds__(256, 5) void render_vjp_kernel(SceneDev sc, SensorD
   }
   const int s0 = sc.sph_off[env], ns = sc.sph_off[env + 1] - s0;
   const int b0 = sc.box_off[env], nb = sc.box_off[env + 1] - b0;
+  int c0 = 0, nc = 0;
+  if (CYL && sc.cyl_off) {  // CYL variants also serve scenes without cylinders
+    c0 = sc.cyl_off[env];
+    nc = sc.cyl_off[env + 1] - c0;
+  }
   int a0 = 0, na = 0;
   if (sc.agents_visible) {
     a0 = sc.agent_off[env];
     na = sc.agent_off[env + 1] - a0;
   }
-  const int np = ns + nb + na;
+  const int nsbc = ns + nb + nc, np = nsbc + na;
   const int nr = sen.n_rays;
   // the env's primitives, staged once: sphere / agent (centre, radius);
-  // box (lo, -) and (hi, -); the room as entry np
+  // box (lo, -) and (hi, -); cylinder (centre, radius) and (half-height, -);
+  // the room as entry np
   extern __shared__ float4 vjp_lds[];
   float4* P0 = vjp_lds;
   float4* P1 = vjp_lds + (np + 1);
@@ -134,8 +151,12 @@ __global__ __launch_bounds__(256, 5) void render_vjp_kernel(SceneDev sc, SensorD
       const float* b = sc.box + (size_t)(b0 + k - ns) * 6;
       P0[k] = make_float4(b[0] - b[3], b[1] - b[4], b[2] - b[5], 0.f);
       P1[k] = make_float4(b[0] + b[3], b[1] + b[4], b[2] + b[5], 0.f);
+    } else if (CYL && k < nsbc) {
+      const float* y = sc.cyl + (size_t)(c0 + k - ns - nb) * 5;
+      P0[k] = make_float4(y[0], y[1], y[2], y[3]);
+      P1[k] = make_float4(y[4], 0.f, 0.f, 0.f);
     } else if (k < np) {
-      const int j = a0 + (k - ns - nb);
+      const int j = a0 + (k - nsbc);
       P0[k] = make_float4(s[j], s[(size_t)A + j], s[2 * (size_t)A + j], sc.agent_radius);
     } else if (sc.room) {
       const float* rm = sc.room + (size_t)env * 6;
@@ -192,7 +213,7 @@ __global__ __launch_bounds__(256, 5) void render_vjp_kernel(SceneDev sc, SensorD
     const float gt = gv * db.w;
     const f3 d32 = ROT ? rot_apply(R32, mk3(db.x, db.y, db.z)) : mk3(db.x, db.y, db.z);
     f3 dto, dtd;  // dt/do and dt/dd (FP32 results)
-    if (k < ns || (k >= ns + nb && k < np)) {
+    if (k < ns || (k >= nsbc && k < np)) {
       const float4 cc = P0[k];
       const d3 c = dk3(cc.x, cc.y, cc.z);
       const double rad = cc.w;
@@ -211,12 +232,7 @@ __global__ __launch_bounds__(256, 5) void render_vjp_kernel(SceneDev sc, SensorD
         dto = scl(sub(scl(d32, t), w32), is);
         dtd = scl(dto, t);
       } else {
-        const double* b64 = sen.dirs64 + (size_t)r * 4;
-        const d3 dbv = dk3(b64[0], b64[1], b64[2]);
-        const d3 d = ROT ? dk3(Rsh[0][0] * dbv.x + Rsh[0][1] * dbv.y + Rsh[0][2] * dbv.z,
-                               Rsh[1][0] * dbv.x + Rsh[1][1] * dbv.y + Rsh[1][2] * dbv.z,
-                               Rsh[2][0] * dbv.x + Rsh[2][1] * dbv.y + Rsh[2][2] * dbv.z)
-                         : dbv;
+        const d3 d = ray_dir64<ROT>(sen, r, Rsh);
         // t = tc - sqrt(disc) and, at the hit point, n.d = -sqrt(disc)/r, so
         // dt/do = -n/(n.d) = (t d - w)/sqrt(disc) and dt/dd = t dt/do.
         // Only the discriminant (a difference of nearly equal squares near
@@ -234,6 +250,55 @@ __global__ __launch_bounds__(256, 5) void render_vjp_kernel(SceneDev sc, SensorD
         const double td = (double)t;
         dto = mk3((float)(td * d.x - w.x) * is, (float)(td * d.y - w.y) * is, (float)(td * d.z - w.z) * is);
         dtd = scl(dto, t);
+      }
+    } else if (CYL && k >= ns + nb && k < nsbc) {
+      // vertical cylinder: the side (radial entry ts0) or a cap (slab entry
+      // tz0), whichever the ray enters last. Side: with x = t d - w the hit
+      // point relative to the centre, x_xy . d_xy = -sqrt(disc), so
+      // dt/do = x_xy / sqrt(disc) (no z part) and dt/dd = t dt/do; grazing
+      // side hits (|n.d| < 0.3) take the discriminant in FP64 as for spheres.
+      // Cap: dt/do_z = -1/d_z, dt/dd = t dt/do.
+      const float4 cc = P0[k];
+      const float hh = P1[k].x;
+      const f3 w32 = mk3(cc.x - o.x, cc.y - o.y, cc.z - o.z);
+      const float r2 = cc.w * cc.w;
+      const float a = d32.x * d32.x + d32.y * d32.y;
+      const float b = d32.x * w32.x + d32.y * w32.y;
+      const float cr = d32.x * w32.y - d32.y * w32.x;
+      const float disc32 = a * r2 - cr * cr;
+      const float C32 = w32.x * w32.x + w32.y * w32.y - r2;
+      const float ts0 = C32 <= 0.f ? -kInf
+                                   : ((b > 0.f && disc32 >= 0.f)
+                                          ? C32 * __builtin_amdgcn_rcpf(b + __builtin_amdgcn_sqrtf(disc32))
+                                          : kInf);
+      const float iz = __builtin_amdgcn_rcpf(d32.z);
+      const float tz0 = fminf((w32.z - hh) * iz, (w32.z + hh) * iz);
+      if (ts0 >= tz0) {
+        float t;
+        if (disc32 > 0.09f * r2) {
+          const float sq = __builtin_amdgcn_sqrtf(disc32);
+          t = C32 * __builtin_amdgcn_rcpf(b + sq);
+          const float is = __builtin_amdgcn_rcpf(sq);
+          dto = mk3((t * d32.x - w32.x) * is, (t * d32.y - w32.y) * is, 0.f);
+        } else {
+          const d3 d = ray_dir64<ROT>(sen, r, Rsh);
+          const d3 w = dk3((double)cc.x - o.x, (double)cc.y - o.y, (double)cc.z - o.z);
+          const double rr = (double)cc.w * cc.w;
+          const double cr64 = d.x * w.y - d.y * w.x;
+          const double disc = (d.x * d.x + d.y * d.y) * rr - cr64 * cr64;
+          if (!(disc > 0.0)) continue;
+          const double C = w.x * w.x + w.y * w.y - rr;
+          const float sq = __builtin_amdgcn_sqrtf((float)disc);
+          t = (float)C * __builtin_amdgcn_rcpf((float)(d.x * w.x + d.y * w.y) + sq);
+          const float is = __builtin_amdgcn_rcpf(sq);
+          const double td = (double)t;
+          dto = mk3((float)(td * d.x - w.x) * is, (float)(td * d.y - w.y) * is, 0.f);
+        }
+        dtd = scl(dto, t);
+      } else {
+        if (d32.z == 0.f) continue;
+        dto = mk3(0.f, 0.f, -iz);
+        dtd = scl(dto, tz0);
       }
     } else {
       // box entry face or room exit face: t = (plane_f - o_f) / d_f
@@ -336,17 +401,20 @@ int launch_render(const SceneDev& sc, const SensorDev& sen, bool rotate, bool cu
   if (n <= 0) return SIM_OK;
   const int P = sc.max_prims > 0 ? sc.max_prims : 1;
   const size_t lds = render_lds_bytes(P, sen.n_tiles);
-  if (rotate) {
-    if (cull)
-      hipLaunchKernelGGL((render_kernel<true, true>), dim3(n), dim3(256), lds, st, sc, sen, s, A, out, rec, out_ld, out_scale, term, beta, d_safe, i0);
-    else
-      hipLaunchKernelGGL((render_kernel<true, false>), dim3(n), dim3(256), lds, st, sc, sen, s, A, out, rec, out_ld, out_scale, term, beta, d_safe, i0);
-  } else {
-    if (cull)
-      hipLaunchKernelGGL((render_kernel<false, true>), dim3(n), dim3(256), lds, st, sc, sen, s, A, out, rec, out_ld, out_scale, term, beta, d_safe, i0);
-    else
-      hipLaunchKernelGGL((render_kernel<false, false>), dim3(n), dim3(256), lds, st, sc, sen, s, A, out, rec, out_ld, out_scale, term, beta, d_safe, i0);
+  const int v = (rotate ? 4 : 0) | (cull ? 2 : 0) | (sc.cyl_off ? 1 : 0);
+  decltype(&render_kernel<true, true, true>) k = nullptr;
+  switch (v) {
+    case 7: k = render_kernel<true, true, true>; break;
+    case 6: k = render_kernel<true, true, false>; break;
+    case 5: k = render_kernel<true, false, true>; break;
+    case 4: k = render_kernel<true, false, false>; break;
+    case 3: k = render_kernel<false, true, true>; break;
+    case 2: k = render_kernel<false, true, false>; break;
+    case 1: k = render_kernel<false, false, true>; break;
+    default: k = render_kernel<false, false, false>; break;
   }
+  hipLaunchKernelGGL(k, dim3(n), dim3(256), lds, st, sc, sen, s, A, out, rec, out_ld, out_scale, term, beta,
+                     d_safe, i0);
   DA_LAUNCH_CHECK("render_kernel");
   return SIM_OK;
 }
@@ -380,18 +448,19 @@ int launch_render_vjp(const SceneDev& sc, const SensorDev& sen, bool rotate, con
   const size_t lds = (size_t)2 * (sc.max_prims + 1) * sizeof(float4);
   const DepthObsGrad ob = obs ? *obs : DepthObsGrad{nullptr, 1.f, 0.f, 0.f, 0.f, nullptr};
   if (obs && !obs->x) return fail(SIM_EINVAL, "render_vjp: observation rows missing");
-  const dim3 grid(n), blk(256);
-  if (rotate) {
-    if (obs)
-      hipLaunchKernelGGL((render_vjp_kernel<true, true>), grid, blk, lds, st, sc, sen, s, A, g, g_ld, rec, g_s, ob, i0);
-    else
-      hipLaunchKernelGGL((render_vjp_kernel<true, false>), grid, blk, lds, st, sc, sen, s, A, g, g_ld, rec, g_s, ob, i0);
-  } else {
-    if (obs)
-      hipLaunchKernelGGL((render_vjp_kernel<false, true>), grid, blk, lds, st, sc, sen, s, A, g, g_ld, rec, g_s, ob, i0);
-    else
-      hipLaunchKernelGGL((render_vjp_kernel<false, false>), grid, blk, lds, st, sc, sen, s, A, g, g_ld, rec, g_s, ob, i0);
+  const int v = (rotate ? 4 : 0) | (obs ? 2 : 0) | (sc.cyl_off ? 1 : 0);
+  decltype(&render_vjp_kernel<true, true, true>) k = nullptr;
+  switch (v) {
+    case 7: k = render_vjp_kernel<true, true, true>; break;
+    case 6: k = render_vjp_kernel<true, true, false>; break;
+    case 5: k = render_vjp_kernel<true, false, true>; break;
+    case 4: k = render_vjp_kernel<true, false, false>; break;
+    case 3: k = render_vjp_kernel<false, true, true>; break;
+    case 2: k = render_vjp_kernel<false, true, false>; break;
+    case 1: k = render_vjp_kernel<false, false, true>; break;
+    default: k = render_vjp_kernel<false, false, false>; break;
   }
+  hipLaunchKernelGGL(k, dim3(n), dim3(256), lds, st, sc, sen, s, A, g, g_ld, rec, g_s, ob, i0);
   DA_LAUNCH_CHECK("render_vjp_kernel");
   return SIM_OK;
 }

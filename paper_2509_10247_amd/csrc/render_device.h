@@ -11,8 +11,8 @@ namespace da {
 constexpr float kInf = __builtin_huge_valf();
 
 struct RenderLds {
-  float4* pa;  // sphere (w, r^2) | box lo'
-  float4* pb;  // sphere (C, ...) | box hi'
+  float4* pa;  // sphere (w, r^2) | box lo' | cylinder (w, r^2)
+  float4* pb;  // sphere (C, ...) | box hi' | cylinder (C, h, ...)
   float4* pc;  // bounding sphere: (centre - o, sqrt(L^2 - rho^2))
   float2* pd;  // (rho, L - rho); rho < 0: never hit
   short* lists;
@@ -70,6 +70,35 @@ __device__ __forceinline__ float box_t(f3 inv, float4 lo, float4 hi) {
   const float t1z = lo.z * inv.z, t2z = hi.z * inv.z;
   const float tn = fmaxf(fmaxf(fminf(t1x, t2x), fminf(t1y, t2y)), fminf(t1z, t2z));
   const float tf = fminf(fminf(fmaxf(t1x, t2x), fmaxf(t1y, t2y)), fmaxf(t1z, t2z));
+  return (tn <= tf && tn >= 0.f) ? tn : kInf;
+}
+
+// Vertical cylinder (axis along world z) with origin-relative centre w,
+// w.w = r^2, C = |w_xy|^2 - r^2 and half-height h, origin outside the solid.
+// The ray is radially inside for t in [ts0, ts1], the roots of
+// a t^2 - 2 b t + C = 0 (a = |d_xy|^2, b = d_xy . w_xy), and inside the slab
+// |t d_z - w_z| <= h for t between (w_z -+ h) / d_z; the hit is the start of
+// the overlap. The discriminant is a r^2 - (d_xy x w_xy)^2 (equal to b^2 - a C,
+// without its cancellation) and the entry root C / (b + sqrt(disc)).
+__device__ __forceinline__ float cylinder_t(f3 d, float inv_z, float4 w, float2 ch) {
+  const float a = d.x * d.x + d.y * d.y;
+  const float b = d.x * w.x + d.y * w.y;
+  const float cr = d.x * w.y - d.y * w.x;
+  const float disc = a * w.w - cr * cr;
+  float ts0, ts1;
+  if (ch.x > 0.f) {
+    if (!(b > 0.f && disc >= 0.f)) return kInf;
+    const float q = b + __builtin_amdgcn_sqrtf(disc);
+    ts0 = ch.x * fast_rcp(q);
+    ts1 = q * fast_rcp(a);
+  } else {
+    // radially inside (so outside the slab): the side interval starts behind
+    ts0 = -kInf;
+    ts1 = a > 0.f ? (b + __builtin_amdgcn_sqrtf(fmaxf(disc, 0.f))) * fast_rcp(a) : kInf;
+  }
+  const float z1 = (w.z - ch.y) * inv_z, z2 = (w.z + ch.y) * inv_z;
+  const float tn = fmaxf(ts0, fminf(z1, z2));
+  const float tf = fminf(ts1, fmaxf(z1, z2));
   return (tn <= tf && tn >= 0.f) ? tn : kInf;
 }
 
@@ -134,13 +163,14 @@ __device__ __forceinline__ Rot agent_rot(const float* s, int A, int i) {
   return R;
 }
 
-// Work counters written per agent and wavefront by the WORK variant.
-enum { kWorkRays = 0, kWorkSph, kWorkBox, kWorkAgt, kWorkTiles, kWorkCone, kWorkN };
+// Work counters written per agent and wavefront by the WORK variant
+// (ray-cylinder tests last, after the cone tests).
+enum { kWorkRays = 0, kWorkSph, kWorkBox, kWorkAgt, kWorkTiles, kWorkCone, kWorkCyl, kWorkN };
 
 // An agent's environment staged in LDS (origin-relative primitives, cone
 // terms) with the values every tile of every sensor of that agent needs.
 struct AgentStage {
-  int i, ns, nb, np;
+  int i, ns, nb, nc, np;
   f3 o;
   Rot R;
   bool has_room, inside;
@@ -149,8 +179,8 @@ struct AgentStage {
 
 // Stages agent i's environment with the whole workgroup (256 threads); LDS
 // is re-staged on entry, so consecutive calls from one workgroup (the
-// persistent rollout kernel) are safe.
-template <bool ROT>
+// persistent rollout kernel) are safe. CYL: the scene may hold cylinders.
+template <bool ROT, bool CYL>
 __device__ __forceinline__ AgentStage stage_agent(const SceneDev& sc, const float* __restrict__ s, int A, int i,
                                                   RenderLds& L) {
   const int tid = threadIdx.x;
@@ -161,12 +191,17 @@ __device__ __forceinline__ AgentStage stage_agent(const SceneDev& sc, const floa
 
   const int s0 = sc.sph_off[env], ns = sc.sph_off[env + 1] - s0;
   const int b0 = sc.box_off[env], nb = sc.box_off[env + 1] - b0;
+  int c0 = 0, nc = 0;
+  if (CYL && sc.cyl_off) {  // CYL variants also serve scenes without cylinders
+    c0 = sc.cyl_off[env];
+    nc = sc.cyl_off[env + 1] - c0;
+  }
   int a0 = 0, na = 0;
   if (sc.agents_visible) {
     a0 = sc.agent_off[env];
     na = sc.agent_off[env + 1] - a0;
   }
-  const int np = ns + nb + na;
+  const int nsbc = ns + nb + nc, np = nsbc + na;
   if (tid == 0) *L.flag = 0;
   __syncthreads();
   bool ins = false;
@@ -193,8 +228,19 @@ __device__ __forceinline__ AgentStage stage_agent(const SceneDev& sc, const floa
       L.pc[k] = cp.c;
       L.pd[k] = cp.d;
       ins |= (lo.x < 0.f && hi.x > 0.f && lo.y < 0.f && hi.y > 0.f && lo.z < 0.f && hi.z > 0.f);
+    } else if (CYL && k < nsbc) {
+      const float* y = sc.cyl + (size_t)(c0 + k - ns - nb) * 5;
+      const f3 w = mk3(y[0] - o.x, y[1] - o.y, y[2] - o.z);
+      const float r2 = y[3] * y[3];
+      const float C = w.x * w.x + w.y * w.y - r2;
+      L.pa[k] = make_float4(w.x, w.y, w.z, r2);
+      L.pb[k] = make_float4(C, y[4], 0.f, 0.f);
+      const ConePrim cp = cone_prep(w, sqrtf(r2 + y[4] * y[4]));
+      L.pc[k] = cp.c;
+      L.pd[k] = cp.d;
+      ins |= C < 0.f && fabsf(w.z) < y[4];
     } else {
-      const int j = a0 + (k - ns - nb);
+      const int j = a0 + (k - nsbc);
       if (j == i) {
         L.pa[k] = make_float4(0.f, 0.f, 0.f, -1.f);
         L.pb[k] = make_float4(1.f, 0.f, 0.f, 0.f);
@@ -230,6 +276,7 @@ __device__ __forceinline__ AgentStage stage_agent(const SceneDev& sc, const floa
   st.i = i;
   st.ns = ns;
   st.nb = nb;
+  st.nc = nc;
   st.np = np;
   st.o = o;
   st.R = R;
@@ -241,17 +288,19 @@ __device__ __forceinline__ AgentStage stage_agent(const SceneDev& sc, const floa
 }
 
 // Renders tiles [tile_begin, tile_end) of one sensor of a staged agent with
-// the whole workgroup. The WORK variant also writes, per wavefront, the rays
-// it cast and the ray-primitive tests and tile-cone tests it ran to
+// the whole workgroup. CYL: the scene may hold cylinders (without, the
+// culling pass sorts survivors into three categories instead of four). The
+// WORK variant also writes, per wavefront, the rays it cast and the
+// ray-primitive tests and tile-cone tests it ran to
 // work[(i * 4 + wave) * kWorkN + c].
-template <bool ROT, bool CULL, bool WORK = false>
+template <bool ROT, bool CULL, bool CYL, bool WORK = false>
 __device__ __forceinline__ void render_tiles(const AgentStage& ag, const SensorDev& sen, RenderLds& L,
                                              int tile_begin, int tile_end, float* __restrict__ out,
                                              int* __restrict__ rec, int out_ld, float out_scale,
                                              float* __restrict__ term, float beta, float d_safe,
                                              int* __restrict__ work = nullptr) {
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int i = ag.i, ns = ag.ns, nb = ag.nb, np = ag.np;
+  const int i = ag.i, ns = ag.ns, nb = ag.nb, nc = CYL ? ag.nc : 0, np = ag.np;
   const Rot& R = ag.R;
   const bool has_room = ag.has_room, inside = ag.inside;
   const f3 rlo = ag.rlo, rhi = ag.rhi;
@@ -270,7 +319,7 @@ __device__ __forceinline__ void render_tiles(const AgentStage& ag, const SensorD
   const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   float tacc = 0.f;  // optional per-agent sum of softplus(beta (d_safe - value))
   const float inv_beta = term ? 1.0f / beta : 0.f;
-  int wk[kWorkN] = {0, 0, 0, 0, 0, 0};
+  int wk[kWorkN] = {0, 0, 0, 0, 0, 0, 0};
 
   // the next tile's ray index and direction are loaded while this tile is
   // processed (ray index two tiles ahead, direction one tile ahead)
@@ -291,28 +340,32 @@ __device__ __forceinline__ void render_tiles(const AgentStage& ag, const SensorD
       }
       continue;
     }
-    int ks = ns, kb = nb, nk = np;
+    int ks = ns, kb = nb, kc = nc, nk = np;
     if (CULL) {
       const float4 ca = L.ax[tile - tile_begin];
       const float4 cb = sen.cone_b[tile];
       const f3 ax = mk3(ca.x, ca.y, ca.z);
-      int cnt = 0, cs = 0, cbx = 0;
+      int cnt = 0, cs = 0, cbx = 0, ccy = 0;
       for (int base = 0; base < np; base += 64) {
         const int k = base + lane;
         const bool keep = (k < np) && cone_keep(L.pc[k], L.pd[k], ax, ca.w, cb.x, cb.y);
         const unsigned long long m = __ballot(keep);
-        // lanes of this chunk holding spheres / spheres or boxes (uniform)
-        const int rs = ns - base, rsb = ns + nb - base;
+        // lanes of this chunk holding spheres / spheres or boxes / spheres,
+        // boxes or cylinders (uniform)
+        const int rs = ns - base, rsb = ns + nb - base, rsbc = ns + nb + nc - base;
         const unsigned long long ls = rs >= 64 ? ~0ull : (rs <= 0 ? 0ull : (1ull << rs) - 1ull);
         const unsigned long long lsb = rsb >= 64 ? ~0ull : (rsb <= 0 ? 0ull : (1ull << rsb) - 1ull);
+        const unsigned long long lsbc = rsbc >= 64 ? ~0ull : (rsbc <= 0 ? 0ull : (1ull << rsbc) - 1ull);
         if (keep) list[cnt + __popcll(m & below)] = (short)k;
         cnt += __popcll(m);
         cs += __popcll(m & ls);
         cbx += __popcll(m & lsb & ~ls);
+        if (CYL) ccy += __popcll(m & lsbc & ~lsb);
       }
       __builtin_amdgcn_wave_barrier();
       ks = cs;
       kb = cbx;
+      kc = CYL ? ccy : 0;
       nk = cnt;
     }
     if (WORK) {
@@ -320,7 +373,8 @@ __device__ __forceinline__ void render_tiles(const AgentStage& ag, const SensorD
       wk[kWorkRays] += nrt;
       wk[kWorkSph] += nrt * ks;
       wk[kWorkBox] += nrt * kb;
-      wk[kWorkAgt] += nrt * (nk - ks - kb);
+      if (CYL) wk[kWorkCyl] += nrt * kc;
+      wk[kWorkAgt] += nrt * (nk - ks - kb - kc);
       wk[kWorkTiles] += 1;
       wk[kWorkCone] += CULL ? np : 0;
     }
@@ -345,7 +399,17 @@ __device__ __forceinline__ void render_tiles(const AgentStage& ag, const SensorD
         id = k;
       }
     }
-    for (int j = ks + kb; j < nk; ++j) {
+    if (CYL)
+      for (int j = ks + kb; j < ks + kb + kc; ++j) {
+        const int k = CULL ? list[j] : j;
+        const float4 pb = L.pb[k];
+        const float t = cylinder_t(d, inv.z, L.pa[k], make_float2(pb.x, pb.y));
+        if (t < best) {
+          best = t;
+          id = k;
+        }
+      }
+    for (int j = ks + kb + kc; j < nk; ++j) {
       const int k = CULL ? list[j] : j;
       const float t = sphere_t(d, L.pa[k], L.pb[k].x);
       if (t < best) {
@@ -392,7 +456,7 @@ __device__ __forceinline__ void render_tiles(const AgentStage& ag, const SensorD
 
 
 // Stage + render of one sensor (the launch-per-op render kernels).
-template <bool ROT, bool CULL, bool WORK = false>
+template <bool ROT, bool CULL, bool CYL, bool WORK = false>
 __device__ __forceinline__ void render_one_agent(const SceneDev& sc, const SensorDev& sen,
                                                  const float* __restrict__ s, int A, int i,
                                                  int tile_begin, int tile_end, float* __restrict__ out,
@@ -400,8 +464,8 @@ __device__ __forceinline__ void render_one_agent(const SceneDev& sc, const Senso
                                                  float* __restrict__ term, float beta, float d_safe,
                                                  void* smem, int* __restrict__ work = nullptr) {
   RenderLds L = carve(smem, sc.max_prims > 0 ? sc.max_prims : 1);
-  const AgentStage ag = stage_agent<ROT>(sc, s, A, i, L);
-  render_tiles<ROT, CULL, WORK>(ag, sen, L, tile_begin, tile_end, out, rec, out_ld, out_scale, term, beta,
+  const AgentStage ag = stage_agent<ROT, CYL>(sc, s, A, i, L);
+  render_tiles<ROT, CULL, CYL, WORK>(ag, sen, L, tile_begin, tile_end, out, rec, out_ld, out_scale, term, beta,
                                 d_safe, work);
 }
 
@@ -422,6 +486,15 @@ __device__ __forceinline__ float collide_one(const SceneDev& sc, const float* __
     const float ex = fmaxf(qx, 0.f), ey = fmaxf(qy, 0.f), ez = fmaxf(qz, 0.f);
     md = fminf(md, sqrtf(ex * ex + ey * ey + ez * ez) + fminf(fmaxf(fmaxf(qx, qy), qz), 0.f));
   }
+  if (sc.cyl_off)
+    for (int k = sc.cyl_off[env]; k < sc.cyl_off[env + 1]; ++k) {
+      // capped cylinder: radial and axial excess, exterior norm + interior max
+      const float* y = sc.cyl + (size_t)k * 5;
+      const float wx = p.x - y[0], wy = p.y - y[1];
+      const float qr = sqrtf(wx * wx + wy * wy) - y[3], qz = fabsf(p.z - y[2]) - y[4];
+      const float er = fmaxf(qr, 0.f), ez = fmaxf(qz, 0.f);
+      md = fminf(md, sqrtf(er * er + ez * ez) + fminf(fmaxf(qr, qz), 0.f));
+    }
   if (sc.room) {
     const float* rm = sc.room + (size_t)env * 6;
     md = fminf(md, fminf(fminf(fminf(p.x - rm[0], rm[3] - p.x), fminf(p.y - rm[1], rm[4] - p.y)),

@@ -81,6 +81,22 @@ constexpr bool rotates_m() {
   return M == SIM_RB13 || M == SIM_NOMINAL13;
 }
 
+// One agent work item: stage the agent's env, then its tiles [w.z, w.w) of
+// the combined camera-then-LiDAR tile range (one copy of the tile loop for
+// both sensors).
+template <bool ROT, bool CULL, bool CYL>
+__device__ __forceinline__ void agent_item(const RolloutArgs& g, int4 w, RenderLds& L) {
+  const AgentStage ag = stage_agent<ROT, CYL>(g.sc, g.s, g.A, w.y, L);
+  const int nc = g.depth ? g.cam.n_tiles : 0;
+  for (int part = 0; part < 2; ++part) {
+    const int b = part ? max(w.z, nc) - nc : w.z, e = part ? w.w - nc : min(w.w, nc);
+    if (b >= e) continue;
+    const SensorDev& sen = part ? g.lidar : g.cam;
+    render_tiles<ROT, CULL, CYL>(ag, sen, L, b, e, part ? g.lidar_out : g.depth, nullptr, sen.n_rays, 1.f,
+                                 nullptr, 1.f, 0.f);
+  }
+}
+
 template <int M, int I, bool CULL>
 __global__ __launch_bounds__(256, 6) void rollout_fused_kernel(RolloutArgs g) {
   extern __shared__ float4 smem_f4[];
@@ -97,16 +113,12 @@ __global__ __launch_bounds__(256, 6) void rollout_fused_kernel(RolloutArgs g) {
     } else {
       constexpr bool ROT = rotates_m<M>();
       RenderLds L = carve(smem_f4, g.sc.max_prims > 0 ? g.sc.max_prims : 1);
-      const AgentStage ag = stage_agent<ROT>(g.sc, g.s, g.A, w.y, L);
-      const int nc = g.depth ? g.cam.n_tiles : 0;
-      // one copy of the tile loop for both sensors
-      for (int part = 0; part < 2; ++part) {
-        const int b = part ? max(w.z, nc) - nc : w.z, e = part ? w.w - nc : min(w.w, nc);
-        if (b >= e) continue;
-        const SensorDev& sen = part ? g.lidar : g.cam;
-        render_tiles<ROT, CULL>(ag, sen, L, b, e, part ? g.lidar_out : g.depth, nullptr, sen.n_rays, 1.f,
-                                nullptr, 1.f, 0.f);
-      }
+      // uniform branch: scenes without cylinders keep the three-category
+      // staging and tile loop
+      if (g.sc.cyl_off)
+        agent_item<ROT, CULL, true>(g, w, L);
+      else
+        agent_item<ROT, CULL, false>(g, w, L);
     }
   }
 }
@@ -210,9 +222,10 @@ static int build_items(sim_handle* h, RolloutPlan* p) {
   std::vector<std::pair<double, int4>> items;
   const auto& so = h->host_sph_off;
   const auto& bo = h->host_box_off;
+  const auto& co = h->host_cyl_off;
   const auto& ao = h->host_agent_off;
   for (int e = 0; e < h->cfg.n_envs; ++e) {
-    int np = (so[e + 1] - so[e]) + (bo[e + 1] - bo[e]);
+    int np = (so[e + 1] - so[e]) + (bo[e + 1] - bo[e]) + (co.empty() ? 0 : co[e + 1] - co[e]);
     if (h->cfg.agents_visible) np += ao[e + 1] - ao[e];
     // combined tile index space: camera tiles, then LiDAR tiles
     const int nt = (h->cam.mem ? h->cam.dev.n_tiles : 0) + (h->lidar.mem ? h->lidar.dev.n_tiles : 0);
@@ -401,9 +414,9 @@ int sim_rollout_get_config(sim_handle* h, int32_t* tile_group, int32_t* blocks_p
 static std::string tune_key(const sim_handle* h, const char* arch) {
   const sim_config& c = h->cfg;
   char buf[512];
-  snprintf(buf, sizeof(buf), "%s|E%d|A%d|m%d|i%d|cam%dx%d|lidar%dx%d|sph%d|box%d|maxp%d|vis%d|cull%d|room%d", arch,
-           c.n_envs, c.n_agents, c.model, c.integrator, c.cam_w, c.cam_h, c.lidar_ch, c.lidar_az, h->n_sph,
-           h->n_box, h->scene.max_prims, c.agents_visible, c.fov_cull, h->scene.room ? 1 : 0);
+  snprintf(buf, sizeof(buf), "%s|E%d|A%d|m%d|i%d|cam%dx%d|lidar%dx%d|sph%d|box%d|cyl%d|maxp%d|vis%d|cull%d|room%d",
+           arch, c.n_envs, c.n_agents, c.model, c.integrator, c.cam_w, c.cam_h, c.lidar_ch, c.lidar_az,
+           h->n_sph, h->n_box, h->n_cyl, h->scene.max_prims, c.agents_visible, c.fov_cull, h->scene.room ? 1 : 0);
   return buf;
 }
 

@@ -265,6 +265,33 @@ static int check_csr(const std::vector<int32_t>& off, int total, const char* wha
   return SIM_OK;
 }
 
+// Per-env obstacle count (spheres + boxes + cylinders) against the limit, the
+// largest per-env primitive count including visible agents, and the render
+// kernel's LDS need for it against the device's limit.
+static int scene_max_prims(const char* fn, const sim_handle* h, const std::vector<int32_t>& so,
+                           const std::vector<int32_t>& bo, const std::vector<int32_t>& co,
+                           const std::vector<int32_t>& ao, int& maxp) {
+  const int E = h->cfg.n_envs;
+  maxp = 0;
+  for (int e = 0; e < E; ++e) {
+    int p = (so[e + 1] - so[e]) + (bo[e + 1] - bo[e]) + (co.empty() ? 0 : co[e + 1] - co[e]);
+    DA_REQUIRE(p <= SIM_MAX_PRIMS_PER_ENV,
+               "%s: env %d has %d primitives (spheres + boxes + cylinders; at most %d)", fn, e, p,
+               SIM_MAX_PRIMS_PER_ENV);
+    if (h->cfg.agents_visible) p += ao[e + 1] - ao[e];
+    maxp = std::max(maxp, p);
+  }
+  int dev = 0, lds_max = 0;
+  DA_HIP(hipGetDevice(&dev));
+  DA_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  const int nt = std::max(h->cam.mem ? h->cam.dev.n_tiles : 0, h->lidar.mem ? h->lidar.dev.n_tiles : 0);
+  const size_t need = render_lds_bytes(maxp > 0 ? maxp : 1, nt);
+  DA_REQUIRE(need <= (size_t)lds_max,
+             "%s: %d primitives in one env and %d sensor tiles need %zu B of LDS per "
+             "workgroup (device: %d)", fn, maxp, nt, need, lds_max);
+  return SIM_OK;
+}
+
 int sim_set_scene(sim_handle* h, const int32_t* sph_off, const float* sph, int32_t n_sph,
                   const int32_t* box_off, const float* box, int32_t n_box, const float* room,
                   const int32_t* agent_off) {
@@ -290,23 +317,7 @@ int sim_set_scene(sim_handle* h, const int32_t* sph_off, const float* sph, int32
     for (int e = 0; e <= E; ++e) ao[e] = e;
   }
   int maxp = 0;
-  for (int e = 0; e < E; ++e) {
-    int p = (so[e + 1] - so[e]) + (bo[e + 1] - bo[e]);
-    DA_REQUIRE(p <= SIM_MAX_PRIMS_PER_ENV, "sim_set_scene: env %d has %d primitives (spheres + boxes; at most %d)",
-               e, p, SIM_MAX_PRIMS_PER_ENV);
-    if (h->cfg.agents_visible) p += ao[e + 1] - ao[e];
-    maxp = std::max(maxp, p);
-  }
-  {
-    int dev = 0, lds_max = 0;
-    DA_HIP(hipGetDevice(&dev));
-    DA_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    const int nt = std::max(h->cam.mem ? h->cam.dev.n_tiles : 0, h->lidar.mem ? h->lidar.dev.n_tiles : 0);
-    const size_t need = render_lds_bytes(maxp > 0 ? maxp : 1, nt);
-    DA_REQUIRE(need <= (size_t)lds_max,
-               "sim_set_scene: %d primitives in one env and %d sensor tiles need %zu B of LDS per "
-               "workgroup (device: %d)", maxp, nt, need, lds_max);
-  }
+  if ((rc = scene_max_prims("sim_set_scene", h, so, bo, {}, ao, maxp))) return rc;
   std::vector<int32_t> env_of(A);
   for (int e = 0; e < E; ++e)
     for (int j = ao[e]; j < ao[e + 1]; ++j) env_of[j] = e;
@@ -324,6 +335,8 @@ int sim_set_scene(sim_handle* h, const int32_t* sph_off, const float* sph, int32
   sc.sph = sph;
   sc.box_off = box_off;
   sc.box = box;
+  sc.cyl_off = nullptr;  // a new scene has no cylinders until sim_set_cylinders
+  sc.cyl = nullptr;
   sc.room = room;
   sc.agent_off = ao_dev;
   sc.agent_env = h->agent_env;
@@ -332,10 +345,38 @@ int sim_set_scene(sim_handle* h, const int32_t* sph_off, const float* sph, int32
   sc.max_prims = maxp;
   h->host_sph_off = so;
   h->host_box_off = bo;
+  h->host_cyl_off.clear();
   h->host_agent_off = ao;
   h->n_sph = n_sph;
   h->n_box = n_box;
+  h->n_cyl = 0;
   h->has_scene = true;
+  rollout_plan_free(h);  // work items depend on the scene
+  return SIM_OK;
+}
+
+int sim_set_cylinders(sim_handle* h, const int32_t* cyl_off, const float* cyl, int32_t n_cyl) {
+  DA_REQUIRE(h, "sim_set_cylinders: null handle");
+  DA_REQUIRE(h->has_scene, "sim_set_cylinders: scene not set");
+  DA_REQUIRE(n_cyl >= 0, "sim_set_cylinders: negative count");
+  std::vector<int32_t> co;
+  if (cyl_off) {
+    DA_REQUIRE(n_cyl == 0 || cyl, "sim_set_cylinders: cylinders pointer is null");
+    int rc = fetch_offsets(cyl_off, h->cfg.n_envs + 1, co);
+    if (rc) return rc;
+    if ((rc = check_csr(co, n_cyl, "cyl", SIM_MAX_PRIMS_PER_ENV))) return rc;
+  } else {
+    DA_REQUIRE(n_cyl == 0, "sim_set_cylinders: cyl_off is NULL but n_cyl = %d", n_cyl);
+  }
+  int maxp = 0;
+  int rc = scene_max_prims("sim_set_cylinders", h, h->host_sph_off, h->host_box_off, co, h->host_agent_off, maxp);
+  if (rc) return rc;
+  SceneDev& sc = h->scene;
+  sc.cyl_off = cyl_off;
+  sc.cyl = cyl_off ? cyl : nullptr;
+  sc.max_prims = maxp;
+  h->host_cyl_off = co;
+  h->n_cyl = n_cyl;
   rollout_plan_free(h);  // work items depend on the scene
   return SIM_OK;
 }

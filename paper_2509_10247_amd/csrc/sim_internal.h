@@ -17,8 +17,8 @@ struct sim_handle {
   int32_t* agent_env = nullptr;        // owned [A]
   int32_t* agent_off_owned = nullptr;  // owned [E+1] when the caller passes NULL
   const float* params = nullptr;       // caller's SoA [P][A]
-  std::vector<int32_t> host_sph_off, host_box_off, host_agent_off;
-  int n_sph = 0, n_box = 0;
+  std::vector<int32_t> host_sph_off, host_box_off, host_cyl_off, host_agent_off;
+  int n_sph = 0, n_box = 0, n_cyl = 0;
   bool has_scene = false;
   void* rollout = nullptr;             // uneven-batch rollout plan (rollout.hip)
 };

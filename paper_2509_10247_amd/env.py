@@ -64,9 +64,26 @@ class Env:
         _lib.sim_set_scene(self.h, k["sph_off"], k["sph"], n_sph, k["box_off"], k["box"], n_box,
                            k["room"], k["agent_off"])
         self._keep["scene"] = k
+        self._keep.pop("cylinders", None)
+
+    def set_cylinders(self, cyl_off, cyl):
+        """Vertical cylinders (cx, cy, cz, r, half-height) per env, CSR; None
+        removes them."""
+        if cyl_off is None:
+            _lib.sim_set_cylinders(self.h, None, None, 0)
+            self._keep.pop("cylinders", None)
+            return
+        k = dict(cyl_off=_dev(cyl_off, torch.int32),
+                 cyl=_dev(np.asarray(cyl, np.float32).reshape(-1, 5), torch.float32))
+        if k["cyl"].numel() == 0:
+            k["cyl"] = torch.zeros(1, 5, device="cuda")
+        _lib.sim_set_cylinders(self.h, k["cyl_off"], k["cyl"], int(np.asarray(cyl_off)[-1]))
+        self._keep["cylinders"] = k
 
     def set_scene_obj(self, scene):
         self.set_scene(scene.sph_off, scene.sph, scene.box_off, scene.box, scene.room, scene.agent_off)
+        if getattr(scene, "cyl_off", None) is not None:
+            self.set_cylinders(scene.cyl_off, scene.cyl)
 
     def set_params(self, params):
         p = _dev(params, torch.float32) if not torch.is_tensor(params) else params.contiguous()

@@ -166,7 +166,7 @@ def test_render_work_counter():
         e = _env(wk, fov_cull=cull)
         d, _, _, _ = e.render(s, depth=True)
         out = torch.empty_like(d)
-        work = torch.full((A, 4, 6), -1, dtype=torch.int32, device="cuda")
+        work = torch.full((A, 4, 7), -1, dtype=torch.int32, device="cuda")
         _lib.sim_render_work(e.h, 0, s, out, work)
         torch.cuda.synchronize()
         assert torch.equal(out, d)
@@ -177,7 +177,7 @@ def test_render_work_counter():
     rays = full[:, 0]
     assert set(rays.tolist()) <= {0, 3072}
     assert torch.equal(full[:, 1], rays * n_sph) and torch.equal(full[:, 2], rays * n_box)
-    assert (full[:, 3] == 0).all() and (full[:, 5] == 0).all()
+    assert (full[:, 3] == 0).all() and (full[:, 5] == 0).all() and (full[:, 6] == 0).all()
     cul = counts[True]
     assert torch.equal(cul[:, 0], rays)
     assert (cul[:, 1:4] <= full[:, 1:4]).all() and cul[:, 1].sum() < full[:, 1].sum()

@@ -306,6 +306,23 @@ def bptt(seed: int = 0, n_envs: int = 16384, T: int = 32, model: int = RB13) -> 
                     (64, 48, 90.0, 10.0), None, goal)
 
 
+def pillars(seed: int = 0, n_envs: int = 1024, T: int = 1, model: int = RB13, agents_per_env=None) -> Workload:
+    """Room as the rigid-body case with 16 spheres r U[0.3,1.2], 10 boxes
+    half-extent U[0.2,0.8] and 14 vertical cylinders (radius U[0.2,0.8],
+    half-height U[0.5,4.0], from short posts to floor-to-ceiling pillars) per
+    env; 64x48 camera max 10 m, LiDAR 16x360 max 20 m."""
+    rng = np.random.default_rng(seed)
+    ape = np.ones(n_envs, np.int64) if agents_per_env is None else np.asarray(agents_per_env, np.int64)
+    A = int(ape.sum())
+    p0 = start_positions(rng, A, ROOM_C2)
+    scene = make_scene(rng, n_envs, 16, 10, ROOM_C2, (0.3, 1.2), (0.2, 0.8), room=True, agents_per_env=ape,
+                       keepout=p0, n_cyl=14, cyl_r=(0.2, 0.8), cyl_h=(0.5, 4.0))
+    s0 = initial_state(rng, model, p0)
+    a = actions(rng, model, A, T)
+    return Workload(f"pillars_{n_envs}env", model, RK4, 0.01, T, scene, s0, params(rng, model, A), a,
+                    (64, 48, 90.0, 10.0), (16, 360, -15.0, 15.0, 20.0))
+
+
 def uneven(seed: int = 0, n_envs: int = 8192, T: int = 128) -> Workload:
     """Per-env obstacle count uniform in {0..256} (60/40 sphere/box), 1-8
     agents per env (r=0.15), room as the rigid-body case, RB13 RK4; LiDAR
