@@ -70,10 +70,14 @@ def lidar_dirs(ch: int, az: int, emin_deg: float, emax_deg: float):
     return d, torch.ones(d.shape[0], dtype=torch.float64)
 
 
-def world_rays(model, s: torch.Tensor, d_body: torch.Tensor):
-    """Origins [A, 3] and world directions [A, R, 3] for states [A, C]."""
+def world_rays(model, s: torch.Tensor, d_body: torch.Tensor, R=None):
+    """Origins [A, 3] and world directions [A, R, 3] for states [A, C]; R
+    [A, 3, 3], when given, is the attitude (the point-mass attitude rule)
+    and replaces the model's own."""
     o = s[:, 0:3]
-    if model in (dyn.RB13, dyn.NOMINAL13):
+    if R is not None:
+        d = torch.einsum("aij,rj->ari", R, d_body)
+    elif model in (dyn.RB13, dyn.NOMINAL13):
         R = dyn.quat_to_rot(s[:, 6:10])
         d = torch.einsum("aij,rj->ari", R, d_body)
     else:
@@ -356,9 +360,10 @@ def sensor_output(t, hid, zfac, max_range, frozen_cls=None):
 
 
 def render(model, ds: DenseScene, s, d_body, zfac, max_range, lanes=None,
-           agents_visible=False, frozen=None, chunk=16):
+           agents_visible=False, frozen=None, chunk=16, R=None):
     """Sensor image for every agent in `lanes`: returns (values [a, R],
-    records [a, R], cos_inc [a, R]). s is the full state [A_total, C]."""
+    records [a, R], cos_inc [a, R]). s is the full state [A_total, C]; R
+    [A_total, 3, 3] optionally overrides the attitude."""
     A = s.shape[0]
     if lanes is None:
         lanes = torch.arange(A)
@@ -366,7 +371,7 @@ def render(model, ds: DenseScene, s, d_body, zfac, max_range, lanes=None,
     vals, recs, coss = [], [], []
     for i in range(0, len(lanes), chunk):
         ln = lanes[i:i + chunk]
-        o, d = world_rays(model, s[ln], d_body)
+        o, d = world_rays(model, s[ln], d_body, None if R is None else R[ln])
         fz = None if frozen is None else frozen[i:i + chunk]
         t, hid, cs, _ = cast(ds, o, d, ln, all_pos, frozen=fz)
         v, r = sensor_output(t, hid, zfac, max_range, frozen_cls=fz)
@@ -377,26 +382,26 @@ def render(model, ds: DenseScene, s, d_body, zfac, max_range, lanes=None,
 
 
 def stable_rays(model, ds, s, d_body, zfac, max_range, lanes=None, agents_visible=False,
-                eps=1e-5, min_cos=0.05):
+                eps=1e-5, min_cos=0.05, R=None):
     """Rays whose record is unchanged when the origin moves by +-eps along
     each axis and the direction tilts by +-eps rad, and whose hit (if any)
     is not grazing (|n . d| >= min_cos). Rays near a silhouette, an occlusion
     boundary or at grazing incidence have an ill-conditioned depth, so an FP32
     result is compared with the FP64 one only on stable rays."""
     s = s.detach()
-    base_v, base_r, base_c = render(model, ds, s, d_body, zfac, max_range, lanes, agents_visible)
+    base_v, base_r, base_c = render(model, ds, s, d_body, zfac, max_range, lanes, agents_visible, R=R)
     ok = torch.ones_like(base_r, dtype=torch.bool)
     ok &= ~((base_r >= 0) & (base_c.abs() < min_cos))
     for axis in range(3):
         for sgn in (-1.0, 1.0):
             sp = s.clone()
             sp[:, axis] += sgn * eps
-            _, r, _ = render(model, ds, sp, d_body, zfac, max_range, lanes, agents_visible)
+            _, r, _ = render(model, ds, sp, d_body, zfac, max_range, lanes, agents_visible, R=R)
             ok &= r == base_r
             db = d_body.clone()
             db[:, axis] += sgn * eps
             db = db / db.norm(dim=1, keepdim=True)
-            _, r, _ = render(model, ds, s, db, zfac, max_range, lanes, agents_visible)
+            _, r, _ = render(model, ds, s, db, zfac, max_range, lanes, agents_visible, R=R)
             ok &= r == base_r
     return ok, base_v, base_r
 
