@@ -73,10 +73,13 @@ def lidar_dirs(ch: int, az: int, emin_deg: float, emax_deg: float):
 def world_rays(model, s: torch.Tensor, d_body: torch.Tensor, R=None):
     """Origins [A, 3] and world directions [A, R, 3] for states [A, C]; R
     [A, 3, 3], when given, is the attitude (the point-mass attitude rule)
-    and replaces the model's own."""
+    and replaces the model's own. The attitude is a rotation: an override
+    that is one only up to rounding (an FP32 R) still gives unit world
+    directions, which the ray-primitive roots below assume."""
     o = s[:, 0:3]
     if R is not None:
         d = torch.einsum("aij,rj->ari", R, d_body)
+        d = d / d.norm(dim=-1, keepdim=True)
     elif model in (dyn.RB13, dyn.NOMINAL13):
         R = dyn.quat_to_rot(s[:, 6:10])
         d = torch.einsum("aij,rj->ari", R, d_body)

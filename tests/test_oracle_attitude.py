@@ -140,4 +140,9 @@ def test_render_override_equals_rigid_body_render():
     db, zf = sen.camera_dirs(16, 12, 90.0)
     v_rb, r_rb, _ = sen.render(dyn.RB13, ds, s13, db, zf, 10.0)
     v_pm, r_pm, _ = sen.render(dyn.PM6, ds, s13[:, :6], db, zf, 10.0, R=R)
-    assert torch.equal(v_rb, v_pm) and torch.equal(r_rb, r_pm)
+    # equal up to the rounding of the override's direction normalisation
+    assert torch.allclose(v_rb, v_pm, rtol=0, atol=1e-12) and torch.equal(r_rb, r_pm)
+    # a rotation scaled by 1 + 1e-6 (an attitude that is a rotation only up
+    # to rounding) casts the same unit rays
+    v_sc, r_sc, _ = sen.render(dyn.PM6, ds, s13[:, :6], db, zf, 10.0, R=R * (1 + 1e-6))
+    assert torch.allclose(v_sc, v_pm, rtol=0, atol=1e-12) and torch.equal(r_sc, r_pm)
