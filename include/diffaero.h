@@ -153,6 +153,47 @@ int sim_step(sim_handle* h, const float* s_in, const float* a, float* s_out, uin
 int sim_render(sim_handle* h, const float* s, float* depth, float* lidar, int32_t* hit_cam,
                int32_t* hit_lidar, void* stream);
 
+/* Point-mass attitude rule (Sec. III-B): for SIM_PM6 / SIM_PM9 / SIM_PMD,
+ * body z along the collective thrust f (the action for SIM_PM6, the
+ * acceleration state, components 6..8, for SIM_PM9 and SIM_PMD) and body x
+ * along the horizontal projection of an exponential moving average of the
+ * velocity: ema <- (1 - alpha) ema + alpha v (in place, SoA [3][A]), then
+ * x_B = normalise(y_c x z_B) with y_c = (-h_y, h_x, 0), h the unit horizontal
+ * direction of ema, and y_B = z_B x x_B. Degenerate inputs: |f|^2 <= 1e-12
+ * gives z_B = e_z, |ema_xy|^2 <= 1e-12 gives h = e_x, |y_c x z_B|^2 <= 1e-12
+ * gives x_B = normalise(h - (h . z_B) z_B). R: out, row-major [9][A]
+ * (R[r][c] at (3r + c) A + i; columns x_B, y_B, z_B, body -> world).
+ * a may be NULL except for SIM_PM6. SIM_EINVAL for other models or alpha
+ * outside (0, 1]. */
+int sim_pm_attitude(sim_handle* h, const float* s, const float* a, float* ema, float alpha, float* R,
+                    void* stream);
+
+/* Adjoint of sim_pm_attitude at (s, a, ema_prev) (the EMA before the
+ * update): with g_R = dL/dR [9][A] and g_ema_next = dL/d(updated ema) [3][A]
+ * (nullable), adds the pull-backs to g_s [C][A] (velocity rows; acceleration
+ * rows for SIM_PM9 / SIM_PMD), g_a [3][A] (SIM_PM6's thrust; nullable) and
+ * g_ema_prev [3][A] (nullable). Degenerate branches are constants (no
+ * gradient through the fallback's choice). */
+int sim_pm_attitude_backward(sim_handle* h, const float* s, const float* a, const float* ema_prev, float alpha,
+                             const float* g_R, const float* g_ema_next, float* g_s, float* g_a,
+                             float* g_ema_prev, void* stream);
+
+/* sim_render with the attitude given by R (row-major [9][A], as written by
+ * sim_pm_attitude) instead of the state's quaternion: the body-frame rays
+ * are rotated by R for every model (the point-mass attitude rule gives the
+ * point-mass models' sensors their orientation, Sec. III-B). Same outputs,
+ * records and errors as sim_render; R is only read. */
+int sim_render_oriented(sim_handle* h, const float* s, const float* R, float* depth, float* lidar,
+                        int32_t* hit_cam, int32_t* hit_lidar, void* stream);
+
+/* Adjoint of sim_render_oriented through the recorded hits (as in
+ * sim_step_backward's render part): adds d(sum g . image)/dp to g_s's
+ * position rows and d(.)/dR to g_R [9][A] (nullable). g_depth / g_lidar
+ * nullable, each with its hit records. */
+int sim_render_oriented_backward(sim_handle* h, const float* s, const float* R, const float* g_depth,
+                                 const float* g_lidar, const int32_t* hit_cam, const int32_t* hit_lidar,
+                                 float* g_s, float* g_R, void* stream);
+
 /* Work count of one sensor's render at s (diagnostics for the roofline; the
  * exclusion of obstacles outside the field of view is Sec. III-B): renders
  * sensor 0 (camera) or 1 (LiDAR) into out ([A][n_rays], as sim_render) and

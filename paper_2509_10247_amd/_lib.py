@@ -62,6 +62,10 @@ _SIGS = {
     "sim_imu": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, ctypes.POINTER(ImuConfig), ctypes.c_uint64,
                         c_int64, c_void_p, c_void_p]),
     "sim_imu_backward": (c_int, [c_void_p] * 7),
+    "sim_pm_attitude": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_float, c_void_p, c_void_p]),
+    "sim_pm_attitude_backward": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_float] + [c_void_p] * 6),
+    "sim_render_oriented": (c_int, [c_void_p] * 8),
+    "sim_render_oriented_backward": (c_int, [c_void_p] * 10),
     "bptt_create": (c_int, [c_void_p, ctypes.POINTER(BpttConfig), ctypes.POINTER(c_void_p)]),
     "bptt_destroy": (c_int, [c_void_p]),
     "bptt_workspace_bytes": (c_int64, [c_void_p]),
@@ -203,6 +207,28 @@ def sim_render_work(h, sensor, s, out, work):
     """work: int32 [A][4][7] (see WORK_FIELDS)."""
     _call("sim_render_work", h, int(sensor), ptr(s, torch.float32), ptr(out, torch.float32),
           ptr(work, torch.int32), stream())
+
+
+def sim_pm_attitude(h, s, a, ema, alpha, R):
+    _call("sim_pm_attitude", h, ptr(s, torch.float32), ptr(a, torch.float32), ptr(ema, torch.float32),
+          float(alpha), ptr(R, torch.float32), stream())
+
+
+def sim_pm_attitude_backward(h, s, a, ema_prev, alpha, g_R, g_ema_next, g_s, g_a=None, g_ema_prev=None):
+    _call("sim_pm_attitude_backward", h, ptr(s, torch.float32), ptr(a, torch.float32),
+          ptr(ema_prev, torch.float32), float(alpha), ptr(g_R, torch.float32), ptr(g_ema_next, torch.float32),
+          ptr(g_s, torch.float32), ptr(g_a, torch.float32), ptr(g_ema_prev, torch.float32), stream())
+
+
+def sim_render_oriented(h, s, R, depth=None, lidar=None, hit_cam=None, hit_lidar=None):
+    _call("sim_render_oriented", h, ptr(s, torch.float32), ptr(R, torch.float32), ptr(depth, torch.float32),
+          ptr(lidar, torch.float32), ptr(hit_cam, torch.int32), ptr(hit_lidar, torch.int32), stream())
+
+
+def sim_render_oriented_backward(h, s, R, g_depth, g_lidar, hit_cam, hit_lidar, g_s, g_R=None):
+    _call("sim_render_oriented_backward", h, ptr(s, torch.float32), ptr(R, torch.float32),
+          ptr(g_depth, torch.float32), ptr(g_lidar, torch.float32), ptr(hit_cam, torch.int32),
+          ptr(hit_lidar, torch.int32), ptr(g_s, torch.float32), ptr(g_R, torch.float32), stream())
 
 
 def sim_collide(h, s, flags=None, min_dist=None):

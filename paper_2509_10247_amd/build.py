@@ -16,7 +16,8 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libdiffaero.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["sim.hip", "dynamics.hip", "render.hip", "gemm.hip", "bptt.hip", "surrogate.hip", "rollout.hip", "imu.hip"]
+SOURCES = ["sim.hip", "dynamics.hip", "render.hip", "gemm.hip", "bptt.hip", "surrogate.hip", "rollout.hip", "imu.hip",
+           "attitude.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -33,6 +33,12 @@ struct SceneDev {
   float agent_radius = 0.15f;
   int agents_visible = 0;
   int max_prims = 0;              // max over envs of spheres + boxes + cylinders + visible agents
+  // per-call attitude override (the point-mass attitude rule): R row-major
+  // [9][A] (R[r][c] at (3r + c) A + i) replaces the state's quaternion, and
+  // the render adjoint adds dL/dR to att_grad [9][A] (nullable) instead of
+  // pulling it back to q
+  const float* att = nullptr;
+  float* att_grad = nullptr;
 };
 
 int state_dim(int model);

@@ -107,9 +107,17 @@ __global__ __launch_bounds__(256, 5) void render_vjp_kernel(SceneDev sc, SensorD
   const f3 o = mk3(s[i], s[(size_t)A + i], s[2 * (size_t)A + i]);
   Rot R32;
   if (ROT) {
-    double qn[4], inv_n, R[3][3];
-    agent_frame64(s, A, i, qn, inv_n);
-    rot64(qn, R);
+    double R[3][3];
+    if (sc.att) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) R[a][c] = sc.att[(size_t)(3 * a + c) * A + i];
+    } else {
+      double qn[4], inv_n;
+      agent_frame64(s, A, i, qn, inv_n);
+      rot64(qn, R);
+    }
     #pragma unroll
     for (int a = 0; a < 3; ++a)
       for (int c = 0; c < 3; ++c) R32.m[a][c] = (float)R[a][c];
@@ -353,7 +361,12 @@ __global__ __launch_bounds__(256, 5) void render_vjp_kernel(SceneDev sc, SensorD
     g_s[i] += (float)tot[0];
     g_s[(size_t)A + i] += (float)tot[1];
     g_s[2 * (size_t)A + i] += (float)tot[2];
-    if (ROT) {
+    if (ROT && sc.att) {
+      // attitude override: dL/dR itself is the result
+      if (sc.att_grad)
+#pragma unroll
+        for (int a = 0; a < 9; ++a) sc.att_grad[(size_t)a * A + i] += (float)tot[3 + a];
+    } else if (ROT) {
       // dL/dR -> dL/dqn (derivative of the quadratic form at the unit qn),
       // then through qn = q/|q|
       double G[3][3];

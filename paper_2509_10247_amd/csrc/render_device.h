@@ -163,6 +163,16 @@ __device__ __forceinline__ Rot agent_rot(const float* s, int A, int i) {
   return R;
 }
 
+// Attitude of agent i from a row-major [9][A] override.
+__device__ __forceinline__ Rot att_rot(const float* __restrict__ att, int A, int i) {
+  Rot R;
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) R.m[r][c] = att[(size_t)(3 * r + c) * A + i];
+  return R;
+}
+
 // Work counters written per agent and wavefront by the WORK variant
 // (ray-cylinder tests last, after the cone tests).
 enum { kWorkRays = 0, kWorkSph, kWorkBox, kWorkAgt, kWorkTiles, kWorkCone, kWorkCyl, kWorkN };
@@ -187,7 +197,7 @@ __device__ __forceinline__ AgentStage stage_agent(const SceneDev& sc, const floa
   __syncthreads();  // previous use of the LDS by this workgroup is complete
   const int env = sc.agent_env[i];
   const f3 o = mk3(s[i], s[(size_t)A + i], s[2 * (size_t)A + i]);
-  const Rot R = agent_rot<ROT>(s, A, i);
+  const Rot R = (ROT && sc.att) ? att_rot(sc.att, A, i) : agent_rot<ROT>(s, A, i);
 
   const int s0 = sc.sph_off[env], ns = sc.sph_off[env + 1] - s0;
   const int b0 = sc.box_off[env], nb = sc.box_off[env + 1] - b0;

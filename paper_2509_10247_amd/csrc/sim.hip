@@ -435,6 +435,52 @@ int sim_render(sim_handle* h, const float* s, float* depth, float* lidar, int32_
   return SIM_OK;
 }
 
+int sim_render_oriented(sim_handle* h, const float* s, const float* R, float* depth, float* lidar,
+                        int32_t* hit_cam, int32_t* hit_lidar, void* stream) {
+  DA_REQUIRE(h && s && R, "sim_render_oriented: null argument");
+  DA_REQUIRE(h->has_scene, "sim_render_oriented: scene not set");
+  SceneDev sc = h->scene;
+  sc.att = R;
+  if (depth || hit_cam) {
+    DA_REQUIRE(h->cam.mem, "sim_render_oriented: no camera configured");
+    DA_REQUIRE(depth, "sim_render_oriented: hit_cam needs depth");
+    int rc = launch_render(sc, h->cam.dev, true, h->cfg.fov_cull != 0, s, h->cfg.n_agents, depth, hit_cam,
+                           h->cam.dev.n_rays, 1.0f, as_stream(stream));
+    if (rc) return rc;
+  }
+  if (lidar || hit_lidar) {
+    DA_REQUIRE(h->lidar.mem, "sim_render_oriented: no LiDAR configured");
+    DA_REQUIRE(lidar, "sim_render_oriented: hit_lidar needs lidar");
+    int rc = launch_render(sc, h->lidar.dev, true, h->cfg.fov_cull != 0, s, h->cfg.n_agents, lidar, hit_lidar,
+                           h->lidar.dev.n_rays, 1.0f, as_stream(stream));
+    if (rc) return rc;
+  }
+  return SIM_OK;
+}
+
+int sim_render_oriented_backward(sim_handle* h, const float* s, const float* R, const float* g_depth,
+                                 const float* g_lidar, const int32_t* hit_cam, const int32_t* hit_lidar, float* g_s,
+                                 float* g_R, void* stream) {
+  DA_REQUIRE(h && s && R && g_s, "sim_render_oriented_backward: null argument");
+  DA_REQUIRE(h->has_scene, "sim_render_oriented_backward: scene not set");
+  DA_REQUIRE(!g_depth || (hit_cam && h->cam.mem), "sim_render_oriented_backward: g_depth needs hit_cam");
+  DA_REQUIRE(!g_lidar || (hit_lidar && h->lidar.mem), "sim_render_oriented_backward: g_lidar needs hit_lidar");
+  SceneDev sc = h->scene;
+  sc.att = R;
+  sc.att_grad = g_R;
+  hipStream_t st = as_stream(stream);
+  if (g_depth) {
+    int rc = launch_render_vjp(sc, h->cam.dev, true, s, h->cfg.n_agents, g_depth, h->cam.dev.n_rays, hit_cam, g_s, st);
+    if (rc) return rc;
+  }
+  if (g_lidar) {
+    int rc = launch_render_vjp(sc, h->lidar.dev, true, s, h->cfg.n_agents, g_lidar, h->lidar.dev.n_rays, hit_lidar,
+                               g_s, st);
+    if (rc) return rc;
+  }
+  return SIM_OK;
+}
+
 int sim_render_work(sim_handle* h, int32_t sensor, const float* s, float* out, int32_t* work,
                     void* stream) {
   DA_REQUIRE(h && s && out && work, "sim_render_work: null argument");

@@ -131,6 +131,40 @@ class Env:
         _lib.sim_imu_backward(self.h, s, a, g_out, g_s, g_a)
         return g_s, g_a
 
+    def pm_attitude(self, s, a, ema, alpha):
+        """Point-mass attitude R [9, A] (row-major 3x3 per agent); ema [3, A]
+        is updated in place."""
+        R = torch.empty(9, self.n_agents, device="cuda")
+        _lib.sim_pm_attitude(self.h, s, a, ema, alpha, R)
+        return R
+
+    def pm_attitude_backward(self, s, a, ema_prev, alpha, g_R, g_ema_next=None):
+        """(g_s, g_a, g_ema_prev) of the attitude update at the previous EMA."""
+        g_s = torch.zeros_like(s)
+        g_a = torch.zeros(3, self.n_agents, device="cuda")
+        g_e = torch.zeros(3, self.n_agents, device="cuda")
+        _lib.sim_pm_attitude_backward(self.h, s, a, ema_prev, alpha, g_R, g_ema_next, g_s, g_a, g_e)
+        return g_s, g_a, g_e
+
+    def render_oriented(self, s, R, depth=True, lidar=False, records=True):
+        A = self.n_agents
+        d = hd = l = hl = None
+        if depth and self.cam:
+            d = torch.empty(A, self.cam[1], self.cam[0], device="cuda")
+            hd = torch.empty(A, self.cam[1], self.cam[0], device="cuda", dtype=torch.int32) if records else None
+        if lidar and self.lidar:
+            l = torch.empty(A, self.lidar[0], self.lidar[1], device="cuda")
+            hl = torch.empty(A, self.lidar[0], self.lidar[1], device="cuda", dtype=torch.int32) if records else None
+        _lib.sim_render_oriented(self.h, s, R, d, l, hd, hl)
+        return d, hd, l, hl
+
+    def render_oriented_backward(self, s, R, g_depth=None, g_lidar=None, hit_cam=None, hit_lidar=None):
+        """(g_s, g_R): the image gradients pulled back to positions and R."""
+        g_s = torch.zeros_like(s)
+        g_R = torch.zeros(9, self.n_agents, device="cuda")
+        _lib.sim_render_oriented_backward(self.h, s, R, g_depth, g_lidar, hit_cam, hit_lidar, g_s, g_R)
+        return g_s, g_R
+
     def step_backward(self, s, a, g_next, g_depth=None, g_lidar=None, hit_cam=None, hit_lidar=None,
                       want_ga=True):
         g_s = torch.empty_like(s)
