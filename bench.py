@@ -55,8 +55,9 @@ def parse():
                    help="also run a plain device copy of MIB MiB (for HBM counter scaling)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-kernel-timing", action="store_true")
-    p.add_argument("--sections", default="step,render,imu,surrogate,uneven",
-                   help="comma list of extra sections after the headline: step, render, imu, surrogate, uneven")
+    p.add_argument("--sections", default="step,render,imu,attitude,surrogate,uneven",
+                   help="comma list of extra sections after the headline: step, render, imu, attitude, surrogate, "
+                        "uneven")
     return p.parse_args()
 
 
@@ -134,6 +135,39 @@ def imu_section(seed=0, reps=20):
     gbs = n * nbytes / (ms * 1e-3) / 1e9
     return {"agents": n, "bytes_per_reading": nbytes, "avg_launch_ms": round(ms, 4),
             "readings_per_s": round(n / (ms * 1e-3), 1),
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                         "frac": round(gbs * 1e9 / PEAK_HBM, 4)}}
+
+
+def attitude_section(seed=0, reps=20):
+    """Point-mass attitude rule (PM9) alone at 2^22 agents: velocity,
+    acceleration (the thrust) and EMA read, EMA and the 3x3 attitude written,
+    (3 + 3 + 3 + 3 + 9) floats per agent."""
+    import numpy as np
+    import torch
+    import workloads as wl
+    from paper_2509_10247_amd import env
+    n, nbytes = 1 << 22, (3 + 3 + 3 + 3 + 9) * 4
+    rng = np.random.default_rng(seed)
+    p0 = wl.start_positions(rng, n, wl.ROOM_C2)
+    e = env.Env(n_envs=n, n_agents=n, model=wl.PM9, integrator=wl.RK4, dt=0.01)
+    s = torch.tensor(wl.initial_state(rng, wl.PM9, p0), device="cuda")
+    s[6:9] = torch.randn(3, n, device="cuda") * 3 + torch.tensor([[0.0], [0.0], [9.81]], device="cuda")
+    ema = torch.randn(3, n, device="cuda")
+    for _ in range(3):
+        R = e.pm_attitude(s, None, ema, 0.1)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        R = e.pm_attitude(s, None, ema, 0.1)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    assert torch.isfinite(R).all()
+    gbs = n * nbytes / (ms * 1e-3) / 1e9
+    return {"agents": n, "bytes_per_agent": nbytes, "avg_launch_ms": round(ms, 4),
+            "attitudes_per_s": round(n / (ms * 1e-3), 1),
             "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM / 1e9, "unit": "GB/s",
                          "frac": round(gbs * 1e9 / PEAK_HBM, 4)}}
 
@@ -582,6 +616,8 @@ def main():
         line["render"] = render_section()
     if "imu" in sections:
         line["imu"] = imu_section()
+    if "attitude" in sections:
+        line["attitude"] = attitude_section()
     if "surrogate" in sections:
         line["surrogate"] = surrogate_section()
     if "uneven" in sections:
