@@ -20,7 +20,9 @@ image rendered at s':
     radius;
   * terminated = collided or a non-finite state component; truncated =
     (k + 1 >= max_steps) and not terminated; done = either;
-  * an agent with a non-finite state gets r_d = r = 0;
+  * an agent with a non-finite state gets r_d = r = 0; to the others it is
+    an obstacle at its position while that position is finite, and none
+    otherwise;
   * done agents are reset in place, s' <- s_init and k <- 0; the others
     count k <- k + 1.
 
@@ -76,7 +78,9 @@ def task_step(ds, s, s_init, goal, depth, k, cfg, agents_visible=False):
     finite = torch.isfinite(s).all(1)
     s_safe = torch.where(finite[:, None], s, torch.zeros_like(s))
     r_d, reached = rewards(s_safe, goal, depth, cfg)
-    md, collided = sen.sdf_min(ds, s_safe, agents_visible=agents_visible)
+    pos_ok = torch.isfinite(s[:, 0:3]).all(1)
+    far = torch.where(pos_ok[:, None], s, torch.full_like(s, float("inf")))
+    md, collided = sen.sdf_min(ds, far, agents_visible=agents_visible)
     collided = collided & finite
     reached = reached & finite
     r = r_d - cfg.c_collision * collided.double() + cfg.c_goal * reached.double()

@@ -93,3 +93,22 @@ def test_differentiable_reward_gradient_closed_form():
     exp[:, 0:3] = -2 * cfg.w_p * (s[:, 0:3] - goal)
     exp[:, 3:6] = -2 * cfg.w_v * s[:, 3:6]
     assert torch.allclose(s.grad, exp, atol=1e-15)
+
+
+def test_nonfinite_agent_is_no_obstacle():
+    """Two visible agents 0.2 m apart collide; with the position of one of
+    them non-finite the other is free, with only its velocity non-finite it
+    still is an obstacle."""
+    cfg = task.TaskConfig()
+    ds = _scene(2)
+    goal = torch.tensor([[0.0, 5, 4]] * 2, dtype=D)
+    s = _states([(0, 0, 4), (0.2, 0, 4)])
+    k = torch.tensor([0, 0])
+    _, _, flags, _, _ = task.task_step(ds, s, s * 0, goal, None, k, cfg, agents_visible=True)
+    assert flags.tolist() == [task.TERMINATED | task.COLLIDED] * 2
+    s[1, 4] = float("nan")
+    _, _, flags, _, _ = task.task_step(ds, s, s * 0, goal, None, k, cfg, agents_visible=True)
+    assert flags.tolist() == [task.TERMINATED | task.COLLIDED, task.TERMINATED | task.NONFINITE]
+    s[1, 0] = float("inf")
+    _, _, flags, _, _ = task.task_step(ds, s, s * 0, goal, None, k, cfg, agents_visible=True)
+    assert flags.tolist() == [0, task.TERMINATED | task.NONFINITE]
