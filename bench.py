@@ -55,9 +55,9 @@ def parse():
                    help="also run a plain device copy of MIB MiB (for HBM counter scaling)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-kernel-timing", action="store_true")
-    p.add_argument("--sections", default="step,render,imu,attitude,surrogate,uneven",
-                   help="comma list of extra sections after the headline: step, render, imu, attitude, surrogate, "
-                        "uneven")
+    p.add_argument("--sections", default="step,render,imu,attitude,task,surrogate,uneven",
+                   help="comma list of extra sections after the headline: step, render, imu, attitude, task, "
+                        "surrogate, uneven")
     return p.parse_args()
 
 
@@ -170,6 +170,63 @@ def attitude_section(seed=0, reps=20):
             "attitudes_per_s": round(n / (ms * 1e-3), 1),
             "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM / 1e9, "unit": "GB/s",
                          "frac": round(gbs * 1e9 / PEAK_HBM, 4)}}
+
+
+def task_section(seed=0, reps=10):
+    """Whole environment step with observation, rewards and reset on the
+    4096-env rigid-body scene: sim_step, the camera render at the new state
+    and sim_task_step (rewards, flags, in-place reset), env-steps/s; and the
+    task layer alone against HBM (depth row, state, goal, counter, rewards
+    and flags per agent)."""
+    import numpy as np
+    import torch
+    import workloads as wl
+    from paper_2509_10247_amd import env
+    wk = wl.rigid_body(seed=seed, n_envs=4096, T=reps + 3)
+    e = env.from_workload(wk)
+    A = 4096
+    s = torch.tensor(wk.state0, device="cuda")
+    s_init = s.clone()
+    s2 = torch.empty_like(s)
+    acts = torch.tensor(wk.actions, device="cuda")
+    goal = torch.tensor(wk.state0[0:3] + 1.0, device="cuda")
+    k = torch.zeros(A, dtype=torch.int32, device="cuda")
+    depth = torch.empty(A, 48, 64, device="cuda")
+    from paper_2509_10247_amd import _lib
+    cfg = _lib.TaskConfig(0.01, 0.1, 1.0, 10.0, 1.0, 10.0, 1.0, 0.3, 1000)
+    r_d = torch.empty(A, device="cuda")
+    r = torch.empty(A, device="cuda")
+    fl = torch.empty(A, dtype=torch.uint8, device="cuda")
+
+    def one(t):
+        e.step(s, acts[t], out=s2)
+        _lib.sim_render(e.h, s2, depth)
+        _lib.sim_task_step(e.h, cfg, s2, s_init, goal, depth, k, r_d, r, fl)
+        s.copy_(s2)
+
+    for t in range(3):
+        one(t)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for t in range(reps):
+        one(3 + t)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_env = ev0.elapsed_time(ev1) / reps
+    ev0.record()
+    for _ in range(reps):
+        _lib.sim_task_step(e.h, cfg, s2, s_init, goal, depth, k, r_d, r, fl)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_task = ev0.elapsed_time(ev1) / reps
+    assert torch.isfinite(r).all()
+    nbytes = 3072 * 4 + 13 * 4 + 3 * 4 + 2 * 4 + 2 * 4 + 1 + 13
+    gbs = A * nbytes / (ms_task * 1e-3) / 1e9
+    return {"envs": A, "ms_per_env_step": round(ms_env, 4), "env_steps_per_s": round(A / (ms_env * 1e-3), 1),
+            "task_ms": round(ms_task, 4), "task_bytes_per_agent": nbytes,
+            "task_roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                              "frac": round(gbs * 1e9 / PEAK_HBM, 4)}}
 
 
 def render_section(seed=0, reps=10):
@@ -618,6 +675,8 @@ def main():
         line["imu"] = imu_section()
     if "attitude" in sections:
         line["attitude"] = attitude_section()
+    if "task" in sections:
+        line["task"] = task_section()
     if "surrogate" in sections:
         line["surrogate"] = surrogate_section()
     if "uneven" in sections:

@@ -194,6 +194,37 @@ int sim_render_oriented_backward(sim_handle* h, const float* s, const float* R, 
                                  const float* g_lidar, const int32_t* hit_cam, const int32_t* hit_lidar,
                                  float* g_s, float* g_R, void* stream);
 
+/* Obstacle-avoidance task layer after the step (Sec. III-C task; Sec. III-D
+ * gives a differentiable and a non-differentiable reward per step, without
+ * formulas; this is a reading). Per agent, on s = s_{t+1} and the camera
+ * image rendered at it:
+ *   reward_d = -(w_p |p - goal|^2 + w_v |v|^2
+ *                + w_o mean_rays softplus(beta (d_safe - depth)) / beta)
+ *              (obstacle term 0 when depth is NULL);
+ *   reward   = reward_d - c_collision [collided] + c_goal [|p - goal| < goal_radius];
+ *   collided: distance from p to the nearest surface (spheres, boxes,
+ *   cylinders, room walls, other agents when agents_visible) < agent_radius;
+ *   terminated = collided or a non-finite state component (rewards 0);
+ *   truncated = k + 1 >= max_steps and not terminated.
+ * Finished agents (terminated or truncated) are reset in place, s <- s_init,
+ * k <- 0; the others count k <- k + 1. flags [A]: TASK_* bits.
+ * s, s_init: SoA [C][A]; goal [3][A]; depth [A][H][W] (camera, nullable);
+ * k int32 [A] in/out; reward_d, reward [A] out. Two launches (rewards and
+ * flags, then the reset). */
+typedef struct task_config {
+  float w_p, w_v, w_o;             /* differentiable reward weights */
+  float beta, d_safe;              /* obstacle term; beta > 0 */
+  float c_collision, c_goal, goal_radius;
+  int32_t max_steps;               /* >= 1 */
+} task_config;
+#define TASK_TERMINATED 1
+#define TASK_TRUNCATED 2
+#define TASK_COLLIDED 4
+#define TASK_REACHED 8
+#define TASK_NONFINITE 16
+int sim_task_step(sim_handle* h, const task_config* cfg, float* s, const float* s_init, const float* goal,
+                  const float* depth, int32_t* k, float* reward_d, float* reward, uint8_t* flags, void* stream);
+
 /* Work count of one sensor's render at s (diagnostics for the roofline; the
  * exclusion of obstacles outside the field of view is Sec. III-B): renders
  * sensor 0 (camera) or 1 (LiDAR) into out ([A][n_rays], as sim_render) and

@@ -39,6 +39,11 @@ class ImuConfig(ctypes.Structure):
                 ("sigma_bgyro", c_float)]
 
 
+class TaskConfig(ctypes.Structure):
+    _fields_ = [("w_p", c_float), ("w_v", c_float), ("w_o", c_float), ("beta", c_float), ("d_safe", c_float),
+                ("c_collision", c_float), ("c_goal", c_float), ("goal_radius", c_float), ("max_steps", c_int)]
+
+
 class BpttConfig(ctypes.Structure):
     _fields_ = [("T", c_int), ("K", c_int), ("w_p", c_float), ("w_v", c_float), ("w_u", c_float),
                 ("w_o", c_float), ("beta", c_float), ("d_safe", c_float),
@@ -65,6 +70,7 @@ _SIGS = {
     "sim_pm_attitude": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_float, c_void_p, c_void_p]),
     "sim_pm_attitude_backward": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_float] + [c_void_p] * 6),
     "sim_render_oriented": (c_int, [c_void_p] * 8),
+    "sim_task_step": (c_int, [c_void_p, ctypes.POINTER(TaskConfig)] + [c_void_p] * 9),
     "sim_render_oriented_backward": (c_int, [c_void_p] * 10),
     "bptt_create": (c_int, [c_void_p, ctypes.POINTER(BpttConfig), ctypes.POINTER(c_void_p)]),
     "bptt_destroy": (c_int, [c_void_p]),
@@ -229,6 +235,12 @@ def sim_render_oriented_backward(h, s, R, g_depth, g_lidar, hit_cam, hit_lidar, 
     _call("sim_render_oriented_backward", h, ptr(s, torch.float32), ptr(R, torch.float32),
           ptr(g_depth, torch.float32), ptr(g_lidar, torch.float32), ptr(hit_cam, torch.int32),
           ptr(hit_lidar, torch.int32), ptr(g_s, torch.float32), ptr(g_R, torch.float32), stream())
+
+
+def sim_task_step(h, cfg, s, s_init, goal, depth, k, reward_d, reward, flags):
+    _call("sim_task_step", h, ctypes.byref(cfg), ptr(s, torch.float32), ptr(s_init, torch.float32),
+          ptr(goal, torch.float32), ptr(depth, torch.float32), ptr(k, torch.int32), ptr(reward_d, torch.float32),
+          ptr(reward, torch.float32), ptr(flags, torch.uint8), stream())
 
 
 def sim_collide(h, s, flags=None, min_dist=None):

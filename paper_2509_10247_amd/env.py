@@ -165,6 +165,17 @@ class Env:
         _lib.sim_render_oriented_backward(self.h, s, R, g_depth, g_lidar, hit_cam, hit_lidar, g_s, g_R)
         return g_s, g_R
 
+    def task_step(self, s, s_init, goal, depth, k, w_p=0.01, w_v=0.1, w_o=1.0, beta=10.0, d_safe=1.0,
+                  c_collision=10.0, c_goal=1.0, goal_radius=0.3, max_steps=1000):
+        """Rewards, flags and in-place reset after the step: returns
+        (reward_d, reward, flags); s and k are updated in place."""
+        cfg = _lib.TaskConfig(w_p, w_v, w_o, beta, d_safe, c_collision, c_goal, goal_radius, max_steps)
+        r_d = torch.empty(self.n_agents, device="cuda")
+        r = torch.empty(self.n_agents, device="cuda")
+        fl = torch.empty(self.n_agents, dtype=torch.uint8, device="cuda")
+        _lib.sim_task_step(self.h, cfg, s, s_init, goal, depth, k, r_d, r, fl)
+        return r_d, r, fl
+
     def step_backward(self, s, a, g_next, g_depth=None, g_lidar=None, hit_cam=None, hit_lidar=None,
                       want_ga=True):
         g_s = torch.empty_like(s)
