@@ -101,3 +101,21 @@ def test_task_step_visible_agents_and_cylinders():
         if a1 - a0 >= 2 and np.isfinite(s[:, a0]).all():
             s[0:3, a0 + 1] = s[0:3, a0] + np.array([0.2, 0.0, 0.0], np.float32)
     _check(wk, e, s, s_init, goal, k, agents_visible=True)
+
+
+def test_task_step_without_depth():
+    """No depth image (position control): no obstacle term; 257 agents, a
+    ragged last workgroup of the wavefront-per-agent launch."""
+    wk = wl.rigid_body(seed=86, n_envs=257, T=1)
+    from paper_2509_10247_amd import env
+    e = env.from_workload(wk)
+    s, s_init, goal, k = _prepare(wk, 87)
+    s_c = cuda(s)
+    k_c = torch.tensor(k, device="cuda")
+    r_d, r, fl = e.task_step(s_c, cuda(s_init), cuda(goal), None, k_c, max_steps=CFG.max_steps)
+    r_do, ro, flo, s_after, _ = otask.task_step(
+        osen.DenseScene(wk.scene), torch.tensor(s.T.astype(np.float64)), torch.tensor(s_init.T.astype(np.float64)),
+        torch.tensor(goal.T.astype(np.float64)), None, torch.tensor(k.astype(np.int64)), CFG)
+    assert torch.equal(fl.cpu().long(), flo)
+    assert torch.allclose(f64(r_d), r_do, rtol=1e-5, atol=1e-5) and torch.allclose(f64(r), ro, rtol=1e-5, atol=1e-5)
+    assert torch.equal(s_c.cpu().T.nan_to_num(7.0), s_after.float().nan_to_num(7.0))
