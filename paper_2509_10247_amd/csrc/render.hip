@@ -22,7 +22,7 @@
 namespace da {
 
 template <bool ROT, bool CULL, bool CYL>
-__global__ __launch_bounds__(256) void render_kernel(SceneDev sc, SensorDev sen,
+__global__ __launch_bounds__(256, 8) void render_kernel(SceneDev sc, SensorDev sen,
                                                      const float* __restrict__ s, int A,
                                                      float* __restrict__ out,
                                                      int* __restrict__ rec, int out_ld,
