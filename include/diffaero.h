@@ -407,18 +407,19 @@ int adam_step(int64_t n, float* w, const float* g, float* m, float* v, float lr,
  * SIM_FLAG_NONFINITE / SIM_FLAG_COLLISION with OR. s (SoA [C][A]) holds s_0
  * on entry and s_T on return. All outputs are identical in every mode and
  * for every tuning choice.
- * mode 0: one persistent fused kernel per step (render items for camera /
- *         LiDAR tile groups, dynamics items), longest-first work queue, the T
+ * mode 0: per step a dynamics launch and one persistent render kernel
+ *         (items: camera / LiDAR tile groups of one agent, staged once), an
+ *         atomic work queue in the tuned item order, the T
  *         launches captured once in a hipGraph and replayed on later calls
  *         with the same T, pointers and tuning;
  * mode 1: plain launch per operation (dynamics, camera, LiDAR) per step;
- * mode 2: the fused kernel without a graph.
+ * mode 2: the persistent path without a graph.
  * The handle owns a second state buffer, per-step work counters and the
  * graph; the first call with a new shape allocates them (synchronous). */
 int sim_rollout(sim_handle* h, int32_t T, float* s, const float* a_seq, float* depth_ring,
                 float* lidar_ring, uint8_t* flags, int32_t mode, void* stream);
 
-/* Sets the fused kernel's tuning: tile_group = camera / LiDAR tiles (64 rays
+/* Sets the persistent render kernel's tuning: tile_group = camera / LiDAR tiles (64 rays
  * each) per work item, blocks_per_cu = persistent workgroups per compute unit
  * (1..16), order = 1 longest-first, 0 env order. Synchronous. */
 int sim_rollout_config(sim_handle* h, int32_t tile_group, int32_t blocks_per_cu, int32_t order);

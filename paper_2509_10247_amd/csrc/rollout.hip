@@ -1,17 +1,18 @@
 // Uneven-batch rollouts: environments with different obstacle and agent
-// counts (Sec. III: environment- and agent-level parallelism) stepped by one
-// persistent fused kernel per time step, T steps captured in a hipGraph.
+// counts (Sec. III: environment- and agent-level parallelism). Per time step
+// one dynamics launch (collision distance at s_t and s_{t+1} = step(s_t, a_t)
+// into the other state buffer) and one persistent render kernel; T steps
+// captured in a hipGraph.
 //
-// Work items of one step (all read s_t only, so no grid-wide barrier is
-// needed inside a step):
-//   - agent item: tiles [tb, te) of one agent's sensors at s_t, in the
-//     combined tile index space (camera tiles, then LiDAR tiles); the
-//     agent's environment is staged in LDS once for both sensors;
-//   - dynamics item: 256 agents' collision distance at s_t and their step
-//     s_{t+1} = step(s_t, a_t), written to the other state buffer.
-// Items are ordered longest-first by an estimated cost (rays x primitives of
-// the env) and handed out by an atomic counter, so a workgroup that drew a
-// cheap env takes the next item instead of idling. Every ray and every agent
+// The render kernel's work items are agent items: tiles [tb, te) of one
+// agent's sensors at s_t, in the combined tile index space (camera tiles,
+// then LiDAR tiles); the agent's environment is staged in LDS once for both
+// sensors. Items are ordered longest-first by an estimated cost (rays x
+// primitives of the env) and handed out by an atomic counter, so a
+// workgroup that drew a cheap env takes the next item instead of idling.
+// The kernel holds only the render path, so it runs at eight wavefronts per
+// SIMD like the launch-per-op render; with the dynamics items in the same
+// kernel, the rigid-body RK4 step set its register budget. Every ray and every agent
 // is computed by the same device code as the launch-per-op path, so the
 // outputs do not depend on the schedule or on the tuning choices.
 //
@@ -31,7 +32,7 @@
 
 namespace da {
 
-enum { ITEM_AGENT = 0, ITEM_DYN = 2 };
+enum { ITEM_AGENT = 0 };
 
 struct RolloutArgs {
   SceneDev sc;
@@ -97,8 +98,8 @@ __device__ __forceinline__ void agent_item(const RolloutArgs& g, int4 w, RenderL
   }
 }
 
-template <int M, int I, bool CULL>
-__global__ __launch_bounds__(256, 6) void rollout_fused_kernel(RolloutArgs g) {
+template <bool ROT, bool CULL, bool CYL>
+__global__ __launch_bounds__(256, 8) void rollout_render_kernel(RolloutArgs g) {
   extern __shared__ float4 smem_f4[];
   __shared__ int cur;
   for (;;) {
@@ -108,18 +109,8 @@ __global__ __launch_bounds__(256, 6) void rollout_fused_kernel(RolloutArgs g) {
     __syncthreads();  // every thread has read the ticket before it is replaced
     if (it >= g.n_items) break;  // uniform over the workgroup: all waves exit
     const int4 w = g.items[it];
-    if (w.x == ITEM_DYN) {
-      dyn_item<M, I>(g, w.y);
-    } else {
-      constexpr bool ROT = rotates_m<M>();
-      RenderLds L = carve(smem_f4, g.sc.max_prims > 0 ? g.sc.max_prims : 1);
-      // uniform branch: scenes without cylinders keep the three-category
-      // staging and tile loop
-      if (g.sc.cyl_off)
-        agent_item<ROT, CULL, true>(g, w, L);
-      else
-        agent_item<ROT, CULL, false>(g, w, L);
-    }
+    RenderLds L = carve(smem_f4, g.sc.max_prims > 0 ? g.sc.max_prims : 1);
+    agent_item<ROT, CULL, CYL>(g, w, L);
   }
 }
 
@@ -140,11 +131,18 @@ __global__ void copy_floats_kernel(const float* __restrict__ src, float* __restr
 
 template <int M, int I>
 static int launch_fused_t(const RolloutArgs& g, bool cull, int grid, size_t lds, hipStream_t st) {
+  hipLaunchKernelGGL((rollout_dyn_kernel<M, I>), dim3(cdiv(g.A, 256)), dim3(256), 0, st, g);
+  DA_LAUNCH_CHECK("rollout_dyn_kernel");
+  // scenes without cylinders keep the three-category staging and tile loop
+  constexpr bool ROT = rotates_m<M>();
+  decltype(&rollout_render_kernel<ROT, true, true>) k = nullptr;
+  const bool cyl = g.sc.cyl_off != nullptr;
   if (cull)
-    hipLaunchKernelGGL((rollout_fused_kernel<M, I, true>), dim3(grid), dim3(256), lds, st, g);
+    k = cyl ? rollout_render_kernel<ROT, true, true> : rollout_render_kernel<ROT, true, false>;
   else
-    hipLaunchKernelGGL((rollout_fused_kernel<M, I, false>), dim3(grid), dim3(256), lds, st, g);
-  DA_LAUNCH_CHECK("rollout_fused_kernel");
+    k = cyl ? rollout_render_kernel<ROT, false, true> : rollout_render_kernel<ROT, false, false>;
+  hipLaunchKernelGGL(k, dim3(grid), dim3(256), lds, st, g);
+  DA_LAUNCH_CHECK("rollout_render_kernel");
   return SIM_OK;
 }
 
@@ -218,7 +216,6 @@ void rollout_plan_free(sim_handle* h) {
 }
 
 static int build_items(sim_handle* h, RolloutPlan* p) {
-  const int A = h->cfg.n_agents;
   std::vector<std::pair<double, int4>> items;
   const auto& so = h->host_sph_off;
   const auto& bo = h->host_box_off;
@@ -238,7 +235,6 @@ static int build_items(sim_handle* h, RolloutPlan* p) {
         items.push_back({cost, make_int4(ITEM_AGENT, i, tb, te)});
       }
   }
-  for (int b = 0; b < cdiv(A, 256); ++b) items.push_back({2000.0, make_int4(ITEM_DYN, b, 0, 0)});
   if (p->order == 1)
     std::stable_sort(items.begin(), items.end(),
                      [](const std::pair<double, int4>& x, const std::pair<double, int4>& y) { return x.first > y.first; });
@@ -250,7 +246,8 @@ static int build_items(sim_handle* h, RolloutPlan* p) {
     DA_HIP(hipMalloc(&p->items_dev, (size_t)n * sizeof(int4)));
     p->items_cap = n;
   }
-  DA_HIP(hipMemcpy(p->items_dev, p->items.data(), (size_t)n * sizeof(int4), hipMemcpyHostToDevice));
+  // no sensor: no items; the render kernel's workgroups draw one ticket each and exit
+  if (n > 0) DA_HIP(hipMemcpy(p->items_dev, p->items.data(), (size_t)n * sizeof(int4), hipMemcpyHostToDevice));
   if (p->exec) {
     (void)hipGraphExecDestroy(p->exec);
     p->exec = nullptr;
