@@ -2,13 +2,17 @@
  * diffaero.h -- C ABI of the MI355X (gfx950) batched, differentiable quadrotor
  * environment step: dynamics integration, ray-cast depth camera / LiDAR,
  * collisions, the hand-written adjoint, the policy-in-the-loop BPTT engine,
- * the BF16 residual-dynamics surrogate and the persistent uneven-batch rollout.
+ * the BF16 residual-dynamics surrogate, the persistent uneven-batch rollout,
+ * the IMU, the point-mass attitude rule and the obstacle-avoidance task layer.
  *
  * The operations follow DiffAero (Zhang et al., 2025):
  *   - dynamics models: Sec. III-A, Eq. (1) full quadrotor, Eq. (2) simplified,
- *     Eq. (3) continuous point mass;
- *   - sensors: Sec. III-B (ray casting against primitive shapes, obstacles
- *     outside the sensor's field of view excluded from casting);
+ *     Eq. (3) continuous point mass, Eq. (4) discrete point mass;
+ *   - sensors: Sec. III-B (ray casting against primitive shapes: spheres,
+ *     boxes, cylinders; obstacles outside the sensor's field of view excluded
+ *     from casting; an IMU with noise and drift; the point-mass attitude);
+ *   - tasks and rewards: Sec. III-C (obstacle avoidance), Sec. III-D
+ *     (differentiable and non-differentiable rewards per step);
  *   - gradients through time: Sec. III-A, Eq. (5);
  *   - environment- and agent-level parallelism: Sec. III (multiple
  *     environments, each with several quadrotors).
