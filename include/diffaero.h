@@ -229,6 +229,17 @@ typedef struct task_config {
 int sim_task_step(sim_handle* h, const task_config* cfg, float* s, const float* s_init, const float* goal,
                   const float* depth, int32_t* k, float* reward_d, float* reward, uint8_t* flags, void* stream);
 
+/* Gradient of sim_task_step's differentiable reward (Sec. III-D): with
+ * g_reward_d = dL/dreward_d [A], adds -2 w_p (p - goal) g and -2 w_v v g to
+ * g_s's position and velocity rows ([C][A]) and writes
+ * g_depth[i][r] = w_o sigmoid(beta (d_safe - depth[i][r])) g[i] / n_rays
+ * (nullable; needs depth; overwritten), which sim_step_backward's g_depth
+ * pulls back through the render. s: the state the reward was computed on
+ * (before the reset), depth: the camera image at it (nullable: no obstacle
+ * term). Agents with a non-finite state get no gradient. */
+int sim_task_backward(sim_handle* h, const task_config* cfg, const float* s, const float* goal,
+                      const float* depth, const float* g_reward_d, float* g_s, float* g_depth, void* stream);
+
 /* Work count of one sensor's render at s (diagnostics for the roofline; the
  * exclusion of obstacles outside the field of view is Sec. III-B): renders
  * sensor 0 (camera) or 1 (LiDAR) into out ([A][n_rays], as sim_render) and

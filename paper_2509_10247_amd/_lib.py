@@ -71,6 +71,7 @@ _SIGS = {
     "sim_pm_attitude_backward": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_float] + [c_void_p] * 6),
     "sim_render_oriented": (c_int, [c_void_p] * 8),
     "sim_task_step": (c_int, [c_void_p, ctypes.POINTER(TaskConfig)] + [c_void_p] * 9),
+    "sim_task_backward": (c_int, [c_void_p, ctypes.POINTER(TaskConfig)] + [c_void_p] * 7),
     "sim_render_oriented_backward": (c_int, [c_void_p] * 10),
     "bptt_create": (c_int, [c_void_p, ctypes.POINTER(BpttConfig), ctypes.POINTER(c_void_p)]),
     "bptt_destroy": (c_int, [c_void_p]),
@@ -241,6 +242,12 @@ def sim_task_step(h, cfg, s, s_init, goal, depth, k, reward_d, reward, flags):
     _call("sim_task_step", h, ctypes.byref(cfg), ptr(s, torch.float32), ptr(s_init, torch.float32),
           ptr(goal, torch.float32), ptr(depth, torch.float32), ptr(k, torch.int32), ptr(reward_d, torch.float32),
           ptr(reward, torch.float32), ptr(flags, torch.uint8), stream())
+
+
+def sim_task_backward(h, cfg, s, goal, depth, g_reward_d, g_s, g_depth=None):
+    _call("sim_task_backward", h, ctypes.byref(cfg), ptr(s, torch.float32), ptr(goal, torch.float32),
+          ptr(depth, torch.float32), ptr(g_reward_d, torch.float32), ptr(g_s, torch.float32),
+          ptr(g_depth, torch.float32), stream())
 
 
 def sim_collide(h, s, flags=None, min_dist=None):

@@ -176,6 +176,14 @@ class Env:
         _lib.sim_task_step(self.h, cfg, s, s_init, goal, depth, k, r_d, r, fl)
         return r_d, r, fl
 
+    def task_backward(self, s, goal, depth, g_reward_d, w_p=0.01, w_v=0.1, w_o=1.0, beta=10.0, d_safe=1.0):
+        """(g_s, g_depth) of the differentiable reward at s (before the reset)."""
+        cfg = _lib.TaskConfig(w_p, w_v, w_o, beta, d_safe, 0.0, 0.0, 0.0, 1)
+        g_s = torch.zeros_like(s)
+        g_d = torch.empty_like(depth) if depth is not None else None
+        _lib.sim_task_backward(self.h, cfg, s, goal, depth, g_reward_d, g_s, g_d)
+        return g_s, g_d
+
     def step_backward(self, s, a, g_next, g_depth=None, g_lidar=None, hit_cam=None, hit_lidar=None,
                       want_ga=True):
         g_s = torch.empty_like(s)

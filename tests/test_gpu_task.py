@@ -119,3 +119,28 @@ def test_task_step_without_depth():
     assert torch.equal(fl.cpu().long(), flo)
     assert torch.allclose(f64(r_d), r_do, rtol=1e-5, atol=1e-5) and torch.allclose(f64(r), ro, rtol=1e-5, atol=1e-5)
     assert torch.equal(s_c.cpu().T.nan_to_num(7.0), s_after.float().nan_to_num(7.0))
+
+
+def test_task_backward_matches_autograd():
+    """Gradient of the differentiable reward in the state and the depth image
+    against autograd through the oracle's reward; non-finite agents get none."""
+    from paper_2509_10247_amd import env
+    wk = wl.rigid_body(seed=88, n_envs=500, T=1)
+    e = env.from_workload(wk)
+    s, _, goal, _ = _prepare(wk, 89)
+    A = 500
+    s_c = cuda(s)
+    depth = e.render(s_c, depth=True)[0].reshape(A, -1)
+    g = np.random.default_rng(90).normal(size=A).astype(np.float32)
+    g_s, g_d = e.task_backward(s_c, cuda(goal), depth, cuda(g), w_p=CFG.w_p, w_v=CFG.w_v, w_o=CFG.w_o,
+                               beta=CFG.beta, d_safe=CFG.d_safe)
+    so = torch.tensor(s.T.astype(np.float64), requires_grad=True)
+    do = f64(depth).requires_grad_(True)
+    r_d, _ = otask.rewards(so, torch.tensor(goal.T.astype(np.float64)), do, CFG)
+    finite = torch.isfinite(torch.tensor(s.T)).all(1)
+    (r_d[finite] * torch.tensor(g.astype(np.float64))[finite]).sum().backward()
+    gs, gd = f64(g_s).T, f64(g_d)
+    assert torch.allclose(gs[finite], so.grad[finite], rtol=1e-5, atol=1e-7)
+    assert torch.allclose(gd[finite], do.grad[finite], rtol=1e-5, atol=1e-10)
+    assert torch.count_nonzero(gs[~finite]) == 0 and torch.count_nonzero(gd[~finite]) == 0
+    assert (~finite).any()
