@@ -253,15 +253,15 @@ static int fetch_offsets(const int32_t* dev, int n, std::vector<int32_t>& host) 
   return SIM_OK;
 }
 
-static int check_csr(const std::vector<int32_t>& off, int total, const char* what, int max_per) {
-  DA_REQUIRE(off[0] == 0, "sim_set_scene: %s_off[0] must be 0", what);
+static int check_csr(const std::vector<int32_t>& off, int total, const char* what, int max_per,
+                     const char* fn = "sim_set_scene") {
+  DA_REQUIRE(off[0] == 0, "%s: %s_off[0] must be 0", fn, what);
   for (size_t e = 1; e < off.size(); ++e) {
-    DA_REQUIRE(off[e] >= off[e - 1], "sim_set_scene: %s_off not monotone at %zu", what, e);
-    DA_REQUIRE(off[e] - off[e - 1] <= max_per, "sim_set_scene: env %zu has %d %s (max %d)", e - 1,
-               off[e] - off[e - 1], what, max_per);
+    DA_REQUIRE(off[e] >= off[e - 1], "%s: %s_off not monotone at %zu", fn, what, e);
+    DA_REQUIRE(off[e] - off[e - 1] <= max_per, "%s: env %zu has %d %s (max %d)", fn, e - 1, off[e] - off[e - 1],
+               what, max_per);
   }
-  DA_REQUIRE(off.back() == total, "sim_set_scene: %s_off[E]=%d but count is %d", what, off.back(),
-             total);
+  DA_REQUIRE(off.back() == total, "%s: %s_off[E]=%d but count is %d", fn, what, off.back(), total);
   return SIM_OK;
 }
 
@@ -364,7 +364,7 @@ int sim_set_cylinders(sim_handle* h, const int32_t* cyl_off, const float* cyl, i
     DA_REQUIRE(n_cyl == 0 || cyl, "sim_set_cylinders: cylinders pointer is null");
     int rc = fetch_offsets(cyl_off, h->cfg.n_envs + 1, co);
     if (rc) return rc;
-    if ((rc = check_csr(co, n_cyl, "cyl", SIM_MAX_PRIMS_PER_ENV))) return rc;
+    if ((rc = check_csr(co, n_cyl, "cyl", SIM_MAX_PRIMS_PER_ENV, "sim_set_cylinders"))) return rc;
   } else {
     DA_REQUIRE(n_cyl == 0, "sim_set_cylinders: cyl_off is NULL but n_cyl = %d", n_cyl);
   }

@@ -191,3 +191,33 @@ def test_cylinder_limits_and_reset():
     e.set_cylinders(None, None)
     _, h2 = _render(e, s, "cam")
     assert torch.equal(h2, h0)
+
+
+def test_cylinder_scene_at_the_primitive_limit():
+    """An env of 1024 thin cylinders (the per-env limit) renders both sensors
+    as the oracle does on stable rays; 1025 are refused."""
+    from paper_2509_10247_amd import env
+    rng = np.random.default_rng(71)
+    p0 = wl.start_positions(rng, 1, wl.ROOM_C2)
+    sc = wl.make_scene(rng, 1, 0, 0, wl.ROOM_C2, (0.3, 1.0), (0.2, 0.8), room=True, keepout=p0, n_cyl=1024,
+                       cyl_r=(0.03, 0.1), cyl_h=(0.05, 0.4))
+    s0 = wl.initial_state(np.random.default_rng(72), wl.RB13, p0)
+    wk = wl.Workload("maxcyl", wl.RB13, wl.RK4, 0.01, 1, sc, s0, wl.params(rng, wl.RB13, 1), None,
+                     (64, 48, 90.0, 10.0), (16, 360, -15.0, 15.0, 20.0))
+    print_case("cyl_max_scene", prims=1024)
+    e = _env(wk)
+    s = cuda(s0)
+    for sensor in ("cam", "lidar"):
+        d, h = _render(e, s, sensor)
+        db, zf, mx = _dirs(wk, sensor)
+        ok, v_orc, r_orc = osen.stable_rays(wl.RB13, osen.DenseScene(sc), torch.tensor(s0.T.astype(np.float64)), db,
+                                            zf, mx, lanes=torch.arange(1), agents_visible=False)
+        assert ok.float().mean().item() >= 0.95
+        err = (f64(d).reshape(1, -1) - v_orc).abs()
+        assert (err[ok] <= 1e-4).all(), f"{sensor}: max depth error {err[ok].max().item():.3e}"
+        assert torch.equal(h.cpu().reshape(1, -1).long()[ok], r_orc[ok])
+        assert ((r_orc >= 0) & (r_orc < 1024)).any()
+    e2 = env.Env(n_envs=1, n_agents=1, model=wl.RB13, integrator=wl.RK4, dt=0.01, cam=wk.cam)
+    e2.set_scene(sc.sph_off, sc.sph, sc.box_off, sc.box, sc.room)
+    with pytest.raises(RuntimeError, match="sim_set_cylinders: env 0 has 1025 cyl"):
+        e2.set_cylinders(np.array([0, 1025], np.int32), np.tile([[0, 0, 1, 0.1, 0.1]], (1025, 1)))
