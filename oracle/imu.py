@@ -9,6 +9,10 @@ model; the reading implemented here (and by the kernels) is:
     f = R^T (dv/dt - g), with dv/dt the model's right-hand side at (s, a)
     (rigid-body models only: they carry the attitude R);
   * gyroscope: the body rate w (state components 10..12);
+  * the point-mass models, given the attitude of the attitude rule (R, and
+    R_prev of the step before): accelerometer R^T (dv/dt - g), gyroscope
+    log(R_prev^T R) / dt, the body rate that turns one attitude into the
+    next over the step (a reading: the rule defines attitudes, not rates);
   * drift: bias random walk b+ = b + sigma_b sqrt(dt) xi_b, per component;
   * noise: out = (f, w) + b+ + sigma xi_w.
 
@@ -93,3 +97,51 @@ def imu_step(model, s, u, prm, bias, sigmas, seed: int, t: int, dt: float):
     sw = torch.tensor([s_acc] * 3 + [s_gyro] * 3, dtype=s.dtype)
     b = bias + sb * xi[:, :6]
     return reading(model, s, u, prm) + b + sw * xi[:, 6:], b
+
+
+# ----------------------------------------------------------------------------
+# point-mass models with the attitude rule (Sec. III-B)
+# ----------------------------------------------------------------------------
+
+def specific_force_pm(model: int, s: torch.Tensor, u: torch.Tensor, prm: torch.Tensor) -> torch.Tensor:
+    """World-frame specific force dv/dt - g [A, 3] of a point-mass model:
+    u (PM6), a - d v (PM9), the applied u_prev (PMD)."""
+    if model == dyn.PM6:
+        return u[:, 0:3]
+    if model == dyn.PM9:
+        return s[:, 6:9] - prm[:, 1:2] * s[:, 3:6]
+    if model == dyn.PMD:
+        return s[:, 6:9]
+    raise ValueError("the oriented IMU is for the point-mass models")
+
+
+def log_rot(Q: torch.Tensor) -> torch.Tensor:
+    """Rotation vector [A, 3] (axis times angle) of rotations Q [A, 3, 3]
+    with angles below pi: sin(angle) axis from the skew part, cos(angle)
+    from the trace."""
+    w = 0.5 * torch.stack([Q[:, 2, 1] - Q[:, 1, 2], Q[:, 0, 2] - Q[:, 2, 0], Q[:, 1, 0] - Q[:, 0, 1]], -1)
+    sn = w.norm(dim=-1)
+    cs = 0.5 * (Q.diagonal(dim1=1, dim2=2).sum(-1) - 1.0)
+    theta = torch.atan2(sn, cs)
+    ok = sn > 1e-12
+    scale = torch.where(ok, theta / torch.where(ok, sn, torch.ones_like(sn)), torch.ones_like(sn))
+    return w * scale[:, None]
+
+
+def reading_oriented(model, s, u, prm, R, R_prev, dt):
+    """Noise-free reading [A, 6] of a point-mass model with attitude R [A, 3,
+    3] (previous step R_prev): accelerometer R^T (dv/dt - g), gyroscope the
+    body rate that turns R_prev into R over the step, log(R_prev^T R) / dt."""
+    f = (R.transpose(1, 2) @ specific_force_pm(model, s, u, prm).unsqueeze(-1)).squeeze(-1)
+    w = log_rot(R_prev.transpose(1, 2) @ R) / dt
+    return torch.cat([f, w], 1)
+
+
+def imu_step_oriented(model, s, u, prm, R, R_prev, bias, sigmas, seed: int, t: int, dt: float):
+    """reading_oriented with drift and noise, as imu_step."""
+    s_acc, s_gyro, s_bacc, s_bgyro = sigmas
+    xi = torch.tensor(normals(seed, t, s.shape[0]), dtype=s.dtype)
+    sb = torch.tensor([s_bacc] * 3 + [s_bgyro] * 3, dtype=s.dtype) * math.sqrt(dt)
+    sw = torch.tensor([s_acc] * 3 + [s_gyro] * 3, dtype=s.dtype)
+    b = bias + sb * xi[:, :6]
+    return reading_oriented(model, s, u, prm, R, R_prev, dt) + b + sw * xi[:, 6:], b

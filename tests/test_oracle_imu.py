@@ -131,3 +131,62 @@ def test_reading_gradient_matches_finite_differences(model):
                 sm, um = (xm, u.detach()) if x is s else (s.detach(), xm)
                 fd[idx] = ((imu.reading(model, sp, up, prm) - imu.reading(model, sm, um, prm)) * w).sum() / (2 * h)
         assert torch.allclose(gx, fd, rtol=1e-6, atol=1e-8)
+
+
+def _rz(a):
+    c, s = math.cos(a), math.sin(a)
+    return torch.tensor([[c, -s, 0.0], [s, c, 0.0], [0.0, 0.0, 1.0]], dtype=D)
+
+
+def _rx(a):
+    c, s = math.cos(a), math.sin(a)
+    return torch.tensor([[1.0, 0.0, 0.0], [0.0, c, -s], [0.0, s, c]], dtype=D)
+
+
+def _exp_rot(w):
+    """Rodrigues: rotation of the rotation vector w [A, 3]."""
+    th = w.norm(dim=-1, keepdim=True)
+    k = w / th
+    K = torch.zeros(w.shape[0], 3, 3, dtype=D)
+    K[:, 0, 1], K[:, 0, 2], K[:, 1, 2] = -k[:, 2], k[:, 1], -k[:, 0]
+    K = K - K.transpose(1, 2)
+    I = torch.eye(3, dtype=D).expand_as(K)
+    return I + torch.sin(th)[..., None] * K + (1 - torch.cos(th))[..., None] * (K @ K)
+
+
+def test_oriented_reading_closed_forms():
+    dt = 0.01
+    s = torch.zeros(3, 9, dtype=D)
+    s[:, 6:9] = torch.tensor([0.0, 0.0, dyn.G], dtype=D)     # PM9 hovering
+    prm = torch.tensor([[20.0, 0.1]] * 3, dtype=D)
+    R = torch.stack([torch.eye(3, dtype=D), _rz(0.7), _rz(-2.0)])
+    r = imu.reading_oriented(dyn.PM9, s, None, prm, R, R, dt)
+    assert torch.allclose(r, torch.tensor([[0.0, 0.0, dyn.G, 0.0, 0.0, 0.0]] * 3, dtype=D), atol=1e-12)
+    # drag: world specific force (-d v, 0, 0) seen after a yaw of +90 deg
+    s[:, 6:9] = 0.0
+    s[:, 3] = 1.0
+    r = imu.reading_oriented(dyn.PM9, s, None, prm, _rz(math.pi / 2).expand(3, 3, 3), _rz(math.pi / 2).expand(3, 3, 3), dt)
+    assert torch.allclose(r[:, :3], torch.tensor([0.0, 0.1, 0.0], dtype=D).expand(3, 3), atol=1e-12)
+    # gyro: a yaw step of 0.02 rad, a body roll step of 0.01 rad
+    Rp = _rz(0.3).expand(2, 3, 3)
+    Rn = torch.stack([_rz(0.32), _rz(0.3) @ _rx(0.01)])
+    w = imu.reading_oriented(dyn.PM6, torch.zeros(2, 6, dtype=D), torch.zeros(2, 3, dtype=D), None, Rn, Rp, dt)[:, 3:]
+    assert torch.allclose(w, torch.tensor([[0.0, 0.0, 2.0], [1.0, 0.0, 0.0]], dtype=D), atol=1e-12)
+    # PMD reads its applied acceleration, PM6 its command
+    sd = torch.zeros(1, 9, dtype=D)
+    sd[0, 6:9] = torch.tensor([1.0, 2.0, 3.0])
+    assert torch.allclose(imu.specific_force_pm(dyn.PMD, sd, None, None), sd[:, 6:9])
+    with pytest.raises(ValueError):
+        imu.specific_force_pm(dyn.RB13, torch.zeros(1, 13, dtype=D), None, None)
+
+
+def test_oriented_gyro_inverts_rodrigues():
+    """log(R_prev^T R) / dt recovers the body rate that Rodrigues' formula
+    turned R_prev into R with, for random rates and attitudes."""
+    g = torch.Generator().manual_seed(4)
+    dt = 0.01
+    w = torch.randn(50, 3, generator=g, dtype=D) * 3.0
+    Rp = _exp_rot(torch.randn(50, 3, generator=g, dtype=D))
+    R = Rp @ _exp_rot(w * dt)
+    out = imu.reading_oriented(dyn.PM6, torch.zeros(50, 6, dtype=D), torch.zeros(50, 3, dtype=D), None, R, Rp, dt)
+    assert torch.allclose(out[:, 3:], w, atol=1e-9)
