@@ -281,11 +281,23 @@ typedef struct {
 /* One IMU reading per agent at (s, a) (as sim_step's inputs): out [6][A]
  * (f_x, f_y, f_z, w_x, w_y, w_z) SoA; bias [6][A] SoA in/out (the caller
  * zeroes it at the start of a rollout; updated in place before the reading);
- * t is the step index. Errors: SIM_EINVAL for point-mass models (their
- * attitude rule is not built), null arguments, negative sigmas, missing
- * parameters. */
+ * t is the step index. Errors: SIM_EINVAL for point-mass models (they take
+ * sim_imu_oriented with the attitude rule's R), null arguments, negative
+ * sigmas, missing parameters. */
 int sim_imu(sim_handle* h, const float* s, const float* a, float* bias, const imu_config* cfg, uint64_t seed,
             int64_t t, float* out, void* stream);
+
+/* IMU of the point-mass models (SIM_PM6 / SIM_PM9 / SIM_PMD), which have an
+ * attitude only through the attitude rule (Sec. III-B; sim_pm_attitude):
+ * accelerometer R^T (dv/dt - g) with the model's specific force (the action
+ * for SIM_PM6, a - d v for SIM_PM9, the applied acceleration for SIM_PMD);
+ * gyroscope log(R_prev^T R) / dt, the body rate that turns the previous
+ * step's attitude R_prev into R over the step (a reading: the rule defines
+ * attitudes, not rates; angles below pi per step). R, R_prev: row-major
+ * [9][A]. Drift, noise, bias, seed and t as sim_imu (the same normals). No
+ * adjoint. a may be NULL except for SIM_PM6. */
+int sim_imu_oriented(sim_handle* h, const float* s, const float* a, const float* R, const float* R_prev,
+                     float* bias, const imu_config* cfg, uint64_t seed, int64_t t, float* out, void* stream);
 
 /* Vector-Jacobian product of the noise-free IMU reading (the bias and noise
  * are additive and carry no gradient): g_s = (d out/d s)^T g_out,

@@ -104,6 +104,54 @@ __global__ void imu_kernel(int A, float dt, const float* __restrict__ s_in, cons
   }
 }
 
+// Point-mass models with the attitude rule: accelerometer R^T (dv/dt - g)
+// with the model's specific force (u for SIM_PM6, a - d v for SIM_PM9, the
+// applied u_prev for SIM_PMD), gyroscope log(R_prev^T R) / dt, the body rate
+// that turns the previous attitude into this one over the step (sin of the
+// angle times the axis from the skew part of Q = R_prev^T R, the cosine from
+// its trace, the angle by atan2). R, R_prev: row-major [9][A].
+template <int M>
+__global__ void imu_oriented_kernel(int A, float dt, const float* __restrict__ s_in, const float* __restrict__ a,
+                                    const float* __restrict__ prm, const float* __restrict__ R,
+                                    const float* __restrict__ Rp, float* __restrict__ bias, ImuSig sg,
+                                    uint64_t seed, int64_t t, float* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A) return;
+  float f[3];
+  for (int c = 0; c < 3; ++c) {
+    if (M == SIM_PM6) {
+      f[c] = a[(size_t)c * A + i];
+    } else if (M == SIM_PM9) {
+      f[c] = s_in[(size_t)(6 + c) * A + i] - prm[(size_t)A + i] * s_in[(size_t)(3 + c) * A + i];
+    } else {
+      f[c] = s_in[(size_t)(6 + c) * A + i];
+    }
+  }
+  float r[9], q[9], o[6], n[12];
+  for (int k = 0; k < 9; ++k) r[k] = R[(size_t)k * A + i];
+  for (int k = 0; k < 9; ++k) q[k] = Rp[(size_t)k * A + i];
+  // body frame: f_b[c] = sum_r R[r][c] f[r]
+  for (int c = 0; c < 3; ++c) o[c] = r[c] * f[0] + r[3 + c] * f[1] + r[6 + c] * f[2];
+  // Q = R_prev^T R: Q[x][y] = sum_r Rp[r][x] R[r][y]
+  float Q[3][3];
+  for (int x = 0; x < 3; ++x)
+    for (int y = 0; y < 3; ++y) Q[x][y] = q[x] * r[y] + q[3 + x] * r[3 + y] + q[6 + x] * r[6 + y];
+  const float wx = 0.5f * (Q[2][1] - Q[1][2]), wy = 0.5f * (Q[0][2] - Q[2][0]), wz = 0.5f * (Q[1][0] - Q[0][1]);
+  const float sn = sqrtf(wx * wx + wy * wy + wz * wz), cs = 0.5f * (Q[0][0] + Q[1][1] + Q[2][2] - 1.f);
+  const float scale = (sn > 1e-12f ? atan2f(sn, cs) / sn : 1.f) / dt;
+  o[3] = wx * scale;
+  o[4] = wy * scale;
+  o[5] = wz * scale;
+  imu_normals(seed, t, i, n);
+  const float sq = sqrtf(dt);
+  for (int c = 0; c < 6; ++c) {
+    const float sb = (c < 3 ? sg.bacc : sg.bgyro) * sq, sw = c < 3 ? sg.acc : sg.gyro;
+    const float b = bias[(size_t)c * A + i] + sb * n[c];
+    bias[(size_t)c * A + i] = b;
+    out[(size_t)c * A + i] = o[c] + b + sw * n[6 + c];
+  }
+}
+
 // g_s += (d(f, w)/ds)^T g, g_a += (d(f, w)/da)^T g
 template <int M>
 __global__ void imu_vjp_kernel(int A, const float* __restrict__ s_in, const float* __restrict__ a,
@@ -166,6 +214,33 @@ int sim_imu(sim_handle* h, const float* s, const float* a, float* bias, const im
     hipLaunchKernelGGL(imu_kernel<SIM_NOMINAL13>, dim3(cdiv(A, 256)), dim3(256), 0, st, A, h->cfg.dt, s, a,
                        h->params, bias, sg, seed, t, out);
   DA_LAUNCH_CHECK("imu_kernel");
+  return SIM_OK;
+}
+
+int sim_imu_oriented(sim_handle* h, const float* s, const float* a, const float* R, const float* R_prev, float* bias,
+                     const imu_config* cfg, uint64_t seed, int64_t t, float* out, void* stream) {
+  DA_REQUIRE(h && s && R && R_prev && bias && cfg && out, "sim_imu_oriented: null argument");
+  const int m = h->cfg.model;
+  DA_REQUIRE(m == SIM_PM6 || m == SIM_PM9 || m == SIM_PMD, "sim_imu_oriented: the oriented IMU is for the point-mass models");
+  DA_REQUIRE(a || m != SIM_PM6, "sim_imu_oriented: SIM_PM6 needs the action (its thrust)");
+  DA_REQUIRE(h->params || m != SIM_PM9, "sim_imu_oriented: parameters not set");
+  DA_REQUIRE(cfg->sigma_acc >= 0.f && cfg->sigma_gyro >= 0.f && cfg->sigma_bacc >= 0.f && cfg->sigma_bgyro >= 0.f,
+             "sim_imu_oriented: sigmas must be >= 0");
+  DA_REQUIRE(t >= 0, "sim_imu_oriented: t must be >= 0");
+  const int A = h->cfg.n_agents;
+  const ImuSig sg{cfg->sigma_acc, cfg->sigma_gyro, cfg->sigma_bacc, cfg->sigma_bgyro};
+  hipStream_t st = as_stream(stream);
+  const dim3 grid(cdiv(A, 256)), blk(256);
+  if (m == SIM_PM6)
+    hipLaunchKernelGGL(imu_oriented_kernel<SIM_PM6>, grid, blk, 0, st, A, h->cfg.dt, s, a, h->params, R, R_prev, bias,
+                       sg, seed, t, out);
+  else if (m == SIM_PM9)
+    hipLaunchKernelGGL(imu_oriented_kernel<SIM_PM9>, grid, blk, 0, st, A, h->cfg.dt, s, a, h->params, R, R_prev, bias,
+                       sg, seed, t, out);
+  else
+    hipLaunchKernelGGL(imu_oriented_kernel<SIM_PMD>, grid, blk, 0, st, A, h->cfg.dt, s, a, h->params, R, R_prev, bias,
+                       sg, seed, t, out);
+  DA_LAUNCH_CHECK("imu_oriented_kernel");
   return SIM_OK;
 }
 

@@ -124,6 +124,15 @@ class Env:
         _lib.sim_imu(self.h, s, a, bias, cfg, seed, t, out)
         return out
 
+    def imu_oriented(self, s, a, R, R_prev, bias, t, seed=0, sigma_acc=0.0, sigma_gyro=0.0, sigma_bacc=0.0,
+                     sigma_bgyro=0.0):
+        """Point-mass IMU reading [6, A] from the attitudes R and R_prev
+        ([9, A], row-major); bias [6, A] is updated in place."""
+        cfg = _lib.ImuConfig(sigma_acc, sigma_gyro, sigma_bacc, sigma_bgyro)
+        out = torch.empty(6, self.n_agents, device="cuda")
+        _lib.sim_imu_oriented(self.h, s, a, R, R_prev, bias, cfg, seed, t, out)
+        return out
+
     def imu_backward(self, s, a, g_out):
         """(d reading/d s)^T g_out and (d reading/d a)^T g_out of the noise-free reading."""
         g_s = torch.zeros_like(s)

@@ -86,3 +86,53 @@ def test_imu_rejects_point_mass():
     a = torch.zeros(3, 8, device="cuda")
     with pytest.raises(RuntimeError, match="rigid-body"):
         e.imu(s, a, torch.zeros(6, 8, device="cuda"), t=0)
+
+
+@pytest.mark.parametrize("model", [wl.PM6, wl.PM9, wl.PMD])
+def test_oriented_imu_matches_oracle(model):
+    """Point-mass IMU from two successive attitudes of the attitude rule,
+    1000 agents, three readings with drift and noise. The gyroscope's
+    tolerance is derived: the entries of R_prev^T R carry FP32 rounding of
+    about 3e-7, divided by dt = 0.01 that is 3e-5 rad/s, bounded by 1e-4."""
+    from paper_2509_10247_amd import env
+    from oracle import attitude as oatt
+    rng = np.random.default_rng(31 + model)
+    A = 1000
+    p0 = wl.start_positions(rng, A, wl.ROOM_C2)
+    wk = wl.Workload("pm", model, wl.EULER, 0.01, 1, wl.make_scene(rng, A, 0, 0, wl.ROOM_C2, (0.3, 1), (0.2, 1),
+                     room=False), wl.initial_state(rng, model, p0), wl.params(rng, model, A), None, None, None)
+    e = env.from_workload(wk)
+    s = wk.state0.copy()
+    if model != wl.PM6:
+        s[6:9] = (rng.normal(size=(3, A)) * 3 + np.array([[0], [0], [9.81]])).astype(np.float32)
+    a = (rng.normal(size=(3, A)) * 3 + np.array([[0], [0], [9.81]])).astype(np.float32)
+    ema = rng.normal(size=(3, A)).astype(np.float32)
+    s_c, a_c, ema_c = cuda(s), cuda(a), cuda(ema)
+    R_prev = e.pm_attitude(s_c, a_c, ema_c, 0.2)
+    s2 = s.copy()
+    s2[3:6] += rng.normal(size=(3, A)).astype(np.float32) * 0.5   # the velocity turns the heading
+    s2_c = cuda(s2)
+    R = e.pm_attitude(s2_c, a_c, ema_c, 0.2)
+    bias = torch.zeros(6, A, device="cuda")
+    bo = torch.zeros(A, 6, dtype=D)
+    so = torch.tensor(s2.T.astype(np.float64))
+    ao = torch.tensor(a.T.astype(np.float64))
+    po = torch.tensor(wk.params.T.astype(np.float64)) if len(wk.params) else None
+    Ro, Rpo = f64(R).T.reshape(A, 3, 3), f64(R_prev).T.reshape(A, 3, 3)
+    print_case("imu_oriented", model=model, A=A)
+    for t in range(3):
+        out = e.imu_oriented(s2_c, a_c, R, R_prev, bias, t=t, seed=5, sigma_acc=SIG[0], sigma_gyro=SIG[1],
+                             sigma_bacc=SIG[2], sigma_bgyro=SIG[3])
+        ref, bo = oimu.imu_step_oriented(model, so, ao, po, Ro, Rpo, bo, SIG, seed=5, t=t, dt=0.01)
+        g = f64(out).T
+        assert _close(g[:, :3], ref[:, :3]), f"accelerometer: {(g[:, :3] - ref[:, :3]).abs().max():.3e}"
+        # near a half turn per step the rotation axis is ill-conditioned
+        # (error ~ 1 / sin(angle)); the reading holds for angles below pi
+        ang = oimu.log_rot(Rpo.transpose(1, 2) @ Ro).norm(dim=1)
+        well = ang < 3.0
+        assert well.float().mean() > 0.99
+        gerr = (g[:, 3:] - ref[:, 3:]).abs()[well]
+        assert (gerr <= 1e-4).all(), f"gyro: {gerr.max():.3e}"
+        assert _close(f64(bias).T, bo)
+    # the attitude really turned: the gyroscope reads a rate
+    assert (ref[:, 3:].abs().max(1).values > 0.1).float().mean() > 0.5
