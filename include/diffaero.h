@@ -294,10 +294,18 @@ int sim_imu(sim_handle* h, const float* s, const float* a, float* bias, const im
  * gyroscope log(R_prev^T R) / dt, the body rate that turns the previous
  * step's attitude R_prev into R over the step (a reading: the rule defines
  * attitudes, not rates; angles below pi per step). R, R_prev: row-major
- * [9][A]. Drift, noise, bias, seed and t as sim_imu (the same normals). No
- * adjoint. a may be NULL except for SIM_PM6. */
+ * [9][A]. Drift, noise, bias, seed and t as sim_imu (the same normals).
+ * a may be NULL except for SIM_PM6. */
 int sim_imu_oriented(sim_handle* h, const float* s, const float* a, const float* R, const float* R_prev,
                      float* bias, const imu_config* cfg, uint64_t seed, int64_t t, float* out, void* stream);
+
+/* Vector-Jacobian product of sim_imu_oriented's noise-free reading: with
+ * g_out [6][A], accumulates (+=) into g_s [C][A] (acceleration rows, and the
+ * velocity rows through SIM_PM9's drag), g_a [3][A] (SIM_PM6; nullable),
+ * g_R and g_R_prev [9][A] (nullable). */
+int sim_imu_oriented_backward(sim_handle* h, const float* s, const float* a, const float* R, const float* R_prev,
+                              const float* g_out, float* g_s, float* g_a, float* g_R, float* g_R_prev,
+                              void* stream);
 
 /* Vector-Jacobian product of the noise-free IMU reading (the bias and noise
  * are additive and carry no gradient): g_s = (d out/d s)^T g_out,

@@ -69,6 +69,7 @@ _SIGS = {
     "sim_imu_backward": (c_int, [c_void_p] * 7),
     "sim_imu_oriented": (c_int, [c_void_p] * 6 + [ctypes.POINTER(ImuConfig), ctypes.c_uint64, c_int64, c_void_p,
                                                    c_void_p]),
+    "sim_imu_oriented_backward": (c_int, [c_void_p] * 11),
     "sim_pm_attitude": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_float, c_void_p, c_void_p]),
     "sim_pm_attitude_backward": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_float] + [c_void_p] * 6),
     "sim_render_oriented": (c_int, [c_void_p] * 8),
@@ -222,6 +223,12 @@ def sim_imu_oriented(h, s, a, R, R_prev, bias, cfg, seed, t, out):
     _call("sim_imu_oriented", h, ptr(s, torch.float32), ptr(a, torch.float32), ptr(R, torch.float32),
           ptr(R_prev, torch.float32), ptr(bias, torch.float32), ctypes.byref(cfg), int(seed) & ((1 << 64) - 1), int(t),
           ptr(out, torch.float32), stream())
+
+
+def sim_imu_oriented_backward(h, s, a, R, R_prev, g_out, g_s, g_a=None, g_R=None, g_R_prev=None):
+    _call("sim_imu_oriented_backward", h, ptr(s, torch.float32), ptr(a, torch.float32), ptr(R, torch.float32),
+          ptr(R_prev, torch.float32), ptr(g_out, torch.float32), ptr(g_s, torch.float32), ptr(g_a, torch.float32),
+          ptr(g_R, torch.float32), ptr(g_R_prev, torch.float32), stream())
 
 
 def sim_pm_attitude(h, s, a, ema, alpha, R):

@@ -152,6 +152,77 @@ __global__ void imu_oriented_kernel(int A, float dt, const float* __restrict__ s
   }
 }
 
+// Adjoint of the point-mass reading (noise and bias are additive). With
+// Q = R_prev^T R, w = vee(Q - Q^T) / 2, sn = |w|, cs = (tr Q - 1) / 2,
+// theta = atan2(sn, cs) and k = theta / sn, the gyroscope reads k w / dt:
+//   dk/dsn = (cs / (sn^2 + cs^2) - k) / sn, dk/dcs = -1 / (sn^2 + cs^2)
+// (k -> 1, dk/dsn -> 0 as sn -> 0); then dL/dR = R_prev G_Q and
+// dL/dR_prev = R G_Q^T. The accelerometer R^T f gives dL/dR[r][c] = f_r g_c
+// and dL/df = R g, pulled back to the state or the action.
+template <int M>
+__global__ void imu_oriented_vjp_kernel(int A, float dt, const float* __restrict__ s_in,
+                                        const float* __restrict__ prm, const float* __restrict__ R,
+                                        const float* __restrict__ Rp, const float* __restrict__ g_out,
+                                        const float* __restrict__ a, float* __restrict__ g_s, float* __restrict__ g_a,
+                                        float* __restrict__ g_R, float* __restrict__ g_Rp) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A) return;
+  float r[9], q[9], g[6], f[3];
+  for (int k = 0; k < 9; ++k) r[k] = R[(size_t)k * A + i];
+  for (int k = 0; k < 9; ++k) q[k] = Rp[(size_t)k * A + i];
+  for (int c = 0; c < 6; ++c) g[c] = g_out[(size_t)c * A + i];
+  const float d = M == SIM_PM9 ? prm[(size_t)A + i] : 0.f;
+  for (int c = 0; c < 3; ++c) {
+    if (M == SIM_PM6) f[c] = a[(size_t)c * A + i];
+    else if (M == SIM_PM9) f[c] = s_in[(size_t)(6 + c) * A + i] - d * s_in[(size_t)(3 + c) * A + i];
+    else f[c] = s_in[(size_t)(6 + c) * A + i];
+  }
+  float GR[9];
+  // accelerometer: out_c = sum_r R[r][c] f_r
+  for (int rr = 0; rr < 3; ++rr)
+    for (int c = 0; c < 3; ++c) GR[3 * rr + c] = f[rr] * g[c];
+  float gf[3];
+  for (int rr = 0; rr < 3; ++rr) gf[rr] = r[3 * rr] * g[0] + r[3 * rr + 1] * g[1] + r[3 * rr + 2] * g[2];
+  // gyroscope
+  float Q[3][3];
+  for (int x = 0; x < 3; ++x)
+    for (int y = 0; y < 3; ++y) Q[x][y] = q[x] * r[y] + q[3 + x] * r[3 + y] + q[6 + x] * r[6 + y];
+  const float w[3] = {0.5f * (Q[2][1] - Q[1][2]), 0.5f * (Q[0][2] - Q[2][0]), 0.5f * (Q[1][0] - Q[0][1])};
+  const float sn = sqrtf(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]), cs = 0.5f * (Q[0][0] + Q[1][1] + Q[2][2] - 1.f);
+  const float h2 = sn * sn + cs * cs;
+  float k = 1.f, dk_dsn = 0.f, dk_dcs = -1.f / h2;
+  if (sn > 1e-6f) {
+    k = atan2f(sn, cs) / sn;
+    dk_dsn = (cs / h2 - k) / sn;
+  }
+  const float inv_dt = 1.f / dt;
+  const float gw_dot = (w[0] * g[3] + w[1] * g[4] + w[2] * g[5]) * inv_dt;
+  float gwv[3];
+  for (int c = 0; c < 3; ++c) gwv[c] = k * g[3 + c] * inv_dt + (sn > 1e-6f ? gw_dot * dk_dsn * w[c] / sn : 0.f);
+  const float gcs = gw_dot * dk_dcs;
+  float GQ[3][3] = {{0.5f * gcs, -0.5f * gwv[2], 0.5f * gwv[1]},
+                    {0.5f * gwv[2], 0.5f * gcs, -0.5f * gwv[0]},
+                    {-0.5f * gwv[1], 0.5f * gwv[0], 0.5f * gcs}};
+  // dL/dR = R_prev G_Q, dL/dR_prev = R G_Q^T
+  if (g_R)
+    for (int x = 0; x < 3; ++x)
+      for (int y = 0; y < 3; ++y)
+        g_R[(size_t)(3 * x + y) * A + i] += GR[3 * x + y] + q[3 * x] * GQ[0][y] + q[3 * x + 1] * GQ[1][y] +
+                                            q[3 * x + 2] * GQ[2][y];
+  if (g_Rp)
+    for (int x = 0; x < 3; ++x)
+      for (int y = 0; y < 3; ++y)
+        g_Rp[(size_t)(3 * x + y) * A + i] += r[3 * x] * GQ[y][0] + r[3 * x + 1] * GQ[y][1] + r[3 * x + 2] * GQ[y][2];
+  for (int c = 0; c < 3; ++c) {
+    if (M == SIM_PM6) {
+      if (g_a) g_a[(size_t)c * A + i] += gf[c];
+    } else {
+      g_s[(size_t)(6 + c) * A + i] += gf[c];
+      if (M == SIM_PM9) g_s[(size_t)(3 + c) * A + i] -= d * gf[c];
+    }
+  }
+}
+
 // g_s += (d(f, w)/ds)^T g, g_a += (d(f, w)/da)^T g
 template <int M>
 __global__ void imu_vjp_kernel(int A, const float* __restrict__ s_in, const float* __restrict__ a,
@@ -241,6 +312,30 @@ int sim_imu_oriented(sim_handle* h, const float* s, const float* a, const float*
     hipLaunchKernelGGL(imu_oriented_kernel<SIM_PMD>, grid, blk, 0, st, A, h->cfg.dt, s, a, h->params, R, R_prev, bias,
                        sg, seed, t, out);
   DA_LAUNCH_CHECK("imu_oriented_kernel");
+  return SIM_OK;
+}
+
+int sim_imu_oriented_backward(sim_handle* h, const float* s, const float* a, const float* R, const float* R_prev,
+                              const float* g_out, float* g_s, float* g_a, float* g_R, float* g_R_prev, void* stream) {
+  DA_REQUIRE(h && s && R && R_prev && g_out && g_s, "sim_imu_oriented_backward: null argument");
+  const int m = h->cfg.model;
+  DA_REQUIRE(m == SIM_PM6 || m == SIM_PM9 || m == SIM_PMD,
+             "sim_imu_oriented_backward: the oriented IMU is for the point-mass models");
+  DA_REQUIRE(a || m != SIM_PM6, "sim_imu_oriented_backward: SIM_PM6 needs the action (its thrust)");
+  DA_REQUIRE(h->params || m != SIM_PM9, "sim_imu_oriented_backward: parameters not set");
+  const int A = h->cfg.n_agents;
+  hipStream_t st = as_stream(stream);
+  const dim3 grid(cdiv(A, 256)), blk(256);
+  if (m == SIM_PM6)
+    hipLaunchKernelGGL(imu_oriented_vjp_kernel<SIM_PM6>, grid, blk, 0, st, A, h->cfg.dt, s, h->params, R, R_prev,
+                       g_out, a, g_s, g_a, g_R, g_R_prev);
+  else if (m == SIM_PM9)
+    hipLaunchKernelGGL(imu_oriented_vjp_kernel<SIM_PM9>, grid, blk, 0, st, A, h->cfg.dt, s, h->params, R, R_prev,
+                       g_out, a, g_s, g_a, g_R, g_R_prev);
+  else
+    hipLaunchKernelGGL(imu_oriented_vjp_kernel<SIM_PMD>, grid, blk, 0, st, A, h->cfg.dt, s, h->params, R, R_prev,
+                       g_out, a, g_s, g_a, g_R, g_R_prev);
+  DA_LAUNCH_CHECK("imu_oriented_vjp_kernel");
   return SIM_OK;
 }
 

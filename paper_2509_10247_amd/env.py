@@ -133,6 +133,15 @@ class Env:
         _lib.sim_imu_oriented(self.h, s, a, R, R_prev, bias, cfg, seed, t, out)
         return out
 
+    def imu_oriented_backward(self, s, a, R, R_prev, g_out):
+        """(g_s, g_a, g_R, g_R_prev) of the point-mass reading."""
+        g_s = torch.zeros_like(s)
+        g_a = torch.zeros(3, self.n_agents, device="cuda")
+        g_R = torch.zeros(9, self.n_agents, device="cuda")
+        g_Rp = torch.zeros(9, self.n_agents, device="cuda")
+        _lib.sim_imu_oriented_backward(self.h, s, a, R, R_prev, g_out, g_s, g_a, g_R, g_Rp)
+        return g_s, g_a, g_R, g_Rp
+
     def imu_backward(self, s, a, g_out):
         """(d reading/d s)^T g_out and (d reading/d a)^T g_out of the noise-free reading."""
         g_s = torch.zeros_like(s)

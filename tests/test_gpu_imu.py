@@ -7,7 +7,7 @@ import torch
 import workloads as wl
 from oracle import dynamics as odyn
 from oracle import imu as oimu
-from tests.helpers import cuda, f64, print_case
+from tests.helpers import cuda, f64, grad_close, print_case
 
 pytestmark = pytest.mark.gpu
 
@@ -136,3 +136,51 @@ def test_oriented_imu_matches_oracle(model):
         assert _close(f64(bias).T, bo)
     # the attitude really turned: the gyroscope reads a rate
     assert (ref[:, 3:].abs().max(1).values > 0.1).float().mean() > 0.5
+
+
+@pytest.mark.parametrize("model", [wl.PM6, wl.PM9, wl.PMD])
+def test_oriented_imu_backward_matches_autograd(model):
+    """Adjoint of the point-mass reading into the state, the action and both
+    attitudes, against autograd through the oracle's reading (rotations
+    of 0.2 to 1.5 rad per step and one of zero, the small-angle branch)."""
+    from paper_2509_10247_amd import env
+    rng = np.random.default_rng(41 + model)
+    A = 600
+    p0 = wl.start_positions(rng, A, wl.ROOM_C2)
+    wk = wl.Workload("pm", model, wl.EULER, 0.01, 1, wl.make_scene(rng, A, 0, 0, wl.ROOM_C2, (0.3, 1), (0.2, 1),
+                     room=False), wl.initial_state(rng, model, p0), wl.params(rng, model, A), None, None, None)
+    e = env.from_workload(wk)
+    s = wk.state0.copy()
+    if model != wl.PM6:
+        s[6:9] = rng.normal(size=(3, A)).astype(np.float32) * 3
+    a = rng.normal(size=(3, A)).astype(np.float32) * 3
+    g = torch.Generator().manual_seed(6)
+
+    def rot(v):
+        th = v.norm(dim=1, keepdim=True)
+        K = torch.zeros(v.shape[0], 3, 3, dtype=D)
+        k = v / th
+        K[:, 0, 1], K[:, 0, 2], K[:, 1, 2] = -k[:, 2], k[:, 1], -k[:, 0]
+        K = K - K.transpose(1, 2)
+        return torch.eye(3, dtype=D) + torch.sin(th)[..., None] * K + (1 - torch.cos(th))[..., None] * (K @ K)
+
+    Rp = rot(torch.randn(A, 3, generator=g, dtype=D))
+    step = torch.randn(A, 3, generator=g, dtype=D)
+    step = step / step.norm(dim=1, keepdim=True) * (0.2 + 1.3 * torch.rand(A, 1, generator=g, dtype=D))
+    R = Rp @ rot(step)
+    R[0] = Rp[0]
+    Rf, Rpf = R.float(), Rp.float()
+    R_c, Rp_c = cuda(Rf.reshape(A, 9).T.numpy()), cuda(Rpf.reshape(A, 9).T.numpy())
+    go = torch.randn(6, A, generator=g).float()
+    g_s, g_a, g_R, g_Rp = e.imu_oriented_backward(cuda(s), cuda(a), R_c, Rp_c, cuda(go.numpy()))
+    so = torch.tensor(s.T.astype(np.float64), requires_grad=True)
+    ao = torch.tensor(a.T.astype(np.float64), requires_grad=True)
+    Ro = Rf.double().requires_grad_(True)
+    Rpo = Rpf.double().requires_grad_(True)
+    po = torch.tensor(wk.params.T.astype(np.float64)) if len(wk.params) else None
+    (oimu.reading_oriented(model, so, ao, po, Ro, Rpo, 0.01) * go.double().T).sum().backward()
+    checks = [("g_R", f64(g_R).T.reshape(A, 3, 3), Ro.grad), ("g_R_prev", f64(g_Rp).T.reshape(A, 3, 3), Rpo.grad)]
+    checks += [("g_a", f64(g_a).T, ao.grad)] if model == wl.PM6 else [("g_s", f64(g_s).T, so.grad)]
+    for name, gpu, ref in checks:
+        ok, rel, _ = grad_close(gpu, ref)
+        assert ok, f"{name}: rel err {rel:.2e}"
