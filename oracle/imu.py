@@ -2,8 +2,8 @@
 see the package header: only the tests, the smoke check and the CPU baseline
 may import it).
 
-Sec. III-B gives the IMU "configurable noise and drift parameters" and no
-model; the reading implemented here (and by the kernels) is:
+Sec. III-B lists an IMU whose noise and drift can be set, without a model
+for either; the reading implemented here (and by the kernels) is:
 
   * accelerometer: the body-frame specific force over the step,
     f = R^T (dv/dt - g), with dv/dt the model's right-hand side at (s, a)
@@ -115,17 +115,38 @@ def specific_force_pm(model: int, s: torch.Tensor, u: torch.Tensor, prm: torch.T
     raise ValueError("the oriented IMU is for the point-mass models")
 
 
+LOG_SMALL = 1e-6      # below it (cosine >= 0) theta / sin(theta) is 1 in FP32
+LOG_HALF_TURN = 1e-2  # sin(theta) below it with cosine < 0: within 0.6 deg of a half turn
+
+
 def log_rot(Q: torch.Tensor) -> torch.Tensor:
-    """Rotation vector [A, 3] (axis times angle) of rotations Q [A, 3, 3]
-    with angles below pi: sin(angle) axis from the skew part, cos(angle)
-    from the trace."""
+    """Rotation vector [A, 3] (axis times angle) of rotations Q [A, 3, 3].
+
+    Regular case: sin(angle) times the axis from the skew part, cos(angle)
+    from the trace, the angle by atan2. Within LOG_HALF_TURN of a half turn
+    the skew part no longer fixes the axis (it is of the size of rounding), so
+    the axis comes from the symmetric part, (Q + Q^T)/2 - cos(angle) I =
+    (1 - cos(angle)) n n^T: its column with the largest diagonal, normalised,
+    with the sign of the skew part. That branch is taken as a constant (no
+    gradient flows through it); the kernels read the same branches."""
     w = 0.5 * torch.stack([Q[:, 2, 1] - Q[:, 1, 2], Q[:, 0, 2] - Q[:, 2, 0], Q[:, 1, 0] - Q[:, 0, 1]], -1)
     sn = w.norm(dim=-1)
     cs = 0.5 * (Q.diagonal(dim1=1, dim2=2).sum(-1) - 1.0)
     theta = torch.atan2(sn, cs)
-    ok = sn > 1e-12
+    ok = sn > LOG_SMALL
     scale = torch.where(ok, theta / torch.where(ok, sn, torch.ones_like(sn)), torch.ones_like(sn))
-    return w * scale[:, None]
+    regular = w * scale[:, None]
+    half = (cs < 0) & (sn <= LOG_HALF_TURN)
+    if not bool(half.any()):
+        return regular
+    with torch.no_grad():
+        B = 0.5 * (Q + Q.transpose(1, 2)) - cs[:, None, None] * torch.eye(3, dtype=Q.dtype)
+        j = B.diagonal(dim1=1, dim2=2).argmax(-1)
+        col = B[torch.arange(Q.shape[0]), :, j]
+        n = col / col.norm(dim=-1, keepdim=True)
+        n = torch.where(((n * w).sum(-1) < 0)[:, None], -n, n)
+        turn = theta[:, None] * n
+    return torch.where(half[:, None], turn, regular)
 
 
 def reading_oriented(model, s, u, prm, R, R_prev, dt):

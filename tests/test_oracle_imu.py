@@ -190,3 +190,44 @@ def test_oriented_gyro_inverts_rodrigues():
     R = Rp @ _exp_rot(w * dt)
     out = imu.reading_oriented(dyn.PM6, torch.zeros(50, 6, dtype=D), torch.zeros(50, 3, dtype=D), None, R, Rp, dt)
     assert torch.allclose(out[:, 3:], w, atol=1e-9)
+
+
+@pytest.mark.parametrize("delta", [0.0, 1e-9, 1e-5, 1e-3, 9.9e-3, 1.01e-2, 0.1, 1.0])
+def test_log_near_a_half_turn(delta):
+    """Rotations by pi - delta about random axes: the logarithm is
+    (pi - delta) n. Below sin(delta) = 1e-2 the axis comes from the symmetric
+    part and is signed along the skew part (a wrong sign fails every
+    delta > 0); at delta = 0 the sign is free. No gradient flows through that
+    branch; the regular branch keeps its gradient."""
+    g = torch.Generator().manual_seed(17)
+    n = torch.randn(30, 3, generator=g, dtype=D)
+    n = n / n.norm(dim=1, keepdim=True)
+    R = _exp_rot(n * (math.pi - delta)).clone().requires_grad_(True)
+    lg = imu.log_rot(R)
+    want = n * (math.pi - delta)
+    if delta == 0.0:
+        err = torch.minimum((lg - want).norm(dim=1), (lg + want).norm(dim=1))
+    else:
+        err = (lg - want).norm(dim=1)
+    assert err.max().item() < 1e-9, err.max().item()
+    lg.sum().backward()
+    if math.sin(delta) <= imu.LOG_HALF_TURN:
+        assert R.grad.abs().max().item() == 0.0
+    else:
+        assert R.grad.abs().max().item() > 0.1
+
+
+def test_log_branches_agree_at_their_boundaries():
+    """Just inside and just outside sin(angle) = LOG_HALF_TURN the two
+    formulas give the same rotation vector, and theta / sin(theta) -> 1 at
+    the small-angle threshold."""
+    g = torch.Generator().manual_seed(18)
+    n = torch.randn(20, 3, generator=g, dtype=D)
+    n = n / n.norm(dim=1, keepdim=True)
+    d0 = math.asin(imu.LOG_HALF_TURN)
+    for d in (d0 * (1 - 1e-9), d0 * (1 + 1e-9)):
+        lg = imu.log_rot(_exp_rot(n * (math.pi - d)))
+        assert torch.allclose(lg, n * (math.pi - d), atol=1e-9)
+    for a in (imu.LOG_SMALL * 0.5, imu.LOG_SMALL * 2):
+        lg = imu.log_rot(_exp_rot(n * a))
+        assert torch.allclose(lg, n * a, rtol=0, atol=1e-15)
