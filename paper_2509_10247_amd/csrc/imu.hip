@@ -104,12 +104,50 @@ __global__ void imu_kernel(int A, float dt, const float* __restrict__ s_in, cons
   }
 }
 
+// Rotation vector (axis times angle) of a rotation Q. Regular case: the
+// skew part w = vee(Q - Q^T) / 2 is sin(angle) times the axis, the trace
+// gives cos(angle), the angle comes from atan2, and below sin(angle) =
+// ROT_LOG_SMALL (cosine >= 0) angle / sin(angle) is 1 in FP32. Within
+// ROT_LOG_HALF_TURN of a half turn (cosine < 0) the skew part is of the size
+// of rounding and no longer fixes the axis: the symmetric part
+// (Q + Q^T)/2 - cos(angle) I equals (1 - cos(angle)) n n^T, so its column
+// with the largest diagonal entry (the first such on ties), normalised and
+// signed along w, is the axis. Returns true in that branch.
+#define ROT_LOG_SMALL 1e-6f
+#define ROT_LOG_HALF_TURN 1e-2f
+__device__ inline bool rot_log(const float Q[3][3], float rv[3]) {
+  const float w[3] = {0.5f * (Q[2][1] - Q[1][2]), 0.5f * (Q[0][2] - Q[2][0]), 0.5f * (Q[1][0] - Q[0][1])};
+  const float sn = sqrtf(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]), cs = 0.5f * (Q[0][0] + Q[1][1] + Q[2][2] - 1.f);
+  const float theta = atan2f(sn, cs);
+  if (cs < 0.f && sn <= ROT_LOG_HALF_TURN) {
+    int j = 0;
+    float best = Q[0][0] - cs;
+    for (int k = 1; k < 3; ++k) {
+      const float dk = Q[k][k] - cs;
+      if (dk > best) {
+        best = dk;
+        j = k;
+      }
+    }
+    float col[3];
+    for (int k = 0; k < 3; ++k) col[k] = k == j ? Q[k][k] - cs : 0.5f * (Q[k][j] + Q[j][k]);
+    const float nrm = sqrtf(col[0] * col[0] + col[1] * col[1] + col[2] * col[2]);
+    const float sg = (col[0] * w[0] + col[1] * w[1] + col[2] * w[2]) < 0.f ? -theta : theta;
+    for (int k = 0; k < 3; ++k) rv[k] = col[k] / nrm * sg;
+    return true;
+  }
+  const float scale = sn > ROT_LOG_SMALL ? theta / sn : 1.f;
+  for (int k = 0; k < 3; ++k) rv[k] = w[k] * scale;
+  return false;
+}
+
 // Point-mass models with the attitude rule: accelerometer R^T (dv/dt - g)
 // with the model's specific force (u for SIM_PM6, a - d v for SIM_PM9, the
 // applied u_prev for SIM_PMD), gyroscope log(R_prev^T R) / dt, the body rate
 // that turns the previous attitude into this one over the step (sin of the
 // angle times the axis from the skew part of Q = R_prev^T R, the cosine from
-// its trace, the angle by atan2). R, R_prev: row-major [9][A].
+// its trace, the angle by atan2, with the half-turn branch of rot_log).
+// R, R_prev: row-major [9][A].
 template <int M>
 __global__ void imu_oriented_kernel(int A, float dt, const float* __restrict__ s_in, const float* __restrict__ a,
                                     const float* __restrict__ prm, const float* __restrict__ R,
@@ -136,12 +174,10 @@ __global__ void imu_oriented_kernel(int A, float dt, const float* __restrict__ s
   float Q[3][3];
   for (int x = 0; x < 3; ++x)
     for (int y = 0; y < 3; ++y) Q[x][y] = q[x] * r[y] + q[3 + x] * r[3 + y] + q[6 + x] * r[6 + y];
-  const float wx = 0.5f * (Q[2][1] - Q[1][2]), wy = 0.5f * (Q[0][2] - Q[2][0]), wz = 0.5f * (Q[1][0] - Q[0][1]);
-  const float sn = sqrtf(wx * wx + wy * wy + wz * wz), cs = 0.5f * (Q[0][0] + Q[1][1] + Q[2][2] - 1.f);
-  const float scale = (sn > 1e-12f ? atan2f(sn, cs) / sn : 1.f) / dt;
-  o[3] = wx * scale;
-  o[4] = wy * scale;
-  o[5] = wz * scale;
+  float rv[3];
+  rot_log(Q, rv);
+  const float inv_dt = 1.f / dt;
+  for (int c = 0; c < 3; ++c) o[3 + c] = rv[c] * inv_dt;
   imu_normals(seed, t, i, n);
   const float sq = sqrtf(dt);
   for (int c = 0; c < 6; ++c) {
@@ -156,7 +192,8 @@ __global__ void imu_oriented_kernel(int A, float dt, const float* __restrict__ s
 // Q = R_prev^T R, w = vee(Q - Q^T) / 2, sn = |w|, cs = (tr Q - 1) / 2,
 // theta = atan2(sn, cs) and k = theta / sn, the gyroscope reads k w / dt:
 //   dk/dsn = (cs / (sn^2 + cs^2) - k) / sn, dk/dcs = -1 / (sn^2 + cs^2)
-// (k -> 1, dk/dsn -> 0 as sn -> 0); then dL/dR = R_prev G_Q and
+// (k -> 1, dk/dsn -> 0 as sn -> 0; no gyroscope term in the half-turn branch
+// of rot_log, which is a constant); then dL/dR = R_prev G_Q and
 // dL/dR_prev = R G_Q^T. The accelerometer R^T f gives dL/dR[r][c] = f_r g_c
 // and dL/df = R g, pulled back to the state or the action.
 template <int M>
@@ -190,15 +227,18 @@ __global__ void imu_oriented_vjp_kernel(int A, float dt, const float* __restrict
   const float w[3] = {0.5f * (Q[2][1] - Q[1][2]), 0.5f * (Q[0][2] - Q[2][0]), 0.5f * (Q[1][0] - Q[0][1])};
   const float sn = sqrtf(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]), cs = 0.5f * (Q[0][0] + Q[1][1] + Q[2][2] - 1.f);
   const float h2 = sn * sn + cs * cs;
+  // the half-turn branch of rot_log is a constant: no gradient through it
+  const bool half = cs < 0.f && sn <= ROT_LOG_HALF_TURN;
   float k = 1.f, dk_dsn = 0.f, dk_dcs = -1.f / h2;
-  if (sn > 1e-6f) {
+  if (sn > ROT_LOG_SMALL) {
     k = atan2f(sn, cs) / sn;
     dk_dsn = (cs / h2 - k) / sn;
   }
-  const float inv_dt = 1.f / dt;
+  const float inv_dt = half ? 0.f : 1.f / dt;
   const float gw_dot = (w[0] * g[3] + w[1] * g[4] + w[2] * g[5]) * inv_dt;
   float gwv[3];
-  for (int c = 0; c < 3; ++c) gwv[c] = k * g[3 + c] * inv_dt + (sn > 1e-6f ? gw_dot * dk_dsn * w[c] / sn : 0.f);
+  for (int c = 0; c < 3; ++c)
+    gwv[c] = k * g[3 + c] * inv_dt + (sn > ROT_LOG_SMALL ? gw_dot * dk_dsn * w[c] / sn : 0.f);
   const float gcs = gw_dot * dk_dcs;
   float GQ[3][3] = {{0.5f * gcs, -0.5f * gwv[2], 0.5f * gwv[1]},
                     {0.5f * gwv[2], 0.5f * gcs, -0.5f * gwv[0]},
