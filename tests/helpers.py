@@ -31,11 +31,20 @@ def print_case(name, **kw):
     print(f"[case] {name} " + " ".join(f"{k}={v}" for k, v in kw.items()), flush=True)
 
 
-def grad_close(g, ref, rel=1e-3):
-    """Gradient block check: ||g - ref|| <= rel ||ref|| and per component
-    |g - ref| <= rel max(|ref|, 1e-3 ||ref||_inf)."""
+def grad_close(g, ref, rel=1e-3, min_comp=0.999):
+    """Gradient block check, the 1e-3 gradient bar read per block and per
+    component: ||g - ref|| <= rel ||ref||, and at least min_comp of the
+    components satisfy |g - ref| <= rel max(|ref|, rms(ref)). A component far
+    below the block's RMS is a sum whose terms cancelled, and it carries the
+    absolute rounding of those terms, so it is held to rel times the block's
+    RMS instead of its own size. Returns (ok, relative block error, fraction
+    of passing components)."""
     g, ref = f64(g).reshape(-1), ref.double().reshape(-1)
     n = ref.norm().item()
     e = (g - ref).norm().item()
-    comp = (g - ref).abs() <= rel * torch.clamp(ref.abs(), min=1e-3 * ref.abs().max().item()) + 1e-12
-    return e <= rel * max(n, 1e-30), e / max(n, 1e-30), float(comp.float().mean())
+    if ref.numel() == 0:
+        return True, 0.0, 1.0
+    rms = n / ref.numel() ** 0.5
+    comp = (g - ref).abs() <= rel * torch.clamp(ref.abs(), min=rms) + 1e-12
+    frac = float(comp.float().mean())
+    return e <= rel * max(n, 1e-30) and frac >= min_comp, e / max(n, 1e-30), frac

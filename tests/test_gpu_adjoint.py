@@ -46,8 +46,12 @@ def test_step_vjp_parity(model, integ):
 
 @pytest.mark.parametrize("model", [wl.RB13, wl.PM9])
 def test_render_vjp_parity(model):
-    """Depth gradient pulled back to (p, q): GPU hand-written VJP vs oracle
-    autograd through the frozen (GPU-recorded) hit topology."""
+    """Depth gradient pulled back to (p, q): the GPU's hand-written VJP against
+    autograd through the oracle's render frozen to the oracle's own hit
+    records. Compared on the stable rays (record unchanged under 1e-5
+    perturbations of origin and direction, not grazing), where the GPU's
+    records must equal the oracle's; the other rays get no incoming gradient
+    on either side."""
     wk = wl.bptt(seed=7, n_envs=64, T=1, model=model)
     print_case("render_vjp", model=model, A=64)
     e = _env(wk)
@@ -58,25 +62,21 @@ def test_render_vjp_parity(model):
     W, H, hfov, mx = wk.cam
     db, zf = osen.camera_dirs(W, H, hfov)
     ds = osen.DenseScene(wk.scene)
-    rec = h.cpu().reshape(64, -1).long()
-    # a ray whose FP32 record names a sphere that FP64 says it just misses
-    # (|n.d| ~ 1e-4 or less) has no FP64 closed form to compare: drop it
-    with torch.no_grad():
-        vchk, _, _ = osen.render(model, ds, torch.tensor(wk.state0.T.astype(np.float64)), db, zf, mx,
-                                 frozen=rec)
-    drop = ~torch.isfinite(vchk)
-    assert drop.float().mean() < 1e-3
-    gd.reshape(64, -1)[drop.numpy()] = 0.0
+    st = torch.tensor(wk.state0.T.astype(np.float64))
+    ok, _, rec = osen.stable_rays(model, ds, st, db, zf, mx)
+    assert ok.float().mean().item() >= 0.999
+    assert torch.equal(h.cpu().reshape(64, -1).long()[ok], rec[ok]), "hit records differ on stable rays"
+    gd.reshape(64, -1)[~ok.numpy()] = 0.0
     zero = torch.zeros_like(s)
     a = torch.zeros(e.K, e.n_agents, device="cuda")
     if model == wl.RB13:
         a[0] = 9.81
     gs, _ = e.step_backward(s, a, zero, g_depth=cuda(gd), hit_cam=h)
-    st = torch.tensor(wk.state0.T.astype(np.float64), requires_grad=True)
+    st.requires_grad_(True)
     v, _, _ = osen.render(model, ds, st, db, zf, mx, frozen=rec)
     (v * torch.tensor(gd.reshape(64, -1).astype(np.float64))).sum().backward()
     ok, rel, comp = grad_close(f64(gs).T, st.grad)
-    assert ok, f"render VJP rel err {rel:.2e}"
+    assert ok, f"render VJP rel err {rel:.2e}, comp {comp:.4f}"
 
 
 def test_step_backward_combines_step_and_render():

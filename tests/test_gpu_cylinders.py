@@ -55,7 +55,7 @@ def test_cylinder_render_matches_oracle(model, sensor):
                                         db, zf, mx, lanes=torch.arange(A), agents_visible=False)
     v = f64(d).reshape(A, -1)
     r = h.cpu().reshape(A, -1).long()
-    assert ok.float().mean().item() >= 0.97
+    assert ok.float().mean().item() >= 0.995
     err = (v - v_orc).abs()
     assert (err[ok] <= 1e-4).all(), f"max depth error {err[ok].max().item():.3e}"
     assert torch.equal(r[ok], r_orc[ok])
@@ -65,8 +65,11 @@ def test_cylinder_render_matches_oracle(model, sensor):
 
 @pytest.mark.parametrize("model", [wl.RB13, wl.PM9])
 def test_cylinder_render_vjp_matches_autograd(model):
-    """Camera depth gradient pulled back to (p, q) through the GPU-recorded
-    hit topology, with cylinder side and cap hits among the records."""
+    """Camera depth gradient pulled back to (p, q) against autograd through
+    the oracle's render frozen to the oracle's own hit records, with cylinder
+    side and cap hits among them; compared on the stable rays, where the
+    GPU's records must equal the oracle's (the others get no incoming
+    gradient on either side)."""
     A = 64
     wk = wl.pillars(seed=21 + model, n_envs=A, model=model)
     print_case("cyl_render_vjp", model=model, A=A)
@@ -75,21 +78,20 @@ def test_cylinder_render_vjp_matches_autograd(model):
     d, h = _render(e, s, "cam")
     db, zf, mx = _dirs(wk, "cam")
     ds = osen.DenseScene(wk.scene)
-    rec = h.cpu().reshape(A, -1).long()
-    assert ((rec >= 26) & (rec < 40)).float().mean().item() > 0.05
+    st0 = torch.tensor(wk.state0.T.astype(np.float64))
+    ok, _, rec = osen.stable_rays(model, ds, st0, db, zf, mx)
+    assert ok.float().mean().item() >= 0.995
+    assert torch.equal(h.cpu().reshape(A, -1).long()[ok], rec[ok]), "hit records differ on stable rays"
+    assert ((rec >= 26) & (rec < 40))[ok].float().mean().item() > 0.05
     gd = np.random.default_rng(6).normal(size=tuple(d.shape)).astype(np.float32)
-    with torch.no_grad():
-        vchk, _, _ = osen.render(model, ds, torch.tensor(wk.state0.T.astype(np.float64)), db, zf, mx, frozen=rec)
-    drop = ~torch.isfinite(vchk)
-    assert drop.float().mean() < 1e-3
-    gd.reshape(A, -1)[drop.numpy()] = 0.0
+    gd.reshape(A, -1)[~ok.numpy()] = 0.0
     a = torch.zeros(e.K, A, device="cuda")
     gs, _ = e.step_backward(s, a, torch.zeros_like(s), g_depth=cuda(gd), hit_cam=h)
-    st = torch.tensor(wk.state0.T.astype(np.float64), requires_grad=True)
+    st = st0.clone().requires_grad_(True)
     v, _, _ = osen.render(model, ds, st, db, zf, mx, frozen=rec)
     (v * torch.tensor(gd.reshape(A, -1).astype(np.float64))).sum().backward()
-    ok, rel, _ = grad_close(f64(gs).T, st.grad)
-    assert ok, f"render VJP rel err {rel:.2e}"
+    ok, rel, comp = grad_close(f64(gs).T, st.grad)
+    assert ok, f"render VJP rel err {rel:.2e}, comp {comp:.4f}"
 
 
 def test_cylinder_collisions_match_oracle():

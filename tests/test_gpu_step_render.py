@@ -62,7 +62,7 @@ def test_tiny_pm_rollout_every_step_matches():
     assert drift < 1e-3
 
 
-def _render_parity(wk, lanes_sample=None, sensor="cam", cull_both=True, min_stable=0.97):
+def _render_parity(wk, lanes_sample=None, sensor="cam", cull_both=True, min_stable=0.999):
     e = _env(wk, fov_cull=True)
     s = cuda(wk.state0)
     if sensor == "cam":
@@ -121,8 +121,11 @@ def test_render_rigid_body_full_size_sampled():
 def test_render_uneven_lidar_and_camera():
     wk = wl.uneven(seed=3, n_envs=24, T=1)
     print_case("render_uneven", A=wk.scene.n_agents)
-    _render_parity(wk, sensor="lidar")
-    _render_parity(wk, sensor="cam")
+    # other agents are spheres of 0.15 m, often seen from a few metres: a
+    # larger share of rays passes within 1e-5 of a silhouette (0.13 % of the
+    # LiDAR rays of this scene), so the stable share is held to 0.998 here
+    _render_parity(wk, sensor="lidar", min_stable=0.998)
+    _render_parity(wk, sensor="cam", min_stable=0.998)
 
 
 def test_render_empty_scene_and_inside():

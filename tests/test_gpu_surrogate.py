@@ -68,7 +68,7 @@ def test_surrogate_gradient_matches_bf16_oracle():
     for name, a, b in FLAT_BLOCKS:
         ok, rel, comp = grad_close(f64(g)[a:b], ref[a:b])
         print(f"  {name}: rel {rel:.2e} comp {comp:.4f}")
-        assert ok, f"{name}: rel {rel:.2e}"
+        assert ok, f"{name}: rel {rel:.2e}, comp {comp:.4f}"
 
 
 def test_norm_matches_column_moments():
