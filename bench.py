@@ -55,6 +55,8 @@ def parse():
                    help="also run a plain device copy of MIB MiB (for HBM counter scaling)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-kernel-timing", action="store_true")
+    p.add_argument("--no-alternatives", action="store_true",
+                   help="skip the other policy-GEMM form and the recompute-all variant")
     p.add_argument("--sections", default="step,render,imu,attitude,task,surrogate,uneven",
                    help="comma list of extra sections after the headline: step, render, imu, attitude, task, "
                         "surrogate, uneven")
@@ -490,30 +492,42 @@ def render_vjp_flops(e, scene, s):
     return flops, {"rays": rays, "sphere_hits": sph, "box_hits": box, "room_hits": other}
 
 
-def dominant_roofline(tm, e, scene, s0, A, T, K, gemm_mode, store):
-    """Roofline of the kernel class with the largest total time in one
-    iteration: algorithmic work per launch / average launch duration (HIP
-    events on the kernels' stream)."""
+def dominant_roofline(tm, e, scene, s0, A, T, K, gemm_mode, store, iters=1):
+    """Roofline of the kernel class with the largest total time in the timed
+    iterations: algorithmic work of the class over the `iters` timed
+    iterations / its summed launch durations (HIP events on each kernel's own
+    stream, streams overlapping as untimed), which is the work per launch /
+    the average launch duration when launches are alike (the forward and the
+    backward sweep run the batch as two half-batch launches).
+
+    The two render kernels are priced against HBM: their algorithmic
+    intensity (culled ray casting, about 50 FLOP per 8 written bytes; the
+    adjoint about 40-90 FLOP per 12 read bytes) is below the chip's ridge of
+    157.3 TFLOP/s / 8 TB/s = 19.7 FLOP/B, so the roofline bound is the
+    bytes. The FLOP view is reported beside it."""
     from paper_2509_10247_amd import _lib
     dom = max(tm, key=lambda k: tm[k][0])
-    avg_s = tm[dom][0] / max(tm[dom][1], 1) / 1e3
-    base = {"kernel": dom, "launches": tm[dom][1], "avg_launch_ms": round(avg_s * 1e3, 4),
+    tot_s = tm[dom][0] / 1e3
+    n_launch = max(tm[dom][1], 1)
+    base = {"kernel": dom, "launches": n_launch, "avg_launch_ms": round(tot_s / n_launch * 1e3, 4),
             "traffic": None}
-    gemm_flops = {"l1_gemm": 2.0 * A * 3084 * 256, "gw1_gemm": 2.0 * 256 * 3084 * A,
-                  "gx_gemm": 2.0 * A * 256 * 3084}
+    # per iteration: T launches' worth of full-batch work for each GEMM class
+    gemm_flops = {"l1_gemm": 2.0 * A * 3084 * 256 * T, "gw1_gemm": 2.0 * 256 * 3084 * A * T,
+                  "gx_gemm": 2.0 * A * 256 * 3084 * T}
     if dom in gemm_flops:
-        ach = gemm_flops[dom] / avg_s
+        ach = gemm_flops[dom] * iters / tot_s
         x3 = gemm_mode == _lib.POLICY_GEMM_BF16X3
-        peak = PEAK_BF16_MFMA if x3 else PEAK_FP32_MFMA
+        peak = PEAK_BF16_MFMA / 3 if x3 else PEAK_FP32_MFMA
         base.update({"bound": "mfma", "achieved": round(ach / 1e12, 2), "peak": peak / 1e12,
                      "unit": "TFLOP/s", "frac": round(ach / peak, 4),
-                     "flops_per_launch": gemm_flops[dom]})
+                     "flops_per_launch": gemm_flops[dom] * iters / n_launch})
         if x3:
-            base["note"] = "FP32 product from three BF16 MFMA products: executed MFMA work is 3x"
+            base["note"] = ("FP32-width product from three BF16 MFMA products: the peak is the BF16 "
+                            "peak / 3 (executed MFMA work is 3x the layer's FLOPs)")
         return base
     if dom == "render":
-        # launches: T forward renders (observation row, obstacle term fused;
-        # with stored activations the last two segments also write hit
+        # per iteration: T forward renders (observation row, obstacle term
+        # fused; with stored activations the last two segments also write hit
         # records) and the backward's recompute of the other segments
         # (observation row and hit record; the term only without stored
         # activations, where every segment is recomputed)
@@ -522,42 +536,38 @@ def dominant_roofline(tm, e, scene, s0, A, T, K, gemm_mode, store):
         nseg = -(-T // K)
         kept = (T - max(0, nseg - 2) * K) if store else 0
         n_rec = T - kept
-        assert T + n_rec == tm[dom][1], "render launch count"
-        flops = (T * f_term + n_rec * (f_plain if store else f_term)) / (T + n_rec)
-        ach = flops / avg_s
+        flops_it = T * f_term + n_rec * (f_plain if store else f_term)
         n_env = e.n_envs
         # algorithmic bytes: 4 B per ray for the observation value, 4 B more
-        # where the hit record is written; read once: each env's 24 spheres,
-        # 16 boxes and room, and the state
-        written = cnt["rays"] * (4.0 * T + 4.0 * kept + 8.0 * n_rec) / (T + n_rec)
-        read = n_env * (24 * 16 + 16 * 24 + 24) + A * 13 * 4
-        base.update({"bound": "alu", "achieved": round(ach / 1e12, 2), "peak": PEAK_FP32_VALU / 1e12,
-                     "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_VALU, 4),
-                     "frac_of_nonpacked_fp32": round(ach / PEAK_FP32_VALU_NONPACKED, 4),
-                     "flops_per_launch": flops, "work_per_launch": cnt,
-                     "algorithmic_bytes_per_launch": written + read,
-                     "hbm_frac": round((written + read) / avg_s / PEAK_HBM, 4)})
+        # where the hit record is written; read once per render: each env's
+        # 24 spheres, 16 boxes and room, and the state
+        written = cnt["rays"] * (4.0 * T + 4.0 * kept + 8.0 * n_rec)
+        read = (n_env * (24 * 16 + 16 * 24 + 24) + A * 13 * 4) * (T + n_rec)
+        bytes_it = written + read
         tr = measured_traffic(RENDER_SOURCES, TRAFFIC_PROFILE, "render")
-        if tr is not None:
-            base["traffic"] = tr["fetch_bytes_per_launch"] + tr["write_bytes_per_launch"]
-            base["traffic_source"] = TRAFFIC_PROFILE
-        return base
-    if dom == "render_vjp":
-        flops, cnt = render_vjp_flops(e, scene, s0)
-        ach = flops / avg_s
-        read = cnt["rays"] * 12.0   # hit record, observation gradient, observation value
-        base.update({"bound": "alu", "achieved": round(ach / 1e12, 2), "peak": PEAK_FP32_VALU / 1e12,
-                     "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_VALU, 4),
-                     "frac_of_nonpacked_fp32": round(ach / PEAK_FP32_VALU_NONPACKED, 4),
-                     "flops_per_launch": flops, "work_per_launch": cnt,
-                     "algorithmic_bytes_per_launch": read,
-                     "hbm_frac": round(read / avg_s / PEAK_HBM, 4)})
+        work = cnt
+    elif dom == "render_vjp":
+        f1, work = render_vjp_flops(e, scene, s0)
+        flops_it = f1 * T
+        bytes_it = work["rays"] * 12.0 * T   # hit record, observation gradient, observation value
         tr = measured_traffic(RENDER_SOURCES, TRAFFIC_PROFILE, "render_vjp")
-        if tr is not None:
-            base["traffic"] = tr["fetch_bytes_per_launch"] + tr["write_bytes_per_launch"]
-            base["traffic_source"] = TRAFFIC_PROFILE
+    else:
+        base.update({"bound": "unknown", "achieved": None, "peak": None, "unit": None, "frac": None})
         return base
-    base.update({"bound": "unknown", "achieved": None, "peak": None, "unit": None, "frac": None})
+    nbytes = bytes_it * iters / n_launch
+    flops = flops_it * iters / n_launch
+    avg_s = tot_s / n_launch
+    gbs = nbytes / avg_s / 1e9
+    base.update({"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                 "frac": round(gbs * 1e9 / PEAK_HBM, 4), "algorithmic_bytes_per_launch": nbytes,
+                 "work_per_full_batch_launch": work,
+                 "flop_view": {"flops_per_launch": flops, "flop_per_byte": round(flops / nbytes, 2),
+                               "ridge_flop_per_byte": round(PEAK_FP32_VALU / PEAK_HBM, 2),
+                               "achieved_tflops": round(flops / avg_s / 1e12, 2),
+                               "frac_of_fp32_vector_peak": round(flops / avg_s / PEAK_FP32_VALU, 4)}})
+    if tr is not None:
+        base["traffic"] = tr["fetch_bytes_per_launch"] + tr["write_bytes_per_launch"]
+        base["traffic_source"] = TRAFFIC_PROFILE
     return base
 
 
@@ -573,23 +583,94 @@ def copy_calibration(mib):
     print(f"[copy-calibration] 3 copies of {mib} MiB", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(model, seed=0, n_envs=256, T=32):
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(model, seed=0, n_envs=256, T=32, n_envs_1t=16, T_1t=8):
     """The FP64 oracle (forward rollout + autograd backward) on a bounded
-    sample of the same workload, on the host's cores."""
+    sample of the same workload, on the host's cores, and on one thread for
+    a smaller sample."""
     import numpy as np
     import torch
     import workloads as wl
     from oracle import policy as opol
-    wk = wl.bptt(seed=seed, n_envs=n_envs, T=T, model=model)
     theta = wl.flatten_mlp(wl.mlp_init(np.random.default_rng(1), wl.POLICY_DIMS))
+
+    def run(n, t):
+        wk = wl.bptt(seed=seed, n_envs=n, T=t, model=model)
+        t0 = time.perf_counter()
+        opol.bptt_grad(model, wk.scene, wk.state0, wk.goal, wk.params, theta, t, wk.dt, wk.integrator, wk.cam)
+        return time.perf_counter() - t0
+
+    threads = torch.get_num_threads()
+    dt = run(n_envs, T)
+    torch.set_num_threads(1)
+    try:
+        dt1 = run(n_envs_1t, T_1t)
+    finally:
+        torch.set_num_threads(threads)
+    return {"value": n_envs * T / dt, "unit": "env-steps/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+            "single_thread_value": n_envs_1t * T_1t / dt1,
+            "sample": f"{n_envs} envs x {T} steps of the same workload on {threads} threads ({dt:.1f} s), and "
+                      f"{n_envs_1t} envs x {T_1t} steps on 1 thread ({dt1:.1f} s); FP64 forward + autograd "
+                      f"backward"}
+
+
+GEMM_DTYPE = {"fp32": "f32", "bf16x3": "f32 (policy GEMMs bf16x3: three BF16 products per FP32 product)"}
+
+
+def bptt_run(wk, theta, A, T, K, store, gemm_mode, steps, warmup, timed=False):
+    """BPTT iterations on the benchmark workload. Returns (ms per iteration,
+    env-steps per s, (env, engine, s0), isolated, live): with timed=True,
+    `isolated` is one extra warm-up iteration with every kernel alone on one
+    stream and HIP events around each kernel class, and `live` the summed
+    durations of the class with the largest isolated total over the timed
+    iterations, from HIP events on that kernel's own stream with the streams
+    overlapping as untimed (only that class is timed, to keep events few)."""
+    import torch
+    from paper_2509_10247_amd import _lib, bptt, env
+    e = env.from_workload(wk)
+    eng = bptt.BpttEngine(e, T, K, store_activations=store, policy_gemm=gemm_mode)
+    th = torch.tensor(theta, device="cuda")
+    s0 = torch.tensor(wk.state0, device="cuda")
+    goal = torch.tensor(wk.goal, device="cuda")
+
+    def one_step():
+        eng.forward(th, s0, goal)
+        return eng.backward(want_s0=False)
+
+    for _ in range(warmup):
+        one_step()
+    isolated = live = None
+    if timed:
+        _lib.bptt_set_timing(eng.h, 1)
+        one_step()
+        torch.cuda.synchronize()
+        isolated = _lib.bptt_get_timing(eng.h)
+        dom = max(isolated, key=lambda k: isolated[k][0])
+        _lib.bptt_set_timing_classes(eng.h, [dom])
+        _lib.bptt_set_timing(eng.h, 2)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    opol.bptt_grad(model, wk.scene, wk.state0, wk.goal, wk.params, theta, T, wk.dt, wk.integrator,
-                   wk.cam)
-    dt = time.perf_counter() - t0
-    return {"value": n_envs * T / dt, "unit": "env-steps/s", "cores": torch.get_num_threads(),
-            "kind": "oracle",
-            "sample": f"{n_envs} envs x {T} steps of the same workload, FP64 forward + autograd "
-                      f"backward ({dt:.1f} s)"}
+    for _ in range(steps):
+        g, _ = one_step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    if timed:
+        live = {dom: _lib.bptt_get_timing(eng.h)[dom]}
+        _lib.bptt_set_timing(eng.h, 0)
+        _lib.bptt_set_timing_classes(eng.h, None)
+    assert torch.isfinite(g).all(), "non-finite gradient"
+    return elapsed / steps * 1e3, A * T * steps / elapsed, (e, eng, s0), isolated, live
 
 
 def main():
@@ -601,49 +682,29 @@ def main():
     import numpy as np
     import torch
     import workloads as wl
-    from paper_2509_10247_amd import _lib, bptt, env
+    from paper_2509_10247_amd import _lib
 
     model = wl.RB13 if args.model == "rb13" else wl.PM9
     A, T, K = args.envs, args.horizon, args.ckpt
     wk = wl.bptt(seed=0, n_envs=A, T=T, model=model)
     theta = wl.flatten_mlp(wl.mlp_init(np.random.default_rng(1), wl.POLICY_DIMS))
-    e = env.from_workload(wk)
-    gemm_mode = _lib.POLICY_GEMM_BF16X3 if args.policy_gemm == "bf16x3" else _lib.POLICY_GEMM_FP32
-    eng = bptt.BpttEngine(e, T, K, store_activations=not args.recompute_all, policy_gemm=gemm_mode)
-    th = torch.tensor(theta, device="cuda")
-    s0 = torch.tensor(wk.state0, device="cuda")
-    goal = torch.tensor(wk.goal, device="cuda")
-
-    def one_step():
-        eng.forward(th, s0, goal)
-        return eng.backward(want_s0=False)
-
-    for _ in range(args.warmup):
-        one_step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        g, _ = one_step()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    assert torch.isfinite(g).all(), "non-finite gradient"
-    ms = elapsed / args.steps * 1e3
-    value = A * T * args.steps / elapsed
-
-    roofline, breakdown = None, None
+    modes = {"fp32": _lib.POLICY_GEMM_FP32, "bf16x3": _lib.POLICY_GEMM_BF16X3}
+    gemm_mode = modes[args.policy_gemm]
+    store = not args.recompute_all
+    ms, value, (e, eng, s0), ti, live = bptt_run(wk, theta, A, T, K, store, gemm_mode, args.steps, args.warmup,
+                                                  timed=not args.no_kernel_timing)
+    roofline, isolated = None, None
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
-    if not args.no_kernel_timing:
-        # one more iteration with HIP events around each kernel class, on the
-        # stream the kernels run on
-        _lib.bptt_set_timing(eng.h, 1)
-        one_step()
-        torch.cuda.synchronize()
-        tm = _lib.bptt_get_timing(eng.h)
-        _lib.bptt_set_timing(eng.h, 0)
-        breakdown = {k: {"ms_total": round(v[0], 3), "launches": v[1],
-                         "ms_avg": round(v[0] / max(v[1], 1), 4)} for k, v in tm.items()}
-        roofline = dominant_roofline(tm, e, wk.scene, s0, A, T, K, gemm_mode, not args.recompute_all)
+    if live is not None:
+        roofline = dominant_roofline(live, e, wk.scene, s0, A, T, K, gemm_mode, store, iters=args.steps)
+        roofline["timing"] = ("HIP events around each launch of this kernel on its own stream over the timed "
+                              "iterations, streams overlapping")
+        isolated = {k: {"ms_total": round(v[0], 3), "launches": v[1], "ms_avg": round(v[0] / max(v[1], 1), 4)}
+                    for k, v in ti.items()}
+    ws = eng.workspace_bytes()
+    del eng
+    torch.cuda.empty_cache()
 
     line = {
         "metric": "env-steps/sec fwd+bwd with 64x48 depth",
@@ -656,16 +717,31 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": GEMM_DTYPE[args.policy_gemm],
         "data": "synthetic",
         "config": {"workload": f"bptt_{args.model}_rk4_{A}env_T{T}_K{K}_cam64x48_room24sph16box",
                    "envs": A, "horizon": T, "checkpoint_every": K, "env_steps_per_step": A * T,
-                   "stored_activations": not args.recompute_all,
-                   "workspace_bytes": eng.workspace_bytes(),
+                   "stored_activations": store,
+                   "workspace_bytes": ws,
                    "policy": f"mlp 3081-256-256-4 tanh ({args.policy_gemm} mfma)"},
         "roofline": roofline,
-        "kernel_breakdown": breakdown,
+        "kernel_breakdown_isolated": isolated,
     }
+    if not args.no_alternatives:
+        # the same step with the other policy-GEMM form, and with classic
+        # recompute (only the K-step state checkpoints kept)
+        alts = {}
+        for name, gm, st in ((f"policy_gemm_{'bf16x3' if args.policy_gemm == 'fp32' else 'fp32'}",
+                              modes["bf16x3" if args.policy_gemm == "fp32" else "fp32"], store),
+                             ("recompute_all", gemm_mode, False)):
+            if name == "recompute_all" and not store:
+                continue
+            m2, v2, _, _, _ = bptt_run(wk, theta, A, T, K, st, gm, args.steps, args.warmup)
+            torch.cuda.empty_cache()
+            gname = "fp32" if gm == _lib.POLICY_GEMM_FP32 else "bf16x3"
+            alts[name] = {"value": round(v2, 1), "ms_per_step": round(m2, 3), "dtype": GEMM_DTYPE[gname],
+                          "stored_activations": st}
+        line["alternatives"] = alts
     sections = [x for x in args.sections.split(",") if x]
     if "step" in sections:
         line["step"] = step_section()

@@ -388,12 +388,15 @@ int bptt_forward(bptt_handle* b, const float* theta, const float* s0, const floa
  * adjoints. Must follow bptt_forward with the same theta / s0 / goal. */
 int bptt_backward(bptt_handle* b, const float* g_loss, float* g_theta, float* g_s0, void* stream);
 
-/* Kernel timing (diagnostics for the roofline report): when enabled, every
- * launch of the kernel classes below is bracketed by HIP events on the
- * caller's stream during bptt_forward / bptt_backward. bptt_get_timing
- * synchronizes on those events and writes, per class c < n, the summed
- * duration ms[c] (host float) and the launch count count[c] (host int32).
- * bptt_set_timing also clears the record. */
+/* Kernel timing (diagnostics for the roofline report): with mode 1 every
+ * launch of the kernel classes below is bracketed by HIP events and runs
+ * alone on the caller's stream (no overlap of streams or half-batches); with
+ * mode 2 the events are recorded on each kernel's own stream and the streams
+ * overlap as in an untimed iteration, so durations include the contention of
+ * concurrent kernels; mode 0 turns timing off. bptt_get_timing synchronizes
+ * on those events and writes, per class c < n, the summed duration ms[c]
+ * (host float) and the launch count count[c] (host int32). bptt_set_timing
+ * also clears the record; any other mode is SIM_EINVAL. */
 enum {
   BPTT_T_RENDER = 0,      /* camera render (render_kernel) */
   BPTT_T_L1 = 1,          /* first policy layer GEMM, 3084 -> 256, + bias + tanh */
@@ -411,6 +414,9 @@ enum {
   BPTT_T_COUNT = 13
 };
 int bptt_set_timing(bptt_handle* b, int32_t enable);
+/* Restricts timing to the classes whose bit (1u << BPTT_T_*) is set in mask
+ * (default: all), so that a concurrent timed run records few events. */
+int bptt_set_timing_classes(bptt_handle* b, uint32_t mask);
 int bptt_get_timing(bptt_handle* b, float* ms, int32_t* count, int32_t n);
 
 /* Stand-alone policy forward / backward on a batch (for tests and tools):

@@ -82,6 +82,7 @@ _SIGS = {
     "bptt_forward": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "bptt_backward": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "bptt_set_timing": (c_int, [c_void_p, c_int]),
+    "bptt_set_timing_classes": (c_int, [c_void_p, ctypes.c_uint32]),
     "bptt_get_timing": (c_int, [c_void_p, ctypes.POINTER(c_float), ctypes.POINTER(c_int), c_int]),
     "policy_forward": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p]),
     "policy_backward": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p]),
@@ -324,7 +325,13 @@ BPTT_TIMING_CLASSES = ["render", "l1_gemm", "gw1_gemm", "gx_gemm", "render_vjp",
 
 
 def bptt_set_timing(b, enable):
-    _call("bptt_set_timing", b, int(bool(enable)))
+    _call("bptt_set_timing", b, int(enable))
+
+
+def bptt_set_timing_classes(b, names=None):
+    """Time only the named classes (None: all)."""
+    mask = 0xFFFFFFFF if names is None else sum(1 << BPTT_TIMING_CLASSES.index(n) for n in names)
+    _call("bptt_set_timing_classes", b, mask)
 
 
 def bptt_get_timing(b):

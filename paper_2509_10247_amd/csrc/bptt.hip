@@ -22,7 +22,7 @@ struct bptt_handle;
 
 namespace da {
 
-static int tmark(bptt_handle* b, hipStream_t st);
+static int tmark(bptt_handle* b, hipStream_t st, int cls);
 static void tpair(bptt_handle* b, int cls, int a, int z);
 
 constexpr int kHid = 256, kOut = 4;
@@ -211,7 +211,7 @@ static int mlp_forward(int B, const PolicyPtrs& p, const float* X, float* H1, fl
   g.M = B; g.N = kHid; g.K = kObsK;
   g.A = X; g.lda = kObsPad; g.B = p.W1p; g.ldb = kObsPad;
   g.C = H1; g.ldc = kHid; g.bias = p.b1;
-  const int e0 = owner ? tmark(owner, st) : -1;
+  const int e0 = owner ? tmark(owner, st, BPTT_T_L1) : -1;
   int rc;
   if (p.W1s_hi) {
     g.B_hi = p.W1s_hi;
@@ -227,15 +227,15 @@ static int mlp_forward(int B, const PolicyPtrs& p, const float* X, float* H1, fl
     rc = launch_gemm(true, true, EPI_BIAS_TANH, g, 1, st, prec);
   }
   if (rc) return rc;
-  if (owner) tpair(owner, BPTT_T_L1, e0, tmark(owner, st));
-  const int e1 = owner ? tmark(owner, st) : -1;
+  if (owner) tpair(owner, BPTT_T_L1, e0, tmark(owner, st, BPTT_T_L1));
+  const int e1 = owner ? tmark(owner, st, BPTT_T_L23) : -1;
   g = GemmArgs();
   g.M = B; g.N = kHid; g.K = kHid;
   g.A = H1; g.lda = kHid; g.B = p.W2; g.ldb = kHid;
   g.C = H2; g.ldc = kHid; g.bias = p.b2;
   if ((rc = launch_gemm(true, true, EPI_BIAS_TANH, g, 1, st, prec))) return rc;
   rc = launch_narrow_fwd(B, kHid, kOut, H2, kHid, p.W3, p.b3, Y, st);
-  if (owner) tpair(owner, BPTT_T_L23, e1, tmark(owner, st));
+  if (owner) tpair(owner, BPTT_T_L23, e1, tmark(owner, st, BPTT_T_L23));
   return rc;
 }
 
@@ -271,21 +271,21 @@ static int mlp_backward_data(int B, const PolicyPtrs& p, const float* H1, const 
                              const float* Y, const float* gY, const LayerGrads& z, float* gX,
                              hipStream_t st, int prec, bptt_handle* owner, hipEvent_t z_ready = nullptr,
                              uint16_t* z1_hi = nullptr, uint16_t* z1_lo = nullptr) {
-  int et = owner ? tmark(owner, st) : -1;
+  int et = owner ? tmark(owner, st, BPTT_T_SMALL_BWD) : -1;
   int rc = launch_narrow_bwd(B, kHid, kOut, gY, Y, p.W3, H2, kHid, z.gZ3, z.gZ2, st);
   if (rc) return rc;
-  if (owner) tpair(owner, BPTT_T_SMALL_BWD, et, tmark(owner, st));
+  if (owner) tpair(owner, BPTT_T_SMALL_BWD, et, tmark(owner, st, BPTT_T_SMALL_BWD));
   // gZ1 = (gZ2 W2) (1 - H1^2)
-  et = owner ? tmark(owner, st) : -1;
+  et = owner ? tmark(owner, st, BPTT_T_GZ1) : -1;
   GemmArgs g;
   g.M = B; g.N = kHid; g.K = kHid;
   g.A = z.gZ2; g.lda = kHid; g.B = p.W2; g.ldb = kHid; g.C = z.gZ1; g.ldc = kHid;
   g.aux = H1; g.ld_aux = kHid;
   if ((rc = launch_gemm(true, false, EPI_MUL_DTANH, g, 1, st, prec))) return rc;
-  if (owner) tpair(owner, BPTT_T_GZ1, et, tmark(owner, st));
+  if (owner) tpair(owner, BPTT_T_GZ1, et, tmark(owner, st, BPTT_T_GZ1));
   if (z_ready) DA_HIP(hipEventRecord(z_ready, st));
   // gX = gZ1 W1
-  et = owner ? tmark(owner, st) : -1;
+  et = owner ? tmark(owner, st, BPTT_T_GX) : -1;
   g = GemmArgs();
   g.M = B; g.N = kObsK; g.K = kHid;
   g.A = z.gZ1; g.lda = kHid; g.B = p.W1p; g.ldb = kObsPad; g.C = gX; g.ldc = kObsPad;
@@ -296,7 +296,7 @@ static int mlp_backward_data(int B, const PolicyPtrs& p, const float* H1, const 
     g.B_hi = p.W1t_hi; g.B_lo = p.W1t_lo; g.ldb_s = kHid;
   }
   rc = launch_gemm(true, false, EPI_STORE, g, 1, st, prec);
-  if (owner) tpair(owner, BPTT_T_GX, et, tmark(owner, st));
+  if (owner) tpair(owner, BPTT_T_GX, et, tmark(owner, st, BPTT_T_GX));
   return rc;
 }
 
@@ -307,7 +307,7 @@ static int mlp_backward_weights(int B, const float* X, const float* H1, const fl
                                 const LayerGrads& z, MlpGradBufs& gb, float* part, hipStream_t st,
                                 int prec, bptt_handle* owner) {
   // gW3 += gZ3^T H2 ; gb3 += colsum(gZ3)
-  int et = owner ? tmark(owner, st) : -1;
+  int et = owner ? tmark(owner, st, BPTT_T_GW23) : -1;
   GemmArgs g;
   g.M = kOut; g.N = kHid; g.K = B;
   g.A = z.gZ3; g.lda = kOut; g.B = H2; g.ldb = kHid; g.C = part; g.ldc = kHid;
@@ -326,9 +326,9 @@ static int mlp_backward_weights(int B, const float* X, const float* H1, const fl
                                  true, st)))
     return rc;
   if ((rc = launch_colsum(B, kHid, z.gZ2, kHid, gb.gb2, true, part, st))) return rc;
-  if (owner) tpair(owner, BPTT_T_GW23, et, tmark(owner, st));
+  if (owner) tpair(owner, BPTT_T_GW23, et, tmark(owner, st, BPTT_T_GW23));
   // gW1 += gZ1^T X ; gb1
-  et = owner ? tmark(owner, st) : -1;
+  et = owner ? tmark(owner, st, BPTT_T_GW1) : -1;
   g = GemmArgs();
   g.M = kHid; g.N = kObsK; g.K = B;
   g.A = z.gZ1; g.lda = kHid; g.B = X; g.ldb = kObsPad; g.C = part; g.ldc = kObsPad;
@@ -336,10 +336,10 @@ static int mlp_backward_weights(int B, const float* X, const float* H1, const fl
   if ((rc = launch_splitk_reduce(gemm_splits_used(B, kSplitW1), kHid, kObsK, kObsPad, part, gb.gW1p,
                                  kObsPad, true, st)))
     return rc;
-  if (owner) tpair(owner, BPTT_T_GW1, et, tmark(owner, st));
-  et = owner ? tmark(owner, st) : -1;
+  if (owner) tpair(owner, BPTT_T_GW1, et, tmark(owner, st, BPTT_T_GW1));
+  et = owner ? tmark(owner, st, BPTT_T_COLSUM1) : -1;
   if ((rc = launch_colsum(B, kHid, z.gZ1, kHid, gb.gb1, true, part, st))) return rc;
-  if (owner) tpair(owner, BPTT_T_COLSUM1, et, tmark(owner, st));
+  if (owner) tpair(owner, BPTT_T_COLSUM1, et, tmark(owner, st, BPTT_T_COLSUM1));
   return SIM_OK;
 }
 
@@ -388,7 +388,8 @@ struct bptt_handle {
   hipStream_t half2 = nullptr;
   hipEvent_t ev_z2[2] = {nullptr, nullptr}, ev_seg2 = nullptr, ev_h2done = nullptr;
   // optional HIP-event timing of the main kernel classes (BPTT_T_*)
-  bool timing = false;
+  int timing = 0;  // 0 off, 1 serialized, 2 concurrent (see bptt_set_timing)
+  uint32_t timing_classes = ~0u;  // bit c: time class c
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<int, int>> ev_pairs[BPTT_T_COUNT];  // (start, stop) indices per class
   int ev_next = 0;
@@ -396,8 +397,8 @@ struct bptt_handle {
 
 namespace da {
 // Records an event on the stream when timing is on; returns its pool index.
-static int tmark(bptt_handle* b, hipStream_t st) {
-  if (!b->timing) return -1;
+static int tmark(bptt_handle* b, hipStream_t st, int cls) {
+  if (!b->timing || !((b->timing_classes >> cls) & 1u)) return -1;
   if (b->ev_next >= (int)b->ev_pool.size()) {
     hipEvent_t e;
     if (hipEventCreate(&e) != hipSuccess) return -1;
@@ -552,9 +553,16 @@ int64_t bptt_workspace_bytes(const bptt_handle* b) { return b ? b->bytes : 0; }
 
 int bptt_set_timing(bptt_handle* b, int32_t enable) {
   DA_REQUIRE(b, "bptt_set_timing: null handle");
-  b->timing = enable != 0;
+  DA_REQUIRE(enable >= 0 && enable <= 2, "bptt_set_timing: mode must be 0, 1 or 2");
+  b->timing = enable;
   for (auto& v : b->ev_pairs) v.clear();
   b->ev_next = 0;
+  return SIM_OK;
+}
+
+int bptt_set_timing_classes(bptt_handle* b, uint32_t mask) {
+  DA_REQUIRE(b, "bptt_set_timing_classes: null handle");
+  b->timing_classes = mask;
   return SIM_OK;
 }
 
@@ -591,29 +599,29 @@ static int forward_step(bptt_handle* b, const PolicyPtrs& pp, const float* s, fl
   sim_handle* h = b->sim;
   const int A = b->A;
   const float dmax = h->cfg.cam_max;
-  int e0 = tmark(b, st);
+  int e0 = tmark(b, st, BPTT_T_RENDER);
   // depth / d_max straight into the observation rows, obstacle term fused
   int rc = launch_render(h->scene, h->cam.dev, h->cfg.model == SIM_RB13, h->cfg.fov_cull != 0, s, A, X,
                          hit, kObsPad, 1.0f / dmax, st, b->lo, b->cfg.beta, b->cfg.d_safe, i0, n);
   if (rc) return rc;
-  tpair(b, BPTT_T_RENDER, e0, tmark(b, st));
-  e0 = tmark(b, st);
+  tpair(b, BPTT_T_RENDER, e0, tmark(b, st, BPTT_T_RENDER));
+  e0 = tmark(b, st, BPTT_T_SMALL_FWD);
   hipLaunchKernelGGL(obs_fwd_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, A, h->cfg.model, X, s, b->goal,
                      i0, n);
   DA_LAUNCH_CHECK("obs_fwd_kernel");
-  tpair(b, BPTT_T_SMALL_FWD, e0, tmark(b, st));
+  tpair(b, BPTT_T_SMALL_FWD, e0, tmark(b, st, BPTT_T_SMALL_FWD));
   if ((rc = mlp_forward(n, pp, X + (size_t)i0 * kObsPad, H1 + (size_t)i0 * kHid, H2 + (size_t)i0 * kHid,
                         Y + (size_t)i0 * kOut, st, b->prec, part, b)))
     return rc;
-  e0 = tmark(b, st);
+  e0 = tmark(b, st, BPTT_T_SMALL_FWD);
   hipLaunchKernelGGL(action_kernel, dim3(cdiv(n, 256)), dim3(256), 0, st, A, h->cfg.model, Y, h->params,
                      act, i0, n);
   DA_LAUNCH_CHECK("action_kernel");
-  tpair(b, BPTT_T_SMALL_FWD, e0, tmark(b, st));
-  e0 = tmark(b, st);
+  tpair(b, BPTT_T_SMALL_FWD, e0, tmark(b, st, BPTT_T_SMALL_FWD));
+  e0 = tmark(b, st, BPTT_T_STEP);
   rc = launch_step(h->cfg.model, h->cfg.integrator, A, h->cfg.dt, s, act, h->params, s_next, nullptr, st,
                    i0, n);
-  tpair(b, BPTT_T_STEP, e0, tmark(b, st));
+  tpair(b, BPTT_T_STEP, e0, tmark(b, st, BPTT_T_STEP));
   return rc;
 }
 
@@ -647,7 +655,7 @@ int bptt_forward(bptt_handle* b, const float* theta, const float* s0, const floa
   // the other half's policy GEMMs (matrix cores) overlap. The halves share
   // nothing but read-only data; every lane's arithmetic is unchanged.
   int nh = 1, hi0[2] = {0, 0}, hn[2] = {A, 0};
-  if (b->store && !b->timing && !b->sim->cfg.agents_visible && A >= 512) {
+  if (b->store && b->timing != 1 && !b->sim->cfg.agents_visible && A >= 512) {
     if ((rc = ensure_streams(b))) return rc;
     nh = 2;
     hn[0] = ((A / 2 + 127) / 128) * 128;
@@ -725,20 +733,20 @@ int bptt_backward(bptt_handle* b, const float* g_loss, float* g_theta, float* g_
     for (int j = 0; j < n; ++j) {
       const float* s = b->seg_s + (size_t)(t0 + j) * C * A;
       float* X = Xs + (size_t)j * A * kObsPad;
-      const int e0 = tmark(b, q);
+      const int e0 = tmark(b, q, BPTT_T_RENDER);
       int r = launch_render(h->scene, h->cam.dev, h->cfg.model == SIM_RB13, h->cfg.fov_cull != 0, s, A, X,
                             Hs + (size_t)j * A * kRays, kObsPad, 1.0f / dmax, q);
       if (r) return r;
-      tpair(b, BPTT_T_RENDER, e0, tmark(b, q));
+      tpair(b, BPTT_T_RENDER, e0, tmark(b, q, BPTT_T_RENDER));
       hipLaunchKernelGGL(obs_fwd_kernel, dim3(cdiv(A, 256)), dim3(256), 0, q, A, h->cfg.model, X, s, b->goal,
                          0, A);
       DA_LAUNCH_CHECK("obs_fwd_kernel");
     }
     return SIM_OK;
   };
-  // with kernel timing on, the recompute stays on the caller's stream so that
-  // every timed kernel runs alone
-  const bool overlap = b->store && !b->timing;
+  // with serialized kernel timing on, the recompute stays on the caller's
+  // stream so that every timed kernel runs alone
+  const bool overlap = b->store && b->timing != 1;
   if (b->store && !overlap) {
     if (!kept_segment(b, b->nseg - 1) && (rc = recompute_renders(b->nseg - 1, st))) return rc;
   } else if (overlap) {
@@ -810,21 +818,21 @@ int bptt_backward(bptt_handle* b, const float* g_loss, float* g_theta, float* g_
       for (int hf = 0; hf < nh; ++hf) {
         hipStream_t q = hf ? b->half2 : st;
         const int i0 = hi0[hf], m = hn[hf];
-        int e0 = tmark(b, q);
+        int e0 = tmark(b, q, BPTT_T_SMALL_BWD);
         hipLaunchKernelGGL(loss_state_grad_kernel, dim3(cdiv(m, 256)), dim3(256), 0, q, A, s1, b->goal, cp, cv,
                            g_loss, g_next, i0, m);
         DA_LAUNCH_CHECK("loss_state_grad_kernel");
-        tpair(b, BPTT_T_SMALL_BWD, e0, tmark(b, q));
-        e0 = tmark(b, q);
+        tpair(b, BPTT_T_SMALL_BWD, e0, tmark(b, q, BPTT_T_SMALL_BWD));
+        e0 = tmark(b, q, BPTT_T_STEP_VJP);
         if ((rc = launch_step_vjp(h->cfg.model, h->cfg.integrator, A, h->cfg.dt, s, act, h->params, g_next,
                                   g_cur, b->ga, q, i0, m)))
           return rc;
-        tpair(b, BPTT_T_STEP_VJP, e0, tmark(b, q));
-        e0 = tmark(b, q);
+        tpair(b, BPTT_T_STEP_VJP, e0, tmark(b, q, BPTT_T_STEP_VJP));
+        e0 = tmark(b, q, BPTT_T_SMALL_BWD);
         hipLaunchKernelGGL(action_bwd_kernel, dim3(cdiv(m, 256)), dim3(256), 0, q, A, h->cfg.model, b->ga, Y,
                            h->params, cu, g_loss, b->gY, i0, m);
         DA_LAUNCH_CHECK("action_bwd_kernel");
-        tpair(b, BPTT_T_SMALL_BWD, e0, tmark(b, q));
+        tpair(b, BPTT_T_SMALL_BWD, e0, tmark(b, q, BPTT_T_SMALL_BWD));
         if (overlap && wsteps >= 2) DA_HIP(hipStreamWaitEvent(q, b->ev_w[par], 0));
         const LayerGrads zh{z.gZ3 + (size_t)i0 * kOut, z.gZ2 + (size_t)i0 * kHid, z.gZ1 + (size_t)i0 * kHid};
         hipEvent_t zr = overlap ? (hf ? b->ev_z2[par] : b->ev_z[par]) : nullptr;
@@ -847,18 +855,18 @@ int bptt_backward(bptt_handle* b, const float* g_loss, float* g_theta, float* g_
       for (int hf = 0; hf < nh; ++hf) {
         hipStream_t q = hf ? b->half2 : st;
         const int i0 = hi0[hf], m = hn[hf];
-        int e0 = tmark(b, q);
+        int e0 = tmark(b, q, BPTT_T_SMALL_BWD);
         hipLaunchKernelGGL(obs_bwd_kernel, dim3(cdiv(m, 256)), dim3(256), 0, q, A, h->cfg.model, b->gX, s, g_cur,
                            i0, m);
         DA_LAUNCH_CHECK("obs_bwd_kernel");
-        tpair(b, BPTT_T_SMALL_BWD, e0, tmark(b, q));
-        e0 = tmark(b, q);
+        tpair(b, BPTT_T_SMALL_BWD, e0, tmark(b, q, BPTT_T_SMALL_BWD));
+        e0 = tmark(b, q, BPTT_T_RENDER_VJP);
         // depth-observation backward fused into the render adjoint
         const DepthObsGrad ob{X, dmax, b->cfg.beta, b->cfg.d_safe, co, g_loss};
         if ((rc = launch_render_vjp(h->scene, h->cam.dev, h->cfg.model == SIM_RB13, s, A, b->gX, kObsPad, hit,
                                     g_cur, q, &ob, i0, m)))
           return rc;
-        tpair(b, BPTT_T_RENDER_VJP, e0, tmark(b, q));
+        tpair(b, BPTT_T_RENDER_VJP, e0, tmark(b, q, BPTT_T_RENDER_VJP));
       }
       std::swap(g_next, g_cur);
     }
