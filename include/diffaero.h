@@ -429,6 +429,20 @@ int policy_forward(const float* theta, const float* x, float* y, int32_t B, int3
 int policy_backward(const float* theta, const float* x, const float* g_y, float* g_theta,
                     float* g_x, int32_t B, int32_t gemm_mode, void* stream);
 
+/* policy_forward without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same kernels and the same result bit for bit as
+ * policy_forward, but its scratch (padded weights and inputs, activations,
+ * split-K partials) lives in a fixed device array of the library, about
+ * 12 MB, of which each GPU that calls it keeps one copy until the process
+ * ends. B <= POLICY_NOALLOC_MAX_B, else SIM_EINVAL with a message. The caller
+ * still passes theta, x and y. Asynchronous on the stream (no sync). Every
+ * call on one GPU shares that GPU's scratch: calls that overlap on one GPU
+ * (two streams, two threads) race and must be ordered by the caller. */
+#define POLICY_NOALLOC_MAX_B 512
+int policy_forward_noalloc(const float* theta, const float* x, float* y, int32_t B, int32_t gemm_mode,
+                           void* stream);
+
 /* Adam (Kingma & Ba 2015) on n FP32 values: m = b1 m + (1-b1) g,
  * v = b2 v + (1-b2) g^2, w -= lr * (m/(1-b1^t)) / (sqrt(v/(1-b2^t)) + eps).
  * t >= 1 is the 1-based update count. */

@@ -103,6 +103,7 @@ _SIGS = {
     "surrogate_load": (c_int, [c_void_p, c_void_p, c_void_p]),
     "sim_surrogate_step": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                    c_void_p, c_int, c_int, ctypes.POINTER(c_float), c_void_p]),
+    "policy_forward_noalloc": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p]),
     "adam_step": (c_int, [c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_float, c_float,
                           c_float, c_float, c_int, c_void_p]),
 }
@@ -344,6 +345,11 @@ def bptt_get_timing(b):
 
 def policy_forward(theta, x, y, gemm_mode=POLICY_GEMM_FP32):
     _call("policy_forward", ptr(theta, torch.float32), ptr(x, torch.float32), ptr(y, torch.float32),
+          int(x.shape[0]), int(gemm_mode), stream())
+
+
+def policy_forward_noalloc(theta, x, y, gemm_mode=POLICY_GEMM_FP32):
+    _call("policy_forward_noalloc", ptr(theta, torch.float32), ptr(x, torch.float32), ptr(y, torch.float32),
           int(x.shape[0]), int(gemm_mode), stream())
 
 

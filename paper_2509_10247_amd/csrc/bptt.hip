@@ -13,6 +13,7 @@
 // Backward sweep, last step first: loss terms, step VJP, action map, the MLP
 // backward on MFMA (weight gradients accumulated with deterministic split-K
 // reductions), observation backward, render VJP.
+#include <mutex>
 #include <vector>
 
 #include "mlp.h"
@@ -922,6 +923,64 @@ int policy_forward(const float* theta, const float* x, float* y, int32_t B, int3
   if (rc) return rc;
   if (e != hipSuccess) return fail(SIM_EHIP, "policy_forward: %s", hipGetErrorString(e));
   return SIM_OK;
+}
+
+// policy_forward_noalloc: the same forward with its scratch (padded first
+// layer, padded inputs, hidden activations, split-K partials of the first
+// layer) in a file-scope device array instead of a per-call allocation.
+// Each GPU that runs it holds its own copy of the array until the process
+// ends; host code reaches it only through the address hipGetSymbolAddress
+// returns on that device.
+constexpr size_t noalloc_floats(int B) {
+  return (size_t)kHid * kObsPad + (size_t)B * kObsPad + 2 * (size_t)B * kHid + (size_t)kSplitL1 * B * kHid + 64;
+}
+static __device__ __align__(256) float scratch[noalloc_floats(POLICY_NOALLOC_MAX_B)];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static float* g_scratch_ptr[kMaxDevices] = {};
+
+// Address of this device's copy of scratch, looked up once per device with
+// that device current.
+static int noalloc_scratch(float** out) {
+  int dev = -1;
+  DA_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(SIM_ENODEV, "policy_forward_noalloc: device %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(SIM_EHIP, "policy_forward_noalloc: hipGetSymbolAddress: %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<float*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return SIM_OK;
+}
+
+int policy_forward_noalloc(const float* theta, const float* x, float* y, int32_t B, int32_t gemm_mode,
+                           void* stream) {
+  DA_REQUIRE(B >= 0, "policy_forward_noalloc: B must be >= 0");
+  DA_REQUIRE(B <= POLICY_NOALLOC_MAX_B, "policy_forward_noalloc: B = %d exceeds the scratch limit %d", (int)B,
+             POLICY_NOALLOC_MAX_B);
+  DA_REQUIRE(gemm_mode == POLICY_GEMM_FP32 || gemm_mode == POLICY_GEMM_BF16X3,
+             "policy_forward_noalloc: bad gemm_mode");
+  if (B == 0) return SIM_OK;
+  DA_REQUIRE(theta && x && y, "policy_forward_noalloc: null argument");
+  int rc = require_device();
+  if (rc) return rc;
+  float* mem = nullptr;
+  if ((rc = noalloc_scratch(&mem))) return rc;
+  hipStream_t st = as_stream(stream);
+  const size_t nW = (size_t)kHid * kObsPad, nX = (size_t)B * kObsPad, nH = (size_t)B * kHid;
+  float *W1p = mem, *X = W1p + nW, *H1 = X + nX, *H2 = H1 + nH;
+  float* part = H2 + nH;
+  // every scratch entry read below is written first in this call (padding
+  // columns included), so nothing needs clearing between calls
+  rc = launch_pad_rows(kHid, kObs, kObsPad, theta + kOffW1, kObs, W1p, st);
+  if (!rc) rc = launch_pad_rows(B, kObs, kObsPad, x, kObs, X, st);
+  if (!rc) rc = mlp_forward(B, policy_ptrs(theta, W1p), X, H1, H2, y, st, policy_prec(gemm_mode), part);
+  return rc;
 }
 
 int policy_backward(const float* theta, const float* x, const float* g_y, float* g_theta, float* g_x,
