@@ -18,6 +18,13 @@ struct SensorDev {
   const float4* cone_b = nullptr;  // [n_tiles] (sin alpha, t_limit, 0, 0)
   int n_rays = 0, n_tiles = 0;
   float max_range = 0.f;
+  // pinhole camera with a width that divides 64 (else pin_w = 0): ray
+  // r = j W + i has the body direction (1, ya + i yd, za + j zd) / norm and
+  // zfac = 1 / norm, so a kernel that walks rays in strides of 64 can form
+  // it without the table
+  int pin_w = 0;
+  float pin_ya = 0.f, pin_yd = 0.f, pin_za = 0.f, pin_zd = 0.f;
+  double pin64[4] = {0.0, 0.0, 0.0, 0.0};  // ya, yd, za, zd in FP64
 };
 
 struct SceneDev {

@@ -13,10 +13,12 @@
 // Culling is conservative, so the nearest hit (lowest index on ties) is
 // identical with culling on or off.
 //
-// Backward: one workgroup per agent; each thread recomputes the recorded
-// primitive's hit for its rays, applies dt/do = -n/(n.d) and
-// dt/dd = -t n/(n.d), and the workgroup reduces dL/do and dL/dR = sum g_d d_b^T
-// in a fixed order before pulling dL/dR back to the quaternion.
+// Backward, dt/do = -n/(n.d) and dt/dd = -t n/(n.d) per hit ray, reduced per
+// agent in a fixed order to dL/do and dL/dR = sum g_d d_b^T, which is pulled
+// back to the quaternion. Two kernels: render_vjp_obs_kernel (the BPTT
+// sweep) reads each hit's distance from the forward's observation row;
+// render_vjp_kernel (hit records alone: sim_step_backward, the LiDAR, the
+// attitude override) recomputes the recorded primitive's hit.
 #include "render_device.h"
 
 namespace da {
@@ -93,12 +95,25 @@ __device__ __forceinline__ d3 ray_dir64(const SensorDev& sen, int r, const doubl
              R[2][0] * b.x + R[2][1] * b.y + R[2][2] * b.z);
 }
 
-template <bool ROT, bool OBS, bool CYL>
+// dL/dqn of R(qn) (the quadratic form's derivative at the unit qn) from
+// G = dL/dR.
+__device__ __forceinline__ void rot_quat_vjp64(const double (&G)[3][3], const double (&qn)[4], double (&gq)[4]) {
+  const double w = qn[0], x = qn[1], y = qn[2], z = qn[3];
+  gq[0] = 2.0 * (-G[0][1] * z + G[0][2] * y + G[1][0] * z - G[1][2] * x - G[2][0] * y + G[2][1] * x);
+  gq[1] = 2.0 * (G[0][1] * y + G[0][2] * z + G[1][0] * y - 2.0 * G[1][1] * x - G[1][2] * w + G[2][0] * z +
+                 G[2][1] * w - 2.0 * G[2][2] * x);
+  gq[2] = 2.0 * (-2.0 * G[0][0] * y + G[0][1] * x + G[0][2] * w + G[1][0] * x + G[1][2] * z - G[2][0] * w +
+                 G[2][1] * z - 2.0 * G[2][2] * y);
+  gq[3] = 2.0 * (-2.0 * G[0][0] * z - G[0][1] * w + G[0][2] * x + G[1][0] * w - 2.0 * G[1][1] * z +
+                 G[1][2] * y + G[2][0] * x + G[2][1] * y);
+}
+
+template <bool ROT, bool CYL>
 __global__ __launch_bounds__(256, 5) void render_vjp_kernel(SceneDev sc, SensorDev sen,
                                                          const float* __restrict__ s, int A,
                                                          const float* __restrict__ g, int g_ld,
                                                          const int* __restrict__ rec,
-                                                         float* __restrict__ g_s, DepthObsGrad ob, int i0) {
+                                                         float* __restrict__ g_s, int i0) {
   __shared__ double red[12][4];
   __shared__ double Rsh[3][3];  // FP64 rotation, read by the grazing-hit path only
   const int i = i0 + (int)blockIdx.x;
@@ -185,34 +200,22 @@ __global__ __launch_bounds__(256, 5) void render_vjp_kernel(SceneDev sc, SensorD
   const int nt = sen.n_tiles;
   const int* recrow = rec + (size_t)i * nr;
   const float* grow = g + (size_t)i * g_ld;
-  const float* xrow = OBS ? ob.x + (size_t)i * g_ld : nullptr;
-  const float inv_dmax = OBS ? 1.f / ob.dmax : 1.f;
-  const float osc = OBS ? (ob.gl ? ob.gl[0] * ob.co : ob.co) : 0.f;
   int r_c = wave < nt ? sen.tile_rays[wave * kTileRays + lane] : -1;
   int k_c = r_c >= 0 ? recrow[r_c] : -1;
   float g_c = r_c >= 0 ? grow[r_c] : 0.f;
-  float x_c = (OBS && r_c >= 0) ? xrow[r_c] : 0.f;
   float4 db_c = r_c >= 0 ? sen.dirs[r_c] : make_float4(0.f, 0.f, 0.f, 0.f);
   int r_n = wave + 4 < nt ? sen.tile_rays[(wave + 4) * kTileRays + lane] : -1;
   for (int tile = wave; tile < nt; tile += 4) {
     const int r_nn = tile + 8 < nt ? sen.tile_rays[(tile + 8) * kTileRays + lane] : -1;
     const int k_n = r_n >= 0 ? recrow[r_n] : -1;
     const float g_n = r_n >= 0 ? grow[r_n] : 0.f;
-    const float x_n = (OBS && r_n >= 0) ? xrow[r_n] : 0.f;
     const float4 db_n = r_n >= 0 ? sen.dirs[r_n] : make_float4(0.f, 0.f, 0.f, 0.f);
     const int r = r_c, k = k_c;
-    float gv = g_c;
-    if (OBS) {
-      // d(loss)/d(depth): the observation's 1/d_max scaling and the
-      // obstacle term softplus(beta (d_safe - depth)) / beta
-      const float sig = __builtin_amdgcn_rcpf(1.f + __expf(-ob.beta * (ob.d_safe - x_c * ob.dmax)));
-      gv = gv * inv_dmax - osc * sig;
-    }
+    const float gv = g_c;
     const float4 db = db_c;
     r_c = r_n;
     k_c = k_n;
     g_c = g_n;
-    x_c = x_n;
     db_c = db_n;
     r_n = r_nn;
     // records outside this env's primitive range (or a room id without a
@@ -375,17 +378,335 @@ __global__ __launch_bounds__(256, 5) void render_vjp_kernel(SceneDev sc, SensorD
         for (int c = 0; c < 3; ++c) G[a][c] = tot[3 + a * 3 + c];
       double qn[4], inv_n;
       agent_frame64(s, A, i, qn, inv_n);
-      const double w = qn[0], x = qn[1], y = qn[2], z = qn[3];
       double gq[4];
-      gq[0] = 2.0 * (-G[0][1] * z + G[0][2] * y + G[1][0] * z - G[1][2] * x - G[2][0] * y + G[2][1] * x);
-      gq[1] = 2.0 * (G[0][1] * y + G[0][2] * z + G[1][0] * y - 2.0 * G[1][1] * x - G[1][2] * w +
-                     G[2][0] * z + G[2][1] * w - 2.0 * G[2][2] * x);
-      gq[2] = 2.0 * (-2.0 * G[0][0] * y + G[0][1] * x + G[0][2] * w + G[1][0] * x + G[1][2] * z -
-                     G[2][0] * w + G[2][1] * z - 2.0 * G[2][2] * y);
-      gq[3] = 2.0 * (-2.0 * G[0][0] * z - G[0][1] * w + G[0][2] * x + G[1][0] * w - 2.0 * G[1][1] * z +
-                     G[1][2] * y + G[2][0] * x + G[2][1] * y);
+      rot_quat_vjp64(G, qn, gq);
       const double dd = qn[0] * gq[0] + qn[1] * gq[1] + qn[2] * gq[2] + qn[3] * gq[3];
       #pragma unroll
+      for (int k = 0; k < 4; ++k) g_s[(6 + k) * (size_t)A + i] += (float)((gq[k] - qn[k] * dd) * inv_n);
+    }
+  }
+}
+
+// Moves a wave-uniform float into a scalar register (frees a vector register
+// in the hot loops below).
+__device__ __forceinline__ float uniform_f(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ double uniform_d(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll)), hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+  return __builtin_bit_cast(double, (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// Grazing sphere / agent / cylinder-side hit along the FP64 world direction
+// dd, for the observation-based render adjoint: with w = c - o (exact in
+// FP64 from the FP32 centre c, radius rad), N = t d - w (radial part for a
+// cylinder side) and N . d = -sqrt(disc) from the FP64 discriminant.
+// Returns false when FP64 finds no intersection (the ray then contributes
+// nothing).
+__device__ __forceinline__ bool grazing_normal64(d3 dd, float4 cr, bool side, f3 o, f3& N, float& nd, float& tt) {
+  const d3 w = dk3((double)cr.x - (double)o.x, (double)cr.y - (double)o.y, (double)cr.z - (double)o.z);
+  const double rad = cr.w;
+  const double wz = side ? 0.0 : w.z, dz = side ? 0.0 : dd.z;
+  const double a2 = dd.x * dd.x + dd.y * dd.y + dz * dz;
+  const double tc = dd.x * w.x + dd.y * w.y + dz * wz;
+  const double C = w.x * w.x + w.y * w.y + wz * wz - rad * rad;
+  const double disc = tc * tc - a2 * C;  // = a r^2 - |d x w|^2 over the radial parts
+  if (!(disc > 0.0)) return false;
+  const double sq = sqrt(disc);
+  const double t64 = C / (tc + sq);
+  tt = (float)t64;
+  N = mk3((float)(t64 * dd.x - w.x), (float)(t64 * dd.y - w.y), side ? 0.f : (float)(t64 * dd.z - w.z));
+  nd = (float)(-sq);
+  return true;
+}
+
+// Render adjoint with the forward's observation row at hand (the BPTT
+// sweep): the recorded hit's distance is t = depth / zfac, read back from
+// the observation value depth / d_max, so nothing is re-intersected. With
+// X = t d - (c - o) the hit point relative to the primitive's centre, every
+// primitive type has dt/do = -N / (N . d) and dt/dd = t dt/do for an
+// (unnormalised) outward normal N read off X: scaled per axis, u = |X| * q
+// with q = 1/h for a box or the room and (1/r, 1/r, 1/h) for a vertical
+// cylinder (whose x and y use the radial |X_xy| / r), the hit lies on the
+// faces where u is largest, and N keeps X on those axes (a box face: one
+// axis; a cylinder side: x and y; a cap: z). A sphere or agent has q = 0, so
+// N = X. The sign of N cancels. Sphere and cylinder-side hits within ~17 deg
+// of grazing take N . d from the FP64 discriminant instead (see below).
+// Every lane runs the same instructions (rays without a hit contribute
+// zero), rays are taken in row-major order
+// (coalesced loads, the next ray's loads issued before the current one is
+// processed), and the per-thread FP32 sums are reduced through LDS in a fixed
+// order, FP64 across lanes. One wavefront per agent (48 rays per lane for a
+// 64x48 camera), so the per-agent staging and reduction are spread over many
+// rays. The attitude override is not supported here.
+template <bool ROT, bool CYL, bool PIN>
+__global__ __launch_bounds__(64, 8) void render_vjp_obs_kernel(SceneDev sc, SensorDev sen,
+                                                             const float* __restrict__ s, int A,
+                                                             const float* __restrict__ g, int g_ld,
+                                                             const int* __restrict__ rec,
+                                                             float* __restrict__ g_s, DepthObsGrad ob, int i0) {
+  constexpr int kNT = 64, kRed = 12, kPart = 4;
+  __shared__ float red[kRed][kNT];
+  __shared__ double part[kRed][kPart];
+  __shared__ double Rsh[3][3];  // FP64 rotation, read by the grazing-hit path only
+  const int i = i0 + (int)blockIdx.x;
+  const int tid = threadIdx.x;
+  const int env = sc.agent_env[i];
+  const f3 o = mk3(uniform_f(s[i]), uniform_f(s[(size_t)A + i]), uniform_f(s[2 * (size_t)A + i]));
+  Rot R = agent_rot<ROT>(s, A, i);
+  if (ROT)
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) R.m[a][c] = uniform_f(R.m[a][c]);
+  if (tid == 0) {
+    double R64[3][3] = {{1.0, 0.0, 0.0}, {0.0, 1.0, 0.0}, {0.0, 0.0, 1.0}};
+    if (ROT) {
+      double qn[4], inv_n;
+      agent_frame64(s, A, i, qn, inv_n);
+      rot64(qn, R64);
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) Rsh[a][c] = R64[a][c];
+  }
+  const int s0 = sc.sph_off[env], ns = sc.sph_off[env + 1] - s0;
+  const int b0 = sc.box_off[env], nb = sc.box_off[env + 1] - b0;
+  int c0 = 0, nc = 0;
+  if (CYL && sc.cyl_off) {
+    c0 = sc.cyl_off[env];
+    nc = sc.cyl_off[env + 1] - c0;
+  }
+  int a0 = 0, na = 0;
+  if (sc.agents_visible) {
+    a0 = sc.agent_off[env];
+    na = sc.agent_off[env + 1] - a0;
+  }
+  const int nsbc = ns + nb + nc, np = nsbc + na;
+  // staged once per agent: PC[k] = (centre - o, cylinder flag), PQ[k] = the
+  // per-axis scale q; the room is entry np
+  extern __shared__ float4 vjp_lds[];
+  float4* PC = vjp_lds;
+  float4* PQ = vjp_lds + (np + 1);
+  float4* PR = vjp_lds + 2 * (np + 1);  // sphere / agent / cylinder: centre, radius (for the FP64 pass)
+  for (int k = tid; k <= np; k += kNT) {
+    float4 c = make_float4(0.f, 0.f, 0.f, 0.f), q = make_float4(0.f, 0.f, 0.f, 0.f);
+    float4 cr = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (k < ns) {
+      const float4 v = reinterpret_cast<const float4*>(sc.sph)[s0 + k];
+      c = make_float4(v.x, v.y, v.z, 0.f);
+      cr = v;
+    } else if (k < ns + nb) {
+      const float* b = sc.box + (size_t)(b0 + k - ns) * 6;
+      c = make_float4(b[0], b[1], b[2], 0.f);
+      q = make_float4(1.f / b[3], 1.f / b[4], 1.f / b[5], 0.f);
+    } else if (k < nsbc) {
+      const float* y = sc.cyl + (size_t)(c0 + k - ns - nb) * 5;
+      c = make_float4(y[0], y[1], y[2], 1.f);
+      q = make_float4(1.f / y[3], 1.f / y[3], 1.f / y[4], 0.f);
+      cr = make_float4(y[0], y[1], y[2], y[3]);
+    } else if (k < np) {
+      const int j = a0 + (k - nsbc);
+      c = make_float4(s[j], s[(size_t)A + j], s[2 * (size_t)A + j], 0.f);
+      cr = make_float4(c.x, c.y, c.z, sc.agent_radius);
+    } else if (sc.room) {
+      const float* rm = sc.room + (size_t)env * 6;
+      c = make_float4(0.5f * (rm[0] + rm[3]), 0.5f * (rm[1] + rm[4]), 0.5f * (rm[2] + rm[5]), 0.f);
+      q = make_float4(2.f / (rm[3] - rm[0]), 2.f / (rm[4] - rm[1]), 2.f / (rm[5] - rm[2]), 0.f);
+    }
+    PC[k] = make_float4(c.x - o.x, c.y - o.y, c.z - o.z, c.w);
+    PQ[k] = q;
+    PR[k] = cr;
+  }
+  __syncthreads();
+  float go[3] = {0.f, 0.f, 0.f};
+  float gR[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  const int nr = sen.n_rays;
+  const int* recrow = rec + (size_t)i * nr;
+  const float* grow = g + (size_t)i * g_ld;
+  const float* xrow = ob.x + (size_t)i * g_ld;
+  const float inv_dmax = uniform_f(1.f / ob.dmax);
+  const float osc = uniform_f(ob.gl ? ob.gl[0] * ob.co : ob.co);
+  const float nbeta = -ob.beta;
+  const int valid_hi = sc.room ? np : np - 1;  // largest record this env can produce
+  // 32-bit offsets from the per-agent row bases; the loads run one ray ahead
+  const unsigned unr = (unsigned)nr;
+  const bool pin = PIN;  // pinhole directions formed in place (sen.pin_w > 0)
+  const unsigned pw = pin ? (unsigned)sen.pin_w : 1u;
+  const float py = sen.pin_ya + (float)(tid % pw) * sen.pin_yd, py2 = 1.f + py * py;
+  const float pzs = uniform_f((float)(kNT / pw) * sen.pin_zd);
+  float pz = sen.pin_za + (float)(tid / pw) * sen.pin_zd;
+  int k_n = 0;
+  float g_n = 0.f, x_n = 0.f;
+  float4 db_n = make_float4(0.f, 0.f, 1.f, 1.f);
+  if ((unsigned)tid < unr) {
+    k_n = recrow[(unsigned)tid];
+    g_n = grow[(unsigned)tid];
+    x_n = xrow[(unsigned)tid];
+    if (!pin) db_n = sen.dirs[(unsigned)tid];
+  }
+  uint64_t gmask = 0;  // this lane's grazing rays (bit j: ray tid + j kNT)
+  for (unsigned r = tid; r < unr; r += kNT) {
+    const int k = k_n;
+    const float gin = g_n, x = x_n;
+    float4 db = db_n;
+    if (r + kNT < unr) {
+      k_n = recrow[r + kNT];
+      g_n = grow[r + kNT];
+      x_n = xrow[r + kNT];
+      if (!pin) db_n = sen.dirs[r + kNT];
+    }
+    if (pin) {
+      const float inv = __builtin_amdgcn_rsqf(py2 + pz * pz);
+      db = make_float4(inv, py * inv, pz * inv, inv);
+      pz += pzs;
+    }
+    // d(loss)/d(depth): the observation's 1/d_max scaling and the obstacle
+    // term softplus(beta (d_safe - depth)) / beta
+    const float depth = x * ob.dmax;
+    const float sig = __builtin_amdgcn_rcpf(1.f + __expf(nbeta * (ob.d_safe - depth)));
+    const float gv = gin * inv_dmax - osc * sig;
+    // miss / clamp / inside records, and records this env cannot produce,
+    // contribute nothing
+    const bool hit = k >= 0 && k <= valid_hi;
+    const int kk = hit ? k : 0;
+    const float t = depth * __builtin_amdgcn_rcpf(db.w);
+    const f3 d = ROT ? rot_apply(R, mk3(db.x, db.y, db.z)) : mk3(db.x, db.y, db.z);
+    const float4 pc = PC[kk], pq = PQ[kk];
+    const f3 X = mk3(t * d.x - pc.x, t * d.y - pc.y, t * d.z - pc.z);
+    float ux = fabsf(X.x) * pq.x, uy = fabsf(X.y) * pq.y;
+    const float uz = fabsf(X.z) * pq.z;
+    if (CYL) {
+      const float radial = __builtin_amdgcn_sqrtf(X.x * X.x + X.y * X.y) * pq.x;
+      ux = pc.w != 0.f ? radial : ux;
+      uy = pc.w != 0.f ? radial : uy;
+    }
+    const float um = fmaxf(ux, fmaxf(uy, uz));
+    f3 N = mk3(ux >= um ? X.x : 0.f, uy >= um ? X.y : 0.f, uz >= um ? X.z : 0.f);
+    float nd = dot(N, d), tt = t;
+    bool ok = hit;
+    // A sphere (or agent) hit, or a cylinder side hit, within ~17 deg of
+    // grazing (|n.d| < 0.3): N . d is a small difference of distances that
+    // the FP32 forward's t (and the FP32 direction) cannot resolve, so it is
+    // recomputed from the FP64 discriminant along the FP64 direction, as the
+    // hit-record adjoint does, in a second pass over those rays (a few per
+    // cent of the hits), which keeps the main loop's registers low.
+    const bool curved = pq.x == 0.f || (CYL && pc.w != 0.f && N.z == 0.f);
+    if (hit && curved && nd * nd < 0.09f * dot(N, N)) {
+      gmask |= 1ull << ((r - (unsigned)tid) / kNT);  // handled in the second pass
+      ok = false;
+    }
+    // d(loss)/do = c N with c = -(d loss/dt) / (N . d)
+    const float c = (ok && nd != 0.f) ? -gv * db.w * __builtin_amdgcn_rcpf(nd) : 0.f;
+    go[0] += c * N.x;
+    go[1] += c * N.y;
+    go[2] += c * N.z;
+    if (ROT) {
+      // d(loss)/dR = t (d(loss)/do) d_b^T
+      const float ct = c * tt;
+      const float n3[3] = {ct * N.x, ct * N.y, ct * N.z};
+      const float bb[3] = {db.x, db.y, db.z};
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int e = 0; e < 3; ++e) gR[a * 3 + e] += n3[a] * bb[e];
+    }
+  }
+  // per-thread sums to LDS; the second pass adds the grazing sphere /
+  // cylinder-side hits to them there, in ray order, so that the main loop's
+  // accumulators are not held in registers across it
+  constexpr int nq = ROT ? 12 : 3;
+#pragma unroll
+  for (int c = 0; c < nq; ++c) red[c][tid] = c < 3 ? go[c] : gR[c - 3];
+  // the FP64 rotation in scalar registers (uniform over the wavefront)
+  double R64[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) R64[a][c] = uniform_d(Rsh[a][c]);
+  while (gmask) {
+    const unsigned j = (unsigned)__builtin_ctzll(gmask);
+    gmask &= gmask - 1ull;
+    const unsigned r = tid + j * kNT;
+    const int k = recrow[r];
+    const float depth = xrow[r] * ob.dmax;
+    const float sig = __builtin_amdgcn_rcpf(1.f + __expf(nbeta * (ob.d_safe - depth)));
+    const float gv = grow[r] * inv_dmax - osc * sig;
+    // FP64 body direction: the pinhole formula, or the FP64 table
+    d3 dd;
+    float zf;
+    if (PIN) {
+      const double y = sen.pin64[0] + (double)(r % pw) * sen.pin64[1];
+      const double z = sen.pin64[2] + (double)(r / pw) * sen.pin64[3];
+      const double inv = 1.0 / sqrt(1.0 + y * y + z * z);
+      dd = dk3(inv, y * inv, z * inv);
+      zf = (float)inv;
+    } else {
+      const double* b64 = sen.dirs64 + (size_t)r * 4;
+      dd = dk3(b64[0], b64[1], b64[2]);
+      zf = (float)b64[3];
+    }
+    const float4 db = make_float4((float)dd.x, (float)dd.y, (float)dd.z, zf);  // body direction, zfac
+    if (ROT)
+      dd = dk3(R64[0][0] * dd.x + R64[0][1] * dd.y + R64[0][2] * dd.z, R64[1][0] * dd.x + R64[1][1] * dd.y + R64[1][2] * dd.z,
+               R64[2][0] * dd.x + R64[2][1] * dd.y + R64[2][2] * dd.z);
+    f3 N;
+    float nd, tt;
+    const bool side = !(k < ns || k >= nsbc);  // cylinder: radial (x, y) part only
+    if (!grazing_normal64(dd, PR[k], side, o, N, nd, tt)) continue;
+    const float c = -gv * db.w * __builtin_amdgcn_rcpf(nd);
+    red[0][tid] += c * N.x;
+    red[1][tid] += c * N.y;
+    red[2][tid] += c * N.z;
+    if (ROT) {
+      const float ct = c * tt;
+      const float n3[3] = {ct * N.x, ct * N.y, ct * N.z};
+      const float bb[3] = {db.x, db.y, db.z};
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int e = 0; e < 3; ++e) red[3 + a * 3 + e][tid] += n3[a] * bb[e];
+    }
+  }
+  // fixed-order reduction: 4 lanes per quantity each add 16 lanes' sums
+  // (FP64), then one lane per quantity adds the 4 partials
+  __syncthreads();
+  if (tid < nq * kPart) {
+    // partial p of quantity c: lanes p, p + 4, p + 8, ... (consecutive
+    // partials read consecutive LDS words)
+    const int c = tid / kPart, p = tid % kPart;
+    double v = 0.0;
+#pragma unroll
+    for (int j = 0; j < kNT / kPart; ++j) v += (double)red[c][p + kPart * j];
+    part[c][p] = v;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double tot[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      double v = 0.0;
+      if (c < nq)
+#pragma unroll
+        for (int j = 0; j < kPart; ++j) v += part[c][j];
+      tot[c] = v;
+    }
+    g_s[i] += (float)tot[0];
+    g_s[(size_t)A + i] += (float)tot[1];
+    g_s[2 * (size_t)A + i] += (float)tot[2];
+    if (ROT) {
+      double G[3][3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        for (int c = 0; c < 3; ++c) G[a][c] = tot[3 + a * 3 + c];
+      double qn[4], inv_n;
+      agent_frame64(s, A, i, qn, inv_n);
+      double gq[4];
+      rot_quat_vjp64(G, qn, gq);
+      const double dd = qn[0] * gq[0] + qn[1] * gq[1] + qn[2] * gq[2] + qn[3] * gq[3];
+#pragma unroll
       for (int k = 0; k < 4; ++k) g_s[(6 + k) * (size_t)A + i] += (float)((gq[k] - qn[k] * dd) * inv_n);
     }
   }
@@ -461,19 +782,37 @@ int launch_render_vjp(const SceneDev& sc, const SensorDev& sen, bool rotate, con
   const size_t lds = (size_t)2 * (sc.max_prims + 1) * sizeof(float4);
   const DepthObsGrad ob = obs ? *obs : DepthObsGrad{nullptr, 1.f, 0.f, 0.f, 0.f, nullptr};
   if (obs && !obs->x) return fail(SIM_EINVAL, "render_vjp: observation rows missing");
-  const int v = (rotate ? 4 : 0) | (obs ? 2 : 0) | (sc.cyl_off ? 1 : 0);
-  decltype(&render_vjp_kernel<true, true, true>) k = nullptr;
-  switch (v) {
-    case 7: k = render_vjp_kernel<true, true, true>; break;
-    case 6: k = render_vjp_kernel<true, true, false>; break;
-    case 5: k = render_vjp_kernel<true, false, true>; break;
-    case 4: k = render_vjp_kernel<true, false, false>; break;
-    case 3: k = render_vjp_kernel<false, true, true>; break;
-    case 2: k = render_vjp_kernel<false, true, false>; break;
-    case 1: k = render_vjp_kernel<false, false, true>; break;
-    default: k = render_vjp_kernel<false, false, false>; break;
+  if (obs) {
+    // the forward's observation rows give each hit's distance
+    if (sc.att) return fail(SIM_EINVAL, "render_vjp: the observation path takes no attitude override");
+    if (sen.n_rays > 64 * 64) return fail(SIM_EINVAL, "render_vjp: the observation path takes at most 4096 rays");
+    const int v = (rotate ? 4 : 0) | (sc.cyl_off ? 2 : 0) | (sen.pin_w > 0 ? 1 : 0);
+    decltype(&render_vjp_obs_kernel<true, true, true>) k = nullptr;
+    switch (v) {
+      case 7: k = render_vjp_obs_kernel<true, true, true>; break;
+      case 6: k = render_vjp_obs_kernel<true, true, false>; break;
+      case 5: k = render_vjp_obs_kernel<true, false, true>; break;
+      case 4: k = render_vjp_obs_kernel<true, false, false>; break;
+      case 3: k = render_vjp_obs_kernel<false, true, true>; break;
+      case 2: k = render_vjp_obs_kernel<false, true, false>; break;
+      case 1: k = render_vjp_obs_kernel<false, false, true>; break;
+      default: k = render_vjp_obs_kernel<false, false, false>; break;
+    }
+    const size_t lds3 = (size_t)3 * (sc.max_prims + 1) * sizeof(float4);
+    hipLaunchKernelGGL(k, dim3(n), dim3(64), lds3, st, sc, sen, s, A, g, g_ld, rec, g_s, ob, i0);
+    DA_LAUNCH_CHECK("render_vjp_obs_kernel");
+    return SIM_OK;
   }
-  hipLaunchKernelGGL(k, dim3(n), dim3(256), lds, st, sc, sen, s, A, g, g_ld, rec, g_s, ob, i0);
+  // hit records only: each hit is recomputed from its recorded primitive
+  const int v = (rotate ? 2 : 0) | (sc.cyl_off ? 1 : 0);
+  decltype(&render_vjp_kernel<true, true>) k = nullptr;
+  switch (v) {
+    case 3: k = render_vjp_kernel<true, true>; break;
+    case 2: k = render_vjp_kernel<true, false>; break;
+    case 1: k = render_vjp_kernel<false, true>; break;
+    default: k = render_vjp_kernel<false, false>; break;
+  }
+  hipLaunchKernelGGL(k, dim3(n), dim3(256), lds, st, sc, sen, s, A, g, g_ld, rec, g_s, i0);
   DA_LAUNCH_CHECK("render_vjp_kernel");
   return SIM_OK;
 }

@@ -218,6 +218,19 @@ int sim_create(const sim_config* cfg, sim_handle** out) {
   h->cfg = c;
   if (c.cam_w > 0) {
     rc = upload_sensor(build_camera(c.cam_w, c.cam_h, c.cam_hfov_deg, c.cam_max), c.cam_max, h->cam);
+    if (!rc && 64 % c.cam_w == 0) {
+      // y_i = -(2 (i + 1/2) / W - 1) tan(hfov/2), z_j = (1 - 2 (j + 1/2) / H) tan(vfov/2)
+      const double th = std::tan(c.cam_hfov_deg * M_PI / 360.0), tv = th * c.cam_h / c.cam_w;
+      h->cam.dev.pin_w = c.cam_w;
+      h->cam.dev.pin_ya = (float)(th * (1.0 - 1.0 / c.cam_w));
+      h->cam.dev.pin_yd = (float)(-2.0 * th / c.cam_w);
+      h->cam.dev.pin_za = (float)(tv * (1.0 - 1.0 / c.cam_h));
+      h->cam.dev.pin_zd = (float)(-2.0 * tv / c.cam_h);
+      h->cam.dev.pin64[0] = th * (1.0 - 1.0 / c.cam_w);
+      h->cam.dev.pin64[1] = -2.0 * th / c.cam_w;
+      h->cam.dev.pin64[2] = tv * (1.0 - 1.0 / c.cam_h);
+      h->cam.dev.pin64[3] = -2.0 * tv / c.cam_h;
+    }
     if (rc) {
       sim_destroy(h);
       return rc;

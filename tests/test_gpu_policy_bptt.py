@@ -176,3 +176,32 @@ def test_bptt_full_size_sampled_agents(mode):
     gs_ref = gs_ref * (len(lanes) / A)
     ok, rel, comp = grad_close(f64(gs8)[:, lanes], torch.tensor(gs_ref), min_comp=MIN_COMP[mode])
     assert ok, f"sampled g_s0 rel {rel:.2e} comp {comp:.4f}"
+
+
+@pytest.mark.parametrize("model", [wl.RB13, wl.PM9])
+def test_bptt_gradient_with_cylinders(model):
+    """BPTT through a scene with vertical cylinders beside spheres, boxes and
+    the room (8 envs, horizon 8, checkpoints every 4): the render adjoint's
+    cylinder side and cap hits inside the sweep, against the FP64 oracle."""
+    wk = wl.pillars(seed=31, n_envs=8, T=8, model=model)
+    wk.goal = wl.goals(np.random.default_rng(32), 8, wl.ROOM_C2)
+    wk.cam = CAM
+    print_case("bptt_cyl", model=model, A=8, T=8, K=4)
+    theta = _theta(33)
+    from paper_2509_10247_amd import bptt, env
+    e = env.from_workload(wk, agents_visible=False)
+    eng = bptt.BpttEngine(e, 8, 4, store_activations=True, policy_gemm=FP32)
+    loss = eng.forward(cuda(theta), cuda(wk.state0), cuda(wk.goal))
+    g_th, g_s0 = eng.backward()
+    L, g_ref, gs_ref, recs = opol.bptt_grad(model, wk.scene, wk.state0, wk.goal, wk.params, theta, 8, wk.dt,
+                                            wk.integrator, CAM)
+    ns, nb = np.diff(wk.scene.sph_off), np.diff(wk.scene.box_off)
+    cyl_hits = sum(int(((r >= torch.as_tensor(ns + nb)[:, None]) & (r < torch.as_tensor(ns + nb + 14)[:, None])).sum())
+                   for r in recs)
+    assert cyl_hits > 1000, "too few cylinder hits to test"
+    assert abs(loss.item() - L) <= 1e-4 * abs(L)
+    for name, a, b in BLOCKS:
+        ok, rel, comp = grad_close(f64(g_th)[a:b], torch.tensor(g_ref[a:b]))
+        assert ok, f"{name}: rel {rel:.2e} comp {comp:.4f}"
+    ok, rel, comp = grad_close(f64(g_s0), torch.tensor(gs_ref))
+    assert ok, f"g_s0: rel {rel:.2e} comp {comp:.4f}"
