@@ -57,8 +57,8 @@
  * counter-clockwise from body +x, output range [A][ch][az]. Point-mass models
  * keep the sensor world-aligned. Miss or value >= max -> max; origin inside an
  * obstacle (or outside the room) -> 0. Hit records (int32 per ray): env-local
- * primitive index (spheres, then boxes, then other agents, then the room),
- * -1 miss / clamp, -2 inside.
+ * primitive index (spheres, then boxes, then cylinders, then other agents,
+ * then the room), -1 miss / clamp, -2 inside.
  */
 #ifndef DIFFAERO_H
 #define DIFFAERO_H
@@ -75,9 +75,9 @@ enum { SIM_EULER = 0, SIM_RK4 = 1 };
 /* step flags bits */
 enum { SIM_FLAG_NONFINITE = 1, SIM_FLAG_COLLISION = 2 };
 
-/* Upper bounds checked by sim_set_scene (the per-env primitive list is staged
- * in LDS by the render kernels): obstacles (spheres + boxes) of one env, and
- * agents of one env. */
+/* Upper bounds checked by sim_set_scene and sim_set_cylinders (the per-env
+ * primitive list is staged in LDS by the render kernels): obstacles
+ * (spheres + boxes + cylinders) of one env, and agents of one env. */
 #define SIM_MAX_PRIMS_PER_ENV 1024
 #define SIM_MAX_AGENTS_PER_ENV 64
 
@@ -135,10 +135,13 @@ int sim_set_scene(sim_handle* h, const int32_t* sph_off, const float* sph, int32
  * previous cylinders). Synchronous. */
 int sim_set_cylinders(sim_handle* h, const int32_t* cyl_off, const float* cyl, int32_t n_cyl);
 
-/* Per-agent parameters SoA [P][A] (P = 0, 2, 8 by model, see above); kept by
- * reference like the scene. Required before sim_step for PM9 / RB13 /
- * NOMINAL13. */
-int sim_set_params(sim_handle* h, const float* params);
+/* Per-agent parameters SoA [P][A] (P = 0, 2, 8 by model, see above), device
+ * pointer. Copied on `stream` into a buffer the handle owns (allocated on the
+ * first call, synchronously), so the caller may release params once that
+ * copy is done, and work enqueued after it on the same stream sees the new
+ * values. Required before sim_step for PM9 / RB13 / NOMINAL13; a no-op for
+ * the models without parameters. */
+int sim_set_params(sim_handle* h, const float* params, void* stream);
 
 /* state[:, i] = init[:, i] for every lane i with mask[i] != 0 (mask NULL = all
  * lanes). SoA [C][A]. */
@@ -442,6 +445,49 @@ int policy_backward(const float* theta, const float* x, const float* g_y, float*
 #define POLICY_NOALLOC_MAX_B 512
 int policy_forward_noalloc(const float* theta, const float* x, float* y, int32_t B, int32_t gemm_mode,
                            void* stream);
+
+/* ------------------------------------------------------------------------
+ * Generic MLP (the MLP backbone of Sec. III-D) on the matrix cores
+ * ------------------------------------------------------------------------
+ * dims[0] -> dims[1] -> ... -> dims[n_layers]; hidden layers tanh
+ * (MLP_ACT_TANH) or SiLU (MLP_ACT_SILU), the output layer linear. kind
+ * MLP_F32: FP32 operands on the FP32 matrix cores; MLP_BF16: GEMM operands
+ * (inputs, weights, hidden activations, backward gradients) rounded to BF16
+ * (nearest even) as they are staged, FP32 accumulation. theta is the flat
+ * FP32 parameter vector [W_1 (dims[1] x dims[0], row-major), b_1, W_2, b_2,
+ * ...], the layout of the policy and surrogate vectors. All tensors are
+ * device pointers owned by the caller; the handle owns only a workspace
+ * (padded weights, layer gradients, split-K partials) that it allocates
+ * (synchronously) on the first call with a larger batch than before. A handle
+ * is not thread-safe. policy_forward / policy_backward are these layers at
+ * the policy's fixed shape (tanh hidden) with a tanh on the output, and the
+ * surrogate entry points these layers at its shape (SiLU hidden, BF16). */
+enum { MLP_F32 = 0, MLP_BF16 = 1 };
+enum { MLP_ACT_TANH = 0, MLP_ACT_SILU = 1 };
+typedef struct mlp_handle mlp_handle;
+/* 1 <= n_layers <= 64, widths 1..65536; SIM_EINVAL otherwise. No device work. */
+int mlp_create(int32_t kind, int32_t n_layers, const int32_t* dims, int32_t act, mlp_handle** out);
+int mlp_destroy(mlp_handle* h);
+/* Number of FP32 values of theta (and of its gradient and Adam moments). */
+int64_t mlp_param_count(const mlp_handle* h);
+/* FP32 values of the activation cache that mlp_forward fills for a batch:
+ * the padded input and each hidden layer's output (and SiLU pre-activation)
+ * at row pitches rounded up to a multiple of 4. */
+int64_t mlp_cache_floats(const mlp_handle* h, int32_t batch);
+/* y [batch][dims[n]] = MLP(x [batch][dims[0]]), row-major; act_cache
+ * (mlp_cache_floats(batch) floats, 16-byte aligned) receives what
+ * mlp_backward needs. batch = 0 is a no-op. */
+int mlp_forward(mlp_handle* h, const float* theta, const float* x, float* y, float* act_cache, int32_t batch,
+                void* stream);
+/* From act_cache of the mlp_forward on the same theta and batch and
+ * g_y = dL/dy [batch][dims[n]]: ADDS dL/dtheta to g_theta (accumulates over
+ * calls; zero it first for a fresh gradient) and writes g_x = dL/dx
+ * [batch][dims[0]] (nullable). */
+int mlp_backward(mlp_handle* h, const float* theta, const float* act_cache, const float* g_y, float* g_x,
+                 float* g_theta, int32_t batch, void* stream);
+/* Adam over the handle's mlp_param_count values, as adam_step. */
+int mlp_adam_step(mlp_handle* h, float* w, const float* g_w, float* m, float* v, float lr, float b1, float b2,
+                  float eps, int32_t t, void* stream);
 
 /* Adam (Kingma & Ba 2015) on n FP32 values: m = b1 m + (1-b1) g,
  * v = b2 v + (1-b2) g^2, w -= lr * (m/(1-b1^t)) / (sqrt(v/(1-b2^t)) + eps).

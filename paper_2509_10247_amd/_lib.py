@@ -57,7 +57,7 @@ _SIGS = {
     "sim_set_scene": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_int,
                               c_void_p, c_void_p]),
     "sim_set_cylinders": (c_int, [c_void_p, c_void_p, c_void_p, c_int]),
-    "sim_set_params": (c_int, [c_void_p, c_void_p]),
+    "sim_set_params": (c_int, [c_void_p, c_void_p, c_void_p]),
     "sim_reset": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "sim_step": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "sim_render": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
@@ -104,6 +104,13 @@ _SIGS = {
     "sim_surrogate_step": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                    c_void_p, c_int, c_int, ctypes.POINTER(c_float), c_void_p]),
     "policy_forward_noalloc": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p]),
+    "mlp_create": (c_int, [c_int, c_int, ctypes.POINTER(c_int), c_int, ctypes.POINTER(c_void_p)]),
+    "mlp_destroy": (c_int, [c_void_p]),
+    "mlp_param_count": (c_int64, [c_void_p]),
+    "mlp_cache_floats": (c_int64, [c_void_p, c_int]),
+    "mlp_forward": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
+    "mlp_backward": (c_int, [c_void_p] * 6 + [c_int, c_void_p]),
+    "mlp_adam_step": (c_int, [c_void_p] * 5 + [c_float, c_float, c_float, c_float, c_int, c_void_p]),
     "adam_step": (c_int, [c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_float, c_float,
                           c_float, c_float, c_int, c_void_p]),
 }
@@ -194,7 +201,7 @@ def sim_set_cylinders(h, cyl_off, cyl, n_cyl):
 
 
 def sim_set_params(h, params):
-    _call("sim_set_params", h, ptr(params, torch.float32))
+    _call("sim_set_params", h, ptr(params, torch.float32), stream())
 
 
 def sim_reset(h, state, init, mask=None):
@@ -357,6 +364,48 @@ def policy_backward(theta, x, g_y, g_theta, g_x=None, gemm_mode=POLICY_GEMM_FP32
     _call("policy_backward", ptr(theta, torch.float32), ptr(x, torch.float32),
           ptr(g_y, torch.float32), ptr(g_theta, torch.float32), ptr(g_x, torch.float32),
           int(x.shape[0]), int(gemm_mode), stream())
+
+
+MLP_F32, MLP_BF16 = 0, 1
+MLP_ACT_TANH, MLP_ACT_SILU = 0, 1
+
+
+class Mlp:
+    """Owner of an mlp_handle (generic MLP of the C ABI)."""
+
+    def __init__(self, dims, kind=MLP_F32, act=MLP_ACT_TANH):
+        self.dims = [int(d) for d in dims]
+        arr = (c_int * len(self.dims))(*self.dims)
+        h = c_void_p()
+        _call("mlp_create", int(kind), len(self.dims) - 1, arr, int(act), ctypes.byref(h))
+        self.h = h
+        self.n_params = int(load().mlp_param_count(h))
+
+    def cache_floats(self, batch):
+        return int(load().mlp_cache_floats(self.h, int(batch)))
+
+    def forward(self, theta, x, y, cache):
+        _call("mlp_forward", self.h, ptr(theta, torch.float32), ptr(x, torch.float32), ptr(y, torch.float32),
+              ptr(cache, torch.float32), int(x.shape[0]), stream())
+
+    def backward(self, theta, cache, g_y, g_theta, g_x=None):
+        _call("mlp_backward", self.h, ptr(theta, torch.float32), ptr(cache, torch.float32), ptr(g_y, torch.float32),
+              ptr(g_x, torch.float32), ptr(g_theta, torch.float32), int(g_y.shape[0]), stream())
+
+    def adam_step(self, w, g, m, v, lr, b1, b2, eps, t):
+        _call("mlp_adam_step", self.h, ptr(w, torch.float32), ptr(g, torch.float32), ptr(m, torch.float32),
+              ptr(v, torch.float32), float(lr), float(b1), float(b2), float(eps), int(t), stream())
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def adam_step(w, g, m, v, lr, b1, b2, eps, t):

@@ -587,7 +587,9 @@ int launch_gemm(bool a_kmaj, bool b_kmaj, int epi, GemmArgs g, int splits, hipSt
     // the layer shapes of the residual-dynamics MLP
     if (key == 3 && epi == EPI_BIAS_SILU) return gemm_bf16_t<true, true, EPI_BIAS_SILU>(g, 1, st);
     if (key == 3 && epi == EPI_BIAS) return gemm_bf16_t<true, true, EPI_BIAS>(g, 1, st);
+    if (key == 3 && epi == EPI_BIAS_TANH) return gemm_bf16_t<true, true, EPI_BIAS_TANH>(g, 1, st);
     if (key == 1 && epi == EPI_MUL_DSILU) return gemm_bf16_t<true, false, EPI_MUL_DSILU>(g, 1, st);
+    if (key == 1 && epi == EPI_MUL_DTANH) return gemm_bf16_t<true, false, EPI_MUL_DTANH>(g, 1, st);
     if (key == 1 && epi == EPI_STORE) return gemm_bf16_t<true, false, EPI_STORE>(g, 1, st);
     if (key == 0 && epi == EPI_PARTIAL) return gemm_bf16_t<false, false, EPI_PARTIAL>(g, splits, st);
     return fail(SIM_EINVAL, "gemm: bf16 layout %d / epilogue %d not built", key, epi);
@@ -601,6 +603,10 @@ int launch_gemm(bool a_kmaj, bool b_kmaj, int epi, GemmArgs g, int splits, hipSt
     case EPI_PARTIAL: return gemm_t<AK, BKM, EPI_PARTIAL>(g, splits, st); \
     case EPI_OBS_GRAD: return gemm_t<AK, BKM, EPI_OBS_GRAD>(g, 1, st);    \
   }
+  // the generic MLP's forward (bias, SiLU) and backward (SiLU') epilogues
+  if (key == 3 && epi == EPI_BIAS) return gemm_t<true, true, EPI_BIAS>(g, 1, st);
+  if (key == 3 && epi == EPI_BIAS_SILU) return gemm_t<true, true, EPI_BIAS_SILU>(g, 1, st);
+  if (key == 1 && epi == EPI_MUL_DSILU) return gemm_t<true, false, EPI_MUL_DSILU>(g, 1, st);
   switch (key) {
     case 0: DA_GEMM_CASE(false, false) break;
     case 1: DA_GEMM_CASE(true, false) break;

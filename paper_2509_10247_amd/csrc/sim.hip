@@ -256,6 +256,7 @@ int sim_destroy(sim_handle* h) {
   if (h->lidar.mem) (void)hipFree(h->lidar.mem);
   if (h->agent_env) (void)hipFree(h->agent_env);
   if (h->agent_off_owned) (void)hipFree(h->agent_off_owned);
+  if (h->params_owned) (void)hipFree(h->params_owned);
   delete h;
   return SIM_OK;
 }
@@ -394,10 +395,15 @@ int sim_set_cylinders(sim_handle* h, const int32_t* cyl_off, const float* cyl, i
   return SIM_OK;
 }
 
-int sim_set_params(sim_handle* h, const float* params) {
+int sim_set_params(sim_handle* h, const float* params, void* stream) {
   DA_REQUIRE(h, "sim_set_params: null handle");
-  DA_REQUIRE(params || param_dim(h->cfg.model) == 0, "sim_set_params: null params");
-  h->params = params;
+  const int P = param_dim(h->cfg.model);
+  if (P == 0) return SIM_OK;
+  DA_REQUIRE(params, "sim_set_params: null params");
+  const size_t bytes = (size_t)P * h->cfg.n_agents * sizeof(float);
+  if (!h->params_owned) DA_HIP(hipMalloc(&h->params_owned, bytes));
+  DA_HIP(hipMemcpyAsync(h->params_owned, params, bytes, hipMemcpyDeviceToDevice, as_stream(stream)));
+  h->params = h->params_owned;
   return SIM_OK;
 }
 

@@ -16,7 +16,8 @@ struct sim_handle {
   da::SceneDev scene;
   int32_t* agent_env = nullptr;        // owned [A]
   int32_t* agent_off_owned = nullptr;  // owned [E+1] when the caller passes NULL
-  const float* params = nullptr;       // caller's SoA [P][A]
+  const float* params = nullptr;       // SoA [P][A]: params_owned once set
+  float* params_owned = nullptr;       // owned copy of the caller's parameters
   std::vector<int32_t> host_sph_off, host_box_off, host_cyl_off, host_agent_off;
   int n_sph = 0, n_box = 0, n_cyl = 0;
   bool has_scene = false;

@@ -103,3 +103,34 @@ def test_sim_reset_is_bitwise(model):
     s = cuda(s0)
     _lib.sim_reset(e.h, s, cuda(init), None)
     assert np.array_equal(s.cpu().numpy().view(np.uint32), init.view(np.uint32))
+
+
+def test_set_params_is_a_stream_ordered_copy():
+    """sim_set_params copies the parameters on the stream into the handle's
+    own buffer: the caller's tensor may go away, and a later call changes
+    the parameters of the steps enqueued after it, bit for bit as a fresh
+    handle with those parameters."""
+    from paper_2509_10247_amd import env
+    A = 300
+    rng = np.random.default_rng(70)
+    p0 = wl.start_positions(rng, A, wl.ROOM_C2)
+    s0 = cuda(wl.initial_state(rng, wl.RB13, p0))
+    a = cuda(wl.actions(rng, wl.RB13, A, 1)[0])
+    prm1 = wl.params(rng, wl.RB13, A, drag_range=(0.1, 0.5))
+    prm2 = wl.params(rng, wl.RB13, A, drag_range=(0.1, 0.5))
+    e = env.Env(n_envs=A, n_agents=A, model=wl.RB13, integrator=wl.RK4, dt=0.01)
+    from paper_2509_10247_amd import _lib
+    t1 = cuda(prm1)
+    _lib.sim_set_params(e.h, t1)
+    torch.cuda.synchronize()
+    t1.fill_(float("nan"))  # the caller's buffer after the copy: not read again
+    out1 = e.step(s0, a)
+    _lib.sim_set_params(e.h, cuda(prm2))
+    out2 = e.step(s0, a)
+    refs = []
+    for prm in (prm1, prm2):
+        f = env.Env(n_envs=A, n_agents=A, model=wl.RB13, integrator=wl.RK4, dt=0.01)
+        f.set_params(prm)
+        refs.append(f.step(s0, a))
+    assert torch.equal(out1, refs[0]) and torch.equal(out2, refs[1])
+    assert not torch.equal(out1, out2)
