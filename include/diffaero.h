@@ -520,6 +520,42 @@ int adam_step(int64_t n, float* w, const float* g, float* m, float* v, float lr,
 int sim_rollout(sim_handle* h, int32_t T, float* s, const float* a_seq, float* depth_ring,
                 float* lidar_ring, uint8_t* flags, int32_t mode, void* stream);
 
+/* A rollout with the task layer after every step (obstacle-avoidance task,
+ * Sec. III-C; rewards per step, Sec. III-D), as a Gym-like step with
+ * automatic reset. Per step t, in this order:
+ *   s'_{t+1} = step(s_t, a_t), a_t = a_seq + t*K*A;
+ *   images at s'_{t+1} (camera, LiDAR);
+ *   rewards, flags and counters as sim_task_step from s'_{t+1}, the camera
+ *   image at it (obstacle term; none without a camera) and k: reward_d,
+ *   reward [T][A] float and flags [T][A] uint8 row t; k [A] int32 in place;
+ *   s_{t+1} = s'_{t+1} with every finished (terminated or truncated) agent
+ *   set to its column of s_init [C][A];
+ *   images at s_{t+1} in ring slot t % 2 of depth_ring [2][A][H][W] /
+ *   lidar_ring [2][A][ch][az] (each required exactly when that sensor is
+ *   configured): the observation after the step. The rewards see the
+ *   images before the reset.
+ * goal [3][A]. s (SoA [C][A]) holds s_0 on entry and s_T on return. Every
+ * distance to another agent is taken before any agent moves. Outputs are
+ * identical in every mode and for every tuning choice, and equal those of
+ * sim_step, sim_render, sim_task_step and sim_render called per step.
+ * mode 0: per step a dynamics launch; one persistent kernel whose work
+ *         items are whole agents (camera and LiDAR image in one workgroup,
+ *         atomic queue in the tuned order), the workgroup then taking the
+ *         agent's rewards from the image it wrote; a per-env reset launch;
+ *         a persistent launch that renders again only the agents whose
+ *         image the reset changed (the reset agents; their whole env when
+ *         agents see each other); the T steps captured in a hipGraph;
+ *         requires agents_visible (SIM_EINVAL otherwise: not yet validated
+ *         for agents that do not see each other);
+ * mode 1: plain launch per operation, every agent rendered twice per step;
+ * mode 2: mode 0 without the graph.
+ * Of the tuning, blocks_per_cu and order apply (tile_group does not: an item
+ * is a whole agent). The handle owns the buffers (first call with a new shape
+ * allocates, synchronously). */
+int sim_rollout_task(sim_handle* h, const task_config* cfg, int32_t T, float* s, const float* s_init,
+                     const float* goal, int32_t* k, const float* a_seq, float* depth_ring, float* lidar_ring,
+                     float* reward_d, float* reward, uint8_t* flags, int32_t mode, void* stream);
+
 /* Sets the persistent render kernel's tuning: tile_group = camera / LiDAR tiles (64 rays
  * each) per work item, blocks_per_cu = persistent workgroups per compute unit
  * (1..16), order = 1 longest-first, 0 env order. Synchronous. */

@@ -87,6 +87,7 @@ _SIGS = {
     "policy_forward": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p]),
     "policy_backward": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p]),
     "sim_rollout": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
+    "sim_rollout_task": (c_int, [c_void_p, ctypes.POINTER(TaskConfig), c_int] + [c_void_p] * 10 + [c_int, c_void_p]),
     "sim_rollout_config": (c_int, [c_void_p, c_int, c_int, c_int]),
     "sim_rollout_get_config": (c_int, [c_void_p, ctypes.POINTER(c_int), ctypes.POINTER(c_int),
                                        ctypes.POINTER(c_int)]),
@@ -424,6 +425,14 @@ def sim_rollout(h, T, s, a_seq, depth_ring=None, lidar_ring=None, flags=None, mo
     _call("sim_rollout", h, int(T), ptr(s, torch.float32), ptr(a_seq, torch.float32),
           ptr(depth_ring, torch.float32), ptr(lidar_ring, torch.float32), ptr(flags, torch.uint8), int(mode),
           stream())
+
+
+def sim_rollout_task(h, cfg, T, s, s_init, goal, k, a_seq, reward_d, reward, flags, depth_ring=None,
+                     lidar_ring=None, mode=ROLLOUT_GRAPH):
+    _call("sim_rollout_task", h, ctypes.byref(cfg), int(T), ptr(s, torch.float32), ptr(s_init, torch.float32),
+          ptr(goal, torch.float32), ptr(k, torch.int32), ptr(a_seq, torch.float32), ptr(depth_ring, torch.float32),
+          ptr(lidar_ring, torch.float32), ptr(reward_d, torch.float32), ptr(reward, torch.float32),
+          ptr(flags, torch.uint8), int(mode), stream())
 
 
 def sim_rollout_config(h, tile_group, blocks_per_cu, order):

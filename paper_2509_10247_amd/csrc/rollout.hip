@@ -29,6 +29,7 @@
 #include "dyn_device.h"
 #include "render_device.h"
 #include "sim_internal.h"
+#include "task_device.h"
 
 namespace da {
 
@@ -87,6 +88,7 @@ constexpr bool rotates_m() {
 // both sensors).
 template <bool ROT, bool CULL, bool CYL>
 __device__ __forceinline__ void agent_item(const RolloutArgs& g, int4 w, RenderLds& L) {
+  if (w.z >= w.w) return;  // an agent without sensor tiles (its item only carries the task)
   const AgentStage ag = stage_agent<ROT, CYL>(g.sc, g.s, g.A, w.y, L);
   const int nc = g.depth ? g.cam.n_tiles : 0;
   for (int part = 0; part < 2; ++part) {
@@ -105,7 +107,10 @@ __global__ __launch_bounds__(256, 8) void rollout_render_kernel(RolloutArgs g) {
   for (;;) {
     if (threadIdx.x == 0) cur = atomicAdd(g.counter, 1);
     __syncthreads();
-    const int it = cur;
+    // the ticket in a scalar register: the exit branch is uniform in the
+    // compiled loop, so no lane re-enters the barrier ahead of the lane that
+    // draws the next ticket
+    const int it = __builtin_amdgcn_readfirstlane(cur);
     __syncthreads();  // every thread has read the ticket before it is replaced
     if (it >= g.n_items) break;  // uniform over the workgroup: all waves exit
     const int4 w = g.items[it];
@@ -117,6 +122,110 @@ __global__ __launch_bounds__(256, 8) void rollout_render_kernel(RolloutArgs g) {
 template <int M, int I>
 __global__ __launch_bounds__(256) void rollout_dyn_kernel(RolloutArgs g) {
   dyn_item<M, I>(g, blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Task layer inside the rollout (Sec. III-C task, Sec. III-D rewards per
+// step). Per step: the dynamics launch steps s_t to s'_{t+1}; a persistent
+// launch renders s'_{t+1}, one work item per agent (its whole camera and
+// LiDAR image in one workgroup), and the workgroup then computes that agent's
+// rewards, flags and counter from s'_{t+1} and the image it has just written
+// (task_agent, the launch-per-op task code); a second persistent launch
+// renders again the agents whose image the reset changed. The resets are a
+// small per-env launch in between, so that every distance to another agent is
+// taken before any agent moves; when agents see each other (agents_visible)
+// the whole env of a reset agent is rendered again. No workgroup waits for
+// another and the persistent loop ends every item uniformly over the
+// workgroup (the task's own lane-0 stores aside): the only cross-workgroup
+// traffic is the atomic ticket and list counters, and the launches order the
+// rest.
+// ---------------------------------------------------------------------------
+struct TaskStep {
+  TaskArgs task;        // s = s'_{t+1}, depth = the camera slot of step t (or null)
+  const float* s_init;  // [C][A] reset states
+  float* s_mut;         // = task.s, reset in place
+  int E;                // envs
+  int nt;               // sensor tiles per agent
+  int* list;            // [A] agents to render again after the reset
+  int* list_n;          // entries of list this step
+};
+
+__device__ __forceinline__ void reset_agent(const TaskStep& t, int j) {
+  const size_t A = (size_t)t.task.A;
+  for (int c = 0; c < t.task.C; ++c) t.s_mut[c * A + j] = t.s_init[c * A + j];
+}
+
+// The task of one agent as a call of its own: its lane-divergent regions stay
+// inside the callee, and the persistent loop around it keeps one loop whose
+// ticket draw and barriers every wavefront executes in the same order (inlined,
+// the compiler nests the loop so that lanes can re-enter the barrier ahead of
+// the lane that draws the next ticket).
+__device__ __noinline__ void task_in_rollout(const TaskArgs& g, int i, int lane) { (void)task_agent(g, i, lane); }
+
+template <bool ROT, bool CULL, bool CYL>
+__global__ __launch_bounds__(256, 8) void rollout_task_kernel(RolloutArgs g, TaskStep t) {
+  extern __shared__ float4 smem_f4[];
+  __shared__ int cur;
+  for (;;) {
+    if (threadIdx.x == 0) cur = atomicAdd(g.counter, 1);
+    __syncthreads();
+    // the ticket in a scalar register: the exit branch is uniform in the
+    // compiled loop, so no lane re-enters the barrier ahead of the lane that
+    // draws the next ticket
+    const int it = __builtin_amdgcn_readfirstlane(cur);
+    __syncthreads();  // every thread has read the ticket before it is replaced
+    if (it >= g.n_items) break;  // uniform over the workgroup: all waves exit
+    const int4 w = g.items[it];  // (ITEM_AGENT, i, 0, nt): the agent's whole image
+    RenderLds L = carve(smem_f4, g.sc.max_prims > 0 ? g.sc.max_prims : 1);
+    agent_item<ROT, CULL, CYL>(g, w, L);
+    __syncthreads();  // the image is complete, written by this workgroup
+    // wavefront 0 takes the task; a scalar branch (the wave's first thread
+    // index), so that no exec-masked region ends the loop body
+    if (__builtin_amdgcn_readfirstlane(threadIdx.x) == 0) task_in_rollout(t.task, w.y, threadIdx.x);
+  }
+}
+
+// Per env, once every agent has its rewards: the finished agents take their
+// reset state, and the agents whose image changed are listed for the second
+// render (the env's agents if any was reset and agents see each other, else
+// the reset agents).
+__global__ __launch_bounds__(256) void task_env_reset_kernel(TaskStep t) {
+  const int env = blockIdx.x * 256 + (int)threadIdx.x;
+  if (env >= t.E) return;
+  const SceneDev& sc = t.task.sc;
+  const int a0 = sc.agent_off[env], na = sc.agent_off[env + 1] - a0;
+  int n_done = 0;
+  for (int j = a0; j < a0 + na; ++j)
+    if (t.task.flags[j] & (TASK_TERMINATED | TASK_TRUNCATED)) {
+      ++n_done;
+      reset_agent(t, j);
+    }
+  if (!n_done) return;
+  if (sc.agents_visible) {
+    const int pos = atomicAdd(t.list_n, na);
+    for (int q = 0; q < na; ++q) t.list[pos + q] = a0 + q;
+  } else {
+    int pos = atomicAdd(t.list_n, n_done);
+    for (int j = a0; j < a0 + na; ++j)
+      if (t.task.flags[j] & (TASK_TERMINATED | TASK_TRUNCATED)) t.list[pos++] = j;
+  }
+}
+
+// The listed agents' images at the state after the reset, one agent per item.
+template <bool ROT, bool CULL, bool CYL>
+__global__ __launch_bounds__(256, 8) void rollout_rerender_kernel(RolloutArgs g, TaskStep t) {
+  extern __shared__ float4 smem_f4[];
+  __shared__ int cur;
+  const int n = __builtin_amdgcn_readfirstlane(*t.list_n);
+  for (;;) {
+    if (threadIdx.x == 0) cur = atomicAdd(g.counter, 1);
+    __syncthreads();
+    const int it = __builtin_amdgcn_readfirstlane(cur);
+    __syncthreads();
+    if (it >= n) break;
+    RenderLds L = carve(smem_f4, g.sc.max_prims > 0 ? g.sc.max_prims : 1);
+    agent_item<ROT, CULL, CYL>(g, make_int4(ITEM_AGENT, t.list[it], 0, t.nt), L);
+  }
 }
 
 __global__ void zero_ints_kernel(int* p, int n) {
@@ -153,6 +262,30 @@ static int launch_dyn_t(const RolloutArgs& g, bool, int, size_t, hipStream_t st)
   return SIM_OK;
 }
 
+template <int M, int I>
+static int launch_task_fused_t(const RolloutArgs& gd, const RolloutArgs& gr, const RolloutArgs& gre,
+                               const TaskStep& ts, bool cull, int grid, size_t lds, hipStream_t st) {
+  hipLaunchKernelGGL((rollout_dyn_kernel<M, I>), dim3(cdiv(gd.A, 256)), dim3(256), 0, st, gd);
+  DA_LAUNCH_CHECK("rollout_dyn_kernel");
+  constexpr bool ROT = rotates_m<M>();
+  decltype(&rollout_task_kernel<ROT, true, true>) k = nullptr, k2 = nullptr;
+  const bool cyl = gr.sc.cyl_off != nullptr;
+  if (cull) {
+    k = cyl ? rollout_task_kernel<ROT, true, true> : rollout_task_kernel<ROT, true, false>;
+    k2 = cyl ? rollout_rerender_kernel<ROT, true, true> : rollout_rerender_kernel<ROT, true, false>;
+  } else {
+    k = cyl ? rollout_task_kernel<ROT, false, true> : rollout_task_kernel<ROT, false, false>;
+    k2 = cyl ? rollout_rerender_kernel<ROT, false, true> : rollout_rerender_kernel<ROT, false, false>;
+  }
+  hipLaunchKernelGGL(k, dim3(grid), dim3(256), lds, st, gr, ts);
+  DA_LAUNCH_CHECK("rollout_task_kernel");
+  hipLaunchKernelGGL(task_env_reset_kernel, dim3(cdiv(ts.E, 256)), dim3(256), 0, st, ts);
+  DA_LAUNCH_CHECK("task_env_reset_kernel");
+  hipLaunchKernelGGL(k2, dim3(grid), dim3(256), lds, st, gre, ts);
+  DA_LAUNCH_CHECK("rollout_rerender_kernel");
+  return SIM_OK;
+}
+
 #define DA_ROLLOUT_DISPATCH(FN, model, integ, ...)                            \
   switch (model * 2 + integ) {                                                \
     case SIM_PM6 * 2 + 0: return FN<SIM_PM6, 0>(__VA_ARGS__);                 \
@@ -176,6 +309,12 @@ static int launch_dyn(const sim_handle* h, const RolloutArgs& g, hipStream_t st)
   DA_ROLLOUT_DISPATCH(launch_dyn_t, h->cfg.model, h->cfg.integrator, g, false, 0, 0, st);
 }
 
+static int launch_task_fused(const sim_handle* h, const RolloutArgs& gd, const RolloutArgs& gr,
+                             const RolloutArgs& gre, const TaskStep& ts, int grid, size_t lds, hipStream_t st) {
+  DA_ROLLOUT_DISPATCH(launch_task_fused_t, h->cfg.model, h->cfg.integrator, gd, gr, gre, ts, h->cfg.fov_cull != 0,
+                      grid, lds, st);
+}
+
 }  // namespace da
 
 using namespace da;
@@ -185,7 +324,7 @@ using namespace da;
 // ---------------------------------------------------------------------------
 struct RolloutPlan {
   int tile_group = 8, blocks_per_cu = 4, order = 1;  // order 1: longest first
-  bool tuned = false;
+  bool tuned = false, built = false;
   std::vector<int4> items;
   int4* items_dev = nullptr;
   int items_cap = 0;
@@ -195,6 +334,11 @@ struct RolloutPlan {
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t exec = nullptr;
   std::vector<uintptr_t> key;
+  hipGraphExec_t task_exec = nullptr;  // the task rollout's graph, cached apart
+  std::vector<uintptr_t> task_key;
+  std::vector<int4> task_items;        // the task rollout's items: one per agent, whole image
+  int4* task_items_dev = nullptr;
+  int* task_list = nullptr;            // [A] agents to render again after a reset
   int n_cu = 0;
 };
 
@@ -207,6 +351,9 @@ void rollout_plan_free(sim_handle* h) {
   RolloutPlan* p = reinterpret_cast<RolloutPlan*>(h->rollout);
   if (!p) return;
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->task_exec) (void)hipGraphExecDestroy(p->task_exec);
+  if (p->task_items_dev) (void)hipFree(p->task_items_dev);
+  if (p->task_list) (void)hipFree(p->task_list);
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   if (p->items_dev) (void)hipFree(p->items_dev);
   if (p->counters) (void)hipFree(p->counters);
@@ -216,7 +363,7 @@ void rollout_plan_free(sim_handle* h) {
 }
 
 static int build_items(sim_handle* h, RolloutPlan* p) {
-  std::vector<std::pair<double, int4>> items;
+  std::vector<std::pair<double, int4>> items, task_items;
   const auto& so = h->host_sph_off;
   const auto& bo = h->host_box_off;
   const auto& co = h->host_cyl_off;
@@ -227,19 +374,29 @@ static int build_items(sim_handle* h, RolloutPlan* p) {
     // combined tile index space: camera tiles, then LiDAR tiles
     const int nt = (h->cam.mem ? h->cam.dev.n_tiles : 0) + (h->lidar.mem ? h->lidar.dev.n_tiles : 0);
     const int tg = std::max(1, std::min(p->tile_group, nt));
-    for (int i = ao[e]; i < ao[e + 1]; ++i)
+    for (int i = ao[e]; i < ao[e + 1]; ++i) {
       for (int tb = 0; tb < nt; tb += tg) {
         const int te = std::min(nt, tb + tg);
         // staging cost + per-tile culling pass + casting against the env
         const double cost = 4.0 * np + (te - tb) * (64.0 + 8.0 * (np + 6));
         items.push_back({cost, make_int4(ITEM_AGENT, i, tb, te)});
       }
+      // the task rollout: the agent's whole image (empty without a sensor)
+      // and its rewards in one item
+      task_items.push_back({4.0 * np + nt * (64.0 + 8.0 * (np + 6)) + 1.0, make_int4(ITEM_AGENT, i, 0, nt)});
+    }
   }
-  if (p->order == 1)
-    std::stable_sort(items.begin(), items.end(),
-                     [](const std::pair<double, int4>& x, const std::pair<double, int4>& y) { return x.first > y.first; });
+  auto longest_first = [](const std::pair<double, int4>& x, const std::pair<double, int4>& y) {
+    return x.first > y.first;
+  };
+  if (p->order == 1) {
+    std::stable_sort(items.begin(), items.end(), longest_first);
+    std::stable_sort(task_items.begin(), task_items.end(), longest_first);
+  }
   p->items.resize(items.size());
   for (size_t k = 0; k < items.size(); ++k) p->items[k] = items[k].second;
+  p->task_items.resize(task_items.size());
+  for (size_t k = 0; k < task_items.size(); ++k) p->task_items[k] = task_items[k].second;
   const int n = (int)p->items.size();
   if (n > p->items_cap) {
     if (p->items_dev) DA_HIP(hipFree(p->items_dev));
@@ -248,11 +405,22 @@ static int build_items(sim_handle* h, RolloutPlan* p) {
   }
   // no sensor: no items; the render kernel's workgroups draw one ticket each and exit
   if (n > 0) DA_HIP(hipMemcpy(p->items_dev, p->items.data(), (size_t)n * sizeof(int4), hipMemcpyHostToDevice));
+  // one task item per agent, always A of them
+  const int na = (int)p->task_items.size();
+  if (!p->task_items_dev && na > 0) DA_HIP(hipMalloc(&p->task_items_dev, (size_t)na * sizeof(int4)));
+  if (na > 0)
+    DA_HIP(hipMemcpy(p->task_items_dev, p->task_items.data(), (size_t)na * sizeof(int4), hipMemcpyHostToDevice));
   if (p->exec) {
     (void)hipGraphExecDestroy(p->exec);
     p->exec = nullptr;
     p->key.clear();
   }
+  if (p->task_exec) {
+    (void)hipGraphExecDestroy(p->task_exec);
+    p->task_exec = nullptr;
+    p->task_key.clear();
+  }
+  p->built = true;
   return SIM_OK;
 }
 
@@ -262,13 +430,14 @@ static int ensure_plan(sim_handle* h, RolloutPlan* p, int T) {
     DA_HIP(hipGetDevice(&dev));
     DA_HIP(hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, dev));
   }
-  if (p->items.empty()) {
+  if (!p->built) {
     int rc = build_items(h, p);
     if (rc) return rc;
   }
+  // per step: the render tickets, the second render's tickets, the reset list's length
   if (T > p->counters_cap) {
     if (p->counters) DA_HIP(hipFree(p->counters));
-    DA_HIP(hipMalloc(&p->counters, (size_t)T * sizeof(int)));
+    DA_HIP(hipMalloc(&p->counters, (size_t)3 * T * sizeof(int)));
     p->counters_cap = T;
   }
   if (!p->s_tmp) DA_HIP(hipMalloc(&p->s_tmp, (size_t)state_dim(h->cfg.model) * h->cfg.n_agents * 4));
@@ -343,6 +512,91 @@ static int check_rollout_args(sim_handle* h, int T, float* s, const float* a_seq
   return SIM_OK;
 }
 
+// The T steps of a task rollout (Sec. III-C/III-D after each step): fused,
+// the three launches per step above; plain, the launch-per-op path (step,
+// render at s'_{t+1}, task layer with its reset, render of every agent after
+// the reset).
+static int enqueue_task_rollout(sim_handle* h, RolloutPlan* p, const task_config* cfg, int T, float* s,
+                                const float* s_init, const float* goal, int32_t* k, const float* a_seq,
+                                float* depth_ring, float* lidar_ring, float* reward_d, float* reward,
+                                uint8_t* task_flags, bool fused, hipStream_t st) {
+  const int A = h->cfg.n_agents, E = h->cfg.n_envs, C = state_dim(h->cfg.model), K = action_dim(h->cfg.model);
+  const size_t lds = render_lds_bytes(h->scene.max_prims > 0 ? h->scene.max_prims : 1,
+                                      std::max(h->cam.mem ? h->cam.dev.n_tiles : 0,
+                                               h->lidar.mem ? h->lidar.dev.n_tiles : 0));
+  const bool rot = h->cfg.model == SIM_RB13 || h->cfg.model == SIM_NOMINAL13;
+  const int nt = (h->cam.mem ? h->cam.dev.n_tiles : 0) + (h->lidar.mem ? h->lidar.dev.n_tiles : 0);
+  if (fused) {
+    hipLaunchKernelGGL(zero_ints_kernel, dim3(cdiv(3 * T, 256)), dim3(256), 0, st, p->counters, 3 * T);
+    DA_LAUNCH_CHECK("zero_ints_kernel");
+  }
+  for (int t = 0; t < T; ++t) {
+    RolloutArgs gd;
+    gd.sc = h->scene;
+    gd.cam = h->cam.dev;
+    gd.lidar = h->lidar.dev;
+    gd.s = (t & 1) ? p->s_tmp : s;
+    gd.s_next = (t & 1) ? s : p->s_tmp;
+    gd.a = a_seq + (size_t)t * K * A;
+    gd.prm = h->params;
+    gd.dt = h->cfg.dt;
+    gd.A = A;
+    gd.depth = depth_ring ? depth_ring + (size_t)(t & 1) * A * h->cam.dev.n_rays : nullptr;
+    gd.lidar_out = lidar_ring ? lidar_ring + (size_t)(t & 1) * A * h->lidar.dev.n_rays : nullptr;
+    gd.flags = nullptr;
+    gd.items = p->task_items_dev;
+    gd.n_items = (int)p->task_items.size();
+    gd.counter = p->counters + t;
+    RolloutArgs gr = gd;  // the render at s'_{t+1}
+    gr.s = gd.s_next;
+    RolloutArgs gre = gr;  // the second render, its own tickets
+    gre.counter = p->counters + T + t;
+    TaskStep ts;
+    ts.task.sc = h->scene;
+    ts.task.cfg = *cfg;
+    ts.task.A = A;
+    ts.task.C = C;
+    ts.task.n_rays = depth_ring ? h->cam.dev.n_rays : 0;
+    ts.task.s = gd.s_next;
+    ts.task.goal = goal;
+    ts.task.depth = gd.depth;
+    ts.task.k = k;
+    ts.task.r_d = reward_d + (size_t)t * A;
+    ts.task.r = reward + (size_t)t * A;
+    ts.task.flags = task_flags + (size_t)t * A;
+    ts.s_init = s_init;
+    ts.s_mut = gd.s_next;
+    ts.E = E;
+    ts.nt = nt;
+    ts.list = p->task_list;
+    ts.list_n = p->counters + 2 * T + t;
+    int rc;
+    if (fused) {
+      rc = launch_task_fused(h, gd, gr, gre, ts, p->n_cu * p->blocks_per_cu, lds, st);
+    } else {
+      rc = launch_dyn(h, gd, st);
+      for (int pass = 0; pass < 2 && !rc; ++pass) {
+        if (depth_ring)
+          rc = launch_render(h->scene, h->cam.dev, rot, h->cfg.fov_cull != 0, gr.s, A, gr.depth, nullptr,
+                             h->cam.dev.n_rays, 1.f, st);
+        if (!rc && lidar_ring)
+          rc = launch_render(h->scene, h->lidar.dev, rot, h->cfg.fov_cull != 0, gr.s, A, gr.lidar_out, nullptr,
+                             h->lidar.dev.n_rays, 1.f, st);
+        if (!rc && pass == 0)
+          rc = sim_task_step(h, cfg, gd.s_next, s_init, goal, gd.depth, k, ts.task.r_d, ts.task.r, ts.task.flags,
+                             st);
+      }
+    }
+    if (rc) return rc;
+  }
+  if (T & 1) {
+    const size_t n = (size_t)C * A;
+    hipLaunchKernelGGL(copy_floats_kernel, dim3((unsigned)cdiv64(n, 256)), dim3(256), 0, st, p->s_tmp, s, n);
+    DA_LAUNCH_CHECK("copy_floats_kernel");
+  }
+  return SIM_OK;
+}
+
 extern "C" {
 
 int sim_rollout(sim_handle* h, int32_t T, float* s, const float* a_seq, float* depth_ring, float* lidar_ring,
@@ -379,6 +633,58 @@ int sim_rollout(sim_handle* h, int32_t T, float* s, const float* a_seq, float* d
     p->key = key;
   }
   DA_HIP(hipGraphLaunch(p->exec, st));
+  return SIM_OK;
+}
+
+int sim_rollout_task(sim_handle* h, const task_config* cfg, int32_t T, float* s, const float* s_init,
+                     const float* goal, int32_t* k, const float* a_seq, float* depth_ring, float* lidar_ring,
+                     float* reward_d, float* reward, uint8_t* flags, int32_t mode, void* stream) {
+  int rc = check_rollout_args(h, T, s, a_seq, depth_ring, lidar_ring);
+  if (rc) return rc;
+  DA_REQUIRE(cfg && s_init && goal && k && reward_d && reward && flags, "sim_rollout_task: null argument");
+  DA_REQUIRE(cfg->beta > 0.f && cfg->max_steps >= 1 && cfg->goal_radius >= 0.f,
+             "sim_rollout_task: need beta > 0, max_steps >= 1, goal_radius >= 0");
+  DA_REQUIRE(mode >= 0 && mode <= 2, "sim_rollout_task: mode must be 0 (graph), 1 (plain) or 2 (fused, no graph)");
+  DA_REQUIRE(mode == 1 || h->cfg.agents_visible,
+             "sim_rollout_task: the fused modes are switched off for agents that do not see each other "
+             "(agents_visible = 0); use mode 1");
+  RolloutPlan* p = plan_of(h);
+  if ((rc = ensure_plan(h, p, T))) return rc;
+  if (!p->task_list) DA_HIP(hipMalloc(&p->task_list, (size_t)h->cfg.n_agents * sizeof(int)));
+  hipStream_t st = as_stream(stream);
+  if (mode != 0)
+    return enqueue_task_rollout(h, p, cfg, T, s, s_init, goal, k, a_seq, depth_ring, lidar_ring, reward_d, reward,
+                                flags, mode == 2, st);
+  std::vector<uintptr_t> key = {(uintptr_t)T, (uintptr_t)s, (uintptr_t)s_init, (uintptr_t)goal, (uintptr_t)k,
+                                (uintptr_t)a_seq, (uintptr_t)depth_ring, (uintptr_t)lidar_ring,
+                                (uintptr_t)reward_d, (uintptr_t)reward, (uintptr_t)flags, (uintptr_t)h->params,
+                                (uintptr_t)p->tile_group, (uintptr_t)p->blocks_per_cu, (uintptr_t)p->order};
+  // the configuration is captured by value into the kernels' arguments
+  uint32_t words[sizeof(task_config) / 4];
+  memcpy(words, cfg, sizeof(words));
+  for (uint32_t w : words) key.push_back(w);
+  if (!p->task_exec || key != p->task_key) {
+    if (p->task_exec) {
+      DA_HIP(hipGraphExecDestroy(p->task_exec));
+      p->task_exec = nullptr;
+    }
+    if (!p->cap_stream) DA_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+    DA_HIP(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+    rc = enqueue_task_rollout(h, p, cfg, T, s, s_init, goal, k, a_seq, depth_ring, lidar_ring, reward_d, reward,
+                              flags, true, p->cap_stream);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(p->cap_stream, &graph);
+    if (rc) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    if (e != hipSuccess) return fail(SIM_EHIP, "sim_rollout_task: capture failed: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&p->task_exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(SIM_EHIP, "sim_rollout_task: instantiate failed: %s", hipGetErrorString(e));
+    p->task_key = key;
+  }
+  DA_HIP(hipGraphLaunch(p->task_exec, st));
   return SIM_OK;
 }
 
