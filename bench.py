@@ -311,6 +311,42 @@ def uneven_section(T=128, reps=3, seed=0):
                      "agent_steps_per_s": round(A * T / dt, 1),
                      "rays_per_s": round(A * T * (3072 + 5760) / dt, 1)}
     out["fused_over_plain"] = round(out["plain"]["ms_per_rollout"] / out["fused_graph"]["ms_per_rollout"], 3)
+
+    # the same rollout with the task layer after every step: images at the
+    # stepped state, rewards, termination (collision, non-finite), truncation
+    # at max_steps, reset to the start states and the post-reset images
+    import numpy as np
+    rng = np.random.default_rng(seed + 1)
+    max_steps = 64
+    cfg = _lib.TaskConfig(0.01, 0.1, 1.0, 10.0, 1.0, 10.0, 1.0, 0.3, max_steps)
+    goal = torch.tensor(wl.goals(rng, A, wl.ROOM_C2), device="cuda")
+    k0 = torch.tensor(rng.integers(0, max_steps, size=A).astype(np.int32), device="cuda")
+    k = k0.clone()
+    r_d = torch.empty(T, A, device="cuda")
+    r = torch.empty(T, A, device="cuda")
+    tfl = torch.empty(T, A, dtype=torch.uint8, device="cuda")
+
+    def run_task(mode):
+        s.copy_(s0)
+        k.copy_(k0)
+        _lib.sim_rollout_task(e.h, cfg, T, s, s0, goal, k, acts, r_d, r, tfl, depth, lidar, mode)
+
+    for name, mode, n in (("task_fused_graph", _lib.ROLLOUT_GRAPH, reps), ("task_plain", _lib.ROLLOUT_PLAIN, 1)):
+        run_task(mode)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n):
+            run_task(mode)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / n
+        out[name] = {"ms_per_rollout": round(dt * 1e3, 2), "env_steps_per_s": round(8192 * T / dt, 1),
+                     "agent_steps_per_s": round(A * T / dt, 1)}
+    done = (tfl.to(torch.int32) & 3) > 0
+    out["task_resets_per_step"] = round(done.sum().item() / T, 1)
+    out["task_over_render_only"] = round(out["task_fused_graph"]["ms_per_rollout"]
+                                         / out["fused_graph"]["ms_per_rollout"], 3)
+    out["task_fused_over_plain"] = round(out["task_plain"]["ms_per_rollout"]
+                                         / out["task_fused_graph"]["ms_per_rollout"], 3)
     return out
 
 

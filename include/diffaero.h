@@ -540,11 +540,13 @@ int sim_rollout(sim_handle* h, int32_t T, float* s, const float* a_seq, float* d
  * sim_step, sim_render, sim_task_step and sim_render called per step.
  * mode 0: per step a dynamics launch; one persistent kernel whose work
  *         items are whole agents (camera and LiDAR image in one workgroup,
- *         atomic queue in the tuned order), the workgroup then taking the
- *         agent's rewards from the image it wrote; a per-env reset launch;
- *         a persistent launch that renders again only the agents whose
- *         image the reset changed (the reset agents; their whole env when
- *         agents see each other); the T steps captured in a hipGraph;
+ *         atomic queue in the tuned order) and which also yields each
+ *         agent's obstacle term (from the render) and nearest-surface
+ *         distance (from the staging of its env); a launch of one thread per
+ *         agent for the rewards, flags, counters and resets; a persistent
+ *         launch that renders again only the agents whose image the reset
+ *         changed (the reset agents; their whole env when agents see each
+ *         other); the T steps captured in a hipGraph;
  *         requires agents_visible (SIM_EINVAL otherwise: not yet validated
  *         for agents that do not see each other);
  * mode 1: plain launch per operation, every agent rendered twice per step;

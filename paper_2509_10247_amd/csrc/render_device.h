@@ -177,6 +177,51 @@ __device__ __forceinline__ Rot att_rot(const float* __restrict__ att, int A, int
 // (ray-cylinder tests last, after the cone tests).
 enum { kWorkRays = 0, kWorkSph, kWorkBox, kWorkAgt, kWorkTiles, kWorkCone, kWorkCyl, kWorkN };
 
+// Signed distance from a point to one primitive's surface (negative inside):
+// the collision check's forms, shared by every kernel that takes the
+// distance to the nearest surface, so that all of them agree bit for bit.
+__device__ __forceinline__ float sdf_sphere(f3 p, float4 c) {
+  const f3 w = mk3(p.x - c.x, p.y - c.y, p.z - c.z);
+  return sqrtf(dot(w, w)) - c.w;
+}
+
+__device__ __forceinline__ float sdf_box(f3 p, const float* __restrict__ b) {
+  const float qx = fabsf(p.x - b[0]) - b[3], qy = fabsf(p.y - b[1]) - b[4], qz = fabsf(p.z - b[2]) - b[5];
+  const float ex = fmaxf(qx, 0.f), ey = fmaxf(qy, 0.f), ez = fmaxf(qz, 0.f);
+  return sqrtf(ex * ex + ey * ey + ez * ez) + fminf(fmaxf(fmaxf(qx, qy), qz), 0.f);
+}
+
+// capped vertical cylinder: radial and axial excess, exterior norm + interior max
+__device__ __forceinline__ float sdf_cylinder(f3 p, const float* __restrict__ y) {
+  const float wx = p.x - y[0], wy = p.y - y[1];
+  const float qr = sqrtf(wx * wx + wy * wy) - y[3], qz = fabsf(p.z - y[2]) - y[4];
+  const float er = fmaxf(qr, 0.f), ez = fmaxf(qz, 0.f);
+  return sqrtf(er * er + ez * ez) + fminf(fmaxf(qr, qz), 0.f);
+}
+
+__device__ __forceinline__ float sdf_agent(f3 p, f3 q, float radius) {
+  const f3 w = mk3(p.x - q.x, p.y - q.y, p.z - q.z);
+  return sqrtf(dot(w, w)) - radius;
+}
+
+// distance to the nearest wall of the room (the inside is free space)
+__device__ __forceinline__ float sdf_room(f3 p, const float* __restrict__ rm) {
+  return fminf(fminf(fminf(p.x - rm[0], rm[3] - p.x), fminf(p.y - rm[1], rm[4] - p.y)),
+               fminf(p.z - rm[2], rm[5] - p.z));
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+__device__ __forceinline__ float wave_min(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fminf(v, __shfl_xor(v, off));
+  return v;
+}
+
 // An agent's environment staged in LDS (origin-relative primitives, cone
 // terms) with the values every tile of every sensor of that agent needs.
 struct AgentStage {
@@ -190,9 +235,12 @@ struct AgentStage {
 // Stages agent i's environment with the whole workgroup (256 threads); LDS
 // is re-staged on entry, so consecutive calls from one workgroup (the
 // persistent rollout kernel) are safe. CYL: the scene may hold cylinders.
-template <bool ROT, bool CYL>
+// SDF: also the distance from the agent's centre to the nearest surface (as
+// the collision check), per wavefront into md_red[0..3] before the final
+// barrier; their minimum is the distance.
+template <bool ROT, bool CYL, bool SDF = false>
 __device__ __forceinline__ AgentStage stage_agent(const SceneDev& sc, const float* __restrict__ s, int A, int i,
-                                                  RenderLds& L) {
+                                                  RenderLds& L, float* md_red = nullptr) {
   const int tid = threadIdx.x;
   __syncthreads();  // previous use of the LDS by this workgroup is complete
   const int env = sc.agent_env[i];
@@ -215,9 +263,11 @@ __device__ __forceinline__ AgentStage stage_agent(const SceneDev& sc, const floa
   if (tid == 0) *L.flag = 0;
   __syncthreads();
   bool ins = false;
+  float md = kInf;
   for (int k = tid; k < np; k += 256) {
     if (k < ns) {
       const float4 c = reinterpret_cast<const float4*>(sc.sph)[s0 + k];
+      if (SDF) md = fminf(md, sdf_sphere(o, c));
       const f3 w = mk3(c.x - o.x, c.y - o.y, c.z - o.z);
       const float r2 = c.w * c.w;
       const float C = dot(w, w) - r2;
@@ -229,6 +279,7 @@ __device__ __forceinline__ AgentStage stage_agent(const SceneDev& sc, const floa
       ins |= C <= 0.f;
     } else if (k < ns + nb) {
       const float* b = sc.box + (size_t)(b0 + k - ns) * 6;
+      if (SDF) md = fminf(md, sdf_box(o, b));
       const f3 lo = mk3(b[0] - b[3] - o.x, b[1] - b[4] - o.y, b[2] - b[5] - o.z);
       const f3 hi = mk3(b[0] + b[3] - o.x, b[1] + b[4] - o.y, b[2] + b[5] - o.z);
       L.pa[k] = make_float4(lo.x, lo.y, lo.z, 0.f);
@@ -240,6 +291,7 @@ __device__ __forceinline__ AgentStage stage_agent(const SceneDev& sc, const floa
       ins |= (lo.x < 0.f && hi.x > 0.f && lo.y < 0.f && hi.y > 0.f && lo.z < 0.f && hi.z > 0.f);
     } else if (CYL && k < nsbc) {
       const float* y = sc.cyl + (size_t)(c0 + k - ns - nb) * 5;
+      if (SDF) md = fminf(md, sdf_cylinder(o, y));
       const f3 w = mk3(y[0] - o.x, y[1] - o.y, y[2] - o.z);
       const float r2 = y[3] * y[3];
       const float C = w.x * w.x + w.y * w.y - r2;
@@ -258,6 +310,7 @@ __device__ __forceinline__ AgentStage stage_agent(const SceneDev& sc, const floa
         L.pc[k] = cp.c;
         L.pd[k] = cp.d;
       } else {
+        if (SDF) md = fminf(md, sdf_agent(o, mk3(s[j], s[(size_t)A + j], s[2 * (size_t)A + j]), sc.agent_radius));
         const f3 w = mk3(s[j] - o.x, s[(size_t)A + j] - o.y, s[2 * (size_t)A + j] - o.z);
         const float r2 = sc.agent_radius * sc.agent_radius;
         const float C = dot(w, w) - r2;
@@ -279,6 +332,11 @@ __device__ __forceinline__ AgentStage stage_agent(const SceneDev& sc, const floa
     if (tid == 0 && (rlo.x > 0.f || rlo.y > 0.f || rlo.z > 0.f || rhi.x < 0.f || rhi.y < 0.f ||
                      rhi.z < 0.f))
       ins = true;
+    if (SDF) md = fminf(md, sdf_room(o, rm));
+  }
+  if (SDF) {
+    md = wave_min(md);
+    if ((tid & 63) == 0) md_red[tid >> 6] = md;
   }
   if (ins) atomicOr(L.flag, 1);
   __syncthreads();
@@ -484,37 +542,16 @@ __device__ __forceinline__ float collide_one(const SceneDev& sc, const float* __
   const int env = sc.agent_env[i];
   const f3 p = mk3(s[i], s[(size_t)A + i], s[2 * (size_t)A + i]);
   float md = kInf;
-  for (int k = sc.sph_off[env]; k < sc.sph_off[env + 1]; ++k) {
-    const float4 c = reinterpret_cast<const float4*>(sc.sph)[k];
-    const f3 w = mk3(p.x - c.x, p.y - c.y, p.z - c.z);
-    md = fminf(md, sqrtf(dot(w, w)) - c.w);
-  }
-  for (int k = sc.box_off[env]; k < sc.box_off[env + 1]; ++k) {
-    const float* b = sc.box + (size_t)k * 6;
-    const float qx = fabsf(p.x - b[0]) - b[3], qy = fabsf(p.y - b[1]) - b[4],
-                qz = fabsf(p.z - b[2]) - b[5];
-    const float ex = fmaxf(qx, 0.f), ey = fmaxf(qy, 0.f), ez = fmaxf(qz, 0.f);
-    md = fminf(md, sqrtf(ex * ex + ey * ey + ez * ez) + fminf(fmaxf(fmaxf(qx, qy), qz), 0.f));
-  }
+  for (int k = sc.sph_off[env]; k < sc.sph_off[env + 1]; ++k)
+    md = fminf(md, sdf_sphere(p, reinterpret_cast<const float4*>(sc.sph)[k]));
+  for (int k = sc.box_off[env]; k < sc.box_off[env + 1]; ++k) md = fminf(md, sdf_box(p, sc.box + (size_t)k * 6));
   if (sc.cyl_off)
-    for (int k = sc.cyl_off[env]; k < sc.cyl_off[env + 1]; ++k) {
-      // capped cylinder: radial and axial excess, exterior norm + interior max
-      const float* y = sc.cyl + (size_t)k * 5;
-      const float wx = p.x - y[0], wy = p.y - y[1];
-      const float qr = sqrtf(wx * wx + wy * wy) - y[3], qz = fabsf(p.z - y[2]) - y[4];
-      const float er = fmaxf(qr, 0.f), ez = fmaxf(qz, 0.f);
-      md = fminf(md, sqrtf(er * er + ez * ez) + fminf(fmaxf(qr, qz), 0.f));
-    }
-  if (sc.room) {
-    const float* rm = sc.room + (size_t)env * 6;
-    md = fminf(md, fminf(fminf(fminf(p.x - rm[0], rm[3] - p.x), fminf(p.y - rm[1], rm[4] - p.y)),
-                         fminf(p.z - rm[2], rm[5] - p.z)));
-  }
+    for (int k = sc.cyl_off[env]; k < sc.cyl_off[env + 1]; ++k) md = fminf(md, sdf_cylinder(p, sc.cyl + (size_t)k * 5));
+  if (sc.room) md = fminf(md, sdf_room(p, sc.room + (size_t)env * 6));
   if (sc.agents_visible) {
     for (int j = sc.agent_off[env]; j < sc.agent_off[env + 1]; ++j) {
       if (j == i) continue;
-      const f3 w = mk3(p.x - s[j], p.y - s[(size_t)A + j], p.z - s[2 * (size_t)A + j]);
-      md = fminf(md, sqrtf(dot(w, w)) - sc.agent_radius);
+      md = fminf(md, sdf_agent(p, mk3(s[j], s[(size_t)A + j], s[2 * (size_t)A + j]), sc.agent_radius));
     }
   }
   return md;

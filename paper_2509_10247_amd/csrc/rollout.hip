@@ -35,6 +35,15 @@ namespace da {
 
 enum { ITEM_AGENT = 0 };
 
+// The thread that draws a persistent loop's work tickets: the last one, so
+// that its condition differs from the thread-0 and lane-0 regions of the loop
+// body. Where a body ends with a region under the same condition as the
+// ticket draw at the top of the loop, the compiler can thread that branch
+// across the back edge and give the drawing lane a path of its own: the other
+// lanes then re-enter the barrier and re-read the old ticket while the drawing
+// lane waits, and the kernel never ends.
+constexpr int kTicketThread = 255;
+
 struct RolloutArgs {
   SceneDev sc;
   SensorDev cam, lidar;
@@ -86,17 +95,23 @@ constexpr bool rotates_m() {
 // One agent work item: stage the agent's env, then its tiles [w.z, w.w) of
 // the combined camera-then-LiDAR tile range (one copy of the tile loop for
 // both sensors).
-template <bool ROT, bool CULL, bool CYL>
-__device__ __forceinline__ void agent_item(const RolloutArgs& g, int4 w, RenderLds& L) {
-  if (w.z >= w.w) return;  // an agent without sensor tiles (its item only carries the task)
-  const AgentStage ag = stage_agent<ROT, CYL>(g.sc, g.s, g.A, w.y, L);
+// term (nullable): the camera part also writes the obstacle term
+// term[i] = mean over its rays of softplus(beta (d_safe - depth)) / beta
+// (the render's fused epilogue; the item must then cover all camera tiles).
+// SDF: the staging also leaves the agent's nearest-surface distance per
+// wavefront in md_red[0..3] (the agent is staged even without sensor tiles).
+template <bool ROT, bool CULL, bool CYL, bool SDF = false>
+__device__ __forceinline__ void agent_item(const RolloutArgs& g, int4 w, RenderLds& L, float* term = nullptr,
+                                           float beta = 1.f, float d_safe = 0.f, float* md_red = nullptr) {
+  if (!SDF && w.z >= w.w) return;  // an agent without sensor tiles
+  const AgentStage ag = stage_agent<ROT, CYL, SDF>(g.sc, g.s, g.A, w.y, L, md_red);
   const int nc = g.depth ? g.cam.n_tiles : 0;
   for (int part = 0; part < 2; ++part) {
     const int b = part ? max(w.z, nc) - nc : w.z, e = part ? w.w - nc : min(w.w, nc);
     if (b >= e) continue;
     const SensorDev& sen = part ? g.lidar : g.cam;
     render_tiles<ROT, CULL, CYL>(ag, sen, L, b, e, part ? g.lidar_out : g.depth, nullptr, sen.n_rays, 1.f,
-                                 nullptr, 1.f, 0.f);
+                                 part ? nullptr : term, beta, d_safe);
   }
 }
 
@@ -105,7 +120,7 @@ __global__ __launch_bounds__(256, 8) void rollout_render_kernel(RolloutArgs g) {
   extern __shared__ float4 smem_f4[];
   __shared__ int cur;
   for (;;) {
-    if (threadIdx.x == 0) cur = atomicAdd(g.counter, 1);
+    if (threadIdx.x == kTicketThread) cur = atomicAdd(g.counter, 1);
     __syncthreads();
     // the ticket in a scalar register: the exit branch is uniform in the
     // compiled loop, so no lane re-enters the barrier ahead of the lane that
@@ -132,11 +147,11 @@ __global__ __launch_bounds__(256) void rollout_dyn_kernel(RolloutArgs g) {
 // rewards, flags and counter from s'_{t+1} and the image it has just written
 // (task_agent, the launch-per-op task code); a second persistent launch
 // renders again the agents whose image the reset changed. The resets are a
-// small per-env launch in between, so that every distance to another agent is
-// taken before any agent moves; when agents see each other (agents_visible)
-// the whole env of a reset agent is rendered again. No workgroup waits for
+// small launch in between (a thread per agent), so that every distance to
+// another agent is taken before any agent moves; when agents see each other
+// (agents_visible) the whole env of a reset agent is rendered again. No workgroup waits for
 // another and the persistent loop ends every item uniformly over the
-// workgroup (the task's own lane-0 stores aside): the only cross-workgroup
+// workgroup (the task's own thread-0 stores aside): the only cross-workgroup
 // traffic is the atomic ticket and list counters, and the launches order the
 // rest.
 // ---------------------------------------------------------------------------
@@ -148,6 +163,10 @@ struct TaskStep {
   int nt;               // sensor tiles per agent
   int* list;            // [A] agents to render again after the reset
   int* list_n;          // entries of list this step
+  float* term;          // [A] the obstacle term from the render's epilogue
+  float* md;            // [A] the distance to the nearest surface at s'_{t+1}
+  int* env_mark;        // [E] step stamp of the last listing of each env
+  int stamp;            // this step's stamp (t + 1; env_mark is cleared per rollout)
 };
 
 __device__ __forceinline__ void reset_agent(const TaskStep& t, int j) {
@@ -155,19 +174,13 @@ __device__ __forceinline__ void reset_agent(const TaskStep& t, int j) {
   for (int c = 0; c < t.task.C; ++c) t.s_mut[c * A + j] = t.s_init[c * A + j];
 }
 
-// The task of one agent as a call of its own: its lane-divergent regions stay
-// inside the callee, and the persistent loop around it keeps one loop whose
-// ticket draw and barriers every wavefront executes in the same order (inlined,
-// the compiler nests the loop so that lanes can re-enter the barrier ahead of
-// the lane that draws the next ticket).
-__device__ __noinline__ void task_in_rollout(const TaskArgs& g, int i, int lane) { (void)task_agent(g, i, lane); }
-
 template <bool ROT, bool CULL, bool CYL>
 __global__ __launch_bounds__(256, 8) void rollout_task_kernel(RolloutArgs g, TaskStep t) {
   extern __shared__ float4 smem_f4[];
   __shared__ int cur;
+  __shared__ float red[4];  // per-wavefront nearest-surface minima
   for (;;) {
-    if (threadIdx.x == 0) cur = atomicAdd(g.counter, 1);
+    if (threadIdx.x == kTicketThread) cur = atomicAdd(g.counter, 1);
     __syncthreads();
     // the ticket in a scalar register: the exit branch is uniform in the
     // compiled loop, so no lane re-enters the barrier ahead of the lane that
@@ -177,54 +190,59 @@ __global__ __launch_bounds__(256, 8) void rollout_task_kernel(RolloutArgs g, Tas
     if (it >= g.n_items) break;  // uniform over the workgroup: all waves exit
     const int4 w = g.items[it];  // (ITEM_AGENT, i, 0, nt): the agent's whole image
     RenderLds L = carve(smem_f4, g.sc.max_prims > 0 ? g.sc.max_prims : 1);
-    agent_item<ROT, CULL, CYL>(g, w, L);
-    __syncthreads();  // the image is complete, written by this workgroup
-    // wavefront 0 takes the task; a scalar branch (the wave's first thread
-    // index), so that no exec-masked region ends the loop body
-    if (__builtin_amdgcn_readfirstlane(threadIdx.x) == 0) task_in_rollout(t.task, w.y, threadIdx.x);
+    agent_item<ROT, CULL, CYL, true>(g, w, L, t.task.depth ? t.term : nullptr, t.task.cfg.beta, t.task.cfg.d_safe,
+                                     red);
+    // the obstacle term is in t.term (the render's epilogue, thread 0); the
+    // nearest-surface distance from the staging's per-wavefront minima (red is
+    // next written after the barriers at the top of the loop)
+    if (threadIdx.x == 0) t.md[w.y] = fminf(fminf(red[0], red[1]), fminf(red[2], red[3]));
   }
 }
 
-// Per env, once every agent has its rewards: the finished agents take their
-// reset state, and the agents whose image changed are listed for the second
-// render (the env's agents if any was reset and agents see each other, else
-// the reset agents).
-__global__ __launch_bounds__(256) void task_env_reset_kernel(TaskStep t) {
-  const int env = blockIdx.x * 256 + (int)threadIdx.x;
-  if (env >= t.E) return;
+// One thread per agent, after the render: the agent's rewards, flags and
+// counter from its state, obstacle term and nearest-surface distance (the
+// launch-per-op task code), then, if it finished, its reset state and its
+// listing for the second render (when agents see each other, the first
+// finished agent of an env lists the whole env). Every distance was taken in
+// the render launch, before any agent moved.
+__global__ __launch_bounds__(256) void task_finish_kernel(TaskStep t) {
+  const int i = blockIdx.x * 256 + (int)threadIdx.x;
+  if (i >= t.task.A) return;
+  const TaskAgent a = task_state(t.task, i);
   const SceneDev& sc = t.task.sc;
-  const int a0 = sc.agent_off[env], na = sc.agent_off[env + 1] - a0;
-  int n_done = 0;
-  for (int j = a0; j < a0 + na; ++j)
-    if (t.task.flags[j] & (TASK_TERMINATED | TASK_TRUNCATED)) {
-      ++n_done;
-      reset_agent(t, j);
-    }
-  if (!n_done) return;
-  if (sc.agents_visible) {
-    const int pos = atomicAdd(t.list_n, na);
-    for (int q = 0; q < na; ++q) t.list[pos + q] = a0 + q;
-  } else {
-    int pos = atomicAdd(t.list_n, n_done);
-    for (int j = a0; j < a0 + na; ++j)
-      if (t.task.flags[j] & (TASK_TERMINATED | TASK_TRUNCATED)) t.list[pos++] = j;
+  if (!task_write(t.task, i, a, t.task.depth ? t.term[i] : 0.f, t.md[i], sc.agent_radius)) return;
+  reset_agent(t, i);
+  if (!sc.agents_visible) {
+    t.list[atomicAdd(t.list_n, 1)] = i;
+    return;
   }
+  const int env = sc.agent_env[i];
+  if (atomicExch(&t.env_mark[env], t.stamp) == t.stamp) return;  // listed by another agent of the env
+  const int a0 = sc.agent_off[env], na = sc.agent_off[env + 1] - a0;
+  const int pos = atomicAdd(t.list_n, na);
+  for (int q = 0; q < na; ++q) t.list[pos + q] = a0 + q;
 }
 
-// The listed agents' images at the state after the reset, one agent per item.
+// The listed agents' images at the state after the reset; an item is
+// kRerenderTiles tiles of one agent, so that the few reset agents spread over
+// the CUs.
+constexpr int kRerenderTiles = 48;
+
 template <bool ROT, bool CULL, bool CYL>
 __global__ __launch_bounds__(256, 8) void rollout_rerender_kernel(RolloutArgs g, TaskStep t) {
   extern __shared__ float4 smem_f4[];
   __shared__ int cur;
-  const int n = __builtin_amdgcn_readfirstlane(*t.list_n);
+  const int G = t.nt > 0 ? (t.nt + kRerenderTiles - 1) / kRerenderTiles : 1;  // items per agent
+  const int n = __builtin_amdgcn_readfirstlane(*t.list_n) * G;
   for (;;) {
-    if (threadIdx.x == 0) cur = atomicAdd(g.counter, 1);
+    if (threadIdx.x == kTicketThread) cur = atomicAdd(g.counter, 1);
     __syncthreads();
     const int it = __builtin_amdgcn_readfirstlane(cur);
     __syncthreads();
     if (it >= n) break;
+    const int tb = (it % G) * kRerenderTiles;
     RenderLds L = carve(smem_f4, g.sc.max_prims > 0 ? g.sc.max_prims : 1);
-    agent_item<ROT, CULL, CYL>(g, make_int4(ITEM_AGENT, t.list[it], 0, t.nt), L);
+    agent_item<ROT, CULL, CYL>(g, make_int4(ITEM_AGENT, t.list[it / G], tb, min(t.nt, tb + kRerenderTiles)), L);
   }
 }
 
@@ -268,7 +286,8 @@ static int launch_task_fused_t(const RolloutArgs& gd, const RolloutArgs& gr, con
   hipLaunchKernelGGL((rollout_dyn_kernel<M, I>), dim3(cdiv(gd.A, 256)), dim3(256), 0, st, gd);
   DA_LAUNCH_CHECK("rollout_dyn_kernel");
   constexpr bool ROT = rotates_m<M>();
-  decltype(&rollout_task_kernel<ROT, true, true>) k = nullptr, k2 = nullptr;
+  decltype(&rollout_task_kernel<ROT, true, true>) k = nullptr;
+  decltype(&rollout_rerender_kernel<ROT, true, true>) k2 = nullptr;
   const bool cyl = gr.sc.cyl_off != nullptr;
   if (cull) {
     k = cyl ? rollout_task_kernel<ROT, true, true> : rollout_task_kernel<ROT, true, false>;
@@ -279,8 +298,8 @@ static int launch_task_fused_t(const RolloutArgs& gd, const RolloutArgs& gr, con
   }
   hipLaunchKernelGGL(k, dim3(grid), dim3(256), lds, st, gr, ts);
   DA_LAUNCH_CHECK("rollout_task_kernel");
-  hipLaunchKernelGGL(task_env_reset_kernel, dim3(cdiv(ts.E, 256)), dim3(256), 0, st, ts);
-  DA_LAUNCH_CHECK("task_env_reset_kernel");
+  hipLaunchKernelGGL(task_finish_kernel, dim3(cdiv(gd.A, 256)), dim3(256), 0, st, ts);
+  DA_LAUNCH_CHECK("task_finish_kernel");
   hipLaunchKernelGGL(k2, dim3(grid), dim3(256), lds, st, gre, ts);
   DA_LAUNCH_CHECK("rollout_rerender_kernel");
   return SIM_OK;
@@ -338,7 +357,8 @@ struct RolloutPlan {
   std::vector<uintptr_t> task_key;
   std::vector<int4> task_items;        // the task rollout's items: one per agent, whole image
   int4* task_items_dev = nullptr;
-  int* task_list = nullptr;            // [A] agents to render again after a reset
+  int* task_list = nullptr;            // [A] agents to render again after a reset, then [E] env stamps
+  float* task_term = nullptr;          // [A] obstacle terms, then [A] nearest-surface distances
   int n_cu = 0;
 };
 
@@ -354,6 +374,8 @@ void rollout_plan_free(sim_handle* h) {
   if (p->task_exec) (void)hipGraphExecDestroy(p->task_exec);
   if (p->task_items_dev) (void)hipFree(p->task_items_dev);
   if (p->task_list) (void)hipFree(p->task_list);
+  if (p->task_term) (void)hipFree(p->task_term);
+
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   if (p->items_dev) (void)hipFree(p->items_dev);
   if (p->counters) (void)hipFree(p->counters);
@@ -512,86 +534,111 @@ static int check_rollout_args(sim_handle* h, int T, float* s, const float* a_seq
   return SIM_OK;
 }
 
+// Arguments of step t of a task rollout: gd the dynamics (s_t -> s'_{t+1}),
+// gr the render at s'_{t+1} with its tickets, gre the second render with its
+// own tickets, ts the task and reset of the step.
+struct TaskRolloutIO {
+  const task_config* cfg;
+  int T;
+  float* s;
+  const float* s_init;
+  const float* goal;
+  int32_t* k;
+  const float* a_seq;
+  float *depth_ring, *lidar_ring, *reward_d, *reward;
+  uint8_t* flags;
+};
+
+static void task_step_args(const sim_handle* h, const RolloutPlan* p, const TaskRolloutIO& io, int t,
+                           RolloutArgs& gd, RolloutArgs& gr, RolloutArgs& gre, TaskStep& ts) {
+  const int A = h->cfg.n_agents, K = action_dim(h->cfg.model), T = io.T;
+  gd.sc = h->scene;
+  gd.cam = h->cam.dev;
+  gd.lidar = h->lidar.dev;
+  gd.s = (t & 1) ? p->s_tmp : io.s;
+  gd.s_next = (t & 1) ? io.s : p->s_tmp;
+  gd.a = io.a_seq + (size_t)t * K * A;
+  gd.prm = h->params;
+  gd.dt = h->cfg.dt;
+  gd.A = A;
+  gd.depth = io.depth_ring ? io.depth_ring + (size_t)(t & 1) * A * h->cam.dev.n_rays : nullptr;
+  gd.lidar_out = io.lidar_ring ? io.lidar_ring + (size_t)(t & 1) * A * h->lidar.dev.n_rays : nullptr;
+  gd.flags = nullptr;
+  gd.items = p->task_items_dev;
+  gd.n_items = (int)p->task_items.size();
+  gd.counter = p->counters + t;
+  gr = gd;  // the render at s'_{t+1}
+  gr.s = gd.s_next;
+  gre = gr;  // the second render, its own tickets
+  gre.counter = p->counters + T + t;
+  ts.task.sc = h->scene;
+  ts.task.cfg = *io.cfg;
+  ts.task.A = A;
+  ts.task.C = state_dim(h->cfg.model);
+  ts.task.n_rays = io.depth_ring ? h->cam.dev.n_rays : 0;
+  ts.task.s = gd.s_next;
+  ts.task.goal = io.goal;
+  ts.task.depth = gd.depth;
+  ts.task.k = io.k;
+  ts.task.r_d = io.reward_d + (size_t)t * A;
+  ts.task.r = io.reward + (size_t)t * A;
+  ts.task.flags = io.flags + (size_t)t * A;
+  ts.s_init = io.s_init;
+  ts.s_mut = gd.s_next;
+  ts.E = h->cfg.n_envs;
+  ts.nt = (h->cam.mem ? h->cam.dev.n_tiles : 0) + (h->lidar.mem ? h->lidar.dev.n_tiles : 0);
+  ts.list = p->task_list;
+  ts.list_n = p->counters + 2 * T + t;
+  ts.term = p->task_term;
+  ts.md = p->task_term + h->cfg.n_agents;
+  ts.env_mark = p->task_list + h->cfg.n_agents;
+  ts.stamp = t + 1;
+  ts.task.tile_rays = h->cam.dev.tile_rays;
+  ts.task.n_tiles = io.depth_ring ? h->cam.dev.n_tiles : 0;
+}
+
 // The T steps of a task rollout (Sec. III-C/III-D after each step): fused,
-// the three launches per step above; plain, the launch-per-op path (step,
-// render at s'_{t+1}, task layer with its reset, render of every agent after
-// the reset).
-static int enqueue_task_rollout(sim_handle* h, RolloutPlan* p, const task_config* cfg, int T, float* s,
-                                const float* s_init, const float* goal, int32_t* k, const float* a_seq,
-                                float* depth_ring, float* lidar_ring, float* reward_d, float* reward,
-                                uint8_t* task_flags, bool fused, hipStream_t st) {
-  const int A = h->cfg.n_agents, E = h->cfg.n_envs, C = state_dim(h->cfg.model), K = action_dim(h->cfg.model);
+// the launches per step above; plain, the launch-per-op path (step, render at s'_{t+1}, task layer with its
+// reset, render of every agent after the reset).
+static int enqueue_task_rollout(sim_handle* h, RolloutPlan* p, const TaskRolloutIO& io, bool fused, hipStream_t st) {
+  const int A = h->cfg.n_agents, C = state_dim(h->cfg.model), T = io.T;
   const size_t lds = render_lds_bytes(h->scene.max_prims > 0 ? h->scene.max_prims : 1,
                                       std::max(h->cam.mem ? h->cam.dev.n_tiles : 0,
                                                h->lidar.mem ? h->lidar.dev.n_tiles : 0));
   const bool rot = h->cfg.model == SIM_RB13 || h->cfg.model == SIM_NOMINAL13;
-  const int nt = (h->cam.mem ? h->cam.dev.n_tiles : 0) + (h->lidar.mem ? h->lidar.dev.n_tiles : 0);
   if (fused) {
     hipLaunchKernelGGL(zero_ints_kernel, dim3(cdiv(3 * T, 256)), dim3(256), 0, st, p->counters, 3 * T);
     DA_LAUNCH_CHECK("zero_ints_kernel");
+    const int E = h->cfg.n_envs;
+    hipLaunchKernelGGL(zero_ints_kernel, dim3(cdiv(E, 256)), dim3(256), 0, st, p->task_list + A, E);
+    DA_LAUNCH_CHECK("zero_ints_kernel");
   }
   for (int t = 0; t < T; ++t) {
-    RolloutArgs gd;
-    gd.sc = h->scene;
-    gd.cam = h->cam.dev;
-    gd.lidar = h->lidar.dev;
-    gd.s = (t & 1) ? p->s_tmp : s;
-    gd.s_next = (t & 1) ? s : p->s_tmp;
-    gd.a = a_seq + (size_t)t * K * A;
-    gd.prm = h->params;
-    gd.dt = h->cfg.dt;
-    gd.A = A;
-    gd.depth = depth_ring ? depth_ring + (size_t)(t & 1) * A * h->cam.dev.n_rays : nullptr;
-    gd.lidar_out = lidar_ring ? lidar_ring + (size_t)(t & 1) * A * h->lidar.dev.n_rays : nullptr;
-    gd.flags = nullptr;
-    gd.items = p->task_items_dev;
-    gd.n_items = (int)p->task_items.size();
-    gd.counter = p->counters + t;
-    RolloutArgs gr = gd;  // the render at s'_{t+1}
-    gr.s = gd.s_next;
-    RolloutArgs gre = gr;  // the second render, its own tickets
-    gre.counter = p->counters + T + t;
+    RolloutArgs gd, gr, gre;
     TaskStep ts;
-    ts.task.sc = h->scene;
-    ts.task.cfg = *cfg;
-    ts.task.A = A;
-    ts.task.C = C;
-    ts.task.n_rays = depth_ring ? h->cam.dev.n_rays : 0;
-    ts.task.s = gd.s_next;
-    ts.task.goal = goal;
-    ts.task.depth = gd.depth;
-    ts.task.k = k;
-    ts.task.r_d = reward_d + (size_t)t * A;
-    ts.task.r = reward + (size_t)t * A;
-    ts.task.flags = task_flags + (size_t)t * A;
-    ts.s_init = s_init;
-    ts.s_mut = gd.s_next;
-    ts.E = E;
-    ts.nt = nt;
-    ts.list = p->task_list;
-    ts.list_n = p->counters + 2 * T + t;
+    task_step_args(h, p, io, t, gd, gr, gre, ts);
     int rc;
     if (fused) {
       rc = launch_task_fused(h, gd, gr, gre, ts, p->n_cu * p->blocks_per_cu, lds, st);
     } else {
       rc = launch_dyn(h, gd, st);
       for (int pass = 0; pass < 2 && !rc; ++pass) {
-        if (depth_ring)
+        if (io.depth_ring)
           rc = launch_render(h->scene, h->cam.dev, rot, h->cfg.fov_cull != 0, gr.s, A, gr.depth, nullptr,
                              h->cam.dev.n_rays, 1.f, st);
-        if (!rc && lidar_ring)
+        if (!rc && io.lidar_ring)
           rc = launch_render(h->scene, h->lidar.dev, rot, h->cfg.fov_cull != 0, gr.s, A, gr.lidar_out, nullptr,
                              h->lidar.dev.n_rays, 1.f, st);
         if (!rc && pass == 0)
-          rc = sim_task_step(h, cfg, gd.s_next, s_init, goal, gd.depth, k, ts.task.r_d, ts.task.r, ts.task.flags,
-                             st);
+          rc = sim_task_step(h, io.cfg, gd.s_next, io.s_init, io.goal, gd.depth, io.k, ts.task.r_d, ts.task.r,
+                             ts.task.flags, st);
       }
     }
     if (rc) return rc;
   }
   if (T & 1) {
     const size_t n = (size_t)C * A;
-    hipLaunchKernelGGL(copy_floats_kernel, dim3((unsigned)cdiv64(n, 256)), dim3(256), 0, st, p->s_tmp, s, n);
+    hipLaunchKernelGGL(copy_floats_kernel, dim3((unsigned)cdiv64(n, 256)), dim3(256), 0, st, p->s_tmp, io.s, n);
     DA_LAUNCH_CHECK("copy_floats_kernel");
   }
   return SIM_OK;
@@ -650,16 +697,19 @@ int sim_rollout_task(sim_handle* h, const task_config* cfg, int32_t T, float* s,
              "(agents_visible = 0); use mode 1");
   RolloutPlan* p = plan_of(h);
   if ((rc = ensure_plan(h, p, T))) return rc;
-  if (!p->task_list) DA_HIP(hipMalloc(&p->task_list, (size_t)h->cfg.n_agents * sizeof(int)));
+  // list [A] then env_mark [E]; term [A] then md [A]
+  if (!p->task_list)
+    DA_HIP(hipMalloc(&p->task_list, ((size_t)h->cfg.n_agents + h->cfg.n_envs) * sizeof(int)));
+  if (!p->task_term) DA_HIP(hipMalloc(&p->task_term, (size_t)2 * h->cfg.n_agents * sizeof(float)));
   hipStream_t st = as_stream(stream);
-  if (mode != 0)
-    return enqueue_task_rollout(h, p, cfg, T, s, s_init, goal, k, a_seq, depth_ring, lidar_ring, reward_d, reward,
-                                flags, mode == 2, st);
+  const TaskRolloutIO io{cfg, T, s, s_init, goal, k, a_seq, depth_ring, lidar_ring, reward_d, reward, flags};
+  if (mode != 0) return enqueue_task_rollout(h, p, io, mode == 2, st);
+  // the configuration and every pointer reach the kernels by value at
+  // capture: all are part of the key
   std::vector<uintptr_t> key = {(uintptr_t)T, (uintptr_t)s, (uintptr_t)s_init, (uintptr_t)goal, (uintptr_t)k,
                                 (uintptr_t)a_seq, (uintptr_t)depth_ring, (uintptr_t)lidar_ring,
                                 (uintptr_t)reward_d, (uintptr_t)reward, (uintptr_t)flags, (uintptr_t)h->params,
                                 (uintptr_t)p->tile_group, (uintptr_t)p->blocks_per_cu, (uintptr_t)p->order};
-  // the configuration is captured by value into the kernels' arguments
   uint32_t words[sizeof(task_config) / 4];
   memcpy(words, cfg, sizeof(words));
   for (uint32_t w : words) key.push_back(w);
@@ -670,8 +720,7 @@ int sim_rollout_task(sim_handle* h, const task_config* cfg, int32_t T, float* s,
     }
     if (!p->cap_stream) DA_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
     DA_HIP(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
-    rc = enqueue_task_rollout(h, p, cfg, T, s, s_init, goal, k, a_seq, depth_ring, lidar_ring, reward_d, reward,
-                              flags, true, p->cap_stream);
+    rc = enqueue_task_rollout(h, p, io, true, p->cap_stream);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(p->cap_stream, &graph);
     if (rc) {

@@ -2,19 +2,24 @@
 // differentiable and non-differentiable rewards per step): rewards, the
 // termination and truncation flags and the in-place reset of finished
 // agents. One wavefront per agent: its lanes reduce the obstacle term over
-// the agent's depth row (coalesced) and the distance to the nearest surface
-// over the env's primitives, and every lane then holds the same scalars. The
-// reset is a second launch, so that every agent's distance to the others is
+// the agent's depth row (in the order of the render's fused epilogue) and the
+// distance to the nearest surface over the env's primitives, and lane 0 writes
+// the results. The reset is a second launch, so that every agent's distance to the others is
 // taken before any of them moves.
 #include "sim_internal.h"
 #include "task_device.h"
 
 namespace da {
 
+// one wavefront per agent
 __global__ __launch_bounds__(256) void task_kernel(TaskArgs g) {
+  const int lane = threadIdx.x & 63;
   const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (i >= g.A) return;  // uniform over the wavefront; no workgroup barrier below
-  (void)task_agent(g, i, threadIdx.x & 63);
+  const TaskAgent a = task_state(g, i);
+  const float term = g.depth ? obstacle_term_wave(g, i, lane) : 0.f;
+  const float md = wave_min(nearest_surface(g.sc, g.s, g.A, i, a.p, lane, 64));
+  if (lane == 0) (void)task_write(g, i, a, term, md, g.sc.agent_radius);
 }
 
 // Gradient of the differentiable reward: with g = dL/dr_d[i],
@@ -88,6 +93,8 @@ int sim_task_step(sim_handle* h, const task_config* cfg, float* s, const float* 
   g.r = reward;
   g.flags = flags;
   hipStream_t st = as_stream(stream);
+  g.tile_rays = h->cam.dev.tile_rays;
+  g.n_tiles = depth ? h->cam.dev.n_tiles : 0;
   hipLaunchKernelGGL(task_kernel, dim3(cdiv(g.A, 4)), dim3(256), 0, st, g);
   DA_LAUNCH_CHECK("task_kernel");
   const int64_t n = (int64_t)g.A * g.C;

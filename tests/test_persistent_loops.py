@@ -3,9 +3,11 @@ cross-compiles gfx950 device code to assembly). Each persistent loop draws a
 work ticket in one thread, then every wavefront passes a barrier and reads the
 ticket. If the compiler nests that loop so that the barriers sit in an inner
 loop the ticket draw is outside of, lanes can re-enter the barrier and read a
-stale ticket while the drawing lane waits outside, and the kernel never ends.
-The test holds every barrier and the ticket atomic of these kernels at loop
-depth 1 (the persistent loop itself)."""
+stale ticket while the drawing lane waits outside, and the kernel never ends
+(it did so when the task layer's thread-0 stores ended the loop body and the
+ticket was drawn by thread 0 as well). The test holds every barrier and the
+ticket atomic of these kernels at loop depth 1 (the persistent loop
+itself)."""
 import os
 import re
 import shutil
