@@ -367,6 +367,10 @@ typedef struct bptt_config {
    *    step) per segment. Same gradient, bit for bit. */
   int32_t store_activations;
   int32_t policy_gemm;   /* POLICY_GEMM_FP32 or POLICY_GEMM_BF16X3 */
+  /* discount of the per-step loss, 0 < gamma <= 1: step t's loss is weighted
+   * by gamma^t (the short-horizon actor loss, Sec. III-E Eq. (6)); 1 gives the
+   * plain mean of the per-step losses, bit for bit. */
+  float gamma;
 } bptt_config;
 
 typedef struct bptt_handle bptt_handle;
@@ -390,6 +394,17 @@ int bptt_forward(bptt_handle* b, const float* theta, const float* s0, const floa
  * (render, policy, step), then runs the reverse sweep with the hand-written
  * adjoints. Must follow bptt_forward with the same theta / s0 / goal. */
 int bptt_backward(bptt_handle* b, const float* g_loss, float* g_theta, float* g_s0, void* stream);
+
+/* bptt_backward with a terminal gradient: g_sT = dJ/ds_T (SoA [C][A],
+ * nullable = 0) of a term J(s_T) added to the loss (the value term of the
+ * short-horizon actor loss, Sec. III-E Eq. (6)) seeds the reverse sweep; it is
+ * not scaled by g_loss. */
+int bptt_backward_terminal(bptt_handle* b, const float* g_loss, const float* g_sT, float* g_theta, float* g_s0,
+                           void* stream);
+
+/* The states s_0 .. s_T of the last bptt_forward into states
+ * [T+1][C][A] (device). Needs store_activations = 1 (SIM_EINVAL otherwise). */
+int bptt_get_states(bptt_handle* b, float* states, void* stream);
 
 /* Kernel timing (diagnostics for the roofline report): with mode 1 every
  * launch of the kernel classes below is bracketed by HIP events and runs
@@ -488,6 +503,52 @@ int mlp_backward(mlp_handle* h, const float* theta, const float* act_cache, cons
 /* Adam over the handle's mlp_param_count values, as adam_step. */
 int mlp_adam_step(mlp_handle* h, float* w, const float* g_w, float* m, float* v, float lr, float b1, float b2,
                   float eps, int32_t t, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Short-horizon asymmetric actor-critic (SHA2C, Sec. III-E) on the step
+ * ------------------------------------------------------------------------
+ * Actor loss, Eq. (6): L = -1/(N T) sum_i [sum_{t<T} gamma^t R_ctrl
+ * + gamma^T V_phi(s_T)] with R_ctrl the negated per-step BPTT loss (the BPTT
+ * handle weights step t by gamma^t); the critic V_phi, an MLP of the full
+ * state [C] -> hidden (tanh) -> 1, is held fixed for the actor's gradient.
+ * Critic targets: lambda-returns of R_goal = c_goal [|p - goal| < goal_radius]
+ * - c_collision [collided] at s_{t+1}, a collision ending the trajectory,
+ * bootstrapped with V_phi(s_T); critic loss: mean over t < T and agents of
+ * (V_phi(s_t) - target)^2. phi: the critic's flat parameters in the generic
+ * MLP layout. */
+typedef struct sha2c_config {
+  float gamma;                          /* equal to the BPTT handle's gamma */
+  float lambda;                         /* 0 <= lambda <= 1 */
+  float c_goal, c_collision, goal_radius;
+  float actor_lr, critic_lr, beta1, beta2, eps;  /* Adam for theta and phi */
+} sha2c_config;
+typedef struct sha2c_handle sha2c_handle;
+/* The BPTT handle (store_activations = 1) drives the rollout; the handle
+ * allocates the critic and its buffers (about (T+1) (2C + 4) + 3 T floats per
+ * agent plus the critic's activations for T A rows), synchronously.
+ * critic_kind: MLP_F32 or MLP_BF16; n_hidden hidden widths. */
+int sha2c_create(bptt_handle* bptt, const sha2c_config* cfg, int32_t n_hidden, const int32_t* hidden,
+                 int32_t critic_kind, sha2c_handle** out);
+int sha2c_destroy(sha2c_handle* h);
+int64_t sha2c_critic_params(const sha2c_handle* h);
+/* Eq. (6) from s0 [C][A] towards goal [3][A]: loss[0] (device) and
+ * g_theta = dL/dtheta [POLICY_N_PARAMS] (overwritten); keeps the trajectory
+ * and V_phi(s_T) for sha2c_critic_grad. */
+int sha2c_actor_grad(sha2c_handle* h, const float* theta, const float* phi, const float* s0, const float* goal,
+                     float* loss, float* g_theta, void* stream);
+/* On the trajectory of the last sha2c_actor_grad: loss[0] = the critic loss,
+ * g_phi = its gradient (overwritten), targets [T][A] (nullable). */
+int sha2c_critic_grad(sha2c_handle* h, const float* phi, const float* goal, float* loss, float* g_phi,
+                      float* targets, void* stream);
+/* One iteration: sha2c_actor_grad, sha2c_critic_grad on the same
+ * trajectory, then Adam (update count t >= 1) on theta and on phi, in place;
+ * losses[0] actor loss, losses[1] critic loss (device). */
+int sha2c_iteration(sha2c_handle* h, float* theta, float* theta_m, float* theta_v, float* phi, float* phi_m,
+                    float* phi_v, int32_t t, const float* s0, const float* goal, float* losses, void* stream);
+/* lambda-returns alone: r, done [T][A] (done uint8), v [T+1][A] with v[T]
+ * the bootstrap; out [T][A]. */
+int sha2c_lambda_returns(int32_t T, int32_t A, const float* r, const float* v, const uint8_t* done, float gamma,
+                         float lambda, float* out, void* stream);
 
 /* Adam (Kingma & Ba 2015) on n FP32 values: m = b1 m + (1-b1) g,
  * v = b2 v + (1-b2) g^2, w -= lr * (m/(1-b1^t)) / (sqrt(v/(1-b2^t)) + eps).

@@ -40,13 +40,16 @@ def critic_value(layers, s):
     return h[:, 0]
 
 
-def actor_loss(model, ds, s0, goal, prm, layers, critic_layers, T, dt, integrator, cam, gamma):
-    """Eq. (6) with R_ctrl = -step_loss: returns (L, s_T)."""
+def actor_loss(model, ds, s0, goal, prm, layers, critic_layers, T, dt, integrator, cam, gamma, states=None):
+    """Eq. (6) with R_ctrl = -step_loss: returns (L, s_T). states (a list,
+    optional) receives s_0 .. s_T."""
     W, H, hfov, d_max = cam
     d_body, zfac = sen.camera_dirs(W, H, hfov)
     s = s0
     A = s0.shape[0]
     total = torch.zeros((), dtype=torch.float64)
+    if states is not None:
+        states.append(s0)
     for t in range(T):
         depth, _, _ = sen.render(model, ds, s, d_body, zfac, d_max)
         y = pol.mlp_tanh(layers, pol.observation(model, s, goal, depth, d_max))
@@ -55,6 +58,8 @@ def actor_loss(model, ds, s0, goal, prm, layers, critic_layers, T, dt, integrato
         # -gamma^t R_ctrl = gamma^t step_loss
         total = total + (gamma ** t) * pol.step_loss(s_next, goal, y, depth).sum()
         s = s_next
+        if states is not None:
+            states.append(s)
     total = total - (gamma ** T) * critic_value(critic_layers, s).sum()
     return total / (A * T), s
 

@@ -44,10 +44,16 @@ class TaskConfig(ctypes.Structure):
                 ("c_collision", c_float), ("c_goal", c_float), ("goal_radius", c_float), ("max_steps", c_int)]
 
 
+class Sha2cConfig(ctypes.Structure):
+    _fields_ = [("gamma", c_float), ("lam", c_float), ("c_goal", c_float), ("c_collision", c_float),
+                ("goal_radius", c_float), ("actor_lr", c_float), ("critic_lr", c_float), ("beta1", c_float),
+                ("beta2", c_float), ("eps", c_float)]
+
+
 class BpttConfig(ctypes.Structure):
     _fields_ = [("T", c_int), ("K", c_int), ("w_p", c_float), ("w_v", c_float), ("w_u", c_float),
                 ("w_o", c_float), ("beta", c_float), ("d_safe", c_float),
-                ("store_activations", c_int), ("policy_gemm", c_int)]
+                ("store_activations", c_int), ("policy_gemm", c_int), ("gamma", c_float)]
 
 
 _SIGS = {
@@ -78,6 +84,16 @@ _SIGS = {
     "sim_render_oriented_backward": (c_int, [c_void_p] * 10),
     "bptt_create": (c_int, [c_void_p, ctypes.POINTER(BpttConfig), ctypes.POINTER(c_void_p)]),
     "bptt_destroy": (c_int, [c_void_p]),
+    "sha2c_create": (c_int, [c_void_p, ctypes.POINTER(Sha2cConfig), c_int, c_void_p, c_int, ctypes.POINTER(c_void_p)]),
+    "sha2c_destroy": (c_int, [c_void_p]),
+    "sha2c_critic_params": (c_int64, [c_void_p]),
+    "sha2c_actor_grad": (c_int, [c_void_p] * 8),
+    "sha2c_critic_grad": (c_int, [c_void_p] * 7),
+    "sha2c_iteration": (c_int, [c_void_p] * 7 + [c_int] + [c_void_p] * 4),
+    "sha2c_lambda_returns": (c_int, [c_int, c_int, c_void_p, c_void_p, c_void_p, c_float, c_float, c_void_p,
+                                     c_void_p]),
+    "bptt_backward_terminal": (c_int, [c_void_p] * 6),
+    "bptt_get_states": (c_int, [c_void_p] * 3),
     "bptt_workspace_bytes": (c_int64, [c_void_p]),
     "bptt_forward": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "bptt_backward": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
@@ -304,8 +320,9 @@ def sim_step_backward(h, s_t, a_t, g_s_next, g_depth, g_lidar, hit_cam, hit_lida
 # --------------------------------------------------------------------------
 
 def bptt_create(h, T, K, w_p, w_v, w_u, w_o, beta, d_safe, store_activations=1,
-                policy_gemm=POLICY_GEMM_FP32) -> int:
-    cfg = BpttConfig(T, K, w_p, w_v, w_u, w_o, beta, d_safe, int(store_activations), int(policy_gemm))
+                policy_gemm=POLICY_GEMM_FP32, gamma=1.0) -> int:
+    cfg = BpttConfig(T, K, w_p, w_v, w_u, w_o, beta, d_safe, int(store_activations), int(policy_gemm),
+                     float(gamma))
     b = c_void_p()
     _call("bptt_create", h, ctypes.byref(cfg), ctypes.byref(b))
     return b.value
@@ -327,6 +344,15 @@ def bptt_forward(b, theta, s0, goal, loss, s_T=None):
 def bptt_backward(b, g_loss, g_theta, g_s0=None):
     _call("bptt_backward", b, ptr(g_loss, torch.float32), ptr(g_theta, torch.float32),
           ptr(g_s0, torch.float32), stream())
+
+
+def bptt_backward_terminal(b, g_loss, g_sT, g_theta, g_s0=None):
+    _call("bptt_backward_terminal", b, ptr(g_loss, torch.float32), ptr(g_sT, torch.float32),
+          ptr(g_theta, torch.float32), ptr(g_s0, torch.float32), stream())
+
+
+def bptt_get_states(b, states):
+    _call("bptt_get_states", b, ptr(states, torch.float32), stream())
 
 
 BPTT_TIMING_CLASSES = ["render", "l1_gemm", "gw1_gemm", "gx_gemm", "render_vjp", "step", "step_vjp",
@@ -407,6 +433,52 @@ class Mlp:
             self.close()
         except Exception:
             pass
+
+
+class Sha2c:
+    """Owner of a sha2c_handle: the SHA2C learner (Sec. III-E) on a BPTT
+    handle created with store_activations=1 and the same gamma."""
+
+    def __init__(self, bptt, hidden=(64, 64), kind=MLP_F32, gamma=0.99, lam=0.95, c_goal=1.0, c_collision=10.0,
+                 goal_radius=0.3, actor_lr=1e-3, critic_lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.cfg = Sha2cConfig(gamma, lam, c_goal, c_collision, goal_radius, actor_lr, critic_lr, beta1, beta2, eps)
+        arr = (c_int * max(1, len(hidden)))(*[int(x) for x in hidden])
+        h = c_void_p()
+        _call("sha2c_create", bptt, ctypes.byref(self.cfg), len(hidden), arr, int(kind), ctypes.byref(h))
+        self.h = h
+        self.n_phi = int(load().sha2c_critic_params(h))
+
+    def actor_grad(self, theta, phi, s0, goal, loss, g_theta):
+        _call("sha2c_actor_grad", self.h, ptr(theta, torch.float32), ptr(phi, torch.float32),
+              ptr(s0, torch.float32), ptr(goal, torch.float32), ptr(loss, torch.float32),
+              ptr(g_theta, torch.float32), stream())
+
+    def critic_grad(self, phi, goal, loss, g_phi, targets=None):
+        _call("sha2c_critic_grad", self.h, ptr(phi, torch.float32), ptr(goal, torch.float32),
+              ptr(loss, torch.float32), ptr(g_phi, torch.float32), ptr(targets, torch.float32), stream())
+
+    def iteration(self, theta, theta_m, theta_v, phi, phi_m, phi_v, t, s0, goal, losses):
+        _call("sha2c_iteration", self.h, ptr(theta, torch.float32), ptr(theta_m, torch.float32),
+              ptr(theta_v, torch.float32), ptr(phi, torch.float32), ptr(phi_m, torch.float32),
+              ptr(phi_v, torch.float32), int(t), ptr(s0, torch.float32), ptr(goal, torch.float32),
+              ptr(losses, torch.float32), stream())
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().sha2c_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sha2c_lambda_returns(r, v, done, gamma, lam, out):
+    T, A = r.shape
+    _call("sha2c_lambda_returns", int(T), int(A), ptr(r, torch.float32), ptr(v, torch.float32),
+          ptr(done, torch.uint8), float(gamma), float(lam), ptr(out, torch.float32), stream())
 
 
 def adam_step(w, g, m, v, lr, b1, b2, eps, t):

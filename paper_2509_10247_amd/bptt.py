@@ -17,12 +17,12 @@ class BpttEngine:
     """Owns a bptt_handle bound to an Env (which must outlive it)."""
 
     def __init__(self, env, T: int, K: int, store_activations: bool = True,
-                 policy_gemm: int = _lib.POLICY_GEMM_FP32, **weights):
+                 policy_gemm: int = _lib.POLICY_GEMM_FP32, gamma: float = 1.0, **weights):
         w = dict(DEFAULT_WEIGHTS)
         w.update(weights)
         self.env, self.T, self.K = env, T, K
         self.h = _lib.bptt_create(env.h, T, K, w["w_p"], w["w_v"], w["w_u"], w["w_o"], w["beta"],
-                                  w["d_safe"], store_activations, policy_gemm)
+                                  w["d_safe"], store_activations, policy_gemm, gamma)
 
     def workspace_bytes(self) -> int:
         return _lib.bptt_workspace_bytes(self.h)

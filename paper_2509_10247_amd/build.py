@@ -17,7 +17,7 @@ LIB = os.path.join(PKG, "libdiffaero.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["sim.hip", "dynamics.hip", "render.hip", "gemm.hip", "bptt.hip", "surrogate.hip", "rollout.hip", "imu.hip",
-           "attitude.hip", "task.hip", "mlp_api.hip"]
+           "attitude.hip", "task.hip", "mlp_api.hip", "sha2c.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

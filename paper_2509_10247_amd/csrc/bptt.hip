@@ -13,6 +13,7 @@
 // Backward sweep, last step first: loss terms, step VJP, action map, the MLP
 // backward on MFMA (weight gradients accumulated with deterministic split-K
 // reductions), observation backward, render VJP.
+#include <cmath>
 #include <mutex>
 #include <vector>
 
@@ -24,6 +25,7 @@ struct bptt_handle;
 namespace da {
 
 static int tmark(bptt_handle* b, hipStream_t st, int cls);
+static float discount(const bptt_handle* b, int t);
 static void tpair(bptt_handle* b, int cls, int a, int z);
 
 constexpr int kHid = 256, kOut = 4;
@@ -85,8 +87,9 @@ struct LossW {
   float w_p, w_v, w_u, w_o, beta, d_safe;
 };
 
+// acc[b] += gt * (step loss of agent b), gt = gamma^t the step's discount
 __global__ void loss_step_kernel(int A, const float* __restrict__ s1, const float* __restrict__ goal,
-                                 const float* __restrict__ Y, const float* __restrict__ lo, LossW w,
+                                 const float* __restrict__ Y, const float* __restrict__ lo, LossW w, float gt,
                                  float* __restrict__ acc, int i0, int n) {
   const int b = i0 + (int)(blockIdx.x * blockDim.x + threadIdx.x);
   if (b >= i0 + n) return;
@@ -98,7 +101,8 @@ __global__ void loss_step_kernel(int A, const float* __restrict__ s1, const floa
     lv += v * v;
   }
   for (int k = 0; k < kOut; ++k) lu += Y[(size_t)b * kOut + k] * Y[(size_t)b * kOut + k];
-  acc[b] += w.w_p * lp + w.w_v * lv + w.w_u * lu + w.w_o * lo[b];
+  const float l = w.w_p * lp + w.w_v * lv + w.w_u * lu + w.w_o * lo[b];
+  acc[b] += gt * l;
 }
 
 __global__ __launch_bounds__(1024) void loss_final_kernel(int A, const float* __restrict__ acc,
@@ -398,6 +402,9 @@ struct bptt_handle {
 
 namespace da {
 // Records an event on the stream when timing is on; returns its pool index.
+// gamma^t, the discount of step t's loss (Eq. (6)); exactly 1 for gamma = 1
+static float discount(const bptt_handle* b, int t) { return (float)std::pow((double)b->cfg.gamma, (double)t); }
+
 static int tmark(bptt_handle* b, hipStream_t st, int cls) {
   if (!b->timing || !((b->timing_classes >> cls) & 1u)) return -1;
   if (b->ev_next >= (int)b->ev_pool.size()) {
@@ -458,6 +465,7 @@ int bptt_create(sim_handle* sim, const bptt_config* cfg, bptt_handle** out) {
   if (rc) return rc;
   DA_REQUIRE(cfg->T >= 1 && cfg->K >= 1 && cfg->K <= cfg->T, "bptt_create: need 1 <= K <= T");
   DA_REQUIRE(cfg->beta > 0.f, "bptt_create: beta must be > 0");
+  DA_REQUIRE(cfg->gamma > 0.f && cfg->gamma <= 1.f, "bptt_create: need 0 < gamma <= 1");
   bptt_handle* b = new bptt_handle();
   b->sim = sim;
   b->cfg = *cfg;
@@ -551,6 +559,22 @@ int bptt_destroy(bptt_handle* b) {
 }
 
 int64_t bptt_workspace_bytes(const bptt_handle* b) { return b ? b->bytes : 0; }
+
+}  // extern "C"
+
+sim_handle* bptt_sim_of(const bptt_handle* b) { return b->sim; }
+const bptt_config* bptt_cfg_of(const bptt_handle* b) { return &b->cfg; }
+
+extern "C" {
+
+int bptt_get_states(bptt_handle* b, float* states, void* stream) {
+  DA_REQUIRE(b && states, "bptt_get_states: null argument");
+  DA_REQUIRE(b->store, "bptt_get_states: needs store_activations = 1 (the states of every step are kept)");
+  DA_REQUIRE(b->have_fwd, "bptt_get_states: call bptt_forward first");
+  const size_t n = (size_t)(b->cfg.T + 1) * b->C * b->A;
+  DA_HIP(hipMemcpyAsync(states, b->seg_s, n * sizeof(float), hipMemcpyDeviceToDevice, as_stream(stream)));
+  return SIM_OK;
+}
 
 int bptt_set_timing(bptt_handle* b, int32_t enable) {
   DA_REQUIRE(b, "bptt_set_timing: null handle");
@@ -689,7 +713,7 @@ int bptt_forward(bptt_handle* b, const float* theta, const float* s0, const floa
                              b->act + (size_t)a * Ka * A, q, hi0[hf], hn[hf], hf ? b->part_w : b->part)))
         return rc;
       hipLaunchKernelGGL(loss_step_kernel, dim3(cdiv(hn[hf], 256)), dim3(256), 0, q, A, nxt, goal,
-                         b->Y + (size_t)a * A * kOut, b->lo, w, b->loss_acc, hi0[hf], hn[hf]);
+                         b->Y + (size_t)a * A * kOut, b->lo, w, discount(b, t), b->loss_acc, hi0[hf], hn[hf]);
       DA_LAUNCH_CHECK("loss_step_kernel");
     }
   }
@@ -707,6 +731,11 @@ int bptt_forward(bptt_handle* b, const float* theta, const float* s0, const floa
 }
 
 int bptt_backward(bptt_handle* b, const float* g_loss, float* g_theta, float* g_s0, void* stream) {
+  return bptt_backward_terminal(b, g_loss, nullptr, g_theta, g_s0, stream);
+}
+
+int bptt_backward_terminal(bptt_handle* b, const float* g_loss, const float* g_sT, float* g_theta, float* g_s0,
+                           void* stream) {
   DA_REQUIRE(b && g_theta, "bptt_backward: null argument");
   DA_REQUIRE(b->have_fwd, "bptt_backward: call bptt_forward first");
   hipStream_t st = as_stream(stream);
@@ -715,14 +744,19 @@ int bptt_backward(bptt_handle* b, const float* g_loss, float* g_theta, float* g_
   const PolicyPtrs pp = bptt_policy_ptrs(b);
   const size_t sbytes = (size_t)C * A * 4;
   const float AT = (float)A * T;
-  const float cp = 2.f * b->cfg.w_p / AT, cv = 2.f * b->cfg.w_v / AT, cu = 2.f * b->cfg.w_u / AT;
-  const float co = b->cfg.w_o / (AT * kRays);
+  // the loss coefficients of step t are these times the discount gamma^t
+  const float cp0 = 2.f * b->cfg.w_p / AT, cv0 = 2.f * b->cfg.w_v / AT, cu0 = 2.f * b->cfg.w_u / AT;
+  const float co0 = b->cfg.w_o / (AT * kRays);
   const float dmax = h->cfg.cam_max;
   DA_HIP(hipMemsetAsync(b->gb.gW1p, 0, (size_t)kHid * kObsPad * 4, st));
   DA_HIP(hipMemsetAsync(b->gflat_tail, 0, (POLICY_N_PARAMS - kOffB1) * 4, st));
   float* g_next = b->g_a;
   float* g_cur = b->g_b;
-  DA_HIP(hipMemsetAsync(g_next, 0, sbytes, st));
+  // dL/ds_T: a terminal term's gradient (Eq. (6) value term), else zero
+  if (g_sT)
+    DA_HIP(hipMemcpyAsync(g_next, g_sT, sbytes, hipMemcpyDeviceToDevice, st));
+  else
+    DA_HIP(hipMemsetAsync(g_next, 0, sbytes, st));
   int rc;
   const size_t xset = (size_t)K * A * kObsPad, hset = (size_t)K * A * kRays;
   // stored mode: renders of a segment only (states are kept); they run on the
@@ -816,6 +850,8 @@ int bptt_backward(bptt_handle* b, const float* g_loss, float* g_theta, float* g_
       // path (gX GEMM, render adjoint) of this and the next step
       const int par = (t0 + j) & 1;
       const LayerGrads& z = b->z[par];
+      const float gt = discount(b, t0 + j);
+      const float cp = cp0 * gt, cv = cv0 * gt, cu = cu0 * gt, co = co0 * gt;
       for (int hf = 0; hf < nh; ++hf) {
         hipStream_t q = hf ? b->half2 : st;
         const int i0 = hi0[hf], m = hn[hf];

@@ -25,3 +25,7 @@ struct sim_handle {
 };
 
 void rollout_plan_free(sim_handle* h);
+
+// the simulator and configuration a BPTT handle was created with
+sim_handle* bptt_sim_of(const bptt_handle* b);
+const bptt_config* bptt_cfg_of(const bptt_handle* b);
