@@ -57,9 +57,9 @@ def parse():
     p.add_argument("--no-kernel-timing", action="store_true")
     p.add_argument("--no-alternatives", action="store_true",
                    help="skip the other policy-GEMM form and the recompute-all variant")
-    p.add_argument("--sections", default="step,render,imu,attitude,task,surrogate,uneven",
+    p.add_argument("--sections", default="step,render,imu,attitude,task,surrogate,uneven,sha2c",
                    help="comma list of extra sections after the headline: step, render, imu, attitude, task, "
-                        "surrogate, uneven")
+                        "surrogate, uneven, sha2c")
     return p.parse_args()
 
 
@@ -318,7 +318,7 @@ def uneven_section(T=128, reps=3, seed=0):
     import numpy as np
     rng = np.random.default_rng(seed + 1)
     max_steps = 64
-    cfg = _lib.TaskConfig(0.01, 0.1, 1.0, 10.0, 1.0, 10.0, 1.0, 0.3, max_steps)
+    tcfg = _lib.TaskConfig(0.01, 0.1, 1.0, 10.0, 1.0, 10.0, 1.0, 0.3, max_steps)
     goal = torch.tensor(wl.goals(rng, A, wl.ROOM_C2), device="cuda")
     k0 = torch.tensor(rng.integers(0, max_steps, size=A).astype(np.int32), device="cuda")
     k = k0.clone()
@@ -329,7 +329,7 @@ def uneven_section(T=128, reps=3, seed=0):
     def run_task(mode):
         s.copy_(s0)
         k.copy_(k0)
-        _lib.sim_rollout_task(e.h, cfg, T, s, s0, goal, k, acts, r_d, r, tfl, depth, lidar, mode)
+        _lib.sim_rollout_task(e.h, tcfg, T, s, s0, goal, k, acts, r_d, r, tfl, depth, lidar, mode)
 
     for name, mode, n in (("task_fused_graph", _lib.ROLLOUT_GRAPH, reps), ("task_plain", _lib.ROLLOUT_PLAIN, 1)):
         run_task(mode)
@@ -343,11 +343,72 @@ def uneven_section(T=128, reps=3, seed=0):
                      "agent_steps_per_s": round(A * T / dt, 1)}
     done = (tfl.to(torch.int32) & 3) > 0
     out["task_resets_per_step"] = round(done.sum().item() / T, 1)
+    # the uniform-batch counterpart: every env padded to the maxima (256
+    # obstacles, 8 agents), stepped launch per operation as without uneven
+    # batching (and, for reference, through the same persistent path)
+    del e
+    pw = wl.uneven_padded(seed=seed, n_envs=8192, T=T)
+    pe = env.from_workload(pw)
+    PA = pw.scene.n_agents
+    pdepth = torch.empty(2, PA, 48, 64, device="cuda")
+    plidar = torch.empty(2, PA, 16, 360, device="cuda")
+    ps0 = torch.tensor(pw.state0, device="cuda")
+    pacts = torch.tensor(pw.actions, device="cuda")
+    ps = ps0.clone()
+    _lib.sim_rollout_config(pe.h, cfg[0], cfg[1], cfg[2])
+    for name, mode in (("padded_plain", _lib.ROLLOUT_PLAIN), ("padded_fused_graph", _lib.ROLLOUT_GRAPH)):
+        ps.copy_(ps0)
+        _lib.sim_rollout(pe.h, T, ps, pacts, pdepth, plidar, None, mode)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ps.copy_(ps0)
+        _lib.sim_rollout(pe.h, T, ps, pacts, pdepth, plidar, None, mode)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[name] = {"ms_per_rollout": round(dt * 1e3, 2), "env_steps_per_s": round(8192 * T / dt, 1),
+                     "agents": PA, "obstacles_per_env": 256}
+    out["fused_over_padded_plain"] = round(out["padded_plain"]["ms_per_rollout"]
+                                           / out["fused_graph"]["ms_per_rollout"], 3)
     out["task_over_render_only"] = round(out["task_fused_graph"]["ms_per_rollout"]
                                          / out["fused_graph"]["ms_per_rollout"], 3)
     out["task_fused_over_plain"] = round(out["task_plain"]["ms_per_rollout"]
                                          / out["task_fused_graph"]["ms_per_rollout"], 3)
     return out
+
+
+def sha2c_section(seed=0, reps=3, gemm_mode=None):
+    """The SHA2C learner (Sec. III-E) at the BPTT configuration: 16384
+    rigid-body envs, horizon 32, checkpoints every 8, the split-BF16 policy
+    GEMMs, a 64-64 FP32 critic of the full state, gamma 0.99, lambda 0.95.
+    One iteration = the Eq. (6) actor gradient (discounted BPTT with the
+    critic's terminal value), the critic's lambda-return targets, loss and
+    gradient on the same trajectory, and Adam on both networks."""
+    import numpy as np
+    import torch
+    import workloads as wl
+    from paper_2509_10247_amd import _lib, bptt, env
+    A, T, K = 16384, 32, 8
+    wk = wl.bptt(seed=seed, n_envs=A, T=T, model=wl.RB13)
+    e = env.from_workload(wk)
+    mode = _lib.POLICY_GEMM_BF16X3 if gemm_mode is None else gemm_mode
+    eng = bptt.BpttEngine(e, T, K, store_activations=True, policy_gemm=mode, gamma=0.99)
+    sh = _lib.Sha2c(eng.h, hidden=(64, 64), gamma=0.99, lam=0.95)
+    theta = torch.tensor(wl.flatten_mlp(wl.mlp_init(np.random.default_rng(1), wl.POLICY_DIMS)), device="cuda")
+    phi = torch.tensor(wl.flatten_mlp(wl.mlp_init(np.random.default_rng(2), (13, 64, 64, 1))), device="cuda")
+    mom = [torch.zeros_like(x) for x in (theta, theta, phi, phi)]
+    s0, goal = torch.tensor(wk.state0, device="cuda"), torch.tensor(wk.goal, device="cuda")
+    losses = torch.empty(2, device="cuda")
+    sh.iteration(theta, mom[0], mom[1], phi, mom[2], mom[3], 1, s0, goal, losses)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in range(reps):
+        sh.iteration(theta, mom[0], mom[1], phi, mom[2], mom[3], 2 + r, s0, goal, losses)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    return {"workload": f"{A} envs RB13, T={T}, K={K}, critic 13-64-64-1 FP32, policy GEMMs "
+                        f"{'bf16x3' if mode == _lib.POLICY_GEMM_BF16X3 else 'fp32'}",
+            "ms_per_iteration": round(dt * 1e3, 2), "env_steps_per_s": round(A * T / dt, 1),
+            "actor_loss": round(losses[0].item(), 6), "critic_loss": round(losses[1].item(), 6)}
 
 
 def surrogate_section(seed=0):
@@ -804,6 +865,8 @@ def main():
         line["surrogate"] = surrogate_section()
     if "uneven" in sections:
         line["uneven"] = uneven_section()
+    if "sha2c" in sections:
+        line["sha2c"] = sha2c_section()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(model)
     print(json.dumps(line), flush=True)

@@ -342,6 +342,26 @@ def uneven(seed: int = 0, n_envs: int = 8192, T: int = 128) -> Workload:
                     params(rng, RB13, A), a, (64, 48, 90.0, 10.0), (16, 360, -15.0, 15.0, 20.0))
 
 
+def uneven_padded(seed: int = 0, n_envs: int = 8192, T: int = 128) -> Workload:
+    """The uneven workload's uniform-batch counterpart: every env holds the
+    uneven workload's maximum counts (256 obstacles, 60/40 sphere/box, and 8
+    agents), as a simulator without uneven batching must pad it; same room,
+    sensors and dynamics."""
+    rng = np.random.default_rng(seed)
+    n_obs = np.full(n_envs, 256)
+    n_sph = rng.binomial(n_obs, 0.6)
+    n_box = n_obs - n_sph
+    n_ag = np.full(n_envs, 8)
+    A = int(n_ag.sum())
+    p0 = start_positions(rng, A, ROOM_C2)
+    scene = make_scene(rng, n_envs, n_sph, n_box, ROOM_C2, (0.3, 1.5), (0.2, 1.0), room=True,
+                       agents_per_env=n_ag, keepout=p0)
+    s0 = initial_state(rng, RB13, p0)
+    a = actions(rng, RB13, A, T)
+    return Workload("uneven_padded_rb13_8192env_256obs_8agents", RB13, RK4, 0.01, T, scene, s0,
+                    params(rng, RB13, A), a, (64, 48, 90.0, 10.0), (16, 360, -15.0, 15.0, 20.0))
+
+
 def surrogate_full(seed: int = 0, n_envs: int = 65536, T: int = 64) -> Workload:
     """Full model for the learned surrogate: RB13 RK4 with rotor drag
     D = diag(kd, kd, 0), kd ~ U[0.1, 0.5] per env, body-rate lag 0.03 s."""
