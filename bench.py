@@ -298,6 +298,7 @@ def uneven_section(T=128, reps=3, seed=0):
     out = {"workload": f"8192 envs, {A} agents, {int(wk.scene.sph_off[-1] + wk.scene.box_off[-1])} obstacles, "
                        f"T={T}, lidar 16x360 + camera 64x48",
            "tuned": {"tile_group": cfg[0], "blocks_per_cu": cfg[1], "order": cfg[2],
+                     "threads": _lib.sim_rollout_get_threads(e.h),
                      "step_ms": round(tune_ms, 4), "tune_s": round(tune_s, 1)}}
     for name, mode, n in (("fused_graph", _lib.ROLLOUT_GRAPH, reps), ("plain", _lib.ROLLOUT_PLAIN, 1)):
         run(mode)
@@ -725,6 +726,9 @@ def cpu_baseline(model, seed=0, n_envs=256, T=32, n_envs_1t=16, T_1t=8):
 GEMM_DTYPE = {"fp32": "f32", "bf16x3": "f32 (policy GEMMs bf16x3: three BF16 products per FP32 product)"}
 
 
+RENDER_THREADS = [256]
+
+
 def bptt_run(wk, theta, A, T, K, store, gemm_mode, steps, warmup, timed=False):
     """BPTT iterations on the benchmark workload. Returns (ms per iteration,
     env-steps per s, (env, engine, s0), isolated, live): with timed=True,
@@ -735,11 +739,16 @@ def bptt_run(wk, theta, A, T, K, store, gemm_mode, steps, warmup, timed=False):
     overlapping as untimed (only that class is timed, to keep events few)."""
     import torch
     from paper_2509_10247_amd import _lib, bptt, env
+    import tempfile
     e = env.from_workload(wk)
     eng = bptt.BpttEngine(e, T, K, store_activations=store, policy_gemm=gemm_mode)
     th = torch.tensor(theta, device="cuda")
     s0 = torch.tensor(wk.state0, device="cuda")
     goal = torch.tensor(wk.goal, device="cuda")
+    # the render's workgroup size (128 or 256 threads per agent), tuned on
+    # the start state; the outputs are the same for both
+    _lib.sim_render_autotune(e.h, s0, os.path.join(tempfile.gettempdir(), "diffaero_autotune.json"))
+    RENDER_THREADS[0] = _lib.sim_render_get_config(e.h)
 
     def one_step():
         eng.forward(th, s0, goal)
@@ -830,7 +839,8 @@ def main():
                    "envs": A, "horizon": T, "checkpoint_every": K, "env_steps_per_step": A * T,
                    "stored_activations": store,
                    "workspace_bytes": ws,
-                   "policy": f"mlp 3081-256-256-4 tanh ({args.policy_gemm} mfma)"},
+                   "policy": f"mlp 3081-256-256-4 tanh ({args.policy_gemm} mfma)",
+                   "render_threads_per_agent": RENDER_THREADS[0]},
         "roofline": roofline,
         "roofline_in_timed_iterations": roofline_live,
         "kernel_breakdown_isolated": isolated,

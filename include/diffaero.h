@@ -619,6 +619,24 @@ int sim_rollout_task(sim_handle* h, const task_config* cfg, int32_t T, float* s,
                      const float* goal, int32_t* k, const float* a_seq, float* depth_ring, float* lidar_ring,
                      float* reward_d, float* reward, uint8_t* flags, int32_t mode, void* stream);
 
+/* Threads per workgroup of the persistent render kernel of sim_rollout
+ * (rays cast at once per workgroup: 128 or 256, one 64-ray tile per
+ * wavefront); outputs are identical for both. sim_autotune chooses it with
+ * the other tuning. SIM_EINVAL for other values. */
+int sim_rollout_set_threads(sim_handle* h, int32_t threads);
+int32_t sim_rollout_get_threads(sim_handle* h);
+
+/* Threads per agent's workgroup of the launch-per-op render (sim_render,
+ * sim_render_oriented, the BPTT observations and the plain rollouts): 128 or
+ * 256 (default); images, hit records and the fused obstacle term are
+ * identical for both. sim_render_autotune times both on the caller's state s
+ * (SoA [C][A]) with the configured sensors, keeps the faster, writes
+ * best_ms (-1 when the choice came from cache_path, a JSON file keyed by the
+ * device and the problem shape; nullable) and stores it in the cache. */
+int sim_render_config(sim_handle* h, int32_t threads);
+int32_t sim_render_get_config(const sim_handle* h);
+int sim_render_autotune(sim_handle* h, const float* s, const char* cache_path, float* best_ms, void* stream);
+
 /* Sets the persistent render kernel's tuning: tile_group = camera / LiDAR tiles (64 rays
  * each) per work item, blocks_per_cu = persistent workgroups per compute unit
  * (1..16), order = 1 longest-first, 0 env order. Synchronous. */
@@ -626,9 +644,10 @@ int sim_rollout_config(sim_handle* h, int32_t tile_group, int32_t blocks_per_cu,
 int sim_rollout_get_config(sim_handle* h, int32_t* tile_group, int32_t* blocks_per_cu, int32_t* order);
 
 /* Times one fused step from state s / action a (SoA, not modified; outputs
- * written to depth / lidar [A][...]) for every (tile_group in {2,4,8,16,all},
- * blocks_per_cu in {2,4,8}, order in {1,0}), keeps the fastest (median of 3
- * after a warm-up) and records it in the JSON file cache_path (nullable)
+ * written to depth / lidar [A][...]) for every (threads per workgroup in
+ * {256, 128}, tile_group in {2,4,8,16,all}, workgroups per CU in {2,4,8}
+ * at 256 threads and twice that at 128, order in {1,0}), keeps the fastest
+ * (median of 3 after a warm-up) and records it in the JSON file cache_path (nullable)
  * under a key of the device and problem shape; a matching cache entry is
  * used without timing (best_ms = -1). best_ms: host float, nullable. The
  * only rollout call that synchronizes the stream. */

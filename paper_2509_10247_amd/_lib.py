@@ -103,6 +103,11 @@ _SIGS = {
     "policy_forward": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p]),
     "policy_backward": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p]),
     "sim_rollout": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
+    "sim_rollout_set_threads": (c_int, [c_void_p, c_int]),
+    "sim_rollout_get_threads": (c_int, [c_void_p]),
+    "sim_render_config": (c_int, [c_void_p, c_int]),
+    "sim_render_get_config": (c_int, [c_void_p]),
+    "sim_render_autotune": (c_int, [c_void_p, c_void_p, ctypes.c_char_p, ctypes.POINTER(c_float), c_void_p]),
     "sim_rollout_task": (c_int, [c_void_p, ctypes.POINTER(TaskConfig), c_int] + [c_void_p] * 10 + [c_int, c_void_p]),
     "sim_rollout_config": (c_int, [c_void_p, c_int, c_int, c_int]),
     "sim_rollout_get_config": (c_int, [c_void_p, ctypes.POINTER(c_int), ctypes.POINTER(c_int),
@@ -505,6 +510,29 @@ def sim_rollout_task(h, cfg, T, s, s_init, goal, k, a_seq, reward_d, reward, fla
           ptr(goal, torch.float32), ptr(k, torch.int32), ptr(a_seq, torch.float32), ptr(depth_ring, torch.float32),
           ptr(lidar_ring, torch.float32), ptr(reward_d, torch.float32), ptr(reward, torch.float32),
           ptr(flags, torch.uint8), int(mode), stream())
+
+
+def sim_rollout_set_threads(h, threads):
+    _call("sim_rollout_set_threads", h, int(threads))
+
+
+def sim_rollout_get_threads(h):
+    return int(load().sim_rollout_get_threads(h))
+
+
+def sim_render_config(h, threads):
+    _call("sim_render_config", h, int(threads))
+
+
+def sim_render_get_config(h):
+    return int(load().sim_render_get_config(h))
+
+
+def sim_render_autotune(h, s, cache_path=None):
+    best = c_float()
+    _call("sim_render_autotune", h, ptr(s, torch.float32), cache_path.encode() if cache_path else None,
+          ctypes.byref(best), stream())
+    return best.value
 
 
 def sim_rollout_config(h, tile_group, blocks_per_cu, order):

@@ -627,7 +627,7 @@ static int forward_step(bptt_handle* b, const PolicyPtrs& pp, const float* s, fl
   int e0 = tmark(b, st, BPTT_T_RENDER);
   // depth / d_max straight into the observation rows, obstacle term fused
   int rc = launch_render(h->scene, h->cam.dev, h->cfg.model == SIM_RB13, h->cfg.fov_cull != 0, s, A, X,
-                         hit, kObsPad, 1.0f / dmax, st, b->lo, b->cfg.beta, b->cfg.d_safe, i0, n);
+                         hit, kObsPad, 1.0f / dmax, st, b->lo, b->cfg.beta, b->cfg.d_safe, i0, n, h->render_nt);
   if (rc) return rc;
   tpair(b, BPTT_T_RENDER, e0, tmark(b, st, BPTT_T_RENDER));
   e0 = tmark(b, st, BPTT_T_SMALL_FWD);
@@ -770,7 +770,8 @@ int bptt_backward_terminal(bptt_handle* b, const float* g_loss, const float* g_s
       float* X = Xs + (size_t)j * A * kObsPad;
       const int e0 = tmark(b, q, BPTT_T_RENDER);
       int r = launch_render(h->scene, h->cam.dev, h->cfg.model == SIM_RB13, h->cfg.fov_cull != 0, s, A, X,
-                            Hs + (size_t)j * A * kRays, kObsPad, 1.0f / dmax, q);
+                            Hs + (size_t)j * A * kRays, kObsPad, 1.0f / dmax, q, nullptr, 1.f, 0.f, 0, -1,
+                            h->render_nt);
       if (r) return r;
       tpair(b, BPTT_T_RENDER, e0, tmark(b, q, BPTT_T_RENDER));
       hipLaunchKernelGGL(obs_fwd_kernel, dim3(cdiv(A, 256)), dim3(256), 0, q, A, h->cfg.model, X, s, b->goal,

@@ -62,10 +62,11 @@ int launch_step_vjp(int model, int integ, int A, float dt, const float* s, const
 // Render one sensor for agents [0, A): out[i*out_ld + r] = value * out_scale
 // (out_ld >= n_rays), rec[i*n_rays + r] (nullable). If term is given, also
 // term[i] = mean_r softplus(beta (d_safe - value_r)) / beta (fused epilogue).
+// nt: threads per agent's workgroup, 128 or 256 (same images and term).
 int launch_render(const SceneDev& sc, const SensorDev& sen, bool rotate, bool cull, const float* s,
                   int A, float* out, int* rec, int out_ld, float out_scale, hipStream_t st,
                   float* term = nullptr, float beta = 1.f, float d_safe = 0.f, int i0 = 0,
-                  int n = -1);
+                  int n = -1, int nt = 256);
 int launch_render_work(const SceneDev& sc, const SensorDev& sen, bool rotate, bool cull,
                        const float* s, int A, float* out, int* work, hipStream_t st);
 // Adds the sensor's contribution (d out/d s)^T g to g_s (p and q components);

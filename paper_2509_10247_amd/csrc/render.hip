@@ -23,16 +23,17 @@
 
 namespace da {
 
-template <bool ROT, bool CULL, bool CYL>
-__global__ __launch_bounds__(256, 8) void render_kernel(SceneDev sc, SensorDev sen,
-                                                     const float* __restrict__ s, int A,
-                                                     float* __restrict__ out,
-                                                     int* __restrict__ rec, int out_ld,
-                                                     float out_scale, float* __restrict__ term,
-                                                     float beta, float d_safe, int i0) {
+// one agent per workgroup of NT threads (128 or 256)
+template <bool ROT, bool CULL, bool CYL, int NT>
+__global__ __launch_bounds__(NT, 8) void render_kernel(SceneDev sc, SensorDev sen,
+                                                    const float* __restrict__ s, int A,
+                                                    float* __restrict__ out,
+                                                    int* __restrict__ rec, int out_ld,
+                                                    float out_scale, float* __restrict__ term,
+                                                    float beta, float d_safe, int i0) {
   extern __shared__ float4 smem_f4[];
-  render_one_agent<ROT, CULL, CYL>(sc, sen, s, A, i0 + (int)blockIdx.x, 0, sen.n_tiles, out, rec, out_ld,
-                              out_scale, term, beta, d_safe, smem_f4);
+  render_one_agent<ROT, CULL, CYL, false, NT>(sc, sen, s, A, i0 + (int)blockIdx.x, 0, sen.n_tiles, out, rec,
+                                              out_ld, out_scale, term, beta, d_safe, smem_f4);
 }
 
 // Same rendering, plus the per-wavefront work counters (diagnostics only).
@@ -728,27 +729,35 @@ __global__ __launch_bounds__(256) void collide_kernel(SceneDev sc, const float* 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+template <int NT>
+static decltype(&render_kernel<true, true, true, NT>) render_kernel_of(int v) {
+  switch (v) {
+    case 7: return render_kernel<true, true, true, NT>;
+    case 6: return render_kernel<true, true, false, NT>;
+    case 5: return render_kernel<true, false, true, NT>;
+    case 4: return render_kernel<true, false, false, NT>;
+    case 3: return render_kernel<false, true, true, NT>;
+    case 2: return render_kernel<false, true, false, NT>;
+    case 1: return render_kernel<false, false, true, NT>;
+    default: return render_kernel<false, false, false, NT>;
+  }
+}
+
 int launch_render(const SceneDev& sc, const SensorDev& sen, bool rotate, bool cull, const float* s,
                   int A, float* out, int* rec, int out_ld, float out_scale, hipStream_t st,
-                  float* term, float beta, float d_safe, int i0, int n) {
+                  float* term, float beta, float d_safe, int i0, int n, int nt) {
   if (n < 0) n = A - i0;
   if (n <= 0) return SIM_OK;
+  if (nt != 128 && nt != 256) return fail(SIM_EINVAL, "render: threads per agent must be 128 or 256");
   const int P = sc.max_prims > 0 ? sc.max_prims : 1;
   const size_t lds = render_lds_bytes(P, sen.n_tiles);
   const int v = (rotate ? 4 : 0) | (cull ? 2 : 0) | (sc.cyl_off ? 1 : 0);
-  decltype(&render_kernel<true, true, true>) k = nullptr;
-  switch (v) {
-    case 7: k = render_kernel<true, true, true>; break;
-    case 6: k = render_kernel<true, true, false>; break;
-    case 5: k = render_kernel<true, false, true>; break;
-    case 4: k = render_kernel<true, false, false>; break;
-    case 3: k = render_kernel<false, true, true>; break;
-    case 2: k = render_kernel<false, true, false>; break;
-    case 1: k = render_kernel<false, false, true>; break;
-    default: k = render_kernel<false, false, false>; break;
-  }
-  hipLaunchKernelGGL(k, dim3(n), dim3(256), lds, st, sc, sen, s, A, out, rec, out_ld, out_scale, term, beta,
-                     d_safe, i0);
+  if (nt == 128)
+    hipLaunchKernelGGL(render_kernel_of<128>(v), dim3(n), dim3(128), lds, st, sc, sen, s, A, out, rec, out_ld,
+                       out_scale, term, beta, d_safe, i0);
+  else
+    hipLaunchKernelGGL(render_kernel_of<256>(v), dim3(n), dim3(256), lds, st, sc, sen, s, A, out, rec, out_ld,
+                       out_scale, term, beta, d_safe, i0);
   DA_LAUNCH_CHECK("render_kernel");
   return SIM_OK;
 }

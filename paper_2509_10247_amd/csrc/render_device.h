@@ -232,13 +232,13 @@ struct AgentStage {
   f3 rlo, rhi;
 };
 
-// Stages agent i's environment with the whole workgroup (256 threads); LDS
+// Stages agent i's environment with the whole workgroup (NT threads); LDS
 // is re-staged on entry, so consecutive calls from one workgroup (the
 // persistent rollout kernel) are safe. CYL: the scene may hold cylinders.
 // SDF: also the distance from the agent's centre to the nearest surface (as
 // the collision check), per wavefront into md_red[0..3] before the final
 // barrier; their minimum is the distance.
-template <bool ROT, bool CYL, bool SDF = false>
+template <bool ROT, bool CYL, bool SDF = false, int NT = 256>
 __device__ __forceinline__ AgentStage stage_agent(const SceneDev& sc, const float* __restrict__ s, int A, int i,
                                                   RenderLds& L, float* md_red = nullptr) {
   const int tid = threadIdx.x;
@@ -264,7 +264,7 @@ __device__ __forceinline__ AgentStage stage_agent(const SceneDev& sc, const floa
   __syncthreads();
   bool ins = false;
   float md = kInf;
-  for (int k = tid; k < np; k += 256) {
+  for (int k = tid; k < np; k += NT) {
     if (k < ns) {
       const float4 c = reinterpret_cast<const float4*>(sc.sph)[s0 + k];
       if (SDF) md = fminf(md, sdf_sphere(o, c));
@@ -360,13 +360,18 @@ __device__ __forceinline__ AgentStage stage_agent(const SceneDev& sc, const floa
 // culling pass sorts survivors into three categories instead of four). The
 // WORK variant also writes, per wavefront, the rays it cast and the
 // ray-primitive tests and tile-cone tests it ran to
-// work[(i * 4 + wave) * kWorkN + c].
-template <bool ROT, bool CULL, bool CYL, bool WORK = false>
+// work[(i * 4 + wave) * kWorkN + c]. NT: threads of the workgroup, 128 or
+// 256 (two or four wavefronts, each casting one 64-ray tile at a time); the
+// images and the obstacle term are the same bit for bit for both.
+template <bool ROT, bool CULL, bool CYL, bool WORK = false, int NT = 256>
 __device__ __forceinline__ void render_tiles(const AgentStage& ag, const SensorDev& sen, RenderLds& L,
                                              int tile_begin, int tile_end, float* __restrict__ out,
                                              int* __restrict__ rec, int out_ld, float out_scale,
                                              float* __restrict__ term, float beta, float d_safe,
                                              int* __restrict__ work = nullptr) {
+  static_assert(NT == 128 || NT == 256, "render_tiles: 128 or 256 threads");
+  static_assert(!WORK || NT == 256, "render_tiles: the work counters assume four wavefronts");
+  constexpr int NW = NT / 64;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int i = ag.i, ns = ag.ns, nb = ag.nb, nc = CYL ? ag.nc : 0, np = ag.np;
   const Rot& R = ag.R;
@@ -374,7 +379,7 @@ __device__ __forceinline__ void render_tiles(const AgentStage& ag, const SensorD
   const f3 rlo = ag.rlo, rhi = ag.rhi;
   __syncthreads();  // the previous sensor's tiles are done with the axes and lists
   if (CULL)
-    for (int tt = tid; tt < tile_end - tile_begin; tt += 256) {
+    for (int tt = tid; tt < tile_end - tile_begin; tt += NT) {
       const float4 ca = sen.cone_a[tile_begin + tt];
       const f3 ax = ROT ? rot_apply(R, mk3(ca.x, ca.y, ca.z)) : mk3(ca.x, ca.y, ca.z);
       L.ax[tt] = make_float4(ax.x, ax.y, ax.z, ca.w);
@@ -385,7 +390,12 @@ __device__ __forceinline__ void render_tiles(const AgentStage& ag, const SensorD
   int* rrow = rec ? rec + (size_t)i * nr : nullptr;
   short* list = L.lists + wave * L.P;
   const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  float tacc = 0.f;  // optional per-agent sum of softplus(beta (d_safe - value))
+  // optional per-agent sum of softplus(beta (d_safe - value)), kept as four
+  // sums over the tiles of each residue mod 4 (lane by lane, in tile order),
+  // whatever the number of wavefronts: wavefront w holds residues w + NW j
+  float tacc[4 / NW];
+#pragma unroll
+  for (int a = 0; a < 4 / NW; ++a) tacc[a] = 0.f;
   const float inv_beta = term ? 1.0f / beta : 0.f;
   int wk[kWorkN] = {0, 0, 0, 0, 0, 0, 0};
 
@@ -393,18 +403,19 @@ __device__ __forceinline__ void render_tiles(const AgentStage& ag, const SensorD
   // processed (ray index two tiles ahead, direction one tile ahead)
   int r_n = tile_begin + wave < tile_end ? sen.tile_rays[(tile_begin + wave) * kTileRays + lane] : -1;
   float4 db_n = r_n >= 0 ? sen.dirs[r_n] : make_float4(0.f, 0.f, 0.f, 0.f);
-  int r_nn = tile_begin + wave + 4 < tile_end ? sen.tile_rays[(tile_begin + wave + 4) * kTileRays + lane] : -1;
-  for (int tile = tile_begin + wave; tile < tile_end; tile += 4) {
+  int r_nn = tile_begin + wave + NW < tile_end ? sen.tile_rays[(tile_begin + wave + NW) * kTileRays + lane] : -1;
+  for (int tile = tile_begin + wave; tile < tile_end; tile += NW) {
+    const int ta = NW == 4 ? 0 : ((tile - tile_begin) >> 1) & 1;  // this tile's term sum
     const int r = r_n;
     const float4 db = db_n;
     r_n = r_nn;
     db_n = r_n >= 0 ? sen.dirs[r_n] : make_float4(0.f, 0.f, 0.f, 0.f);
-    r_nn = tile + 8 < tile_end ? sen.tile_rays[(tile + 8) * kTileRays + lane] : -1;
+    r_nn = tile + 2 * NW < tile_end ? sen.tile_rays[(tile + 2 * NW) * kTileRays + lane] : -1;
     if (inside) {
       if (r >= 0) {
         orow[r] = 0.f;
         if (rrow) rrow[r] = -2;
-        if (term) tacc += softplus_fast(beta * d_safe);
+        if (term) tacc[ta] += softplus_fast(beta * d_safe);
       }
       continue;
     }
@@ -507,16 +518,21 @@ __device__ __forceinline__ void render_tiles(const AgentStage& ag, const SensorD
     }
     orow[r] = val * out_scale;
     if (rrow) rrow[r] = rc;
-    if (term) tacc += softplus_fast(beta * (d_safe - val));
+    if (term) tacc[ta] += softplus_fast(beta * (d_safe - val));
   }
   if (WORK && lane == 0)
     for (int c = 0; c < kWorkN; ++c) work[((size_t)i * 4 + wave) * kWorkN + c] = wk[c];
   if (term) {
-    // fixed-order reduction: butterfly within each wave, then waves 0..3
-    for (int off = 32; off > 0; off >>= 1) tacc += __shfl_xor(tacc, off);
+    // fixed-order reduction: a butterfly per residue sum, then residues 0..3
+    // in order
+#pragma unroll
+    for (int a = 0; a < 4 / NW; ++a)
+      for (int off = 32; off > 0; off >>= 1) tacc[a] += __shfl_xor(tacc[a], off);
     __syncthreads();
     float* wsum = reinterpret_cast<float*>(L.ax);  // re-staged by the next render_tiles
-    if (lane == 0) wsum[wave] = tacc;
+    if (lane == 0)
+#pragma unroll
+      for (int a = 0; a < 4 / NW; ++a) wsum[wave + NW * a] = tacc[a];
     __syncthreads();
     if (tid == 0) term[i] = (((wsum[0] + wsum[1]) + wsum[2]) + wsum[3]) * (inv_beta / (float)nr);
   }
@@ -524,7 +540,7 @@ __device__ __forceinline__ void render_tiles(const AgentStage& ag, const SensorD
 
 
 // Stage + render of one sensor (the launch-per-op render kernels).
-template <bool ROT, bool CULL, bool CYL, bool WORK = false>
+template <bool ROT, bool CULL, bool CYL, bool WORK = false, int NT = 256>
 __device__ __forceinline__ void render_one_agent(const SceneDev& sc, const SensorDev& sen,
                                                  const float* __restrict__ s, int A, int i,
                                                  int tile_begin, int tile_end, float* __restrict__ out,
@@ -532,9 +548,9 @@ __device__ __forceinline__ void render_one_agent(const SceneDev& sc, const Senso
                                                  float* __restrict__ term, float beta, float d_safe,
                                                  void* smem, int* __restrict__ work = nullptr) {
   RenderLds L = carve(smem, sc.max_prims > 0 ? sc.max_prims : 1);
-  const AgentStage ag = stage_agent<ROT, CYL>(sc, s, A, i, L);
-  render_tiles<ROT, CULL, CYL, WORK>(ag, sen, L, tile_begin, tile_end, out, rec, out_ld, out_scale, term, beta,
-                                d_safe, work);
+  const AgentStage ag = stage_agent<ROT, CYL, false, NT>(sc, s, A, i, L);
+  render_tiles<ROT, CULL, CYL, WORK, NT>(ag, sen, L, tile_begin, tile_end, out, rec, out_ld, out_scale, term, beta,
+                                         d_safe, work);
 }
 
 __device__ __forceinline__ float collide_one(const SceneDev& sc, const float* __restrict__ s, int A,

@@ -22,6 +22,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -35,7 +36,8 @@ namespace da {
 
 enum { ITEM_AGENT = 0 };
 
-// The thread that draws a persistent loop's work tickets: the last one, so
+// The thread that draws a persistent loop's work tickets: the last one (of
+// kTicketThread + 1 = 256, or NT - 1 for a workgroup of NT threads), so
 // that its condition differs from the thread-0 and lane-0 regions of the loop
 // body. Where a body ends with a region under the same condition as the
 // ticket draw at the top of the loop, the compiler can thread that branch
@@ -100,27 +102,28 @@ constexpr bool rotates_m() {
 // (the render's fused epilogue; the item must then cover all camera tiles).
 // SDF: the staging also leaves the agent's nearest-surface distance per
 // wavefront in md_red[0..3] (the agent is staged even without sensor tiles).
-template <bool ROT, bool CULL, bool CYL, bool SDF = false>
+// NT: threads of the workgroup (128 or 256).
+template <bool ROT, bool CULL, bool CYL, bool SDF = false, int NT = 256>
 __device__ __forceinline__ void agent_item(const RolloutArgs& g, int4 w, RenderLds& L, float* term = nullptr,
                                            float beta = 1.f, float d_safe = 0.f, float* md_red = nullptr) {
   if (!SDF && w.z >= w.w) return;  // an agent without sensor tiles
-  const AgentStage ag = stage_agent<ROT, CYL, SDF>(g.sc, g.s, g.A, w.y, L, md_red);
+  const AgentStage ag = stage_agent<ROT, CYL, SDF, NT>(g.sc, g.s, g.A, w.y, L, md_red);
   const int nc = g.depth ? g.cam.n_tiles : 0;
   for (int part = 0; part < 2; ++part) {
     const int b = part ? max(w.z, nc) - nc : w.z, e = part ? w.w - nc : min(w.w, nc);
     if (b >= e) continue;
     const SensorDev& sen = part ? g.lidar : g.cam;
-    render_tiles<ROT, CULL, CYL>(ag, sen, L, b, e, part ? g.lidar_out : g.depth, nullptr, sen.n_rays, 1.f,
-                                 part ? nullptr : term, beta, d_safe);
+    render_tiles<ROT, CULL, CYL, false, NT>(ag, sen, L, b, e, part ? g.lidar_out : g.depth, nullptr, sen.n_rays,
+                                            1.f, part ? nullptr : term, beta, d_safe);
   }
 }
 
-template <bool ROT, bool CULL, bool CYL>
-__global__ __launch_bounds__(256, 8) void rollout_render_kernel(RolloutArgs g) {
+template <bool ROT, bool CULL, bool CYL, int NT>
+__global__ __launch_bounds__(NT, 8) void rollout_render_kernel(RolloutArgs g) {
   extern __shared__ float4 smem_f4[];
   __shared__ int cur;
   for (;;) {
-    if (threadIdx.x == kTicketThread) cur = atomicAdd(g.counter, 1);
+    if (threadIdx.x == NT - 1) cur = atomicAdd(g.counter, 1);
     __syncthreads();
     // the ticket in a scalar register: the exit branch is uniform in the
     // compiled loop, so no lane re-enters the barrier ahead of the lane that
@@ -130,7 +133,7 @@ __global__ __launch_bounds__(256, 8) void rollout_render_kernel(RolloutArgs g) {
     if (it >= g.n_items) break;  // uniform over the workgroup: all waves exit
     const int4 w = g.items[it];
     RenderLds L = carve(smem_f4, g.sc.max_prims > 0 ? g.sc.max_prims : 1);
-    agent_item<ROT, CULL, CYL>(g, w, L);
+    agent_item<ROT, CULL, CYL, false, NT>(g, w, L);
   }
 }
 
@@ -256,25 +259,33 @@ __global__ void copy_floats_kernel(const float* __restrict__ src, float* __restr
   if (i < n) dst[i] = src[i];
 }
 
-template <int M, int I>
-static int launch_fused_t(const RolloutArgs& g, bool cull, int grid, size_t lds, hipStream_t st) {
-  hipLaunchKernelGGL((rollout_dyn_kernel<M, I>), dim3(cdiv(g.A, 256)), dim3(256), 0, st, g);
-  DA_LAUNCH_CHECK("rollout_dyn_kernel");
+template <bool ROT, int NT>
+static void launch_render_persistent(const RolloutArgs& g, bool cull, int grid, size_t lds, hipStream_t st) {
   // scenes without cylinders keep the three-category staging and tile loop
-  constexpr bool ROT = rotates_m<M>();
-  decltype(&rollout_render_kernel<ROT, true, true>) k = nullptr;
+  decltype(&rollout_render_kernel<ROT, true, true, NT>) k = nullptr;
   const bool cyl = g.sc.cyl_off != nullptr;
   if (cull)
-    k = cyl ? rollout_render_kernel<ROT, true, true> : rollout_render_kernel<ROT, true, false>;
+    k = cyl ? rollout_render_kernel<ROT, true, true, NT> : rollout_render_kernel<ROT, true, false, NT>;
   else
-    k = cyl ? rollout_render_kernel<ROT, false, true> : rollout_render_kernel<ROT, false, false>;
-  hipLaunchKernelGGL(k, dim3(grid), dim3(256), lds, st, g);
+    k = cyl ? rollout_render_kernel<ROT, false, true, NT> : rollout_render_kernel<ROT, false, false, NT>;
+  hipLaunchKernelGGL(k, dim3(grid), dim3(NT), lds, st, g);
+}
+
+template <int M, int I>
+static int launch_fused_t(const RolloutArgs& g, bool cull, int grid, size_t lds, int nt, hipStream_t st) {
+  hipLaunchKernelGGL((rollout_dyn_kernel<M, I>), dim3(cdiv(g.A, 256)), dim3(256), 0, st, g);
+  DA_LAUNCH_CHECK("rollout_dyn_kernel");
+  constexpr bool ROT = rotates_m<M>();
+  if (nt == 128)
+    launch_render_persistent<ROT, 128>(g, cull, grid, lds, st);
+  else
+    launch_render_persistent<ROT, 256>(g, cull, grid, lds, st);
   DA_LAUNCH_CHECK("rollout_render_kernel");
   return SIM_OK;
 }
 
 template <int M, int I>
-static int launch_dyn_t(const RolloutArgs& g, bool, int, size_t, hipStream_t st) {
+static int launch_dyn_t(const RolloutArgs& g, bool, int, size_t, int, hipStream_t st) {
   hipLaunchKernelGGL((rollout_dyn_kernel<M, I>), dim3(cdiv(g.A, 256)), dim3(256), 0, st, g);
   DA_LAUNCH_CHECK("rollout_dyn_kernel");
   return SIM_OK;
@@ -320,12 +331,12 @@ static int launch_task_fused_t(const RolloutArgs& gd, const RolloutArgs& gr, con
     default: return fail(SIM_EINVAL, "bad model/integrator");                 \
   }
 
-static int launch_fused(const sim_handle* h, const RolloutArgs& g, int grid, size_t lds, hipStream_t st) {
-  DA_ROLLOUT_DISPATCH(launch_fused_t, h->cfg.model, h->cfg.integrator, g, h->cfg.fov_cull != 0, grid, lds, st);
+static int launch_fused(const sim_handle* h, const RolloutArgs& g, int grid, size_t lds, int nt, hipStream_t st) {
+  DA_ROLLOUT_DISPATCH(launch_fused_t, h->cfg.model, h->cfg.integrator, g, h->cfg.fov_cull != 0, grid, lds, nt, st);
 }
 
 static int launch_dyn(const sim_handle* h, const RolloutArgs& g, hipStream_t st) {
-  DA_ROLLOUT_DISPATCH(launch_dyn_t, h->cfg.model, h->cfg.integrator, g, false, 0, 0, st);
+  DA_ROLLOUT_DISPATCH(launch_dyn_t, h->cfg.model, h->cfg.integrator, g, false, 0, 0, 256, st);
 }
 
 static int launch_task_fused(const sim_handle* h, const RolloutArgs& gd, const RolloutArgs& gr,
@@ -343,6 +354,7 @@ using namespace da;
 // ---------------------------------------------------------------------------
 struct RolloutPlan {
   int tile_group = 8, blocks_per_cu = 4, order = 1;  // order 1: longest first
+  int nt = 256;  // threads per workgroup of the persistent render (128 or 256)
   bool tuned = false, built = false;
   std::vector<int4> items;
   int4* items_dev = nullptr;
@@ -498,15 +510,15 @@ static int enqueue_rollout(sim_handle* h, RolloutPlan* p, int T, float* s, const
     g.counter = p->counters + t;
     int rc;
     if (fused) {
-      rc = launch_fused(h, g, p->n_cu * p->blocks_per_cu, lds, st);
+      rc = launch_fused(h, g, p->n_cu * p->blocks_per_cu, lds, p->nt, st);
     } else {
       rc = launch_dyn(h, g, st);
       if (!rc && depth_ring)
         rc = launch_render(h->scene, h->cam.dev, rot, h->cfg.fov_cull != 0, g.s, A, g.depth, nullptr,
-                           h->cam.dev.n_rays, 1.f, st);
+                           h->cam.dev.n_rays, 1.f, st, nullptr, 1.f, 0.f, 0, -1, h->render_nt);
       if (!rc && lidar_ring)
         rc = launch_render(h->scene, h->lidar.dev, rot, h->cfg.fov_cull != 0, g.s, A, g.lidar_out, nullptr,
-                           h->lidar.dev.n_rays, 1.f, st);
+                           h->lidar.dev.n_rays, 1.f, st, nullptr, 1.f, 0.f, 0, -1, h->render_nt);
     }
     if (rc) return rc;
   }
@@ -625,10 +637,10 @@ static int enqueue_task_rollout(sim_handle* h, RolloutPlan* p, const TaskRollout
       for (int pass = 0; pass < 2 && !rc; ++pass) {
         if (io.depth_ring)
           rc = launch_render(h->scene, h->cam.dev, rot, h->cfg.fov_cull != 0, gr.s, A, gr.depth, nullptr,
-                             h->cam.dev.n_rays, 1.f, st);
+                             h->cam.dev.n_rays, 1.f, st, nullptr, 1.f, 0.f, 0, -1, h->render_nt);
         if (!rc && io.lidar_ring)
           rc = launch_render(h->scene, h->lidar.dev, rot, h->cfg.fov_cull != 0, gr.s, A, gr.lidar_out, nullptr,
-                             h->lidar.dev.n_rays, 1.f, st);
+                             h->lidar.dev.n_rays, 1.f, st, nullptr, 1.f, 0.f, 0, -1, h->render_nt);
         if (!rc && pass == 0)
           rc = sim_task_step(h, io.cfg, gd.s_next, io.s_init, io.goal, gd.depth, io.k, ts.task.r_d, ts.task.r,
                              ts.task.flags, st);
@@ -658,7 +670,8 @@ int sim_rollout(sim_handle* h, int32_t T, float* s, const float* a_seq, float* d
   if (mode == 2) return enqueue_rollout(h, p, T, s, a_seq, depth_ring, lidar_ring, flags, true, st);
   std::vector<uintptr_t> key = {(uintptr_t)T, (uintptr_t)s, (uintptr_t)a_seq, (uintptr_t)depth_ring,
                                 (uintptr_t)lidar_ring, (uintptr_t)flags, (uintptr_t)h->params,
-                                (uintptr_t)p->tile_group, (uintptr_t)p->blocks_per_cu, (uintptr_t)p->order};
+                                (uintptr_t)p->tile_group, (uintptr_t)p->blocks_per_cu, (uintptr_t)p->order,
+                                (uintptr_t)p->nt, (uintptr_t)h->render_nt};
   if (!p->exec || key != p->key) {
     if (p->exec) {
       DA_HIP(hipGraphExecDestroy(p->exec));
@@ -772,7 +785,8 @@ static std::string tune_key(const sim_handle* h, const char* arch) {
   return buf;
 }
 
-static bool read_cache(const char* path, const std::string& key, int* tg, int* bpc, int* ord) {
+// *nt: the entry's "threads" (256 when the entry has none)
+static bool read_cache(const char* path, const std::string& key, int* tg, int* bpc, int* ord, int* nt) {
   if (!path || !*path) return false;
   FILE* f = fopen(path, "r");
   if (!f) return false;
@@ -786,11 +800,15 @@ static bool read_cache(const char* path, const std::string& key, int* tg, int* b
   if (at == std::string::npos) return false;
   size_t brace = text.find('{', at);
   if (brace == std::string::npos) return false;
-  return sscanf(text.c_str() + brace, "{\"tile_group\": %d, \"blocks_per_cu\": %d, \"order\": %d", tg, bpc,
-                ord) == 3;
+  const size_t close = text.find('}', brace);
+  const std::string entry = text.substr(brace, close == std::string::npos ? std::string::npos : close - brace);
+  *nt = 256;
+  const size_t th = entry.find("\"threads\": ");
+  if (th != std::string::npos) *nt = atoi(entry.c_str() + th + 11);
+  return sscanf(entry.c_str(), "{\"tile_group\": %d, \"blocks_per_cu\": %d, \"order\": %d", tg, bpc, ord) == 3;
 }
 
-static void write_cache(const char* path, const std::string& key, int tg, int bpc, int ord, float ms) {
+static void write_cache(const char* path, const std::string& key, int tg, int bpc, int ord, int nt, float ms) {
   if (!path || !*path) return;
   // keep other entries: read, drop the old line for this key, append
   std::string text;
@@ -811,8 +829,9 @@ static void write_cache(const char* path, const std::string& key, int tg, int bp
     pos = e + 1;
   }
   char buf[1024];
-  snprintf(buf, sizeof(buf), "  \"%s\": {\"tile_group\": %d, \"blocks_per_cu\": %d, \"order\": %d, \"ms\": %.4f}",
-           key.c_str(), tg, bpc, ord, ms);
+  snprintf(buf, sizeof(buf),
+           "  \"%s\": {\"tile_group\": %d, \"blocks_per_cu\": %d, \"order\": %d, \"threads\": %d, \"ms\": %.4f}",
+           key.c_str(), tg, bpc, ord, nt, ms);
   lines.push_back(buf);
   FILE* f = fopen(path, "w");
   if (!f) return;
@@ -837,9 +856,10 @@ extern "C" int sim_autotune(sim_handle* h, const float* s, const float* a, float
   DA_HIP(hipGetDeviceProperties(&prop, dev));
   const std::string key = tune_key(h, prop.gcnArchName);
   RolloutPlan* p = plan_of(h);
-  int tg, bpc, ord;
-  if (read_cache(cache_path, key, &tg, &bpc, &ord)) {
+  int tg, bpc, ord, nt;
+  if (read_cache(cache_path, key, &tg, &bpc, &ord, &nt)) {
     if ((rc = sim_rollout_config(h, tg, bpc, ord))) return rc;
+    p->nt = (nt == 128) ? 128 : 256;
     if (best_ms) *best_ms = -1.f;
     p->tuned = true;
     return SIM_OK;
@@ -854,41 +874,130 @@ extern "C" int sim_autotune(sim_handle* h, const float* s, const float* a, float
   DA_HIP(hipEventCreate(&e1));
   const int tgs[] = {2, 4, 8, 16, 1 << 20};
   const int bpcs[] = {2, 4, 8};
+  const int nts[] = {256, 128};
   float best = 1e30f;
-  int btg = 8, bbpc = 4, bord = 1;
-  for (int ord_ : {1, 0})
-    for (int tg_ : tgs)
-      for (int bpc_ : bpcs) {
-        if ((rc = sim_rollout_config(h, tg_, bpc_, ord_))) break;
-        if ((rc = ensure_plan(h, p, 1))) break;
-        std::vector<float> ts;
-        for (int rep = 0; rep < 4 && !rc; ++rep) {
-          DA_HIP(hipMemcpyAsync(s_work, s, (size_t)C * A * 4, hipMemcpyDeviceToDevice, st));
-          DA_HIP(hipEventRecord(e0, st));
-          rc = enqueue_rollout(h, p, 1, s_work, a, depth, lidar, nullptr, true, st);
-          DA_HIP(hipEventRecord(e1, st));
-          DA_HIP(hipEventSynchronize(e1));
-          float ms = 0.f;
-          DA_HIP(hipEventElapsedTime(&ms, e0, e1));
-          if (rep > 0) ts.push_back(ms);  // first run is a warm-up
+  int btg = 8, bbpc = 4, bord = 1, bnt = 256;
+  for (int nt_ : nts)
+    for (int ord_ : {1, 0})
+      for (int tg_ : tgs)
+        for (int bpc_ : bpcs) {
+          // a workgroup of 128 threads: twice the workgroups per CU for the same waves
+          const int wg = nt_ == 128 ? 2 * bpc_ : bpc_;
+          if (wg > 16) continue;
+          if ((rc = sim_rollout_config(h, tg_, wg, ord_))) break;
+          p->nt = nt_;
+          if ((rc = ensure_plan(h, p, 1))) break;
+          std::vector<float> ts;
+          for (int rep = 0; rep < 4 && !rc; ++rep) {
+            DA_HIP(hipMemcpyAsync(s_work, s, (size_t)C * A * 4, hipMemcpyDeviceToDevice, st));
+            DA_HIP(hipEventRecord(e0, st));
+            rc = enqueue_rollout(h, p, 1, s_work, a, depth, lidar, nullptr, true, st);
+            DA_HIP(hipEventRecord(e1, st));
+            DA_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            DA_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (rep > 0) ts.push_back(ms);  // first run is a warm-up
+          }
+          if (rc) break;
+          std::sort(ts.begin(), ts.end());
+          const float med = ts[ts.size() / 2];
+          if (med < best) {
+            best = med;
+            btg = tg_;
+            bbpc = wg;
+            bord = ord_;
+            bnt = nt_;
+          }
         }
-        if (rc) break;
-        std::sort(ts.begin(), ts.end());
-        const float med = ts[ts.size() / 2];
-        if (med < best) {
-          best = med;
-          btg = tg_;
-          bbpc = bpc_;
-          bord = ord_;
-        }
-      }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   (void)hipFree(s_work);
   if (rc) return rc;
   if ((rc = sim_rollout_config(h, btg, bbpc, bord))) return rc;
-  write_cache(cache_path, key, btg, bbpc, bord, best);
+  p->nt = bnt;
+  write_cache(cache_path, key, btg, bbpc, bord, bnt, best);
   if (best_ms) *best_ms = best;
   p->tuned = true;
   return SIM_OK;
 }
+
+extern "C" {
+
+int sim_rollout_set_threads(sim_handle* h, int32_t threads) {
+  DA_REQUIRE(h, "sim_rollout_set_threads: null handle");
+  DA_REQUIRE(threads == 128 || threads == 256, "sim_rollout_set_threads: threads must be 128 or 256");
+  plan_of(h)->nt = threads;
+  return SIM_OK;
+}
+
+int32_t sim_rollout_get_threads(sim_handle* h) { return h ? plan_of(h)->nt : -1; }
+
+int sim_render_config(sim_handle* h, int32_t threads) {
+  DA_REQUIRE(h, "sim_render_config: null handle");
+  DA_REQUIRE(threads == 128 || threads == 256, "sim_render_config: threads must be 128 or 256");
+  h->render_nt = threads;
+  return SIM_OK;
+}
+
+int32_t sim_render_get_config(const sim_handle* h) { return h ? h->render_nt : -1; }
+
+int sim_render_autotune(sim_handle* h, const float* s, const char* cache_path, float* best_ms, void* stream) {
+  DA_REQUIRE(h && s, "sim_render_autotune: null argument");
+  DA_REQUIRE(h->has_scene, "sim_render_autotune: scene not set");
+  DA_REQUIRE(h->cam.mem || h->lidar.mem, "sim_render_autotune: no sensor configured");
+  hipStream_t st = as_stream(stream);
+  int dev = 0;
+  DA_HIP(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  DA_HIP(hipGetDeviceProperties(&prop, dev));
+  const std::string key = "render|" + tune_key(h, prop.gcnArchName);
+  int tg, bpc, ord, nt;
+  if (read_cache(cache_path, key, &tg, &bpc, &ord, &nt)) {
+    h->render_nt = (nt == 128) ? 128 : 256;
+    if (best_ms) *best_ms = -1.f;
+    return SIM_OK;
+  }
+  const int A = h->cfg.n_agents;
+  const bool rot = h->cfg.model == SIM_RB13 || h->cfg.model == SIM_NOMINAL13;
+  float* out = nullptr;
+  const int nr = std::max(h->cam.mem ? h->cam.dev.n_rays : 0, h->lidar.mem ? h->lidar.dev.n_rays : 0);
+  DA_HIP(hipMalloc(&out, (size_t)A * nr * 4 + 4));
+  hipEvent_t e0, e1;
+  DA_HIP(hipEventCreate(&e0));
+  DA_HIP(hipEventCreate(&e1));
+  float best = 1e30f;
+  int bnt = 256, rc = SIM_OK;
+  for (int nt_ : {256, 128}) {
+    std::vector<float> ts;
+    for (int rep = 0; rep < 4 && !rc; ++rep) {
+      DA_HIP(hipEventRecord(e0, st));
+      if (h->cam.mem)
+        rc = launch_render(h->scene, h->cam.dev, rot, h->cfg.fov_cull != 0, s, A, out, nullptr, h->cam.dev.n_rays,
+                           1.f, st, nullptr, 1.f, 0.f, 0, -1, nt_);
+      if (!rc && h->lidar.mem)
+        rc = launch_render(h->scene, h->lidar.dev, rot, h->cfg.fov_cull != 0, s, A, out, nullptr,
+                           h->lidar.dev.n_rays, 1.f, st, nullptr, 1.f, 0.f, 0, -1, nt_);
+      DA_HIP(hipEventRecord(e1, st));
+      DA_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      DA_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (rep > 0) ts.push_back(ms);
+    }
+    if (rc) break;
+    std::sort(ts.begin(), ts.end());
+    if (ts[ts.size() / 2] < best) {
+      best = ts[ts.size() / 2];
+      bnt = nt_;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(out);
+  if (rc) return rc;
+  h->render_nt = bnt;
+  write_cache(cache_path, key, 0, 0, 0, bnt, best);
+  if (best_ms) *best_ms = best;
+  return SIM_OK;
+}
+
+}  // extern "C"

@@ -441,14 +441,16 @@ int sim_render(sim_handle* h, const float* s, float* depth, float* lidar, int32_
     DA_REQUIRE(h->cam.mem, "sim_render: no camera configured");
     DA_REQUIRE(depth, "sim_render: hit_cam needs depth");
     int rc = launch_render(h->scene, h->cam.dev, rot, h->cfg.fov_cull != 0, s, h->cfg.n_agents,
-                           depth, hit_cam, h->cam.dev.n_rays, 1.0f, as_stream(stream));
+                           depth, hit_cam, h->cam.dev.n_rays, 1.0f, as_stream(stream), nullptr, 1.f, 0.f, 0, -1,
+                           h->render_nt);
     if (rc) return rc;
   }
   if (lidar || hit_lidar) {
     DA_REQUIRE(h->lidar.mem, "sim_render: no LiDAR configured");
     DA_REQUIRE(lidar, "sim_render: hit_lidar needs lidar");
     int rc = launch_render(h->scene, h->lidar.dev, rot, h->cfg.fov_cull != 0, s, h->cfg.n_agents,
-                           lidar, hit_lidar, h->lidar.dev.n_rays, 1.0f, as_stream(stream));
+                           lidar, hit_lidar, h->lidar.dev.n_rays, 1.0f, as_stream(stream), nullptr, 1.f, 0.f, 0,
+                           -1, h->render_nt);
     if (rc) return rc;
   }
   return SIM_OK;
@@ -464,14 +466,14 @@ int sim_render_oriented(sim_handle* h, const float* s, const float* R, float* de
     DA_REQUIRE(h->cam.mem, "sim_render_oriented: no camera configured");
     DA_REQUIRE(depth, "sim_render_oriented: hit_cam needs depth");
     int rc = launch_render(sc, h->cam.dev, true, h->cfg.fov_cull != 0, s, h->cfg.n_agents, depth, hit_cam,
-                           h->cam.dev.n_rays, 1.0f, as_stream(stream));
+                           h->cam.dev.n_rays, 1.0f, as_stream(stream), nullptr, 1.f, 0.f, 0, -1, h->render_nt);
     if (rc) return rc;
   }
   if (lidar || hit_lidar) {
     DA_REQUIRE(h->lidar.mem, "sim_render_oriented: no LiDAR configured");
     DA_REQUIRE(lidar, "sim_render_oriented: hit_lidar needs lidar");
     int rc = launch_render(sc, h->lidar.dev, true, h->cfg.fov_cull != 0, s, h->cfg.n_agents, lidar, hit_lidar,
-                           h->lidar.dev.n_rays, 1.0f, as_stream(stream));
+                           h->lidar.dev.n_rays, 1.0f, as_stream(stream), nullptr, 1.f, 0.f, 0, -1, h->render_nt);
     if (rc) return rc;
   }
   return SIM_OK;

@@ -22,6 +22,7 @@ struct sim_handle {
   int n_sph = 0, n_box = 0, n_cyl = 0;
   bool has_scene = false;
   void* rollout = nullptr;             // uneven-batch rollout plan (rollout.hip)
+  int render_nt = 256;                 // threads per agent of the launch-per-op render (128 or 256)
 };
 
 void rollout_plan_free(sim_handle* h);

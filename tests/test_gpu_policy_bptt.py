@@ -205,3 +205,23 @@ def test_bptt_gradient_with_cylinders(model):
         assert ok, f"{name}: rel {rel:.2e} comp {comp:.4f}"
     ok, rel, comp = grad_close(f64(g_s0), torch.tensor(gs_ref))
     assert ok, f"g_s0: rel {rel:.2e} comp {comp:.4f}"
+
+
+def test_bptt_render_threads_are_bitwise_invariant():
+    """The launch-per-op render at 128 threads per agent (two wavefronts)
+    gives bitwise the loss and gradients of the 256-thread render: the fused
+    obstacle term keeps one sum per tile residue mod 4 in either case."""
+    from paper_2509_10247_amd import _lib
+    wk = wl.bptt(seed=11, n_envs=64, T=8, model=wl.RB13)
+    theta = _theta(12)
+    out = []
+    for nt in (256, 128):
+        e, eng = _engine(wk, 8, 4, True, X3)
+        _lib.sim_render_config(e.h, nt)
+        th, s0, goal = cuda(theta), cuda(wk.state0), cuda(wk.goal)
+        loss = eng.forward(th, s0, goal)
+        g_th, g_s0 = eng.backward()
+        torch.cuda.synchronize()
+        out.append((loss.clone(), g_th.clone(), g_s0.clone()))
+    for u, v in zip(*out):
+        assert torch.equal(u, v)

@@ -123,3 +123,36 @@ def test_full_size_uneven_graph_matches_plain():
     graph = _run(e, wk, bufs, _lib.ROLLOUT_GRAPH)
     _same(plain, graph)
     assert torch.isfinite(plain[0]).all()
+
+
+def test_threads_per_workgroup_do_not_change_results():
+    """The persistent render at 128 threads per workgroup (two wavefronts)
+    and the launch-per-op render at 128 threads give bitwise the outputs of
+    the 256-thread kernels."""
+    from paper_2509_10247_amd import _lib
+    wk, e, bufs = _setup(40, 3, seed=8)
+    ref = _run(e, wk, bufs, _lib.ROLLOUT_PLAIN)
+    _lib.sim_rollout_set_threads(e.h, 128)
+    assert _lib.sim_rollout_get_threads(e.h) == 128
+    for tg, bpc in [(1 << 20, 8), (4, 16)]:
+        _lib.sim_rollout_config(e.h, tg, bpc, 1)
+        _same(ref, _run(e, wk, bufs, _lib.ROLLOUT_FUSED))
+        _same(ref, _run(e, wk, bufs, _lib.ROLLOUT_GRAPH))
+    _lib.sim_render_config(e.h, 128)
+    _same(ref, _run(e, wk, bufs, _lib.ROLLOUT_PLAIN))
+    with pytest.raises(RuntimeError, match="128 or 256"):
+        _lib.sim_render_config(e.h, 64)
+
+
+def test_render_autotune_cache_roundtrip():
+    from paper_2509_10247_amd import _lib
+    wk, e, bufs = _setup(32, 1, seed=9)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "tune.json")
+        s = cuda(wk.state0)
+        best = _lib.sim_render_autotune(e.h, s, path)
+        choice = _lib.sim_render_get_config(e.h)
+        assert best > 0 and choice in (128, 256)
+        _lib.sim_render_config(e.h, 384 - choice)
+        assert _lib.sim_render_autotune(e.h, s, path) == -1.0 and _lib.sim_render_get_config(e.h) == choice
+        assert "render|" in open(path).read()
