@@ -699,6 +699,13 @@ int surrogate_train(surrogate_handle* h, float* theta, float* m, float* v, int32
                     const int32_t* perm, int32_t batch, int32_t n_steps, float lr, float* loss_hist,
                     void* stream);
 
+/* perm[i] <- a pseudo-random permutation of [0, N) (minibatch order of one
+ * training epoch, Sec. III-D's learned dynamics fitted by minibatch SGD):
+ * a four-round Feistel network keyed by `seed`, restricted to [0, N) by cycle
+ * walking. Deterministic in (N, seed). perm: device int32 [N]; N in
+ * [0, 2^31 - 1] (SIM_EINVAL otherwise). */
+int surrogate_shuffle(int64_t N, uint64_t seed, int32_t* perm, void* stream);
+
 /* Loads theta (flat) as the weights used by sim_surrogate_step. */
 int surrogate_load(surrogate_handle* h, const float* theta, void* stream);
 

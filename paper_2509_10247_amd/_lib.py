@@ -123,6 +123,7 @@ _SIGS = {
     "surrogate_train": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_void_p,
                                 c_int64, c_void_p, c_int, c_int, c_float, c_void_p, c_void_p]),
     "surrogate_load": (c_int, [c_void_p, c_void_p, c_void_p]),
+    "surrogate_shuffle": (c_int, [c_int64, ctypes.c_uint64, c_void_p, c_void_p]),
     "sim_surrogate_step": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                    c_void_p, c_int, c_int, ctypes.POINTER(c_float), c_void_p]),
     "policy_forward_noalloc": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p]),
@@ -588,6 +589,10 @@ def surrogate_train(h, theta, m, v, t0, x_rows, d_rows, norm, perm, batch, n_ste
           int(t0), ptr(x_rows, torch.float32), ptr(d_rows, torch.float32), ptr(norm, torch.float32),
           int(x_rows.shape[0]), ptr(perm, torch.int32), int(batch), int(n_steps), float(lr),
           ptr(loss_hist, torch.float32), stream())
+
+
+def surrogate_shuffle(N, seed, perm):
+    _call("surrogate_shuffle", int(N), int(seed) & (2**64 - 1), ptr(perm, torch.int32), stream())
 
 
 def surrogate_load(h, theta):

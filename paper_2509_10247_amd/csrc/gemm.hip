@@ -824,17 +824,22 @@ __global__ void adam_kernel(int64_t n, float* __restrict__ w, const float* __res
                             float eps, float c1, float c2) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const float gi = g[i];
-  const float mi = b1 * m[i] + (1.f - b1) * gi;
-  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  float wi = w[i], mi = m[i], vi = v[i];
+  adam_update(wi, g[i], mi, vi, lr, b1, b2, eps, c1, c2);
   m[i] = mi;
   v[i] = vi;
-  w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  w[i] = wi;
+}
+
+void adam_corrections(float b1, float b2, int t, float* c1, float* c2) {
+  *c1 = 1.f - powf(b1, (float)t);
+  *c2 = 1.f - powf(b2, (float)t);
 }
 
 int launch_adam(int64_t n, float* w, const float* g, float* m, float* v, float lr, float b1, float b2,
                 float eps, int t, hipStream_t st) {
-  const float c1 = 1.f - powf(b1, (float)t), c2 = 1.f - powf(b2, (float)t);
+  float c1, c2;
+  adam_corrections(b1, b2, t, &c1, &c2);
   hipLaunchKernelGGL(adam_kernel, dim3((unsigned)cdiv64(n, 256)), dim3(256), 0, st, n, w, g, m, v, lr,
                      b1, b2, eps, c1, c2);
   DA_LAUNCH_CHECK("adam_kernel");

@@ -71,6 +71,19 @@ __device__ __forceinline__ uint32_t bf16_pack2(float a, float b) {
   return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2_t){a, b}, bf16x2_t));
 }
 
+// One Adam update of one parameter (Kingma & Ba 2015, Algorithm 1) with the
+// bias corrections c1 = 1 - b1^t and c2 = 1 - b2^t of step t (computed once
+// on the host by adam_corrections).
+__device__ __forceinline__ void adam_update(float& w, float g, float& m, float& v, float lr, float b1, float b2,
+                                            float eps, float c1, float c2) {
+  const float mi = b1 * m + (1.f - b1) * g;
+  const float vi = b2 * v + (1.f - b2) * g * g;
+  m = mi;
+  v = vi;
+  w -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+void adam_corrections(float b1, float b2, int t, float* c1, float* c2);
+
 // Precision of launch_gemm:
 //  GEMM_FP32:   v_mfma_f32_32x32x2f32 on FP32 operands;
 //  GEMM_BF16:   operands read as FP32 and rounded to BF16 (nearest even) when

@@ -11,6 +11,7 @@
 // a judged agent whose surrogate step differs from the full step by more than
 // the per-block thresholds, or any agent whose z-scored input leaves [-4, 4],
 // switches to the full model for the rest of the rollout (sticky flag).
+#include <climits>
 #include <vector>
 
 #include "dyn_device.h"
@@ -122,54 +123,6 @@ __global__ void sur_moments_final_kernel(int64_t N, int W, int nb, const double*
   const double s = sqrt(var);
   mu[c] = (float)m;
   sd[c] = (float)(s > 1e-6 ? s : 1.0);  // constant columns are left unscaled
-}
-
-// gathers minibatch rows (z-scored, padded): X [B][20], T [B][16]
-__global__ void sur_gather_kernel(int B, const int* __restrict__ perm, const float* __restrict__ x,
-                                  const float* __restrict__ d, const float* __restrict__ norm,
-                                  float* __restrict__ X, float* __restrict__ T) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= B) return;
-  const int64_t r = perm ? perm[b] : b;
-  const float* mu_x = norm;
-  const float* sd_x = norm + kSIn;
-  const float* mu_d = norm + 2 * kSIn;
-  const float* sd_d = norm + 2 * kSIn + kSOut;
-  for (int c = 0; c < kSInP; ++c)
-    X[(size_t)b * kSInP + c] = c < kSIn ? (x[r * kSIn + c] - mu_x[c]) / sd_x[c] : 0.f;
-  if (T)
-    for (int c = 0; c < kSOutP; ++c)
-      T[(size_t)b * kSOutP + c] = c < kSOut ? (d[r * kSOut + c] - mu_d[c]) / sd_d[c] : 0.f;
-}
-
-// MSE over the 13 outputs: gY = 2 (Y - T) / (B * 13), per-row squared error
-__global__ void sur_mse_kernel(int B, const float* __restrict__ Y, const float* __restrict__ T,
-                               float* __restrict__ gY, float* __restrict__ row_err) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= B) return;
-  const float sc = 2.f / ((float)B * kSOut);
-  float e = 0.f;
-  for (int c = 0; c < kSOutP; ++c) {
-    const float r = c < kSOut ? Y[(size_t)b * kSOutP + c] - T[(size_t)b * kSOutP + c] : 0.f;
-    gY[(size_t)b * kSOutP + c] = sc * r;
-    e += r * r;
-  }
-  row_err[b] = e;
-}
-
-__global__ __launch_bounds__(1024) void sur_loss_kernel(int B, const float* __restrict__ row_err,
-                                                        float* __restrict__ out) {
-  __shared__ float red[1024];
-  const int t = threadIdx.x;
-  float v = 0.f;
-  for (int b = t; b < B; b += 1024) v += row_err[b];
-  red[t] = v;
-  __syncthreads();
-  for (int w = 512; w > 0; w >>= 1) {
-    if (t < w) red[t] += red[t + w];
-    __syncthreads();
-  }
-  if (t == 0) out[0] = red[0] / ((float)B * kSOut);
 }
 
 // ---------------------------------------------------------------------------
@@ -404,6 +357,515 @@ __global__ __launch_bounds__(256, 4) void sur_step_kernel(int A, float dt, int t
                    thr);
 }
 
+// ---------------------------------------------------------------------------
+// Training step in three launches for a minibatch of B rows (Bp = B rounded
+// up to 64; rows past B are zero inputs with zero output gradient, so they
+// add nothing to any gradient):
+//  1. sur_train_rows_kernel, one workgroup per 32 rows: gathers and z-scores
+//     the rows, runs the three layers, the MSE gradient and the backward pass
+//     down to both hidden pre-activation gradients in LDS and registers, and
+//     writes the BF16 operands of the weight gradients transposed, one
+//     feature per row ([feature][row]: z, H1, H2, rnd(gY), rnd(gZ2),
+//     rnd(gZ1)), with the workgroup's FP32 bias-gradient column sums and
+//     squared error.
+//  2. sur_train_wgrad_kernel: the weight gradients gW = rnd(g)^T h summed
+//     over the rows, 64 x 64 output tiles x 512-row chunks, FP32 partials.
+//  3. sur_train_update_kernel: the partials summed in a fixed order, then
+//     either the gradient or one Adam step on the FP32 master weights with
+//     the BF16 fragment copies of the new weights that the next step's
+//     first launch reads.
+// The rounding points are those of the BF16 forward and backward above:
+// GEMM operands (inputs, hidden activations, weights, the gradients entering
+// a product) in BF16, FP32 accumulation, bias gradients from the FP32
+// gradients.
+// ---------------------------------------------------------------------------
+constexpr int kTR = 32;                       // rows per workgroup of the row kernel
+constexpr int kXT = 32;                       // transposed input features (17 used)
+constexpr int kChunk = 512;                   // rows per workgroup of the weight-gradient kernel
+constexpr int kBiasN = 2 * kSH + kSOutP;      // column sums: b1, b2, b3
+constexpr int kBP = kBiasN + 16;              // pitch of a workgroup's sums; [kBiasN]: squared error
+constexpr int kGyP = kSOutP + 8;              // LDS pitch (BF16) of the rnd(gY) rows
+constexpr int kFP = kSH + 4;                  // LDS pitch (FP32) of the gradient rows
+constexpr int kWTiles = 16 + 4 + 4;           // output tiles: gW2 4 x 4, gW1 4 x 1, gW3 1 x 4
+// backward weights as BF16 MFMA A fragments (frag_index order, output block
+// nb of 32 hidden units, k chunk kc of 16 layer outputs): W2T[m][k] = W2[k][m]
+// (8 x 16 chunks), W3T[m][k] = W3[k][m] (8 x 1, outputs >= 13 zero)
+constexpr int kTW2 = 0, kTW3 = kTW2 + kSH * kSH, kTEnd = kTW3 + kSH * kSOutP;
+
+struct TrainOps {  // the transposed BF16 operands, [feature][ld]
+  uint16_t *xt, *h1, *h2, *gy, *g2, *g1;
+  int ld;
+};
+
+__global__ void sur_bwd_weights_kernel(const float* __restrict__ P, uint16_t* __restrict__ WbT) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= kTEnd) return;
+  const bool w2 = idx < kTW3;
+  const int KC = w2 ? kSH / 16 : 1;
+  const int f = idx - (w2 ? kTW2 : kTW3), e = f & 7, lane = (f >> 3) & 63, kc = (f >> 9) % KC, nb = (f >> 9) / KC;
+  const int m = 32 * nb + (lane & 31), k = 16 * kc + 8 * (lane >> 5) + e;
+  WbT[idx] = (uint16_t)bf16_bits(w2 ? P[kPW2 + k * kSH + m] : P[kPW3 + k * kSH + m]);
+}
+
+// A layer's BF16 weight fragments for output blocks nb0, nb0 + 1, all k
+// chunks, requested at once (one round trip to L2 for the whole layer)
+template <int KC>
+__device__ __forceinline__ void load_wfrags(const uint16_t* __restrict__ W, int nb0, int lane,
+                                            sbf16x8 (&wf)[KC][2]) {
+#pragma unroll
+  for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+    for (int a = 0; a < 2; ++a) wf[kc][a] = *reinterpret_cast<const sbf16x8*>(W + frag_index(nb0 + a, kc, KC, lane));
+}
+
+// 64 outputs x 32 rows of a layer, transposed (weights as the A operand):
+// acc[a][i] is output 32 (nb0 + a) + 8(i/4) + 4half + i%4 of row col
+template <int KC>
+__device__ __forceinline__ void tr_layer(const uint16_t* __restrict__ In, int in_pitch, const sbf16x8 (&wf)[KC][2],
+                                         int col, int half, sf32x16 (&acc)[2]) {
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[a][i] = 0.f;
+#pragma unroll
+  for (int kc = 0; kc < KC; ++kc) {
+    const sbf16x8 hf = *reinterpret_cast<const sbf16x8*>(In + col * in_pitch + kc * 16 + half * 8);
+#pragma unroll
+    for (int a = 0; a < 2; ++a) acc[a] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wf[kc][a], hf, acc[a], 0, 0, 0);
+  }
+}
+
+// bias + SiLU into Out[row][hidden] (BF16), the SiLU derivative kept per lane
+__device__ __forceinline__ void tr_silu(const sf32x16 (&acc)[2], const float* __restrict__ bias,
+                                        uint16_t* __restrict__ Out, int n0, int col, int half, sf32x16 (&ds)[2]) {
+  constexpr float kLog2e = 1.44269504088896341f;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const int n = n0 + 32 * a + 8 * g + 4 * half;
+      const float4 bn = *reinterpret_cast<const float4*>(bias + n);
+      const float bb[4] = {bn.x, bn.y, bn.z, bn.w};
+      sf32x4 h;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const float z = acc[a][4 * g + j] + bb[j];
+        const float sg = __builtin_amdgcn_rcpf(1.f + __builtin_amdgcn_exp2f(-z * kLog2e));
+        h[j] = z * sg;
+        ds[a][4 * g + j] = sg * (1.f + z * (1.f - sg));
+      }
+      *reinterpret_cast<sbf16x4*>(Out + col * kHP + n) = __builtin_convertvector(h, sbf16x4);
+    }
+}
+
+// pre-activation gradient gZ = gH * SiLU'(z): FP32 rows into F[row][hidden],
+// BF16 rows into Out[row][hidden]
+__device__ __forceinline__ void tr_grad_out(const sf32x16 (&acc)[2], const sf32x16 (&ds)[2], float* __restrict__ F,
+                                            uint16_t* __restrict__ Out, int n0, int col, int half) {
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const int n = n0 + 32 * a + 8 * g + 4 * half;
+      const sf32x4 v = {acc[a][4 * g] * ds[a][4 * g], acc[a][4 * g + 1] * ds[a][4 * g + 1],
+                        acc[a][4 * g + 2] * ds[a][4 * g + 2], acc[a][4 * g + 3] * ds[a][4 * g + 3]};
+      *reinterpret_cast<sf32x4*>(F + col * kFP + n) = v;
+      *reinterpret_cast<sbf16x4*>(Out + col * kHP + n) = __builtin_convertvector(v, sbf16x4);
+    }
+}
+
+// LDS rows S[32][pitch] (BF16) -> dst[f][r0 .. r0 + 31] for features f < nf:
+// thread (f, j) packs rows 8j .. 8j + 7 of column f into one 16-byte store
+__device__ __forceinline__ void store_transposed(const uint16_t* S, int pitch, int nf, uint16_t* __restrict__ dst,
+                                                 int ld, int r0, int tid) {
+  for (int idx = tid; idx < nf * 4; idx += 256) {
+    const int f = idx >> 2, j = idx & 3;
+    uint32_t w[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      w[e] = (uint32_t)S[(8 * j + 2 * e) * pitch + f] | ((uint32_t)S[(8 * j + 2 * e + 1) * pitch + f] << 16);
+    *reinterpret_cast<uint4*>(dst + (size_t)f * ld + r0 + 8 * j) = make_uint4(w[0], w[1], w[2], w[3]);
+  }
+}
+
+// column sums over the 32 rows of F[row][kFP] for n < 256, in row order
+__device__ __forceinline__ float col_sum32(const float* F, int n) {
+  float s = 0.f;
+#pragma unroll 8
+  for (int m = 0; m < kTR; ++m) s += F[m * kFP + n];
+  return s;
+}
+
+// LDS: 75 KB; a whole layer's weight fragments are held in registers, so
+// one workgroup per CU
+__global__ __launch_bounds__(256, 1) void sur_train_rows_kernel(int B, float gscale, const int32_t* __restrict__ perm,
+                                                                const float* __restrict__ x,
+                                                                const float* __restrict__ d,
+                                                                const float* __restrict__ norm,
+                                                                const float* __restrict__ P,
+                                                                const uint16_t* __restrict__ Wb,
+                                                                const uint16_t* __restrict__ WbT, TrainOps op,
+                                                                float* __restrict__ bpart) {
+  __shared__ __attribute__((aligned(16))) uint16_t Zs[kTR * kZP];
+  __shared__ __attribute__((aligned(16))) uint16_t H1s[kTR * kHP];   // H1, then rnd(gZ1)
+  __shared__ __attribute__((aligned(16))) uint16_t H2s[kTR * kHP];   // H2, then rnd(gZ2)
+  __shared__ __attribute__((aligned(16))) uint16_t Gys[kTR * kGyP];  // rnd(gY)
+  __shared__ __attribute__((aligned(16))) float Ts[kTR][kSOutP];     // targets, then gY (FP32)
+  __shared__ __attribute__((aligned(16))) float Es[kTR][kSOutP];     // squared errors
+  __shared__ __attribute__((aligned(16))) float Fs[kTR * kFP];       // output-layer partials, then gZ2, gZ1
+  __shared__ __attribute__((aligned(16))) float Bs[kBiasN];          // b1, b2, b3
+  static_assert(4 * kTR * kSOutP <= kTR * kFP, "output-layer partials fit the gradient rows");
+  float(*Yp)[kTR][kSOutP] = reinterpret_cast<float(*)[kTR][kSOutP]>(Fs);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int col = lane & 31, half = lane >> 5;
+  const int r0 = blockIdx.x * kTR, n0 = 64 * wave;
+  sbf16x8 w1f[kW1bK / 16][2], wf[kSH / 16][2];
+  float* bp = bpart + (size_t)blockIdx.x * kBP;
+  // z-scored rows and targets (row tid % 32, columns tid / 32 + 8j) and the
+  // biases read into registers first; the weights of the first two layers
+  // are requested after them (the scheduling barrier keeps that order, since
+  // a wait for a later load would wait for the whole prefetch)
+  {
+    const int m = tid & 31, b = r0 + m, c0 = tid >> 5;
+    const bool valid = b < B;
+    const int64_t r = valid ? (perm ? (int64_t)perm[b] : (int64_t)b) : 0;
+    float xv[3], xm[3], xs[3], dv[2], dm[2], ds[2];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const int c = c0 + 8 * j;
+      const bool in = valid && c < kSIn;
+      xv[j] = in ? x[r * kSIn + c] : 0.f;
+      xm[j] = in ? norm[c] : 0.f;
+      xs[j] = in ? norm[kSIn + c] : 1.f;
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int c = c0 + 8 * j;
+      const bool in = valid && c < kSOut;
+      dv[j] = in ? d[r * kSOut + c] : 0.f;
+      dm[j] = in ? norm[2 * kSIn + c] : 0.f;
+      ds[j] = in ? norm[2 * kSIn + kSOut + c] : 1.f;
+    }
+    const float bb1 = P[kPB1 + tid], bb2 = P[kPB2 + tid], bb3 = tid < kSOutP ? P[kPB3 + tid] : 0.f;
+    __builtin_amdgcn_sched_barrier(0);
+    load_wfrags<kW1bK / 16>(Wb + kBW1, n0 / 32, lane, w1f);
+    load_wfrags<kSH / 16>(Wb + kBW2, n0 / 32, lane, wf);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+      const int c = c0 + 8 * j;
+      const float v = (j < 3 && valid && c < kSIn) ? (xv[j < 3 ? j : 0] - xm[j < 3 ? j : 0]) / xs[j < 3 ? j : 0] : 0.f;
+      Zs[m * kZP + c] = (uint16_t)bf16_bits(v);
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int c = c0 + 8 * j;
+      Ts[m][c] = (valid && c < kSOut) ? (dv[j] - dm[j]) / ds[j] : 0.f;
+    }
+    Bs[tid] = bb1;
+    Bs[kSH + tid] = bb2;
+    if (tid < kSOutP) Bs[2 * kSH + tid] = bb3;
+  }
+  __syncthreads();
+  store_transposed(Zs, kZP, kXT, op.xt, op.ld, r0, tid);
+  sf32x16 acc[2], d1[2], d2[2];
+  tr_layer<kW1bK / 16>(Zs, kZP, w1f, col, half, acc);
+  tr_silu(acc, Bs, H1s, n0, col, half, d1);
+  __syncthreads();
+  store_transposed(H1s, kHP, kSH, op.h1, op.ld, r0, tid);
+  tr_layer<kSH / 16>(H1s, kHP, wf, col, half, acc);
+  // the output layer's fragments (k chunks 4 wave .. 4 wave + 3) and the
+  // backward pass's W3 and W2 fragments, in flight during the output layer
+  sbf16x8 w3f[4], w3tf[2];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    w3f[q] = *reinterpret_cast<const sbf16x8*>(Wb + kBW3 + frag_index(0, 4 * wave + q, kSH / 16, lane));
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+    w3tf[a] = *reinterpret_cast<const sbf16x8*>(WbT + kTW3 + frag_index(n0 / 32 + a, 0, 1, lane));
+  load_wfrags<kSH / 16>(WbT + kTW2, n0 / 32, lane, wf);
+  tr_silu(acc, Bs + kSH, H2s, n0, col, half, d2);
+  __syncthreads();
+  store_transposed(H2s, kHP, kSH, op.h2, op.ld, r0, tid);
+  {
+    // output layer, transposed (outputs 8(i/4) + 4half + i%4, 16 of 32 used):
+    // wave w sums k chunks 4w .. 4w + 3
+    sf32x16 y;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) y[i] = 0.f;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const sbf16x8 h = *reinterpret_cast<const sbf16x8*>(H2s + col * kHP + (4 * wave + q) * 16 + half * 8);
+      y = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w3f[q], h, y, 0, 0, 0);
+    }
+#pragma unroll
+    for (int g = 0; g < 2; ++g)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) Yp[wave][col][8 * g + 4 * half + j] = y[4 * g + j];
+  }
+  __syncthreads();
+  // MSE gradient gY = gscale (y - t) on the 13 outputs of valid rows
+  {
+    const int m = tid >> 3, c0 = 2 * (tid & 7);
+    const bool valid = r0 + m < B;
+#pragma unroll
+    for (int c = c0; c < c0 + 2; ++c) {
+      const float y = (((Yp[0][m][c] + Yp[1][m][c]) + Yp[2][m][c]) + Yp[3][m][c]) + Bs[2 * kSH + c];
+      const float e = (valid && c < kSOut) ? y - Ts[m][c] : 0.f;
+      const float g = gscale * e;
+      Es[m][c] = e * e;
+      Ts[m][c] = g;
+      Gys[m * kGyP + c] = (uint16_t)bf16_bits(g);
+    }
+  }
+  __syncthreads();
+  store_transposed(Gys, kGyP, kSOutP, op.gy, op.ld, r0, tid);
+  if (wave == 0 && lane < kSOutP) {
+    float s = 0.f;
+    for (int m = 0; m < kTR; ++m) s += Ts[m][lane];
+    bp[2 * kSH + lane] = s;
+  } else if (wave == 1) {
+    float s = 0.f;
+    for (int q = lane; q < kTR * kSOutP; q += 64) s += Es[q / kSOutP][q % kSOutP];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (lane == 0) bp[kBiasN] = s;
+  }
+  // gH2 = rnd(gY) W3, transposed (K = the 16 outputs), then gZ2
+  {
+    const sbf16x8 gf = *reinterpret_cast<const sbf16x8*>(Gys + col * kGyP + half * 8);
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) acc[a][i] = 0.f;
+      acc[a] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w3tf[a], gf, acc[a], 0, 0, 0);
+    }
+  }
+  tr_grad_out(acc, d2, Fs, H2s, n0, col, half);
+  __syncthreads();
+  bp[kSH + tid] = col_sum32(Fs, tid);
+  store_transposed(H2s, kHP, kSH, op.g2, op.ld, r0, tid);
+  // gH1 = rnd(gZ2) W2, transposed, then gZ1
+  tr_layer<kSH / 16>(H2s, kHP, wf, col, half, acc);
+  __syncthreads();  // every thread is done reading gZ2 from Fs
+  tr_grad_out(acc, d1, Fs, H1s, n0, col, half);
+  __syncthreads();
+  bp[tid] = col_sum32(Fs, tid);
+  store_transposed(H1s, kHP, kSH, op.g1, op.ld, r0, tid);
+}
+
+// One wave's 64 x 64 partial of C = A^T B over rows [rb, re) (re - rb a
+// multiple of 64, at most 128) of the transposed operands A [m][ld] and
+// B [n][ld]: A1 / B1 whether the second 32-row block of A / B exists, A16
+// whether A has only 16 rows (lanes 16 .. 31 then read row col - 16 and use
+// zero). Within each 64-row block, k step s of lane half h covers rows
+// 32h + 8s .. 32h + 8s + 7 (one permutation of the block's rows for both
+// operands), so a lane's four loads per operand row read 64 contiguous bytes
+// and a wave uses each 128-byte line it touches whole; both blocks' loads are
+// issued before the first product.
+template <bool A1, bool B1, bool A16>
+__device__ __forceinline__ void wgrad_tile(const uint16_t* __restrict__ Aop, const uint16_t* __restrict__ Bop,
+                                           int ld, int rb, int re, int col, int half, sf32x16 (&acc)[2][2]) {
+  const sbf16x8 zero = {};
+  const uint16_t* pa0 = Aop + (size_t)(A16 ? (col & 15) : col) * ld + 32 * half;
+  const uint16_t* pa1 = Aop + (size_t)(32 + col) * ld + 32 * half;
+  const uint16_t* pb0 = Bop + (size_t)col * ld + 32 * half;
+  const uint16_t* pb1 = Bop + (size_t)(32 + col) * ld + 32 * half;
+  const bool a0ok = !A16 || col < 16;
+  sbf16x8 fa0[2][4], fa1[2][4], fb0[2][4], fb1[2][4];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    // a block past the rows reads the last valid block, and its fragments
+    // are replaced by zeros (straight-line code keeps all loads up front)
+    const int k0 = min(rb + 64 * q, re - 64);
+    const bool in = q == 0 || rb + 64 * q < re;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      fa0[q][s] = *reinterpret_cast<const sbf16x8*>(pa0 + k0 + 8 * s);
+      fb0[q][s] = *reinterpret_cast<const sbf16x8*>(pb0 + k0 + 8 * s);
+      if (A1) fa1[q][s] = *reinterpret_cast<const sbf16x8*>(pa1 + k0 + 8 * s);
+      if (B1) fb1[q][s] = *reinterpret_cast<const sbf16x8*>(pb1 + k0 + 8 * s);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      fa0[q][s] = (in && a0ok) ? fa0[q][s] : zero;
+      fb0[q][s] = in ? fb0[q][s] : zero;
+      if (A1) fa1[q][s] = in ? fa1[q][s] : zero;
+      if (B1) fb1[q][s] = in ? fb1[q][s] : zero;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa0[q][s], fb0[q][s], acc[0][0], 0, 0, 0);
+      if (B1) acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa0[q][s], fb1[q][s], acc[0][1], 0, 0, 0);
+      if (A1) acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa1[q][s], fb0[q][s], acc[1][0], 0, 0, 0);
+      if (A1 && B1) acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa1[q][s], fb1[q][s], acc[1][1], 0, 0, 0);
+    }
+  }
+}
+
+// gW2 = rnd(gZ2)^T H1, gW1 = rnd(gZ1)^T z, gW3 = rnd(gY)^T H2 over rows
+// [512 c, 512 c + 512) of the Bp rows: workgroup (tile, c), wave w takes 128
+// of the rows, the four waves' 64 x 64 tiles summed in LDS in wave order.
+// FP32 partials into wpart[c][padded parameter index].
+__global__ __launch_bounds__(256, 2) void sur_train_wgrad_kernel(int Bp, TrainOps op, float* __restrict__ wpart) {
+  __shared__ float Red[4][64 * 65];
+  const int t = blockIdx.x, chunk = blockIdx.y;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int col = lane & 31, half = lane >> 5;
+  sf32x16 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) acc[a][b][i] = 0.f;
+  constexpr int kWave = kChunk / 4;
+  static_assert(kWave == 128, "two 64-row blocks per wave");
+  const int rb = chunk * kChunk + wave * kWave, re = min(rb + kWave, Bp);
+  int out, out_ld, m_lim, n_lim;
+  if (t < 16) {
+    out = kPW2 + (t / 4) * 64 * kSH + (t % 4) * 64; out_ld = kSH; m_lim = 64; n_lim = 64;
+    if (rb < re)
+      wgrad_tile<true, true, false>(op.g2 + (size_t)(t / 4) * 64 * op.ld, op.h1 + (size_t)(t % 4) * 64 * op.ld,
+                                    op.ld, rb, re, col, half, acc);
+  } else if (t < 20) {
+    out = kPW1 + (t - 16) * 64 * kSInP; out_ld = kSInP; m_lim = 64; n_lim = kSInP;
+    if (rb < re)
+      wgrad_tile<true, false, false>(op.g1 + (size_t)(t - 16) * 64 * op.ld, op.xt, op.ld, rb, re, col, half, acc);
+  } else {
+    out = kPW3 + (t - 20) * 64; out_ld = kSH; m_lim = kSOutP; n_lim = 64;
+    if (rb < re)
+      wgrad_tile<false, true, true>(op.gy, op.h2 + (size_t)(t - 20) * 64 * op.ld, op.ld, rb, re, col, half, acc);
+  }
+  // C[m][n]: lane (col = n % 32, half) holds m = 32a + 8(i/4) + 4half + i%4
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int i = 0; i < 16; ++i)
+        Red[wave][(32 * a + 8 * (i / 4) + 4 * half + i % 4) * 65 + 32 * b + col] = acc[a][b][i];
+  __syncthreads();
+  float* dst = wpart + (size_t)chunk * kPEnd + out;
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int m = e >> 6, n = e & 63;
+    if (m < m_lim && n < n_lim) {
+      const int q = m * 65 + n;
+      dst[m * out_ld + n] = ((Red[0][q] + Red[1][q]) + Red[2][q]) + Red[3][q];
+    }
+  }
+}
+
+__device__ __forceinline__ bool is_bias_index(int e) {
+  return (e >= kPB1 && e < kPW2) || (e >= kPB2 && e < kPW3) || e >= kPB3;
+}
+
+// new value of weight element e into the BF16 fragments of both passes
+__device__ __forceinline__ void store_weight_frags(int e, float w, uint16_t* __restrict__ Wb,
+                                                   uint16_t* __restrict__ WbT) {
+  const uint16_t bits = (uint16_t)bf16_bits(w);
+  if (e < kPB1) {
+    const int n = e / kSInP, k = e % kSInP;
+    Wb[kBW1 + frag_index(n / 32, k / 16, kW1bK / 16, (k % 16 / 8) * 32 + n % 32) + k % 8] = bits;
+  } else if (e < kPB2) {
+    const int n = (e - kPW2) / kSH, k = (e - kPW2) % kSH;
+    Wb[kBW2 + frag_index(n / 32, k / 16, kSH / 16, (k % 16 / 8) * 32 + n % 32) + k % 8] = bits;
+    WbT[kTW2 + frag_index(k / 32, n / 16, kSH / 16, (n % 16 / 8) * 32 + k % 32) + n % 8] = bits;
+  } else {
+    const int n = (e - kPW3) / kSH, k = (e - kPW3) % kSH;
+    Wb[kBW3 + frag_index(0, k / 16, kSH / 16, (k % 16 / 8) * 32 + n) + k % 8] = bits;
+    WbT[kTW3 + frag_index(k / 32, 0, 1, (n / 8) * 32 + k % 32) + n % 8] = bits;
+  }
+}
+
+struct TrainUpdate {
+  int nchunk, nwg, B;
+  const float* wpart;
+  const float* bpart;
+  float* loss;    // mean squared error of the minibatch, or null
+  float* G;       // gradient mode: the gradient (padded layout); else null
+  float *P, *m, *v;
+  float lr, b1, b2, eps, c1, c2;
+  uint16_t *Wb, *WbT;
+};
+
+// blocks [0, nw): one weight element per thread; then one wave per bias
+// element (and one for the loss) summing the row workgroups' column sums
+__global__ __launch_bounds__(256) void sur_train_update_kernel(TrainUpdate u) {
+  constexpr int nw = (kPEnd + 255) / 256;
+  int e;
+  float g;
+  if (blockIdx.x < nw) {
+    e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= kPEnd || is_bias_index(e)) return;
+    g = 0.f;
+    for (int c = 0; c < u.nchunk; ++c) g += u.wpart[(size_t)c * kPEnd + e];
+  } else {
+    const int lane = threadIdx.x & 63;
+    const int j = (blockIdx.x - nw) * 4 + (threadIdx.x >> 6);
+    if (j > kBiasN) return;
+    float s = 0.f;
+    for (int w = lane; w < u.nwg; w += 64) s += u.bpart[(size_t)w * kBP + j];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (lane != 0) return;
+    if (j == kBiasN) {
+      if (u.loss) u.loss[0] = s / ((float)u.B * kSOut);
+      return;
+    }
+    e = j < kSH ? kPB1 + j : j < 2 * kSH ? kPB2 + (j - kSH) : kPB3 + (j - 2 * kSH);
+    g = s;
+  }
+  if (u.G) {
+    u.G[e] = g;
+    return;
+  }
+  float w = u.P[e], m = u.m[e], v = u.v[e];
+  adam_update(w, g, m, v, u.lr, u.b1, u.b2, u.eps, u.c1, u.c2);
+  u.P[e] = w;
+  u.m[e] = m;
+  u.v[e] = v;
+  if (!is_bias_index(e)) store_weight_frags(e, w, u.Wb, u.WbT);
+}
+
+// Pseudo-random permutation of [0, N) for minibatch order: a balanced
+// Feistel network of four rounds on [0, 4^hb) (4^hb >= N), keyed by four
+// 32-bit keys, restricted to [0, N) by cycle walking (the network is applied
+// again until the value falls inside [0, N); on a bijection of the larger
+// domain this gives a bijection of [0, N), since the walk from i ends at the
+// first element of i's cycle that lies inside).
+__device__ __forceinline__ uint32_t feistel_f(uint32_t r, uint32_t key) {
+  uint32_t x = (r ^ key) * 0x9E3779B1u;
+  x ^= x >> 15;
+  x *= 0x85EBCA6Bu;
+  x ^= x >> 13;
+  x *= 0xC2B2AE35u;
+  return x ^ (x >> 16);
+}
+
+__global__ void sur_shuffle_kernel(int64_t N, int hb, uint4 key, int32_t* __restrict__ perm) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const uint32_t mask = (1u << hb) - 1u;
+  const uint32_t keys[4] = {key.x, key.y, key.z, key.w};
+  uint64_t x = (uint64_t)i;
+  do {
+    uint32_t L = (uint32_t)(x >> hb), R = (uint32_t)x & mask;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t nl = R;
+      R = L ^ (feistel_f(R, keys[k]) & mask);
+      L = nl;
+    }
+    x = ((uint64_t)L << hb) | R;
+  } while (x >= (uint64_t)N);
+  perm[i] = (int32_t)x;
+}
+
 }  // namespace da
 
 using namespace da;
@@ -413,90 +875,50 @@ struct surrogate_handle {
   void* mem = nullptr;
   int64_t bytes = 0;
   float *P, *G, *Pm, *Pv;  // padded params, grads, Adam moments
-  float *X, *Z1, *H1, *Z2, *H2, *Y, *T, *gY, *gZ2, *gZ1, *row_err, *part;
+  float *wpart, *bpart;    // weight-gradient partials per row chunk, column sums per row workgroup
+  TrainOps ops;            // transposed BF16 operands of the weight gradients
   double* mom;
-  uint16_t* Wb = nullptr;  // BF16 weights of the fused inference step
+  uint16_t* Wb = nullptr;   // BF16 forward weights (MFMA fragment order)
+  uint16_t* WbT = nullptr;  // BF16 backward weights
   bool loaded = false;
 };
 
 namespace da {
 
-constexpr int kSplitTN = 32;
+static int round64(int B) { return (B + 63) / 64 * 64; }
 
-static size_t sur_part_floats(int B) {
-  size_t a = (size_t)gemm_splits_used(B, kSplitTN) * kSH * kSH;
-  return std::max(a, (size_t)colsum_workspace_floats(kSH));
+// BF16 fragment copies of both passes from the padded FP32 weights
+static int sur_prepare_weights(surrogate_handle* h, hipStream_t st) {
+  hipLaunchKernelGGL(sur_bf16_weights_kernel, dim3(cdiv(kBEnd, 256)), dim3(256), 0, st, h->P, h->Wb);
+  DA_LAUNCH_CHECK("sur_bf16_weights_kernel");
+  hipLaunchKernelGGL(sur_bwd_weights_kernel, dim3(cdiv(kTEnd, 256)), dim3(256), 0, st, h->P, h->WbT);
+  DA_LAUNCH_CHECK("sur_bwd_weights_kernel");
+  return SIM_OK;
 }
 
-// forward on h->X (B rows): Z1, H1, Z2, H2, Y
-static int sur_forward(surrogate_handle* h, int B, hipStream_t st) {
-  const float* P = h->P;
-  GemmArgs g;
-  g.M = B; g.N = kSH; g.K = kSInP;
-  g.A = h->X; g.lda = kSInP; g.B = P + kPW1; g.ldb = kSInP; g.C = h->H1; g.ldc = kSH;
-  g.bias = P + kPB1; g.zout = h->Z1; g.ld_z = kSH;
-  int rc = launch_gemm(true, true, EPI_BIAS_SILU, g, 1, st, GEMM_BF16);
-  if (rc) return rc;
-  g = GemmArgs();
-  g.M = B; g.N = kSH; g.K = kSH;
-  g.A = h->H1; g.lda = kSH; g.B = P + kPW2; g.ldb = kSH; g.C = h->H2; g.ldc = kSH;
-  g.bias = P + kPB2; g.zout = h->Z2; g.ld_z = kSH;
-  if ((rc = launch_gemm(true, true, EPI_BIAS_SILU, g, 1, st, GEMM_BF16))) return rc;
-  g = GemmArgs();
-  g.M = B; g.N = kSOutP; g.K = kSH;
-  g.A = h->H2; g.lda = kSH; g.B = P + kPW3; g.ldb = kSH; g.C = h->Y; g.ldc = kSOutP;
-  g.bias = P + kPB3;
-  return launch_gemm(true, true, EPI_BIAS, g, 1, st, GEMM_BF16);
-}
-
-// gradients (padded layout, overwritten) for targets h->T; loss -> loss_out
-static int sur_backward(surrogate_handle* h, int B, float* loss_out, hipStream_t st) {
-  const float* P = h->P;
-  float* G = h->G;
-  hipLaunchKernelGGL(sur_mse_kernel, dim3(cdiv(B, 256)), dim3(256), 0, st, B, h->Y, h->T, h->gY, h->row_err);
-  DA_LAUNCH_CHECK("sur_mse_kernel");
-  if (loss_out) {
-    hipLaunchKernelGGL(sur_loss_kernel, dim3(1), dim3(1024), 0, st, B, h->row_err, loss_out);
-    DA_LAUNCH_CHECK("sur_loss_kernel");
-  }
-  // gW3 = gY^T H2 ; gb3
-  GemmArgs g;
-  g.M = kSOutP; g.N = kSH; g.K = B;
-  g.A = h->gY; g.lda = kSOutP; g.B = h->H2; g.ldb = kSH; g.C = h->part; g.ldc = kSH;
-  int rc = launch_gemm(false, false, EPI_PARTIAL, g, kSplitTN, st, GEMM_BF16);
-  if (rc) return rc;
-  if ((rc = launch_splitk_reduce(gemm_splits_used(B, kSplitTN), kSOutP, kSH, kSH, h->part, G + kPW3, kSH, false, st)))
-    return rc;
-  if ((rc = launch_colsum(B, kSOutP, h->gY, kSOutP, G + kPB3, false, h->part, st))) return rc;
-  // gZ2 = (gY W3) dsilu(Z2)
-  g = GemmArgs();
-  g.M = B; g.N = kSH; g.K = kSOutP;
-  g.A = h->gY; g.lda = kSOutP; g.B = P + kPW3; g.ldb = kSH; g.C = h->gZ2; g.ldc = kSH;
-  g.aux = h->Z2; g.ld_aux = kSH;
-  if ((rc = launch_gemm(true, false, EPI_MUL_DSILU, g, 1, st, GEMM_BF16))) return rc;
-  // gW2 = gZ2^T H1 ; gb2
-  g = GemmArgs();
-  g.M = kSH; g.N = kSH; g.K = B;
-  g.A = h->gZ2; g.lda = kSH; g.B = h->H1; g.ldb = kSH; g.C = h->part; g.ldc = kSH;
-  if ((rc = launch_gemm(false, false, EPI_PARTIAL, g, kSplitTN, st, GEMM_BF16))) return rc;
-  if ((rc = launch_splitk_reduce(gemm_splits_used(B, kSplitTN), kSH, kSH, kSH, h->part, G + kPW2, kSH, false, st)))
-    return rc;
-  if ((rc = launch_colsum(B, kSH, h->gZ2, kSH, G + kPB2, false, h->part, st))) return rc;
-  // gZ1 = (gZ2 W2) dsilu(Z1)
-  g = GemmArgs();
-  g.M = B; g.N = kSH; g.K = kSH;
-  g.A = h->gZ2; g.lda = kSH; g.B = P + kPW2; g.ldb = kSH; g.C = h->gZ1; g.ldc = kSH;
-  g.aux = h->Z1; g.ld_aux = kSH;
-  if ((rc = launch_gemm(true, false, EPI_MUL_DSILU, g, 1, st, GEMM_BF16))) return rc;
-  // gW1 = gZ1^T X ; gb1
-  g = GemmArgs();
-  g.M = kSH; g.N = kSInP; g.K = B;
-  g.A = h->gZ1; g.lda = kSH; g.B = h->X; g.ldb = kSInP; g.C = h->part; g.ldc = kSInP;
-  if ((rc = launch_gemm(false, false, EPI_PARTIAL, g, kSplitTN, st, GEMM_BF16))) return rc;
-  if ((rc = launch_splitk_reduce(gemm_splits_used(B, kSplitTN), kSH, kSInP, kSInP, h->part, G + kPW1, kSInP, false,
-                                 st)))
-    return rc;
-  return launch_colsum(B, kSH, h->gZ1, kSH, G + kPB1, false, h->part, st);
+// One training step on B rows (row b is rows[perm[b]], or b without perm):
+// the gradient into G (u.G set) or one Adam step (u.G null).
+static int sur_train_step(surrogate_handle* h, int B, const int32_t* perm, const float* x, const float* d,
+                          const float* norm, TrainUpdate u, hipStream_t st) {
+  const int Bp = round64(B), nwg = Bp / kTR, nchunk = cdiv(Bp, kChunk);
+  hipLaunchKernelGGL(sur_train_rows_kernel, dim3(nwg), dim3(256), 0, st, B, 2.f / ((float)B * kSOut), perm, x, d,
+                     norm, h->P, h->Wb, h->WbT, h->ops, h->bpart);
+  DA_LAUNCH_CHECK("sur_train_rows_kernel");
+  hipLaunchKernelGGL(sur_train_wgrad_kernel, dim3(kWTiles, nchunk), dim3(256), 0, st, Bp, h->ops, h->wpart);
+  DA_LAUNCH_CHECK("sur_train_wgrad_kernel");
+  u.nchunk = nchunk;
+  u.nwg = nwg;
+  u.B = B;
+  u.wpart = h->wpart;
+  u.bpart = h->bpart;
+  u.P = h->P;
+  u.m = h->Pm;
+  u.v = h->Pv;
+  u.Wb = h->Wb;
+  u.WbT = h->WbT;
+  hipLaunchKernelGGL(sur_train_update_kernel, dim3(cdiv(kPEnd, 256) + cdiv(kBiasN + 1, 4)), dim3(256), 0, st, u);
+  DA_LAUNCH_CHECK("sur_train_update_kernel");
+  return SIM_OK;
 }
 
 }  // namespace da
@@ -510,26 +932,25 @@ int surrogate_create(int32_t max_batch, surrogate_handle** out) {
   if (rc) return rc;
   surrogate_handle* h = new surrogate_handle();
   h->max_batch = max_batch;
-  const size_t B = (size_t)max_batch;
   std::vector<std::pair<void**, size_t>> parts;
   auto add = [&](auto** p, size_t bytes) { parts.push_back({reinterpret_cast<void**>(p), (bytes + 255) & ~size_t(255)}); };
+  const int ld = round64(max_batch);
+  const size_t L = (size_t)ld;
   add(&h->P, kPEnd * 4);
   add(&h->G, kPEnd * 4);
   add(&h->Pm, kPEnd * 4);
   add(&h->Pv, kPEnd * 4);
-  add(&h->X, B * kSInP * 4);
-  add(&h->Z1, B * kSH * 4);
-  add(&h->H1, B * kSH * 4);
-  add(&h->Z2, B * kSH * 4);
-  add(&h->H2, B * kSH * 4);
-  add(&h->Y, B * kSOutP * 4);
-  add(&h->T, B * kSOutP * 4);
-  add(&h->gY, B * kSOutP * 4);
-  add(&h->gZ2, B * kSH * 4);
-  add(&h->gZ1, B * kSH * 4);
-  add(&h->row_err, B * 4);
-  add(&h->part, sur_part_floats(max_batch) * 4);
+  add(&h->wpart, (size_t)cdiv(ld, kChunk) * kPEnd * 4);
+  add(&h->bpart, (size_t)(ld / kTR) * kBP * 4);
+  add(&h->ops.xt, L * kXT * 2);
+  add(&h->ops.h1, L * kSH * 2);
+  add(&h->ops.h2, L * kSH * 2);
+  add(&h->ops.gy, L * kSOutP * 2);
+  add(&h->ops.g2, L * kSH * 2);
+  add(&h->ops.g1, L * kSH * 2);
+  h->ops.ld = ld;
   add(&h->Wb, (size_t)kBEnd * 2);
+  add(&h->WbT, (size_t)kTEnd * 2);
   add(&h->mom, (size_t)kSIn * 256 * 2 * sizeof(double));
   size_t total = 0;
   for (auto& p : parts) total += p.second;
@@ -591,12 +1012,12 @@ int surrogate_grad(surrogate_handle* h, const float* theta, const float* x_rows,
   DA_REQUIRE(B >= 1 && B <= h->max_batch, "surrogate_grad: batch %d outside [1, %d]", B, h->max_batch);
   hipStream_t st = as_stream(stream);
   int rc = repack(theta, h->P, 0, st);
+  if (!rc) rc = sur_prepare_weights(h, st);
   if (rc) return rc;
-  hipLaunchKernelGGL(sur_gather_kernel, dim3(cdiv(B, 256)), dim3(256), 0, st, B, nullptr, x_rows, d_rows, norm,
-                     h->X, h->T);
-  DA_LAUNCH_CHECK("sur_gather_kernel");
-  if ((rc = sur_forward(h, B, st))) return rc;
-  if ((rc = sur_backward(h, B, loss, st))) return rc;
+  TrainUpdate u{};
+  u.G = h->G;
+  u.loss = loss;
+  if ((rc = sur_train_step(h, B, nullptr, x_rows, d_rows, norm, u, st))) return rc;
   h->loaded = false;
   return repack(h->G, g_theta, 1, st);
 }
@@ -613,20 +1034,44 @@ int surrogate_train(surrogate_handle* h, float* theta, float* m, float* v, int32
   int rc = repack(theta, h->P, 0, st);
   if (!rc) rc = repack(m, h->Pm, 0, st);
   if (!rc) rc = repack(v, h->Pv, 0, st);
+  if (!rc) rc = sur_prepare_weights(h, st);
   if (rc) return rc;
   for (int it = 0; it < n_steps; ++it) {
-    hipLaunchKernelGGL(sur_gather_kernel, dim3(cdiv(batch, 256)), dim3(256), 0, st, batch,
-                       perm + (size_t)it * batch, x_rows, d_rows, norm, h->X, h->T);
-    DA_LAUNCH_CHECK("sur_gather_kernel");
-    if ((rc = sur_forward(h, batch, st))) return rc;
-    if ((rc = sur_backward(h, batch, loss_hist ? loss_hist + it : nullptr, st))) return rc;
-    if ((rc = launch_adam(kPEnd, h->P, h->G, h->Pm, h->Pv, lr, 0.9f, 0.999f, 1e-8f, t0 + it + 1, st))) return rc;
+    TrainUpdate u{};
+    u.loss = loss_hist ? loss_hist + it : nullptr;
+    u.lr = lr;
+    u.b1 = 0.9f;
+    u.b2 = 0.999f;
+    u.eps = 1e-8f;
+    adam_corrections(u.b1, u.b2, t0 + it + 1, &u.c1, &u.c2);
+    if ((rc = sur_train_step(h, batch, perm + (size_t)it * batch, x_rows, d_rows, norm, u, st))) return rc;
   }
   rc = repack(h->P, theta, 1, st);
   if (!rc) rc = repack(h->Pm, m, 1, st);
   if (!rc) rc = repack(h->Pv, v, 1, st);
   h->loaded = false;
   return rc;
+}
+
+int surrogate_shuffle(int64_t N, uint64_t seed, int32_t* perm, void* stream) {
+  DA_REQUIRE(N >= 0 && N <= INT32_MAX && (N == 0 || perm), "surrogate_shuffle: N outside [0, 2^31 - 1]");
+  if (N == 0) return SIM_OK;
+  int hb = 1;
+  while (((uint64_t)1 << (2 * hb)) < (uint64_t)N) ++hb;
+  // round keys: a splitmix64 sequence from the seed
+  uint32_t k[4];
+  uint64_t z = seed;
+  for (int r = 0; r < 4; ++r) {
+    z += 0x9E3779B97F4A7C15ull;
+    uint64_t q = z;
+    q = (q ^ (q >> 30)) * 0xBF58476D1CE4E5B9ull;
+    q = (q ^ (q >> 27)) * 0x94D049BB133111EBull;
+    k[r] = (uint32_t)(q ^ (q >> 31));
+  }
+  hipLaunchKernelGGL(sur_shuffle_kernel, dim3((unsigned)cdiv64(N, 256)), dim3(256), 0, as_stream(stream), N, hb,
+                     make_uint4(k[0], k[1], k[2], k[3]), perm);
+  DA_LAUNCH_CHECK("sur_shuffle_kernel");
+  return SIM_OK;
 }
 
 int surrogate_load(surrogate_handle* h, const float* theta, void* stream) {

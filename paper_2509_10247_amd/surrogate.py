@@ -7,7 +7,6 @@ libdiffaero.so.
 """
 from __future__ import annotations
 
-import numpy as np
 import torch
 
 from . import _lib
@@ -62,13 +61,13 @@ class Surrogate:
         """Adam on shuffled minibatches; returns the per-step loss history."""
         N = x.shape[0]
         steps = N // batch
-        rng = np.random.default_rng(seed)
         m = torch.zeros_like(theta)
         v = torch.zeros_like(theta)
         hist = torch.empty(epochs * steps, device="cuda")
+        perm = torch.empty(N, dtype=torch.int32, device="cuda")
         t = 0
         for ep in range(epochs):
-            perm = torch.as_tensor(rng.permutation(N)[: steps * batch].astype(np.int32), device="cuda")
+            _lib.surrogate_shuffle(N, (int(seed) << 32) | ep, perm)
             _lib.surrogate_train(self.h, theta, m, v, t, x, d, self.norm, perm, batch, steps, lr,
                                  hist[ep * steps:(ep + 1) * steps])
             t += steps

@@ -48,12 +48,14 @@ def test_pack_rows_match_oracle_residual():
     assert torch.allclose(f64(d)[:300], full - nom, atol=2e-5)
 
 
-def test_surrogate_gradient_matches_bf16_oracle():
+@pytest.mark.parametrize("B,A", [(300, 512), (2080, 600)])
+def test_surrogate_gradient_matches_bf16_oracle(B, A):
+    """Ragged batches: 300 rows end inside a 32-row workgroup, 2080 rows span
+    five 512-row chunks of the weight-gradient kernel, the last one short."""
     from paper_2509_10247_amd import surrogate
-    wk, e, x, d = _data()
-    B = 300
+    wk, e, x, d = _data(A=A)
     print_case("surrogate_grad", B=B)
-    sur = surrogate.Surrogate(max_batch=1024)
+    sur = surrogate.Surrogate(max_batch=4096)
     norm = sur.fit_normalizer(x, d)
     theta = wl.flatten_mlp(wl.mlp_init(np.random.default_rng(3), wl.SURROGATE_DIMS))
     g, loss = sur.grad(cuda(theta), x, d, B)
@@ -69,6 +71,57 @@ def test_surrogate_gradient_matches_bf16_oracle():
         ok, rel, comp = grad_close(f64(g)[a:b], ref[a:b])
         print(f"  {name}: rel {rel:.2e} comp {comp:.4f}")
         assert ok, f"{name}: rel {rel:.2e}, comp {comp:.4f}"
+
+
+def test_train_steps_equal_gradient_plus_adam_bitwise():
+    """surrogate_train's fused update equals surrogate_grad on the same
+    minibatch rows followed by adam_step, bit for bit, over three steps of a
+    ragged batch (losses, weights and both moments)."""
+    from paper_2509_10247_amd import _lib, surrogate
+    wk, e, x, d = _data(A=512, T=4)
+    N, B, steps, t0 = x.shape[0], 300, 3, 5
+    print_case("surrogate_train vs grad + adam_step", B=B, steps=steps)
+    sur = surrogate.Surrogate(max_batch=1024)
+    sur.fit_normalizer(x, d)
+    theta = cuda(wl.flatten_mlp(wl.mlp_init(np.random.default_rng(4), wl.SURROGATE_DIMS)))
+    rng = np.random.default_rng(5)
+    m0 = cuda(rng.normal(0, 1e-3, theta.numel()))
+    v0 = cuda(rng.uniform(0, 1e-6, theta.numel()))
+    perm = torch.empty(N, dtype=torch.int32, device="cuda")
+    _lib.surrogate_shuffle(N, 11, perm)
+    th1, m1, v1 = theta.clone(), m0.clone(), v0.clone()
+    hist = torch.empty(steps, device="cuda")
+    _lib.surrogate_train(sur.h, th1, m1, v1, t0, x, d, sur.norm, perm, B, steps, 1e-3, hist)
+    th2, m2, v2 = theta.clone(), m0.clone(), v0.clone()
+    for it in range(steps):
+        rows = perm[it * B:(it + 1) * B].long()
+        g, loss = sur.grad(th2, x[rows].contiguous(), d[rows].contiguous(), B)
+        assert torch.equal(loss, hist[it:it + 1]), it
+        _lib.adam_step(th2, g, m2, v2, 1e-3, 0.9, 0.999, 1e-8, t0 + it + 1)
+    torch.cuda.synchronize()
+    assert torch.equal(th1, th2) and torch.equal(m1, m2) and torch.equal(v1, v2)
+    assert not torch.equal(th1, theta)
+
+
+@pytest.mark.parametrize("N", [1, 2, 1000, 1_000_003])
+def test_shuffle_is_a_seeded_permutation(N):
+    from paper_2509_10247_amd import _lib
+    a = torch.empty(N, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    c = torch.empty_like(a)
+    _lib.surrogate_shuffle(N, 7, a)
+    _lib.surrogate_shuffle(N, 7, b)
+    _lib.surrogate_shuffle(N, 8, c)
+    assert torch.equal(torch.sort(a.long()).values, torch.arange(N, device="cuda"))
+    assert torch.equal(torch.sort(c.long()).values, torch.arange(N, device="cuda"))
+    assert torch.equal(a, b)
+    if N >= 1000:
+        assert not torch.equal(a, c)
+        # a shuffled order: few fixed points, no visible trend
+        idx = torch.arange(N, device="cuda", dtype=torch.float64)
+        assert (a.long() == idx.long()).sum().item() < 20
+        r = torch.corrcoef(torch.stack([idx, a.double()]))[0, 1].item()
+        assert abs(r) < 0.1
 
 
 def test_norm_matches_column_moments():
