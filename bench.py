@@ -59,7 +59,7 @@ def parse():
                    help="skip the other policy-GEMM form and the recompute-all variant")
     p.add_argument("--sections", default="step,render,imu,attitude,task,surrogate,uneven,sha2c",
                    help="comma list of extra sections after the headline: step, render, imu, attitude, task, "
-                        "surrogate, uneven, sha2c")
+                        "surrogate, surrogate_train, uneven, sha2c")
     return p.parse_args()
 
 
@@ -509,6 +509,61 @@ def surrogate_section(seed=0):
     return out
 
 
+# Algorithmic FLOPs of one surrogate training row (17-256-256-13 MLP): the
+# forward products, the three weight-gradient products and the input
+# gradients of the two upper layers, 2 FLOPs per multiply-add
+SUR_DIMS = (17, 256, 256, 13)
+SUR_TRAIN_FLOP_PER_ROW = (2 * sum(a * b for a, b in zip(SUR_DIMS, SUR_DIMS[1:])) * 2
+                          + 2 * sum(a * b for a, b in zip(SUR_DIMS[1:], SUR_DIMS[2:])))
+
+
+def surrogate_train_section(seed=0, R=4, epochs=2, batch=8192):
+    """Surrogate training alone: R x 4096 x 64 full-model transitions, `epochs`
+    epochs of Adam steps at `batch` rows (three kernels per step, the
+    minibatch order drawn on the GPU once per epoch). Time from HIP events
+    around each epoch's training call on the launch stream; roofline against
+    the BF16 matrix-core peak on the algorithmic FLOPs of a step."""
+    import numpy as np
+    import torch
+    import workloads as wl
+    from paper_2509_10247_amd import _lib, env, surrogate
+    A, T = 4096, 64
+    x = torch.empty(A * T * R, 17, device="cuda")
+    d = torch.empty(A * T * R, 13, device="cuda")
+    for r in range(R):
+        wk = wl.surrogate_full(seed=100 + r, n_envs=A, T=T)
+        e = env.from_workload(wk)
+        surrogate.Surrogate.collect(e, torch.tensor(wk.state0, device="cuda"),
+                                    torch.tensor(wk.actions, device="cuda"), x, d, offset=r * A * T)
+    sur = surrogate.Surrogate(max_batch=batch)
+    sur.fit_normalizer(x, d)
+    theta = torch.tensor(wl.flatten_mlp(wl.mlp_init(np.random.default_rng(seed), wl.SURROGATE_DIMS)),
+                         device="cuda")
+    N = x.shape[0]
+    steps = N // batch
+    m, v = torch.zeros_like(theta), torch.zeros_like(theta)
+    perm = torch.empty(N, dtype=torch.int32, device="cuda")
+    hist = torch.empty(steps, device="cuda")
+    ms = []
+    for ep in range(epochs + 1):  # the first epoch is a warm-up
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        _lib.surrogate_shuffle(N, (seed << 32) | ep, perm)
+        _lib.surrogate_train(sur.h, theta, m, v, ep * steps, x, d, sur.norm, perm, batch, steps, 1e-3, hist)
+        ev1.record()
+        torch.cuda.synchronize()
+        if ep:
+            ms.append(ev0.elapsed_time(ev1))
+    us = 1e3 * sum(ms) / (epochs * steps)
+    flops = SUR_TRAIN_FLOP_PER_ROW * batch
+    tf = flops / (us * 1e-6) / 1e12
+    return {"rows": N, "batch": batch, "steps_timed": epochs * steps, "us_per_step": round(us, 2),
+            "steps_per_s": round(1e6 / us, 1), "final_loss": float(hist[-1].item()),
+            "roofline": {"bound": "mfma", "achieved": round(tf, 2), "peak": PEAK_BF16_MFMA / 1e12, "unit": "TFLOP/s",
+                         "frac": round(tf * 1e12 / PEAK_BF16_MFMA, 4), "flops_per_step": flops,
+                         "kernels": "sur_train_rows_kernel, sur_train_wgrad_kernel, sur_train_update_kernel"}}
+
+
 def render_work_flops(e, s, term):
     """Algorithmic FLOPs of one camera render at state s: the ray and test
     counts come from sim_render_work (the same kernel with counters)."""
@@ -873,6 +928,8 @@ def main():
         line["task"] = task_section()
     if "surrogate" in sections:
         line["surrogate"] = surrogate_section()
+    if "surrogate_train" in sections:
+        line["surrogate_train"] = surrogate_train_section()
     if "uneven" in sections:
         line["uneven"] = uneven_section()
     if "sha2c" in sections:

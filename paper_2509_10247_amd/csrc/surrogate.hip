@@ -366,8 +366,8 @@ __global__ __launch_bounds__(256, 4) void sur_step_kernel(int A, float dt, int t
 //     down to both hidden pre-activation gradients in LDS and registers, and
 //     writes the BF16 operands of the weight gradients transposed, one
 //     feature per row ([feature][row]: z, H1, H2, rnd(gY), rnd(gZ2),
-//     rnd(gZ1)), with the workgroup's FP32 bias-gradient column sums and
-//     squared error.
+//     rnd(gZ1)) in MFMA fragment order (below), with the workgroup's FP32
+//     bias-gradient column sums and squared error.
 //  2. sur_train_wgrad_kernel: the weight gradients gW = rnd(g)^T h summed
 //     over the rows, 64 x 64 output tiles x 512-row chunks, FP32 partials.
 //  3. sur_train_update_kernel: the partials summed in a fixed order, then
@@ -381,6 +381,7 @@ __global__ __launch_bounds__(256, 4) void sur_step_kernel(int A, float dt, int t
 // ---------------------------------------------------------------------------
 constexpr int kTR = 32;                       // rows per workgroup of the row kernel
 constexpr int kXT = 32;                       // transposed input features (17 used)
+constexpr int kGT = 32;                       // transposed output-gradient features (13 used, rest zero)
 constexpr int kChunk = 512;                   // rows per workgroup of the weight-gradient kernel
 constexpr int kBiasN = 2 * kSH + kSOutP;      // column sums: b1, b2, b3
 constexpr int kBP = kBiasN + 16;              // pitch of a workgroup's sums; [kBiasN]: squared error
@@ -392,9 +393,16 @@ constexpr int kWTiles = 16 + 4 + 4;           // output tiles: gW2 4 x 4, gW1 4 
 // (8 x 16 chunks), W3T[m][k] = W3[k][m] (8 x 1, outputs >= 13 zero)
 constexpr int kTW2 = 0, kTW3 = kTW2 + kSH * kSH, kTEnd = kTW3 + kSH * kSOutP;
 
-struct TrainOps {  // the transposed BF16 operands, [feature][ld]
+// The weight-gradient operands (F features x the rows, BF16) in MFMA
+// fragment order: block (row block kb of 16 rows, feature block fb of 32)
+// is 512 contiguous halfwords, lane (col, half) holding features 32 fb + col
+// of rows 16 kb + 8 half .. + 7, so that a wave reads or writes one block as
+// one contiguous 1 KB run. F is a multiple of 32 (padding features zero).
+__host__ __device__ constexpr size_t op_block(int kb, int fb, int nfb) { return ((size_t)kb * nfb + fb) * 512; }
+
+struct TrainOps {  // transposed BF16 operands in fragment order
   uint16_t *xt, *h1, *h2, *gy, *g2, *g1;
-  int ld;
+  int ld;  // rows allocated (a multiple of 64)
 };
 
 __global__ void sur_bwd_weights_kernel(const float* __restrict__ P, uint16_t* __restrict__ WbT) {
@@ -474,17 +482,49 @@ __device__ __forceinline__ void tr_grad_out(const sf32x16 (&acc)[2], const sf32x
     }
 }
 
-// LDS rows S[32][pitch] (BF16) -> dst[f][r0 .. r0 + 31] for features f < nf:
-// thread (f, j) packs rows 8j .. 8j + 7 of column f into one 16-byte store
-__device__ __forceinline__ void store_transposed(const uint16_t* S, int pitch, int nf, uint16_t* __restrict__ dst,
-                                                 int ld, int r0, int tid) {
-  for (int idx = tid; idx < nf * 4; idx += 256) {
-    const int f = idx >> 2, j = idx & 3;
-    uint32_t w[4];
+// LDS rows S[32][PITCH] (BF16, features f < NF) -> the operand rows r0 ..
+// r0 + 31 in fragment order (NFP features, those from NF on written as
+// zeros): item (features 4q .. 4q + 3, rows 8j .. 8j + 7) reads eight 8-byte
+// runs (one per row) and writes four 16-byte runs (lanes 4q % 32 .. + 3 of
+// one block, 64 contiguous bytes), the halfwords regrouped by byte permutes;
+// all of a thread's reads are issued before its first store.
+template <int NF, int NFP, int PITCH>
+__device__ __forceinline__ void store_transposed(const uint16_t* S, uint16_t* __restrict__ dst, int r0, int tid) {
+  static_assert(NF % 4 == 0 && NFP % 32 == 0 && NF <= NFP && PITCH % 4 == 0, "8-byte runs, whole blocks");
+  constexpr int kItems = NFP, kIt = (kItems + 255) / 256;  // NFP / 4 quads x 4 row groups
+  uint2 v[kIt][8];
 #pragma unroll
-    for (int e = 0; e < 4; ++e)
-      w[e] = (uint32_t)S[(8 * j + 2 * e) * pitch + f] | ((uint32_t)S[(8 * j + 2 * e + 1) * pitch + f] << 16);
-    *reinterpret_cast<uint4*>(dst + (size_t)f * ld + r0 + 8 * j) = make_uint4(w[0], w[1], w[2], w[3]);
+  for (int it = 0; it < kIt; ++it) {
+    const int idx = tid + 256 * it;
+    const int q = idx >> 2, j = idx & 3;
+    if ((kItems % 256 == 0 || idx < kItems) && 4 * q < NF) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[it][e] = *reinterpret_cast<const uint2*>(S + (8 * j + e) * PITCH + 4 * q);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[it][e] = make_uint2(0u, 0u);
+    }
+  }
+#pragma unroll
+  for (int it = 0; it < kIt; ++it) {
+    const int idx = tid + 256 * it;
+    if (kItems % 256 == 0 || idx < kItems) {
+      const int q = idx >> 2, j = idx & 3;
+      const int r = r0 + 8 * j;  // r0 is a multiple of 32
+      uint16_t* blk = dst + op_block(r >> 4, (4 * q) >> 5, NFP / 32) + ((j & 1) * 32 + (4 * q) % 32) * 8;
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        // halfword f of rows 2k and 2k + 1 into dword k (low, high)
+        uint32_t w[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const uint32_t a = (f < 2) ? v[it][2 * k].x : v[it][2 * k].y;
+          const uint32_t b = (f < 2) ? v[it][2 * k + 1].x : v[it][2 * k + 1].y;
+          w[k] = (f & 1) ? __builtin_amdgcn_perm(b, a, 0x07060302u) : __builtin_amdgcn_perm(b, a, 0x05040100u);
+        }
+        *reinterpret_cast<uint4*>(blk + 8 * f) = make_uint4(w[0], w[1], w[2], w[3]);
+      }
+    }
   }
 }
 
@@ -567,12 +607,12 @@ __global__ __launch_bounds__(256, 1) void sur_train_rows_kernel(int B, float gsc
     if (tid < kSOutP) Bs[2 * kSH + tid] = bb3;
   }
   __syncthreads();
-  store_transposed(Zs, kZP, kXT, op.xt, op.ld, r0, tid);
+  store_transposed<kXT, kXT, kZP>(Zs, op.xt, r0, tid);
   sf32x16 acc[2], d1[2], d2[2];
   tr_layer<kW1bK / 16>(Zs, kZP, w1f, col, half, acc);
   tr_silu(acc, Bs, H1s, n0, col, half, d1);
   __syncthreads();
-  store_transposed(H1s, kHP, kSH, op.h1, op.ld, r0, tid);
+  store_transposed<kSH, kSH, kHP>(H1s, op.h1, r0, tid);
   tr_layer<kSH / 16>(H1s, kHP, wf, col, half, acc);
   // the output layer's fragments (k chunks 4 wave .. 4 wave + 3) and the
   // backward pass's W3 and W2 fragments, in flight during the output layer
@@ -586,7 +626,7 @@ __global__ __launch_bounds__(256, 1) void sur_train_rows_kernel(int B, float gsc
   load_wfrags<kSH / 16>(WbT + kTW2, n0 / 32, lane, wf);
   tr_silu(acc, Bs + kSH, H2s, n0, col, half, d2);
   __syncthreads();
-  store_transposed(H2s, kHP, kSH, op.h2, op.ld, r0, tid);
+  store_transposed<kSH, kSH, kHP>(H2s, op.h2, r0, tid);
   {
     // output layer, transposed (outputs 8(i/4) + 4half + i%4, 16 of 32 used):
     // wave w sums k chunks 4w .. 4w + 3
@@ -619,18 +659,7 @@ __global__ __launch_bounds__(256, 1) void sur_train_rows_kernel(int B, float gsc
     }
   }
   __syncthreads();
-  store_transposed(Gys, kGyP, kSOutP, op.gy, op.ld, r0, tid);
-  if (wave == 0 && lane < kSOutP) {
-    float s = 0.f;
-    for (int m = 0; m < kTR; ++m) s += Ts[m][lane];
-    bp[2 * kSH + lane] = s;
-  } else if (wave == 1) {
-    float s = 0.f;
-    for (int q = lane; q < kTR * kSOutP; q += 64) s += Es[q / kSOutP][q % kSOutP];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-    if (lane == 0) bp[kBiasN] = s;
-  }
+  store_transposed<kSOutP, kGT, kGyP>(Gys, op.gy, r0, tid);
   // gH2 = rnd(gY) W3, transposed (K = the 16 outputs), then gZ2
   {
     const sbf16x8 gf = *reinterpret_cast<const sbf16x8*>(Gys + col * kGyP + half * 8);
@@ -644,34 +673,39 @@ __global__ __launch_bounds__(256, 1) void sur_train_rows_kernel(int B, float gsc
   tr_grad_out(acc, d2, Fs, H2s, n0, col, half);
   __syncthreads();
   bp[kSH + tid] = col_sum32(Fs, tid);
-  store_transposed(H2s, kHP, kSH, op.g2, op.ld, r0, tid);
+  store_transposed<kSH, kSH, kHP>(H2s, op.g2, r0, tid);
   // gH1 = rnd(gZ2) W2, transposed, then gZ1
   tr_layer<kSH / 16>(H2s, kHP, wf, col, half, acc);
   __syncthreads();  // every thread is done reading gZ2 from Fs
   tr_grad_out(acc, d1, Fs, H1s, n0, col, half);
   __syncthreads();
   bp[tid] = col_sum32(Fs, tid);
-  store_transposed(H1s, kHP, kSH, op.g1, op.ld, r0, tid);
+  store_transposed<kSH, kSH, kHP>(H1s, op.g1, r0, tid);
+  // b3 column sums and the squared error (Ts and Es are not written after
+  // the MSE step), last so that no wave waits for them at a barrier
+  if (wave == 0 && lane < kSOutP) {
+    float s = 0.f;
+    for (int m = 0; m < kTR; ++m) s += Ts[m][lane];
+    bp[2 * kSH + lane] = s;
+  } else if (wave == 1) {
+    float s = 0.f;
+    for (int q = lane; q < kTR * kSOutP; q += 64) s += Es[q / kSOutP][q % kSOutP];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (lane == 0) bp[kBiasN] = s;
+  }
 }
 
 // One wave's 64 x 64 partial of C = A^T B over rows [rb, re) (re - rb a
-// multiple of 64, at most 128) of the transposed operands A [m][ld] and
-// B [n][ld]: A1 / B1 whether the second 32-row block of A / B exists, A16
-// whether A has only 16 rows (lanes 16 .. 31 then read row col - 16 and use
-// zero). Within each 64-row block, k step s of lane half h covers rows
-// 32h + 8s .. 32h + 8s + 7 (one permutation of the block's rows for both
-// operands), so a lane's four loads per operand row read 64 contiguous bytes
-// and a wave uses each 128-byte line it touches whole; both blocks' loads are
-// issued before the first product.
-template <bool A1, bool B1, bool A16>
-__device__ __forceinline__ void wgrad_tile(const uint16_t* __restrict__ Aop, const uint16_t* __restrict__ Bop,
-                                           int ld, int rb, int re, int col, int half, sf32x16 (&acc)[2][2]) {
+// multiple of 64, at most 128) of two operands in fragment order: A's
+// feature blocks fa, fa + 1 (of nfa), B's fb, fb + 1 (of nfb); A1 / B1
+// whether the second block is used. Every fragment is one contiguous 1 KB
+// run, and both 64-row blocks' loads are issued before the first product.
+template <bool A1, bool B1>
+__device__ __forceinline__ void wgrad_tile(const uint16_t* __restrict__ A, int fa, int nfa,
+                                           const uint16_t* __restrict__ B, int fb, int nfb, int rb, int re, int lane,
+                                           sf32x16 (&acc)[2][2]) {
   const sbf16x8 zero = {};
-  const uint16_t* pa0 = Aop + (size_t)(A16 ? (col & 15) : col) * ld + 32 * half;
-  const uint16_t* pa1 = Aop + (size_t)(32 + col) * ld + 32 * half;
-  const uint16_t* pb0 = Bop + (size_t)col * ld + 32 * half;
-  const uint16_t* pb1 = Bop + (size_t)(32 + col) * ld + 32 * half;
-  const bool a0ok = !A16 || col < 16;
   sbf16x8 fa0[2][4], fa1[2][4], fb0[2][4], fb1[2][4];
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
@@ -681,15 +715,16 @@ __device__ __forceinline__ void wgrad_tile(const uint16_t* __restrict__ Aop, con
     const bool in = q == 0 || rb + 64 * q < re;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      fa0[q][s] = *reinterpret_cast<const sbf16x8*>(pa0 + k0 + 8 * s);
-      fb0[q][s] = *reinterpret_cast<const sbf16x8*>(pb0 + k0 + 8 * s);
-      if (A1) fa1[q][s] = *reinterpret_cast<const sbf16x8*>(pa1 + k0 + 8 * s);
-      if (B1) fb1[q][s] = *reinterpret_cast<const sbf16x8*>(pb1 + k0 + 8 * s);
+      const int kb = (k0 >> 4) + s;
+      fa0[q][s] = *reinterpret_cast<const sbf16x8*>(A + op_block(kb, fa, nfa) + lane * 8);
+      fb0[q][s] = *reinterpret_cast<const sbf16x8*>(B + op_block(kb, fb, nfb) + lane * 8);
+      if (A1) fa1[q][s] = *reinterpret_cast<const sbf16x8*>(A + op_block(kb, fa + 1, nfa) + lane * 8);
+      if (B1) fb1[q][s] = *reinterpret_cast<const sbf16x8*>(B + op_block(kb, fb + 1, nfb) + lane * 8);
     }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      fa0[q][s] = (in && a0ok) ? fa0[q][s] : zero;
+      fa0[q][s] = in ? fa0[q][s] : zero;
       fb0[q][s] = in ? fb0[q][s] : zero;
       if (A1) fa1[q][s] = in ? fa1[q][s] : zero;
       if (B1) fb1[q][s] = in ? fb1[q][s] : zero;
@@ -710,10 +745,24 @@ __device__ __forceinline__ void wgrad_tile(const uint16_t* __restrict__ Aop, con
 // gW2 = rnd(gZ2)^T H1, gW1 = rnd(gZ1)^T z, gW3 = rnd(gY)^T H2 over rows
 // [512 c, 512 c + 512) of the Bp rows: workgroup (tile, c), wave w takes 128
 // of the rows, the four waves' 64 x 64 tiles summed in LDS in wave order.
-// FP32 partials into wpart[c][padded parameter index].
-__global__ __launch_bounds__(256, 2) void sur_train_wgrad_kernel(int Bp, TrainOps op, float* __restrict__ wpart) {
+// FP32 partials into wpart[c][padded parameter index]. Workgroups go to the
+// eight XCDs in turn (workgroup L on XCD L % 8); with a multiple of 8
+// chunks, all 24 tiles of chunk c are placed on XCD c % 8, so the chunk's
+// operand rows are read from memory once into that XCD's L2 and the other
+// tiles that share them hit there.
+__global__ __launch_bounds__(256, 2) void sur_train_wgrad_kernel(int Bp, int nchunk, TrainOps op,
+                                                                 float* __restrict__ wpart) {
   __shared__ float Red[4][64 * 65];
-  const int t = blockIdx.x, chunk = blockIdx.y;
+  const int L = blockIdx.x;
+  int t, chunk;
+  if (nchunk % 8 == 0) {
+    const int xcd = L % 8, slot = L / 8;
+    chunk = xcd + 8 * (slot / kWTiles);
+    t = slot % kWTiles;
+  } else {
+    t = L % kWTiles;
+    chunk = L / kWTiles;
+  }
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int col = lane & 31, half = lane >> 5;
   sf32x16 acc[2][2];
@@ -730,16 +779,13 @@ __global__ __launch_bounds__(256, 2) void sur_train_wgrad_kernel(int Bp, TrainOp
   if (t < 16) {
     out = kPW2 + (t / 4) * 64 * kSH + (t % 4) * 64; out_ld = kSH; m_lim = 64; n_lim = 64;
     if (rb < re)
-      wgrad_tile<true, true, false>(op.g2 + (size_t)(t / 4) * 64 * op.ld, op.h1 + (size_t)(t % 4) * 64 * op.ld,
-                                    op.ld, rb, re, col, half, acc);
+      wgrad_tile<true, true>(op.g2, 2 * (t / 4), kSH / 32, op.h1, 2 * (t % 4), kSH / 32, rb, re, lane, acc);
   } else if (t < 20) {
     out = kPW1 + (t - 16) * 64 * kSInP; out_ld = kSInP; m_lim = 64; n_lim = kSInP;
-    if (rb < re)
-      wgrad_tile<true, false, false>(op.g1 + (size_t)(t - 16) * 64 * op.ld, op.xt, op.ld, rb, re, col, half, acc);
+    if (rb < re) wgrad_tile<true, false>(op.g1, 2 * (t - 16), kSH / 32, op.xt, 0, kXT / 32, rb, re, lane, acc);
   } else {
     out = kPW3 + (t - 20) * 64; out_ld = kSH; m_lim = kSOutP; n_lim = 64;
-    if (rb < re)
-      wgrad_tile<false, true, true>(op.gy, op.h2 + (size_t)(t - 20) * 64 * op.ld, op.ld, rb, re, col, half, acc);
+    if (rb < re) wgrad_tile<false, true>(op.gy, 0, kGT / 32, op.h2, 2 * (t - 20), kSH / 32, rb, re, lane, acc);
   }
   // C[m][n]: lane (col = n % 32, half) holds m = 32a + 8(i/4) + 4half + i%4
 #pragma unroll
@@ -793,43 +839,68 @@ struct TrainUpdate {
   uint16_t *Wb, *WbT;
 };
 
-// blocks [0, nw): one weight element per thread; then one wave per bias
-// element (and one for the loss) summing the row workgroups' column sums
-__global__ __launch_bounds__(256) void sur_train_update_kernel(TrainUpdate u) {
-  constexpr int nw = (kPEnd + 255) / 256;
-  int e;
-  float g;
-  if (blockIdx.x < nw) {
-    e = blockIdx.x * 256 + threadIdx.x;
-    if (e >= kPEnd || is_bias_index(e)) return;
-    g = 0.f;
-    for (int c = 0; c < u.nchunk; ++c) g += u.wpart[(size_t)c * kPEnd + e];
-  } else {
-    const int lane = threadIdx.x & 63;
-    const int j = (blockIdx.x - nw) * 4 + (threadIdx.x >> 6);
-    if (j > kBiasN) return;
-    float s = 0.f;
-    for (int w = lane; w < u.nwg; w += 64) s += u.bpart[(size_t)w * kBP + j];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-    if (lane != 0) return;
-    if (j == kBiasN) {
-      if (u.loss) u.loss[0] = s / ((float)u.B * kSOut);
-      return;
-    }
-    e = j < kSH ? kPB1 + j : j < 2 * kSH ? kPB2 + (j - kSH) : kPB3 + (j - 2 * kSH);
-    g = s;
-  }
+// gradient g of padded parameter e: written out, or one Adam step from the
+// current weight and moments (w, m, v) with the new BF16 fragments
+__device__ __forceinline__ void sur_finish_param(const TrainUpdate& u, int e, float g, float w, float m, float v) {
   if (u.G) {
     u.G[e] = g;
     return;
   }
-  float w = u.P[e], m = u.m[e], v = u.v[e];
   adam_update(w, g, m, v, u.lr, u.b1, u.b2, u.eps, u.c1, u.c2);
   u.P[e] = w;
   u.m[e] = m;
   u.v[e] = v;
   if (!is_bias_index(e)) store_weight_frags(e, w, u.Wb, u.WbT);
+}
+
+// blocks [0, nw): one weight element per thread; then one wave per bias
+// element (and one for the loss) summing the row workgroups' column sums
+__global__ __launch_bounds__(256) void sur_train_update_kernel(TrainUpdate u) {
+  constexpr int nw = (kPEnd + 255) / 256;
+  if (blockIdx.x < nw) {
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= kPEnd || is_bias_index(e)) return;
+    float w = 0.f, m = 0.f, v = 0.f;
+    if (!u.G) {
+      w = u.P[e];
+      m = u.m[e];
+      v = u.v[e];
+    }
+    // the chunks' partials in chunk order; each group of 8 loads is issued
+    // at once (indices clamped into range, surplus loads not added)
+    float g = 0.f;
+    for (int c0 = 0; c0 < u.nchunk; c0 += 8) {
+      float p[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) p[q] = u.wpart[(size_t)min(c0 + q, u.nchunk - 1) * kPEnd + e];
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (c0 + q < u.nchunk) g += p[q];
+    }
+    sur_finish_param(u, e, g, w, m, v);
+    return;
+  }
+  const int lane = threadIdx.x & 63;
+  const int j = (blockIdx.x - nw) * 4 + (threadIdx.x >> 6);
+  if (j > kBiasN) return;
+  float s = 0.f;
+  for (int w0 = lane; w0 < u.nwg; w0 += 4 * 64) {
+    float p[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) p[q] = u.bpart[(size_t)min(w0 + 64 * q, u.nwg - 1) * kBP + j];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (w0 + 64 * q < u.nwg) s += p[q];
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if (lane != 0) return;
+  if (j == kBiasN) {
+    if (u.loss) u.loss[0] = s / ((float)u.B * kSOut);
+    return;
+  }
+  const int e = j < kSH ? kPB1 + j : j < 2 * kSH ? kPB2 + (j - kSH) : kPB3 + (j - 2 * kSH);
+  sur_finish_param(u, e, s, u.G ? 0.f : u.P[e], u.G ? 0.f : u.m[e], u.G ? 0.f : u.v[e]);
 }
 
 // Pseudo-random permutation of [0, N) for minibatch order: a balanced
@@ -904,7 +975,8 @@ static int sur_train_step(surrogate_handle* h, int B, const int32_t* perm, const
   hipLaunchKernelGGL(sur_train_rows_kernel, dim3(nwg), dim3(256), 0, st, B, 2.f / ((float)B * kSOut), perm, x, d,
                      norm, h->P, h->Wb, h->WbT, h->ops, h->bpart);
   DA_LAUNCH_CHECK("sur_train_rows_kernel");
-  hipLaunchKernelGGL(sur_train_wgrad_kernel, dim3(kWTiles, nchunk), dim3(256), 0, st, Bp, h->ops, h->wpart);
+  hipLaunchKernelGGL(sur_train_wgrad_kernel, dim3(kWTiles * nchunk), dim3(256), 0, st, Bp, nchunk, h->ops,
+                     h->wpart);
   DA_LAUNCH_CHECK("sur_train_wgrad_kernel");
   u.nchunk = nchunk;
   u.nwg = nwg;
@@ -945,7 +1017,7 @@ int surrogate_create(int32_t max_batch, surrogate_handle** out) {
   add(&h->ops.xt, L * kXT * 2);
   add(&h->ops.h1, L * kSH * 2);
   add(&h->ops.h2, L * kSH * 2);
-  add(&h->ops.gy, L * kSOutP * 2);
+  add(&h->ops.gy, L * kGT * 2);
   add(&h->ops.g2, L * kSH * 2);
   add(&h->ops.g1, L * kSH * 2);
   h->ops.ld = ld;
