@@ -413,13 +413,20 @@ __global__ void split_rows_kernel(int R, int K, const float* __restrict__ src, i
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= R * q) return;
   const int r = idx / q, k = (idx % q) * 8;
+  const float* row = src + (size_t)r * ld + k;
+  float v[8];
+  if (k + 8 <= K && ((reinterpret_cast<uintptr_t>(row) & 15) == 0)) {
+    // a whole aligned run: two 16-byte loads
+    const float4 u0 = reinterpret_cast<const float4*>(row)[0], u1 = reinterpret_cast<const float4*>(row)[1];
+    v[0] = u0.x; v[1] = u0.y; v[2] = u0.z; v[3] = u0.w;
+    v[4] = u1.x; v[5] = u1.y; v[6] = u1.z; v[7] = u1.w;
+  } else {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = k + j < K ? row[j] : 0.f;
+  }
   uint32_t hp[4], lp[4];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const float a = k + 2 * j < K ? src[(size_t)r * ld + k + 2 * j] : 0.f;
-    const float b = k + 2 * j + 1 < K ? src[(size_t)r * ld + k + 2 * j + 1] : 0.f;
-    split2(a, b, hp[j], lp[j]);
-  }
+  for (int j = 0; j < 4; ++j) split2(v[2 * j], v[2 * j + 1], hp[j], lp[j]);
   *reinterpret_cast<uint4*>(hi + (size_t)r * ldo + k) = make_uint4(hp[0], hp[1], hp[2], hp[3]);
   *reinterpret_cast<uint4*>(lo + (size_t)r * ldo + k) = make_uint4(lp[0], lp[1], lp[2], lp[3]);
 }
@@ -650,15 +657,24 @@ __global__ void splitk_bias_tanh_kernel(int S, int M, int N, int ldp, const floa
   const int nq = N >> 2;
   if (idx >= M * nq) return;
   const int m = idx / nq, n = (idx % nq) * 4;
-  float4 v = *reinterpret_cast<const float4*>(part + (size_t)m * ldp + n);
-  for (int s = 1; s < S; ++s) {
-    const float4 w = *reinterpret_cast<const float4*>(part + (size_t)s * M * ldp + (size_t)m * ldp + n);
-    v.x += w.x;
-    v.y += w.y;
-    v.z += w.z;
-    v.w += w.w;
-  }
   const float4 b = *reinterpret_cast<const float4*>(bias + n);
+  float4 v = *reinterpret_cast<const float4*>(part + (size_t)m * ldp + n);
+  // the partials in split order; each group of four loads is issued at once
+  // (split index clamped into range, surplus loads not added)
+  for (int s0 = 1; s0 < S; s0 += 4) {
+    float4 w[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      w[q] = *reinterpret_cast<const float4*>(part + (size_t)min(s0 + q, S - 1) * M * ldp + (size_t)m * ldp + n);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (s0 + q < S) {
+        v.x += w[q].x;
+        v.y += w[q].y;
+        v.z += w[q].z;
+        v.w += w[q].w;
+      }
+  }
   *reinterpret_cast<float4*>(out + (size_t)m * ldo + n) =
       make_float4(tanhf(v.x + b.x), tanhf(v.y + b.y), tanhf(v.z + b.z), tanhf(v.w + b.w));
 }
@@ -751,6 +767,13 @@ __global__ __launch_bounds__(256) void narrow_fwd_kernel(int B, int J, int O, co
                                                          const float* __restrict__ bias, float* __restrict__ Y) {
   const int lane = threadIdx.x & 63;
   const int b0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * kNarrowRows;
+  // the first 256 columns of all the wavefront's rows requested at once (the
+  // common case J = 256 then needs no further loads of H)
+  float4 x0[kNarrowRows];
+#pragma unroll
+  for (int r = 0; r < kNarrowRows; ++r)
+    x0[r] = (b0 + r < B && 4 * lane < J) ? *reinterpret_cast<const float4*>(H + (size_t)(b0 + r) * ldh + 4 * lane)
+                                         : make_float4(0.f, 0.f, 0.f, 0.f);
   for (int r = 0; r < kNarrowRows; ++r) {
     const int b = b0 + r;
     if (b >= B) break;
@@ -758,7 +781,7 @@ __global__ __launch_bounds__(256) void narrow_fwd_kernel(int B, int J, int O, co
 #pragma unroll
     for (int o = 0; o < 8; ++o) acc[o] = 0.f;
     for (int j = 4 * lane; j < J; j += 256) {
-      const float4 x = *reinterpret_cast<const float4*>(H + (size_t)b * ldh + j);
+      const float4 x = j == 4 * lane ? x0[r] : *reinterpret_cast<const float4*>(H + (size_t)b * ldh + j);
 #pragma unroll
       for (int o = 0; o < 8; ++o)
         if (o < O) {
@@ -797,20 +820,31 @@ __global__ __launch_bounds__(256) void narrow_bwd_kernel(int J, int O, int nb, c
                                                          const float* __restrict__ H, int ldh,
                                                          float* __restrict__ gZ3, float* __restrict__ gZ2) {
   const int b = blockIdx.x / nb, j = (blockIdx.x % nb) * 256 + threadIdx.x;
-  float acc = 0.f;
-  for (int o = 0; o < O; ++o) {
-    const float y = Y[b * O + o];
-    const float gz = gY[b * O + o] * (1.f - y * y);
-    if (j < J) acc += gz * W[o * J + j];
-    if (j == 0) gZ3[b * O + o] = gz;
+  // every load of the row issued before the sums (O <= 8; outputs in order)
+  const float h = j < J ? H[(size_t)b * ldh + j] : 0.f;
+  float y[8], g[8], w[8];
+#pragma unroll
+  for (int o = 0; o < 8; ++o) {
+    const bool in = o < O;
+    y[o] = in ? Y[b * O + o] : 0.f;
+    g[o] = in ? gY[b * O + o] : 0.f;
+    w[o] = (in && j < J) ? W[o * J + j] : 0.f;
   }
+  float acc = 0.f;
+#pragma unroll
+  for (int o = 0; o < 8; ++o)
+    if (o < O) {
+      const float gz = g[o] * (1.f - y[o] * y[o]);
+      if (j < J) acc += gz * w[o];
+      if (j == 0) gZ3[b * O + o] = gz;
+    }
   if (j >= J) return;
-  const float h = H[(size_t)b * ldh + j];
   gZ2[(size_t)b * ldh + j] = acc * (1.f - h * h);
 }
 
 int launch_narrow_bwd(int B, int J, int O, const float* gY, const float* Y, const float* W,
                       const float* H, int ldh, float* gZ3, float* gZ2, hipStream_t st) {
+  if (O > 8) return fail(SIM_EINVAL, "narrow_bwd: O <= 8");
   if (B == 0 || J == 0) return SIM_OK;
   const int nb = cdiv(J, 256);
   hipLaunchKernelGGL(narrow_bwd_kernel, dim3((unsigned)((int64_t)B * nb)), dim3(256), 0, st, J, O, nb, gY, Y, W, H,
