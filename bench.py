@@ -50,7 +50,7 @@ def parse():
     p.add_argument("--recompute-all", action="store_true",
                    help="keep only the K-step state checkpoints (recompute policy and step too)")
     p.add_argument("--policy-gemm", choices=["fp32", "bf16x3"], default="bf16x3",
-                   help="policy layers on FP32 MFMA, or FP32 recovered from three BF16 MFMA products")
+                   help="policy layers on FP32 MFMA, or approximated by three BF16 MFMA products of a hi / lo split (about 2^-16 relative error per product, against 2^-24 for FP32)")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                    help="also run a plain device copy of MIB MiB (for HBM counter scaling)")
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -778,7 +778,7 @@ def cpu_baseline(model, seed=0, n_envs=256, T=32, n_envs_1t=16, T_1t=8):
                       f"backward"}
 
 
-GEMM_DTYPE = {"fp32": "f32", "bf16x3": "f32 (policy GEMMs bf16x3: three BF16 products per FP32 product)"}
+GEMM_DTYPE = {"fp32": "f32", "bf16x3": "bf16x3 policy GEMMs (three BF16 products per product, ~2^-16 relative), f32 elsewhere"}
 
 
 RENDER_THREADS = [256]

@@ -350,9 +350,10 @@ int sim_step_backward(sim_handle* h, const float* s_t, const float* a_t, const f
  */
 #define POLICY_N_PARAMS 855812
 /* Arithmetic of the policy's dense layers: FP32 operands on the FP32 matrix
- * cores, or the FP32 product recovered from three BF16 products of a hi / lo
- * split of each operand (Ootomo & Yokota 2022; relative error ~1e-5, FP32
- * accumulation) on the BF16 matrix cores, which run 16x faster on gfx950. */
+ * cores, or an approximation of the FP32 product by three BF16 products of a
+ * hi / lo split of each operand (Ootomo & Yokota 2022; the lo * lo term is
+ * dropped, about 2^-16 relative error per product against 2^-24 for FP32;
+ * FP32 accumulation) on the BF16 matrix cores, which run 16x faster on gfx950. */
 enum { POLICY_GEMM_FP32 = 0, POLICY_GEMM_BF16X3 = 1 };
 
 typedef struct bptt_config {
