@@ -312,6 +312,20 @@ def uneven_section(T=128, reps=3, seed=0):
                      "agent_steps_per_s": round(A * T / dt, 1),
                      "rays_per_s": round(A * T * (3072 + 5760) / dt, 1)}
     out["fused_over_plain"] = round(out["plain"]["ms_per_rollout"] / out["fused_graph"]["ms_per_rollout"], 3)
+    # roofline of the fused rollout: the ray-cast FLOPs of one camera and one
+    # LiDAR render, counted by the renderer's work counters at the start states
+    # (the per-step work changes as the agents move), times T, over the
+    # rollout time; the dynamics' FLOPs (< 1 %) are left out
+    flops, counts = 0, {}
+    for sensor, name in ((0, "camera"), (1, "lidar")):
+        f, c = render_work_flops(e, s0, term=False, sensor=sensor)
+        flops += f
+        counts[name] = c
+    ach = flops * T / (out["fused_graph"]["ms_per_rollout"] * 1e-3)
+    out["fused_graph"]["roofline"] = {"bound": "alu", "achieved": round(ach / 1e12, 2), "peak": PEAK_FP32_VALU / 1e12,
+                                      "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_VALU, 4),
+                                      "frac_of_nonpacked_fp32": round(ach / PEAK_FP32_VALU_NONPACKED, 4),
+                                      "flops_per_step": flops, "work_per_step_at_start": counts}
 
     # the same rollout with the task layer after every step: images at the
     # stepped state, rewards, termination (collision, non-finite), truncation
@@ -564,15 +578,17 @@ def surrogate_train_section(seed=0, R=4, epochs=2, batch=8192):
                          "kernels": "sur_train_rows_kernel, sur_train_wgrad_kernel, sur_train_update_kernel"}}
 
 
-def render_work_flops(e, s, term):
-    """Algorithmic FLOPs of one camera render at state s: the ray and test
-    counts come from sim_render_work (the same kernel with counters)."""
+def render_work_flops(e, s, term, sensor=0):
+    """Algorithmic FLOPs of one render of `sensor` (0 camera, 1 LiDAR) at
+    state s: the ray and test counts come from sim_render_work (the same
+    kernel with counters)."""
     import torch
     from paper_2509_10247_amd import _lib
     A = e.n_agents
-    out = torch.empty(A, e.cam[1] * e.cam[0], device="cuda")
+    nr = e.cam[1] * e.cam[0] if sensor == 0 else e.lidar[0] * e.lidar[1]
+    out = torch.empty(A, nr, device="cuda")
     work = torch.zeros(A, 4, 7, dtype=torch.int32, device="cuda")
-    _lib.sim_render_work(e.h, 0, s, out, work)
+    _lib.sim_render_work(e.h, sensor, s, out, work)
     w = work.long().sum((0, 1)).tolist()
     c = dict(zip(_lib.WORK_FIELDS, w))
     f = RENDER_FLOP
