@@ -124,6 +124,16 @@ def test_shuffle_is_a_seeded_permutation(N):
         assert abs(r) < 0.1
 
 
+def test_shuffle_edges():
+    """N = 0 writes nothing; N beyond the int32 index range is refused."""
+    from paper_2509_10247_amd import _lib
+    a = torch.full((4,), -7, dtype=torch.int32, device="cuda")
+    _lib.surrogate_shuffle(0, 1, a)
+    assert torch.equal(a, torch.full_like(a, -7))
+    with pytest.raises(RuntimeError):
+        _lib.surrogate_shuffle(2**31, 1, a)
+
+
 def test_norm_matches_column_moments():
     from paper_2509_10247_amd import surrogate
     wk, e, x, d = _data(A=700, T=3)
