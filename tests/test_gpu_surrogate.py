@@ -48,14 +48,16 @@ def test_pack_rows_match_oracle_residual():
     assert torch.allclose(f64(d)[:300], full - nom, atol=2e-5)
 
 
-@pytest.mark.parametrize("B,A", [(300, 512), (2080, 600)])
+@pytest.mark.parametrize("B,A", [(300, 512), (2080, 600), (8192, 2100)])
 def test_surrogate_gradient_matches_bf16_oracle(B, A):
     """Ragged batches: 300 rows end inside a 32-row workgroup, 2080 rows span
-    five 512-row chunks of the weight-gradient kernel, the last one short."""
+    five 512-row chunks of the weight-gradient kernel, the last one short;
+    the training batch of 8192 rows gives 16 chunks, whose tiles the kernel
+    groups per XCD."""
     from paper_2509_10247_amd import surrogate
     wk, e, x, d = _data(A=A)
     print_case("surrogate_grad", B=B)
-    sur = surrogate.Surrogate(max_batch=4096)
+    sur = surrogate.Surrogate(max_batch=8192)
     norm = sur.fit_normalizer(x, d)
     theta = wl.flatten_mlp(wl.mlp_init(np.random.default_rng(3), wl.SURROGATE_DIMS))
     g, loss = sur.grad(cuda(theta), x, d, B)
