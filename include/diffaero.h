@@ -259,7 +259,7 @@ int sim_render_work(sim_handle* h, int32_t sensor, const float* s, float* out, i
  * Either output nullable. */
 int sim_collide(sim_handle* h, const float* s, uint8_t* flags, float* min_dist, void* stream);
 
-/* IMU with configurable noise and drift (Sec. III-B; the paper gives no
+/* IMU with settable noise and drift (Sec. III-B; the paper gives no
  * noise model, so this one is a reading): for the rigid-body models
  * (SIM_RB13, SIM_NOMINAL13) the accelerometer reads the body-frame specific
  * force f = R^T (dv/dt - g) of the model at (s, a) over the step, i.e.
