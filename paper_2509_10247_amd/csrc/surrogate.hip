@@ -364,10 +364,10 @@ __global__ __launch_bounds__(256, 4) void sur_step_kernel(int A, float dt, int t
 //  1. sur_train_rows_kernel, one workgroup per 32 rows: gathers and z-scores
 //     the rows, runs the three layers, the MSE gradient and the backward pass
 //     down to both hidden pre-activation gradients in LDS and registers, and
-//     writes the BF16 operands of the weight gradients transposed, one
-//     feature per row ([feature][row]: z, H1, H2, rnd(gY), rnd(gZ2),
-//     rnd(gZ1)) in MFMA fragment order (below), with the workgroup's FP32
-//     bias-gradient column sums and squared error.
+//     writes the BF16 operands of the weight gradients (z, H1, H2, rnd(gY),
+//     rnd(gZ2), rnd(gZ1)) with the rows as the contiguous dimension, in the
+//     MFMA fragment order below, and the workgroup's FP32 bias-gradient
+//     column sums and squared error.
 //  2. sur_train_wgrad_kernel: the weight gradients gW = rnd(g)^T h summed
 //     over the rows, 64 x 64 output tiles x 512-row chunks, FP32 partials.
 //  3. sur_train_update_kernel: the partials summed in a fixed order, then
