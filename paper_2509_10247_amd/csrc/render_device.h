@@ -17,7 +17,8 @@ struct RenderLds {
   float2* pd;  // (rho, L - rho); rho < 0: never hit
   short* lists;
   int* flag;
-  float4* ax;  // per tile of the call: (world cone axis, cos of the half-angle)
+  float4* ax;  // per tile of the call, two entries: (world cone axis, cos of the
+               // half-angle), then (sin of the half-angle, range limit, 0, 0)
   int P;       // primitive capacity (stride of the per-wave lists)
 };
 
@@ -35,10 +36,10 @@ __device__ __forceinline__ RenderLds carve(void* base, int P) {
 }
 
 // P primitives (48 + 8 B each, 4 per-wave index lists of 2 B each), the flag
-// word and the rotated cone axes of up to T tiles.
+// word and the cones of up to T tiles (rotated axis and angle, 32 B each).
 inline size_t render_lds_bytes(int P, int T) {
   static_assert(3 * sizeof(float4) + sizeof(float2) + 4 * sizeof(short) == 64, "render LDS layout");
-  return 64 * (size_t)P + 32 + 16 * (size_t)T;
+  return 64 * (size_t)P + 32 + 2 * sizeof(float4) * (size_t)T;
 }
 
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
@@ -382,7 +383,8 @@ __device__ __forceinline__ void render_tiles(const AgentStage& ag, const SensorD
     for (int tt = tid; tt < tile_end - tile_begin; tt += NT) {
       const float4 ca = sen.cone_a[tile_begin + tt];
       const f3 ax = ROT ? rot_apply(R, mk3(ca.x, ca.y, ca.z)) : mk3(ca.x, ca.y, ca.z);
-      L.ax[tt] = make_float4(ax.x, ax.y, ax.z, ca.w);
+      L.ax[2 * tt] = make_float4(ax.x, ax.y, ax.z, ca.w);
+      L.ax[2 * tt + 1] = sen.cone_b[tile_begin + tt];
     }
   __syncthreads();
   const int nr = sen.n_rays;
@@ -399,30 +401,21 @@ __device__ __forceinline__ void render_tiles(const AgentStage& ag, const SensorD
   const float inv_beta = term ? 1.0f / beta : 0.f;
   int wk[kWorkN] = {0, 0, 0, 0, 0, 0, 0};
 
-  // the next tile's ray index and direction are loaded while this tile is
-  // processed (ray index two tiles ahead, direction one tile ahead)
-  int r_n = tile_begin + wave < tile_end ? sen.tile_rays[(tile_begin + wave) * kTileRays + lane] : -1;
-  float4 db_n = r_n >= 0 ? sen.dirs[r_n] : make_float4(0.f, 0.f, 0.f, 0.f);
-  int r_nn = tile_begin + wave + NW < tile_end ? sen.tile_rays[(tile_begin + wave + NW) * kTileRays + lane] : -1;
-  for (int tile = tile_begin + wave; tile < tile_end; tile += NW) {
-    const int ta = NW == 4 ? 0 : ((tile - tile_begin) >> 1) & 1;  // this tile's term sum
-    const int r = r_n;
-    const float4 db = db_n;
-    r_n = r_nn;
-    db_n = r_n >= 0 ? sen.dirs[r_n] : make_float4(0.f, 0.f, 0.f, 0.f);
-    r_nn = tile + 2 * NW < tile_end ? sen.tile_rays[(tile + 2 * NW) * kTileRays + lane] : -1;
+  // one 64-ray tile: cull, cast, write the row entries and add the term
+  // summands to tsum (the sum of this tile's residue)
+  auto cast_tile = [&](int tile, int r, const float4 db, float& tsum) {
     if (inside) {
       if (r >= 0) {
         orow[r] = 0.f;
         if (rrow) rrow[r] = -2;
-        if (term) tacc[ta] += softplus_fast(beta * d_safe);
+        if (term) tsum += softplus_fast(beta * d_safe);
       }
-      continue;
+      return;
     }
     int ks = ns, kb = nb, kc = nc, nk = np;
     if (CULL) {
-      const float4 ca = L.ax[tile - tile_begin];
-      const float4 cb = sen.cone_b[tile];
+      const float4 ca = L.ax[2 * (tile - tile_begin)];
+      const float4 cb = L.ax[2 * (tile - tile_begin) + 1];
       const f3 ax = mk3(ca.x, ca.y, ca.z);
       int cnt = 0, cs = 0, cbx = 0, ccy = 0;
       for (int base = 0; base < np; base += 64) {
@@ -457,7 +450,7 @@ __device__ __forceinline__ void render_tiles(const AgentStage& ag, const SensorD
       wk[kWorkTiles] += 1;
       wk[kWorkCone] += CULL ? np : 0;
     }
-    if (r < 0) continue;
+    if (r < 0) return;
     const f3 d = ROT ? rot_apply(R, mk3(db.x, db.y, db.z)) : mk3(db.x, db.y, db.z);
     const f3 inv = mk3(__builtin_amdgcn_rcpf(d.x), __builtin_amdgcn_rcpf(d.y), __builtin_amdgcn_rcpf(d.z));
     float best = kInf;
@@ -518,7 +511,29 @@ __device__ __forceinline__ void render_tiles(const AgentStage& ag, const SensorD
     }
     orow[r] = val * out_scale;
     if (rrow) rrow[r] = rc;
-    if (term) tacc[ta] += softplus_fast(beta * (d_safe - val));
+    if (term) tsum += softplus_fast(beta * (d_safe - val));
+  };
+
+  // each tile's ray index is loaded two tiles ahead and its direction one tile
+  // ahead; the loop body casts two tiles, this wavefront's j-th and (j + 1)-th
+  // (with two wavefronts, residues w and w + 2 mod 4), so the two register
+  // sets and term sums alternate without copies
+  auto ray_of = [&](int tile) { return tile < tile_end ? sen.tile_rays[tile * kTileRays + lane] : -1; };
+  auto dir_of = [&](int r) { return r >= 0 ? sen.dirs[r] : make_float4(0.f, 0.f, 0.f, 0.f); };
+  int ra = ray_of(tile_begin + wave);
+  float4 da = dir_of(ra);
+  int rb = ray_of(tile_begin + wave + NW);
+  for (int tile = tile_begin + wave; tile < tile_end; tile += 2 * NW) {
+    const float4 db = dir_of(rb);
+    const int ra_n = ray_of(tile + 2 * NW);
+    cast_tile(tile, ra, da, tacc[0]);
+    da = dir_of(ra_n);
+    ra = ra_n;
+    const int rb_n = ray_of(tile + 3 * NW);
+    // a guard, not a loop exit: a second exit would let the compiler fold the
+    // barriers after the loop into a loop of their own
+    if (tile + NW < tile_end) cast_tile(tile + NW, rb, db, tacc[NW == 4 ? 0 : 1]);
+    rb = rb_n;
   }
   if (WORK && lane == 0)
     for (int c = 0; c < kWorkN; ++c) work[((size_t)i * 4 + wave) * kWorkN + c] = wk[c];

@@ -95,8 +95,7 @@ constexpr bool rotates_m() {
 }
 
 // One agent work item: stage the agent's env, then its tiles [w.z, w.w) of
-// the combined camera-then-LiDAR tile range (one copy of the tile loop for
-// both sensors).
+// the combined camera-then-LiDAR tile range.
 // term (nullable): the camera part also writes the obstacle term
 // term[i] = mean over its rays of softplus(beta (d_safe - depth)) / beta
 // (the render's fused epilogue; the item must then cover all camera tiles).
@@ -109,6 +108,8 @@ __device__ __forceinline__ void agent_item(const RolloutArgs& g, int4 w, RenderL
   if (!SDF && w.z >= w.w) return;  // an agent without sensor tiles
   const AgentStage ag = stage_agent<ROT, CYL, SDF, NT>(g.sc, g.s, g.A, w.y, L, md_red);
   const int nc = g.depth ? g.cam.n_tiles : 0;
+  // unrolled: every barrier stays in the persistent loop itself
+#pragma unroll
   for (int part = 0; part < 2; ++part) {
     const int b = part ? max(w.z, nc) - nc : w.z, e = part ? w.w - nc : min(w.w, nc);
     if (b >= e) continue;
