@@ -539,26 +539,27 @@ __global__ __launch_bounds__(64, 8) void render_vjp_obs_kernel(SceneDev sc, Sens
   const float py = sen.pin_ya + (float)(tid % pw) * sen.pin_yd, py2 = 1.f + py * py;
   const float pzs = uniform_f((float)(kNT / pw) * sen.pin_zd);
   float pz = sen.pin_za + (float)(tid / pw) * sen.pin_zd;
-  int k_n = 0;
-  float g_n = 0.f, x_n = 0.f;
-  float4 db_n = make_float4(0.f, 0.f, 1.f, 1.f);
-  if ((unsigned)tid < unr) {
-    k_n = recrow[(unsigned)tid];
-    g_n = grow[(unsigned)tid];
-    x_n = xrow[(unsigned)tid];
-    if (!pin) db_n = sen.dirs[(unsigned)tid];
-  }
+  // one ray's record, gradient, observation and (table) direction; the
+  // 32-bit byte offset r * 4 from the three uniform row bases is one register
+  struct RayIn {
+    int k;
+    float g, x;
+    float4 db;
+  };
+  auto load = [&](unsigned r) {
+    const unsigned off = r * 4u;
+    RayIn v;
+    v.k = *reinterpret_cast<const int*>(reinterpret_cast<const char*>(recrow) + off);
+    v.g = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(grow) + off);
+    v.x = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(xrow) + off);
+    v.db = pin ? make_float4(0.f, 0.f, 1.f, 1.f) : sen.dirs[r];
+    return v;
+  };
   uint64_t gmask = 0;  // this lane's grazing rays (bit j: ray tid + j kNT)
-  for (unsigned r = tid; r < unr; r += kNT) {
-    const int k = k_n;
-    const float gin = g_n, x = x_n;
-    float4 db = db_n;
-    if (r + kNT < unr) {
-      k_n = recrow[r + kNT];
-      g_n = grow[r + kNT];
-      x_n = xrow[r + kNT];
-      if (!pin) db_n = sen.dirs[r + kNT];
-    }
+  auto cast_back = [&](unsigned r, const RayIn& in) {
+    const int k = in.k;
+    const float gin = in.g, x = in.x;
+    float4 db = in.db;
     if (pin) {
       const float inv = __builtin_amdgcn_rsqf(py2 + pz * pz);
       db = make_float4(inv, py * inv, pz * inv, inv);
@@ -614,6 +615,18 @@ __global__ __launch_bounds__(64, 8) void render_vjp_obs_kernel(SceneDev sc, Sens
 #pragma unroll
         for (int e = 0; e < 3; ++e) gR[a * 3 + e] += n3[a] * bb[e];
     }
+  };
+  // two rays per pass, each loaded one ray ahead, so the two register sets
+  // alternate without copies; past the last ray the loads are clamped to it
+  // rather than skipped (unused), so that no branch makes the compiler wait
+  // for the ray ahead along with the current one
+  RayIn ra = {0, 0.f, 0.f, make_float4(0.f, 0.f, 1.f, 1.f)}, rb = ra;
+  if ((unsigned)tid < unr) ra = load((unsigned)tid);
+  for (unsigned r = tid; r < unr; r += 2 * kNT) {
+    rb = load(min(r + kNT, unr - 1u));
+    cast_back(r, ra);
+    ra = load(min(r + 2 * kNT, unr - 1u));
+    if (r + kNT < unr) cast_back(r + kNT, rb);
   }
   // per-thread sums to LDS; the second pass adds the grazing sphere /
   // cylinder-side hits to them there, in ray order, so that the main loop's
