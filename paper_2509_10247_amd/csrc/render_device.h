@@ -44,6 +44,18 @@ inline size_t render_lds_bytes(int P, int T) {
 
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// Element idx of an array whose base is uniform over the wavefront, addressed
+// by a 32-bit byte offset: the base stays in scalar registers and one vector
+// register holds the offset (idx * sizeof(T) must stay below 2^32).
+template <typename T>
+__device__ __forceinline__ T& at32(T* base, unsigned idx) {
+  return *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + idx * (unsigned)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ const T& at32(const T* base, unsigned idx) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + idx * (unsigned)sizeof(T));
+}
+
 // softplus(x) = max(x, 0) + log(1 + exp(-|x|)) on the hardware exp2 / log2
 // units; the log2 argument lies in [1, 2], where the raw instruction needs no
 // range reduction.
@@ -406,8 +418,8 @@ __device__ __forceinline__ void render_tiles(const AgentStage& ag, const SensorD
   auto cast_tile = [&](int tile, int r, const float4 db, float& tsum) {
     if (inside) {
       if (r >= 0) {
-        orow[r] = 0.f;
-        if (rrow) rrow[r] = -2;
+        at32(orow, r) = 0.f;
+        if (rrow) at32(rrow, r) = -2;
         if (term) tsum += softplus_fast(beta * d_safe);
       }
       return;
@@ -509,8 +521,8 @@ __device__ __forceinline__ void render_tiles(const AgentStage& ag, const SensorD
       val = z;
       rc = id;
     }
-    orow[r] = val * out_scale;
-    if (rrow) rrow[r] = rc;
+    at32(orow, r) = val * out_scale;
+    if (rrow) at32(rrow, r) = rc;
     if (term) tsum += softplus_fast(beta * (d_safe - val));
   };
 
@@ -518,8 +530,8 @@ __device__ __forceinline__ void render_tiles(const AgentStage& ag, const SensorD
   // ahead; the loop body casts two tiles, this wavefront's j-th and (j + 1)-th
   // (with two wavefronts, residues w and w + 2 mod 4), so the two register
   // sets and term sums alternate without copies
-  auto ray_of = [&](int tile) { return tile < tile_end ? sen.tile_rays[tile * kTileRays + lane] : -1; };
-  auto dir_of = [&](int r) { return r >= 0 ? sen.dirs[r] : make_float4(0.f, 0.f, 0.f, 0.f); };
+  auto ray_of = [&](int tile) { return tile < tile_end ? at32(sen.tile_rays, tile * kTileRays + lane) : -1; };
+  auto dir_of = [&](int r) { return r >= 0 ? at32(sen.dirs, r) : make_float4(0.f, 0.f, 0.f, 0.f); };
   int ra = ray_of(tile_begin + wave);
   float4 da = dir_of(ra);
   int rb = ray_of(tile_begin + wave + NW);
