@@ -640,10 +640,12 @@ __global__ __launch_bounds__(64, 8) void render_vjp_obs_kernel(SceneDev sc, Sens
   for (int a = 0; a < 3; ++a)
 #pragma unroll
     for (int c = 0; c < 3; ++c) R64[a][c] = uniform_d(Rsh[a][c]);
-  while (gmask) {
-    const unsigned j = (unsigned)__builtin_ctzll(gmask);
-    gmask &= gmask - 1ull;
-    const unsigned r = tid + j * kNT;
+  // The grazing rays are dealt out one per lane: each pass, the lanes' pending
+  // rays (in lane order, each lane's in ray order) fill a list of 64, lane e
+  // takes entry e and adds its part to its own sums. One pass usually takes
+  // them all, where lanes walking their own rays would keep the wavefront
+  // waiting for the lane with the most.
+  auto graze = [&](const unsigned r) {
     const int k = recrow[r];
     const float depth = xrow[r] * ob.dmax;
     const float sig = __builtin_amdgcn_rcpf(1.f + __expf(nbeta * (ob.d_safe - depth)));
@@ -669,7 +671,7 @@ __global__ __launch_bounds__(64, 8) void render_vjp_obs_kernel(SceneDev sc, Sens
     f3 N;
     float nd, tt;
     const bool side = !(k < ns || k >= nsbc);  // cylinder: radial (x, y) part only
-    if (!grazing_normal64(dd, PR[k], side, o, N, nd, tt)) continue;
+    if (!grazing_normal64(dd, PR[k], side, o, N, nd, tt)) return;
     const float c = -gv * db.w * __builtin_amdgcn_rcpf(nd);
     red[0][tid] += c * N.x;
     red[1][tid] += c * N.y;
@@ -683,6 +685,26 @@ __global__ __launch_bounds__(64, 8) void render_vjp_obs_kernel(SceneDev sc, Sens
 #pragma unroll
         for (int e = 0; e < 3; ++e) red[3 + a * 3 + e][tid] += n3[a] * bb[e];
     }
+  };
+  __shared__ unsigned glist[kNT];
+  for (;;) {
+    const unsigned cnt = (unsigned)__popcll(gmask);
+    unsigned incl = cnt;  // inclusive prefix sum of the counts over the lanes
+#pragma unroll
+    for (int off = 1; off < kNT; off <<= 1) {
+      const unsigned v = __shfl_up(incl, off);
+      if (tid >= off) incl += v;
+    }
+    const unsigned total = __shfl(incl, kNT - 1);
+    if (total == 0) break;  // uniform: every lane holds the same total
+    for (unsigned pos = incl - cnt; gmask && pos < (unsigned)kNT; ++pos) {
+      const unsigned j = (unsigned)__builtin_ctzll(gmask);
+      gmask &= gmask - 1ull;
+      glist[pos] = tid + j * kNT;
+    }
+    __syncthreads();
+    if ((unsigned)tid < total) graze(glist[tid]);
+    __syncthreads();  // the list is read before the next pass fills it
   }
   // fixed-order reduction: 4 lanes per quantity each add 16 lanes' sums
   // (FP64), then one lane per quantity adds the 4 partials
