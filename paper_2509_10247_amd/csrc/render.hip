@@ -556,15 +556,17 @@ __global__ __launch_bounds__(64, 8) void render_vjp_obs_kernel(SceneDev sc, Sens
     return v;
   };
   uint64_t gmask = 0;  // this lane's grazing rays (bit j: ray tid + j kNT)
+  // A pinhole ray is taken unnormalised in the body frame, (1, py, pz), with
+  // u = R (1, py, pz) in the world: t d = depth u (t = depth / zfac and
+  // d = zfac u), N . d = zfac (N . u), so zfac cancels from c below, and
+  // d(loss)/dR = t (d(loss)/do) d_b^T = c depth N (1, py, pz)^T, whose py
+  // column is py times the first (py is fixed per lane), formed after the
+  // loop. Q = R (1, py, 0) per lane.
+  const f3 Q = ROT ? mk3(R.m[0][0] + py * R.m[0][1], R.m[1][0] + py * R.m[1][1], R.m[2][0] + py * R.m[2][1])
+                   : mk3(1.f, py, 0.f);
   auto cast_back = [&](unsigned r, const RayIn& in) {
     const int k = in.k;
     const float gin = in.g, x = in.x;
-    float4 db = in.db;
-    if (pin) {
-      const float inv = __builtin_amdgcn_rsqf(py2 + pz * pz);
-      db = make_float4(inv, py * inv, pz * inv, inv);
-      pz += pzs;
-    }
     // d(loss)/d(depth): the observation's 1/d_max scaling and the obstacle
     // term softplus(beta (d_safe - depth)) / beta
     const float depth = x * ob.dmax;
@@ -574,46 +576,80 @@ __global__ __launch_bounds__(64, 8) void render_vjp_obs_kernel(SceneDev sc, Sens
     // contribute nothing
     const bool hit = k >= 0 && k <= valid_hi;
     const int kk = hit ? k : 0;
-    const float t = depth * __builtin_amdgcn_rcpf(db.w);
-    const f3 d = ROT ? rot_apply(R, mk3(db.x, db.y, db.z)) : mk3(db.x, db.y, db.z);
     const float4 pc = PC[kk], pq = PQ[kk];
-    const f3 X = mk3(t * d.x - pc.x, t * d.y - pc.y, t * d.z - pc.z);
-    float ux = fabsf(X.x) * pq.x, uy = fabsf(X.y) * pq.y;
-    const float uz = fabsf(X.z) * pq.z;
-    if (CYL) {
-      const float radial = __builtin_amdgcn_sqrtf(X.x * X.x + X.y * X.y) * pq.x;
-      ux = pc.w != 0.f ? radial : ux;
-      uy = pc.w != 0.f ? radial : uy;
-    }
-    const float um = fmaxf(ux, fmaxf(uy, uz));
-    f3 N = mk3(ux >= um ? X.x : 0.f, uy >= um ? X.y : 0.f, uz >= um ? X.z : 0.f);
-    float nd = dot(N, d), tt = t;
-    bool ok = hit;
+    // the face normal at the hit offset X (see above)
+    auto normal = [&](const f3 X) {
+      float ux = fabsf(X.x) * pq.x, uy = fabsf(X.y) * pq.y;
+      const float uz = fabsf(X.z) * pq.z;
+      if (CYL) {
+        const float radial = __builtin_amdgcn_sqrtf(X.x * X.x + X.y * X.y) * pq.x;
+        ux = pc.w != 0.f ? radial : ux;
+        uy = pc.w != 0.f ? radial : uy;
+      }
+      const float um = fmaxf(ux, fmaxf(uy, uz));
+      return mk3(ux >= um ? X.x : 0.f, uy >= um ? X.y : 0.f, uz >= um ? X.z : 0.f);
+    };
     // A sphere (or agent) hit, or a cylinder side hit, within ~17 deg of
     // grazing (|n.d| < 0.3): N . d is a small difference of distances that
     // the FP32 forward's t (and the FP32 direction) cannot resolve, so it is
     // recomputed from the FP64 discriminant along the FP64 direction, as the
     // hit-record adjoint does, in a second pass over those rays (a few per
     // cent of the hits), which keeps the main loop's registers low.
-    const bool curved = pq.x == 0.f || (CYL && pc.w != 0.f && N.z == 0.f);
-    if (hit && curved && nd * nd < 0.09f * dot(N, N)) {
-      gmask |= 1ull << ((r - (unsigned)tid) / kNT);  // handled in the second pass
-      ok = false;
-    }
-    // d(loss)/do = c N with c = -(d loss/dt) / (N . d)
-    const float c = (ok && nd != 0.f) ? -gv * db.w * __builtin_amdgcn_rcpf(nd) : 0.f;
-    go[0] += c * N.x;
-    go[1] += c * N.y;
-    go[2] += c * N.z;
-    if (ROT) {
-      // d(loss)/dR = t (d(loss)/do) d_b^T
-      const float ct = c * tt;
-      const float n3[3] = {ct * N.x, ct * N.y, ct * N.z};
-      const float bb[3] = {db.x, db.y, db.z};
+    if constexpr (PIN) {
+      const float pzr = pz;
+      pz += pzs;
+      const f3 u = ROT ? mk3(Q.x + pzr * R.m[0][2], Q.y + pzr * R.m[1][2], Q.z + pzr * R.m[2][2])
+                       : mk3(1.f, py, pzr);
+      const f3 N = normal(mk3(depth * u.x - pc.x, depth * u.y - pc.y, depth * u.z - pc.z));
+      const float nu = dot(N, u);
+      bool ok = hit;
+      const bool curved = pq.x == 0.f || (CYL && pc.w != 0.f && N.z == 0.f);
+      // (N . d)^2 < 0.09 |N|^2 with |u|^2 = 1 + py^2 + pz^2 = 1 / zfac^2
+      if (hit && curved && nu * nu < 0.09f * dot(N, N) * (py2 + pzr * pzr)) {
+        gmask |= 1ull << ((r - (unsigned)tid) / kNT);  // handled in the second pass
+        ok = false;
+      }
+      // d(loss)/do = c N with c = -(d loss/d depth) / (N . u)
+      const float c = (ok && nu != 0.f) ? -gv * __builtin_amdgcn_rcpf(nu) : 0.f;
+      go[0] += c * N.x;
+      go[1] += c * N.y;
+      go[2] += c * N.z;
+      if (ROT) {
+        const float cd = c * depth;
+        const float w[3] = {cd * N.x, cd * N.y, cd * N.z};
 #pragma unroll
-      for (int a = 0; a < 3; ++a)
+        for (int a = 0; a < 3; ++a) {
+          gR[a * 3] += w[a];
+          gR[a * 3 + 2] += w[a] * pzr;
+        }
+      }
+    } else {
+      const float4 db = in.db;
+      const float t = depth * __builtin_amdgcn_rcpf(db.w);
+      const f3 d = ROT ? rot_apply(R, mk3(db.x, db.y, db.z)) : mk3(db.x, db.y, db.z);
+      const f3 N = normal(mk3(t * d.x - pc.x, t * d.y - pc.y, t * d.z - pc.z));
+      const float nd = dot(N, d);
+      bool ok = hit;
+      const bool curved = pq.x == 0.f || (CYL && pc.w != 0.f && N.z == 0.f);
+      if (hit && curved && nd * nd < 0.09f * dot(N, N)) {
+        gmask |= 1ull << ((r - (unsigned)tid) / kNT);  // handled in the second pass
+        ok = false;
+      }
+      // d(loss)/do = c N with c = -(d loss/dt) / (N . d)
+      const float c = (ok && nd != 0.f) ? -gv * db.w * __builtin_amdgcn_rcpf(nd) : 0.f;
+      go[0] += c * N.x;
+      go[1] += c * N.y;
+      go[2] += c * N.z;
+      if (ROT) {
+        // d(loss)/dR = t (d(loss)/do) d_b^T
+        const float ct = c * t;
+        const float n3[3] = {ct * N.x, ct * N.y, ct * N.z};
+        const float bb[3] = {db.x, db.y, db.z};
 #pragma unroll
-        for (int e = 0; e < 3; ++e) gR[a * 3 + e] += n3[a] * bb[e];
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int e = 0; e < 3; ++e) gR[a * 3 + e] += n3[a] * bb[e];
+      }
     }
   };
   // two rays per pass, each loaded one ray ahead, so the two register sets
@@ -628,6 +664,9 @@ __global__ __launch_bounds__(64, 8) void render_vjp_obs_kernel(SceneDev sc, Sens
     ra = load(min(r + 2 * kNT, unr - 1u));
     if (r + kNT < unr) cast_back(r + kNT, rb);
   }
+  if (PIN && ROT)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) gR[a * 3 + 1] = py * gR[a * 3];
   // per-thread sums to LDS; the second pass adds the grazing sphere /
   // cylinder-side hits to them there, in ray order, so that the main loop's
   // accumulators are not held in registers across it
