@@ -11,8 +11,8 @@ namespace da {
 constexpr float kInf = __builtin_huge_valf();
 
 struct RenderLds {
-  float4* pa;  // sphere (w, r^2) | box lo' | cylinder (w, r^2)
-  float4* pb;  // sphere (C, ...) | box hi' | cylinder (C, h, ...)
+  float4* pa;  // [2 k]: sphere (w, r^2) | box lo' | cylinder (w, r^2)
+  float4* pb;  // [2 k]: sphere (C, ...) | box hi' | cylinder (C, h, ...)
   float4* pc;  // bounding sphere: (centre - o, sqrt(L^2 - rho^2))
   float2* pd;  // (rho, L - rho); rho < 0: never hit
   short* lists;
@@ -25,8 +25,8 @@ struct RenderLds {
 __device__ __forceinline__ RenderLds carve(void* base, int P) {
   RenderLds L;
   L.pa = reinterpret_cast<float4*>(base);
-  L.pb = L.pa + P;
-  L.pc = L.pb + P;
+  L.pb = L.pa + 1;  // interleaved with pa: one index addresses both
+  L.pc = L.pa + 2 * P;
   L.pd = reinterpret_cast<float2*>(L.pc + P);
   L.flag = reinterpret_cast<int*>(L.pd + P);
   L.lists = reinterpret_cast<short*>(L.flag + 4);
@@ -284,8 +284,8 @@ __device__ __forceinline__ AgentStage stage_agent(const SceneDev& sc, const floa
       const f3 w = mk3(c.x - o.x, c.y - o.y, c.z - o.z);
       const float r2 = c.w * c.w;
       const float C = dot(w, w) - r2;
-      L.pa[k] = make_float4(w.x, w.y, w.z, r2);
-      L.pb[k] = make_float4(C, 0.f, 0.f, 0.f);
+      L.pa[2 * k] = make_float4(w.x, w.y, w.z, r2);
+      L.pb[2 * k] = make_float4(C, 0.f, 0.f, 0.f);
       const ConePrim cp = cone_prep(w, c.w);
       L.pc[k] = cp.c;
       L.pd[k] = cp.d;
@@ -295,8 +295,8 @@ __device__ __forceinline__ AgentStage stage_agent(const SceneDev& sc, const floa
       if (SDF) md = fminf(md, sdf_box(o, b));
       const f3 lo = mk3(b[0] - b[3] - o.x, b[1] - b[4] - o.y, b[2] - b[5] - o.z);
       const f3 hi = mk3(b[0] + b[3] - o.x, b[1] + b[4] - o.y, b[2] + b[5] - o.z);
-      L.pa[k] = make_float4(lo.x, lo.y, lo.z, 0.f);
-      L.pb[k] = make_float4(hi.x, hi.y, hi.z, 0.f);
+      L.pa[2 * k] = make_float4(lo.x, lo.y, lo.z, 0.f);
+      L.pb[2 * k] = make_float4(hi.x, hi.y, hi.z, 0.f);
       const ConePrim cp = cone_prep(mk3(0.5f * (lo.x + hi.x), 0.5f * (lo.y + hi.y), 0.5f * (lo.z + hi.z)),
                                     sqrtf(b[3] * b[3] + b[4] * b[4] + b[5] * b[5]));
       L.pc[k] = cp.c;
@@ -308,8 +308,8 @@ __device__ __forceinline__ AgentStage stage_agent(const SceneDev& sc, const floa
       const f3 w = mk3(y[0] - o.x, y[1] - o.y, y[2] - o.z);
       const float r2 = y[3] * y[3];
       const float C = w.x * w.x + w.y * w.y - r2;
-      L.pa[k] = make_float4(w.x, w.y, w.z, r2);
-      L.pb[k] = make_float4(C, y[4], 0.f, 0.f);
+      L.pa[2 * k] = make_float4(w.x, w.y, w.z, r2);
+      L.pb[2 * k] = make_float4(C, y[4], 0.f, 0.f);
       const ConePrim cp = cone_prep(w, sqrtf(r2 + y[4] * y[4]));
       L.pc[k] = cp.c;
       L.pd[k] = cp.d;
@@ -317,8 +317,8 @@ __device__ __forceinline__ AgentStage stage_agent(const SceneDev& sc, const floa
     } else {
       const int j = a0 + (k - nsbc);
       if (j == i) {
-        L.pa[k] = make_float4(0.f, 0.f, 0.f, -1.f);
-        L.pb[k] = make_float4(1.f, 0.f, 0.f, 0.f);
+        L.pa[2 * k] = make_float4(0.f, 0.f, 0.f, -1.f);
+        L.pb[2 * k] = make_float4(1.f, 0.f, 0.f, 0.f);
         const ConePrim cp = cone_prep(mk3(0.f, 0.f, 0.f), -1.f);
         L.pc[k] = cp.c;
         L.pd[k] = cp.d;
@@ -327,8 +327,8 @@ __device__ __forceinline__ AgentStage stage_agent(const SceneDev& sc, const floa
         const f3 w = mk3(s[j] - o.x, s[(size_t)A + j] - o.y, s[2 * (size_t)A + j] - o.z);
         const float r2 = sc.agent_radius * sc.agent_radius;
         const float C = dot(w, w) - r2;
-        L.pa[k] = make_float4(w.x, w.y, w.z, r2);
-        L.pb[k] = make_float4(C, 0.f, 0.f, 0.f);
+        L.pa[2 * k] = make_float4(w.x, w.y, w.z, r2);
+        L.pb[2 * k] = make_float4(C, 0.f, 0.f, 0.f);
         const ConePrim cp = cone_prep(w, sc.agent_radius);
         L.pc[k] = cp.c;
         L.pd[k] = cp.d;
@@ -469,7 +469,7 @@ __device__ __forceinline__ void render_tiles(const AgentStage& ag, const SensorD
     int id = -1;
     for (int j = 0; j < ks; ++j) {
       const int k = CULL ? list[j] : j;
-      const float t = sphere_t(d, L.pa[k], L.pb[k].x);
+      const float t = sphere_t(d, L.pa[2 * k], L.pb[2 * k].x);
       if (t < best) {
         best = t;
         id = k;
@@ -477,7 +477,7 @@ __device__ __forceinline__ void render_tiles(const AgentStage& ag, const SensorD
     }
     for (int j = ks; j < ks + kb; ++j) {
       const int k = CULL ? list[j] : j;
-      const float t = box_t(inv, L.pa[k], L.pb[k]);
+      const float t = box_t(inv, L.pa[2 * k], L.pb[2 * k]);
       if (t < best) {
         best = t;
         id = k;
@@ -486,8 +486,8 @@ __device__ __forceinline__ void render_tiles(const AgentStage& ag, const SensorD
     if (CYL)
       for (int j = ks + kb; j < ks + kb + kc; ++j) {
         const int k = CULL ? list[j] : j;
-        const float4 pb = L.pb[k];
-        const float t = cylinder_t(d, inv.z, L.pa[k], make_float2(pb.x, pb.y));
+        const float4 pb = L.pb[2 * k];
+        const float t = cylinder_t(d, inv.z, L.pa[2 * k], make_float2(pb.x, pb.y));
         if (t < best) {
           best = t;
           id = k;
@@ -495,7 +495,7 @@ __device__ __forceinline__ void render_tiles(const AgentStage& ag, const SensorD
       }
     for (int j = ks + kb + kc; j < nk; ++j) {
       const int k = CULL ? list[j] : j;
-      const float t = sphere_t(d, L.pa[k], L.pb[k].x);
+      const float t = sphere_t(d, L.pa[2 * k], L.pb[2 * k].x);
       if (t < best) {
         best = t;
         id = k;
